@@ -1,0 +1,133 @@
+"""Pins of the oracle's analytic backward (FP64), loss and Adam: central finite
+differences, an independent torch float64 autograd renderer, torch's L1 loss
+and torch.optim.Adam. CPU only."""
+import numpy as np
+import pytest
+import torch
+
+import scenes
+from scenes import identity_camera
+
+import torch_ref
+
+
+def _masked_grads(orc, s, seed, margin_floor=1e-3):
+    """Seeded upstream gradients with pixels near a decision threshold zeroed,
+    so that a small parameter step cannot move a contributing decision."""
+    grads = scenes.random_image_grads(seed, s.cameras)
+    out = []
+    for cam, (gr, gd, ga) in zip(s.cameras, grads):
+        r = orc.render(s.params, s.sh_degree, cam, mode="f64")
+        keep = (r["margin"] > margin_floor).astype(np.float32)
+        out.append((gr * keep[None], gd * keep, ga * keep))
+    return out
+
+
+def _objective(orc, params, s, grads):
+    total = 0.0
+    for cam, (gr, gd, ga) in zip(s.cameras, grads):
+        r = orc.render(params, s.sh_degree, cam, mode="f64")
+        total += (gr * r["rgb"]).sum() + (gd * r["depth"]).sum() + (ga * r["alpha"]).sum()
+    return total
+
+
+@pytest.mark.parametrize("k,deg,two_views", [(0, 0, False), (1, 3, False), (2, 1, True)])
+def test_backward_matches_central_differences(orc, k, deg, two_views):
+    s = scenes.tiny_random(k, n=10, width=28, height=24, sh_degree=deg)
+    if two_views:
+        s.cameras.append(scenes.look_at_camera([0.4, -0.3, -0.2], [0.0, 0.0, 2.0], 26, 22, 24.0))
+    grads = _masked_grads(orc, s, k)
+    g = orc.backward(s.params, s.sh_degree, s.cameras, grads, pinned=False)
+    rng = np.random.default_rng(k)
+    P, n = s.params.shape
+    # the parameters are float32; perturb them in float32 with a step that
+    # is exactly representable relative to each value
+    checked = bad = 0
+    for _ in range(60):
+        pl, i = int(rng.integers(0, P)), int(rng.integers(0, n))
+        theta = float(s.params[pl, i])
+        h = 2.0 ** (np.floor(np.log2(max(abs(theta), 0.25))) - 12)
+        vals = []
+        for sgn in (+1, -1, +2, -2):
+            p = s.params.copy()
+            p[pl, i] = np.float32(theta + sgn * h)
+            vals.append(_objective(orc, p, s, grads))
+        fd1 = (vals[0] - vals[1]) / (2 * h)
+        fd2 = (vals[2] - vals[3]) / (4 * h)
+        if abs(fd1 - fd2) > 1e-3 * max(abs(fd1), 1e-3):
+            continue                                # non-smooth here (kink), skip
+        checked += 1
+        scale = max(abs(fd1), 1e-2 * np.abs(g[pl]).max(), 1e-8)
+        if abs(g[pl, i] - fd1) > 2e-3 * scale:
+            bad += 1
+    assert checked >= 45
+    assert bad == 0
+
+
+@pytest.mark.parametrize("k,deg", [(5, 0), (6, 3), (7, 2)])
+def test_backward_matches_torch_autograd(orc, k, deg):
+    s = scenes.tiny_random(k, n=14, width=30, height=26, sh_degree=deg)
+    grads = scenes.random_image_grads(k, s.cameras)
+    g = orc.backward(s.params, deg, s.cameras, grads, pinned=False)
+    p = torch.tensor(s.params, dtype=torch.float64, requires_grad=True)
+    rgb, depth, alpha = torch_ref.render(p, deg, s.cameras[0])
+    gr, gd, ga = grads[0]
+    L = (torch.tensor(gr, dtype=torch.float64) * rgb).sum() + (torch.tensor(gd, dtype=torch.float64) * depth).sum() \
+        + (torch.tensor(ga, dtype=torch.float64) * alpha).sum()
+    L.backward()
+    ref = p.grad.numpy()
+    # forward values agree too
+    r = orc.render(s.params, deg, s.cameras[0], mode="f64")
+    assert np.allclose(r["rgb"], rgb.detach().numpy(), rtol=1e-12, atol=1e-13)
+    assert np.allclose(g, ref, rtol=1e-9, atol=1e-11 * np.abs(ref).max())
+
+
+def test_pinned_equals_unpinned_away_from_thresholds(orc):
+    s = scenes.tiny_random(8, n=16, width=32, height=32)
+    grads = _masked_grads(orc, s, 8, margin_floor=1e-4)
+    a = orc.backward(s.params, 0, s.cameras, grads, pinned=True)
+    b = orc.backward(s.params, 0, s.cameras, grads, pinned=False)
+    assert np.allclose(a, b, rtol=1e-9, atol=1e-12 * np.abs(b).max())
+
+
+def test_screen_space_gradients_sum_over_views(orc):
+    s = scenes.tiny_random(9, n=12, width=24, height=20)
+    cams = [s.cameras[0], identity_camera(24, 20, 22.0, cx=11.0, cy=9.0)]
+    grads = scenes.random_image_grads(9, cams)
+    both = orc.backward(s.params, 0, cams, grads, pinned=True)
+    one = orc.backward(s.params, 0, cams[:1], grads[:1], pinned=True)
+    two = orc.backward(s.params, 0, cams[1:], grads[1:], pinned=True)
+    assert np.allclose(both, one + two, rtol=1e-12, atol=1e-15)
+
+
+def test_l1_loss_matches_torch(orc):
+    rng = np.random.default_rng(0)
+    rgb, trgb = rng.random((3, 7, 9)), rng.random((3, 7, 9))
+    dep, tdep = rng.random((7, 9)) * 4, rng.random((7, 9)) * 4
+    dep[0, 0] = tdep[0, 0]                       # sign(0) = 0
+    L, gr, gd = orc.l1_loss_and_grad(rgb, dep, trgb, tdep)
+    a = torch.tensor(rgb, requires_grad=True)
+    b = torch.tensor(dep, requires_grad=True)
+    T = torch.nn.functional.l1_loss(a, torch.tensor(trgb)) + 0.5 * torch.nn.functional.l1_loss(b, torch.tensor(tdep))
+    T.backward()
+    assert np.isclose(L, T.item(), rtol=1e-14)
+    assert np.allclose(gr, a.grad.numpy(), rtol=1e-14)
+    assert np.allclose(gd, b.grad.numpy(), rtol=1e-14)
+
+
+def test_adam_matches_torch(orc):
+    rng = np.random.default_rng(1)
+    P, n = 6, 50
+    x0 = rng.normal(size=(P, n))
+    lrs = np.array([1e-3, 2e-3, 5e-3, 1e-2, 3e-2, 1e-1])
+    params = [torch.tensor(x0[i].copy(), requires_grad=True) for i in range(P)]
+    opt = torch.optim.Adam([{"params": [params[i]], "lr": lrs[i]} for i in range(P)], betas=(0.9, 0.999), eps=1e-15)
+    x, m, v = x0.copy(), np.zeros_like(x0), np.zeros_like(x0)
+    for step in range(1, 6):
+        g = rng.normal(size=(P, n))
+        for i in range(P):
+            params[i].grad = torch.tensor(g[i].copy())
+        opt.step()
+        x, m, v = orc.adam_step(x, g, m, v, step, lrs)
+    ref = np.stack([p.detach().numpy() for p in params])
+    assert np.allclose(x, ref, rtol=1e-12, atol=1e-14)
