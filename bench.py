@@ -1,0 +1,174 @@
+"""Mapping-iteration benchmark of the HIP rasterizer on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--workload NAME] [--tile 16x16]
+
+One step = one mapping iteration over the workload's views: forward render
+(projection, binning, depth-keyed radix sort, compositing), L1 colour +
+0.5 L1 depth loss against a target rendered from perturbed parameters,
+backward to the parameters (and Adam where the workload includes it). The
+inputs are resident in HBM before the timed region. Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "mapping iters/sec (fwd+bwd) 640x480, 200k Gaussians; render Mpix/s"
+ADAM_WORKLOADS = {"surfaces_1200x680_1M_sh3", "mixed16_2M_sh3"}
+
+# MI355X published peaks
+PEAK_HBM_GBS = 8000.0
+PEAK_FP32_VECTOR_TFLOPS = 157.3
+
+# Algorithmic work per unit ("Roofline")
+FLOP_PER_PAIR_BWD = 50.0      # blend backward, per (pixel, Gaussian) pair walked
+FLOP_PER_PAIR_FWD = 22.0      # blend forward, per pair up to the last composited
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="keyframe_640x480_200k")
+    ap.add_argument("--tile", default="16x16")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--breakdown", action="store_true", help="print a per-stage time breakdown to stderr")
+    return ap.parse_args()
+
+
+def cpu_baseline(scene, cams, targets_np):
+    """The CPU oracle as it stands, one full mapping iteration of the workload's first view."""
+    import numpy as np
+    import oracle
+    cores = oracle.set_threads(0)
+    cam = cams[0]
+    t0 = time.perf_counter()
+    r = oracle.render(scene.params, scene.sh_degree, cam, mode="f32")
+    L, grgb, gdep = oracle.l1_loss_and_grad(r["rgb"], r["depth"], targets_np[0][0], targets_np[0][1])
+    oracle.backward(scene.params, scene.sh_degree, [cam],
+                    [(grgb.astype(np.float32), gdep.astype(np.float32), np.zeros_like(gdep, np.float32))],
+                    pinned=True)
+    dt = time.perf_counter() - t0
+    return {"value": round(1.0 / dt, 5), "unit": "iters/s", "cores": cores, "kind": "oracle",
+            "sample": f"one mapping iteration (FP32 brute-force forward, L1 loss, FP64 analytic backward) of view 0 "
+                      f"of {scene.name}, {cam.width}x{cam.height}, {scene.num} Gaussians; {dt:.2f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
+              "(the path would shard by view; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import scenes
+    from paper_2509_06433_amd.rasterize import Rasterizer
+
+    tw, th = (int(x) for x in args.tile.split("x"))
+    scene = scenes.WORKLOADS[args.workload]()
+    cams = scene.cameras
+    deg = scene.sh_degree
+    R = Rasterizer(tile_w=tw, tile_h=th)
+    dev = torch.device("cuda:0")
+    params = torch.from_numpy(scene.params).to(dev)
+    tparams = torch.from_numpy(scene.target_params).to(dev)
+    targets = [tuple(t.clone() for t in o) for o in R.render(tparams, deg, cams)]
+    del tparams
+    outs = R.alloc_images(cams, dev)
+    gimgs = [(torch.empty_like(o[0]), torch.empty_like(o[1]), torch.zeros_like(o[2])) for o in outs]
+    loss = torch.zeros(1, device=dev)
+    grad = torch.zeros_like(params)
+    use_adam = args.workload in ADAM_WORKLOADS
+    m = torch.zeros_like(params)
+    v = torch.zeros_like(params)
+    P = params.shape[0]
+    lrs = [1.6e-4] * 3 + [5e-3] * 3 + [1e-3] * 4 + [5e-2] + [2.5e-3] * 3 + [1.25e-4] * (P - 14)
+    from paper_2509_06433_amd import _lib
+
+    def step(it):
+        R.render(params, deg, cams, outs)
+        _lib.gsr_loss_l1(R.handle, cams, outs, targets, gimgs, 0.5, loss)
+        grad.zero_()
+        R.render_backward(params, deg, cams, gimgs, grad)
+        if use_adam:
+            R.adam_step(params, grad, m, v, lrs, it)
+
+    it = 0
+    for _ in range(args.warmup):
+        it += 1
+        step(it)
+    torch.cuda.synchronize()
+    dominant = "blend_bwd"
+    R.set_profiling([dominant])
+    R.profile(reset=True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        it += 1
+        step(it)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = R.profile(reset=True)
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    pairs, visible = R.count_work(len(cams))
+    dom_ms, dom_n = prof[dominant]
+    dom_avg_ms = dom_ms / max(dom_n, 1)
+    achieved = FLOP_PER_PAIR_BWD * pairs / (dom_avg_ms * 1e-3) / 1e12
+
+    # per-stage breakdown (separate, untimed pass)
+    R.set_profiling(None)
+    for _ in range(3):
+        it += 1
+        step(it)
+    torch.cuda.synchronize()
+    stages = {k: (ms / max(n, 1)) for k, (ms, n) in R.profile(reset=True).items() if n}
+    R.set_profiling([])
+    render_ms = sum(stages.get(k, 0.0) for k in ["project", "depth_sort", "scan", "emit", "tile_sort", "ranges",
+                                                   "blend_fwd"])
+    pix = sum(c.width * c.height for c in cams)
+    mpix = pix / (render_ms * 1e-3) / 1e6 if render_ms > 0 else None
+    st = R.status()
+    if args.breakdown:
+        print(json.dumps({"stage_ms": stages, "instances": st["instances"], "pairs": pairs, "visible": visible},
+                         indent=1), file=sys.stderr)
+
+    out = {
+        "metric": METRIC,
+        "value": round(1000.0 / ms_per_step, 3),
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": scene.name, "views": len(cams),
+                   "resolutions": sorted({f"{c.width}x{c.height}" for c in cams}),
+                   "gaussians": scene.num, "sh_degree": deg, "tile": args.tile, "adam": use_adam,
+                   "render_mpix_s": round(mpix, 2) if mpix else None,
+                   "instances": st["instances"], "visible_per_view": visible,
+                   "stage_ms": {k: round(x, 4) for k, x in stages.items()}},
+        "roofline": {"bound": "alu", "kernel": dominant, "achieved": round(achieved, 3),
+                     "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": None,
+                     "avg_ms": round(dom_avg_ms, 4), "pairs": pairs, "flop_per_pair": FLOP_PER_PAIR_BWD},
+    }
+    if not args.no_cpu_baseline:
+        tnp = [(t[0].cpu().numpy(), t[1].cpu().numpy()) for t in targets]
+        out["cpu_baseline"] = cpu_baseline(scene, cams, tnp)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,205 @@
+/*
+ * gsr.h -- C ABI of the MI355X (gfx950) differentiable Gaussian rasterizer.
+ *
+ * The library renders a map of anisotropic 3D Gaussians (mean, covariance from
+ * scale and rotation, opacity, spherical-harmonic colour; paper Sec. II-A) into
+ * RGB, depth and alpha images, and back-propagates image gradients to the
+ * Gaussian parameters, as the renderer that drives the continuous mapping
+ * optimisation of a Gaussian-splatting SLAM system does (paper Sec. II-B,
+ * Fig. "GS_SLAM", renderer I1). The paper gives no formula; the image
+ * formation is EWA splatting with front-to-back alpha compositing: alpha is
+ * clamped to 0.99, alphas below 1/255 are skipped and a pixel stops
+ * (without compositing the Gaussian that would cross it) once its
+ * transmittance would fall below 1e-4.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - All pointers named "device" are HIP device memory on the current device;
+ *   all others are host memory, read during the call only.
+ * - `stream` is a hipStream_t (0 = legacy default stream). Every call is
+ *   asynchronous on that stream unless stated otherwise; the context keeps
+ *   device scratch that later calls on the same context reuse, so one context
+ *   must not be used from two streams at the same time.
+ * - Return value: GSR_OK (0) or a negative gsr_status. No C++ exception
+ *   crosses this boundary. After GSR_ERR_HIP the HIP error code is available
+ *   from gsr_last_hip_error().
+ *
+ * Parameter layout ("the map"), float32, planar structure-of-arrays [P][stride]:
+ *   planes 0..2   mean x, y, z (world)
+ *   planes 3..5   log-scale of the three local axes (scale = exp)
+ *   planes 6..9   rotation quaternion (w, x, y, z), unnormalised
+ *   plane  10     opacity logit (opacity = sigmoid)
+ *   plane  11+3k+c  real spherical-harmonic coefficient k (k = l^2 + l + m,
+ *                 Condon-Shortley phase), colour channel c
+ *   P = 11 + 3 (sh_degree + 1)^2; colour = max(0, sum_k coef_k Y_k(dir) + 0.5)
+ *   where dir is the unit vector from the camera centre to the mean.
+ *
+ * Cameras: world-to-camera rotation R (row-major) and translation t, OpenCV
+ * axes (x right, y down, z forward), pinhole fx, fy, cx, cy; pixel (px, py)
+ * is sampled at (px + 0.5, py + 0.5).
+ *
+ * Images: per view, planar float32 rgb [3][H][W], depth [H][W] (sum of
+ * weights times camera-space z of each mean), alpha [H][W] (1 - final
+ * transmittance); rgb includes final transmittance times the background.
+ */
+#ifndef GSR_H
+#define GSR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GSR_OK = 0,
+  GSR_ERR_INVALID = -1,      /* bad argument (null pointer, size, degree ...) */
+  GSR_ERR_OOM = -2,          /* device allocation failed */
+  GSR_ERR_HIP = -3,          /* a HIP runtime call failed */
+  GSR_ERR_STATE = -4,        /* call order violated (backward without matching forward) */
+  GSR_ERR_CAPACITY = -5,     /* fixed-capacity scratch too small (mapping iteration) */
+  GSR_ERR_UNSUPPORTED = -6   /* option not supported by this build */
+} gsr_status;
+
+typedef struct gsr_ctx gsr_ctx;
+
+typedef struct {
+  int32_t tile_w, tile_h;   /* screen tile; 0 = 16 x 16. Supported: 16x16, 16x8, 8x8, 32x8 */
+  int32_t batch_depth;      /* Gaussians staged in LDS per batch; 0 = tile_w * tile_h */
+  float bg[3];              /* background colour; default 0 */
+  float znear;              /* near-plane cull distance; <= 0 means 0.2 */
+} gsr_options;
+
+typedef struct {
+  float R[9];               /* world -> camera rotation, row-major */
+  float t[3];               /* world -> camera translation */
+  float fx, fy, cx, cy;     /* pinhole intrinsics, pixels */
+  int32_t width, height;    /* image size, 1 .. 16384 each */
+} gsr_camera;
+
+typedef struct {
+  const float* params;      /* device [P][stride] float32, layout above */
+  int64_t num;              /* N Gaussians, 0 .. 2^27 */
+  int64_t stride;           /* floats between planes, >= num */
+  int32_t sh_degree;        /* 0 .. 3 */
+} gsr_gaussians;
+
+typedef struct {
+  float* rgb;               /* device [3][H][W] */
+  float* depth;             /* device [H][W] */
+  float* alpha;             /* device [H][W] */
+} gsr_image;
+
+/* Create a context with the given options (NULL = defaults). *out receives
+ * the handle. The context owns all device scratch (projected splats, sort
+ * buffers, tile ranges, per-pixel backward state, screen-space gradient
+ * accumulators); it grows on demand and is freed by gsr_destroy. */
+int gsr_create(gsr_ctx** out, const gsr_options* opt);
+
+/* Free the context and its device scratch (synchronises the device first).
+ * NULL is ignored. */
+void gsr_destroy(gsr_ctx* ctx);
+
+/* Forward render of num_views views (>= 1) of the same map: EWA projection
+ * of every Gaussian into every view, tile binning, depth-keyed radix sort of
+ * the (tile, Gaussian) instances, front-to-back compositing per tile.
+ * cams[num_views] host; out[num_views] host array of device image pointers.
+ * Keeps what render_backward needs (per-pixel final transmittance and
+ * last-composited index, the sorted instance lists) in the context.
+ * Synchronises `stream` once to size the instance buffers. */
+int gsr_render(gsr_ctx* ctx, const gsr_gaussians* g, int32_t num_views,
+               const gsr_camera* cams, const gsr_image* out, void* stream);
+
+/* Single-view convenience form: gsr_render with num_views = 1. */
+int gsr_render1(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_camera* cam,
+                const gsr_image* out, void* stream);
+
+/* Backward of the last gsr_render on this context: given dL/d(rgb, depth,
+ * alpha) per view (grad_out[num_views], device pointers; a NULL plane means
+ * zero), ADDS dL/dparams to grad_params (device [P][stride] float32, same
+ * stride as g). g, num_views and cams must equal those of the last render
+ * (else GSR_ERR_STATE). Per-pixel transmittance is recomputed in reverse
+ * order from the stored final value; screen-space gradients are reduced
+ * across each wavefront and workgroup before global atomics; gradients of
+ * all views are summed. */
+int gsr_render_backward(gsr_ctx* ctx, const gsr_gaussians* g, int32_t num_views,
+                        const gsr_camera* cams, const gsr_image* grad_out,
+                        float* grad_params, void* stream);
+
+/* Mapping loss of one or more rendered views against targets:
+ *   L = sum_v [ mean|rgb_v - rgb*_v| + depth_weight * mean|depth_v - depth*_v| ]
+ * (means over 3HW and HW; sign(0) = 0). Writes dL/drgb and dL/ddepth into
+ * grad_out[v].rgb / .depth (device, overwritten; .alpha if non-NULL is set
+ * to 0) and, if loss is not NULL, the scalar L into loss (device float,
+ * overwritten). rendered/target/grad_out are host arrays of num_views
+ * device-image descriptors (target alpha unused). */
+int gsr_loss_l1(gsr_ctx* ctx, int32_t num_views, const gsr_camera* cams,
+                const gsr_image* rendered, const gsr_image* target, float depth_weight,
+                const gsr_image* grad_out, float* loss, void* stream);
+
+/* One Adam step (bias-corrected, step >= 1) over P planes of `num` floats
+ * with plane stride `stride` (device params, grads, m, v; params, m, v
+ * updated in place):
+ *   m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2;
+ *   p -= lr[plane] * (m / (1-b1^step)) / (sqrt(v / (1-b2^step)) + eps).
+ * lr_per_plane: host [num_planes]. */
+int gsr_adam_step(gsr_ctx* ctx, float* params, const float* grads, float* m, float* v,
+                  int64_t num, int64_t stride, int32_t num_planes, const float* lr_per_plane,
+                  float beta1, float beta2, float eps, int32_t step, void* stream);
+
+/* Status of the last render on this context (synchronises the context's last
+ * stream): number of (tile, Gaussian) instances over all views, number of
+ * visible (view, Gaussian) splats, and the number of tiles. Any pointer may
+ * be NULL. */
+int gsr_query_status(gsr_ctx* ctx, int64_t* num_instances, int64_t* num_visible,
+                     int64_t* num_tiles);
+
+/* Copy the sorted instance list of the last render to host: tile[k] is the
+ * global tile id (view tile offset + ty * tiles_x + tx, views in order),
+ * gid[k] the Gaussian index, ordered by (tile, depth bits, Gaussian index).
+ * Writes min(capacity, count) entries; *count receives the total. Synchronous. */
+int gsr_copy_instances(gsr_ctx* ctx, uint32_t* tile, uint32_t* gid, int64_t capacity,
+                       int64_t* count);
+
+/* Copy the projected splats of view `view` of the last render to host:
+ * out[num][16] = u, v, z, a, b, c (dilated 2D covariance), A, B, C (conic),
+ * opacity, r, g, b, then px0, py0, px1, py1 (inclusive pixel rectangle,
+ * stored as float) for visible Gaussians; culled rows are all zero with
+ * px1 = py1 = -1. Synchronous. */
+int gsr_copy_splats(gsr_ctx* ctx, int32_t view, float* out, int64_t num);
+
+/* Work counters of the last render (synchronise the context's last stream):
+ * pairs = sum over all pixels of the number of list entries up to and
+ * including the last composited Gaussian (the pairs the backward walks);
+ * visible[num_views] (may be NULL) = Gaussians with at least one tile per view. */
+int gsr_count_work(gsr_ctx* ctx, int64_t* pairs, int64_t* visible, int32_t num_views);
+
+/* Stages timed when profiling is on. */
+typedef enum {
+  GSR_STAGE_PROJECT = 0, GSR_STAGE_DEPTH_SORT, GSR_STAGE_SCAN, GSR_STAGE_EMIT,
+  GSR_STAGE_TILE_SORT, GSR_STAGE_RANGES, GSR_STAGE_BLEND_FWD, GSR_STAGE_LOSS,
+  GSR_STAGE_BLEND_BWD, GSR_STAGE_PROJECT_BWD, GSR_STAGE_ADAM, GSR_STAGE_ZERO,
+  GSR_NUM_STAGES
+} gsr_stage;
+
+/* Per-stage timing: for every stage k with bit k set in stage_mask the
+ * context records a pair of HIP events on the call's stream around the
+ * stage's launches (0 turns timing off). */
+int gsr_set_profiling(gsr_ctx* ctx, uint32_t stage_mask);
+
+/* Accumulated time of one stage since the last reset, in ms, and the number
+ * of timed launches (synchronises on the recorded events); reset != 0
+ * clears the stage's record afterwards. */
+int gsr_get_profile(gsr_ctx* ctx, int32_t stage, double* total_ms, int64_t* launches, int32_t reset);
+
+/* HIP error code recorded by the last GSR_ERR_HIP on this context. */
+int gsr_last_hip_error(gsr_ctx* ctx);
+
+/* Static description of a status code. */
+const char* gsr_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GSR_H */

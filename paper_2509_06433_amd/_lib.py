@@ -1,0 +1,263 @@
+"""ctypes binding of libgsr.so (argument marshalling only).
+
+Every function here has the name of the C entry point it calls (include/gsr.h)
+and takes torch CUDA tensors for device buffers; all arithmetic happens in
+the HIP kernels. There is no fallback: if libgsr.so is not built, loading
+raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgsr.so")
+
+GSR_OK = 0
+STATUS_NAMES = {0: "GSR_OK", -1: "GSR_ERR_INVALID", -2: "GSR_ERR_OOM", -3: "GSR_ERR_HIP",
+                -4: "GSR_ERR_STATE", -5: "GSR_ERR_CAPACITY", -6: "GSR_ERR_UNSUPPORTED"}
+
+EXPORTED = sorted(["gsr_create", "gsr_destroy", "gsr_render", "gsr_render1", "gsr_render_backward", "gsr_loss_l1",
+                   "gsr_adam_step", "gsr_query_status", "gsr_copy_instances", "gsr_copy_splats",
+                   "gsr_count_work", "gsr_set_profiling", "gsr_get_profile", "gsr_last_hip_error",
+                   "gsr_status_string"])
+
+STAGES = ["project", "depth_sort", "scan", "emit", "tile_sort", "ranges", "blend_fwd", "loss", "blend_bwd",
+          "project_bwd", "adam", "zero"]
+
+
+class GsrError(RuntimeError):
+    def __init__(self, fn, status, hip=0):
+        self.status = status
+        msg = f"{fn} failed: {STATUS_NAMES.get(status, status)}"
+        if hip:
+            msg += f" (hipError {hip})"
+        super().__init__(msg)
+
+
+class gsr_options(ctypes.Structure):
+    _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("batch_depth", ctypes.c_int32),
+                ("bg", ctypes.c_float * 3), ("znear", ctypes.c_float)]
+
+
+class gsr_camera(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_float * 9), ("t", ctypes.c_float * 3), ("fx", ctypes.c_float),
+                ("fy", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32)]
+
+
+class gsr_gaussians(ctypes.Structure):
+    _fields_ = [("params", ctypes.c_void_p), ("num", ctypes.c_int64), ("stride", ctypes.c_int64),
+                ("sh_degree", ctypes.c_int32)]
+
+
+class gsr_image(ctypes.Structure):
+    _fields_ = [("rgb", ctypes.c_void_p), ("depth", ctypes.c_void_p), ("alpha", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2509_06433_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER
+        vp, i32, i64, f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float
+        sig = {
+            "gsr_create": ([P(vp), P(gsr_options)], ctypes.c_int),
+            "gsr_destroy": ([vp], None),
+            "gsr_render": ([vp, P(gsr_gaussians), i32, P(gsr_camera), P(gsr_image), vp], ctypes.c_int),
+            "gsr_render1": ([vp, P(gsr_gaussians), P(gsr_camera), P(gsr_image), vp], ctypes.c_int),
+            "gsr_render_backward": ([vp, P(gsr_gaussians), i32, P(gsr_camera), P(gsr_image), vp, vp],
+                                    ctypes.c_int),
+            "gsr_loss_l1": ([vp, i32, P(gsr_camera), P(gsr_image), P(gsr_image), f32, P(gsr_image), vp, vp],
+                            ctypes.c_int),
+            "gsr_adam_step": ([vp, vp, vp, vp, vp, i64, i64, i32, P(f32), f32, f32, f32, i32, vp], ctypes.c_int),
+            "gsr_query_status": ([vp, P(i64), P(i64), P(i64)], ctypes.c_int),
+            "gsr_copy_instances": ([vp, P(ctypes.c_uint32), P(ctypes.c_uint32), i64, P(i64)], ctypes.c_int),
+            "gsr_copy_splats": ([vp, i32, P(f32), i64], ctypes.c_int),
+            "gsr_count_work": ([vp, P(i64), P(i64), i32], ctypes.c_int),
+            "gsr_set_profiling": ([vp, ctypes.c_uint32], ctypes.c_int),
+            "gsr_get_profile": ([vp, i32, P(ctypes.c_double), P(i64), i32], ctypes.c_int),
+            "gsr_last_hip_error": ([vp], ctypes.c_int),
+            "gsr_status_string": ([ctypes.c_int], ctypes.c_char_p),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def make_camera(cam) -> gsr_camera:
+    """gsr_camera from any object with R (3x3), t (3), fx, fy, cx, cy, width, height."""
+    c = gsr_camera()
+    R = [float(x) for row in cam.R for x in row]
+    for k in range(9):
+        c.R[k] = R[k]
+    for k in range(3):
+        c.t[k] = float(cam.t[k])
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    c.width, c.height = int(cam.width), int(cam.height)
+    return c
+
+
+def _cams(cams):
+    arr = (gsr_camera * len(cams))()
+    for i, c in enumerate(cams):
+        arr[i] = c if isinstance(c, gsr_camera) else make_camera(c)
+    return arr
+
+
+def _images(imgs):
+    arr = (gsr_image * len(imgs))()
+    for i, (rgb, depth, alpha) in enumerate(imgs):
+        arr[i] = gsr_image(_ptr(rgb), _ptr(depth), _ptr(alpha))
+    return arr
+
+
+def _gauss(params: torch.Tensor, sh_degree: int, num=None, stride=None) -> gsr_gaussians:
+    if params.dtype != torch.float32 or not params.is_cuda or params.dim() != 2:
+        raise ValueError("params must be a CUDA float32 tensor [P, N]")
+    if params.stride(1) != 1:
+        raise ValueError("params planes must be contiguous")
+    n = params.shape[1] if num is None else num
+    st = params.stride(0) if stride is None else stride
+    if params.shape[0] != 11 + 3 * (sh_degree + 1) ** 2:
+        raise ValueError("params has the wrong number of planes for sh_degree")
+    return gsr_gaussians(_ptr(params), n, st, sh_degree)
+
+
+def _check(ctx, fn, rc):
+    if rc != GSR_OK:
+        hip = load().gsr_last_hip_error(ctx) if ctx else 0
+        raise GsrError(fn, rc, hip)
+
+
+# --- one wrapper per C entry point ------------------------------------------
+
+def gsr_create(tile_w=16, tile_h=16, batch_depth=0, bg=(0.0, 0.0, 0.0), znear=0.2):
+    opt = gsr_options(tile_w, tile_h, batch_depth, (ctypes.c_float * 3)(*bg), znear)
+    h = ctypes.c_void_p()
+    _check(None, "gsr_create", load().gsr_create(ctypes.byref(h), ctypes.byref(opt)))
+    return h
+
+
+def gsr_destroy(ctx):
+    load().gsr_destroy(ctx)
+
+
+def gsr_render(ctx, params, sh_degree, cams, outs, stream=None):
+    """outs: list of (rgb [3,H,W], depth [H,W], alpha [H,W]) CUDA float32 tensors, written."""
+    g = _gauss(params, sh_degree)
+    _check(ctx, "gsr_render", load().gsr_render(ctx, ctypes.byref(g), len(cams), _cams(cams), _images(outs),
+                                                _stream(stream)))
+
+
+def gsr_render1(ctx, params, sh_degree, cam, out, stream=None):
+    g = _gauss(params, sh_degree)
+    _check(ctx, "gsr_render1", load().gsr_render1(ctx, ctypes.byref(g), _cams([cam]), _images([out]),
+                                                  _stream(stream)))
+
+
+def gsr_render_backward(ctx, params, sh_degree, cams, grads, grad_params, stream=None):
+    """grads: list of (dL/drgb, dL/ddepth, dL/dalpha), entries may be None. grad_params += dL/dparams."""
+    g = _gauss(params, sh_degree)
+    if grad_params.shape != params.shape or grad_params.stride() != params.stride():
+        raise ValueError("grad_params must match params in shape and stride")
+    _check(ctx, "gsr_render_backward",
+           load().gsr_render_backward(ctx, ctypes.byref(g), len(cams), _cams(cams), _images(grads),
+                                      _ptr(grad_params), _stream(stream)))
+
+
+def gsr_loss_l1(ctx, cams, rendered, targets, grads, depth_weight=0.5, loss=None, stream=None):
+    _check(ctx, "gsr_loss_l1",
+           load().gsr_loss_l1(ctx, len(cams), _cams(cams), _images(rendered), _images(targets),
+                              float(depth_weight), _images(grads), _ptr(loss), _stream(stream)))
+
+
+def gsr_adam_step(ctx, params, grads, m, v, lr_per_plane, step, beta1=0.9, beta2=0.999, eps=1e-15,
+                  stream=None):
+    P, n = params.shape
+    for t in (grads, m, v):
+        if t.shape != params.shape or t.stride() != params.stride():
+            raise ValueError("Adam tensors must match params in shape and stride")
+    lr = (ctypes.c_float * P)(*[float(x) for x in lr_per_plane])
+    _check(ctx, "gsr_adam_step",
+           load().gsr_adam_step(ctx, _ptr(params), _ptr(grads), _ptr(m), _ptr(v), n, params.stride(0), P, lr,
+                                beta1, beta2, eps, int(step), _stream(stream)))
+
+
+def gsr_query_status(ctx):
+    a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(ctx, "gsr_query_status", load().gsr_query_status(ctx, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return {"instances": a.value, "visible": b.value, "tiles": c.value}
+
+
+def gsr_copy_instances(ctx):
+    import numpy as np
+    cnt = ctypes.c_int64()
+    _check(ctx, "gsr_copy_instances", load().gsr_copy_instances(ctx, None, None, 0, ctypes.byref(cnt)))
+    n = cnt.value
+    tiles = np.empty(max(n, 1), np.uint32)
+    gids = np.empty(max(n, 1), np.uint32)
+    PU = ctypes.POINTER(ctypes.c_uint32)
+    _check(ctx, "gsr_copy_instances",
+           load().gsr_copy_instances(ctx, tiles.ctypes.data_as(PU), gids.ctypes.data_as(PU), n, ctypes.byref(cnt)))
+    return tiles[:n], gids[:n]
+
+
+def gsr_copy_splats(ctx, view, num):
+    import numpy as np
+    out = np.empty((num, 16), np.float32)
+    _check(ctx, "gsr_copy_splats",
+           load().gsr_copy_splats(ctx, int(view), out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), num))
+    return out
+
+
+def gsr_count_work(ctx, num_views):
+    pairs = ctypes.c_int64()
+    vis = (ctypes.c_int64 * num_views)()
+    _check(ctx, "gsr_count_work", load().gsr_count_work(ctx, ctypes.byref(pairs), vis, num_views))
+    return pairs.value, list(vis)
+
+
+def gsr_set_profiling(ctx, stages=None):
+    """Time the named stages (None = all, [] = none)."""
+    names = STAGES if stages is None else stages
+    mask = 0
+    for nm in names:
+        mask |= 1 << STAGES.index(nm)
+    _check(ctx, "gsr_set_profiling", load().gsr_set_profiling(ctx, mask))
+
+
+def gsr_get_profile(ctx, reset=True):
+    """{stage name: (total ms, launches)} accumulated since the last reset."""
+    out = {}
+    for k, name in enumerate(STAGES):
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        _check(ctx, "gsr_get_profile", load().gsr_get_profile(ctx, k, ctypes.byref(ms), ctypes.byref(n), int(reset)))
+        out[name] = (ms.value, n.value)
+    return out
+
+
+def gsr_status_string(status: int) -> str:
+    return load().gsr_status_string(int(status)).decode()

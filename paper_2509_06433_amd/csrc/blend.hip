@@ -1,0 +1,339 @@
+// Front-to-back alpha compositing of the sorted tile lists, its backward,
+// the L1 mapping loss and Adam.
+//
+// One workgroup per screen tile, one thread per pixel (wave64 = 4 rows of a
+// 16-wide tile). The tile's instance list is staged through LDS in batches;
+// every lane reads the same LDS record, so the reads are broadcasts. A pixel
+// stops when compositing the next Gaussian would take its transmittance below
+// 1e-4 (that Gaussian is not composited); alpha is clamped to 0.99 and
+// alphas below 1/255 are skipped. The workgroup leaves the tile as soon as
+// every pixel has stopped.
+//
+// The backward walks each pixel's list in reverse from the last composited
+// Gaussian, recovering T_k = T_{k+1} / (1 - alpha_k) from the stored final
+// transmittance instead of storing per-Gaussian blend state, and keeps the
+// suffix sum S_k of later contributions. Per-pair screen-space gradients are
+// summed over the wavefront with a butterfly, over the workgroup in LDS, and
+// only then added with one global atomic per (tile, Gaussian, component).
+//
+// Compiled with -ffp-contract=off: alpha is written with explicit fused
+// multiply-adds so the forward and backward recompute it bit-identically.
+
+#include "gsr_internal.h"
+
+namespace gsr {
+namespace {
+
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kLn2 = 0.6931471805599453f;
+
+// Blend-ready record of one Gaussian in LDS: q0 = (u, v, Ah, Bh),
+// q1 = (Ch, opacity, z, 0), q2 = (r, g, b, 0) where the base-2 exponent is
+// p2 = Ah dx^2 + Bh dx dy + Ch dy^2 = log2(e) * power.
+__device__ __forceinline__ void stage_record(const Splat& sp, float4& q0, float4& q1, float4& q2) {
+  q0 = make_float4(sp.w0.x, sp.w0.y, -0.5f * kLog2e * sp.w1.x, -kLog2e * sp.w1.y);
+  q1 = make_float4(-0.5f * kLog2e * sp.w1.z, sp.w0.w, sp.w0.z, 0.0f);
+  q2 = sp.w2;
+}
+
+// Alpha of one pair. Returns false when the pair is skipped (exponent
+// positive or alpha below 1/255). G = exp(power), clamped = alpha hit 0.99.
+__device__ __forceinline__ bool pair_alpha(const float4& q0, const float4& q1, float xs, float ys, float& dx,
+                                           float& dy, float& G, float& alpha, bool& clamped) {
+  dx = q0.x - xs;
+  dy = q0.y - ys;
+  const float p2 = fmaf(q0.z * dx, dx, fmaf(q1.x * dy, dy, q0.w * dx * dy));
+  G = __builtin_amdgcn_exp2f(p2);
+  const float araw = q1.y * G;
+  clamped = araw > kAlphaMax;
+  alpha = clamped ? kAlphaMax : araw;
+  return (p2 <= 0.0f) && (alpha >= kAlphaMin);
+}
+
+__device__ __forceinline__ int find_view(const ViewDesc* views, int num_views, int tile) {
+  int v = 0;
+  while (v + 1 < num_views && tile >= views[v + 1].tile_offset) ++v;
+  return v;
+}
+
+template <int TW, int TH>
+__global__ void __launch_bounds__(TW* TH) blend_forward_kernel(BlendArgs a) {
+  constexpr int NT = TW * TH;
+  constexpr int BATCH = NT;
+  __shared__ float4 s_q0[BATCH], s_q1[BATCH], s_q2[BATCH];
+  const int tile = blockIdx.x;
+  const int view = find_view(a.views, a.num_views, tile);
+  const ViewDesc& V = a.views[view];
+  const int lt = tile - V.tile_offset;
+  const int tx = lt % V.tiles_x, ty = lt / V.tiles_x;
+  const int tid = threadIdx.x;
+  const int px = tx * TW + (tid % TW), py = ty * TH + (tid / TW);
+  const bool inside = px < V.width && py < V.height;
+  const float xs = (float)px + 0.5f, ys = (float)py + 0.5f;
+  const uint2 rg = a.ranges[tile];
+  float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, D = 0.0f;
+  uint32_t last = 0;
+  bool done = !inside;
+  for (uint32_t b0 = rg.x; b0 < rg.y; b0 += BATCH) {
+    if (__syncthreads_count(done) == NT) break;
+    const uint32_t j = b0 + tid;
+    if (j < rg.y) {
+      const Splat sp = a.splats[a.inst_vals[j]];
+      stage_record(sp, s_q0[tid], s_q1[tid], s_q2[tid]);
+    }
+    __syncthreads();
+    const int cnt = (int)min((uint32_t)BATCH, rg.y - b0);
+    if (!done) {
+      for (int k = 0; k < cnt; ++k) {
+        const float4 q0 = s_q0[k], q1 = s_q1[k];
+        float dx, dy, G, alpha;
+        bool clamped;
+        if (!pair_alpha(q0, q1, xs, ys, dx, dy, G, alpha, clamped)) continue;
+        const float Tn = T * (1.0f - alpha);
+        if (Tn < kTransMin) {
+          done = true;
+          break;
+        }
+        const float4 q2 = s_q2[k];
+        const float w = alpha * T;
+        C0 = fmaf(w, q2.x, C0);
+        C1 = fmaf(w, q2.y, C1);
+        C2 = fmaf(w, q2.z, C2);
+        D = fmaf(w, q1.z, D);
+        T = Tn;
+        last = b0 + k - rg.x + 1;
+      }
+    }
+  }
+  if (inside) {
+    const ViewImages im = a.images[view];
+    const int64_t HW = (int64_t)V.width * V.height;
+    const int64_t p = (int64_t)py * V.width + px;
+    im.rgb[p] = fmaf(T, a.bg[0], C0);
+    im.rgb[HW + p] = fmaf(T, a.bg[1], C1);
+    im.rgb[2 * HW + p] = fmaf(T, a.bg[2], C2);
+    im.depth[p] = D;
+    im.alpha[p] = 1.0f - T;
+    a.tfinal[V.pix_offset + p] = T;
+    a.last[V.pix_offset + p] = last;
+  }
+}
+
+__device__ __forceinline__ float wave_sum(float x) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, 64);
+  return x;
+}
+
+template <int TW, int TH>
+__global__ void __launch_bounds__(TW* TH) blend_backward_kernel(BlendArgs a) {
+  constexpr int NT = TW * TH;
+  constexpr int NW = NT / 64;
+  constexpr int BATCH = NT < 128 ? NT : 128;
+  __shared__ float4 s_q0[BATCH], s_q1[BATCH], s_q2[BATCH];
+  __shared__ uint32_t s_id[BATCH];
+  __shared__ float s_red[NW][G2_N][BATCH];
+  __shared__ uint32_t s_maxlast;
+  const int tile = blockIdx.x;
+  const int view = find_view(a.views, a.num_views, tile);
+  const ViewDesc& V = a.views[view];
+  const int lt = tile - V.tile_offset;
+  const int tx = lt % V.tiles_x, ty = lt / V.tiles_x;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int px = tx * TW + (tid % TW), py = ty * TH + (tid / TW);
+  const bool inside = px < V.width && py < V.height;
+  const float xs = (float)px + 0.5f, ys = (float)py + 0.5f;
+  const uint2 rg = a.ranges[tile];
+  const int64_t HW = (int64_t)V.width * V.height;
+  const int64_t p = (int64_t)py * V.width + px;
+  float T = 1.0f, gc0 = 0.f, gc1 = 0.f, gc2 = 0.f, gd = 0.f, ga = 0.f;
+  uint32_t mylast = 0;
+  if (tid == 0) s_maxlast = 0;
+  __syncthreads();
+  if (inside) {
+    T = a.tfinal[V.pix_offset + p];
+    mylast = a.last[V.pix_offset + p];
+    const ViewImages g = a.images[view];
+    if (g.rgb) {
+      gc0 = g.rgb[p];
+      gc1 = g.rgb[HW + p];
+      gc2 = g.rgb[2 * HW + p];
+    }
+    if (g.depth) gd = g.depth[p];
+    if (g.alpha) ga = g.alpha[p];
+    atomicMax(&s_maxlast, mylast);
+  }
+  const float tfin = T;
+  const float bgterm = ga - (gc0 * a.bg[0] + gc1 * a.bg[1] + gc2 * a.bg[2]);
+  float S = 0.0f;
+  __syncthreads();
+  const uint32_t maxlast = min(s_maxlast, rg.y - rg.x);
+  for (int64_t bend = (int64_t)rg.x + maxlast; bend > (int64_t)rg.x; bend -= BATCH) {
+    const int64_t b0 = bend - BATCH > (int64_t)rg.x ? bend - BATCH : (int64_t)rg.x;
+    const int cnt = (int)(bend - b0);
+    __syncthreads();
+    if (tid < cnt) {
+      const uint32_t sid = a.inst_vals[b0 + tid];
+      s_id[tid] = sid;
+      stage_record(a.splats[sid], s_q0[tid], s_q1[tid], s_q2[tid]);
+    }
+    __syncthreads();
+    for (int k = cnt - 1; k >= 0; --k) {
+      const uint32_t local = (uint32_t)(b0 + k - rg.x);
+      float v[G2_N];
+#pragma unroll
+      for (int c = 0; c < G2_N; ++c) v[c] = 0.0f;
+      bool contrib = false;
+      if (local < mylast) {
+        const float4 q0 = s_q0[k], q1 = s_q1[k];
+        float dx, dy, G, alpha;
+        bool clamped;
+        if (pair_alpha(q0, q1, xs, ys, dx, dy, G, alpha, clamped)) {
+          contrib = true;
+          const float4 q2 = s_q2[k];
+          const float r1m = __builtin_amdgcn_rcpf(1.0f - alpha);
+          T = T * r1m;                                    // T_k, transmittance before k
+          const float w = alpha * T;
+          v[G2_R] = w * gc0;
+          v[G2_G] = w * gc1;
+          v[G2_BL] = w * gc2;
+          v[G2_Z] = w * gd;
+          const float x = fmaf(gc0, q2.x, fmaf(gc1, q2.y, fmaf(gc2, q2.z, gd * q1.z)));
+          const float galpha = fmaf(T, x - S, tfin * bgterm * r1m);
+          S = fmaf(alpha, x, (1.0f - alpha) * S);
+          if (!clamped) {
+            v[G2_O] = galpha * G;
+            const float gpow = galpha * alpha;             // dL/dpower
+            const float gl = gpow * kLn2;
+            v[G2_U] = gl * fmaf(2.0f * q0.z, dx, q0.w * dy);
+            v[G2_V] = gl * fmaf(2.0f * q1.x, dy, q0.w * dx);
+            v[G2_A] = -0.5f * gpow * dx * dx;
+            v[G2_B] = -gpow * dx * dy;
+            v[G2_C] = -0.5f * gpow * dy * dy;
+          }
+        }
+      }
+      const bool any = __ballot(contrib) != 0ull;
+      if (any) {
+#pragma unroll
+        for (int c = 0; c < G2_N; ++c) v[c] = wave_sum(v[c]);
+      }
+      if (lane == 0) {
+#pragma unroll
+        for (int c = 0; c < G2_N; ++c) s_red[wave][c][k] = any ? v[c] : 0.0f;
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < cnt * G2_N; e += NT) {
+      const int c = e / cnt, k = e - c * cnt;
+      float sum = 0.0f;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) sum += s_red[w][c][k];
+      if (sum != 0.0f) unsafeAtomicAdd(&a.g2[(int64_t)s_id[k] * G2_N + c], sum);
+    }
+  }
+}
+
+template <int TW, int TH>
+void fwd_launch(const BlendArgs& a, hipStream_t st) {
+  blend_forward_kernel<TW, TH><<<a.num_tiles, TW * TH, 0, st>>>(a);
+}
+template <int TW, int TH>
+void bwd_launch(const BlendArgs& a, hipStream_t st) {
+  blend_backward_kernel<TW, TH><<<a.num_tiles, TW * TH, 0, st>>>(a);
+}
+
+__global__ void __launch_bounds__(256) loss_l1_kernel(const ViewDesc* __restrict__ views,
+                                                      const ViewImages* __restrict__ rendered,
+                                                      const ViewImages* __restrict__ target,
+                                                      const ViewImages* __restrict__ grad, float depth_weight,
+                                                      float* __restrict__ loss) {
+  __shared__ float wsum[4];
+  const int view = blockIdx.y;
+  const ViewDesc& V = views[view];
+  const int64_t HW = (int64_t)V.width * V.height;
+  const float inv3 = 1.0f / (3.0f * (float)HW), inv1 = depth_weight / (float)HW;
+  const ViewImages r = rendered[view], t = target[view], g = grad[view];
+  float acc = 0.0f;
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < HW; p += (int64_t)gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+      const float d = r.rgb[ch * HW + p] - t.rgb[ch * HW + p];
+      g.rgb[ch * HW + p] = d > 0.0f ? inv3 : (d < 0.0f ? -inv3 : 0.0f);
+      acc += fabsf(d) * inv3;
+    }
+    const float dd = r.depth[p] - t.depth[p];
+    g.depth[p] = dd > 0.0f ? inv1 : (dd < 0.0f ? -inv1 : 0.0f);
+    acc += fabsf(dd) * inv1;
+    if (g.alpha) g.alpha[p] = 0.0f;
+  }
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0 && loss) unsafeAtomicAdd(loss, wsum[0] + wsum[1] + wsum[2] + wsum[3]);
+}
+
+__global__ void __launch_bounds__(256) adam_kernel(float* __restrict__ p, const float* __restrict__ g,
+                                                   float* __restrict__ m, float* __restrict__ v, int64_t num,
+                                                   int64_t stride, int planes, const float* __restrict__ lr,
+                                                   float b1, float b2, float eps, float bc1, float bc2) {
+  const int64_t total = num * planes;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int plane = (int)(e / num);
+    const int64_t i = plane * stride + (e - (int64_t)plane * num);
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr[plane] * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+  }
+}
+
+int grid_cap(int64_t n, int block) {
+  int64_t gsz = (n + block - 1) / block;
+  if (gsz < 1) gsz = 1;
+  if (gsz > 16384) gsz = 16384;
+  return (int)gsz;
+}
+
+}  // namespace
+
+bool blend_supported(int tile_w, int tile_h) {
+  return (tile_w == 16 && tile_h == 16) || (tile_w == 16 && tile_h == 8) || (tile_w == 8 && tile_h == 8) ||
+         (tile_w == 32 && tile_h == 8);
+}
+
+void launch_blend_forward(const BlendArgs& a, int tile_w, int tile_h, hipStream_t st) {
+  if (a.num_tiles == 0) return;
+  if (tile_w == 16 && tile_h == 16) fwd_launch<16, 16>(a, st);
+  else if (tile_w == 16 && tile_h == 8) fwd_launch<16, 8>(a, st);
+  else if (tile_w == 8 && tile_h == 8) fwd_launch<8, 8>(a, st);
+  else if (tile_w == 32 && tile_h == 8) fwd_launch<32, 8>(a, st);
+}
+
+void launch_blend_backward(const BlendArgs& a, int tile_w, int tile_h, hipStream_t st) {
+  if (a.num_tiles == 0) return;
+  if (tile_w == 16 && tile_h == 16) bwd_launch<16, 16>(a, st);
+  else if (tile_w == 16 && tile_h == 8) bwd_launch<16, 8>(a, st);
+  else if (tile_w == 8 && tile_h == 8) bwd_launch<8, 8>(a, st);
+  else if (tile_w == 32 && tile_h == 8) bwd_launch<32, 8>(a, st);
+}
+
+void launch_loss_l1(const ViewDesc* views, const ViewImages* rendered, const ViewImages* target,
+                    const ViewImages* grad, int num_views, int max_pixels, float depth_weight, float* loss,
+                    hipStream_t st) {
+  if (loss) launch_fill_f32(loss, 0.0f, 1, st);
+  dim3 grid(grid_cap(max_pixels, 256) < 1024 ? grid_cap(max_pixels, 256) : 1024, num_views);
+  loss_l1_kernel<<<grid, 256, 0, st>>>(views, rendered, target, grad, depth_weight, loss);
+}
+
+void launch_adam(float* p, const float* g, float* m, float* v, int64_t num, int64_t stride, int planes,
+                 const float* lr_dev, float b1, float b2, float eps, float bc1, float bc2, hipStream_t st) {
+  const int64_t total = num * planes;
+  if (total == 0) return;
+  adam_kernel<<<grid_cap(total, 256), 256, 0, st>>>(p, g, m, v, num, stride, planes, lr_dev, b1, b2, eps, bc1, bc2);
+}
+
+}  // namespace gsr

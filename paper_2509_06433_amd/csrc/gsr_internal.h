@@ -1,0 +1,104 @@
+// Internal declarations shared by the HIP translation units of libgsr.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gsr {
+
+// Per-view constants the kernels read from device memory.
+struct ViewDesc {
+  float R[9];
+  float t[3];
+  float fx, fy, cx, cy;
+  float campos[3];        // camera centre in world coordinates, -R^T t
+  int32_t width, height;
+  int32_t tiles_x, tiles_y;
+  int32_t tile_offset;    // first global tile id of this view
+  int32_t pix_offset;     // first pixel of this view in per-pixel scratch
+};
+
+// Per-view image pointers (forward outputs, backward inputs, loss targets).
+struct ViewImages {
+  float* rgb;
+  float* depth;
+  float* alpha;
+};
+
+// Projected splat of one (view, Gaussian): three 16-byte words.
+//   w0 = (u, v, z, opacity)  w1 = (A, B, C, 0) conic  w2 = (r, g, b, 0)
+struct Splat {
+  float4 w0, w1, w2;
+};
+
+// Screen-space gradient of one (view, Gaussian), accumulated by atomics.
+enum { G2_U = 0, G2_V, G2_A, G2_B, G2_C, G2_O, G2_R, G2_G, G2_BL, G2_Z, G2_N };
+
+constexpr float kAlphaMax = 0.99f;
+constexpr float kAlphaMin = 1.0f / 255.0f;
+constexpr float kTransMin = 1e-4f;
+
+// ---- project.hip ---------------------------------------------------------
+// One thread per (view, Gaussian). Writes splats[s], rect[s] (pixel rectangle,
+// inclusive; x1 < x0 when culled), ntiles[s] and depth key zkey[s] (raw float
+// bits of z, 0xFFFFFFFF when culled); s = view * N + i.
+void launch_project(const float* params, int64_t n, int64_t stride, int deg, int num_views,
+                    const ViewDesc* views, int tile_w, int tile_h, float znear, Splat* splats,
+                    int4* rect, uint32_t* ntiles, uint32_t* zkey, uint32_t* svals, hipStream_t st);
+// Chain rule from screen-space gradients g2[V*N][10] to grad_params (+=).
+void launch_project_backward(const float* params, int64_t n, int64_t stride, int deg, int num_views,
+                             const ViewDesc* views, float znear, const float* g2, float* grad,
+                             hipStream_t st);
+// Inspection copy of the splats of one view: out[n][16] (see gsr_copy_splats).
+void launch_export_splats(const float* params, int64_t n, int64_t stride, const ViewDesc* view, float znear,
+                          const Splat* splats, const int4* rect, float* out, hipStream_t st);
+
+// ---- sort.hip --------------------------------------------------------------
+// Scratch sizes (in uint32 elements) a radix sort of n keys needs.
+void radix_scratch_sizes(int64_t n, int64_t* hist_elems, int64_t* partial_elems);
+// Stable LSD radix sort of (keys, vals) on the low `bits` bits of the keys,
+// 8 bits per pass, ping-ponging between the buffers; on return keys/vals point
+// at the sorted data and keys_alt/vals_alt at the other pair.
+void radix_sort_pairs(uint32_t*& keys, uint32_t*& vals, uint32_t*& keys_alt, uint32_t*& vals_alt, int64_t n,
+                      int bits, uint32_t* hist, uint32_t* partials, hipStream_t st);
+// Exclusive scan out[r] = sum_{j<r} in[idx[r]] (idx may be null); total -> *total_dev.
+void scan_gather_exclusive(const uint32_t* in, const uint32_t* idx, uint32_t* out, int64_t n,
+                           uint32_t* total_dev, uint32_t* partials, hipStream_t st);
+// Instance emission in depth order; writes beyond `capacity` are dropped.
+void launch_emit(const uint32_t* sorted_s, const uint32_t* offsets, const int4* rect, int64_t count,
+                 int64_t n, const ViewDesc* views, int tile_w, int tile_h, uint32_t* keys,
+                 uint32_t* vals, int64_t capacity, hipStream_t st);
+// ranges[t] = (start, end) of global tile t in the sorted key array.
+void launch_tile_ranges(const uint32_t* keys, int64_t count, uint2* ranges, int64_t num_tiles,
+                        hipStream_t st);
+void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
+// out[0] = sum of last[0..npix); out[1+v] = number of nonzero ntiles in view v's segment of n.
+void launch_count_work(const uint32_t* last, int64_t npix, const uint32_t* ntiles, int64_t n, int num_views,
+                       unsigned long long* out, hipStream_t st);
+void launch_fill_f32(float* p, float v, int64_t n, hipStream_t st);
+
+// ---- blend.hip -------------------------------------------------------------
+struct BlendArgs {
+  const ViewDesc* views;
+  const ViewImages* images;     // forward: outputs; backward: dL/dimage
+  int32_t num_views;
+  int32_t num_tiles;
+  const uint2* ranges;
+  const uint32_t* inst_vals;    // splat index per sorted instance
+  const Splat* splats;
+  float* tfinal;                // per pixel, all views
+  uint32_t* last;               // per pixel: index (within the tile list) after the last composited
+  float* g2;                    // backward: screen-space gradient accumulators [V*N][10]
+  float bg[3];
+};
+bool blend_supported(int tile_w, int tile_h);
+void launch_blend_forward(const BlendArgs& a, int tile_w, int tile_h, hipStream_t st);
+void launch_blend_backward(const BlendArgs& a, int tile_w, int tile_h, hipStream_t st);
+void launch_loss_l1(const ViewDesc* views, const ViewImages* rendered, const ViewImages* target,
+                    const ViewImages* grad, int num_views, int max_pixels, float depth_weight,
+                    float* loss, hipStream_t st);
+void launch_adam(float* p, const float* g, float* m, float* v, int64_t num, int64_t stride,
+                 int planes, const float* lr_dev, float b1, float b2, float eps, float bc1,
+                 float bc2, hipStream_t st);
+
+}  // namespace gsr

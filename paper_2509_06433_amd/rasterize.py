@@ -1,0 +1,103 @@
+"""Differentiable rasterization for torch: a context object and an
+autograd Function whose forward and backward are the library's HIP kernels.
+
+The backward saves nothing per Gaussian: it calls gsr_render_backward, which
+recomputes each pixel's transmittance in reverse order from the final value
+the forward stored in the context.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import _lib
+
+
+class Rasterizer:
+    """Owns one gsr context (device scratch) and its options."""
+
+    def __init__(self, tile_w=16, tile_h=16, bg=(0.0, 0.0, 0.0), znear=0.2):
+        self.tile_w, self.tile_h = tile_w, tile_h
+        self.bg = tuple(float(x) for x in bg)
+        self.znear = znear
+        self.handle = _lib.gsr_create(tile_w, tile_h, 0, self.bg, znear)
+
+    def close(self):
+        if self.handle is not None:
+            _lib.gsr_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def alloc_images(cams, device="cuda"):
+        return [(torch.empty(3, c.height, c.width, device=device),
+                 torch.empty(c.height, c.width, device=device),
+                 torch.empty(c.height, c.width, device=device)) for c in cams]
+
+    def render(self, params, sh_degree, cams, outs=None):
+        if outs is None:
+            outs = self.alloc_images(cams, params.device)
+        _lib.gsr_render(self.handle, params, sh_degree, cams, outs)
+        return outs
+
+    def render_backward(self, params, sh_degree, cams, grads, grad_params=None):
+        if grad_params is None:
+            grad_params = torch.zeros_like(params)
+        _lib.gsr_render_backward(self.handle, params, sh_degree, cams, grads, grad_params)
+        return grad_params
+
+    def loss_l1(self, cams, rendered, targets, depth_weight=0.5):
+        grads = [(torch.empty_like(r[0]), torch.empty_like(r[1]), torch.empty_like(r[2])) for r in rendered]
+        loss = torch.empty(1, device=rendered[0][0].device)
+        _lib.gsr_loss_l1(self.handle, cams, rendered, targets, grads, depth_weight, loss)
+        return loss, grads
+
+    def adam_step(self, params, grads, m, v, lr_per_plane, step, beta1=0.9, beta2=0.999, eps=1e-15):
+        _lib.gsr_adam_step(self.handle, params, grads, m, v, lr_per_plane, step, beta1, beta2, eps)
+
+    def status(self):
+        return _lib.gsr_query_status(self.handle)
+
+    def set_profiling(self, stages=None):
+        _lib.gsr_set_profiling(self.handle, stages)
+
+    def profile(self, reset=True):
+        return _lib.gsr_get_profile(self.handle, reset)
+
+    def count_work(self, num_views):
+        return _lib.gsr_count_work(self.handle, num_views)
+
+    def instances(self):
+        return _lib.gsr_copy_instances(self.handle)
+
+    def splats(self, view, num):
+        return _lib.gsr_copy_splats(self.handle, view, num)
+
+
+class Rasterize(torch.autograd.Function):
+    """rgb_0, depth_0, alpha_0, rgb_1, ... = Rasterize.apply(params, sh_degree, cams, rasterizer)."""
+
+    @staticmethod
+    def forward(ctx, params, sh_degree, cams, rasterizer):
+        outs = rasterizer.render(params.detach(), sh_degree, cams)
+        ctx.save_for_backward(params)
+        ctx.sh_degree, ctx.cams, ctx.rasterizer = sh_degree, cams, rasterizer
+        return tuple(t for o in outs for t in o)
+
+    @staticmethod
+    def backward(ctx, *grads):
+        (params,) = ctx.saved_tensors
+        per_view = [tuple(g.contiguous() if g is not None else None for g in grads[3 * v:3 * v + 3])
+                    for v in range(len(ctx.cams))]
+        gp = ctx.rasterizer.render_backward(params.detach(), ctx.sh_degree, ctx.cams, per_view)
+        return gp, None, None, None
+
+
+def rasterize(params, sh_degree, cams, rasterizer):
+    """List of (rgb, depth, alpha) per view, differentiable with respect to params."""
+    flat = Rasterize.apply(params, sh_degree, cams, rasterizer)
+    return [tuple(flat[3 * v:3 * v + 3]) for v in range(len(cams))]

@@ -1,0 +1,53 @@
+"""Tolerance metrics shared by the GPU parity tests.
+
+Images (colour, depth): |x - ref| <= 1e-5 * max(|ref|, 0.01 * max|ref| of that
+plane), evaluated on pixels whose compositing decisions are not ambiguous.
+A pixel is ambiguous when some decision it took (alpha >= 1/255, alpha clamp
+at 0.99, T (1 - alpha) >= 1e-4, exponent <= 0) lies within 1e-5 relative of
+its threshold in the FP32 oracle: there the GPU's FP32 exponential (a few ulp
+from the oracle's) may take the other branch.
+
+Gradients: per parameter group, |g - ref| <= 1e-3 * max(|ref|, 0.01 * rms(ref)).
+"""
+import numpy as np
+
+IMG_RTOL = 1e-5
+GRAD_RTOL = 1e-3
+AMBIGUOUS_MARGIN = 1e-5
+
+GROUPS = {"mean": slice(0, 3), "logscale": slice(3, 6), "quat": slice(6, 10), "logit": slice(10, 11)}
+
+
+def image_violations(x, ref, mask=None, rtol=IMG_RTOL):
+    """(number of pixels outside tolerance, worst |x - ref| / tolerance) over `mask`."""
+    x = np.asarray(x, np.float64)
+    ref = np.asarray(ref, np.float64)
+    floor = 0.01 * np.abs(ref).max() if ref.size else 0.0
+    tol = rtol * np.maximum(np.abs(ref), floor)
+    tol = np.where(tol > 0, tol, 1e-30)
+    ratio = np.abs(x - ref) / tol
+    if mask is not None:
+        ratio = np.where(mask, ratio, 0.0)
+    return int((ratio > 1.0).sum()), float(ratio.max(initial=0.0))
+
+
+def grad_groups(P):
+    g = dict(GROUPS)
+    g["sh"] = slice(11, P)
+    return g
+
+
+def grad_violations(g, ref, rtol=GRAD_RTOL):
+    """Returns {group: (violations, worst relative error, relative L2)}."""
+    out = {}
+    P = ref.shape[0]
+    for name, sl in grad_groups(P).items():
+        a = np.asarray(g[sl], np.float64).ravel()
+        b = np.asarray(ref[sl], np.float64).ravel()
+        rms = np.sqrt(np.mean(b * b)) if b.size else 0.0
+        scale = np.maximum(np.abs(b), 0.01 * rms)
+        scale = np.where(scale > 0, scale, 1e-30)
+        rel = np.abs(a - b) / scale
+        l2 = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+        out[name] = (int((rel > rtol).sum()), float(rel.max(initial=0.0)), float(l2))
+    return out

@@ -1,0 +1,343 @@
+"""GPU parity: the HIP path against the CPU oracle on the same seeded inputs.
+
+Bit-exact: projected geometry (u, v, z, screen covariance, conic, opacity,
+pixel rectangle) and the sorted instance list. Colour/depth/alpha within
+1e-5 relative of the FP32 oracle off ambiguous pixels; parameter gradients
+within 1e-3 relative of the FP64 oracle with FP32-pinned decisions.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import scenes
+from scenes import identity_camera
+from parity import AMBIGUOUS_MARGIN, grad_violations, image_violations
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    from paper_2509_06433_amd import rasterize
+    return rasterize
+
+
+def make(gpu, **kw):
+    return gpu.Rasterizer(**kw)
+
+
+def to_dev(p):
+    return torch.from_numpy(np.ascontiguousarray(p)).cuda()
+
+
+def scene_cases():
+    s_small = scenes.small_128x96()
+    s_tiny = scenes.tiny_random(3, n=40, width=45, height=37)
+    s_sh3 = scenes.tiny_random(6, n=60, width=50, height=42, sh_degree=3)
+    return {"small": s_small, "tiny_ragged": s_tiny, "tiny_sh3": s_sh3}
+
+
+CASES = scene_cases()
+
+
+# ---------------------------------------------------------------------------
+# projection and binning: bit-exact
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_projection_bit_exact(gpu, orc, name):
+    s = CASES[name]
+    say("case", name)
+    R = make(gpu)
+    p = to_dev(s.params)
+    R.render(p, s.sh_degree, s.cameras)
+    sp = R.splats(0, s.num)
+    ref = orc.project(s.params, s.sh_degree, s.cameras[0], prec=32)
+    vis = ref["vis"]
+    assert np.array_equal(sp[:, 15] >= 0, vis)
+    f32 = lambda x: np.asarray(x, np.float32)
+    for col, key in [(0, "u"), (1, "v"), (2, "z"), (3, "a"), (4, "b"), (5, "c"), (6, "A"), (7, "B"), (8, "C"),
+                     (9, "o")]:
+        assert np.array_equal(sp[vis, col], f32(ref[key][vis])), key
+    assert np.array_equal(sp[vis, 13:16].astype(np.int32), ref["rect"][vis, :3])
+    for col, key in [(10, "r"), (11, "g"), (12, "b_")]:
+        assert np.allclose(sp[vis, col], ref[key][vis], rtol=2e-6, atol=1e-7), key
+
+
+@pytest.mark.parametrize("tile", [(16, 16), (16, 8), (8, 8), (32, 8)])
+@pytest.mark.parametrize("name", list(CASES))
+def test_tile_list_bit_exact(gpu, orc, name, tile):
+    s = CASES[name]
+    say("case", name, tile)
+    R = make(gpu, tile_w=tile[0], tile_h=tile[1])
+    R.render(to_dev(s.params), s.sh_degree, s.cameras)
+    t_gpu, g_gpu = R.instances()
+    t_ref, g_ref = orc.tile_list(s.params, s.sh_degree, s.cameras, tile[0], tile[1])
+    assert len(t_gpu) == len(t_ref)
+    assert np.array_equal(t_gpu, t_ref)
+    assert np.array_equal(g_gpu, g_ref)
+
+
+def test_tile_list_multiview_bit_exact(gpu, orc):
+    s = scenes.tiny_random(4, n=80, width=45, height=37)
+    cams = [s.cameras[0], identity_camera(29, 21, 25.0), scenes.look_at_camera([0.3, 0.1, -0.5], [0, 0, 2], 64, 33, 40.0)]
+    R = make(gpu)
+    R.render(to_dev(s.params), 0, cams)
+    t_gpu, g_gpu = R.instances()
+    t_ref, g_ref = orc.tile_list(s.params, 0, cams, 16, 16)
+    assert np.array_equal(t_gpu, t_ref) and np.array_equal(g_gpu, g_ref)
+
+
+# ---------------------------------------------------------------------------
+# forward images: 1e-5 relative off ambiguous pixels
+# ---------------------------------------------------------------------------
+
+def check_images(outs, ref, label):
+    rgb, depth, alpha = [o.cpu().numpy() for o in outs]
+    mask = ref["margin"] >= AMBIGUOUS_MARGIN
+    amb = int((~mask).sum())
+    say(label, "ambiguous pixels", amb, "of", mask.size)
+    assert amb <= max(2, 2e-3 * mask.size)
+    worst = {}
+    for ch in range(3):
+        nbad, worst[f"rgb{ch}"] = image_violations(rgb[ch], ref["rgb"][ch], mask)
+        assert nbad == 0, (label, "rgb", ch, worst)
+    nbad, worst["depth"] = image_violations(depth, ref["depth"], mask)
+    assert nbad == 0, (label, "depth", worst)
+    nbad, worst["alpha"] = image_violations(alpha, ref["alpha"], mask)
+    assert nbad == 0, (label, "alpha", worst)
+    say(label, "worst ratio to tolerance", worst)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_forward_matches_fp32_oracle(gpu, orc, name):
+    s = CASES[name]
+    say("case", name)
+    R = make(gpu)
+    outs = R.render(to_dev(s.params), s.sh_degree, s.cameras)
+    ref = orc.render(s.params, s.sh_degree, s.cameras[0], mode="f32")
+    check_images(outs[0], ref, name)
+
+
+def test_forward_background(gpu, orc):
+    s = CASES["tiny_ragged"]
+    bg = (0.25, 0.5, 0.75)
+    R = make(gpu, bg=bg)
+    outs = R.render(to_dev(s.params), 0, s.cameras)
+    ref = orc.render(s.params, 0, s.cameras[0], mode="f32", bg=bg)
+    check_images(outs[0], ref, "bg")
+
+
+# ---------------------------------------------------------------------------
+# backward: 1e-3 relative against the FP64 oracle (FP32-pinned decisions)
+# ---------------------------------------------------------------------------
+
+def masked_grads(orc, s, seed):
+    grads = scenes.random_image_grads(seed, s.cameras)
+    out = []
+    for cam, (gr, gd, ga) in zip(s.cameras, grads):
+        r = orc.render(s.params, s.sh_degree, cam, mode="f32")
+        keep = (r["margin"] >= AMBIGUOUS_MARGIN).astype(np.float32)
+        out.append((gr * keep[None], gd * keep, ga * keep))
+    return out
+
+
+def check_grads(g, ref, label):
+    res = grad_violations(g, ref)
+    say(label, res)
+    for grp, (nbad, worst, l2) in res.items():
+        assert nbad == 0, (label, grp, nbad, worst, l2)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_backward_matches_fp64_oracle(gpu, orc, name):
+    s = CASES[name]
+    say("case", name)
+    grads = masked_grads(orc, s, 1)
+    R = make(gpu)
+    p = to_dev(s.params)
+    R.render(p, s.sh_degree, s.cameras)
+    dgr = [tuple(to_dev(x) for x in gv) for gv in grads]
+    g = R.render_backward(p, s.sh_degree, s.cameras, dgr).cpu().numpy()
+    ref = orc.backward(s.params, s.sh_degree, s.cameras, grads, pinned=True)
+    check_grads(g, ref, name)
+
+
+def test_backward_multiview_sums(gpu, orc):
+    s = scenes.tiny_random(4, n=50, width=40, height=30)
+    s.cameras = [s.cameras[0], scenes.look_at_camera([0.3, 0.1, -0.5], [0, 0, 2], 36, 28, 30.0)]
+    grads = masked_grads(orc, s, 2)
+    R = make(gpu)
+    p = to_dev(s.params)
+    R.render(p, 0, s.cameras)
+    g = R.render_backward(p, 0, s.cameras, [tuple(to_dev(x) for x in gv) for gv in grads]).cpu().numpy()
+    ref = orc.backward(s.params, 0, s.cameras, grads, pinned=True)
+    check_grads(g, ref, "multiview")
+
+
+def test_autograd_function(gpu, orc):
+    s = CASES["tiny_ragged"]
+    R = make(gpu)
+    p = to_dev(s.params).requires_grad_(True)
+    (rgb, depth, alpha), = gpu.rasterize(p, 0, s.cameras, R)
+    grads = masked_grads(orc, s, 3)
+    gr, gd, ga = [to_dev(x) for x in grads[0]]
+    L = (rgb * gr).sum() + (depth * gd).sum() + (alpha * ga).sum()
+    L.backward()
+    ref = orc.backward(s.params, 0, s.cameras, grads, pinned=True)
+    check_grads(p.grad.cpu().numpy(), ref, "autograd")
+
+
+# ---------------------------------------------------------------------------
+# loss and Adam
+# ---------------------------------------------------------------------------
+
+def test_loss_matches_oracle(gpu, orc):
+    s = CASES["small"]
+    R = make(gpu)
+    outs = R.render(to_dev(s.params), 0, s.cameras)
+    rng = np.random.default_rng(0)
+    trgb = rng.random((3, 96, 128)).astype(np.float32)
+    tdep = (rng.random((96, 128)) * 4).astype(np.float32)
+    tgt = [(to_dev(trgb), to_dev(tdep), None)]
+    loss, grads = R.loss_l1(s.cameras, outs, tgt)
+    L, gr, gd = orc.l1_loss_and_grad(outs[0][0].cpu().numpy(), outs[0][1].cpu().numpy(), trgb, tdep)
+    assert np.isclose(loss.item(), L, rtol=1e-5)
+    assert np.allclose(grads[0][0].cpu().numpy(), gr, rtol=1e-6, atol=0)
+    assert np.allclose(grads[0][1].cpu().numpy(), gd, rtol=1e-6, atol=0)
+    assert (grads[0][2].cpu().numpy() == 0).all()
+
+
+def test_adam_matches_oracle(gpu, orc):
+    rng = np.random.default_rng(2)
+    P, n = 14, 1000
+    x0 = rng.normal(size=(P, n)).astype(np.float32)
+    lrs = np.linspace(1e-3, 1e-2, P).astype(np.float32)
+    R = make(gpu)
+    x = to_dev(x0)
+    m = torch.zeros_like(x)
+    v = torch.zeros_like(x)
+    xr, mr, vr = x0.astype(np.float64), np.zeros((P, n)), np.zeros((P, n))
+    for step in range(1, 4):
+        g = rng.normal(size=(P, n)).astype(np.float32)
+        R.adam_step(x, to_dev(g), m, v, lrs, step)
+        xr, mr, vr = orc.adam_step(xr, g, mr, vr, step, lrs.astype(np.float64))
+    upd = np.abs(xr - x0)
+    assert np.all(np.abs(x.cpu().numpy() - xr) <= 1e-5 * upd + 1e-7)
+
+
+# ---------------------------------------------------------------------------
+# invariants of the tiled method
+# ---------------------------------------------------------------------------
+
+def test_tile_size_invariance(gpu):
+    s = CASES["small"]
+    p = to_dev(s.params)
+    ref = None
+    for tile in [(16, 16), (16, 8), (8, 8), (32, 8)]:
+        outs = make(gpu, tile_w=tile[0], tile_h=tile[1]).render(p, 0, s.cameras)
+        cur = [o.cpu().numpy() for o in outs[0]]
+        if ref is None:
+            ref = cur
+        else:
+            for a, b in zip(cur, ref):
+                assert np.array_equal(a, b), tile
+
+
+def test_batched_equals_single(gpu):
+    s = scenes.tiny_random(4, n=200, width=45, height=37)
+    cams = [s.cameras[0], identity_camera(29, 21, 25.0), scenes.look_at_camera([0.3, 0.1, -0.5], [0, 0, 2], 64, 33, 40.0)]
+    p = to_dev(s.params)
+    R = make(gpu)
+    both = R.render(p, 0, cams)
+    for v, cam in enumerate(cams):
+        one = make(gpu).render(p, 0, [cam])
+        for a, b in zip(both[v], one[0]):
+            assert torch.equal(a, b)
+
+
+def test_forward_deterministic_and_permutation_invariant(gpu):
+    s = CASES["small"]
+    R = make(gpu)
+    a = [o.clone() for o in R.render(to_dev(s.params), 0, s.cameras)[0]]
+    b = R.render(to_dev(s.params), 0, s.cameras)[0]
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+    perm = np.random.default_rng(7).permutation(s.num)
+    c = R.render(to_dev(s.params[:, perm]), 0, s.cameras)[0]
+    for x, y in zip(a, c):
+        assert torch.equal(x, y)
+
+
+# ---------------------------------------------------------------------------
+# edge cases
+# ---------------------------------------------------------------------------
+
+def test_empty_and_culled(gpu, orc):
+    R = make(gpu, bg=(0.1, 0.2, 0.3))
+    cam = identity_camera(33, 17, 20.0)
+    p = torch.zeros(14, 0, device="cuda")
+    outs = R.render(p, 0, [cam])
+    assert torch.allclose(outs[0][0][2], torch.full((17, 33), 0.3, device="cuda"))
+    assert (outs[0][2] == 0).all()
+    assert R.status()["instances"] == 0
+    g = R.render_backward(p, 0, [cam], [(torch.ones(3, 17, 33, device="cuda"), None, None)])
+    assert g.shape == (14, 0)
+    # everything behind the camera
+    q = np.zeros((14, 5), np.float32)
+    q[2] = -3.0
+    q[6] = 1.0
+    outs = R.render(to_dev(q), 0, [cam])
+    assert (outs[0][2] == 0).all()
+    assert R.status()["instances"] == 0
+
+
+def test_one_pixel_and_huge_gaussian(gpu, orc):
+    cam1 = identity_camera(1, 1, 1.0)
+    big = np.zeros((14, 1), np.float32)
+    big[2], big[3:6], big[6], big[10] = 2.0, np.log(5.0), 1.0, 3.0
+    R = make(gpu)
+    outs = R.render(to_dev(big), 0, [cam1])
+    ref = orc.render(big, 0, cam1, mode="f32")
+    assert np.allclose(outs[0][2].cpu().numpy(), ref["alpha"], rtol=1e-6)
+    cam = identity_camera(200, 150, 100.0)
+    outs = R.render(to_dev(big), 0, [cam])
+    assert R.status()["instances"] == 13 * 10        # covers every tile
+    ref = orc.render(big, 0, cam, mode="f32")
+    check_images(outs[0], ref, "huge")
+
+
+def test_backward_without_forward_is_state_error(gpu):
+    from paper_2509_06433_amd._lib import GsrError
+    R = make(gpu)
+    s = CASES["tiny_ragged"]
+    p = to_dev(s.params)
+    with pytest.raises(GsrError) as e:
+        R.render_backward(p, 0, s.cameras, [(None, None, None)])
+    assert e.value.status == -4
+    R.render(p, 0, s.cameras)
+    other = [identity_camera(45, 37, 30.0)]
+    with pytest.raises(GsrError) as e:
+        R.render_backward(p, 0, other, [(None, None, None)])
+    assert e.value.status == -4
+
+
+def test_invalid_arguments(gpu):
+    from paper_2509_06433_amd import _lib
+    with pytest.raises(_lib.GsrError) as e:
+        _lib.gsr_create(tile_w=12, tile_h=12)
+    assert e.value.status == -6
+    R = make(gpu)
+    bad = identity_camera(0, 10, 10.0)
+    with pytest.raises(_lib.GsrError) as e:
+        R.render(torch.zeros(14, 3, device="cuda"), 0, [bad], outs=[(torch.empty(3, 10, 1, device="cuda"),) * 3])
+    assert e.value.status == -1
