@@ -153,7 +153,9 @@ def render(params, sh_degree, cam, mode="f32", prefilter=True, bg=(0.0, 0.0, 0.0
 def backward(params, sh_degree, cams, grads, pinned=True, bg=(0.0, 0.0, 0.0), znear=0.2, want_2d=False):
     """FP64 analytic gradient of sum_v <grads_v, (rgb_v, depth_v, alpha_v)> with respect
     to the parameters [P, N]. grads: list of (g_rgb [3,H,W], g_depth [H,W], g_alpha [H,W]).
-    pinned: decisions from the FP32 recurrence (True) or from FP64 itself (False)."""
+    pinned: False = FP64 decisions; True = decisions from the FP32 recurrence;
+    "splats32" = FP32 decisions and FP32-rounded screen-space splat values
+    (u, v, conic, opacity, colour, depth), FP64 arithmetic."""
     p = np.ascontiguousarray(params, np.float32)
     P, n = p.shape
     camf = np.ascontiguousarray(np.stack([_cam_floats(c) for c in cams]), np.float32)
@@ -164,7 +166,8 @@ def backward(params, sh_degree, cams, grads, pinned=True, bg=(0.0, 0.0, 0.0), zn
     galp = np.ascontiguousarray(np.concatenate([np.asarray(g[2], np.float32).ravel() for g in grads]))
     grad = np.empty((P, n), np.float64)
     g2 = np.empty((len(cams), n, 10), np.float64) if want_2d else None
-    rc = lib().orc_backward(int(bool(pinned)), p, n, n, int(sh_degree), len(cams), camf, wh, float(znear),
+    mode = 2 if pinned == "splats32" else int(bool(pinned))
+    rc = lib().orc_backward(mode, p, n, n, int(sh_degree), len(cams), camf, wh, float(znear),
                             np.ascontiguousarray(bg, np.float32), grgb, gdep, galp, grad,
                             g2.ctypes.data if want_2d else None)
     assert rc == 0

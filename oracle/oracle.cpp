@@ -23,7 +23,11 @@
 //               implementation of the same sequence reproduces it bit for bit.
 //   FP64 pinned the reference for gradients: values in double, every discrete
 //               decision (cull, depth order, skip, clamp, stop) taken from the
-//               FP32 recurrence evaluated alongside.
+//               FP32 recurrence evaluated alongside. A stricter variant also
+//               takes the per-Gaussian screen-space values the compositing
+//               uses (u, v, conic, opacity, colour, depth) rounded to FP32,
+//               the precision the method runs in, and differentiates the
+//               compositing and the projection in double from there.
 //   FP64        values and decisions in double (for finite differences).
 //
 // Parity status: pinned by closed forms, library routines, invariants,
@@ -573,14 +577,25 @@ void project_backward_one(const float* P, int64_t stride, int64_t i, int deg, co
 }
 
 // Blend backward for one view: accumulates screen-space gradients g2[n][10].
-// With `pinned`, decisions come from the FP32 recurrence, values from FP64.
+// With `pinned`, decisions come from the FP32 recurrence, values from FP64;
+// with `splats32` the compositing values are the FP32 projection's.
 void blend_backward_view(const float* P, int64_t n, int64_t stride, int deg, const float* camf, int width, int height,
                          float znear, const float* bg, const float* grgb, const float* gdepth, const float* galpha,
-                         bool pinned, std::vector<double>& g2out, std::vector<Proj<double>>& p64out) {
+                         bool pinned, bool splats32, std::vector<double>& g2out, std::vector<Proj<double>>& p64out) {
   Cam<float> c32 = make_cam<float>(camf, width, height);
   Cam<double> c64 = make_cam<double>(camf, width, height);
   std::vector<Proj<float>> p32 = project_all<float>(P, n, stride, deg, c32, znear);
   std::vector<Proj<double>> p64 = project_all<double>(P, n, stride, deg, c64, (double)znear);
+  // the chain rule to the parameters always uses the double projection
+  std::vector<Proj<double>> blendv = p64;
+  if (splats32)
+    for (int64_t i = 0; i < n; ++i) {
+      if (!p32[i].vis) continue;
+      Proj<double>& d = blendv[i];
+      const Proj<float>& f = p32[i];
+      d.u = f.u; d.v = f.v; d.z = f.z; d.A = f.A; d.B = f.B; d.C = f.C; d.o = f.o;
+      for (int ch = 0; ch < 3; ++ch) d.col[ch] = f.col[ch];
+    }
   std::vector<int64_t> order;
   if (pinned) {
     order = depth_order(p32);
@@ -603,7 +618,7 @@ void blend_backward_view(const float* P, int64_t n, int64_t stride, int deg, con
         trace.clear();
         double Tfin;
         if (pinned) {
-          PixelResult<float, double> r = composite_pixel<float, double>(p32, p64, order, p32, true, px, py, bg, &trace);
+          PixelResult<float, double> r = composite_pixel<float, double>(p32, blendv, order, p32, true, px, py, bg, &trace);
           Tfin = r.T;
         } else {
           PixelResult<double, double> r = composite_pixel<double, double>(p64, p64, order, p32, false, px, py, bg, &trace);
@@ -617,7 +632,7 @@ void blend_backward_view(const float* P, int64_t n, int64_t stride, int deg, con
         const double bgterm = ga - (gc[0] * bg[0] + gc[1] * bg[1] + gc[2] * bg[2]);
         for (int k = (int)trace.size() - 1; k >= 0; --k) {
           const Composited& e = trace[k];
-          const Proj<double>& g = p64[e.idx];
+          const Proj<double>& g = pinned ? blendv[e.idx] : p64[e.idx];
           const double al = e.alpha;
           T = T / (1.0 - al);
           const double xk = gc[0] * g.col[0] + gc[1] * g.col[1] + gc[2] * g.col[2] + gd * g.z;
@@ -756,7 +771,9 @@ int orc_render(int mode, int prefilter, const float* params, int64_t n, int64_t 
 }
 
 // Analytic gradient of sum_v <dL/dimage_v, image_v> with respect to the
-// parameters, summed over views. Images of view v start at the offsets
+// parameters, summed over views. pinned: 0 = FP64 decisions and values;
+// 1 = FP32 decisions, FP64 values; 2 = FP32 decisions and FP32 screen-space
+// splat values, FP64 arithmetic. Images of view v start at the offsets
 // img_off[v] (pixels) in grgb ([3][H][W] per view), gdepth and galpha
 // ([H][W] per view). grad[P][n] is overwritten. If g2 is not null it
 // receives the screen-space gradients [V][n][10] (u v A B C o r g b z).
@@ -771,7 +788,7 @@ int orc_backward(int pinned, const float* params, int64_t n, int64_t stride, int
     std::vector<double> g2v;
     std::vector<Proj<double>> p64;
     blend_backward_view(params, n, stride, deg, cams + 16 * v, W, H, znear, bg, grgb + 3 * off, gdepth + off,
-                        galpha + off, pinned != 0, g2v, p64);
+                        galpha + off, pinned != 0, pinned == 2, g2v, p64);
     if (g2) std::memcpy(g2 + (size_t)v * n * G2_N, g2v.data(), sizeof(double) * n * G2_N);
     Cam<double> c64 = make_cam<double>(cams + 16 * v, W, H);
 #pragma omp parallel for schedule(static)

@@ -125,6 +125,27 @@ __device__ __forceinline__ float wave_sum(float x) {
   return x;
 }
 
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_add(float x) {
+  const int y = __builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xF, false);
+  return x + __int_as_float(y);
+}
+
+// Sum over the 64 lanes of a wavefront with DPP moves only (no LDS traffic):
+// pairs and quads by quad permutes, the 16-lane rows by two rotations, then
+// row 0 + row 1 and row 2 + row 3 by a broadcast of lane 15 of the row above,
+// and rows 0-1 into rows 2-3 by a broadcast of lane 31. The total ends in
+// lane 63; other lanes hold partial sums.
+__device__ __forceinline__ float wave_sum_lane63(float x) {
+  x = dpp_add<0xB1, 0xF>(x);    // quad_perm [1,0,3,2]
+  x = dpp_add<0x4E, 0xF>(x);    // quad_perm [2,3,0,1]
+  x = dpp_add<0x124, 0xF>(x);   // row_ror:4
+  x = dpp_add<0x128, 0xF>(x);   // row_ror:8
+  x = dpp_add<0x142, 0xA>(x);   // row_bcast:15 into rows 1 and 3
+  x = dpp_add<0x143, 0xC>(x);   // row_bcast:31 into rows 2 and 3
+  return x;
+}
+
 template <int TW, int TH>
 __global__ void __launch_bounds__(TW* TH) blend_backward_kernel(BlendArgs a) {
   constexpr int NT = TW * TH;
@@ -217,9 +238,9 @@ __global__ void __launch_bounds__(TW* TH) blend_backward_kernel(BlendArgs a) {
       const bool any = __ballot(contrib) != 0ull;
       if (any) {
 #pragma unroll
-        for (int c = 0; c < G2_N; ++c) v[c] = wave_sum(v[c]);
+        for (int c = 0; c < G2_N; ++c) v[c] = wave_sum_lane63(v[c]);
       }
-      if (lane == 0) {
+      if (lane == 63) {
 #pragma unroll
         for (int c = 0; c < G2_N; ++c) s_red[wave][c][k] = any ? v[c] : 0.0f;
       }

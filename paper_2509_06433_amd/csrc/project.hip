@@ -47,6 +47,27 @@ __device__ __forceinline__ float exp_cw(float x) {
 
 __device__ __forceinline__ bool finitef(float x) { return __builtin_isfinite(x); }
 
+// Correctly rounded square root. The hardware square root is within one ulp;
+// the result is moved to the neighbour whose rounding interval contains the
+// exact root, decided by comparing x with the squares of the midpoints
+// between neighbouring floats (exact in double: 25-bit midpoints square to at
+// most 50 bits, and no float is the square of a midpoint).
+__device__ __forceinline__ float sqrt_rn(float x) {
+  float y = __builtin_sqrtf(x);
+  if (!(x > 0.0f) || !finitef(x)) return y;
+  const double xd = (double)x;
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const float up = __uint_as_float(__float_as_uint(y) + 1u);   // y > 0: neighbours by bit pattern
+    const float dn = __uint_as_float(__float_as_uint(y) - 1u);
+    const double mu = 0.5 * ((double)y + (double)up);
+    const double md = 0.5 * ((double)y + (double)dn);
+    if (mu * mu < xd) y = up;
+    else if (md * md > xd) y = dn;
+  }
+  return y;
+}
+
 // Real spherical harmonics (Condon-Shortley phase) up to degree 3 as
 // polynomials of the unit direction, normalisations sqrt((2l+1)/(4pi)
 // (l-m)!/(l+m)!) (times sqrt 2 for m != 0) folded into the constants.
@@ -84,49 +105,6 @@ __device__ __forceinline__ void sh_basis(int deg, float x, float y, float z, flo
   Y[15] = -SH_K0 * x * (xx - 3.0f * yy);
 }
 
-// Gradient of sum_k c_k Y_k with respect to the (unnormalised) direction,
-// treating each Y_k as the polynomial above.
-__device__ __forceinline__ void sh_dir_grad(int deg, float x, float y, float z, const float* c, float* g) {
-  g[0] = g[1] = g[2] = 0.0f;
-  if (deg < 1) return;
-  g[1] += -SH_C1 * c[1];
-  g[2] += SH_C1 * c[2];
-  g[0] += -SH_C1 * c[3];
-  if (deg < 2) return;
-  const float xx = x * x, yy = y * y, zz = z * z;
-  g[0] += SH_C2a * y * c[4];
-  g[1] += SH_C2a * x * c[4];
-  g[1] += -SH_C2a * z * c[5];
-  g[2] += -SH_C2a * y * c[5];
-  g[0] += -2.0f * SH_C2b * x * c[6];
-  g[1] += -2.0f * SH_C2b * y * c[6];
-  g[2] += 4.0f * SH_C2b * z * c[6];
-  g[0] += -SH_C2a * z * c[7];
-  g[2] += -SH_C2a * x * c[7];
-  g[0] += 2.0f * SH_C2c * x * c[8];
-  g[1] += -2.0f * SH_C2c * y * c[8];
-  if (deg < 3) return;
-  g[0] += -6.0f * SH_K0 * x * y * c[9];
-  g[1] += -SH_K0 * (3.0f * xx - 3.0f * yy) * c[9];
-  g[0] += SH_K1 * y * z * c[10];
-  g[1] += SH_K1 * x * z * c[10];
-  g[2] += SH_K1 * x * y * c[10];
-  g[0] += 2.0f * SH_K2 * x * y * c[11];
-  g[1] += -SH_K2 * (4.0f * zz - xx - 3.0f * yy) * c[11];
-  g[2] += -8.0f * SH_K2 * y * z * c[11];
-  g[0] += -6.0f * SH_K3 * x * z * c[12];
-  g[1] += -6.0f * SH_K3 * y * z * c[12];
-  g[2] += SH_K3 * (6.0f * zz - 3.0f * xx - 3.0f * yy) * c[12];
-  g[0] += -SH_K2 * (4.0f * zz - 3.0f * xx - yy) * c[13];
-  g[1] += 2.0f * SH_K2 * x * y * c[13];
-  g[2] += -8.0f * SH_K2 * x * z * c[13];
-  g[0] += 2.0f * SH_K5 * x * z * c[14];
-  g[1] += -2.0f * SH_K5 * y * z * c[14];
-  g[2] += SH_K5 * (xx - yy) * c[14];
-  g[0] += -SH_K0 * (3.0f * xx - 3.0f * yy) * c[15];
-  g[1] += 6.0f * SH_K0 * x * y * c[15];
-}
-
 // Everything the projection computes for one (view, Gaussian).
 struct ProjState {
   float s[3], qn, qh[4], R[9], M[9], Sig[9];
@@ -156,7 +134,7 @@ __device__ __forceinline__ bool project_geometry(const float* __restrict__ P, in
   ss = ss + qy * qy;
   ss = ss + qz * qz;
   if (!(ss > 0.0f) || !finitef(ss)) return false;
-  g.qn = __fsqrt_rn(ss);
+  g.qn = sqrt_rn(ss);
   const float w = __fdiv_rn(qw, g.qn), x = __fdiv_rn(qx, g.qn), y = __fdiv_rn(qy, g.qn), z = __fdiv_rn(qz, g.qn);
   g.qh[0] = w; g.qh[1] = x; g.qh[2] = y; g.qh[3] = z;
   float* R = g.R;
@@ -231,8 +209,8 @@ __device__ __forceinline__ bool project_geometry(const float* __restrict__ P, in
   g.u = __fdiv_rn(V.fx * g.tx, g.tz) + V.cx;
   g.v = __fdiv_rn(V.fy * g.ty, g.tz) + V.cy;
   if (!finitef(g.u) || !finitef(g.v)) return false;
-  const float ex = __fsqrt_rn(kQMax * a);
-  const float ey = __fsqrt_rn(kQMax * c);
+  const float ex = sqrt_rn(kQMax * a);
+  const float ey = sqrt_rn(kQMax * c);
   float x0 = ceilf((g.u - ex) - 0.5f);
   float x1 = floorf((g.u + ex) - 0.5f);
   float y0 = ceilf((g.v - ey) - 0.5f);
@@ -316,111 +294,246 @@ __global__ void __launch_bounds__(256) project_kernel(const float* __restrict__ 
   }
 }
 
+// Projection intermediates in double for the backward chain rule (the chain
+// rule is cheap next to the blend, and double keeps its cancellations -- the
+// conic inverse, the Jacobian terms of the depth -- out of the gradient).
+struct ProjD {
+  double s[3], qn, qh[4], R[9], M[9], Sig[9];
+  double tx, ty, tz, xi, yi;
+  bool xclamp, yclamp;
+  double Tm[6];
+  double a, b, c, det;
+};
+
+__device__ __forceinline__ void geometry_f64(const float* __restrict__ P, int64_t stride, int64_t i,
+                                             const ViewDesc& V, ProjD& g) {
+  const double mx = P[0 * stride + i], my = P[1 * stride + i], mz = P[2 * stride + i];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) g.s[k] = exp((double)P[(3 + k) * stride + i]);
+  const double qw = P[6 * stride + i], qx = P[7 * stride + i], qy = P[8 * stride + i], qz = P[9 * stride + i];
+  g.qn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+  const double w = qw / g.qn, x = qx / g.qn, y = qy / g.qn, z = qz / g.qn;
+  g.qh[0] = w; g.qh[1] = x; g.qh[2] = y; g.qh[3] = z;
+  double* R = g.R;
+  R[0] = 1.0 - 2.0 * (y * y + z * z);
+  R[1] = 2.0 * (x * y - w * z);
+  R[2] = 2.0 * (x * z + w * y);
+  R[3] = 2.0 * (x * y + w * z);
+  R[4] = 1.0 - 2.0 * (x * x + z * z);
+  R[5] = 2.0 * (y * z - w * x);
+  R[6] = 2.0 * (x * z - w * y);
+  R[7] = 2.0 * (y * z + w * x);
+  R[8] = 1.0 - 2.0 * (x * x + y * y);
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) g.M[r * 3 + k] = R[r * 3 + k] * g.s[k];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      g.Sig[r * 3 + k] = g.M[r * 3 + 0] * g.M[k * 3 + 0] + g.M[r * 3 + 1] * g.M[k * 3 + 1] +
+                         g.M[r * 3 + 2] * g.M[k * 3 + 2];
+  const float* W = V.R;
+  g.tx = W[0] * mx + W[1] * my + W[2] * mz + V.t[0];
+  g.ty = W[3] * mx + W[4] * my + W[5] * mz + V.t[1];
+  g.tz = W[6] * mx + W[7] * my + W[8] * mz + V.t[2];
+  const double limx = (double)kClampFov * (0.5 * (double)V.width / (double)V.fx);
+  const double limy = (double)kClampFov * (0.5 * (double)V.height / (double)V.fy);
+  const double xr = g.tx / g.tz, yr = g.ty / g.tz;
+  g.xclamp = (xr < -limx) || (xr > limx);
+  g.yclamp = (yr < -limy) || (yr > limy);
+  g.xi = fmin(fmax(xr, -limx), limx);
+  g.yi = fmin(fmax(yr, -limy), limy);
+  const double J00 = V.fx / g.tz, J02 = -(V.fx * g.xi) / g.tz;
+  const double J11 = V.fy / g.tz, J12 = -(V.fy * g.yi) / g.tz;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    g.Tm[k] = J00 * W[k] + J02 * W[6 + k];
+    g.Tm[3 + k] = J11 * W[3 + k] + J12 * W[6 + k];
+  }
+  double U[6];
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      U[r * 3 + k] = g.Tm[r * 3 + 0] * g.Sig[k] + g.Tm[r * 3 + 1] * g.Sig[3 + k] + g.Tm[r * 3 + 2] * g.Sig[6 + k];
+  g.a = U[0] * g.Tm[0] + U[1] * g.Tm[1] + U[2] * g.Tm[2] + (double)kDilation;
+  g.b = U[0] * g.Tm[3] + U[1] * g.Tm[4] + U[2] * g.Tm[5];
+  g.c = U[3] * g.Tm[3] + U[4] * g.Tm[4] + U[5] * g.Tm[5] + (double)kDilation;
+  g.det = g.a * g.c - g.b * g.b;
+}
+
+__device__ __forceinline__ void sh_basis_d(int deg, double x, double y, double z, double* Y) {
+  Y[0] = 0.28209479177387814;
+  if (deg < 1) return;
+  const double c1 = 0.4886025119029199;
+  Y[1] = -c1 * y; Y[2] = c1 * z; Y[3] = -c1 * x;
+  if (deg < 2) return;
+  const double xx = x * x, yy = y * y, zz = z * z;
+  Y[4] = 1.0925484305920792 * x * y;
+  Y[5] = -1.0925484305920792 * y * z;
+  Y[6] = 0.31539156525252005 * (2.0 * zz - xx - yy);
+  Y[7] = -1.0925484305920792 * x * z;
+  Y[8] = 0.5462742152960396 * (xx - yy);
+  if (deg < 3) return;
+  Y[9] = -0.5900435899266435 * y * (3.0 * xx - yy);
+  Y[10] = 2.890611442640554 * x * y * z;
+  Y[11] = -0.4570457994644658 * y * (4.0 * zz - xx - yy);
+  Y[12] = 0.3731763325901154 * z * (2.0 * zz - 3.0 * xx - 3.0 * yy);
+  Y[13] = -0.4570457994644658 * x * (4.0 * zz - xx - yy);
+  Y[14] = 1.445305721320277 * z * (xx - yy);
+  Y[15] = -0.5900435899266435 * x * (xx - 3.0 * yy);
+}
+
+// d/d(x, y, z) of sum_k c_k Y_k for the polynomials above.
+__device__ __forceinline__ void sh_dir_grad_d(int deg, double x, double y, double z, const double* c, double* g) {
+  g[0] = g[1] = g[2] = 0.0;
+  if (deg < 1) return;
+  const double C1 = 0.4886025119029199, C2a = 1.0925484305920792, C2b = 0.31539156525252005,
+               C2c = 0.5462742152960396, K0 = 0.5900435899266435, K1 = 2.890611442640554,
+               K2 = 0.4570457994644658, K3 = 0.3731763325901154, K5 = 1.445305721320277;
+  g[1] -= C1 * c[1];
+  g[2] += C1 * c[2];
+  g[0] -= C1 * c[3];
+  if (deg < 2) return;
+  const double xx = x * x, yy = y * y, zz = z * z;
+  g[0] += C2a * y * c[4];            g[1] += C2a * x * c[4];
+  g[1] -= C2a * z * c[5];            g[2] -= C2a * y * c[5];
+  g[0] -= 2.0 * C2b * x * c[6];      g[1] -= 2.0 * C2b * y * c[6];     g[2] += 4.0 * C2b * z * c[6];
+  g[0] -= C2a * z * c[7];            g[2] -= C2a * x * c[7];
+  g[0] += 2.0 * C2c * x * c[8];      g[1] -= 2.0 * C2c * y * c[8];
+  if (deg < 3) return;
+  g[0] -= 6.0 * K0 * x * y * c[9];   g[1] -= K0 * (3.0 * xx - 3.0 * yy) * c[9];
+  g[0] += K1 * y * z * c[10];        g[1] += K1 * x * z * c[10];      g[2] += K1 * x * y * c[10];
+  g[0] += 2.0 * K2 * x * y * c[11];  g[1] -= K2 * (4.0 * zz - xx - 3.0 * yy) * c[11];  g[2] -= 8.0 * K2 * y * z * c[11];
+  g[0] -= 6.0 * K3 * x * z * c[12];  g[1] -= 6.0 * K3 * y * z * c[12];  g[2] += K3 * (6.0 * zz - 3.0 * xx - 3.0 * yy) * c[12];
+  g[0] -= K2 * (4.0 * zz - 3.0 * xx - yy) * c[13];  g[1] += 2.0 * K2 * x * y * c[13];  g[2] -= 8.0 * K2 * x * z * c[13];
+  g[0] += 2.0 * K5 * x * z * c[14];  g[1] -= 2.0 * K5 * y * z * c[14];  g[2] += K5 * (xx - yy) * c[14];
+  g[0] -= K0 * (3.0 * xx - 3.0 * yy) * c[15];  g[1] += 6.0 * K0 * x * y * c[15];
+}
+
 // Chain rule from the screen-space gradients (u, v, conic, opacity, colour,
-// depth) of every view to the parameters, summed over views. One thread per
-// Gaussian, so the parameter gradients need no atomics.
+// depth) of every view to the parameters, summed over views, in double.
+// One thread per Gaussian, so the parameter gradients need no atomics.
+template <int DEG>
 __global__ void __launch_bounds__(256) project_backward_kernel(const float* __restrict__ P, int64_t n, int64_t stride,
-                                                               int deg, int num_views,
-                                                               const ViewDesc* __restrict__ views, float znear,
+                                                               int num_views, const ViewDesc* __restrict__ views,
                                                                const float* __restrict__ g2,
                                                                float* __restrict__ grad) {
+  constexpr int K = (DEG + 1) * (DEG + 1);
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const int K = (deg + 1) * (deg + 1);
-    float gmean[3] = {0.f, 0.f, 0.f}, gls[3] = {0.f, 0.f, 0.f}, gq[4] = {0.f, 0.f, 0.f, 0.f};
-    float glogit = 0.f;
-    float gsh[48];
-    for (int k = 0; k < 3 * K; ++k) gsh[k] = 0.f;
+    double gmean[3] = {0, 0, 0}, gls[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, glogit = 0.0;
+    double gsh[3 * K];
+#pragma unroll
+    for (int k = 0; k < 3 * K; ++k) gsh[k] = 0.0;
+    double coef[3][K];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) coef[ch][k] = P[(11 + 3 * k + ch) * stride + i];
     bool touched = false;
     for (int view = 0; view < num_views; ++view) {
       const float* gv = g2 + ((int64_t)view * n + i) * G2_N;
-      float G[G2_N];
-#pragma unroll
-      for (int k = 0; k < G2_N; ++k) G[k] = gv[k];
+      double G[G2_N];
       bool any = false;
 #pragma unroll
-      for (int k = 0; k < G2_N; ++k) any = any || (G[k] != 0.0f);
+      for (int k = 0; k < G2_N; ++k) {
+        G[k] = gv[k];
+        any = any || (G[k] != 0.0);
+      }
       if (!any) continue;
-      const ViewDesc& V = views[view];
-      ProjState g;
-      if (!project_geometry(P, stride, i, V, znear, g)) continue;
       touched = true;
+      const ViewDesc& V = views[view];
+      ProjD g;
+      geometry_f64(P, stride, i, V, g);
       // opacity
-      const float o = 1.0f / (1.0f + exp_cw(-P[10 * stride + i]));
-      glogit += G[G2_O] * o * (1.0f - o);
+      const double o = 1.0 / (1.0 + exp(-(double)P[10 * stride + i]));
+      glogit += G[G2_O] * o * (1.0 - o);
       // colour
-      float raw[3], col[3], dir[3], dnorm;
-      project_colour(P, stride, i, deg, V, raw, col, dir, &dnorm);
-      float Y[16];
-      sh_basis(deg, dir[0], dir[1], dir[2], Y);
-      float gdir[3] = {0.f, 0.f, 0.f};
+      double dir[3] = {0.0, 0.0, 0.0}, dnorm = 1.0;
+      if (DEG > 0) {
+        dir[0] = (double)P[0 * stride + i] - (double)V.campos[0];
+        dir[1] = (double)P[1 * stride + i] - (double)V.campos[1];
+        dir[2] = (double)P[2 * stride + i] - (double)V.campos[2];
+        dnorm = sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
+        dir[0] /= dnorm; dir[1] /= dnorm; dir[2] /= dnorm;
+      }
+      double Y[16];
+      sh_basis_d(DEG, dir[0], dir[1], dir[2], Y);
+      double gdir[3] = {0.0, 0.0, 0.0};
+#pragma unroll
       for (int ch = 0; ch < 3; ++ch) {
-        if (raw[ch] < 0.0f) continue;
-        const float gc = G[G2_R + ch];
+        double raw = 0.5;
+#pragma unroll
+        for (int k = 0; k < K; ++k) raw += coef[ch][k] * Y[k];
+        if (raw < 0.0) continue;
+        const double gc = G[G2_R + ch];
+#pragma unroll
         for (int k = 0; k < K; ++k) gsh[3 * k + ch] += gc * Y[k];
-        if (deg > 0) {
-          float coef[16], gd[3];
-          for (int k = 0; k < K; ++k) coef[k] = P[(11 + 3 * k + ch) * stride + i];
-          sh_dir_grad(deg, dir[0], dir[1], dir[2], coef, gd);
+        if (DEG > 0) {
+          double gd[3];
+          sh_dir_grad_d(DEG, dir[0], dir[1], dir[2], coef[ch], gd);
           gdir[0] += gc * gd[0];
           gdir[1] += gc * gd[1];
           gdir[2] += gc * gd[2];
         }
       }
-      if (deg > 0) {
-        const float dot = dir[0] * gdir[0] + dir[1] * gdir[1] + dir[2] * gdir[2];
+      if (DEG > 0) {
+        const double dot = dir[0] * gdir[0] + dir[1] * gdir[1] + dir[2] * gdir[2];
+#pragma unroll
         for (int j = 0; j < 3; ++j) gmean[j] += (gdir[j] - dir[j] * dot) / dnorm;
       }
       // conic (A, B, C) = (c, -b, a) / det
-      const float a = g.a, b = g.b, c = g.c, det = g.det;
-      const float id = 1.0f / det, id2 = id * id;
-      const float gA = G[G2_A], gB = G[G2_B], gC = G[G2_C];
-      const float ga = (-gA * c * c + gB * b * c - gC * b * b) * id2;
-      const float gb = (2.0f * gA * b * c - 2.0f * gB * b * b + 2.0f * gC * a * b) * id2 - gB * id;
-      const float gc_ = (-gA * b * b + gB * a * b - gC * a * a) * id2;
+      const double a = g.a, b = g.b, c = g.c, det = g.det;
+      const double id = 1.0 / det, id2 = id * id;
+      const double gA = G[G2_A], gB = G[G2_B], gC = G[G2_C];
+      const double ga = (-gA * c * c + gB * b * c - gC * b * b) * id2;
+      const double gb = (2.0 * gA * b * c - 2.0 * gB * b * b + 2.0 * gC * a * b) * id2 - gB * id;
+      const double gc_ = (-gA * b * b + gB * a * b - gC * a * a) * id2;
       // Sigma' = T Sigma T^T
-      const float* T0 = g.Tm;
-      const float* T1 = g.Tm + 3;
-      const float* S = g.Sig;
-      float ST0[3], ST1[3];
+      const double* T0 = g.Tm;
+      const double* T1 = g.Tm + 3;
+      const double* S = g.Sig;
+      double ST0[3], ST1[3];
 #pragma unroll
       for (int r = 0; r < 3; ++r) {
         ST0[r] = S[r * 3 + 0] * T0[0] + S[r * 3 + 1] * T0[1] + S[r * 3 + 2] * T0[2];
         ST1[r] = S[r * 3 + 0] * T1[0] + S[r * 3 + 1] * T1[1] + S[r * 3 + 2] * T1[2];
       }
-      float gT0[3], gT1[3];
+      double gT0[3], gT1[3];
 #pragma unroll
       for (int r = 0; r < 3; ++r) {
-        gT0[r] = 2.0f * ga * ST0[r] + gb * ST1[r];
-        gT1[r] = gb * ST0[r] + 2.0f * gc_ * ST1[r];
+        gT0[r] = 2.0 * ga * ST0[r] + gb * ST1[r];
+        gT1[r] = gb * ST0[r] + 2.0 * gc_ * ST1[r];
       }
-      // symmetric part of dL/dSigma, doubled: gS + gS^T
-      float gSS[9];
+      double gSS[9];
 #pragma unroll
       for (int r = 0; r < 3; ++r)
 #pragma unroll
         for (int k = 0; k < 3; ++k)
-          gSS[r * 3 + k] = 2.0f * ga * T0[r] * T0[k] + gb * (T0[r] * T1[k] + T1[r] * T0[k]) +
-                           2.0f * gc_ * T1[r] * T1[k];
+          gSS[r * 3 + k] = 2.0 * ga * T0[r] * T0[k] + gb * (T0[r] * T1[k] + T1[r] * T0[k]) +
+                           2.0 * gc_ * T1[r] * T1[k];
       const float* W = V.R;
-      float gJ00 = 0.f, gJ02 = 0.f, gJ11 = 0.f, gJ12 = 0.f;
+      double gJ00 = 0, gJ02 = 0, gJ11 = 0, gJ12 = 0;
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        gJ00 += gT0[k] * W[0 * 3 + k];
-        gJ02 += gT0[k] * W[2 * 3 + k];
-        gJ11 += gT1[k] * W[1 * 3 + k];
-        gJ12 += gT1[k] * W[2 * 3 + k];
+        gJ00 += gT0[k] * W[k];
+        gJ02 += gT0[k] * W[6 + k];
+        gJ11 += gT1[k] * W[3 + k];
+        gJ12 += gT1[k] * W[6 + k];
       }
-      const float tx = g.tx, ty = g.ty, tz = g.tz, fx = V.fx, fy = V.fy;
-      const float itz = 1.0f / tz, itz2 = itz * itz;
-      float gtx = 0.f, gty = 0.f, gtz = 0.f;
+      const double tx = g.tx, ty = g.ty, tz = g.tz, fx = V.fx, fy = V.fy;
+      const double itz = 1.0 / tz, itz2 = itz * itz;
+      double gtx = 0, gty = 0, gtz = 0;
       gtz += -gJ00 * fx * itz2 - gJ11 * fy * itz2 + gJ02 * fx * g.xi * itz2 + gJ12 * fy * g.yi * itz2;
       if (!g.xclamp) {
-        const float gxi = -gJ02 * fx * itz;
+        const double gxi = -gJ02 * fx * itz;
         gtx += gxi * itz;
         gtz += -gxi * tx * itz2;
       }
       if (!g.yclamp) {
-        const float gyi = -gJ12 * fy * itz;
+        const double gyi = -gJ12 * fy * itz;
         gty += gyi * itz;
         gtz += -gyi * ty * itz2;
       }
@@ -430,49 +543,46 @@ __global__ void __launch_bounds__(256) project_backward_kernel(const float* __re
       gtz += -G[G2_V] * fy * ty * itz2;
       gtz += G[G2_Z];
 #pragma unroll
-      for (int j = 0; j < 3; ++j) gmean[j] += W[0 * 3 + j] * gtx + W[1 * 3 + j] * gty + W[2 * 3 + j] * gtz;
+      for (int j = 0; j < 3; ++j) gmean[j] += W[j] * gtx + W[3 + j] * gty + W[6 + j] * gtz;
       // Sigma = M M^T, M = R diag(s)
-      float gM[9];
+      double gM[9];
 #pragma unroll
       for (int r = 0; r < 3; ++r)
 #pragma unroll
         for (int k = 0; k < 3; ++k)
-          gM[r * 3 + k] = gSS[r * 3 + 0] * g.M[0 * 3 + k] + gSS[r * 3 + 1] * g.M[1 * 3 + k] +
-                          gSS[r * 3 + 2] * g.M[2 * 3 + k];
-      float gR[9];
+          gM[r * 3 + k] = gSS[r * 3 + 0] * g.M[k] + gSS[r * 3 + 1] * g.M[3 + k] + gSS[r * 3 + 2] * g.M[6 + k];
+      double gR[9];
 #pragma unroll
       for (int r = 0; r < 3; ++r)
 #pragma unroll
         for (int k = 0; k < 3; ++k) gR[r * 3 + k] = gM[r * 3 + k] * g.s[k];
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const float gs = gM[0 * 3 + k] * g.R[0 * 3 + k] + gM[1 * 3 + k] * g.R[1 * 3 + k] + gM[2 * 3 + k] * g.R[2 * 3 + k];
-        gls[k] += gs * g.s[k];
-      }
-      const float w = g.qh[0], x = g.qh[1], y = g.qh[2], z = g.qh[3];
-      const float gw = 2.0f * (-z * gR[1] + y * gR[2] + z * gR[3] - x * gR[5] - y * gR[6] + x * gR[7]);
-      const float gx = 2.0f * (y * gR[1] + z * gR[2] + y * gR[3] - 2.0f * x * gR[4] - w * gR[5] + z * gR[6] +
-                               w * gR[7] - 2.0f * x * gR[8]);
-      const float gy = 2.0f * (-2.0f * y * gR[0] + x * gR[1] + w * gR[2] + x * gR[3] + z * gR[5] - w * gR[6] +
-                               z * gR[7] - 2.0f * y * gR[8]);
-      const float gz = 2.0f * (-2.0f * z * gR[0] - w * gR[1] + x * gR[2] + w * gR[3] - 2.0f * z * gR[4] +
+      for (int k = 0; k < 3; ++k)
+        gls[k] += (gM[k] * g.R[k] + gM[3 + k] * g.R[3 + k] + gM[6 + k] * g.R[6 + k]) * g.s[k];
+      const double w = g.qh[0], x = g.qh[1], y = g.qh[2], z = g.qh[3];
+      const double gw = 2.0 * (-z * gR[1] + y * gR[2] + z * gR[3] - x * gR[5] - y * gR[6] + x * gR[7]);
+      const double gx = 2.0 * (y * gR[1] + z * gR[2] + y * gR[3] - 2.0 * x * gR[4] - w * gR[5] + z * gR[6] +
+                               w * gR[7] - 2.0 * x * gR[8]);
+      const double gy = 2.0 * (-2.0 * y * gR[0] + x * gR[1] + w * gR[2] + x * gR[3] + z * gR[5] - w * gR[6] +
+                               z * gR[7] - 2.0 * y * gR[8]);
+      const double gz = 2.0 * (-2.0 * z * gR[0] - w * gR[1] + x * gR[2] + w * gR[3] - 2.0 * z * gR[4] +
                                y * gR[5] + x * gR[6] + y * gR[7]);
-      const float dot = w * gw + x * gx + y * gy + z * gz;
-      const float iqn = 1.0f / g.qn;
-      gq[0] += (gw - w * dot) * iqn;
-      gq[1] += (gx - x * dot) * iqn;
-      gq[2] += (gy - y * dot) * iqn;
-      gq[3] += (gz - z * dot) * iqn;
+      const double dot = w * gw + x * gx + y * gy + z * gz;
+      gq[0] += (gw - w * dot) / g.qn;
+      gq[1] += (gx - x * dot) / g.qn;
+      gq[2] += (gy - y * dot) / g.qn;
+      gq[3] += (gz - z * dot) / g.qn;
     }
     if (!touched) continue;
 #pragma unroll
-    for (int j = 0; j < 3; ++j) grad[(0 + j) * stride + i] += gmean[j];
+    for (int j = 0; j < 3; ++j) grad[(0 + j) * stride + i] += (float)gmean[j];
 #pragma unroll
-    for (int j = 0; j < 3; ++j) grad[(3 + j) * stride + i] += gls[j];
+    for (int j = 0; j < 3; ++j) grad[(3 + j) * stride + i] += (float)gls[j];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) grad[(6 + j) * stride + i] += gq[j];
-    grad[10 * stride + i] += glogit;
-    for (int k = 0; k < 3 * K; ++k) grad[(11 + k) * stride + i] += gsh[k];
+    for (int j = 0; j < 4; ++j) grad[(6 + j) * stride + i] += (float)gq[j];
+    grad[10 * stride + i] += (float)glogit;
+#pragma unroll
+    for (int k = 0; k < 3 * K; ++k) grad[(11 + k) * stride + i] += (float)gsh[k];
   }
 }
 
@@ -521,9 +631,15 @@ void launch_project(const float* params, int64_t n, int64_t stride, int deg, int
 
 void launch_project_backward(const float* params, int64_t n, int64_t stride, int deg, int num_views,
                              const ViewDesc* views, float znear, const float* g2, float* grad, hipStream_t st) {
+  (void)znear;
   if (n == 0) return;
-  project_backward_kernel<<<grid_for(n, 256), 256, 0, st>>>(params, n, stride, deg, num_views, views, znear, g2,
-                                                            grad);
+  const int gsz = grid_for(n, 256);
+  switch (deg) {
+    case 0: project_backward_kernel<0><<<gsz, 256, 0, st>>>(params, n, stride, num_views, views, g2, grad); break;
+    case 1: project_backward_kernel<1><<<gsz, 256, 0, st>>>(params, n, stride, num_views, views, g2, grad); break;
+    case 2: project_backward_kernel<2><<<gsz, 256, 0, st>>>(params, n, stride, num_views, views, g2, grad); break;
+    default: project_backward_kernel<3><<<gsz, 256, 0, st>>>(params, n, stride, num_views, views, g2, grad); break;
+  }
 }
 
 void launch_export_splats(const float* params, int64_t n, int64_t stride, const ViewDesc* view, float znear,

@@ -7,7 +7,9 @@ at 0.99, T (1 - alpha) >= 1e-4, exponent <= 0) lies within 1e-5 relative of
 its threshold in the FP32 oracle: there the GPU's FP32 exponential (a few ulp
 from the oracle's) may take the other branch.
 
-Gradients: per parameter group, |g - ref| <= 1e-3 * max(|ref|, 0.01 * rms(ref)).
+Gradients: per parameter group, |g - ref| <= 1e-3 * max(|ref|, 0.01 * rms(ref_group),
+1e-6 * rms(ref_all)); the last floor only matters for groups whose exact
+gradient vanishes (rotations of isotropic Gaussians).
 """
 import numpy as np
 
@@ -41,11 +43,13 @@ def grad_violations(g, ref, rtol=GRAD_RTOL):
     """Returns {group: (violations, worst relative error, relative L2)}."""
     out = {}
     P = ref.shape[0]
+    ref = np.asarray(ref, np.float64)
+    rms_all = np.sqrt(np.mean(ref * ref)) if ref.size else 0.0
     for name, sl in grad_groups(P).items():
         a = np.asarray(g[sl], np.float64).ravel()
         b = np.asarray(ref[sl], np.float64).ravel()
         rms = np.sqrt(np.mean(b * b)) if b.size else 0.0
-        scale = np.maximum(np.abs(b), 0.01 * rms)
+        scale = np.maximum(np.abs(b), max(0.01 * rms, 1e-6 * rms_all))
         scale = np.where(scale > 0, scale, 1e-30)
         rel = np.abs(a - b) / scale
         l2 = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)

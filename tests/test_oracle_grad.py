@@ -131,3 +131,15 @@ def test_adam_matches_torch(orc):
         x, m, v = orc.adam_step(x, g, m, v, step, lrs)
     ref = np.stack([p.detach().numpy() for p in params])
     assert np.allclose(x, ref, rtol=1e-12, atol=1e-14)
+
+
+def test_fp32_splat_rounding_changes_gradients_only_at_rounding_level(orc):
+    # the FP32-splat reference differs from the FP64 one only by the rounding
+    # of u, v, conic, opacity, colour and depth to float
+    from parity import grad_violations
+    s = scenes.small_128x96()
+    grads = _masked_grads(orc, s, 1, margin_floor=1e-5)
+    a = orc.backward(s.params, 0, s.cameras, grads, pinned=True)
+    b = orc.backward(s.params, 0, s.cameras, grads, pinned="splats32")
+    for grp, (nbad, worst, l2) in grad_violations(b, a, rtol=1e-2).items():
+        assert nbad == 0 and l2 < 1e-5, grp
