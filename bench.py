@@ -38,6 +38,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="keyframe_640x480_200k")
     ap.add_argument("--tile", default="16x16")
+    ap.add_argument("--ppt", type=int, default=0, help="pixels per thread in the blend kernels (0 = default)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain 256 MiB device copy (reference for HBM byte counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--breakdown", action="store_true", help="print a per-stage time breakdown to stderr")
     return ap.parse_args()
@@ -77,8 +80,14 @@ def main():
     scene = scenes.WORKLOADS[args.workload]()
     cams = scene.cameras
     deg = scene.sh_degree
-    R = Rasterizer(tile_w=tw, tile_h=th)
+    R = Rasterizer(tile_w=tw, tile_h=th, pixels_per_thread=args.ppt)
     dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        src = torch.ones(64 * 1024 * 1024, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     params = torch.from_numpy(scene.params).to(dev)
     tparams = torch.from_numpy(scene.target_params).to(dev)
     targets = [tuple(t.clone() for t in o) for o in R.render(tparams, deg, cams)]
@@ -155,7 +164,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": scene.name, "views": len(cams),
                    "resolutions": sorted({f"{c.width}x{c.height}" for c in cams}),
-                   "gaussians": scene.num, "sh_degree": deg, "tile": args.tile, "adam": use_adam,
+                   "gaussians": scene.num, "sh_degree": deg, "tile": args.tile, "pixels_per_thread": args.ppt or 1,
+                   "adam": use_adam,
                    "render_mpix_s": round(mpix, 2) if mpix else None,
                    "instances": st["instances"], "visible_per_view": visible,
                    "stage_ms": {k: round(x, 4) for k, x in stages.items()}},

@@ -58,7 +58,8 @@ typedef enum {
   GSR_ERR_HIP = -3,          /* a HIP runtime call failed */
   GSR_ERR_STATE = -4,        /* call order violated (backward without matching forward) */
   GSR_ERR_CAPACITY = -5,     /* fixed-capacity scratch too small (mapping iteration) */
-  GSR_ERR_UNSUPPORTED = -6   /* option not supported by this build */
+  GSR_ERR_UNSUPPORTED = -6, /* option not supported by this build */
+  GSR_ERR_DEVICE = -7        /* a bounded device-side wait expired; the call's results are invalid */
 } gsr_status;
 
 typedef struct gsr_ctx gsr_ctx;
@@ -68,6 +69,7 @@ typedef struct {
   int32_t batch_depth;      /* Gaussians staged in LDS per batch; 0 = tile_w * tile_h */
   float bg[3];              /* background colour; default 0 */
   float znear;              /* near-plane cull distance; <= 0 means 0.2 */
+  int32_t pixels_per_thread; /* blend kernels: 0 = default (1), 1, or 2 (tiles of >= 128 pixels) */
 } gsr_options;
 
 typedef struct {

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libgsr.so")
 
 GSR_OK = 0
 STATUS_NAMES = {0: "GSR_OK", -1: "GSR_ERR_INVALID", -2: "GSR_ERR_OOM", -3: "GSR_ERR_HIP",
-                -4: "GSR_ERR_STATE", -5: "GSR_ERR_CAPACITY", -6: "GSR_ERR_UNSUPPORTED"}
+                -4: "GSR_ERR_STATE", -5: "GSR_ERR_CAPACITY", -6: "GSR_ERR_UNSUPPORTED", -7: "GSR_ERR_DEVICE"}
 
 EXPORTED = sorted(["gsr_create", "gsr_destroy", "gsr_render", "gsr_render1", "gsr_render_backward", "gsr_loss_l1",
                    "gsr_adam_step", "gsr_query_status", "gsr_copy_instances", "gsr_copy_splats",
@@ -39,7 +39,7 @@ class GsrError(RuntimeError):
 
 class gsr_options(ctypes.Structure):
     _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("batch_depth", ctypes.c_int32),
-                ("bg", ctypes.c_float * 3), ("znear", ctypes.c_float)]
+                ("bg", ctypes.c_float * 3), ("znear", ctypes.c_float), ("pixels_per_thread", ctypes.c_int32)]
 
 
 class gsr_camera(ctypes.Structure):
@@ -154,8 +154,8 @@ def _check(ctx, fn, rc):
 
 # --- one wrapper per C entry point ------------------------------------------
 
-def gsr_create(tile_w=16, tile_h=16, batch_depth=0, bg=(0.0, 0.0, 0.0), znear=0.2):
-    opt = gsr_options(tile_w, tile_h, batch_depth, (ctypes.c_float * 3)(*bg), znear)
+def gsr_create(tile_w=16, tile_h=16, batch_depth=0, bg=(0.0, 0.0, 0.0), znear=0.2, pixels_per_thread=0):
+    opt = gsr_options(tile_w, tile_h, batch_depth, (ctypes.c_float * 3)(*bg), znear, pixels_per_thread)
     h = ctypes.c_void_p()
     _check(None, "gsr_create", load().gsr_create(ctypes.byref(h), ctypes.byref(opt)))
     return h

@@ -28,6 +28,7 @@ constexpr size_t kSlotBytes = 64 * 1024;
 
 struct gsr_ctx {
   int tile_w = 16, tile_h = 16;
+  int ppt = 1;                          // pixels per thread in the blend kernels
   float bg[3] = {0.f, 0.f, 0.f};
   float znear = 0.2f;
   int hip_err = 0;
@@ -248,14 +249,13 @@ int render_impl(gsr_ctx* ctx, const gsr_gaussians* g, int32_t nv, const gsr_came
   RET_IF(ensure(ctx, ctx->tfinal, sizeof(float) * (size_t)npix));
   RET_IF(ensure(ctx, ctx->last, sizeof(uint32_t) * (size_t)npix));
   RET_IF(ensure(ctx, ctx->total, 64));
-  int64_t hist_n, part_n;
-  radix_scratch_sizes(total, &hist_n, &part_n);
-  RET_IF(ensure(ctx, ctx->hist, sizeof(uint32_t) * (size_t)hist_n));
-  RET_IF(ensure(ctx, ctx->partials, sizeof(uint32_t) * (size_t)part_n));
+  RET_IF(ensure(ctx, ctx->hist, sizeof(uint32_t) * (size_t)radix_scratch_elems(total)));
+  RET_IF(ensure(ctx, ctx->partials, sizeof(uint32_t) * (size_t)scan_partial_elems(total)));
 
   RET_IF(upload(ctx, ctx->views.p, views.data(), sizeof(ViewDesc) * nv, st));
   RET_IF(upload(ctx, ctx->images.p, ims.data(), sizeof(ViewImages) * nv, st));
 
+  launch_fill_u32(as<uint32_t>(ctx->total), 0u, 2, st);
   // projection (one thread per view x Gaussian)
   {
   StageTimer tm(ctx, GSR_STAGE_PROJECT, st);
@@ -271,7 +271,7 @@ int render_impl(gsr_ctx* ctx, const gsr_gaussians* g, int32_t nv, const gsr_came
   uint32_t* sva = as<uint32_t>(ctx->svals_alt);
   {
     StageTimer tm(ctx, GSR_STAGE_DEPTH_SORT, st);
-    radix_sort_pairs(zk, sv, zka, sva, total, 32, as<uint32_t>(ctx->hist), as<uint32_t>(ctx->partials), st);
+    radix_sort_pairs(zk, sv, zka, sva, total, 32, as<uint32_t>(ctx->hist), as<uint32_t>(ctx->total) + 1, st);
   }
   CHECK_LAUNCH(ctx);
   // instance offsets in depth order
@@ -282,18 +282,18 @@ int render_impl(gsr_ctx* ctx, const gsr_gaussians* g, int32_t nv, const gsr_came
                           as<uint32_t>(ctx->partials), st);
   }
   CHECK_LAUNCH(ctx);
-  HIP_TRY(ctx, hipMemcpyAsync(ctx->host_total, total_dev, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->host_total, total_dev, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
   HIP_TRY(ctx, hipStreamSynchronize(st));
   const int64_t I = (int64_t)ctx->host_total[0];
+  if (ctx->host_total[1] != 0) return GSR_ERR_DEVICE;
 
   const size_t i4 = sizeof(uint32_t) * (size_t)std::max<int64_t>(I, 1);
   RET_IF(ensure(ctx, ctx->ikeys, i4));
   RET_IF(ensure(ctx, ctx->ivals, i4));
   RET_IF(ensure(ctx, ctx->ikeys_alt, i4));
   RET_IF(ensure(ctx, ctx->ivals_alt, i4));
-  radix_scratch_sizes(std::max(I, total), &hist_n, &part_n);
-  RET_IF(ensure(ctx, ctx->hist, sizeof(uint32_t) * (size_t)hist_n));
-  RET_IF(ensure(ctx, ctx->partials, sizeof(uint32_t) * (size_t)part_n));
+  if (I >= (int64_t(1) << 30)) return GSR_ERR_CAPACITY;
+  RET_IF(ensure(ctx, ctx->hist, sizeof(uint32_t) * (size_t)radix_scratch_elems(std::max(I, total))));
 
   uint32_t* ik = as<uint32_t>(ctx->ikeys);
   uint32_t* iv = as<uint32_t>(ctx->ivals);
@@ -301,14 +301,13 @@ int render_impl(gsr_ctx* ctx, const gsr_gaussians* g, int32_t nv, const gsr_came
   uint32_t* iva = as<uint32_t>(ctx->ivals_alt);
   {
     StageTimer tm(ctx, GSR_STAGE_EMIT, st);
-    launch_emit(sv, as<uint32_t>(ctx->offsets), as<int4>(ctx->rect), total, N, as<ViewDesc>(ctx->views),
+    launch_emit(sv, as<uint32_t>(ctx->offsets), total_dev, as<int4>(ctx->rect), total, N, as<ViewDesc>(ctx->views),
                 ctx->tile_w, ctx->tile_h, ik, iv, I, st);
   }
   CHECK_LAUNCH(ctx);
   {
     StageTimer tm(ctx, GSR_STAGE_TILE_SORT, st);
-    radix_sort_pairs(ik, iv, ika, iva, I, bits_for(ntiles - 1), as<uint32_t>(ctx->hist),
-                     as<uint32_t>(ctx->partials), st);
+    radix_sort_pairs(ik, iv, ika, iva, I, bits_for(ntiles - 1), as<uint32_t>(ctx->hist), total_dev + 1, st);
   }
   CHECK_LAUNCH(ctx);
   {
@@ -331,7 +330,7 @@ int render_impl(gsr_ctx* ctx, const gsr_gaussians* g, int32_t nv, const gsr_came
   for (int k = 0; k < 3; ++k) ba.bg[k] = ctx->bg[k];
   {
     StageTimer tm(ctx, GSR_STAGE_BLEND_FWD, st);
-    launch_blend_forward(ba, ctx->tile_w, ctx->tile_h, st);
+    launch_blend_forward(ba, ctx->tile_w, ctx->tile_h, ctx->ppt, st);
   }
   CHECK_LAUNCH(ctx);
 
@@ -388,7 +387,7 @@ int backward_impl(gsr_ctx* ctx, const gsr_gaussians* g, int32_t nv, const gsr_ca
   for (int k = 0; k < 3; ++k) ba.bg[k] = ctx->bg[k];
   {
     StageTimer tm(ctx, GSR_STAGE_BLEND_BWD, st);
-    launch_blend_backward(ba, ctx->tile_w, ctx->tile_h, st);
+    launch_blend_backward(ba, ctx->tile_w, ctx->tile_h, ctx->ppt, st);
   }
   CHECK_LAUNCH(ctx);
   {
@@ -421,6 +420,12 @@ int gsr_create(gsr_ctx** out, const gsr_options* opt) {
     }
     ctx->tile_w = tw;
     ctx->tile_h = th;
+    if (opt->pixels_per_thread < 0 || opt->pixels_per_thread > 2 ||
+        (opt->pixels_per_thread == 2 && tw * th < 128)) {
+      delete ctx;
+      return GSR_ERR_UNSUPPORTED;
+    }
+    ctx->ppt = opt->pixels_per_thread == 0 ? 1 : opt->pixels_per_thread;
     for (int k = 0; k < 3; ++k) ctx->bg[k] = opt->bg[k];
     ctx->znear = opt->znear > 0.f ? opt->znear : 0.2f;
   }
@@ -553,7 +558,12 @@ int gsr_adam_step(gsr_ctx* ctx, float* params, const float* grads, float* m, flo
 
 int gsr_query_status(gsr_ctx* ctx, int64_t* num_instances, int64_t* num_visible, int64_t* num_tiles) {
   if (!ctx) return GSR_ERR_INVALID;
-  if (ctx->last_stream || true) HIP_TRY(ctx, hipStreamSynchronize(ctx->last_stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->last_stream));
+  if (ctx->total.p) {
+    uint32_t flag = 0;
+    HIP_TRY(ctx, hipMemcpy(&flag, as<uint32_t>(ctx->total) + 1, sizeof(uint32_t), hipMemcpyDeviceToHost));
+    if (flag) return GSR_ERR_DEVICE;
+  }
   if (num_instances) *num_instances = ctx->have_forward ? ctx->fw_instances : 0;
   if (num_visible) *num_visible = -1;
   if (num_tiles) *num_tiles = ctx->have_forward ? ctx->fw_tiles : 0;
@@ -651,6 +661,7 @@ const char* gsr_status_string(int status) {
     case GSR_ERR_STATE: return "call order violated (backward without a matching forward)";
     case GSR_ERR_CAPACITY: return "fixed-capacity scratch too small";
     case GSR_ERR_UNSUPPORTED: return "unsupported option";
+    case GSR_ERR_DEVICE: return "a bounded device-side wait expired (sort look-back); results invalid";
     default: return "unknown status";
   }
 }

@@ -56,9 +56,43 @@ __device__ __forceinline__ int find_view(const ViewDesc* views, int num_views, i
   return v;
 }
 
-template <int TW, int TH>
-__global__ void __launch_bounds__(TW* TH) blend_forward_kernel(BlendArgs a) {
-  constexpr int NT = TW * TH;
+// Pixels per thread: a thread owns PPT pixels of one tile column, TH/PPT rows
+// apart, so every LDS record it reads serves PPT pairs and the backward's
+// wave reduction covers 64 * PPT pixels. The Gaussian loop is unrolled by
+// two: the alphas of consecutive Gaussians are independent, only the
+// transmittance update is sequential, which gives each wave independent work
+// to overlap with LDS and transcendental latency.
+template <int TW, int TH, int PPT>
+struct TileShape {
+  static constexpr int NT = TW * TH / PPT;       // threads per workgroup
+  static constexpr int ROWS = TH / PPT;          // row stride between a thread's pixels
+  static_assert(NT % 64 == 0, "workgroup must be whole wavefronts");
+};
+
+// Front-to-back update of one pixel with one Gaussian whose alpha is known.
+__device__ __forceinline__ void composite_one(bool ok, float alpha, const float4& q1, const float4& q2, float& T,
+                                              float& C0, float& C1, float& C2, float& D, bool& done,
+                                              uint32_t& last, uint32_t pos) {
+  if (done || !ok) return;
+  const float Tn = T * (1.0f - alpha);
+  if (Tn < kTransMin) {
+    done = true;
+    return;
+  }
+  const float w = alpha * T;
+  C0 = fmaf(w, q2.x, C0);
+  C1 = fmaf(w, q2.y, C1);
+  C2 = fmaf(w, q2.z, C2);
+  D = fmaf(w, q1.z, D);
+  T = Tn;
+  last = pos;
+}
+
+template <int TW, int TH, int PPT>
+__global__ void __launch_bounds__(TW * TH / PPT) blend_forward_kernel(BlendArgs a) {
+  using Shape = TileShape<TW, TH, PPT>;
+  constexpr int NT = Shape::NT;
+  constexpr int ROWS = Shape::ROWS;
   constexpr int BATCH = NT;
   __shared__ float4 s_q0[BATCH], s_q1[BATCH], s_q2[BATCH];
   const int tile = blockIdx.x;
@@ -67,15 +101,28 @@ __global__ void __launch_bounds__(TW* TH) blend_forward_kernel(BlendArgs a) {
   const int lt = tile - V.tile_offset;
   const int tx = lt % V.tiles_x, ty = lt / V.tiles_x;
   const int tid = threadIdx.x;
-  const int px = tx * TW + (tid % TW), py = ty * TH + (tid / TW);
-  const bool inside = px < V.width && py < V.height;
-  const float xs = (float)px + 0.5f, ys = (float)py + 0.5f;
+  const int px = tx * TW + (tid % TW);
+  int py[PPT];
+  bool inside[PPT], done[PPT];
+  float ys[PPT], T[PPT], C0[PPT], C1[PPT], C2[PPT], D[PPT];
+  uint32_t last[PPT];
+#pragma unroll
+  for (int i = 0; i < PPT; ++i) {
+    py[i] = ty * TH + (tid / TW) + i * ROWS;
+    inside[i] = px < V.width && py[i] < V.height;
+    done[i] = !inside[i];
+    ys[i] = (float)py[i] + 0.5f;
+    T[i] = 1.0f;
+    C0[i] = C1[i] = C2[i] = D[i] = 0.0f;
+    last[i] = 0;
+  }
+  const float xs = (float)px + 0.5f;
   const uint2 rg = a.ranges[tile];
-  float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, D = 0.0f;
-  uint32_t last = 0;
-  bool done = !inside;
   for (uint32_t b0 = rg.x; b0 < rg.y; b0 += BATCH) {
-    if (__syncthreads_count(done) == NT) break;
+    bool all_done = true;
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) all_done = all_done && done[i];
+    if (__syncthreads_count(all_done) == NT) break;
     const uint32_t j = b0 + tid;
     if (j < rg.y) {
       const Splat sp = a.splats[a.inst_vals[j]];
@@ -83,39 +130,54 @@ __global__ void __launch_bounds__(TW* TH) blend_forward_kernel(BlendArgs a) {
     }
     __syncthreads();
     const int cnt = (int)min((uint32_t)BATCH, rg.y - b0);
-    if (!done) {
-      for (int k = 0; k < cnt; ++k) {
-        const float4 q0 = s_q0[k], q1 = s_q1[k];
-        float dx, dy, G, alpha;
-        bool clamped;
-        if (!pair_alpha(q0, q1, xs, ys, dx, dy, G, alpha, clamped)) continue;
-        const float Tn = T * (1.0f - alpha);
-        if (Tn < kTransMin) {
-          done = true;
-          break;
-        }
-        const float4 q2 = s_q2[k];
-        const float w = alpha * T;
-        C0 = fmaf(w, q2.x, C0);
-        C1 = fmaf(w, q2.y, C1);
-        C2 = fmaf(w, q2.z, C2);
-        D = fmaf(w, q1.z, D);
-        T = Tn;
-        last = b0 + k - rg.x + 1;
+    const uint32_t pos0 = b0 - rg.x + 1;
+    int k = 0;
+    for (; k + 1 < cnt; k += 2) {
+      bool busy = false;
+#pragma unroll
+      for (int i = 0; i < PPT; ++i) busy = busy || !done[i];
+      if (!busy) break;
+      const float4 qa0 = s_q0[k], qa1 = s_q1[k], qb0 = s_q0[k + 1], qb1 = s_q1[k + 1];
+      float al_a[PPT], al_b[PPT];
+      bool ok_a[PPT], ok_b[PPT];
+#pragma unroll
+      for (int i = 0; i < PPT; ++i) {
+        float dx, dy, G;
+        bool cl;
+        ok_a[i] = pair_alpha(qa0, qa1, xs, ys[i], dx, dy, G, al_a[i], cl);
+        ok_b[i] = pair_alpha(qb0, qb1, xs, ys[i], dx, dy, G, al_b[i], cl);
+      }
+      const float4 qa2 = s_q2[k], qb2 = s_q2[k + 1];
+#pragma unroll
+      for (int i = 0; i < PPT; ++i) {
+        composite_one(ok_a[i], al_a[i], qa1, qa2, T[i], C0[i], C1[i], C2[i], D[i], done[i], last[i], pos0 + k);
+        composite_one(ok_b[i], al_b[i], qb1, qb2, T[i], C0[i], C1[i], C2[i], D[i], done[i], last[i], pos0 + k + 1);
+      }
+    }
+    if (k < cnt) {
+      const float4 q0 = s_q0[k], q1 = s_q1[k], q2 = s_q2[k];
+#pragma unroll
+      for (int i = 0; i < PPT; ++i) {
+        float dx, dy, G, al;
+        bool cl;
+        const bool ok = pair_alpha(q0, q1, xs, ys[i], dx, dy, G, al, cl);
+        composite_one(ok, al, q1, q2, T[i], C0[i], C1[i], C2[i], D[i], done[i], last[i], pos0 + k);
       }
     }
   }
-  if (inside) {
-    const ViewImages im = a.images[view];
-    const int64_t HW = (int64_t)V.width * V.height;
-    const int64_t p = (int64_t)py * V.width + px;
-    im.rgb[p] = fmaf(T, a.bg[0], C0);
-    im.rgb[HW + p] = fmaf(T, a.bg[1], C1);
-    im.rgb[2 * HW + p] = fmaf(T, a.bg[2], C2);
-    im.depth[p] = D;
-    im.alpha[p] = 1.0f - T;
-    a.tfinal[V.pix_offset + p] = T;
-    a.last[V.pix_offset + p] = last;
+  const ViewImages im = a.images[view];
+  const int64_t HW = (int64_t)V.width * V.height;
+#pragma unroll
+  for (int i = 0; i < PPT; ++i) {
+    if (!inside[i]) continue;
+    const int64_t p = (int64_t)py[i] * V.width + px;
+    im.rgb[p] = fmaf(T[i], a.bg[0], C0[i]);
+    im.rgb[HW + p] = fmaf(T[i], a.bg[1], C1[i]);
+    im.rgb[2 * HW + p] = fmaf(T[i], a.bg[2], C2[i]);
+    im.depth[p] = D[i];
+    im.alpha[p] = 1.0f - T[i];
+    a.tfinal[V.pix_offset + p] = T[i];
+    a.last[V.pix_offset + p] = last[i];
   }
 }
 
@@ -146,11 +208,70 @@ __device__ __forceinline__ float wave_sum_lane63(float x) {
   return x;
 }
 
-template <int TW, int TH>
-__global__ void __launch_bounds__(TW* TH) blend_backward_kernel(BlendArgs a) {
-  constexpr int NT = TW * TH;
+// Per-(wave, Gaussian) sums the backward reduces. The conic and mean
+// gradients are linear in the moments of dL/dpower over the pixels, so the
+// per-pair work accumulates the moments and the lane that publishes the
+// wave sum turns them into (u, v, A, B, C) gradients.
+enum { M_R = 0, M_G, M_B, M_Z, M_O, M_X, M_Y, M_XX, M_XY, M_YY, M_N };
+
+// Reverse step of one pixel over one composited Gaussian: recover T_k,
+// accumulate the pair's moments, update the suffix sum.
+__device__ __forceinline__ void reverse_one(bool ok, float alpha, float G, bool clamped, float dx, float dy,
+                                            const float4& q1, const float4& q2, float gc0, float gc1, float gc2,
+                                            float gd, float tb, float& T, float& S, float* m) {
+  if (!ok) return;
+  const float r1m = __builtin_amdgcn_rcpf(1.0f - alpha);
+  T = T * r1m;                                          // T_k, transmittance before k
+  const float w = alpha * T;
+  m[M_R] = fmaf(w, gc0, m[M_R]);
+  m[M_G] = fmaf(w, gc1, m[M_G]);
+  m[M_B] = fmaf(w, gc2, m[M_B]);
+  m[M_Z] = fmaf(w, gd, m[M_Z]);
+  const float x = fmaf(gc0, q2.x, fmaf(gc1, q2.y, fmaf(gc2, q2.z, gd * q1.z)));
+  const float galpha = fmaf(T, x - S, tb * r1m);
+  S = fmaf(alpha, x, (1.0f - alpha) * S);
+  if (!clamped) {
+    m[M_O] = fmaf(galpha, G, m[M_O]);
+    const float gpow = galpha * alpha;                  // dL/dpower
+    const float gx = gpow * dx, gy = gpow * dy;
+    m[M_X] += gx;
+    m[M_Y] += gy;
+    m[M_XX] = fmaf(gx, dx, m[M_XX]);
+    m[M_XY] = fmaf(gx, dy, m[M_XY]);
+    m[M_YY] = fmaf(gy, dy, m[M_YY]);
+  }
+}
+
+// Reduce one Gaussian's moments over the wave and publish its gradient row.
+template <int NW, int BATCH>
+__device__ __forceinline__ void publish(float* m, bool any, int lane, int wave, int k, const float4& q0,
+                                        const float4& q1, float (*s_red)[G2_N][BATCH]) {
+  if (any) {
+#pragma unroll
+    for (int c = 0; c < M_N; ++c) m[c] = wave_sum_lane63(m[c]);
+  }
+  if (lane == 63) {
+    // d power / d u = (2 Ah dx + Bh dy) ln 2 with Ah = -A log2(e) / 2, Bh = -B log2(e)
+    s_red[wave][G2_U][k] = any ? kLn2 * (2.0f * q0.z * m[M_X] + q0.w * m[M_Y]) : 0.0f;
+    s_red[wave][G2_V][k] = any ? kLn2 * (q0.w * m[M_X] + 2.0f * q1.x * m[M_Y]) : 0.0f;
+    s_red[wave][G2_A][k] = any ? -0.5f * m[M_XX] : 0.0f;
+    s_red[wave][G2_B][k] = any ? -m[M_XY] : 0.0f;
+    s_red[wave][G2_C][k] = any ? -0.5f * m[M_YY] : 0.0f;
+    s_red[wave][G2_O][k] = any ? m[M_O] : 0.0f;
+    s_red[wave][G2_R][k] = any ? m[M_R] : 0.0f;
+    s_red[wave][G2_G][k] = any ? m[M_G] : 0.0f;
+    s_red[wave][G2_BL][k] = any ? m[M_B] : 0.0f;
+    s_red[wave][G2_Z][k] = any ? m[M_Z] : 0.0f;
+  }
+}
+
+template <int TW, int TH, int PPT>
+__global__ void __launch_bounds__(TW * TH / PPT) blend_backward_kernel(BlendArgs a) {
+  using Shape = TileShape<TW, TH, PPT>;
+  constexpr int NT = Shape::NT;
+  constexpr int ROWS = Shape::ROWS;
   constexpr int NW = NT / 64;
-  constexpr int BATCH = NT < 128 ? NT : 128;
+  constexpr int BATCH = NT;
   __shared__ float4 s_q0[BATCH], s_q1[BATCH], s_q2[BATCH];
   __shared__ uint32_t s_id[BATCH];
   __shared__ float s_red[NW][G2_N][BATCH];
@@ -162,32 +283,42 @@ __global__ void __launch_bounds__(TW* TH) blend_backward_kernel(BlendArgs a) {
   const int tx = lt % V.tiles_x, ty = lt / V.tiles_x;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int px = tx * TW + (tid % TW), py = ty * TH + (tid / TW);
-  const bool inside = px < V.width && py < V.height;
-  const float xs = (float)px + 0.5f, ys = (float)py + 0.5f;
+  const int px = tx * TW + (tid % TW);
+  const float xs = (float)px + 0.5f;
   const uint2 rg = a.ranges[tile];
   const int64_t HW = (int64_t)V.width * V.height;
-  const int64_t p = (int64_t)py * V.width + px;
-  float T = 1.0f, gc0 = 0.f, gc1 = 0.f, gc2 = 0.f, gd = 0.f, ga = 0.f;
-  uint32_t mylast = 0;
+  const ViewImages gimg = a.images[view];
+  float ys[PPT], T[PPT], S[PPT], gc0[PPT], gc1[PPT], gc2[PPT], gd[PPT], tb[PPT];
+  uint32_t mylast[PPT];
   if (tid == 0) s_maxlast = 0;
   __syncthreads();
-  if (inside) {
-    T = a.tfinal[V.pix_offset + p];
-    mylast = a.last[V.pix_offset + p];
-    const ViewImages g = a.images[view];
-    if (g.rgb) {
-      gc0 = g.rgb[p];
-      gc1 = g.rgb[HW + p];
-      gc2 = g.rgb[2 * HW + p];
+  uint32_t tmax = 0;
+#pragma unroll
+  for (int i = 0; i < PPT; ++i) {
+    const int py = ty * TH + (tid / TW) + i * ROWS;
+    ys[i] = (float)py + 0.5f;
+    T[i] = 1.0f;
+    S[i] = 0.0f;
+    gc0[i] = gc1[i] = gc2[i] = gd[i] = 0.0f;
+    float ga = 0.0f;
+    mylast[i] = 0;
+    if (px < V.width && py < V.height) {
+      const int64_t p = (int64_t)py * V.width + px;
+      T[i] = a.tfinal[V.pix_offset + p];
+      mylast[i] = a.last[V.pix_offset + p];
+      if (gimg.rgb) {
+        gc0[i] = gimg.rgb[p];
+        gc1[i] = gimg.rgb[HW + p];
+        gc2[i] = gimg.rgb[2 * HW + p];
+      }
+      if (gimg.depth) gd[i] = gimg.depth[p];
+      if (gimg.alpha) ga = gimg.alpha[p];
     }
-    if (g.depth) gd = g.depth[p];
-    if (g.alpha) ga = g.alpha[p];
-    atomicMax(&s_maxlast, mylast);
+    // T_final (dL/dalpha_out - dL/drgb . bg): the background term of dL/dalpha_k
+    tb[i] = T[i] * (ga - (gc0[i] * a.bg[0] + gc1[i] * a.bg[1] + gc2[i] * a.bg[2]));
+    tmax = max(tmax, mylast[i]);
   }
-  const float tfin = T;
-  const float bgterm = ga - (gc0 * a.bg[0] + gc1 * a.bg[1] + gc2 * a.bg[2]);
-  float S = 0.0f;
+  atomicMax(&s_maxlast, tmax);
   __syncthreads();
   const uint32_t maxlast = min(s_maxlast, rg.y - rg.x);
   for (int64_t bend = (int64_t)rg.x + maxlast; bend > (int64_t)rg.x; bend -= BATCH) {
@@ -200,69 +331,67 @@ __global__ void __launch_bounds__(TW* TH) blend_backward_kernel(BlendArgs a) {
       stage_record(a.splats[sid], s_q0[tid], s_q1[tid], s_q2[tid]);
     }
     __syncthreads();
-    for (int k = cnt - 1; k >= 0; --k) {
-      const uint32_t local = (uint32_t)(b0 + k - rg.x);
-      float v[G2_N];
+    const uint32_t lbase = (uint32_t)(b0 - rg.x);
+    int k = cnt - 1;
+    for (; k >= 1; k -= 2) {
+      // Gaussians k (nearer the back, processed first) and k - 1
+      const float4 qa0 = s_q0[k], qa1 = s_q1[k], qa2 = s_q2[k];
+      const float4 qb0 = s_q0[k - 1], qb1 = s_q1[k - 1], qb2 = s_q2[k - 1];
+      float ma[M_N], mb[M_N];
 #pragma unroll
-      for (int c = 0; c < G2_N; ++c) v[c] = 0.0f;
-      bool contrib = false;
-      if (local < mylast) {
-        const float4 q0 = s_q0[k], q1 = s_q1[k];
-        float dx, dy, G, alpha;
-        bool clamped;
-        if (pair_alpha(q0, q1, xs, ys, dx, dy, G, alpha, clamped)) {
-          contrib = true;
-          const float4 q2 = s_q2[k];
-          const float r1m = __builtin_amdgcn_rcpf(1.0f - alpha);
-          T = T * r1m;                                    // T_k, transmittance before k
-          const float w = alpha * T;
-          v[G2_R] = w * gc0;
-          v[G2_G] = w * gc1;
-          v[G2_BL] = w * gc2;
-          v[G2_Z] = w * gd;
-          const float x = fmaf(gc0, q2.x, fmaf(gc1, q2.y, fmaf(gc2, q2.z, gd * q1.z)));
-          const float galpha = fmaf(T, x - S, tfin * bgterm * r1m);
-          S = fmaf(alpha, x, (1.0f - alpha) * S);
-          if (!clamped) {
-            v[G2_O] = galpha * G;
-            const float gpow = galpha * alpha;             // dL/dpower
-            const float gl = gpow * kLn2;
-            v[G2_U] = gl * fmaf(2.0f * q0.z, dx, q0.w * dy);
-            v[G2_V] = gl * fmaf(2.0f * q1.x, dy, q0.w * dx);
-            v[G2_A] = -0.5f * gpow * dx * dx;
-            v[G2_B] = -gpow * dx * dy;
-            v[G2_C] = -0.5f * gpow * dy * dy;
-          }
-        }
-      }
-      const bool any = __ballot(contrib) != 0ull;
-      if (any) {
+      for (int c = 0; c < M_N; ++c) ma[c] = mb[c] = 0.0f;
+      bool ca = false, cb = false;
 #pragma unroll
-        for (int c = 0; c < G2_N; ++c) v[c] = wave_sum_lane63(v[c]);
+      for (int i = 0; i < PPT; ++i) {
+        float dxa, dya, Ga, ala, dxb, dyb, Gb, alb;
+        bool cla, clb;
+        const bool oka = (lbase + k < mylast[i]) && pair_alpha(qa0, qa1, xs, ys[i], dxa, dya, Ga, ala, cla);
+        const bool okb = (lbase + k - 1 < mylast[i]) && pair_alpha(qb0, qb1, xs, ys[i], dxb, dyb, Gb, alb, clb);
+        ca = ca || oka;
+        cb = cb || okb;
+        reverse_one(oka, ala, Ga, cla, dxa, dya, qa1, qa2, gc0[i], gc1[i], gc2[i], gd[i], tb[i], T[i], S[i], ma);
+        reverse_one(okb, alb, Gb, clb, dxb, dyb, qb1, qb2, gc0[i], gc1[i], gc2[i], gd[i], tb[i], T[i], S[i], mb);
       }
-      if (lane == 63) {
+      const bool anya = __ballot(ca) != 0ull, anyb = __ballot(cb) != 0ull;
+      publish<NW, BATCH>(ma, anya, lane, wave, k, qa0, qa1, s_red);
+      publish<NW, BATCH>(mb, anyb, lane, wave, k - 1, qb0, qb1, s_red);
+    }
+    if (k == 0) {
+      const float4 q0 = s_q0[0], q1 = s_q1[0], q2 = s_q2[0];
+      float m[M_N];
 #pragma unroll
-        for (int c = 0; c < G2_N; ++c) s_red[wave][c][k] = any ? v[c] : 0.0f;
+      for (int c = 0; c < M_N; ++c) m[c] = 0.0f;
+      bool cc = false;
+#pragma unroll
+      for (int i = 0; i < PPT; ++i) {
+        float dx, dy, G, al;
+        bool cl;
+        const bool ok = (lbase < mylast[i]) && pair_alpha(q0, q1, xs, ys[i], dx, dy, G, al, cl);
+        cc = cc || ok;
+        reverse_one(ok, al, G, cl, dx, dy, q1, q2, gc0[i], gc1[i], gc2[i], gd[i], tb[i], T[i], S[i], m);
       }
+      publish<NW, BATCH>(m, __ballot(cc) != 0ull, lane, wave, 0, q0, q1, s_red);
     }
     __syncthreads();
     for (int e = tid; e < cnt * G2_N; e += NT) {
-      const int c = e / cnt, k = e - c * cnt;
+      const int c = e / cnt, kk = e - c * cnt;
       float sum = 0.0f;
 #pragma unroll
-      for (int w = 0; w < NW; ++w) sum += s_red[w][c][k];
-      if (sum != 0.0f) unsafeAtomicAdd(&a.g2[(int64_t)s_id[k] * G2_N + c], sum);
+      for (int w = 0; w < NW; ++w) sum += s_red[w][c][kk];
+      if (sum != 0.0f) unsafeAtomicAdd(&a.g2[(int64_t)s_id[kk] * G2_N + c], sum);
     }
   }
 }
 
 template <int TW, int TH>
-void fwd_launch(const BlendArgs& a, hipStream_t st) {
-  blend_forward_kernel<TW, TH><<<a.num_tiles, TW * TH, 0, st>>>(a);
+void fwd_launch(const BlendArgs& a, int ppt, hipStream_t st) {
+  if (ppt == 2 && TW * TH >= 128) blend_forward_kernel<TW, TH, (TW * TH >= 128 ? 2 : 1)><<<a.num_tiles, TW * TH / 2, 0, st>>>(a);
+  else blend_forward_kernel<TW, TH, 1><<<a.num_tiles, TW * TH, 0, st>>>(a);
 }
 template <int TW, int TH>
-void bwd_launch(const BlendArgs& a, hipStream_t st) {
-  blend_backward_kernel<TW, TH><<<a.num_tiles, TW * TH, 0, st>>>(a);
+void bwd_launch(const BlendArgs& a, int ppt, hipStream_t st) {
+  if (ppt == 2 && TW * TH >= 128) blend_backward_kernel<TW, TH, (TW * TH >= 128 ? 2 : 1)><<<a.num_tiles, TW * TH / 2, 0, st>>>(a);
+  else blend_backward_kernel<TW, TH, 1><<<a.num_tiles, TW * TH, 0, st>>>(a);
 }
 
 __global__ void __launch_bounds__(256) loss_l1_kernel(const ViewDesc* __restrict__ views,
@@ -326,20 +455,20 @@ bool blend_supported(int tile_w, int tile_h) {
          (tile_w == 32 && tile_h == 8);
 }
 
-void launch_blend_forward(const BlendArgs& a, int tile_w, int tile_h, hipStream_t st) {
+void launch_blend_forward(const BlendArgs& a, int tile_w, int tile_h, int ppt, hipStream_t st) {
   if (a.num_tiles == 0) return;
-  if (tile_w == 16 && tile_h == 16) fwd_launch<16, 16>(a, st);
-  else if (tile_w == 16 && tile_h == 8) fwd_launch<16, 8>(a, st);
-  else if (tile_w == 8 && tile_h == 8) fwd_launch<8, 8>(a, st);
-  else if (tile_w == 32 && tile_h == 8) fwd_launch<32, 8>(a, st);
+  if (tile_w == 16 && tile_h == 16) fwd_launch<16, 16>(a, ppt, st);
+  else if (tile_w == 16 && tile_h == 8) fwd_launch<16, 8>(a, ppt, st);
+  else if (tile_w == 8 && tile_h == 8) fwd_launch<8, 8>(a, ppt, st);
+  else if (tile_w == 32 && tile_h == 8) fwd_launch<32, 8>(a, ppt, st);
 }
 
-void launch_blend_backward(const BlendArgs& a, int tile_w, int tile_h, hipStream_t st) {
+void launch_blend_backward(const BlendArgs& a, int tile_w, int tile_h, int ppt, hipStream_t st) {
   if (a.num_tiles == 0) return;
-  if (tile_w == 16 && tile_h == 16) bwd_launch<16, 16>(a, st);
-  else if (tile_w == 16 && tile_h == 8) bwd_launch<16, 8>(a, st);
-  else if (tile_w == 8 && tile_h == 8) bwd_launch<8, 8>(a, st);
-  else if (tile_w == 32 && tile_h == 8) bwd_launch<32, 8>(a, st);
+  if (tile_w == 16 && tile_h == 16) bwd_launch<16, 16>(a, ppt, st);
+  else if (tile_w == 16 && tile_h == 8) bwd_launch<16, 8>(a, ppt, st);
+  else if (tile_w == 8 && tile_h == 8) bwd_launch<8, 8>(a, ppt, st);
+  else if (tile_w == 32 && tile_h == 8) bwd_launch<32, 8>(a, ppt, st);
 }
 
 void launch_loss_l1(const ViewDesc* views, const ViewImages* rendered, const ViewImages* target,

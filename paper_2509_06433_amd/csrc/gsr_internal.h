@@ -54,19 +54,22 @@ void launch_export_splats(const float* params, int64_t n, int64_t stride, const 
                           const Splat* splats, const int4* rect, float* out, hipStream_t st);
 
 // ---- sort.hip --------------------------------------------------------------
-// Scratch sizes (in uint32 elements) a radix sort of n keys needs.
-void radix_scratch_sizes(int64_t n, int64_t* hist_elems, int64_t* partial_elems);
+// Scratch (uint32 elements) a radix sort of n keys needs.
+int64_t radix_scratch_elems(int64_t n);
 // Stable LSD radix sort of (keys, vals) on the low `bits` bits of the keys,
 // 8 bits per pass, ping-ponging between the buffers; on return keys/vals point
-// at the sorted data and keys_alt/vals_alt at the other pair.
+// at the sorted data and keys_alt/vals_alt at the other pair. *err becomes
+// nonzero if a look-back wait hit its bound (the result is then invalid).
 void radix_sort_pairs(uint32_t*& keys, uint32_t*& vals, uint32_t*& keys_alt, uint32_t*& vals_alt, int64_t n,
-                      int bits, uint32_t* hist, uint32_t* partials, hipStream_t st);
+                      int bits, uint32_t* scratch, uint32_t* err, hipStream_t st);
+// Scan partials needed by scan_gather_exclusive for n elements.
+int64_t scan_partial_elems(int64_t n);
 // Exclusive scan out[r] = sum_{j<r} in[idx[r]] (idx may be null); total -> *total_dev.
 void scan_gather_exclusive(const uint32_t* in, const uint32_t* idx, uint32_t* out, int64_t n,
                            uint32_t* total_dev, uint32_t* partials, hipStream_t st);
 // Instance emission in depth order; writes beyond `capacity` are dropped.
-void launch_emit(const uint32_t* sorted_s, const uint32_t* offsets, const int4* rect, int64_t count,
-                 int64_t n, const ViewDesc* views, int tile_w, int tile_h, uint32_t* keys,
+void launch_emit(const uint32_t* sorted_s, const uint32_t* offsets, const uint32_t* total_dev, const int4* rect,
+                 int64_t count, int64_t n, const ViewDesc* views, int tile_w, int tile_h, uint32_t* keys,
                  uint32_t* vals, int64_t capacity, hipStream_t st);
 // ranges[t] = (start, end) of global tile t in the sorted key array.
 void launch_tile_ranges(const uint32_t* keys, int64_t count, uint2* ranges, int64_t num_tiles,
@@ -92,8 +95,9 @@ struct BlendArgs {
   float bg[3];
 };
 bool blend_supported(int tile_w, int tile_h);
-void launch_blend_forward(const BlendArgs& a, int tile_w, int tile_h, hipStream_t st);
-void launch_blend_backward(const BlendArgs& a, int tile_w, int tile_h, hipStream_t st);
+// ppt: pixels per thread (1, or 2 for tiles of at least 128 pixels)
+void launch_blend_forward(const BlendArgs& a, int tile_w, int tile_h, int ppt, hipStream_t st);
+void launch_blend_backward(const BlendArgs& a, int tile_w, int tile_h, int ppt, hipStream_t st);
 void launch_loss_l1(const ViewDesc* views, const ViewImages* rendered, const ViewImages* target,
                     const ViewImages* grad, int num_views, int max_pixels, float depth_weight,
                     float* loss, hipStream_t st);

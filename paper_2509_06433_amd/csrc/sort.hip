@@ -129,38 +129,65 @@ __global__ void __launch_bounds__(kScanThreads) scan_down_kernel(const uint32_t*
   }
 }
 
-// Per-block histogram of the digit (key >> shift) & 255, stored digit-major:
-// hist[digit * nblocks + block].
-__global__ void __launch_bounds__(kSortThreads) radix_hist_kernel(const uint32_t* __restrict__ keys, int64_t n,
-                                                                  int shift, uint32_t* __restrict__ hist) {
-  __shared__ uint32_t h[kRadix];
-  h[threadIdx.x] = 0;
+// ---------------------------------------------------------------------------
+// Onesweep LSD radix sort, 8-bit digits.
+//   global_hist: digit histograms of every pass in one read of the keys.
+//   pass:        one kernel per digit. Workgroups take tickets so that a lower
+//                ticket is always already running; each ranks its 4096 keys
+//                with wave ballots, publishes its per-digit counts, and gets
+//                its per-digit offset by looking back over the published
+//                counts of lower tickets (decoupled look-back). A wait on a
+//                predecessor is bounded: past the spin limit the workgroup
+//                raises the error flag and goes on, so every wave exits.
+// Status word per (ticket, digit): 2 flag bits (1 = count of this workgroup,
+// 2 = inclusive prefix up to this workgroup) over a 30-bit count.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kFlagAgg = 1u << 30;
+constexpr uint32_t kFlagInc = 2u << 30;
+constexpr uint32_t kCountMask = (1u << 30) - 1;
+constexpr int kMaxPasses = 4;
+constexpr uint32_t kSpinLimit = 1u << 20;
+
+__global__ void __launch_bounds__(kSortThreads) global_hist_kernel(const uint32_t* __restrict__ keys, int64_t n,
+                                                                   int passes, uint32_t* __restrict__ ghist) {
+  __shared__ uint32_t h[kSortThreads / 64][kMaxPasses][kRadix];
+  const int wave = threadIdx.x >> 6;
+  for (int e = threadIdx.x; e < (kSortThreads / 64) * kMaxPasses * kRadix; e += kSortThreads)
+    (&h[0][0][0])[e] = 0;
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * kSortChunk;
-#pragma unroll 4
   for (int k = 0; k < kSortItems; ++k) {
     const int64_t j = base + k * kSortThreads + threadIdx.x;
-    if (j < n) atomicAdd(&h[(keys[j] >> shift) & (kRadix - 1)], 1u);
+    if (j < n) {
+      const uint32_t key = keys[j];
+      for (int p = 0; p < passes; ++p) atomicAdd(&h[wave][p][(key >> (8 * p)) & (kRadix - 1)], 1u);
+    }
   }
   __syncthreads();
-  hist[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
+  for (int p = 0; p < passes; ++p) {
+    uint32_t c = 0;
+#pragma unroll
+    for (int w = 0; w < kSortThreads / 64; ++w) c += h[w][p][threadIdx.x];
+    if (c) atomicAdd(&ghist[p * kRadix + threadIdx.x], c);
+  }
 }
 
-// Stable scatter. Wave w of a block owns keys [base + w*1024, base + (w+1)*1024)
-// and walks them in 16 rounds of 64 consecutive keys. Within a round, lanes with
-// equal digits are found with 8 ballots; a wave-private LDS counter per digit
-// carries ranks across rounds, so no block barrier is needed until the end.
-__global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(
+__global__ void __launch_bounds__(kSortThreads) onesweep_pass_kernel(
     const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals, int64_t n, int shift,
-    const uint32_t* __restrict__ hist_scanned, uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out) {
+    const uint32_t* __restrict__ ghist, uint32_t* __restrict__ status, uint32_t* __restrict__ ticket,
+    uint32_t* __restrict__ err, uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out) {
   __shared__ uint32_t wcnt[kSortThreads / 64][kRadix];
   __shared__ uint32_t gofs[kRadix];
+  __shared__ uint32_t s_bid;
+  __shared__ uint32_t s_wsum[kSortThreads / 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int d0 = threadIdx.x;                       // the digit this thread publishes and looks back for
+  if (threadIdx.x == 0) s_bid = atomicAdd(ticket, 1u);
 #pragma unroll
   for (int w = 0; w < kSortThreads / 64; ++w) wcnt[w][threadIdx.x] = 0;
-  gofs[threadIdx.x] = hist_scanned[(int64_t)threadIdx.x * gridDim.x + blockIdx.x];
   __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * kSortChunk + (int64_t)wave * kWaveChunk;
+  const uint32_t bid = s_bid;
+  const int64_t base = (int64_t)bid * kSortChunk + (int64_t)wave * kWaveChunk;
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   uint32_t k_reg[kSortItems], v_reg[kSortItems], off[kSortItems];
 #pragma unroll
@@ -182,19 +209,56 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(
     const uint32_t before = wcnt[wave][d];
     off[r] = before + rank;
     if (valid && rank == 0) wcnt[wave][d] = before + (uint32_t)__popcll(mask);
-    // keep this wave's LDS read of the next round after this write
     __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
-  {
-    const int d = threadIdx.x;
-    uint32_t run = 0;
+  // per digit: wave prefixes in place, block count
+  uint32_t mine = 0;
 #pragma unroll
-    for (int w = 0; w < kSortThreads / 64; ++w) {
-      const uint32_t c = wcnt[w][d];
-      wcnt[w][d] = run;
-      run += c;
+  for (int w = 0; w < kSortThreads / 64; ++w) {
+    const uint32_t c = wcnt[w][d0];
+    wcnt[w][d0] = mine;
+    mine += c;
+  }
+  uint32_t* st = status + (size_t)bid * kRadix + d0;
+  __hip_atomic_store(st, (bid == 0 ? kFlagInc : kFlagAgg) | mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  // exclusive prefix over lower tickets
+  uint32_t excl = 0;
+  if (bid > 0) {
+    int64_t p = (int64_t)bid - 1;
+    uint32_t spins = 0;
+    while (p >= 0) {
+      const uint32_t v = __hip_atomic_load(status + (size_t)p * kRadix + d0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const uint32_t flag = v & ~kCountMask;
+      if (flag == 0u) {
+        if (++spins > kSpinLimit) {
+          atomicOr(err, 1u);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        continue;
+      }
+      excl += v & kCountMask;
+      if (flag == kFlagInc) break;
+      --p;
     }
+    __hip_atomic_store(st, kFlagInc | (excl + mine), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  // start of each digit in the output: exclusive scan of the global histogram
+  {
+    const uint32_t g = ghist[d0];
+    uint32_t x = g;
+#pragma unroll
+    for (int dd = 1; dd < 64; dd <<= 1) {
+      const uint32_t y = __shfl_up(x, dd, 64);
+      if (lane >= dd) x += y;
+    }
+    if (lane == 63) s_wsum[wave] = x;
+    __syncthreads();
+    uint32_t before = 0;
+#pragma unroll
+    for (int w = 0; w < kSortThreads / 64; ++w) before += (w < wave) ? s_wsum[w] : 0u;
+    gofs[d0] = before + x - g + excl;
   }
   __syncthreads();
 #pragma unroll
@@ -211,26 +275,54 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(
   }
 }
 
-__global__ void emit_kernel(const uint32_t* __restrict__ sorted_s, const uint32_t* __restrict__ offsets,
-                            const int4* __restrict__ rect, int64_t count, int64_t n,
-                            const ViewDesc* __restrict__ views, int tile_w, int tile_h, uint32_t* __restrict__ keys,
-                            uint32_t* __restrict__ vals, int64_t capacity) {
-  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < count; r += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t s = sorted_s[r];
-    const int4 pr = rect[s];
-    if (pr.z < pr.x) continue;
-    const int view = (int)(s / n);
-    const ViewDesc& V = views[view];
-    const int tx0 = pr.x / tile_w, tx1 = pr.z / tile_w, ty0 = pr.y / tile_h, ty1 = pr.w / tile_h;
-    int64_t o = offsets[r];
-    for (int ty = ty0; ty <= ty1; ++ty)
-      for (int tx = tx0; tx <= tx1; ++tx) {
-        if (o < capacity) {
-          keys[o] = (uint32_t)(V.tile_offset + ty * V.tiles_x + tx);
-          vals[o] = s;
-        }
-        ++o;
-      }
+// Instance emission, load-balanced: workgroup b owns the 256 depth ranks
+// [256 b, 256 b + 256) and the contiguous output range of their instances;
+// each thread writes output positions round-robin and finds the owning
+// Gaussian by binary search over the 257 staged offsets.
+constexpr int kEmitChunk = 256;
+__global__ void __launch_bounds__(kEmitChunk) emit_kernel(const uint32_t* __restrict__ sorted_s,
+                                                         const uint32_t* __restrict__ offsets,
+                                                         const uint32_t* __restrict__ total_dev,
+                                                         const int4* __restrict__ rect, int64_t count, int64_t n,
+                                                         const ViewDesc* __restrict__ views, int tile_w, int tile_h,
+                                                         uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                                                         int64_t capacity) {
+  __shared__ uint32_t s_off[kEmitChunk + 1];
+  __shared__ uint32_t s_sid[kEmitChunk];
+  __shared__ int3 s_geo[kEmitChunk];      // first tile id of the rectangle, rectangle width, view row pitch
+  const int64_t r0 = (int64_t)blockIdx.x * kEmitChunk;
+  const uint32_t total = *total_dev;
+  const int tid = threadIdx.x;
+  const int64_t r = r0 + tid;
+  s_off[tid] = r < count ? offsets[r] : total;
+  const uint32_t sid = r < count ? sorted_s[r] : 0u;
+  s_sid[tid] = sid;
+  if (r < count) {
+    const int4 pr = rect[sid];
+    if (pr.z >= pr.x) {
+      const ViewDesc& V = views[(int)(sid / (uint64_t)n)];
+      const int tx0 = pr.x / tile_w, tx1 = pr.z / tile_w, ty0 = pr.y / tile_h;
+      s_geo[tid] = make_int3(V.tile_offset + ty0 * V.tiles_x + tx0, tx1 - tx0 + 1, V.tiles_x);
+    }
+  }
+  if (tid == 0) s_off[kEmitChunk] = (r0 + kEmitChunk < count) ? offsets[r0 + kEmitChunk] : total;
+  __syncthreads();
+  const uint32_t start = s_off[0], end = s_off[kEmitChunk];
+  for (uint32_t o = start + tid; o < end; o += kEmitChunk) {
+    int lo = 0, hi = kEmitChunk;                  // s_off[lo] <= o < s_off[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (s_off[mid] <= o) lo = mid;
+      else hi = mid;
+    }
+    const int3 geo = s_geo[lo];
+    const uint32_t wdt = (uint32_t)geo.y;
+    const uint32_t local = o - s_off[lo];
+    const uint32_t dy = local / wdt, dx = local - dy * wdt;
+    if ((int64_t)o < capacity) {
+      keys[o] = (uint32_t)geo.x + dy * (uint32_t)geo.z + dx;
+      vals[o] = s_sid[lo];
+    }
   }
 }
 
@@ -254,15 +346,24 @@ __global__ void fill_f32_kernel(float* __restrict__ p, float v, int64_t n) {
     p[i] = v;
 }
 
-__global__ void count_work_kernel(const uint32_t* __restrict__ last, int64_t npix, const uint32_t* __restrict__ ntiles,
-                                  int64_t n, int num_views, unsigned long long* __restrict__ out) {
-  unsigned long long s = 0;
+__global__ void __launch_bounds__(256) count_work_kernel(const uint32_t* __restrict__ last, int64_t npix,
+                                                         const uint32_t* __restrict__ ntiles, int64_t n, int num_views,
+                                                         unsigned long long* __restrict__ out) {
+  __shared__ unsigned long long s_pairs;
+  __shared__ unsigned int s_vis[256];
+  if (threadIdx.x == 0) s_pairs = 0;
+  s_vis[threadIdx.x] = 0;
+  __syncthreads();
+  unsigned long long acc = 0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < npix; i += (int64_t)gridDim.x * blockDim.x)
-    s += last[i];
-  if (s) atomicAdd(&out[0], s);
+    acc += last[i];
+  atomicAdd(&s_pairs, acc);
   const int64_t total = n * num_views;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x)
-    if (ntiles[i]) atomicAdd(&out[1 + i / n], 1ull);
+    if (ntiles[i]) atomicAdd(&s_vis[i / n], 1u);
+  __syncthreads();
+  if (threadIdx.x == 0 && s_pairs) atomicAdd(&out[0], s_pairs);
+  if (threadIdx.x < num_views && s_vis[threadIdx.x]) atomicAdd(&out[1 + threadIdx.x], (unsigned long long)s_vis[threadIdx.x]);
 }
 
 int grid_cap(int64_t n, int block) {
@@ -274,12 +375,13 @@ int grid_cap(int64_t n, int block) {
 
 }  // namespace
 
-void radix_scratch_sizes(int64_t n, int64_t* hist_elems, int64_t* partial_elems) {
+int64_t radix_scratch_elems(int64_t n) {
   const int64_t nb = blocks_for(n, kSortChunk);
-  *hist_elems = (int64_t)kRadix * (nb > 0 ? nb : 1);
-  const int64_t scan_n = *hist_elems > n ? *hist_elems : n;
-  *partial_elems = blocks_for(scan_n, kScanChunk) + 1;
+  // status words for every pass, global histograms, tickets
+  return (int64_t)kMaxPasses * (nb > 0 ? nb : 1) * kRadix + kMaxPasses * kRadix + kMaxPasses;
 }
+
+int64_t scan_partial_elems(int64_t n) { return blocks_for(n > 0 ? n : 1, kScanChunk) + 1; }
 
 void scan_gather_exclusive(const uint32_t* in, const uint32_t* idx, uint32_t* out, int64_t n, uint32_t* total_dev,
                            uint32_t* partials, hipStream_t st) {
@@ -294,25 +396,31 @@ void scan_gather_exclusive(const uint32_t* in, const uint32_t* idx, uint32_t* ou
 }
 
 void radix_sort_pairs(uint32_t*& keys, uint32_t*& vals, uint32_t*& keys_alt, uint32_t*& vals_alt, int64_t n,
-                      int bits, uint32_t* hist, uint32_t* partials, hipStream_t st) {
-  if (n <= 1) return;
+                      int bits, uint32_t* scratch, uint32_t* err, hipStream_t st) {
+  if (n <= 1 || bits <= 0) return;
   const int nb = blocks_for(n, kSortChunk);
-  const int64_t hn = (int64_t)kRadix * nb;
-  for (int shift = 0; shift < bits; shift += 8) {
-    radix_hist_kernel<<<nb, kSortThreads, 0, st>>>(keys, n, shift, hist);
-    scan_gather_exclusive(hist, nullptr, hist, hn, nullptr, partials, st);
-    radix_scatter_kernel<<<nb, kSortThreads, 0, st>>>(keys, vals, n, shift, hist, keys_alt, vals_alt);
+  const int passes = (bits + 7) / 8;
+  uint32_t* status = scratch;
+  uint32_t* ghist = scratch + (int64_t)kMaxPasses * nb * kRadix;
+  uint32_t* tickets = ghist + kMaxPasses * kRadix;
+  const int64_t clear = (int64_t)kMaxPasses * nb * kRadix + kMaxPasses * kRadix + kMaxPasses;
+  fill_u32_kernel<<<grid_cap(clear, 256), 256, 0, st>>>(scratch, 0u, clear);
+  global_hist_kernel<<<nb, kSortThreads, 0, st>>>(keys, n, passes, ghist);
+  for (int p = 0; p < passes; ++p) {
+    onesweep_pass_kernel<<<nb, kSortThreads, 0, st>>>(keys, vals, n, 8 * p, ghist + p * kRadix,
+                                                      status + (int64_t)p * nb * kRadix, tickets + p, err, keys_alt,
+                                                      vals_alt);
     uint32_t* t = keys; keys = keys_alt; keys_alt = t;
     t = vals; vals = vals_alt; vals_alt = t;
   }
 }
 
-void launch_emit(const uint32_t* sorted_s, const uint32_t* offsets, const int4* rect, int64_t count, int64_t n,
-                 const ViewDesc* views, int tile_w, int tile_h, uint32_t* keys, uint32_t* vals, int64_t capacity,
-                 hipStream_t st) {
+void launch_emit(const uint32_t* sorted_s, const uint32_t* offsets, const uint32_t* total_dev, const int4* rect,
+                 int64_t count, int64_t n, const ViewDesc* views, int tile_w, int tile_h, uint32_t* keys,
+                 uint32_t* vals, int64_t capacity, hipStream_t st) {
   if (count == 0) return;
-  emit_kernel<<<grid_cap(count, 256), 256, 0, st>>>(sorted_s, offsets, rect, count, n, views, tile_w, tile_h, keys,
-                                                    vals, capacity);
+  emit_kernel<<<blocks_for(count, kEmitChunk), kEmitChunk, 0, st>>>(sorted_s, offsets, total_dev, rect, count, n,
+                                                                     views, tile_w, tile_h, keys, vals, capacity);
 }
 
 void launch_tile_ranges(const uint32_t* keys, int64_t count, uint2* ranges, int64_t num_tiles, hipStream_t st) {

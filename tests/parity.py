@@ -52,6 +52,6 @@ def grad_violations(g, ref, rtol=GRAD_RTOL):
         scale = np.maximum(np.abs(b), max(0.01 * rms, 1e-6 * rms_all))
         scale = np.where(scale > 0, scale, 1e-30)
         rel = np.abs(a - b) / scale
-        l2 = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+        l2 = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-6 * rms_all * np.sqrt(b.size), 1e-300)
         out[name] = (int((rel > rtol).sum()), float(rel.max(initial=0.0)), float(l2))
     return out

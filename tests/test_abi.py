@@ -49,7 +49,7 @@ def test_ctypes_struct_layout_matches_header():
     assert ctypes.sizeof(_lib.gsr_camera) == 16 * 4 + 8
     assert ctypes.sizeof(_lib.gsr_gaussians) == 32
     assert ctypes.sizeof(_lib.gsr_image) == 24
-    assert ctypes.sizeof(_lib.gsr_options) == 4 * 3 + 12 + 4
+    assert ctypes.sizeof(_lib.gsr_options) == 4 * 3 + 12 + 4 + 4
 
 
 def test_product_does_not_import_oracle():

@@ -118,11 +118,12 @@ def check_images(outs, ref, label):
     say(label, "worst ratio to tolerance", worst)
 
 
+@pytest.mark.parametrize("ppt", [1, 2])
 @pytest.mark.parametrize("name", list(CASES))
-def test_forward_matches_fp32_oracle(gpu, orc, name):
+def test_forward_matches_fp32_oracle(gpu, orc, name, ppt):
     s = CASES[name]
-    say("case", name)
-    R = make(gpu)
+    say("case", name, "pixels per thread", ppt)
+    R = make(gpu, pixels_per_thread=ppt)
     outs = R.render(to_dev(s.params), s.sh_degree, s.cameras)
     ref = orc.render(s.params, s.sh_degree, s.cameras[0], mode="f32")
     check_images(outs[0], ref, name)
@@ -170,12 +171,13 @@ def oracle_grads(orc, s, cams, grads):
             orc.backward(s.params, s.sh_degree, cams, grads, pinned=True))
 
 
+@pytest.mark.parametrize("ppt", [1, 2])
 @pytest.mark.parametrize("name", list(CASES))
-def test_backward_matches_fp64_oracle(gpu, orc, name):
+def test_backward_matches_fp64_oracle(gpu, orc, name, ppt):
     s = CASES[name]
-    say("case", name)
+    say("case", name, "pixels per thread", ppt)
     grads = masked_grads(orc, s, 1)
-    R = make(gpu)
+    R = make(gpu, pixels_per_thread=ppt)
     p = to_dev(s.params)
     R.render(p, s.sh_degree, s.cameras)
     dgr = [tuple(to_dev(x) for x in gv) for gv in grads]
@@ -257,8 +259,8 @@ def test_tile_size_invariance(gpu):
     s = CASES["small"]
     p = to_dev(s.params)
     ref = None
-    for tile in [(16, 16), (16, 8), (8, 8), (32, 8)]:
-        outs = make(gpu, tile_w=tile[0], tile_h=tile[1]).render(p, 0, s.cameras)
+    for tile in [(16, 16, 1), (16, 16, 2), (16, 8, 1), (16, 8, 2), (8, 8, 1), (32, 8, 1), (32, 8, 2)]:
+        outs = make(gpu, tile_w=tile[0], tile_h=tile[1], pixels_per_thread=tile[2]).render(p, 0, s.cameras)
         cur = [o.cpu().numpy() for o in outs[0]]
         if ref is None:
             ref = cur
