@@ -242,39 +242,45 @@ __device__ __forceinline__ void reverse_one(bool ok, float alpha, float G, bool 
   }
 }
 
-// Reduce one Gaussian's moments over the wave and publish its gradient row.
-template <int NW, int BATCH>
-__device__ __forceinline__ void publish(float* m, bool any, int lane, int wave, int k, const float4& q0,
-                                        const float4& q1, float (*s_red)[G2_N][BATCH]) {
-  if (any) {
+// Sum over each 16-lane row of a wavefront with fused DPP adds (quad
+// permutes, then row rotations by 4 and 8): every lane ends with its row's
+// total. Step-major over the M_N moments so that the independent chains fill
+// the DPP read-after-write wait states.
+__device__ __forceinline__ void row_sums(float* m) {
 #pragma unroll
-    for (int c = 0; c < M_N; ++c) m[c] = wave_sum_lane63(m[c]);
-  }
-  if (lane == 63) {
-    // d power / d u = (2 Ah dx + Bh dy) ln 2 with Ah = -A log2(e) / 2, Bh = -B log2(e)
-    s_red[wave][G2_U][k] = any ? kLn2 * (2.0f * q0.z * m[M_X] + q0.w * m[M_Y]) : 0.0f;
-    s_red[wave][G2_V][k] = any ? kLn2 * (q0.w * m[M_X] + 2.0f * q1.x * m[M_Y]) : 0.0f;
-    s_red[wave][G2_A][k] = any ? -0.5f * m[M_XX] : 0.0f;
-    s_red[wave][G2_B][k] = any ? -m[M_XY] : 0.0f;
-    s_red[wave][G2_C][k] = any ? -0.5f * m[M_YY] : 0.0f;
-    s_red[wave][G2_O][k] = any ? m[M_O] : 0.0f;
-    s_red[wave][G2_R][k] = any ? m[M_R] : 0.0f;
-    s_red[wave][G2_G][k] = any ? m[M_G] : 0.0f;
-    s_red[wave][G2_BL][k] = any ? m[M_B] : 0.0f;
-    s_red[wave][G2_Z][k] = any ? m[M_Z] : 0.0f;
+  for (int c = 0; c < M_N; ++c) m[c] = dpp_add<0xB1, 0xF>(m[c]);   // quad_perm [1,0,3,2]
+#pragma unroll
+  for (int c = 0; c < M_N; ++c) m[c] = dpp_add<0x4E, 0xF>(m[c]);   // quad_perm [2,3,0,1]
+#pragma unroll
+  for (int c = 0; c < M_N; ++c) m[c] = dpp_add<0x124, 0xF>(m[c]);  // row_ror:4
+#pragma unroll
+  for (int c = 0; c < M_N; ++c) m[c] = dpp_add<0x128, 0xF>(m[c]);  // row_ror:8
+}
+
+// Row-reduce one Gaussian's moments and store the four row partials of this
+// wave (lanes 15, 31, 47, 63 each hold one row's sum).
+template <int NW, int BATCH>
+__device__ __forceinline__ void publish(float* m, bool any, int lane, int wave, int k,
+                                        float (*s_red)[4][M_N][BATCH]) {
+  if (any) row_sums(m);
+  if ((lane & 15) == 15) {
+    const int row = lane >> 4;
+#pragma unroll
+    for (int c = 0; c < M_N; ++c) s_red[wave][row][c][k] = any ? m[c] : 0.0f;
   }
 }
 
 template <int TW, int TH, int PPT>
-__global__ void __launch_bounds__(TW * TH / PPT) blend_backward_kernel(BlendArgs a) {
+__global__ void __launch_bounds__(TW * TH / PPT) __attribute__((amdgpu_waves_per_eu(4)))
+blend_backward_kernel(BlendArgs a) {
   using Shape = TileShape<TW, TH, PPT>;
   constexpr int NT = Shape::NT;
   constexpr int ROWS = Shape::ROWS;
   constexpr int NW = NT / 64;
-  constexpr int BATCH = NT;
+  constexpr int BATCH = NW >= 4 ? 32 : 64;      // keeps the row partials at 20 KB of LDS
   __shared__ float4 s_q0[BATCH], s_q1[BATCH], s_q2[BATCH];
   __shared__ uint32_t s_id[BATCH];
-  __shared__ float s_red[NW][G2_N][BATCH];
+  __shared__ float s_red[NW][4][M_N][BATCH];   // moments per (wave, 16-lane row)
   __shared__ uint32_t s_maxlast;
   const int tile = blockIdx.x;
   const int view = find_view(a.views, a.num_views, tile);
@@ -353,8 +359,8 @@ __global__ void __launch_bounds__(TW * TH / PPT) blend_backward_kernel(BlendArgs
         reverse_one(okb, alb, Gb, clb, dxb, dyb, qb1, qb2, gc0[i], gc1[i], gc2[i], gd[i], tb[i], T[i], S[i], mb);
       }
       const bool anya = __ballot(ca) != 0ull, anyb = __ballot(cb) != 0ull;
-      publish<NW, BATCH>(ma, anya, lane, wave, k, qa0, qa1, s_red);
-      publish<NW, BATCH>(mb, anyb, lane, wave, k - 1, qb0, qb1, s_red);
+      publish<NW, BATCH>(ma, anya, lane, wave, k, s_red);
+      publish<NW, BATCH>(mb, anyb, lane, wave, k - 1, s_red);
     }
     if (k == 0) {
       const float4 q0 = s_q0[0], q1 = s_q1[0], q2 = s_q2[0];
@@ -370,15 +376,43 @@ __global__ void __launch_bounds__(TW * TH / PPT) blend_backward_kernel(BlendArgs
         cc = cc || ok;
         reverse_one(ok, al, G, cl, dx, dy, q1, q2, gc0[i], gc1[i], gc2[i], gd[i], tb[i], T[i], S[i], m);
       }
-      publish<NW, BATCH>(m, __ballot(cc) != 0ull, lane, wave, 0, q0, q1, s_red);
+      publish<NW, BATCH>(m, __ballot(cc) != 0ull, lane, wave, 0, s_red);
     }
     __syncthreads();
-    for (int e = tid; e < cnt * G2_N; e += NT) {
+    // sum the row partials of every wave into slot [0][0], then turn the
+    // moments into screen-space gradients and add them with one atomic per
+    // (Gaussian, component)
+    for (int e = tid; e < cnt * M_N; e += NT) {
       const int c = e / cnt, kk = e - c * cnt;
       float sum = 0.0f;
 #pragma unroll
-      for (int w = 0; w < NW; ++w) sum += s_red[w][c][kk];
-      if (sum != 0.0f) unsafeAtomicAdd(&a.g2[(int64_t)s_id[kk] * G2_N + c], sum);
+      for (int w = 0; w < NW; ++w)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sum += s_red[w][r][c][kk];
+      s_red[0][0][c][kk] = sum;
+    }
+    __syncthreads();
+    for (int kk = tid; kk < cnt; kk += NT) {
+      float mm[M_N];
+#pragma unroll
+      for (int c = 0; c < M_N; ++c) mm[c] = s_red[0][0][c][kk];
+      const float4 q0 = s_q0[kk], q1 = s_q1[kk];
+      float g[G2_N];
+      // d power / d u = (2 Ah dx + Bh dy) ln 2 with Ah = -A log2(e) / 2, Bh = -B log2(e)
+      g[G2_U] = kLn2 * (2.0f * q0.z * mm[M_X] + q0.w * mm[M_Y]);
+      g[G2_V] = kLn2 * (q0.w * mm[M_X] + 2.0f * q1.x * mm[M_Y]);
+      g[G2_A] = -0.5f * mm[M_XX];
+      g[G2_B] = -mm[M_XY];
+      g[G2_C] = -0.5f * mm[M_YY];
+      g[G2_O] = mm[M_O];
+      g[G2_R] = mm[M_R];
+      g[G2_G] = mm[M_G];
+      g[G2_BL] = mm[M_B];
+      g[G2_Z] = mm[M_Z];
+      float* dst = a.g2 + (int64_t)s_id[kk] * G2_N;
+#pragma unroll
+      for (int c = 0; c < G2_N; ++c)
+        if (g[c] != 0.0f) unsafeAtomicAdd(dst + c, g[c]);
     }
   }
 }
