@@ -271,7 +271,7 @@ int render_impl(gsr_ctx* ctx, const gsr_gaussians* g, int32_t nv, const gsr_came
   uint32_t* sva = as<uint32_t>(ctx->svals_alt);
   {
     StageTimer tm(ctx, GSR_STAGE_DEPTH_SORT, st);
-    radix_sort_pairs(zk, sv, zka, sva, total, 32, as<uint32_t>(ctx->hist), as<uint32_t>(ctx->total) + 1, st);
+    radix_sort_pairs(zk, sv, zka, sva, total, nullptr, 32, as<uint32_t>(ctx->hist), as<uint32_t>(ctx->total) + 1, st);
   }
   CHECK_LAUNCH(ctx);
   // instance offsets in depth order
@@ -307,7 +307,7 @@ int render_impl(gsr_ctx* ctx, const gsr_gaussians* g, int32_t nv, const gsr_came
   CHECK_LAUNCH(ctx);
   {
     StageTimer tm(ctx, GSR_STAGE_TILE_SORT, st);
-    radix_sort_pairs(ik, iv, ika, iva, I, bits_for(ntiles - 1), as<uint32_t>(ctx->hist), total_dev + 1, st);
+    radix_sort_pairs(ik, iv, ika, iva, I, nullptr, bits_for(ntiles - 1), as<uint32_t>(ctx->hist), total_dev + 1, st);
   }
   CHECK_LAUNCH(ctx);
   {

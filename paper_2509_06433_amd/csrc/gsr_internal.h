@@ -58,10 +58,12 @@ void launch_export_splats(const float* params, int64_t n, int64_t stride, const 
 int64_t radix_scratch_elems(int64_t n);
 // Stable LSD radix sort of (keys, vals) on the low `bits` bits of the keys,
 // 8 bits per pass, ping-ponging between the buffers; on return keys/vals point
-// at the sorted data and keys_alt/vals_alt at the other pair. *err becomes
-// nonzero if a look-back wait hit its bound (the result is then invalid).
+// at the sorted data and keys_alt/vals_alt at the other pair. The element
+// count is *n_dev when n_dev is not null (n is then the capacity the grid is
+// sized for), else n. *err becomes nonzero if a look-back wait hit its bound
+// (the result is then invalid).
 void radix_sort_pairs(uint32_t*& keys, uint32_t*& vals, uint32_t*& keys_alt, uint32_t*& vals_alt, int64_t n,
-                      int bits, uint32_t* scratch, uint32_t* err, hipStream_t st);
+                      const uint32_t* n_dev, int bits, uint32_t* scratch, uint32_t* err, hipStream_t st);
 // Scan partials needed by scan_gather_exclusive for n elements.
 int64_t scan_partial_elems(int64_t n);
 // Exclusive scan out[r] = sum_{j<r} in[idx[r]] (idx may be null); total -> *total_dev.

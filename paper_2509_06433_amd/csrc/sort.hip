@@ -148,8 +148,10 @@ constexpr uint32_t kCountMask = (1u << 30) - 1;
 constexpr int kMaxPasses = 4;
 constexpr uint32_t kSpinLimit = 1u << 20;
 
-__global__ void __launch_bounds__(kSortThreads) global_hist_kernel(const uint32_t* __restrict__ keys, int64_t n,
+__global__ void __launch_bounds__(kSortThreads) global_hist_kernel(const uint32_t* __restrict__ keys,
+                                                                   const uint32_t* __restrict__ n_dev, int64_t n_host,
                                                                    int passes, uint32_t* __restrict__ ghist) {
+  const int64_t n = n_dev ? (int64_t)*n_dev : n_host;
   __shared__ uint32_t h[kSortThreads / 64][kMaxPasses][kRadix];
   const int wave = threadIdx.x >> 6;
   for (int e = threadIdx.x; e < (kSortThreads / 64) * kMaxPasses * kRadix; e += kSortThreads)
@@ -173,15 +175,19 @@ __global__ void __launch_bounds__(kSortThreads) global_hist_kernel(const uint32_
 }
 
 __global__ void __launch_bounds__(kSortThreads) onesweep_pass_kernel(
-    const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals, int64_t n, int shift,
-    const uint32_t* __restrict__ ghist, uint32_t* __restrict__ status, uint32_t* __restrict__ ticket,
-    uint32_t* __restrict__ err, uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out) {
+    const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals, const uint32_t* __restrict__ n_dev,
+    int64_t n_host, int shift, const uint32_t* __restrict__ ghist, uint32_t* __restrict__ status,
+    uint32_t* __restrict__ ticket, uint32_t* __restrict__ err, uint32_t* __restrict__ keys_out,
+    uint32_t* __restrict__ vals_out) {
   __shared__ uint32_t wcnt[kSortThreads / 64][kRadix];
-  __shared__ uint32_t gofs[kRadix];
+  __shared__ uint32_t gofs[kRadix];        // global start of each digit's run of this block
+  __shared__ uint32_t lstart[kRadix];      // block-local start of each digit's run
+  __shared__ uint32_t s_keys[kSortChunk], s_vals[kSortChunk];
   __shared__ uint32_t s_bid;
-  __shared__ uint32_t s_wsum[kSortThreads / 64];
+  __shared__ uint32_t s_wsum[2][kSortThreads / 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int d0 = threadIdx.x;                       // the digit this thread publishes and looks back for
+  const int64_t n = n_dev ? (int64_t)*n_dev : n_host;
   if (threadIdx.x == 0) s_bid = atomicAdd(ticket, 1u);
 #pragma unroll
   for (int w = 0; w < kSortThreads / 64; ++w) wcnt[w][threadIdx.x] = 0;
@@ -207,7 +213,7 @@ __global__ void __launch_bounds__(kSortThreads) onesweep_pass_kernel(
     }
     const uint32_t rank = (uint32_t)__popcll(mask & lt_mask);
     const uint32_t before = wcnt[wave][d];
-    off[r] = before + rank;
+    off[r] = valid ? before + rank : 0xFFFFFFFFu;
     if (valid && rank == 0) wcnt[wave][d] = before + (uint32_t)__popcll(mask);
     __builtin_amdgcn_wave_barrier();
   }
@@ -244,33 +250,54 @@ __global__ void __launch_bounds__(kSortThreads) onesweep_pass_kernel(
     }
     __hip_atomic_store(st, kFlagInc | (excl + mine), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-  // start of each digit in the output: exclusive scan of the global histogram
+  // exclusive scans over the 256 digits: of the global histogram (start of
+  // each digit in the output) and of this block's counts (local runs)
   {
     const uint32_t g = ghist[d0];
-    uint32_t x = g;
+    uint32_t x = g, y = mine;
 #pragma unroll
     for (int dd = 1; dd < 64; dd <<= 1) {
-      const uint32_t y = __shfl_up(x, dd, 64);
-      if (lane >= dd) x += y;
+      const uint32_t xs = __shfl_up(x, dd, 64), ys = __shfl_up(y, dd, 64);
+      if (lane >= dd) {
+        x += xs;
+        y += ys;
+      }
     }
-    if (lane == 63) s_wsum[wave] = x;
+    if (lane == 63) {
+      s_wsum[0][wave] = x;
+      s_wsum[1][wave] = y;
+    }
     __syncthreads();
-    uint32_t before = 0;
+    uint32_t bx = 0, by = 0;
 #pragma unroll
-    for (int w = 0; w < kSortThreads / 64; ++w) before += (w < wave) ? s_wsum[w] : 0u;
-    gofs[d0] = before + x - g + excl;
+    for (int w = 0; w < kSortThreads / 64; ++w) {
+      bx += (w < wave) ? s_wsum[0][w] : 0u;
+      by += (w < wave) ? s_wsum[1][w] : 0u;
+    }
+    lstart[d0] = by + y - mine;
+    gofs[d0] = bx + x - g + excl;
   }
   __syncthreads();
+  // stage the block's keys in LDS in digit order
 #pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
-    const int64_t j = base + r * 64 + lane;
-    if (j < n) {
-      const uint32_t d = (k_reg[r] >> shift) & (kRadix - 1);
-      const uint32_t pos = gofs[d] + wcnt[wave][d] + off[r];
-      if (pos < n) {
-        keys_out[pos] = k_reg[r];
-        vals_out[pos] = v_reg[r];
-      }
+    if (off[r] == 0xFFFFFFFFu) continue;
+    const uint32_t d = (k_reg[r] >> shift) & (kRadix - 1);
+    const uint32_t lp = lstart[d] + wcnt[wave][d] + off[r];
+    s_keys[lp] = k_reg[r];
+    s_vals[lp] = v_reg[r];
+  }
+  __syncthreads();
+  // consecutive threads write consecutive positions of each digit's run
+  const int64_t blk0 = (int64_t)bid * kSortChunk;
+  const int cnt = (int)(n - blk0 < kSortChunk ? (n - blk0 > 0 ? n - blk0 : 0) : kSortChunk);
+  for (int j = threadIdx.x; j < cnt; j += kSortThreads) {
+    const uint32_t key = s_keys[j];
+    const uint32_t d = (key >> shift) & (kRadix - 1);
+    const uint32_t pos = gofs[d] + (uint32_t)j - lstart[d];
+    if (pos < n) {
+      keys_out[pos] = key;
+      vals_out[pos] = s_vals[j];
     }
   }
 }
@@ -396,7 +423,7 @@ void scan_gather_exclusive(const uint32_t* in, const uint32_t* idx, uint32_t* ou
 }
 
 void radix_sort_pairs(uint32_t*& keys, uint32_t*& vals, uint32_t*& keys_alt, uint32_t*& vals_alt, int64_t n,
-                      int bits, uint32_t* scratch, uint32_t* err, hipStream_t st) {
+                      const uint32_t* n_dev, int bits, uint32_t* scratch, uint32_t* err, hipStream_t st) {
   if (n <= 1 || bits <= 0) return;
   const int nb = blocks_for(n, kSortChunk);
   const int passes = (bits + 7) / 8;
@@ -405,9 +432,9 @@ void radix_sort_pairs(uint32_t*& keys, uint32_t*& vals, uint32_t*& keys_alt, uin
   uint32_t* tickets = ghist + kMaxPasses * kRadix;
   const int64_t clear = (int64_t)kMaxPasses * nb * kRadix + kMaxPasses * kRadix + kMaxPasses;
   fill_u32_kernel<<<grid_cap(clear, 256), 256, 0, st>>>(scratch, 0u, clear);
-  global_hist_kernel<<<nb, kSortThreads, 0, st>>>(keys, n, passes, ghist);
+  global_hist_kernel<<<nb, kSortThreads, 0, st>>>(keys, n_dev, n, passes, ghist);
   for (int p = 0; p < passes; ++p) {
-    onesweep_pass_kernel<<<nb, kSortThreads, 0, st>>>(keys, vals, n, 8 * p, ghist + p * kRadix,
+    onesweep_pass_kernel<<<nb, kSortThreads, 0, st>>>(keys, vals, n_dev, n, 8 * p, ghist + p * kRadix,
                                                       status + (int64_t)p * nb * kRadix, tickets + p, err, keys_alt,
                                                       vals_alt);
     uint32_t* t = keys; keys = keys_alt; keys_alt = t;
