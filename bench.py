@@ -7,6 +7,11 @@ One step = one mapping iteration over the workload's views: forward render
 0.5 L1 depth loss against a target rendered from perturbed parameters,
 backward to the parameters (and Adam where the workload includes it). The
 inputs are resident in HBM before the timed region. Prints one JSON line.
+
+--mode graph (default) replays the whole iteration as one HIP graph
+(gsr_mapping_iteration); --mode eager issues the entry points one view at a
+time (render, loss, backward per view, then Adam). The other mode is timed
+too, after the headline, and reported in config for comparison.
 """
 from __future__ import annotations
 
@@ -43,6 +48,8 @@ def parse():
                     help="first run a plain 256 MiB device copy (reference for HBM byte counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--breakdown", action="store_true", help="print a per-stage time breakdown to stderr")
+    ap.add_argument("--mode", choices=["graph", "eager"], default="graph")
+    ap.add_argument("--compare-steps", type=int, default=20, help="steps of the other mode (0 = skip)")
     return ap.parse_args()
 
 
@@ -96,49 +103,81 @@ def main():
     gimgs = [(torch.empty_like(o[0]), torch.empty_like(o[1]), torch.zeros_like(o[2])) for o in outs]
     loss = torch.zeros(1, device=dev)
     grad = torch.zeros_like(params)
+    params0 = params.clone()
     use_adam = args.workload in ADAM_WORKLOADS
     m = torch.zeros_like(params)
     v = torch.zeros_like(params)
     P = params.shape[0]
     lrs = [1.6e-4] * 3 + [5e-3] * 3 + [1e-3] * 4 + [5e-2] + [2.5e-3] * 3 + [1.25e-4] * (P - 14)
     from paper_2509_06433_amd import _lib
+    adam = dict(m=m, v=v, lr=lrs, beta1=0.9, beta2=0.999, eps=1e-15) if use_adam else None
 
-    def step(it):
-        R.render(params, deg, cams, outs)
-        _lib.gsr_loss_l1(R.handle, cams, outs, targets, gimgs, 0.5, loss)
+    def graph_step(it):
+        if adam is not None:
+            adam["step"] = 1 if it == 1 else 0
+        R.mapping_iteration(params, deg, cams, outs, targets, grad, 0.5, loss, adam)
+
+    def eager_step(it):
         grad.zero_()
-        R.render_backward(params, deg, cams, gimgs, grad)
+        for view, cam in enumerate(cams):
+            R.render(params, deg, [cam], [outs[view]])
+            _lib.gsr_loss_l1(R.handle, [cam], [outs[view]], [targets[view]], [gimgs[view]], 0.5, loss)
+            R.render_backward(params, deg, [cam], [gimgs[view]], grad)
         if use_adam:
             R.adam_step(params, grad, m, v, lrs, it)
 
-    it = 0
-    for _ in range(args.warmup):
-        it += 1
-        step(it)
-    torch.cuda.synchronize()
+    steps = {"graph": graph_step, "eager": eager_step}
     dominant = "blend_bwd"
-    R.set_profiling([dominant])
-    R.profile(reset=True)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        it += 1
-        step(it)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = R.profile(reset=True)
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
+
+    def timed(mode, n_steps, n_warm, profile):
+        """Warm up, then time n_steps; returns (ms per step, dominant-stage profile)."""
+        fn = steps[mode]
+        R.set_profiling([dominant] if profile else [])
+        it0 = timed.it
+        for _ in range(n_warm):
+            timed.it += 1
+            fn(timed.it - it0)
+        torch.cuda.synchronize()
+        R.profile(reset=True)
+        t0 = time.perf_counter()
+        for _ in range(n_steps):
+            timed.it += 1
+            fn(timed.it - it0)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        return (t1 - t0) * 1e3 / max(n_steps, 1), R.profile(reset=True)[dominant]
+
+    timed.it = 0
+    ms_per_step, (dom_ms, dom_n) = timed(args.mode, args.steps, args.warmup, True)
+    if args.mode == "graph":
+        mst = R.mapping_status()
+        if mst["skipped"]:
+            print(f"warning: {mst['skipped']} iterations skipped for instance overflow", file=sys.stderr)
     pairs, visible = R.count_work(len(cams))
-    dom_ms, dom_n = prof[dominant]
-    dom_avg_ms = dom_ms / max(dom_n, 1)
+    dom_avg_ms = dom_ms / max(args.steps, 1)     # one launch per step in graph mode
     achieved = FLOP_PER_PAIR_BWD * pairs / (dom_avg_ms * 1e-3) / 1e12
 
+    other = "eager" if args.mode == "graph" else "graph"
+    other_ms = None
+    if args.compare_steps > 0:
+        params.copy_(params0)
+        m.zero_()
+        v.zero_()
+        timed.it = 0
+        other_ms, _ = timed(other, args.compare_steps, 2, False)
+
     # per-stage breakdown (separate, untimed pass)
+    params.copy_(params0)
+    m.zero_()
+    v.zero_()
     R.set_profiling(None)
-    for _ in range(3):
-        it += 1
-        step(it)
+    for k in range(4):
+        steps[args.mode](k + 1)
+        if k == 0:
+            torch.cuda.synchronize()
+            R.profile(reset=True)
     torch.cuda.synchronize()
-    stages = {k: (ms / max(n, 1)) for k, (ms, n) in R.profile(reset=True).items() if n}
+    stages = {k: ms / 3 for k, (ms, n) in R.profile(reset=True).items() if n}     # ms per step
     R.set_profiling([])
     render_ms = sum(stages.get(k, 0.0) for k in ["project", "depth_sort", "scan", "emit", "tile_sort", "ranges",
                                                    "blend_fwd"])
@@ -165,14 +204,16 @@ def main():
         "config": {"workload": scene.name, "views": len(cams),
                    "resolutions": sorted({f"{c.width}x{c.height}" for c in cams}),
                    "gaussians": scene.num, "sh_degree": deg, "tile": args.tile, "pixels_per_thread": args.ppt or 1,
-                   "adam": use_adam,
+                   "adam": use_adam, "mode": args.mode,
+                   f"{other}_iters_s": round(1000.0 / other_ms, 3) if other_ms else None,
                    "render_mpix_s": round(mpix, 2) if mpix else None,
                    "instances": st["instances"], "visible_per_view": visible,
                    "stage_ms": {k: round(x, 4) for k, x in stages.items()}},
         "roofline": {"bound": "alu", "kernel": dominant, "achieved": round(achieved, 3),
                      "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": None,
-                     "avg_ms": round(dom_avg_ms, 4), "pairs": pairs, "flop_per_pair": FLOP_PER_PAIR_BWD},
+                     "avg_ms": round(dom_avg_ms, 4), "launches": dom_n, "pairs": pairs,
+                     "flop_per_pair": FLOP_PER_PAIR_BWD},
     }
     if not args.no_cpu_baseline:
         tnp = [(t[0].cpu().numpy(), t[1].cpu().numpy()) for t in targets]

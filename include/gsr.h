@@ -149,10 +149,61 @@ int gsr_adam_step(gsr_ctx* ctx, float* params, const float* grads, float* m, flo
                   int64_t num, int64_t stride, int32_t num_planes, const float* lr_per_plane,
                   float beta1, float beta2, float eps, int32_t step, void* stream);
 
-/* Status of the last render on this context (synchronises the context's last
- * stream): number of (tile, Gaussian) instances over all views, number of
- * visible (view, Gaussian) splats, and the number of tiles. Any pointer may
- * be NULL. */
+/* Optimiser of a mapping iteration: Adam over every parameter plane. */
+typedef struct {
+  float* m;                   /* device [P][stride] first moments, updated in place */
+  float* v;                   /* device [P][stride] second moments, updated in place */
+  const float* lr_per_plane;  /* host [P] learning rate of each parameter plane */
+  float beta1, beta2, eps;
+  int32_t step;               /* > 0: this call's update is Adam step `step` and the
+                                 context's step count restarts there; 0: continue the
+                                 count kept on the device (one per completed update) */
+} gsr_adam;
+
+/* One mapping iteration of the continuous map optimisation (paper Sec. II-B,
+ * mapping thread): forward render of num_views views, the L1 loss of
+ * gsr_loss_l1 against `targets`, the backward to the parameters and, if adam
+ * is not NULL, one Adam update of params (in place) -- the whole iteration
+ * enqueued on `stream` as one replay of a HIP graph, with no host
+ * synchronisation.
+ *   params       device [P][stride] (layout above; updated when adam != NULL)
+ *   out          host [num_views] of device images: the rendered views (written)
+ *   targets      host [num_views] of device images: rgb and depth targets
+ *   grad_params  device [P][stride]: overwritten with dL/dparams
+ *   loss         device float, overwritten with L (may be NULL)
+ * The context captures the graph on the first call and again whenever a
+ * pointer, size, num_views, image size, depth_weight, the Adam constants or
+ * the profiling mask differ from the capture; camera poses and intrinsics,
+ * target and output image pointers and learning rates may change between
+ * calls without a new capture. Instance storage has a fixed capacity, set
+ * from the instance count of a first pass (x1.25): an iteration whose count
+ * exceeds it, or whose sort wait expired, is skipped on the device (params
+ * and Adam state unchanged; its images, loss and gradients are not valid),
+ * counted, and the next call captures again with a larger capacity. The
+ * status and copy queries then report on this iteration's buffers. */
+int gsr_mapping_iteration(gsr_ctx* ctx, float* params, int64_t num, int64_t stride, int32_t sh_degree,
+                          int32_t num_views, const gsr_camera* cams, const gsr_image* out,
+                          const gsr_image* targets, float depth_weight, float* grad_params,
+                          float* loss, const gsr_adam* adam, void* stream);
+
+/* Counters of the context's mapping iterations (synchronises the stream of
+ * the last iteration). Returns GSR_ERR_DEVICE if any iteration's sort wait
+ * expired. */
+typedef struct {
+  int64_t iterations;       /* completed (not skipped) iterations */
+  int64_t skipped;          /* iterations skipped for instance overflow or an expired wait */
+  int64_t captures;         /* graphs captured */
+  int64_t capacity;         /* instance slots of the current graph */
+  int64_t last_instances;   /* instance count of the last iteration */
+  int64_t adam_steps;       /* the device-side Adam step count */
+} gsr_mapping_stats;
+int gsr_mapping_status(gsr_ctx* ctx, gsr_mapping_stats* out);
+
+/* Status of the last render (gsr_render or gsr_mapping_iteration) on this
+ * context (synchronises the context's last stream): number of (tile,
+ * Gaussian) instances over all views, -1 for the number of visible splats
+ * (see gsr_count_work), and the number of tiles. Any pointer may be NULL.
+ * GSR_ERR_DEVICE if that render's sort wait expired. */
 int gsr_query_status(gsr_ctx* ctx, int64_t* num_instances, int64_t* num_visible,
                      int64_t* num_tiles);
 

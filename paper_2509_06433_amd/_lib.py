@@ -22,7 +22,7 @@ STATUS_NAMES = {0: "GSR_OK", -1: "GSR_ERR_INVALID", -2: "GSR_ERR_OOM", -3: "GSR_
 EXPORTED = sorted(["gsr_create", "gsr_destroy", "gsr_render", "gsr_render1", "gsr_render_backward", "gsr_loss_l1",
                    "gsr_adam_step", "gsr_query_status", "gsr_copy_instances", "gsr_copy_splats",
                    "gsr_count_work", "gsr_set_profiling", "gsr_get_profile", "gsr_last_hip_error",
-                   "gsr_status_string"])
+                   "gsr_status_string", "gsr_mapping_iteration", "gsr_mapping_status"])
 
 STAGES = ["project", "depth_sort", "scan", "emit", "tile_sort", "ranges", "blend_fwd", "loss", "blend_bwd",
           "project_bwd", "adam", "zero"]
@@ -57,6 +57,17 @@ class gsr_image(ctypes.Structure):
     _fields_ = [("rgb", ctypes.c_void_p), ("depth", ctypes.c_void_p), ("alpha", ctypes.c_void_p)]
 
 
+class gsr_adam(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_void_p), ("v", ctypes.c_void_p), ("lr_per_plane", ctypes.POINTER(ctypes.c_float)),
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
+                ("step", ctypes.c_int32)]
+
+
+class gsr_mapping_stats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int64), ("skipped", ctypes.c_int64), ("captures", ctypes.c_int64),
+                ("capacity", ctypes.c_int64), ("last_instances", ctypes.c_int64), ("adam_steps", ctypes.c_int64)]
+
+
 _lib = None
 
 
@@ -86,6 +97,9 @@ def load():
             "gsr_get_profile": ([vp, i32, P(ctypes.c_double), P(i64), i32], ctypes.c_int),
             "gsr_last_hip_error": ([vp], ctypes.c_int),
             "gsr_status_string": ([ctypes.c_int], ctypes.c_char_p),
+            "gsr_mapping_iteration": ([vp, vp, i64, i64, i32, i32, P(gsr_camera), P(gsr_image), P(gsr_image), f32,
+                                       vp, vp, P(gsr_adam), vp], ctypes.c_int),
+            "gsr_mapping_status": ([vp, P(gsr_mapping_stats)], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -257,6 +271,37 @@ def gsr_get_profile(ctx, reset=True):
         _check(ctx, "gsr_get_profile", load().gsr_get_profile(ctx, k, ctypes.byref(ms), ctypes.byref(n), int(reset)))
         out[name] = (ms.value, n.value)
     return out
+
+
+def gsr_mapping_iteration(ctx, params, sh_degree, cams, outs, targets, depth_weight, grad_params, loss=None,
+                          adam=None, stream=None):
+    """One graph-replayed mapping iteration. adam: None or a dict with m, v (tensors like params),
+    lr (per-plane list), beta1, beta2, eps, step (0 = continue the device count)."""
+    g = _gauss(params, sh_degree)
+    if grad_params.shape != params.shape or grad_params.stride() != params.stride():
+        raise ValueError("grad_params must match params in shape and stride")
+    a = None
+    if adam is not None:
+        for t in (adam["m"], adam["v"]):
+            if t.shape != params.shape or t.stride() != params.stride():
+                raise ValueError("Adam tensors must match params in shape and stride")
+        lr = adam["lr"]
+        if len(lr) != params.shape[0]:
+            raise ValueError("one learning rate per parameter plane")
+        lr_arr = (ctypes.c_float * len(lr))(*[float(x) for x in lr])
+        a = gsr_adam(_ptr(adam["m"]), _ptr(adam["v"]), lr_arr, float(adam.get("beta1", 0.9)),
+                     float(adam.get("beta2", 0.999)), float(adam.get("eps", 1e-15)), int(adam.get("step", 0)))
+    _check(ctx, "gsr_mapping_iteration",
+           load().gsr_mapping_iteration(ctx, g.params, g.num, g.stride, sh_degree, len(cams), _cams(cams),
+                                        _images(outs), _images([(t[0], t[1], None) for t in targets]),
+                                        float(depth_weight), _ptr(grad_params), _ptr(loss),
+                                        ctypes.byref(a) if a is not None else None, _stream(stream)))
+
+
+def gsr_mapping_status(ctx):
+    s = gsr_mapping_stats()
+    _check(ctx, "gsr_mapping_status", load().gsr_mapping_status(ctx, ctypes.byref(s)))
+    return {k: getattr(s, k) for k, _ in gsr_mapping_stats._fields_}
 
 
 def gsr_status_string(status: int) -> str:

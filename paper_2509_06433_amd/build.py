@@ -33,6 +33,7 @@ SOURCES = {
     "blend.hip": ["-ffp-contract=off"],
     "sort.hip": [],
     "api.hip": [],
+    "iteration.hip": [],
 }
 
 

@@ -1,5 +1,5 @@
-// Host side of the C ABI: argument checking, the context's device scratch,
-// and the order of the kernel launches for render, backward, loss and Adam.
+// Host side of the C ABI: argument checking and the order of the kernel
+// launches for render, backward, loss and Adam.
 
 #include <algorithm>
 #include <cmath>
@@ -7,325 +7,133 @@
 #include <new>
 #include <vector>
 
-#include "../../include/gsr.h"
-#include "gsr_internal.h"
+#include "context.h"
 
 using namespace gsr;
 
-namespace {
+namespace gsr {
 
-struct DevBuf {
-  void* p = nullptr;
-  size_t cap = 0;
-};
-
-// Pinned staging slots for host->device uploads of small descriptor arrays;
-// each slot is reused only after the event recorded behind its last copy.
-constexpr int kSlots = 8;
-constexpr size_t kSlotBytes = 64 * 1024;
-
-}  // namespace
-
-struct gsr_ctx {
-  int tile_w = 16, tile_h = 16;
-  int ppt = 1;                          // pixels per thread in the blend kernels
-  float bg[3] = {0.f, 0.f, 0.f};
-  float znear = 0.2f;
-  int hip_err = 0;
-  hipStream_t last_stream = nullptr;
-
-  DevBuf views, images, images2, images3;
-  DevBuf splats, rect, ntiles, zkey, svals, zkey_alt, svals_alt, offsets;
-  DevBuf ikeys, ivals, ikeys_alt, ivals_alt;
-  DevBuf hist, partials, ranges, tfinal, last, g2, lr, total, splat_out;
-  uint32_t* host_total = nullptr;
-  void* slots[kSlots] = {};
-  hipEvent_t slot_ev[kSlots] = {};
-  bool slot_used[kSlots] = {};
-  int next_slot = 0;
-
-  // state of the last render, checked by the backward
-  bool have_forward = false;
-  const float* fw_params = nullptr;
-  int64_t fw_num = 0, fw_stride = 0;
-  int fw_deg = 0;
-  std::vector<gsr_camera> fw_cams;
-  int64_t fw_instances = 0, fw_tiles = 0, fw_pixels = 0;
-  std::vector<ViewDesc> fw_views;
-  uint32_t* sorted_splats = nullptr;   // depth-sorted splat indices
-  uint32_t* inst_keys = nullptr;       // sorted instance list
-  uint32_t* inst_vals = nullptr;
-
-  // per-stage timing
-  uint32_t profile_mask = 0;          // bit k: time stage k
-  std::vector<hipEvent_t> ev_pool;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending[GSR_NUM_STAGES];
-  DevBuf counts;
-};
-
-namespace {
-
-#define HIP_TRY(ctx, expr)                      \
-  do {                                          \
-    hipError_t e_ = (expr);                     \
-    if (e_ != hipSuccess) {                     \
-      (ctx)->hip_err = (int)e_;                 \
-      return GSR_ERR_HIP;                       \
-    }                                           \
-  } while (0)
-
-#define CHECK_LAUNCH(ctx) HIP_TRY(ctx, hipGetLastError())
-
-int ensure(gsr_ctx* ctx, DevBuf& b, size_t bytes) {
-  if (bytes <= b.cap) return GSR_OK;
-  size_t want = std::max<size_t>(bytes + bytes / 4, 256);
-  if (b.p) {
-    HIP_TRY(ctx, hipDeviceSynchronize());
-    HIP_TRY(ctx, hipFree(b.p));
-    b.p = nullptr;
-    b.cap = 0;
-  }
-  hipError_t e = hipMalloc(&b.p, want);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    b.p = nullptr;
-    e = hipMalloc(&b.p, bytes);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      b.p = nullptr;
-      return GSR_ERR_OOM;
-    }
-    want = bytes;
-  }
-  b.cap = want;
-  return GSR_OK;
-}
-
-template <class T>
-T* as(DevBuf& b) {
-  return static_cast<T*>(b.p);
-}
-
-int upload(gsr_ctx* ctx, void* dev, const void* host, size_t bytes, hipStream_t st) {
-  if (bytes == 0) return GSR_OK;
-  if (bytes > kSlotBytes) {
-    HIP_TRY(ctx, hipMemcpyAsync(dev, host, bytes, hipMemcpyHostToDevice, st));
-    HIP_TRY(ctx, hipStreamSynchronize(st));
-    return GSR_OK;
-  }
-  const int k = ctx->next_slot;
-  ctx->next_slot = (k + 1) % kSlots;
-  if (ctx->slot_used[k]) HIP_TRY(ctx, hipEventSynchronize(ctx->slot_ev[k]));
-  std::memcpy(ctx->slots[k], host, bytes);
-  HIP_TRY(ctx, hipMemcpyAsync(dev, ctx->slots[k], bytes, hipMemcpyHostToDevice, st));
-  HIP_TRY(ctx, hipEventRecord(ctx->slot_ev[k], st));
-  ctx->slot_used[k] = true;
-  return GSR_OK;
-}
-
-// Brackets one stage's launches with events when profiling is on.
-struct StageTimer {
-  gsr_ctx* ctx;
-  int stage;
-  hipStream_t st;
-  hipEvent_t a = nullptr, b = nullptr;
-  StageTimer(gsr_ctx* c, int s, hipStream_t stream) : ctx(c), stage(s), st(stream) {
-    if (!((ctx->profile_mask >> s) & 1u)) return;
-    a = take();
-    b = take();
-    if (a && b) (void)hipEventRecord(a, st);
-  }
-  hipEvent_t take() {
-    if (!ctx->ev_pool.empty()) {
-      hipEvent_t e = ctx->ev_pool.back();
-      ctx->ev_pool.pop_back();
-      return e;
-    }
-    hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
-    return e;
-  }
-  ~StageTimer() {
-    if (!a || !b) return;
-    (void)hipEventRecord(b, st);
-    ctx->ev_pending[stage].emplace_back(a, b);
-  }
-};
-
-#define RET_IF(expr)            \
-  do {                          \
-    int r_ = (expr);            \
-    if (r_ != GSR_OK) return r_; \
-  } while (0)
-
-int check_gaussians(const gsr_gaussians* g) {
-  if (!g) return GSR_ERR_INVALID;
-  if (g->num < 0 || g->num > (int64_t(1) << 27)) return GSR_ERR_INVALID;
-  if (g->stride < g->num) return GSR_ERR_INVALID;
-  if (g->sh_degree < 0 || g->sh_degree > 3) return GSR_ERR_INVALID;
-  if (g->num > 0 && !g->params) return GSR_ERR_INVALID;
-  return GSR_OK;
-}
-
-int num_planes(int deg) { return 11 + 3 * (deg + 1) * (deg + 1); }
-
-int check_cams(const gsr_camera* cams, int32_t num_views) {
-  if (num_views < 1 || num_views > 256 || !cams) return GSR_ERR_INVALID;
-  for (int v = 0; v < num_views; ++v) {
-    const gsr_camera& c = cams[v];
-    if (c.width < 1 || c.height < 1 || c.width > 16384 || c.height > 16384) return GSR_ERR_INVALID;
-    if (!(c.fx > 0.f) || !(c.fy > 0.f) || !std::isfinite(c.cx) || !std::isfinite(c.cy)) return GSR_ERR_INVALID;
-    for (int k = 0; k < 9; ++k) if (!std::isfinite(c.R[k])) return GSR_ERR_INVALID;
-    for (int k = 0; k < 3; ++k) if (!std::isfinite(c.t[k])) return GSR_ERR_INVALID;
-  }
-  return GSR_OK;
-}
-
-// Per-view descriptors; returns total tiles and pixels.
-std::vector<ViewDesc> make_views(const gsr_ctx* ctx, const gsr_camera* cams, int nv, int64_t* tiles,
-                                 int64_t* pixels) {
-  std::vector<ViewDesc> out(nv);
-  int64_t toff = 0, poff = 0;
-  for (int v = 0; v < nv; ++v) {
-    const gsr_camera& c = cams[v];
-    ViewDesc& d = out[v];
-    std::memcpy(d.R, c.R, sizeof(d.R));
-    std::memcpy(d.t, c.t, sizeof(d.t));
-    d.fx = c.fx; d.fy = c.fy; d.cx = c.cx; d.cy = c.cy;
-    for (int j = 0; j < 3; ++j) {
-      double s = 0.0;
-      for (int i = 0; i < 3; ++i) s -= (double)c.R[i * 3 + j] * (double)c.t[i];
-      d.campos[j] = (float)s;
-    }
-    d.width = c.width; d.height = c.height;
-    d.tiles_x = (c.width + ctx->tile_w - 1) / ctx->tile_w;
-    d.tiles_y = (c.height + ctx->tile_h - 1) / ctx->tile_h;
-    d.tile_offset = (int32_t)toff;
-    d.pix_offset = (int32_t)poff;
-    toff += (int64_t)d.tiles_x * d.tiles_y;
-    poff += (int64_t)c.width * c.height;
-  }
-  *tiles = toff;
-  *pixels = poff;
-  return out;
-}
-
-int bits_for(int64_t max_key) {
-  int b = 0;
-  while (b < 32 && (int64_t(1) << b) <= max_key) ++b;
-  return b;
-}
-
-int render_impl(gsr_ctx* ctx, const gsr_gaussians* g, int32_t nv, const gsr_camera* cams, const gsr_image* out,
-                hipStream_t st) {
+int plan_render(gsr_ctx* ctx, const gsr_gaussians* g, int32_t nv, const gsr_camera* cams, RenderPlan* plan) {
   RET_IF(check_gaussians(g));
   RET_IF(check_cams(cams, nv));
-  if (!out) return GSR_ERR_INVALID;
-  for (int v = 0; v < nv; ++v)
-    if (!out[v].rgb || !out[v].depth || !out[v].alpha) return GSR_ERR_INVALID;
-  ctx->have_forward = false;
-  ctx->last_stream = st;
-  const int64_t N = g->num;
-  const int64_t total = N * nv;
-  if (total > (int64_t(1) << 31)) return GSR_ERR_INVALID;
-  int64_t ntiles = 0, npix = 0;
-  std::vector<ViewDesc> views = make_views(ctx, cams, nv, &ntiles, &npix);
-  if (ntiles >= (int64_t(1) << 31)) return GSR_ERR_INVALID;
+  RenderPlan& P = *plan;
+  P.num = g->num;
+  P.stride = g->stride;
+  P.deg = g->sh_degree;
+  P.nv = nv;
+  P.total = g->num * nv;
+  if (P.total > (int64_t(1) << 31)) return GSR_ERR_INVALID;
+  P.views = make_views(ctx, cams, nv, &P.ntiles, &P.npix);
+  if (P.ntiles >= (int64_t(1) << 31)) return GSR_ERR_INVALID;
+  P.capacity = 0;
+  P.sorted_splats = P.inst_keys = P.inst_vals = nullptr;
+  return GSR_OK;
+}
+
+int size_instances(gsr_ctx* ctx, Buffers& B, const RenderPlan& P) {
+  if (P.capacity >= (int64_t(1) << 30)) return GSR_ERR_CAPACITY;
+  const size_t i4 = sizeof(uint32_t) * (size_t)std::max<int64_t>(P.capacity, 1);
+  RET_IF(ensure(ctx, B.ikeys, i4));
+  RET_IF(ensure(ctx, B.ivals, i4));
+  RET_IF(ensure(ctx, B.ikeys_alt, i4));
+  RET_IF(ensure(ctx, B.ivals_alt, i4));
+  RET_IF(ensure(ctx, B.hist, sizeof(uint32_t) * (size_t)radix_scratch_elems(std::max(P.total, P.capacity))));
+  return GSR_OK;
+}
+
+int size_render(gsr_ctx* ctx, Buffers& B, RenderPlan& P, const gsr_image* out, hipStream_t st) {
+  const int nv = P.nv;
   std::vector<ViewImages> ims(nv);
   for (int v = 0; v < nv; ++v) ims[v] = ViewImages{out[v].rgb, out[v].depth, out[v].alpha};
+  const size_t t4 = sizeof(uint32_t) * (size_t)std::max<int64_t>(P.total, 1);
+  RET_IF(ensure(ctx, B.views, sizeof(ViewDesc) * nv));
+  RET_IF(ensure(ctx, B.images, sizeof(ViewImages) * nv));
+  RET_IF(ensure(ctx, B.images2, sizeof(ViewImages) * nv));
+  RET_IF(ensure(ctx, B.splats, sizeof(Splat) * (size_t)std::max<int64_t>(P.total, 1)));
+  RET_IF(ensure(ctx, B.rect, sizeof(int4) * (size_t)std::max<int64_t>(P.total, 1)));
+  RET_IF(ensure(ctx, B.ntiles, t4));
+  RET_IF(ensure(ctx, B.zkey, t4));
+  RET_IF(ensure(ctx, B.svals, t4));
+  RET_IF(ensure(ctx, B.zkey_alt, t4));
+  RET_IF(ensure(ctx, B.svals_alt, t4));
+  RET_IF(ensure(ctx, B.offsets, t4));
+  RET_IF(size_instances(ctx, B, P));
+  RET_IF(ensure(ctx, B.ranges, sizeof(uint2) * (size_t)std::max<int64_t>(P.ntiles, 1)));
+  RET_IF(ensure(ctx, B.tfinal, sizeof(float) * (size_t)P.npix));
+  RET_IF(ensure(ctx, B.last, sizeof(uint32_t) * (size_t)P.npix));
+  RET_IF(ensure(ctx, B.g2, sizeof(float) * G2_N * (size_t)std::max<int64_t>(P.total, 1)));
+  RET_IF(ensure(ctx, B.total, 64));
+  RET_IF(ensure(ctx, B.partials, sizeof(uint32_t) * (size_t)scan_partial_elems(P.total)));
+  RET_IF(upload(ctx, B.views.p, P.views.data(), sizeof(ViewDesc) * nv, st));
+  RET_IF(upload(ctx, B.images.p, ims.data(), sizeof(ViewImages) * nv, st));
+  return GSR_OK;
+}
 
-  const size_t t4 = sizeof(uint32_t) * (size_t)std::max<int64_t>(total, 1);
-  RET_IF(ensure(ctx, ctx->views, sizeof(ViewDesc) * nv));
-  RET_IF(ensure(ctx, ctx->images, sizeof(ViewImages) * nv));
-  RET_IF(ensure(ctx, ctx->splats, sizeof(Splat) * (size_t)std::max<int64_t>(total, 1)));
-  RET_IF(ensure(ctx, ctx->rect, sizeof(int4) * (size_t)std::max<int64_t>(total, 1)));
-  RET_IF(ensure(ctx, ctx->ntiles, t4));
-  RET_IF(ensure(ctx, ctx->zkey, t4));
-  RET_IF(ensure(ctx, ctx->svals, t4));
-  RET_IF(ensure(ctx, ctx->zkey_alt, t4));
-  RET_IF(ensure(ctx, ctx->svals_alt, t4));
-  RET_IF(ensure(ctx, ctx->offsets, t4));
-  RET_IF(ensure(ctx, ctx->ranges, sizeof(uint2) * (size_t)ntiles));
-  RET_IF(ensure(ctx, ctx->tfinal, sizeof(float) * (size_t)npix));
-  RET_IF(ensure(ctx, ctx->last, sizeof(uint32_t) * (size_t)npix));
-  RET_IF(ensure(ctx, ctx->total, 64));
-  RET_IF(ensure(ctx, ctx->hist, sizeof(uint32_t) * (size_t)radix_scratch_elems(total)));
-  RET_IF(ensure(ctx, ctx->partials, sizeof(uint32_t) * (size_t)scan_partial_elems(total)));
-
-  RET_IF(upload(ctx, ctx->views.p, views.data(), sizeof(ViewDesc) * nv, st));
-  RET_IF(upload(ctx, ctx->images.p, ims.data(), sizeof(ViewImages) * nv, st));
-
-  launch_fill_u32(as<uint32_t>(ctx->total), 0u, 2, st);
-  // projection (one thread per view x Gaussian)
+int launch_front(gsr_ctx* ctx, Buffers& B, RenderPlan& P, const float* params, hipStream_t st) {
+  const int nv = P.nv;
+  uint32_t* totals = as<uint32_t>(B.total);
   {
-  StageTimer tm(ctx, GSR_STAGE_PROJECT, st);
-  launch_project(g->params, N, g->stride, g->sh_degree, nv, as<ViewDesc>(ctx->views), ctx->tile_w, ctx->tile_h,
-                 ctx->znear, as<Splat>(ctx->splats), as<int4>(ctx->rect), as<uint32_t>(ctx->ntiles),
-                 as<uint32_t>(ctx->zkey), as<uint32_t>(ctx->svals), st);
+    StageTimer tm(ctx, GSR_STAGE_PROJECT, st);
+    launch_project(params, P.num, P.stride, P.deg, nv, as<ViewDesc>(B.views), ctx->tile_w, ctx->tile_h, ctx->znear,
+                   as<Splat>(B.splats), as<int4>(B.rect), as<uint32_t>(B.ntiles), as<uint32_t>(B.zkey),
+                   as<uint32_t>(B.svals), st);
   }
   CHECK_LAUNCH(ctx);
-  // depth sort of the splats
-  uint32_t* zk = as<uint32_t>(ctx->zkey);
-  uint32_t* sv = as<uint32_t>(ctx->svals);
-  uint32_t* zka = as<uint32_t>(ctx->zkey_alt);
-  uint32_t* sva = as<uint32_t>(ctx->svals_alt);
+  uint32_t* zk = as<uint32_t>(B.zkey);
+  uint32_t* sv = as<uint32_t>(B.svals);
+  uint32_t* zka = as<uint32_t>(B.zkey_alt);
+  uint32_t* sva = as<uint32_t>(B.svals_alt);
   {
     StageTimer tm(ctx, GSR_STAGE_DEPTH_SORT, st);
-    radix_sort_pairs(zk, sv, zka, sva, total, nullptr, 32, as<uint32_t>(ctx->hist), as<uint32_t>(ctx->total) + 1, st);
+    radix_sort_pairs(zk, sv, zka, sva, P.total, nullptr, 32, as<uint32_t>(B.hist), totals + 1, st);
   }
   CHECK_LAUNCH(ctx);
-  // instance offsets in depth order
-  uint32_t* total_dev = as<uint32_t>(ctx->total);
   {
     StageTimer tm(ctx, GSR_STAGE_SCAN, st);
-    scan_gather_exclusive(as<uint32_t>(ctx->ntiles), sv, as<uint32_t>(ctx->offsets), total, total_dev,
-                          as<uint32_t>(ctx->partials), st);
+    scan_gather_exclusive(as<uint32_t>(B.ntiles), sv, as<uint32_t>(B.offsets), P.total, totals,
+                          as<uint32_t>(B.partials), st);
   }
   CHECK_LAUNCH(ctx);
-  HIP_TRY(ctx, hipMemcpyAsync(ctx->host_total, total_dev, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-  HIP_TRY(ctx, hipStreamSynchronize(st));
-  const int64_t I = (int64_t)ctx->host_total[0];
-  if (ctx->host_total[1] != 0) return GSR_ERR_DEVICE;
+  P.sorted_splats = sv;
+  return GSR_OK;
+}
 
-  const size_t i4 = sizeof(uint32_t) * (size_t)std::max<int64_t>(I, 1);
-  RET_IF(ensure(ctx, ctx->ikeys, i4));
-  RET_IF(ensure(ctx, ctx->ivals, i4));
-  RET_IF(ensure(ctx, ctx->ikeys_alt, i4));
-  RET_IF(ensure(ctx, ctx->ivals_alt, i4));
-  if (I >= (int64_t(1) << 30)) return GSR_ERR_CAPACITY;
-  RET_IF(ensure(ctx, ctx->hist, sizeof(uint32_t) * (size_t)radix_scratch_elems(std::max(I, total))));
-
-  uint32_t* ik = as<uint32_t>(ctx->ikeys);
-  uint32_t* iv = as<uint32_t>(ctx->ivals);
-  uint32_t* ika = as<uint32_t>(ctx->ikeys_alt);
-  uint32_t* iva = as<uint32_t>(ctx->ivals_alt);
+int launch_back(gsr_ctx* ctx, Buffers& B, RenderPlan& P, hipStream_t st) {
+  uint32_t* totals = as<uint32_t>(B.total);
+  uint32_t* ik = as<uint32_t>(B.ikeys);
+  uint32_t* iv = as<uint32_t>(B.ivals);
+  uint32_t* ika = as<uint32_t>(B.ikeys_alt);
+  uint32_t* iva = as<uint32_t>(B.ivals_alt);
   {
     StageTimer tm(ctx, GSR_STAGE_EMIT, st);
-    launch_emit(sv, as<uint32_t>(ctx->offsets), total_dev, as<int4>(ctx->rect), total, N, as<ViewDesc>(ctx->views),
-                ctx->tile_w, ctx->tile_h, ik, iv, I, st);
+    launch_emit(P.sorted_splats, as<uint32_t>(B.offsets), totals, as<int4>(B.rect), P.total, P.num,
+                as<ViewDesc>(B.views), ctx->tile_w, ctx->tile_h, ik, iv, P.capacity, totals + 2, st);
   }
   CHECK_LAUNCH(ctx);
   {
     StageTimer tm(ctx, GSR_STAGE_TILE_SORT, st);
-    radix_sort_pairs(ik, iv, ika, iva, I, nullptr, bits_for(ntiles - 1), as<uint32_t>(ctx->hist), total_dev + 1, st);
+    radix_sort_pairs(ik, iv, ika, iva, P.capacity, totals, bits_for(P.ntiles - 1), as<uint32_t>(B.hist), totals + 1,
+                     st);
   }
   CHECK_LAUNCH(ctx);
   {
     StageTimer tm(ctx, GSR_STAGE_RANGES, st);
-    launch_tile_ranges(ik, I, as<uint2>(ctx->ranges), ntiles, st);
+    launch_tile_ranges(ik, totals, P.capacity, as<uint2>(B.ranges), P.ntiles, st);
   }
   CHECK_LAUNCH(ctx);
+  P.inst_keys = ik;
+  P.inst_vals = iv;
 
   BlendArgs ba{};
-  ba.views = as<ViewDesc>(ctx->views);
-  ba.images = as<ViewImages>(ctx->images);
-  ba.num_views = nv;
-  ba.num_tiles = (int32_t)ntiles;
-  ba.ranges = as<uint2>(ctx->ranges);
+  ba.views = as<ViewDesc>(B.views);
+  ba.images = as<ViewImages>(B.images);
+  ba.num_views = P.nv;
+  ba.num_tiles = (int32_t)P.ntiles;
+  ba.ranges = as<uint2>(B.ranges);
   ba.inst_vals = iv;
-  ba.splats = as<Splat>(ctx->splats);
-  ba.tfinal = as<float>(ctx->tfinal);
-  ba.last = as<uint32_t>(ctx->last);
+  ba.splats = as<Splat>(B.splats);
+  ba.tfinal = as<float>(B.tfinal);
+  ba.last = as<uint32_t>(B.last);
   ba.g2 = nullptr;
   for (int k = 0; k < 3; ++k) ba.bg[k] = ctx->bg[k];
   {
@@ -333,57 +141,28 @@ int render_impl(gsr_ctx* ctx, const gsr_gaussians* g, int32_t nv, const gsr_came
     launch_blend_forward(ba, ctx->tile_w, ctx->tile_h, ctx->ppt, st);
   }
   CHECK_LAUNCH(ctx);
-
-  ctx->have_forward = true;
-  ctx->fw_params = g->params;
-  ctx->fw_num = N;
-  ctx->fw_stride = g->stride;
-  ctx->fw_deg = g->sh_degree;
-  ctx->fw_cams.assign(cams, cams + nv);
-  ctx->fw_instances = I;
-  ctx->fw_tiles = ntiles;
-  ctx->fw_pixels = npix;
-  ctx->fw_views = views;
-  ctx->sorted_splats = sv;
-  ctx->inst_keys = ik;
-  ctx->inst_vals = iv;
   return GSR_OK;
 }
 
-int backward_impl(gsr_ctx* ctx, const gsr_gaussians* g, int32_t nv, const gsr_camera* cams,
-                  const gsr_image* grad_out, float* grad_params, hipStream_t st) {
-  RET_IF(check_gaussians(g));
-  RET_IF(check_cams(cams, nv));
-  if (!grad_out || (g->num > 0 && !grad_params)) return GSR_ERR_INVALID;
-  if (!ctx->have_forward || ctx->fw_params != g->params || ctx->fw_num != g->num || ctx->fw_stride != g->stride ||
-      ctx->fw_deg != g->sh_degree || (int)ctx->fw_cams.size() != nv ||
-      std::memcmp(ctx->fw_cams.data(), cams, sizeof(gsr_camera) * nv) != 0)
-    return GSR_ERR_STATE;
-  ctx->last_stream = st;
-  const int64_t N = g->num;
-  const int64_t total = N * nv;
-  std::vector<ViewImages> ims(nv);
-  for (int v = 0; v < nv; ++v) ims[v] = ViewImages{grad_out[v].rgb, grad_out[v].depth, grad_out[v].alpha};
-  RET_IF(ensure(ctx, ctx->images2, sizeof(ViewImages) * nv));
-  RET_IF(ensure(ctx, ctx->g2, sizeof(float) * G2_N * (size_t)std::max<int64_t>(total, 1)));
-  RET_IF(upload(ctx, ctx->images2.p, ims.data(), sizeof(ViewImages) * nv, st));
-  if (total == 0) return GSR_OK;
+int launch_bwd(gsr_ctx* ctx, Buffers& B, const RenderPlan& P, const float* params, float* grad_params,
+               hipStream_t st) {
+  if (P.total == 0) return GSR_OK;
   {
     StageTimer tm(ctx, GSR_STAGE_ZERO, st);
-    launch_fill_f32(as<float>(ctx->g2), 0.0f, total * G2_N, st);
+    launch_fill_f32(as<float>(B.g2), 0.0f, P.total * G2_N, st);
   }
   CHECK_LAUNCH(ctx);
   BlendArgs ba{};
-  ba.views = as<ViewDesc>(ctx->views);
-  ba.images = as<ViewImages>(ctx->images2);
-  ba.num_views = nv;
-  ba.num_tiles = (int32_t)ctx->fw_tiles;
-  ba.ranges = as<uint2>(ctx->ranges);
-  ba.inst_vals = ctx->inst_vals;
-  ba.splats = as<Splat>(ctx->splats);
-  ba.tfinal = as<float>(ctx->tfinal);
-  ba.last = as<uint32_t>(ctx->last);
-  ba.g2 = as<float>(ctx->g2);
+  ba.views = as<ViewDesc>(B.views);
+  ba.images = as<ViewImages>(B.images2);
+  ba.num_views = P.nv;
+  ba.num_tiles = (int32_t)P.ntiles;
+  ba.ranges = as<uint2>(B.ranges);
+  ba.inst_vals = P.inst_vals;
+  ba.splats = as<Splat>(B.splats);
+  ba.tfinal = as<float>(B.tfinal);
+  ba.last = as<uint32_t>(B.last);
+  ba.g2 = as<float>(B.g2);
   for (int k = 0; k < 3; ++k) ba.bg[k] = ctx->bg[k];
   {
     StageTimer tm(ctx, GSR_STAGE_BLEND_BWD, st);
@@ -392,11 +171,78 @@ int backward_impl(gsr_ctx* ctx, const gsr_gaussians* g, int32_t nv, const gsr_ca
   CHECK_LAUNCH(ctx);
   {
     StageTimer tm(ctx, GSR_STAGE_PROJECT_BWD, st);
-    launch_project_backward(g->params, N, g->stride, g->sh_degree, nv, as<ViewDesc>(ctx->views), ctx->znear,
-                            as<float>(ctx->g2), grad_params, st);
+    launch_project_backward(params, P.num, P.stride, P.deg, P.nv, as<ViewDesc>(B.views), ctx->znear,
+                            as<float>(B.g2), grad_params, st);
   }
   CHECK_LAUNCH(ctx);
   return GSR_OK;
+}
+
+void free_buffers(Buffers& B) {
+  DevBuf* bufs[] = {&B.views, &B.images, &B.images2, &B.splats, &B.rect, &B.ntiles, &B.zkey, &B.svals,
+                    &B.zkey_alt, &B.svals_alt, &B.offsets, &B.ikeys, &B.ivals, &B.ikeys_alt, &B.ivals_alt,
+                    &B.hist, &B.partials, &B.ranges, &B.tfinal, &B.last, &B.g2, &B.total};
+  for (DevBuf* b : bufs) {
+    if (b->p) (void)hipFree(b->p);
+    b->p = nullptr;
+    b->cap = 0;
+  }
+}
+
+}  // namespace gsr
+
+namespace {
+
+// Eager forward: the instance count is read back (one stream synchronisation)
+// and the instance buffers are sized to it exactly.
+int render_impl(gsr_ctx* ctx, const gsr_gaussians* g, int32_t nv, const gsr_camera* cams, const gsr_image* out,
+                hipStream_t st) {
+  ctx->have_forward = false;
+  ctx->q_bufs = nullptr;
+  ctx->q_plan = nullptr;
+  RenderPlan& P = ctx->fw;
+  RET_IF(plan_render(ctx, g, nv, cams, &P));
+  if (!out) return GSR_ERR_INVALID;
+  for (int v = 0; v < nv; ++v)
+    if (!out[v].rgb || !out[v].depth || !out[v].alpha) return GSR_ERR_INVALID;
+  ctx->last_stream = st;
+  Buffers& B = ctx->eager;
+  P.capacity = 0;
+  RET_IF(size_render(ctx, B, P, out, st));
+  launch_fill_u32(as<uint32_t>(B.total), 0u, 4, st);
+  RET_IF(launch_front(ctx, B, P, g->params, st));
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->host_total, B.total.p, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  HIP_TRY(ctx, hipStreamSynchronize(st));
+  if (ctx->host_total[1] != 0) return GSR_ERR_DEVICE;
+  P.capacity = (int64_t)ctx->host_total[0];
+  RET_IF(size_instances(ctx, B, P));
+  RET_IF(launch_back(ctx, B, P, st));
+
+  ctx->have_forward = true;
+  ctx->fw_params = g->params;
+  ctx->fw_cams.assign(cams, cams + nv);
+  ctx->q_bufs = &B;
+  ctx->q_plan = &P;
+  ctx->q_params = g->params;
+  return GSR_OK;
+}
+
+int backward_impl(gsr_ctx* ctx, const gsr_gaussians* g, int32_t nv, const gsr_camera* cams,
+                  const gsr_image* grad_out, float* grad_params, hipStream_t st) {
+  RET_IF(check_gaussians(g));
+  RET_IF(check_cams(cams, nv));
+  if (!grad_out || (g->num > 0 && !grad_params)) return GSR_ERR_INVALID;
+  const RenderPlan& P = ctx->fw;
+  if (!ctx->have_forward || ctx->fw_params != g->params || P.num != g->num || P.stride != g->stride ||
+      P.deg != g->sh_degree || (int)ctx->fw_cams.size() != nv ||
+      std::memcmp(ctx->fw_cams.data(), cams, sizeof(gsr_camera) * nv) != 0)
+    return GSR_ERR_STATE;
+  ctx->last_stream = st;
+  Buffers& B = ctx->eager;
+  std::vector<ViewImages> ims(nv);
+  for (int v = 0; v < nv; ++v) ims[v] = ViewImages{grad_out[v].rgb, grad_out[v].depth, grad_out[v].alpha};
+  RET_IF(upload(ctx, B.images2.p, ims.data(), sizeof(ViewImages) * nv, st));
+  return launch_bwd(ctx, B, P, g->params, grad_params, st);
 }
 
 }  // namespace
@@ -446,11 +292,9 @@ int gsr_create(gsr_ctx** out, const gsr_options* opt) {
 void gsr_destroy(gsr_ctx* ctx) {
   if (!ctx) return;
   (void)hipDeviceSynchronize();
-  DevBuf* bufs[] = {&ctx->views, &ctx->images, &ctx->images2, &ctx->images3, &ctx->splats, &ctx->rect,
-                    &ctx->ntiles, &ctx->zkey, &ctx->svals, &ctx->zkey_alt, &ctx->svals_alt, &ctx->offsets,
-                    &ctx->ikeys, &ctx->ivals, &ctx->ikeys_alt, &ctx->ivals_alt, &ctx->hist, &ctx->partials,
-                    &ctx->ranges, &ctx->tfinal, &ctx->last, &ctx->g2, &ctx->lr, &ctx->total, &ctx->splat_out,
-                    &ctx->counts};
+  destroy_graph(ctx);
+  free_buffers(ctx->eager);
+  DevBuf* bufs[] = {&ctx->images3, &ctx->lr, &ctx->splat_out, &ctx->counts};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   for (int k = 0; k < kSlots; ++k) {
@@ -550,7 +394,8 @@ int gsr_adam_step(gsr_ctx* ctx, float* params, const float* grads, float* m, flo
   const float bc2 = (float)(1.0 - std::pow((double)beta2, (double)step));
   {
     StageTimer tm(ctx, GSR_STAGE_ADAM, st);
-    launch_adam(params, grads, m, v, num, stride, num_planes, as<float>(ctx->lr), beta1, beta2, eps, bc1, bc2, st);
+    launch_adam(params, grads, m, v, num, stride, num_planes, as<float>(ctx->lr), beta1, beta2, eps, bc1, bc2, nullptr,
+                nullptr, st);
   }
   CHECK_LAUNCH(ctx);
   return GSR_OK;
@@ -559,44 +404,48 @@ int gsr_adam_step(gsr_ctx* ctx, float* params, const float* grads, float* m, flo
 int gsr_query_status(gsr_ctx* ctx, int64_t* num_instances, int64_t* num_visible, int64_t* num_tiles) {
   if (!ctx) return GSR_ERR_INVALID;
   HIP_TRY(ctx, hipStreamSynchronize(ctx->last_stream));
-  if (ctx->total.p) {
-    uint32_t flag = 0;
-    HIP_TRY(ctx, hipMemcpy(&flag, as<uint32_t>(ctx->total) + 1, sizeof(uint32_t), hipMemcpyDeviceToHost));
-    if (flag) return GSR_ERR_DEVICE;
+  int64_t I = 0;
+  if (ctx->q_bufs) {
+    uint32_t t[3] = {0, 0, 0};
+    HIP_TRY(ctx, hipMemcpy(t, ctx->q_bufs->total.p, sizeof(t), hipMemcpyDeviceToHost));
+    if (t[1]) return GSR_ERR_DEVICE;
+    I = std::min<int64_t>((int64_t)t[0], ctx->q_plan->capacity);
   }
-  if (num_instances) *num_instances = ctx->have_forward ? ctx->fw_instances : 0;
+  if (num_instances) *num_instances = I;
   if (num_visible) *num_visible = -1;
-  if (num_tiles) *num_tiles = ctx->have_forward ? ctx->fw_tiles : 0;
+  if (num_tiles) *num_tiles = ctx->q_plan ? ctx->q_plan->ntiles : 0;
   return GSR_OK;
 }
 
 int gsr_copy_instances(gsr_ctx* ctx, uint32_t* tile, uint32_t* gid, int64_t capacity, int64_t* count) {
   if (!ctx || !count || capacity < 0) return GSR_ERR_INVALID;
-  if (!ctx->have_forward) return GSR_ERR_STATE;
-  HIP_TRY(ctx, hipStreamSynchronize(ctx->last_stream));
-  const int64_t I = ctx->fw_instances;
+  if (!ctx->q_bufs) return GSR_ERR_STATE;
+  int64_t I = 0;
+  RET_IF(gsr_query_status(ctx, &I, nullptr, nullptr));
   *count = I;
   const int64_t m = std::min(capacity, I);
   if (m == 0) return GSR_OK;
   if (!tile || !gid) return GSR_ERR_INVALID;
-  HIP_TRY(ctx, hipMemcpy(tile, ctx->inst_keys, sizeof(uint32_t) * m, hipMemcpyDeviceToHost));
-  HIP_TRY(ctx, hipMemcpy(gid, ctx->inst_vals, sizeof(uint32_t) * m, hipMemcpyDeviceToHost));
-  const uint32_t N = (uint32_t)ctx->fw_num;
+  HIP_TRY(ctx, hipMemcpy(tile, ctx->q_plan->inst_keys, sizeof(uint32_t) * m, hipMemcpyDeviceToHost));
+  HIP_TRY(ctx, hipMemcpy(gid, ctx->q_plan->inst_vals, sizeof(uint32_t) * m, hipMemcpyDeviceToHost));
+  const uint32_t N = (uint32_t)ctx->q_plan->num;
   for (int64_t k = 0; k < m; ++k) gid[k] = gid[k] % N;
   return GSR_OK;
 }
 
 int gsr_copy_splats(gsr_ctx* ctx, int32_t view, float* out, int64_t num) {
   if (!ctx || !out) return GSR_ERR_INVALID;
-  if (!ctx->have_forward) return GSR_ERR_STATE;
-  if (view < 0 || view >= (int)ctx->fw_cams.size() || num != ctx->fw_num) return GSR_ERR_INVALID;
+  if (!ctx->q_bufs) return GSR_ERR_STATE;
+  const RenderPlan& P = *ctx->q_plan;
+  Buffers& B = *ctx->q_bufs;
+  if (view < 0 || view >= P.nv || num != P.num) return GSR_ERR_INVALID;
   HIP_TRY(ctx, hipStreamSynchronize(ctx->last_stream));
   if (num == 0) return GSR_OK;
   hipStream_t st = ctx->last_stream;
   RET_IF(ensure(ctx, ctx->splat_out, sizeof(float) * 16 * (size_t)num));
   const int64_t off = (int64_t)view * num;
-  launch_export_splats(ctx->fw_params, num, ctx->fw_stride, as<ViewDesc>(ctx->views) + view, ctx->znear,
-                       as<Splat>(ctx->splats) + off, as<int4>(ctx->rect) + off, as<float>(ctx->splat_out), st);
+  launch_export_splats(ctx->q_params, num, P.stride, as<ViewDesc>(B.views) + view, ctx->znear,
+                       as<Splat>(B.splats) + off, as<int4>(B.rect) + off, as<float>(ctx->splat_out), st);
   CHECK_LAUNCH(ctx);
   HIP_TRY(ctx, hipStreamSynchronize(st));
   HIP_TRY(ctx, hipMemcpy(out, ctx->splat_out.p, sizeof(float) * 16 * (size_t)num, hipMemcpyDeviceToHost));
@@ -605,13 +454,15 @@ int gsr_copy_splats(gsr_ctx* ctx, int32_t view, float* out, int64_t num) {
 
 int gsr_count_work(gsr_ctx* ctx, int64_t* pairs, int64_t* visible, int32_t num_views) {
   if (!ctx || !pairs) return GSR_ERR_INVALID;
-  if (!ctx->have_forward) return GSR_ERR_STATE;
-  if (visible && num_views != (int32_t)ctx->fw_cams.size()) return GSR_ERR_INVALID;
+  if (!ctx->q_bufs) return GSR_ERR_STATE;
+  const RenderPlan& P = *ctx->q_plan;
+  Buffers& B = *ctx->q_bufs;
+  if (visible && num_views != P.nv) return GSR_ERR_INVALID;
   hipStream_t st = ctx->last_stream;
-  const int nv = (int)ctx->fw_cams.size();
+  const int nv = P.nv;
   RET_IF(ensure(ctx, ctx->counts, sizeof(unsigned long long) * (size_t)(1 + nv)));
   unsigned long long* c = as<unsigned long long>(ctx->counts);
-  launch_count_work(as<uint32_t>(ctx->last), ctx->fw_pixels, as<uint32_t>(ctx->ntiles), ctx->fw_num, nv, c, st);
+  launch_count_work(as<uint32_t>(B.last), P.npix, as<uint32_t>(B.ntiles), P.num, nv, c, st);
   CHECK_LAUNCH(ctx);
   std::vector<unsigned long long> h(1 + nv);
   HIP_TRY(ctx, hipStreamSynchronize(st));

@@ -461,7 +461,16 @@ __global__ void __launch_bounds__(256) loss_l1_kernel(const ViewDesc* __restrict
 __global__ void __launch_bounds__(256) adam_kernel(float* __restrict__ p, const float* __restrict__ g,
                                                    float* __restrict__ m, float* __restrict__ v, int64_t num,
                                                    int64_t stride, int planes, const float* __restrict__ lr,
-                                                   float b1, float b2, float eps, float bc1, float bc2) {
+                                                   float b1, float b2, float eps, float bc1, float bc2,
+                                                   const uint32_t* __restrict__ step_dev,
+                                                   const uint32_t* __restrict__ skip) {
+  if (skip && (skip[0] | skip[1])) return;
+  if (step_dev) {
+    // in double, as the host does: 1 - b^step cancels badly in float
+    const int step = *step_dev + 1;
+    bc1 = (float)(1.0 - pow((double)b1, (double)step));
+    bc2 = (float)(1.0 - pow((double)b2, (double)step));
+  }
   const int64_t total = num * planes;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
     const int plane = (int)(e / num);
@@ -514,10 +523,12 @@ void launch_loss_l1(const ViewDesc* views, const ViewImages* rendered, const Vie
 }
 
 void launch_adam(float* p, const float* g, float* m, float* v, int64_t num, int64_t stride, int planes,
-                 const float* lr_dev, float b1, float b2, float eps, float bc1, float bc2, hipStream_t st) {
+                 const float* lr_dev, float b1, float b2, float eps, float bc1, float bc2, const uint32_t* step_dev,
+                 const uint32_t* skip, hipStream_t st) {
   const int64_t total = num * planes;
   if (total == 0) return;
-  adam_kernel<<<grid_cap(total, 256), 256, 0, st>>>(p, g, m, v, num, stride, planes, lr_dev, b1, b2, eps, bc1, bc2);
+  adam_kernel<<<grid_cap(total, 256), 256, 0, st>>>(p, g, m, v, num, stride, planes, lr_dev, b1, b2, eps, bc1, bc2,
+                                                    step_dev, skip);
 }
 
 }  // namespace gsr

@@ -1,0 +1,301 @@
+// The context behind the C ABI: device scratch, staging, call-order state
+// and per-stage timing, plus the host helpers the entry points share.
+#pragma once
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/gsr.h"
+#include "gsr_internal.h"
+
+struct gsr_ctx;
+
+namespace gsr {
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+};
+
+// Pinned staging slots for host->device uploads of small descriptor arrays;
+// each slot is reused only after the event recorded behind its last copy.
+constexpr int kSlots = 8;
+constexpr size_t kSlotBytes = 64 * 1024;
+
+// Device buffers of one render + backward pipeline. The eager entry points
+// and a captured mapping iteration each own a set, so that growing one never
+// moves memory the other's kernels (or a captured graph) refer to.
+struct Buffers {
+  DevBuf views, images, images2;
+  DevBuf splats, rect, ntiles, zkey, svals, zkey_alt, svals_alt, offsets;
+  DevBuf ikeys, ivals, ikeys_alt, ivals_alt;
+  DevBuf hist, partials, ranges, tfinal, last, g2;
+  DevBuf total;   // [0] instance count, [1] sort wait expired, [2] instance overflow
+};
+
+// Sizes and final buffer roles of one forward render.
+struct RenderPlan {
+  int64_t num = 0, stride = 0;
+  int deg = 0, nv = 0;
+  int64_t total = 0;                   // num * nv projected splats
+  int64_t ntiles = 0, npix = 0;
+  int64_t capacity = 0;                // instance slots (eager: exactly the count)
+  std::vector<ViewDesc> views;
+  uint32_t* sorted_splats = nullptr;   // depth-sorted splat indices
+  uint32_t* inst_keys = nullptr;       // sorted instance list
+  uint32_t* inst_vals = nullptr;
+};
+
+struct GraphState;   // captured mapping iteration
+
+// Receives the stage boundaries of a timed stage while a mapping iteration is
+// being captured: the capture is cut there so that the replay can record
+// ordinary events between the pieces.
+struct CaptureHook {
+  virtual void cut(int stage, bool end) = 0;
+  virtual ~CaptureHook() = default;
+};
+
+// Brackets one stage's launches with events when profiling is on.
+struct StageTimer {
+  gsr_ctx* ctx;
+  int stage;
+  hipStream_t st;
+  hipEvent_t a = nullptr, b = nullptr;
+  bool cut = false;
+  StageTimer(gsr_ctx* c, int s, hipStream_t stream);
+  ~StageTimer();
+};
+
+}  // namespace gsr
+
+struct gsr_ctx {
+  using DevBuf = gsr::DevBuf;
+  using ViewDesc = gsr::ViewDesc;
+  int tile_w = 16, tile_h = 16;
+  int ppt = 1;                          // pixels per thread in the blend kernels
+  float bg[3] = {0.f, 0.f, 0.f};
+  float znear = 0.2f;
+  int hip_err = 0;
+  hipStream_t last_stream = nullptr;
+
+  gsr::Buffers eager;                   // buffers of gsr_render / gsr_render_backward
+  DevBuf images3, lr, splat_out;
+  uint32_t* host_total = nullptr;
+  void* slots[gsr::kSlots] = {};
+  hipEvent_t slot_ev[gsr::kSlots] = {};
+  bool slot_used[gsr::kSlots] = {};
+  int next_slot = 0;
+
+  // state of the last eager render, checked by the backward
+  bool have_forward = false;
+  const float* fw_params = nullptr;
+  std::vector<gsr_camera> fw_cams;
+  gsr::RenderPlan fw;
+
+  // what the status and copy queries report on: the last eager render or
+  // the last mapping iteration
+  gsr::Buffers* q_bufs = nullptr;
+  const gsr::RenderPlan* q_plan = nullptr;
+  const float* q_params = nullptr;
+
+  // per-stage timing
+  uint32_t profile_mask = 0;          // bit k: time stage k
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending[GSR_NUM_STAGES];
+  DevBuf counts;
+
+  // captured mapping iteration
+  gsr::GraphState* graph = nullptr;
+  gsr::CaptureHook* capture = nullptr;   // set while capturing
+};
+
+namespace gsr {
+
+// A timing event from the context's pool (created when the pool is empty).
+inline hipEvent_t take_event(gsr_ctx* ctx) {
+  if (!ctx->ev_pool.empty()) {
+    hipEvent_t e = ctx->ev_pool.back();
+    ctx->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+inline StageTimer::StageTimer(gsr_ctx* c, int s, hipStream_t stream) : ctx(c), stage(s), st(stream) {
+  if (!((ctx->profile_mask >> s) & 1u)) return;
+  if (ctx->capture) {
+    ctx->capture->cut(s, false);
+    cut = true;
+    return;
+  }
+  a = take_event(ctx);
+  b = take_event(ctx);
+  if (a && b) (void)hipEventRecord(a, st);
+}
+
+inline StageTimer::~StageTimer() {
+  if (cut) {
+    ctx->capture->cut(stage, true);
+    return;
+  }
+  if (!a || !b) return;
+  (void)hipEventRecord(b, st);
+  ctx->ev_pending[stage].emplace_back(a, b);
+}
+
+}  // namespace gsr
+
+namespace gsr {
+
+#define HIP_TRY(ctx, expr)                      \
+  do {                                          \
+    hipError_t e_ = (expr);                     \
+    if (e_ != hipSuccess) {                     \
+      (ctx)->hip_err = (int)e_;                 \
+      return GSR_ERR_HIP;                       \
+    }                                           \
+  } while (0)
+
+#define CHECK_LAUNCH(ctx) HIP_TRY(ctx, hipGetLastError())
+
+inline int ensure(gsr_ctx* ctx, DevBuf& b, size_t bytes) {
+  if (bytes <= b.cap) return GSR_OK;
+  size_t want = std::max<size_t>(bytes + bytes / 4, 256);
+  if (b.p) {
+    HIP_TRY(ctx, hipDeviceSynchronize());
+    HIP_TRY(ctx, hipFree(b.p));
+    b.p = nullptr;
+    b.cap = 0;
+  }
+  hipError_t e = hipMalloc(&b.p, want);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    b.p = nullptr;
+    e = hipMalloc(&b.p, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      b.p = nullptr;
+      return GSR_ERR_OOM;
+    }
+    want = bytes;
+  }
+  b.cap = want;
+  return GSR_OK;
+}
+
+template <class T>
+inline T* as(DevBuf& b) {
+  return static_cast<T*>(b.p);
+}
+
+inline int upload(gsr_ctx* ctx, void* dev, const void* host, size_t bytes, hipStream_t st) {
+  if (bytes == 0) return GSR_OK;
+  if (bytes > kSlotBytes) {
+    HIP_TRY(ctx, hipMemcpyAsync(dev, host, bytes, hipMemcpyHostToDevice, st));
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    return GSR_OK;
+  }
+  const int k = ctx->next_slot;
+  ctx->next_slot = (k + 1) % kSlots;
+  if (ctx->slot_used[k]) HIP_TRY(ctx, hipEventSynchronize(ctx->slot_ev[k]));
+  std::memcpy(ctx->slots[k], host, bytes);
+  HIP_TRY(ctx, hipMemcpyAsync(dev, ctx->slots[k], bytes, hipMemcpyHostToDevice, st));
+  HIP_TRY(ctx, hipEventRecord(ctx->slot_ev[k], st));
+  ctx->slot_used[k] = true;
+  return GSR_OK;
+}
+
+#define RET_IF(expr)            \
+  do {                          \
+    int r_ = (expr);            \
+    if (r_ != GSR_OK) return r_; \
+  } while (0)
+
+inline int check_gaussians(const gsr_gaussians* g) {
+  if (!g) return GSR_ERR_INVALID;
+  if (g->num < 0 || g->num > (int64_t(1) << 27)) return GSR_ERR_INVALID;
+  if (g->stride < g->num) return GSR_ERR_INVALID;
+  if (g->sh_degree < 0 || g->sh_degree > 3) return GSR_ERR_INVALID;
+  if (g->num > 0 && !g->params) return GSR_ERR_INVALID;
+  return GSR_OK;
+}
+
+inline int num_planes(int deg) { return 11 + 3 * (deg + 1) * (deg + 1); }
+
+inline int check_cams(const gsr_camera* cams, int32_t num_views) {
+  if (num_views < 1 || num_views > 256 || !cams) return GSR_ERR_INVALID;
+  for (int v = 0; v < num_views; ++v) {
+    const gsr_camera& c = cams[v];
+    if (c.width < 1 || c.height < 1 || c.width > 16384 || c.height > 16384) return GSR_ERR_INVALID;
+    if (!(c.fx > 0.f) || !(c.fy > 0.f) || !std::isfinite(c.cx) || !std::isfinite(c.cy)) return GSR_ERR_INVALID;
+    for (int k = 0; k < 9; ++k) if (!std::isfinite(c.R[k])) return GSR_ERR_INVALID;
+    for (int k = 0; k < 3; ++k) if (!std::isfinite(c.t[k])) return GSR_ERR_INVALID;
+  }
+  return GSR_OK;
+}
+
+// Per-view descriptors; returns total tiles and pixels.
+inline std::vector<ViewDesc> make_views(const gsr_ctx* ctx, const gsr_camera* cams, int nv, int64_t* tiles,
+                                 int64_t* pixels) {
+  std::vector<ViewDesc> out(nv);
+  int64_t toff = 0, poff = 0;
+  for (int v = 0; v < nv; ++v) {
+    const gsr_camera& c = cams[v];
+    ViewDesc& d = out[v];
+    std::memcpy(d.R, c.R, sizeof(d.R));
+    std::memcpy(d.t, c.t, sizeof(d.t));
+    d.fx = c.fx; d.fy = c.fy; d.cx = c.cx; d.cy = c.cy;
+    for (int j = 0; j < 3; ++j) {
+      double s = 0.0;
+      for (int i = 0; i < 3; ++i) s -= (double)c.R[i * 3 + j] * (double)c.t[i];
+      d.campos[j] = (float)s;
+    }
+    d.width = c.width; d.height = c.height;
+    d.tiles_x = (c.width + ctx->tile_w - 1) / ctx->tile_w;
+    d.tiles_y = (c.height + ctx->tile_h - 1) / ctx->tile_h;
+    d.tile_offset = (int32_t)toff;
+    d.pix_offset = (int32_t)poff;
+    toff += (int64_t)d.tiles_x * d.tiles_y;
+    poff += (int64_t)c.width * c.height;
+  }
+  *tiles = toff;
+  *pixels = poff;
+  return out;
+}
+
+inline int bits_for(int64_t max_key) {
+  int b = 0;
+  while (b < 32 && (int64_t(1) << b) <= max_key) ++b;
+  return b;
+}
+
+// Render pipeline shared by the eager entry points and the captured mapping
+// iteration (api.hip).
+//   plan_render: checks arguments, fills the plan's sizes and view descriptors.
+//   size_render: grows B for the plan (instance slots: plan.capacity) and
+//                uploads the view descriptors and output image pointers.
+//   launch_front: projection, depth sort, instance offsets; B.total[0] = count.
+//   launch_back:  instance emission (at most plan.capacity), tile sort, tile
+//                 ranges, compositing. Counts are read on the device.
+//   launch_bwd:   blend backward and projection backward into grad_params,
+//                 image gradients from the descriptors in B.images2.
+// The launch_* functions make no allocation, copy or synchronisation, so a
+// stream capture can record them.
+int plan_render(gsr_ctx* ctx, const gsr_gaussians* g, int32_t nv, const gsr_camera* cams, RenderPlan* plan);
+int size_render(gsr_ctx* ctx, Buffers& B, RenderPlan& plan, const gsr_image* out, hipStream_t st);
+int launch_front(gsr_ctx* ctx, Buffers& B, RenderPlan& plan, const float* params, hipStream_t st);
+int launch_back(gsr_ctx* ctx, Buffers& B, RenderPlan& plan, hipStream_t st);
+int launch_bwd(gsr_ctx* ctx, Buffers& B, const RenderPlan& plan, const float* params, float* grad_params,
+               hipStream_t st);
+int size_instances(gsr_ctx* ctx, Buffers& B, const RenderPlan& plan);
+void free_buffers(Buffers& B);
+// Frees the captured mapping iteration and its buffers (iteration.hip).
+void destroy_graph(gsr_ctx* ctx);
+
+}  // namespace gsr

@@ -69,13 +69,16 @@ int64_t scan_partial_elems(int64_t n);
 // Exclusive scan out[r] = sum_{j<r} in[idx[r]] (idx may be null); total -> *total_dev.
 void scan_gather_exclusive(const uint32_t* in, const uint32_t* idx, uint32_t* out, int64_t n,
                            uint32_t* total_dev, uint32_t* partials, hipStream_t st);
-// Instance emission in depth order; writes beyond `capacity` are dropped.
+// Instance emission in depth order; writes beyond `capacity` are dropped and
+// set *overflow when the total exceeds it.
 void launch_emit(const uint32_t* sorted_s, const uint32_t* offsets, const uint32_t* total_dev, const int4* rect,
                  int64_t count, int64_t n, const ViewDesc* views, int tile_w, int tile_h, uint32_t* keys,
-                 uint32_t* vals, int64_t capacity, hipStream_t st);
-// ranges[t] = (start, end) of global tile t in the sorted key array.
-void launch_tile_ranges(const uint32_t* keys, int64_t count, uint2* ranges, int64_t num_tiles,
+                 uint32_t* vals, int64_t capacity, uint32_t* overflow, hipStream_t st);
+// ranges[t] = (start, end) of global tile t in the sorted key array of
+// min(*n_dev, count) instances (count if n_dev is null).
+void launch_tile_ranges(const uint32_t* keys, const uint32_t* n_dev, int64_t count, uint2* ranges, int64_t num_tiles,
                         hipStream_t st);
+
 void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
 // out[0] = sum of last[0..npix); out[1+v] = number of nonzero ntiles in view v's segment of n.
 void launch_count_work(const uint32_t* last, int64_t npix, const uint32_t* ntiles, int64_t n, int num_views,
@@ -103,8 +106,11 @@ void launch_blend_backward(const BlendArgs& a, int tile_w, int tile_h, int ppt, 
 void launch_loss_l1(const ViewDesc* views, const ViewImages* rendered, const ViewImages* target,
                     const ViewImages* grad, int num_views, int max_pixels, float depth_weight,
                     float* loss, hipStream_t st);
+// Adam; with step_dev the bias corrections are those of step *step_dev + 1
+// (bc1, bc2 ignored); skip[0] or skip[1] nonzero (if skip is not null) leaves
+// everything unchanged.
 void launch_adam(float* p, const float* g, float* m, float* v, int64_t num, int64_t stride,
                  int planes, const float* lr_dev, float b1, float b2, float eps, float bc1,
-                 float bc2, hipStream_t st);
+                 float bc2, const uint32_t* step_dev, const uint32_t* skip, hipStream_t st);
 
 }  // namespace gsr

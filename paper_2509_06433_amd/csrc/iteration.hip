@@ -1,0 +1,480 @@
+// The mapping iteration as one HIP graph: render, loss, backward and Adam of
+// the continuous map optimisation (paper Sec. II-B, mapping thread), replayed
+// per call without host synchronisation.
+//
+// A graph fixes every launch's grid, so the instance storage has a fixed
+// capacity and every kernel after the instance-offset scan reads the count
+// from device memory, clamped to the capacity. An iteration whose count
+// exceeds the capacity (or whose sort look-back wait expired) still runs
+// with bounded, in-range work; its Adam node sees the flag and leaves the
+// parameters alone, and the closing node counts it as skipped. The host sees
+// the counters through a copy into pinned memory at the end of each replay,
+// without waiting for it, and captures a larger graph on the next call.
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "context.h"
+
+namespace gsr {
+
+namespace {
+
+// stats words (device, copied to host at the end of each replay)
+enum : int {
+  kStatAdamSteps = 0,
+  kStatIterations = 1,
+  kStatSkipped = 2,
+  kStatMaxInstances = 3,
+  kStatLastInstances = 4,
+  kStatErrors = 5,
+  kStatWords = 8
+};
+
+__global__ void iteration_begin_kernel(uint32_t* __restrict__ totals) {
+  if (threadIdx.x < 4) totals[threadIdx.x] = 0u;
+}
+
+__global__ void iteration_end_kernel(const uint32_t* __restrict__ totals, uint32_t* __restrict__ stats, int adam) {
+  if (threadIdx.x != 0) return;
+  const uint32_t count = totals[0];
+  const bool err = totals[1] != 0u, over = totals[2] != 0u;
+  if (err || over) {
+    stats[kStatSkipped] += 1u;
+    if (err) stats[kStatErrors] += 1u;
+  } else {
+    stats[kStatIterations] += 1u;
+    if (adam) stats[kStatAdamSteps] += 1u;
+  }
+  stats[kStatMaxInstances] = max(stats[kStatMaxInstances], count);
+  stats[kStatLastInstances] = count;
+}
+
+}  // namespace
+
+struct GraphState {
+  Buffers B;
+  RenderPlan P;
+  // what the capture depends on
+  float* params = nullptr;
+  float* grad = nullptr;
+  float* loss = nullptr;
+  float* m = nullptr;
+  float* v = nullptr;
+  int64_t num = -1, stride = -1;
+  int deg = -1;
+  std::vector<int32_t> sizes;          // width, height per view
+  float depth_weight = 0.f, beta1 = 0.f, beta2 = 0.f, eps = 0.f;
+  bool adam = false;
+  uint32_t profile_mask = 0;
+  int64_t capacity = 0;
+  bool captured = false;
+  // host copies of the descriptors last uploaded
+  std::vector<ViewDesc> views;
+  std::vector<ViewImages> outs, targets;
+  std::vector<float> lr;
+  DevBuf tdesc, gimg, lrbuf, stats;
+  uint32_t* host_stats = nullptr;      // pinned, written by the last node of each replay
+  // The iteration is one graph, or, with timed stages, a chain of graphs with
+  // an event recorded between consecutive pieces: mark k is recorded after
+  // the first marks[k].after pieces.
+  struct Mark {
+    size_t after;
+    int stage;
+    bool end;
+  };
+  std::vector<hipGraph_t> graphs;
+  std::vector<hipGraphExec_t> execs;
+  std::vector<Mark> marks;
+  hipStream_t cap = nullptr;
+  hipEvent_t done = nullptr;
+  int64_t captures = 0;
+  uint32_t seen_skipped = 0;
+  bool grow = false;
+};
+
+namespace {
+
+void drop_graph(GraphState* G) {
+  for (hipGraphExec_t e : G->execs) (void)hipGraphExecDestroy(e);
+  for (hipGraph_t g : G->graphs) (void)hipGraphDestroy(g);
+  G->execs.clear();
+  G->graphs.clear();
+  G->marks.clear();
+  G->captured = false;
+}
+
+int init_state(gsr_ctx* ctx, GraphState* G) {
+  HIP_TRY(ctx, hipStreamCreateWithFlags(&G->cap, hipStreamNonBlocking));
+  HIP_TRY(ctx, hipEventCreateWithFlags(&G->done, hipEventDisableTiming));
+  HIP_TRY(ctx, hipHostMalloc((void**)&G->host_stats, sizeof(uint32_t) * kStatWords, hipHostMallocDefault));
+  std::memset(G->host_stats, 0, sizeof(uint32_t) * kStatWords);
+  RET_IF(ensure(ctx, G->stats, sizeof(uint32_t) * kStatWords));
+  HIP_TRY(ctx, hipMemset(G->stats.p, 0, sizeof(uint32_t) * kStatWords));
+  HIP_TRY(ctx, hipDeviceSynchronize());
+  return GSR_OK;
+}
+
+// Instance count of the current parameters, from the front half of a render
+// into the graph's own buffers.
+int measure_instances(gsr_ctx* ctx, GraphState* G, const float* params, const gsr_image* out, int64_t* count,
+                      hipStream_t st) {
+  RenderPlan& P = G->P;
+  P.capacity = std::max<int64_t>(P.capacity, 0);
+  RET_IF(size_render(ctx, G->B, P, out, st));
+  launch_fill_u32(as<uint32_t>(G->B.total), 0u, 4, st);
+  const uint32_t mask = ctx->profile_mask;
+  ctx->profile_mask = 0;
+  const int r = launch_front(ctx, G->B, P, params, st);
+  ctx->profile_mask = mask;
+  RET_IF(r);
+  uint32_t t[2];
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->host_total, G->B.total.p, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  HIP_TRY(ctx, hipStreamSynchronize(st));
+  std::memcpy(t, ctx->host_total, sizeof(t));
+  if (t[1] != 0) return GSR_ERR_DEVICE;
+  *count = (int64_t)t[0];
+  return GSR_OK;
+}
+
+int upload_descriptors(gsr_ctx* ctx, GraphState* G, int nv, const std::vector<ViewImages>& outs,
+                       const std::vector<ViewImages>& targets, const float* lr, int planes, bool adam, bool force,
+                       hipStream_t st) {
+  if (force || std::memcmp(G->views.data(), G->P.views.data(), sizeof(ViewDesc) * nv) != 0) {
+    RET_IF(upload(ctx, G->B.views.p, G->P.views.data(), sizeof(ViewDesc) * nv, st));
+    G->views = G->P.views;
+  }
+  if (force || std::memcmp(G->outs.data(), outs.data(), sizeof(ViewImages) * nv) != 0) {
+    RET_IF(upload(ctx, G->B.images.p, outs.data(), sizeof(ViewImages) * nv, st));
+    G->outs = outs;
+  }
+  if (force || std::memcmp(G->targets.data(), targets.data(), sizeof(ViewImages) * nv) != 0) {
+    RET_IF(upload(ctx, G->tdesc.p, targets.data(), sizeof(ViewImages) * nv, st));
+    G->targets = targets;
+  }
+  if (adam && (force || std::memcmp(G->lr.data(), lr, sizeof(float) * planes) != 0)) {
+    RET_IF(upload(ctx, G->lrbuf.p, lr, sizeof(float) * planes, st));
+    G->lr.assign(lr, lr + planes);
+  }
+  return GSR_OK;
+}
+
+// Records the whole iteration on the capture stream.
+int record_iteration(gsr_ctx* ctx, GraphState* G, float* params, float* grad, float* loss, const gsr_adam* adam,
+                     float depth_weight, int planes, hipStream_t st) {
+  Buffers& B = G->B;
+  RenderPlan& P = G->P;
+  uint32_t* totals = as<uint32_t>(B.total);
+  iteration_begin_kernel<<<1, 64, 0, st>>>(totals);
+  CHECK_LAUNCH(ctx);
+  RET_IF(launch_front(ctx, B, P, params, st));
+  RET_IF(launch_back(ctx, B, P, st));
+  int maxpix = 0;
+  for (int v = 0; v < P.nv; ++v) maxpix = std::max(maxpix, P.views[v].width * P.views[v].height);
+  {
+    StageTimer tm(ctx, GSR_STAGE_LOSS, st);
+    launch_loss_l1(as<ViewDesc>(B.views), as<ViewImages>(B.images), as<ViewImages>(G->tdesc),
+                   as<ViewImages>(B.images2), P.nv, maxpix, depth_weight, loss, st);
+  }
+  CHECK_LAUNCH(ctx);
+  {
+    StageTimer tm(ctx, GSR_STAGE_ZERO, st);
+    launch_fill_f32(grad, 0.0f, (int64_t)planes * P.stride, st);
+  }
+  CHECK_LAUNCH(ctx);
+  RET_IF(launch_bwd(ctx, B, P, params, grad, st));
+  if (adam) {
+    StageTimer tm(ctx, GSR_STAGE_ADAM, st);
+    launch_adam(params, grad, adam->m, adam->v, P.num, P.stride, planes, as<float>(G->lrbuf), adam->beta1,
+                adam->beta2, adam->eps, 1.0f, 1.0f, as<uint32_t>(G->stats) + kStatAdamSteps, totals + 1, st);
+  }
+  CHECK_LAUNCH(ctx);
+  iteration_end_kernel<<<1, 64, 0, st>>>(totals, as<uint32_t>(G->stats), adam ? 1 : 0);
+  CHECK_LAUNCH(ctx);
+  HIP_TRY(ctx, hipMemcpyAsync(G->host_stats, G->stats.p, sizeof(uint32_t) * kStatWords, hipMemcpyDeviceToHost, st));
+  return GSR_OK;
+}
+
+// Ends the current capture piece at each timed-stage boundary and starts
+// the next; empty pieces are dropped.
+struct Cutter : CaptureHook {
+  gsr_ctx* ctx;
+  GraphState* G;
+  hipError_t err = hipSuccess;
+  Cutter(gsr_ctx* c, GraphState* g) : ctx(c), G(g) {}
+  hipError_t close_piece() {
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(G->cap, &g);
+    if (e != hipSuccess) return e;
+    size_t n = 0;
+    e = hipGraphGetNodes(g, nullptr, &n);
+    if (e != hipSuccess || n == 0) {
+      (void)hipGraphDestroy(g);
+      return e;
+    }
+    G->graphs.push_back(g);
+    return hipSuccess;
+  }
+  void cut(int stage, bool end) override {
+    if (err != hipSuccess) return;
+    err = close_piece();
+    if (err != hipSuccess) return;
+    G->marks.push_back(GraphState::Mark{G->graphs.size(), stage, end});
+    err = hipStreamBeginCapture(G->cap, hipStreamCaptureModeThreadLocal);
+  }
+};
+
+int capture(gsr_ctx* ctx, GraphState* G, float* params, float* grad, float* loss, const gsr_adam* adam,
+            float depth_weight, int planes) {
+  drop_graph(G);
+  Cutter cutter(ctx, G);
+  HIP_TRY(ctx, hipStreamBeginCapture(G->cap, hipStreamCaptureModeThreadLocal));
+  ctx->capture = &cutter;
+  const int r = record_iteration(ctx, G, params, grad, loss, adam, depth_weight, planes, G->cap);
+  ctx->capture = nullptr;
+  hipError_t e = cutter.err;
+  if (e == hipSuccess) {
+    e = cutter.close_piece();
+  } else {
+    hipGraph_t g = nullptr;
+    (void)hipStreamEndCapture(G->cap, &g);
+    if (g) (void)hipGraphDestroy(g);
+  }
+  if (r != GSR_OK || e != hipSuccess) {
+    drop_graph(G);
+    (void)hipGetLastError();
+    if (r != GSR_OK) return r;
+    ctx->hip_err = (int)e;
+    return GSR_ERR_HIP;
+  }
+  for (hipGraph_t g : G->graphs) {
+    hipGraphExec_t x = nullptr;
+    HIP_TRY(ctx, hipGraphInstantiate(&x, g, nullptr, nullptr, 0));
+    G->execs.push_back(x);
+  }
+  G->captured = true;
+  G->captures += 1;
+  return GSR_OK;
+}
+
+// Launches the pieces on `st`, recording a fresh pair of events around every
+// timed stage.
+int replay(gsr_ctx* ctx, GraphState* G, hipStream_t st) {
+  hipEvent_t open[GSR_NUM_STAGES] = {};
+  size_t m = 0;
+  for (size_t k = 0; k <= G->execs.size(); ++k) {
+    for (; m < G->marks.size() && G->marks[m].after == k; ++m) {
+      const GraphState::Mark& mk = G->marks[m];
+      hipEvent_t ev = take_event(ctx);
+      if (!ev) return GSR_ERR_HIP;
+      HIP_TRY(ctx, hipEventRecord(ev, st));
+      if (!mk.end) {
+        open[mk.stage] = ev;
+      } else if (open[mk.stage]) {
+        ctx->ev_pending[mk.stage].emplace_back(open[mk.stage], ev);
+        open[mk.stage] = nullptr;
+      } else {
+        ctx->ev_pool.push_back(ev);
+      }
+    }
+    if (k < G->execs.size()) HIP_TRY(ctx, hipGraphLaunch(G->execs[k], st));
+  }
+  return GSR_OK;
+}
+
+int iteration_impl(gsr_ctx* ctx, float* params, int64_t num, int64_t stride, int32_t deg, int32_t nv,
+                   const gsr_camera* cams, const gsr_image* out, const gsr_image* targets, float depth_weight,
+                   float* grad, float* loss, const gsr_adam* adam, hipStream_t st) {
+  gsr_gaussians g{params, num, stride, deg};
+  RET_IF(check_gaussians(&g));
+  RET_IF(check_cams(cams, nv));
+  if (!out || !targets || (num > 0 && !grad)) return GSR_ERR_INVALID;
+  for (int v = 0; v < nv; ++v)
+    if (!out[v].rgb || !out[v].depth || !out[v].alpha || !targets[v].rgb || !targets[v].depth)
+      return GSR_ERR_INVALID;
+  const int planes = num_planes(deg);
+  if (adam) {
+    if (!adam->lr_per_plane || adam->step < 0 || (num > 0 && (!adam->m || !adam->v))) return GSR_ERR_INVALID;
+    if (!(adam->beta1 >= 0.f && adam->beta1 < 1.f && adam->beta2 >= 0.f && adam->beta2 < 1.f))
+      return GSR_ERR_INVALID;
+  }
+  if (!ctx->graph) {
+    ctx->graph = new (std::nothrow) GraphState();
+    if (!ctx->graph) return GSR_ERR_OOM;
+    const int r = init_state(ctx, ctx->graph);
+    if (r != GSR_OK) {
+      destroy_graph(ctx);
+      return r;
+    }
+  }
+  GraphState* G = ctx->graph;
+  ctx->last_stream = st;
+  ctx->q_bufs = nullptr;
+  ctx->q_plan = nullptr;
+
+  // a finished replay that had to skip asks for a larger capacity
+  if (G->captured) {
+    const hipError_t q = hipEventQuery(G->done);
+    if (q == hipSuccess) {
+      if (G->host_stats[kStatSkipped] != G->seen_skipped) {
+        G->seen_skipped = G->host_stats[kStatSkipped];
+        if ((int64_t)G->host_stats[kStatMaxInstances] > G->capacity) G->grow = true;
+      }
+    } else {
+      (void)hipGetLastError();
+    }
+  }
+
+  std::vector<int32_t> sizes(2 * nv);
+  for (int v = 0; v < nv; ++v) {
+    sizes[2 * v] = cams[v].width;
+    sizes[2 * v + 1] = cams[v].height;
+  }
+  const bool same = G->captured && !G->grow && G->params == params && G->grad == grad && G->loss == loss &&
+                    G->num == num && G->stride == stride && G->deg == deg && G->sizes == sizes &&
+                    G->depth_weight == depth_weight && G->adam == (adam != nullptr) &&
+                    G->profile_mask == ctx->profile_mask &&
+                    (!adam || (G->m == adam->m && G->v == adam->v && G->beta1 == adam->beta1 &&
+                               G->beta2 == adam->beta2 && G->eps == adam->eps));
+
+  RenderPlan plan;
+  RET_IF(plan_render(ctx, &g, nv, cams, &plan));
+  std::vector<ViewImages> outs(nv), tgts(nv);
+  for (int v = 0; v < nv; ++v) {
+    outs[v] = ViewImages{out[v].rgb, out[v].depth, out[v].alpha};
+    tgts[v] = ViewImages{targets[v].rgb, targets[v].depth, nullptr};
+  }
+
+  if (!same) {
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    HIP_TRY(ctx, hipDeviceSynchronize());
+    drop_graph(G);
+    const int64_t old_cap = G->capacity;
+    const bool layout_same = G->num == num && G->deg == deg && G->sizes == sizes && G->P.nv == nv;
+    plan.capacity = layout_same ? old_cap : 0;
+    G->P = plan;
+    int64_t count = 0;
+    RET_IF(measure_instances(ctx, G, params, out, &count, st));
+    int64_t need = count;
+    if (layout_same) {
+      need = std::max<int64_t>(count, (int64_t)G->host_stats[kStatMaxInstances]);
+    } else {
+      const uint32_t zero = 0;
+      RET_IF(upload(ctx, as<uint32_t>(G->stats) + kStatMaxInstances, &zero, sizeof(zero), st));
+      G->host_stats[kStatMaxInstances] = 0;
+    }
+    int64_t cap = need + need / 4 + 4096;
+    if (layout_same && !G->grow && old_cap >= need) cap = old_cap;
+    G->P.capacity = cap;
+    G->capacity = cap;
+    G->grow = false;
+    RET_IF(size_render(ctx, G->B, G->P, out, st));
+    RET_IF(ensure(ctx, G->tdesc, sizeof(ViewImages) * nv));
+    int64_t gpix = 0;
+    for (int v = 0; v < nv; ++v) gpix += 4 * (int64_t)cams[v].width * cams[v].height;
+    RET_IF(ensure(ctx, G->gimg, sizeof(float) * (size_t)gpix));
+    std::vector<ViewImages> gims(nv);
+    float* gp = as<float>(G->gimg);
+    for (int v = 0; v < nv; ++v) {
+      const int64_t hw = (int64_t)cams[v].width * cams[v].height;
+      gims[v] = ViewImages{gp, gp + 3 * hw, nullptr};
+      gp += 4 * hw;
+    }
+    RET_IF(upload(ctx, G->B.images2.p, gims.data(), sizeof(ViewImages) * nv, st));
+    RET_IF(ensure(ctx, G->lrbuf, sizeof(float) * planes));
+    RET_IF(upload_descriptors(ctx, G, nv, outs, tgts, adam ? adam->lr_per_plane : nullptr, planes, adam != nullptr,
+                              true, st));
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    G->params = params;
+    G->grad = grad;
+    G->loss = loss;
+    G->num = num;
+    G->stride = stride;
+    G->deg = deg;
+    G->sizes = sizes;
+    G->depth_weight = depth_weight;
+    G->adam = adam != nullptr;
+    G->m = adam ? adam->m : nullptr;
+    G->v = adam ? adam->v : nullptr;
+    G->beta1 = adam ? adam->beta1 : 0.f;
+    G->beta2 = adam ? adam->beta2 : 0.f;
+    G->eps = adam ? adam->eps : 0.f;
+    G->profile_mask = ctx->profile_mask;
+    RET_IF(capture(ctx, G, params, grad, loss, adam, depth_weight, planes));
+  } else {
+    G->P.views = plan.views;
+    RET_IF(upload_descriptors(ctx, G, nv, outs, tgts, adam ? adam->lr_per_plane : nullptr, planes, adam != nullptr,
+                              false, st));
+  }
+  if (adam && adam->step > 0) {
+    const uint32_t s0 = (uint32_t)(adam->step - 1);
+    RET_IF(upload(ctx, as<uint32_t>(G->stats) + kStatAdamSteps, &s0, sizeof(s0), st));
+  }
+  RET_IF(replay(ctx, G, st));
+  HIP_TRY(ctx, hipEventRecord(G->done, st));
+  ctx->q_bufs = &G->B;
+  ctx->q_plan = &G->P;
+  ctx->q_params = params;
+  return GSR_OK;
+}
+
+}  // namespace
+
+void destroy_graph(gsr_ctx* ctx) {
+  GraphState* G = ctx->graph;
+  if (!G) return;
+  if (ctx->q_bufs == &G->B) {
+    ctx->q_bufs = nullptr;
+    ctx->q_plan = nullptr;
+  }
+  drop_graph(G);
+  free_buffers(G->B);
+  DevBuf* bufs[] = {&G->tdesc, &G->gimg, &G->lrbuf, &G->stats};
+  for (DevBuf* b : bufs)
+    if (b->p) (void)hipFree(b->p);
+  if (G->host_stats) (void)hipHostFree(G->host_stats);
+  if (G->done) (void)hipEventDestroy(G->done);
+  if (G->cap) (void)hipStreamDestroy(G->cap);
+  delete G;
+  ctx->graph = nullptr;
+}
+
+}  // namespace gsr
+
+extern "C" {
+
+int gsr_mapping_iteration(gsr_ctx* ctx, float* params, int64_t num, int64_t stride, int32_t sh_degree,
+                          int32_t num_views, const gsr_camera* cams, const gsr_image* out,
+                          const gsr_image* targets, float depth_weight, float* grad_params, float* loss,
+                          const gsr_adam* adam, void* stream) {
+  if (!ctx) return GSR_ERR_INVALID;
+  try {
+    return gsr::iteration_impl(ctx, params, num, stride, sh_degree, num_views, cams, out, targets, depth_weight,
+                               grad_params, loss, adam, (hipStream_t)stream);
+  } catch (const std::bad_alloc&) {
+    return GSR_ERR_OOM;
+  } catch (...) {
+    return GSR_ERR_INVALID;
+  }
+}
+
+int gsr_mapping_status(gsr_ctx* ctx, gsr_mapping_stats* out) {
+  if (!ctx || !out) return GSR_ERR_INVALID;
+  std::memset(out, 0, sizeof(*out));
+  gsr::GraphState* G = ctx->graph;
+  if (!G) return GSR_OK;
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->last_stream));
+  HIP_TRY(ctx, hipEventSynchronize(G->done));
+  uint32_t s[gsr::kStatWords];
+  HIP_TRY(ctx, hipMemcpy(s, G->stats.p, sizeof(s), hipMemcpyDeviceToHost));
+  out->iterations = s[gsr::kStatIterations];
+  out->skipped = s[gsr::kStatSkipped];
+  out->captures = G->captures;
+  out->capacity = G->capacity;
+  out->last_instances = s[gsr::kStatLastInstances];
+  out->adam_steps = s[gsr::kStatAdamSteps];
+  return s[gsr::kStatErrors] ? GSR_ERR_DEVICE : GSR_OK;
+}
+
+}  // extern "C"

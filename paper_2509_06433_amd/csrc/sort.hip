@@ -7,9 +7,8 @@
 //   2. instances are emitted in that depth order, then a stable LSD radix
 //      sort on the global tile id groups them by tile while keeping the depth
 //      order inside every tile.
-// The radix sort is reduce-then-scan with 8-bit digits: a per-block digit
-// histogram, a device-wide exclusive scan of the digit-major histogram
-// table, and a stable scatter that ranks keys inside wave64s with ballots.
+// The radix sort is an 8-bit-digit onesweep (see below); instance offsets
+// come from a reduce-then-scan over the tile counts in depth order.
 
 #include "gsr_internal.h"
 
@@ -151,7 +150,7 @@ constexpr uint32_t kSpinLimit = 1u << 20;
 __global__ void __launch_bounds__(kSortThreads) global_hist_kernel(const uint32_t* __restrict__ keys,
                                                                    const uint32_t* __restrict__ n_dev, int64_t n_host,
                                                                    int passes, uint32_t* __restrict__ ghist) {
-  const int64_t n = n_dev ? (int64_t)*n_dev : n_host;
+  const int64_t n = n_dev ? min((int64_t)*n_dev, n_host) : n_host;
   __shared__ uint32_t h[kSortThreads / 64][kMaxPasses][kRadix];
   const int wave = threadIdx.x >> 6;
   for (int e = threadIdx.x; e < (kSortThreads / 64) * kMaxPasses * kRadix; e += kSortThreads)
@@ -187,7 +186,7 @@ __global__ void __launch_bounds__(kSortThreads) onesweep_pass_kernel(
   __shared__ uint32_t s_wsum[2][kSortThreads / 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int d0 = threadIdx.x;                       // the digit this thread publishes and looks back for
-  const int64_t n = n_dev ? (int64_t)*n_dev : n_host;
+  const int64_t n = n_dev ? min((int64_t)*n_dev, n_host) : n_host;
   if (threadIdx.x == 0) s_bid = atomicAdd(ticket, 1u);
 #pragma unroll
   for (int w = 0; w < kSortThreads / 64; ++w) wcnt[w][threadIdx.x] = 0;
@@ -313,13 +312,14 @@ __global__ void __launch_bounds__(kEmitChunk) emit_kernel(const uint32_t* __rest
                                                          const int4* __restrict__ rect, int64_t count, int64_t n,
                                                          const ViewDesc* __restrict__ views, int tile_w, int tile_h,
                                                          uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
-                                                         int64_t capacity) {
+                                                         int64_t capacity, uint32_t* __restrict__ overflow) {
   __shared__ uint32_t s_off[kEmitChunk + 1];
   __shared__ uint32_t s_sid[kEmitChunk];
   __shared__ int3 s_geo[kEmitChunk];      // first tile id of the rectangle, rectangle width, view row pitch
   const int64_t r0 = (int64_t)blockIdx.x * kEmitChunk;
   const uint32_t total = *total_dev;
   const int tid = threadIdx.x;
+  if (blockIdx.x == 0 && tid == 0 && (int64_t)total > capacity) atomicOr(overflow, 1u);
   const int64_t r = r0 + tid;
   s_off[tid] = r < count ? offsets[r] : total;
   const uint32_t sid = r < count ? sorted_s[r] : 0u;
@@ -353,8 +353,9 @@ __global__ void __launch_bounds__(kEmitChunk) emit_kernel(const uint32_t* __rest
   }
 }
 
-__global__ void tile_ranges_kernel(const uint32_t* __restrict__ keys, int64_t count, uint2* __restrict__ ranges,
-                                   int64_t num_tiles) {
+__global__ void tile_ranges_kernel(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ n_dev,
+                                   int64_t n_host, uint2* __restrict__ ranges, int64_t num_tiles) {
+  const int64_t count = n_dev ? min((int64_t)*n_dev, n_host) : n_host;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
     const uint32_t k = keys[i];
     if (k >= num_tiles) continue;
@@ -444,18 +445,21 @@ void radix_sort_pairs(uint32_t*& keys, uint32_t*& vals, uint32_t*& keys_alt, uin
 
 void launch_emit(const uint32_t* sorted_s, const uint32_t* offsets, const uint32_t* total_dev, const int4* rect,
                  int64_t count, int64_t n, const ViewDesc* views, int tile_w, int tile_h, uint32_t* keys,
-                 uint32_t* vals, int64_t capacity, hipStream_t st) {
+                 uint32_t* vals, int64_t capacity, uint32_t* overflow, hipStream_t st) {
   if (count == 0) return;
   emit_kernel<<<blocks_for(count, kEmitChunk), kEmitChunk, 0, st>>>(sorted_s, offsets, total_dev, rect, count, n,
-                                                                     views, tile_w, tile_h, keys, vals, capacity);
+                                                                     views, tile_w, tile_h, keys, vals, capacity,
+                                                                     overflow);
 }
 
-void launch_tile_ranges(const uint32_t* keys, int64_t count, uint2* ranges, int64_t num_tiles, hipStream_t st) {
+void launch_tile_ranges(const uint32_t* keys, const uint32_t* n_dev, int64_t count, uint2* ranges, int64_t num_tiles,
+                        hipStream_t st) {
   fill_u32_kernel<<<grid_cap(2 * num_tiles, 256), 256, 0, st>>>(reinterpret_cast<uint32_t*>(ranges), 0u,
                                                                 2 * num_tiles);
   if (count == 0) return;
-  tile_ranges_kernel<<<grid_cap(count, 256), 256, 0, st>>>(keys, count, ranges, num_tiles);
+  tile_ranges_kernel<<<grid_cap(count, 256), 256, 0, st>>>(keys, n_dev, count, ranges, num_tiles);
 }
+
 
 void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st) {
   if (n == 0) return;

@@ -59,6 +59,16 @@ class Rasterizer:
     def adam_step(self, params, grads, m, v, lr_per_plane, step, beta1=0.9, beta2=0.999, eps=1e-15):
         _lib.gsr_adam_step(self.handle, params, grads, m, v, lr_per_plane, step, beta1, beta2, eps)
 
+    def mapping_iteration(self, params, sh_degree, cams, outs, targets, grad_params, depth_weight=0.5, loss=None,
+                          adam=None):
+        """Render, L1 loss, backward and (optionally) Adam of one mapping iteration, replayed as one HIP
+        graph; grad_params is overwritten, params updated in place when adam is given."""
+        _lib.gsr_mapping_iteration(self.handle, params, sh_degree, cams, outs, targets, depth_weight, grad_params,
+                                   loss, adam)
+
+    def mapping_status(self):
+        return _lib.gsr_mapping_status(self.handle)
+
     def status(self):
         return _lib.gsr_query_status(self.handle)
 
