@@ -27,13 +27,24 @@ sys.path.insert(0, ROOT)
 METRIC = "mapping iters/sec (fwd+bwd) 640x480, 200k Gaussians; render Mpix/s"
 ADAM_WORKLOADS = {"surfaces_1200x680_1M_sh3", "mixed16_2M_sh3"}
 
-# MI355X published peaks
+# MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz issue 39.3e12 FP32 VALU lane
+# operations per second without packed FP32 math (which this build does not
+# emit); the 157.3 TFLOP/s vector figure counts packed FMAs as four FLOPs.
+PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
 PEAK_HBM_GBS = 8000.0
-PEAK_FP32_VECTOR_TFLOPS = 157.3
 
-# Algorithmic work per unit ("Roofline")
-FLOP_PER_PAIR_BWD = 50.0      # blend backward, per (pixel, Gaussian) pair walked
-FLOP_PER_PAIR_FWD = 22.0      # blend forward, per pair up to the last composited
+# Algorithmic VALU lane operations per (pixel, Gaussian) pair walked by the
+# blend backward: 16 for the alpha (exp counted at its quarter issue rate),
+# 29 for the reverse step (rcp likewise), 10 for the wave sums of the ten
+# per-Gaussian moments (63 adds per 64 lanes each).
+OPS_PER_PAIR_BWD = 55.0
+
+
+# HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE on this workload, each scaled by what the counter reads for a
+# 256 MiB device copy (FETCH x2.0, WRITE x1.0); cleared whenever the kernel
+# changes.
+TRAFFIC = {}
 
 
 def parse():
@@ -155,7 +166,7 @@ def main():
             print(f"warning: {mst['skipped']} iterations skipped for instance overflow", file=sys.stderr)
     pairs, visible = R.count_work(len(cams))
     dom_avg_ms = dom_ms / max(args.steps, 1)     # one launch per step in graph mode
-    achieved = FLOP_PER_PAIR_BWD * pairs / (dom_avg_ms * 1e-3) / 1e12
+    achieved = OPS_PER_PAIR_BWD * pairs / (dom_avg_ms * 1e-3) / 1e12
 
     other = "eager" if args.mode == "graph" else "graph"
     other_ms = None
@@ -210,10 +221,10 @@ def main():
                    "instances": st["instances"], "visible_per_view": visible,
                    "stage_ms": {k: round(x, 4) for k, x in stages.items()}},
         "roofline": {"bound": "alu", "kernel": dominant, "achieved": round(achieved, 3),
-                     "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": None,
+                     "peak": round(PEAK_VALU_TOPS, 2), "unit": "TOP/s (FP32 VALU lane ops)",
+                     "frac": round(achieved / PEAK_VALU_TOPS, 4), "traffic": TRAFFIC.get(dominant),
                      "avg_ms": round(dom_avg_ms, 4), "launches": dom_n, "pairs": pairs,
-                     "flop_per_pair": FLOP_PER_PAIR_BWD},
+                     "ops_per_pair": OPS_PER_PAIR_BWD},
     }
     if not args.no_cpu_baseline:
         tnp = [(t[0].cpu().numpy(), t[1].cpu().numpy()) for t in targets]
