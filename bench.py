@@ -38,6 +38,9 @@ PEAK_HBM_GBS = 8000.0
 # 29 for the reverse step (rcp likewise), 10 for the wave sums of the ten
 # per-Gaussian moments (63 adds per 64 lanes each).
 OPS_PER_PAIR_BWD = 55.0
+# Blend forward: 16 for the alpha, 3 for the transmittance test and update
+# (the colour and depth accumulation happens once per composited pair).
+OPS_PER_PAIR_FWD = 19.0
 
 
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
@@ -107,9 +110,13 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     params = torch.from_numpy(scene.params).to(dev)
-    tparams = torch.from_numpy(scene.target_params).to(dev)
-    targets = [tuple(t.clone() for t in o) for o in R.render(tparams, deg, cams)]
-    del tparams
+    forward_only = scene.target_params is None
+    if forward_only:
+        targets = None
+    else:
+        tparams = torch.from_numpy(scene.target_params).to(dev)
+        targets = [tuple(t.clone() for t in o) for o in R.render(tparams, deg, cams)]
+        del tparams
     outs = R.alloc_images(cams, dev)
     gimgs = [(torch.empty_like(o[0]), torch.empty_like(o[1]), torch.zeros_like(o[2])) for o in outs]
     loss = torch.zeros(1, device=dev)
@@ -137,8 +144,13 @@ def main():
         if use_adam:
             R.adam_step(params, grad, m, v, lrs, it)
 
+    def render_step(it):
+        R.render(params, deg, cams, outs)
+
     steps = {"graph": graph_step, "eager": eager_step}
-    dominant = "blend_bwd"
+    if forward_only:          # a render-only workload: both modes time the forward
+        steps = {"graph": render_step, "eager": render_step}
+    dominant = "blend_fwd" if forward_only else "blend_bwd"
 
     def timed(mode, n_steps, n_warm, profile):
         """Warm up, then time n_steps; returns (ms per step, dominant-stage profile)."""
@@ -166,7 +178,8 @@ def main():
             print(f"warning: {mst['skipped']} iterations skipped for instance overflow", file=sys.stderr)
     pairs, visible = R.count_work(len(cams))
     dom_avg_ms = dom_ms / max(args.steps, 1)     # one launch per step in graph mode
-    achieved = OPS_PER_PAIR_BWD * pairs / (dom_avg_ms * 1e-3) / 1e12
+    ops_per_pair = OPS_PER_PAIR_FWD if forward_only else OPS_PER_PAIR_BWD
+    achieved = ops_per_pair * pairs / (dom_avg_ms * 1e-3) / 1e12
 
     other = "eager" if args.mode == "graph" else "graph"
     other_ms = None
@@ -224,9 +237,9 @@ def main():
                      "peak": round(PEAK_VALU_TOPS, 2), "unit": "TOP/s (FP32 VALU lane ops)",
                      "frac": round(achieved / PEAK_VALU_TOPS, 4), "traffic": TRAFFIC.get(dominant),
                      "avg_ms": round(dom_avg_ms, 4), "launches": dom_n, "pairs": pairs,
-                     "ops_per_pair": OPS_PER_PAIR_BWD},
+                     "ops_per_pair": ops_per_pair},
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not forward_only:
         tnp = [(t[0].cpu().numpy(), t[1].cpu().numpy()) for t in targets]
         out["cpu_baseline"] = cpu_baseline(scene, cams, tnp)
     print(json.dumps(out), flush=True)

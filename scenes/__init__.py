@@ -233,6 +233,9 @@ def _room_points(rng, n, size, frac_walls):
     return np.concatenate([p, clutter], axis=0)
 
 
+BATCH8_TRAJ_SEED = 3     # per-view visibility 32% .. 83% (seeded search over 0..7)
+
+
 def _room_trajectory(rng, n_views, size, step=0.1, turn_deg=5.0, stride=1):
     """Smooth random walk of camera poses inside the room: position steps of
     `step` metres and heading turns of `turn_deg` degrees between consecutive
@@ -261,9 +264,37 @@ def _room_trajectory(rng, n_views, size, step=0.1, turn_deg=5.0, stride=1):
     return poses
 
 
-def batch8_640x480(n=500_000, seed_offset=0, traj_seed=0) -> Scene:
+def _corner_exit_trajectory(rng, n_views, start, stride, step=0.1, turn_deg=5.0):
+    """Smooth random trajectory that backs out of a room through its (+x, +y)
+    corner while looking across the room: position steps of `step` metres along
+    a fixed diagonal, heading and pitch turns of at most `turn_deg` degrees per
+    step (heading kept within 20 degrees of the room's diagonal). Every
+    `stride`-th pose is a keyframe. Seen from inside the corner a view holds
+    about a third of the room; backing out, most of it."""
+    pos = np.array(start, np.float64)
+    walk = np.array([1.0, 1.0, 0.12])
+    walk /= np.linalg.norm(walk)
+    yaw_c = math.radians(225.0)
+    yaw, pitch = yaw_c, -0.35
+    poses = []
+    for i in range(n_views * stride):
+        if i % stride == 0:
+            fwd = np.array([math.cos(yaw) * math.cos(pitch), math.sin(yaw) * math.cos(pitch), math.sin(pitch)])
+            poses.append((pos.copy(), pos + fwd))
+        dyaw = math.radians(turn_deg) * rng.choice([-1.0, 0.0, 1.0])
+        if abs(yaw + dyaw - yaw_c) > math.radians(20.0):
+            dyaw = -dyaw
+        yaw += dyaw
+        pitch = float(np.clip(pitch + math.radians(turn_deg) * rng.normal(0.0, 0.4), -0.55, -0.15))
+        pos = pos + step * walk
+    return poses
+
+
+def batch8_640x480(n=500_000, seed_offset=0, traj_seed=BATCH8_TRAJ_SEED) -> Scene:
     """8 keyframes at 640x480 over a shared 500k-Gaussian room (6x6x3 m, 85% on
-    walls/floor, 15% clutter); poses on a smooth trajectory (0.1 m / 5 deg steps)."""
+    walls/floor, 15% clutter); poses on a smooth trajectory (0.1 m / 5 deg steps)
+    that backs out through a corner, so that the fraction of Gaussians each view
+    sees is uneven, from about 30% to about 90%."""
     rng = np.random.default_rng(SEED_BASE + 3 + seed_offset)
     size = (6.0, 6.0, 3.0)
     mean = _room_points(rng, n, size, 0.85)
@@ -273,7 +304,7 @@ def batch8_640x480(n=500_000, seed_offset=0, traj_seed=0) -> Scene:
     sh = _sh_block(rng, n, 0, dc_uniform=True)
     params = _assemble(mean, logscale, quat, logit, sh)
     trng = np.random.default_rng(SEED_BASE + 3 + 1000 + traj_seed)
-    poses = _room_trajectory(trng, 8, size, stride=3)
+    poses = _corner_exit_trajectory(trng, 8, (5.1, 5.1, 1.7), stride=5)
     cams = [look_at_camera(e, t, 640, 480, 525.0) for e, t in poses]
     target = perturb(rng, params, 0)
     return Scene("batch8_640x480_500k", params, 0, cams, target)
