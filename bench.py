@@ -34,13 +34,15 @@ PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
 PEAK_HBM_GBS = 8000.0
 
 # Algorithmic VALU lane operations per (pixel, Gaussian) pair walked by the
-# blend backward: 16 for the alpha (exp counted at its quarter issue rate),
-# 29 for the reverse step (rcp likewise), 10 for the wave sums of the ten
-# per-Gaussian moments (63 adds per 64 lanes each).
-OPS_PER_PAIR_BWD = 55.0
-# Blend forward: 16 for the alpha, 3 for the transmittance test and update
+# blend backward: 20 for the alpha (10 for the exponent in its definition's
+# float order, 1 scaling, the exp counted as 4 for its quarter issue rate,
+# 5 for opacity, clamp and the skip tests), 29 for the reverse step (rcp
+# likewise counted as 4), 10 for the wave sums of the ten per-Gaussian moments
+# (63 adds per 64 lanes each).
+OPS_PER_PAIR_BWD = 59.0
+# Blend forward: 20 for the alpha, 3 for the transmittance test and update
 # (the colour and depth accumulation happens once per composited pair).
-OPS_PER_PAIR_FWD = 19.0
+OPS_PER_PAIR_FWD = 23.0
 
 
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and

@@ -37,7 +37,7 @@ int size_instances(gsr_ctx* ctx, Buffers& B, const RenderPlan& P) {
   RET_IF(ensure(ctx, B.ivals, i4));
   RET_IF(ensure(ctx, B.ikeys_alt, i4));
   RET_IF(ensure(ctx, B.ivals_alt, i4));
-  RET_IF(ensure(ctx, B.hist, sizeof(uint32_t) * (size_t)radix_scratch_elems(std::max(P.total, P.capacity))));
+  RET_IF(ensure(ctx, B.hist2, sizeof(uint32_t) * (size_t)radix_scratch_elems(P.capacity)));
   return GSR_OK;
 }
 
@@ -63,20 +63,33 @@ int size_render(gsr_ctx* ctx, Buffers& B, RenderPlan& P, const gsr_image* out, h
   RET_IF(ensure(ctx, B.last, sizeof(uint32_t) * (size_t)P.npix));
   RET_IF(ensure(ctx, B.g2, sizeof(float) * G2_N * (size_t)std::max<int64_t>(P.total, 1)));
   RET_IF(ensure(ctx, B.total, 64));
+  RET_IF(ensure(ctx, B.hist, sizeof(uint32_t) * (size_t)radix_scratch_elems(P.total)));
   RET_IF(ensure(ctx, B.partials, sizeof(uint32_t) * (size_t)scan_partial_elems(P.total)));
   RET_IF(upload(ctx, B.views.p, P.views.data(), sizeof(ViewDesc) * nv, st));
   RET_IF(upload(ctx, B.images.p, ims.data(), sizeof(ViewImages) * nv, st));
   return GSR_OK;
 }
 
+void front_clears(Buffers& B, const RenderPlan& P, ClearList& L) {
+  L.add(B.total.p, 4);
+  L.add(B.partials.p, scan_partial_elems(P.total));
+  if (P.total > 1) L.add(B.hist.p, radix_scratch_elems(P.total));
+}
+
+void back_clears(Buffers& B, const RenderPlan& P, ClearList& L) {
+  if (P.capacity > 1) L.add(B.hist2.p, radix_scratch_elems(P.capacity));
+  L.add(B.ranges.p, 2 * P.ntiles);
+}
+
 int launch_front(gsr_ctx* ctx, Buffers& B, RenderPlan& P, const float* params, hipStream_t st) {
   const int nv = P.nv;
   uint32_t* totals = as<uint32_t>(B.total);
+  uint32_t* zhist = P.total > 1 ? radix_hist(as<uint32_t>(B.hist), P.total) : nullptr;
   {
     StageTimer tm(ctx, GSR_STAGE_PROJECT, st);
     launch_project(params, P.num, P.stride, P.deg, nv, as<ViewDesc>(B.views), ctx->tile_w, ctx->tile_h, ctx->znear,
                    as<Splat>(B.splats), as<int4>(B.rect), as<uint32_t>(B.ntiles), as<uint32_t>(B.zkey),
-                   as<uint32_t>(B.svals), st);
+                   as<uint32_t>(B.svals), zhist, st);
   }
   CHECK_LAUNCH(ctx);
   uint32_t* zk = as<uint32_t>(B.zkey);
@@ -85,13 +98,13 @@ int launch_front(gsr_ctx* ctx, Buffers& B, RenderPlan& P, const float* params, h
   uint32_t* sva = as<uint32_t>(B.svals_alt);
   {
     StageTimer tm(ctx, GSR_STAGE_DEPTH_SORT, st);
-    radix_sort_pairs(zk, sv, zka, sva, P.total, nullptr, 32, as<uint32_t>(B.hist), totals + 1, st);
+    radix_sort_pairs(zk, sv, zka, sva, P.total, nullptr, 32, as<uint32_t>(B.hist), totals + 1, false, true, st);
   }
   CHECK_LAUNCH(ctx);
   {
     StageTimer tm(ctx, GSR_STAGE_SCAN, st);
     scan_gather_exclusive(as<uint32_t>(B.ntiles), sv, as<uint32_t>(B.offsets), P.total, totals,
-                          as<uint32_t>(B.partials), st);
+                          as<uint32_t>(B.partials), totals + 1, false, st);
   }
   CHECK_LAUNCH(ctx);
   P.sorted_splats = sv;
@@ -104,21 +117,24 @@ int launch_back(gsr_ctx* ctx, Buffers& B, RenderPlan& P, hipStream_t st) {
   uint32_t* iv = as<uint32_t>(B.ivals);
   uint32_t* ika = as<uint32_t>(B.ikeys_alt);
   uint32_t* iva = as<uint32_t>(B.ivals_alt);
+  const int tbits = bits_for(P.ntiles - 1);
+  const bool hist_in_emit = P.capacity > 1 && tbits > 0 && tbits <= 16;
+  uint32_t* thist = hist_in_emit ? radix_hist(as<uint32_t>(B.hist2), P.capacity) : nullptr;
   {
     StageTimer tm(ctx, GSR_STAGE_EMIT, st);
     launch_emit(P.sorted_splats, as<uint32_t>(B.offsets), totals, as<int4>(B.rect), P.total, P.num,
-                as<ViewDesc>(B.views), ctx->tile_w, ctx->tile_h, ik, iv, P.capacity, totals + 2, st);
+                as<ViewDesc>(B.views), ctx->tile_w, ctx->tile_h, ik, iv, P.capacity, totals + 2, thist, tbits, st);
   }
   CHECK_LAUNCH(ctx);
   {
     StageTimer tm(ctx, GSR_STAGE_TILE_SORT, st);
-    radix_sort_pairs(ik, iv, ika, iva, P.capacity, totals, bits_for(P.ntiles - 1), as<uint32_t>(B.hist), totals + 1,
-                     st);
+    radix_sort_pairs(ik, iv, ika, iva, P.capacity, totals, tbits, as<uint32_t>(B.hist2), totals + 1, false,
+                     hist_in_emit, st);
   }
   CHECK_LAUNCH(ctx);
   {
     StageTimer tm(ctx, GSR_STAGE_RANGES, st);
-    launch_tile_ranges(ik, totals, P.capacity, as<uint2>(B.ranges), P.ntiles, st);
+    launch_tile_ranges(ik, totals, P.capacity, as<uint2>(B.ranges), P.ntiles, false, st);
   }
   CHECK_LAUNCH(ctx);
   P.inst_keys = ik;
@@ -145,9 +161,9 @@ int launch_back(gsr_ctx* ctx, Buffers& B, RenderPlan& P, hipStream_t st) {
 }
 
 int launch_bwd(gsr_ctx* ctx, Buffers& B, const RenderPlan& P, const float* params, float* grad_params,
-               hipStream_t st) {
+               bool clear_g2, hipStream_t st) {
   if (P.total == 0) return GSR_OK;
-  {
+  if (clear_g2) {
     StageTimer tm(ctx, GSR_STAGE_ZERO, st);
     launch_fill_f32(as<float>(B.g2), 0.0f, P.total * G2_N, st);
   }
@@ -181,7 +197,7 @@ int launch_bwd(gsr_ctx* ctx, Buffers& B, const RenderPlan& P, const float* param
 void free_buffers(Buffers& B) {
   DevBuf* bufs[] = {&B.views, &B.images, &B.images2, &B.splats, &B.rect, &B.ntiles, &B.zkey, &B.svals,
                     &B.zkey_alt, &B.svals_alt, &B.offsets, &B.ikeys, &B.ivals, &B.ikeys_alt, &B.ivals_alt,
-                    &B.hist, &B.partials, &B.ranges, &B.tfinal, &B.last, &B.g2, &B.total};
+                    &B.hist, &B.hist2, &B.partials, &B.ranges, &B.tfinal, &B.last, &B.g2, &B.total};
   for (DevBuf* b : bufs) {
     if (b->p) (void)hipFree(b->p);
     b->p = nullptr;
@@ -209,13 +225,18 @@ int render_impl(gsr_ctx* ctx, const gsr_gaussians* g, int32_t nv, const gsr_came
   Buffers& B = ctx->eager;
   P.capacity = 0;
   RET_IF(size_render(ctx, B, P, out, st));
-  launch_fill_u32(as<uint32_t>(B.total), 0u, 4, st);
+  ClearList L{};
+  front_clears(B, P, L);
+  launch_clear(L, st);
   RET_IF(launch_front(ctx, B, P, g->params, st));
   HIP_TRY(ctx, hipMemcpyAsync(ctx->host_total, B.total.p, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
   HIP_TRY(ctx, hipStreamSynchronize(st));
   if (ctx->host_total[1] != 0) return GSR_ERR_DEVICE;
   P.capacity = (int64_t)ctx->host_total[0];
   RET_IF(size_instances(ctx, B, P));
+  ClearList L2{};
+  back_clears(B, P, L2);
+  launch_clear(L2, st);
   RET_IF(launch_back(ctx, B, P, st));
 
   ctx->have_forward = true;
@@ -242,7 +263,7 @@ int backward_impl(gsr_ctx* ctx, const gsr_gaussians* g, int32_t nv, const gsr_ca
   std::vector<ViewImages> ims(nv);
   for (int v = 0; v < nv; ++v) ims[v] = ViewImages{grad_out[v].rgb, grad_out[v].depth, grad_out[v].alpha};
   RET_IF(upload(ctx, B.images2.p, ims.data(), sizeof(ViewImages) * nv, st));
-  return launch_bwd(ctx, B, P, g->params, grad_params, st);
+  return launch_bwd(ctx, B, P, g->params, grad_params, true, st);
 }
 
 }  // namespace
@@ -372,7 +393,7 @@ int gsr_loss_l1(gsr_ctx* ctx, int32_t num_views, const gsr_camera* cams, const g
     RET_IF(upload(ctx, dc, c.data(), sizeof(ViewImages) * num_views, st));
     RET_IF(upload(ctx, dv, views.data(), sizeof(ViewDesc) * num_views, st));
     StageTimer tm(ctx, GSR_STAGE_LOSS, st);
-    launch_loss_l1(dv, da, db, dc, num_views, maxpix, depth_weight, loss, st);
+    launch_loss_l1(dv, da, db, dc, num_views, maxpix, depth_weight, loss, true, st);
     CHECK_LAUNCH(ctx);
   } catch (...) {
     return GSR_ERR_OOM;
@@ -481,7 +502,8 @@ int gsr_set_profiling(gsr_ctx* ctx, uint32_t stage_mask) {
 
 int gsr_get_profile(gsr_ctx* ctx, int32_t stage, double* total_ms, int64_t* launches, int32_t reset) {
   if (!ctx || stage < 0 || stage >= GSR_NUM_STAGES || !total_ms) return GSR_ERR_INVALID;
-  double sum = 0.0;
+  RET_IF(harvest_graph(ctx));
+  double sum = ctx->acc_ms[stage];
   auto& v = ctx->ev_pending[stage];
   for (auto& pr : v) {
     HIP_TRY(ctx, hipEventSynchronize(pr.second));
@@ -490,13 +512,15 @@ int gsr_get_profile(gsr_ctx* ctx, int32_t stage, double* total_ms, int64_t* laun
     sum += ms;
   }
   *total_ms = sum;
-  if (launches) *launches = (int64_t)v.size();
+  if (launches) *launches = (int64_t)v.size() + ctx->acc_n[stage];
   if (reset) {
     for (auto& pr : v) {
       ctx->ev_pool.push_back(pr.first);
       ctx->ev_pool.push_back(pr.second);
     }
     v.clear();
+    ctx->acc_ms[stage] = 0.0;
+    ctx->acc_n[stage] = 0;
   }
   return GSR_OK;
 }

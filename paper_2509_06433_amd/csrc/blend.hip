@@ -13,11 +13,16 @@
 // Gaussian, recovering T_k = T_{k+1} / (1 - alpha_k) from the stored final
 // transmittance instead of storing per-Gaussian blend state, and keeps the
 // suffix sum S_k of later contributions. Per-pair screen-space gradients are
-// summed over the wavefront with a butterfly, over the workgroup in LDS, and
-// only then added with one global atomic per (tile, Gaussian, component).
+// summed as ten moments per Gaussian over each 16-lane row with DPP, over the
+// workgroup in LDS, and only then added with one global atomic per (tile
+// batch, Gaussian, component).
 //
-// Compiled with -ffp-contract=off: alpha is written with explicit fused
-// multiply-adds so the forward and backward recompute it bit-identically.
+// Compiled with -ffp-contract=off. The exponent of a pair is formed with the
+// float roundings of its plain definition, -(A dx^2 + C dy^2)/2 - B dx dy
+// summed as ((A dx) dx + (C dy) dy) and (B dx) dy, so it is the same float as
+// a plain float evaluation of the formula; the forward and backward recompute
+// it bit-identically. For thin Gaussians the terms cancel and any other
+// association of the sum would differ from it by much more than an ulp.
 
 #include "gsr_internal.h"
 
@@ -25,14 +30,14 @@ namespace gsr {
 namespace {
 
 constexpr float kLog2e = 1.4426950408889634f;
-constexpr float kLn2 = 0.6931471805599453f;
 
-// Blend-ready record of one Gaussian in LDS: q0 = (u, v, Ah, Bh),
-// q1 = (Ch, opacity, z, 0), q2 = (r, g, b, 0) where the base-2 exponent is
-// p2 = Ah dx^2 + Bh dx dy + Ch dy^2 = log2(e) * power.
+// Blend-ready record of one Gaussian in LDS: q0 = (u, v, -A/2, -B),
+// q1 = (-C/2, opacity, z, 0), q2 = (r, g, b, 0). Halving and negating are
+// exact, so ((-A/2 dx) dx + (-C/2 dy) dy) + (-B dx) dy rounds exactly like
+// -((A dx) dx + (C dy) dy)/2 - (B dx) dy.
 __device__ __forceinline__ void stage_record(const Splat& sp, float4& q0, float4& q1, float4& q2) {
-  q0 = make_float4(sp.w0.x, sp.w0.y, -0.5f * kLog2e * sp.w1.x, -kLog2e * sp.w1.y);
-  q1 = make_float4(-0.5f * kLog2e * sp.w1.z, sp.w0.w, sp.w0.z, 0.0f);
+  q0 = make_float4(sp.w0.x, sp.w0.y, -0.5f * sp.w1.x, -sp.w1.y);
+  q1 = make_float4(-0.5f * sp.w1.z, sp.w0.w, sp.w0.z, 0.0f);
   q2 = sp.w2;
 }
 
@@ -42,12 +47,12 @@ __device__ __forceinline__ bool pair_alpha(const float4& q0, const float4& q1, f
                                            float& dy, float& G, float& alpha, bool& clamped) {
   dx = q0.x - xs;
   dy = q0.y - ys;
-  const float p2 = fmaf(q0.z * dx, dx, fmaf(q1.x * dy, dy, q0.w * dx * dy));
-  G = __builtin_amdgcn_exp2f(p2);
+  const float power = ((q0.z * dx) * dx + (q1.x * dy) * dy) + (q0.w * dx) * dy;
+  G = __builtin_amdgcn_exp2f(power * kLog2e);
   const float araw = q1.y * G;
   clamped = araw > kAlphaMax;
   alpha = clamped ? kAlphaMax : araw;
-  return (p2 <= 0.0f) && (alpha >= kAlphaMin);
+  return (power <= 0.0f) && (alpha >= kAlphaMin);
 }
 
 __device__ __forceinline__ int find_view(const ViewDesc* views, int num_views, int tile) {
@@ -398,9 +403,9 @@ blend_backward_kernel(BlendArgs a) {
       for (int c = 0; c < M_N; ++c) mm[c] = s_red[0][0][c][kk];
       const float4 q0 = s_q0[kk], q1 = s_q1[kk];
       float g[G2_N];
-      // d power / d u = (2 Ah dx + Bh dy) ln 2 with Ah = -A log2(e) / 2, Bh = -B log2(e)
-      g[G2_U] = kLn2 * (2.0f * q0.z * mm[M_X] + q0.w * mm[M_Y]);
-      g[G2_V] = kLn2 * (q0.w * mm[M_X] + 2.0f * q1.x * mm[M_Y]);
+      // d power / d u = -(A dx + B dy) = 2 (-A/2) dx + (-B) dy, likewise for v
+      g[G2_U] = 2.0f * q0.z * mm[M_X] + q0.w * mm[M_Y];
+      g[G2_V] = q0.w * mm[M_X] + 2.0f * q1.x * mm[M_Y];
       g[G2_A] = -0.5f * mm[M_XX];
       g[G2_B] = -mm[M_XY];
       g[G2_C] = -0.5f * mm[M_YY];
@@ -516,8 +521,8 @@ void launch_blend_backward(const BlendArgs& a, int tile_w, int tile_h, int ppt, 
 
 void launch_loss_l1(const ViewDesc* views, const ViewImages* rendered, const ViewImages* target,
                     const ViewImages* grad, int num_views, int max_pixels, float depth_weight, float* loss,
-                    hipStream_t st) {
-  if (loss) launch_fill_f32(loss, 0.0f, 1, st);
+                    bool clear_loss, hipStream_t st) {
+  if (loss && clear_loss) launch_fill_f32(loss, 0.0f, 1, st);
   dim3 grid(grid_cap(max_pixels, 256) < 1024 ? grid_cap(max_pixels, 256) : 1024, num_views);
   loss_l1_kernel<<<grid, 256, 0, st>>>(views, rendered, target, grad, depth_weight, loss);
 }

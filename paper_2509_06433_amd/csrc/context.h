@@ -4,6 +4,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -14,6 +16,8 @@
 struct gsr_ctx;
 
 namespace gsr {
+
+inline void note_hip_failure(gsr_ctx* ctx, hipError_t e, const char* expr, const char* file, int line);
 
 struct DevBuf {
   void* p = nullptr;
@@ -32,7 +36,7 @@ struct Buffers {
   DevBuf views, images, images2;
   DevBuf splats, rect, ntiles, zkey, svals, zkey_alt, svals_alt, offsets;
   DevBuf ikeys, ivals, ikeys_alt, ivals_alt;
-  DevBuf hist, partials, ranges, tfinal, last, g2;
+  DevBuf hist, hist2, partials, ranges, tfinal, last, g2;   // hist: depth sort, hist2: tile sort
   DevBuf total;   // [0] instance count, [1] sort wait expired, [2] instance overflow
 };
 
@@ -51,24 +55,41 @@ struct RenderPlan {
 
 struct GraphState;   // captured mapping iteration
 
-// Receives the stage boundaries of a timed stage while a mapping iteration is
-// being captured: the capture is cut there so that the replay can record
-// ordinary events between the pieces.
-struct CaptureHook {
-  virtual void cut(int stage, bool end) = 0;
-  virtual ~CaptureHook() = default;
+// Brackets one stage's launches with events when profiling is on. While a
+// mapping iteration is being captured, the events become event-record nodes
+// of the graph and the pair goes to the capture's list instead.
+struct TimedPair {
+  int stage;
+  hipEvent_t a, b;
+  hipGraphNode_t na = nullptr, nb = nullptr;   // their event-record nodes, when captured
 };
 
-// Brackets one stage's launches with events when profiling is on.
 struct StageTimer {
   gsr_ctx* ctx;
   int stage;
   hipStream_t st;
   hipEvent_t a = nullptr, b = nullptr;
-  bool cut = false;
+  hipGraphNode_t na = nullptr;
   StageTimer(gsr_ctx* c, int s, hipStream_t stream);
   ~StageTimer();
 };
+
+// Appends an event-record node behind the work captured so far on `st` and
+// makes it the dependency of what is captured next (the capture-time form of
+// recording an event on the stream).
+inline hipError_t capture_event_node(hipStream_t st, hipEvent_t ev, hipGraphNode_t* node) {
+  hipStreamCaptureStatus cs;
+  unsigned long long id = 0;
+  hipGraph_t g = nullptr;
+  const hipGraphNode_t* deps = nullptr;
+  size_t nd = 0;
+  hipError_t e = hipStreamGetCaptureInfo_v2(st, &cs, &id, &g, &deps, &nd);
+  if (e != hipSuccess) return e;
+  if (cs != hipStreamCaptureStatusActive || !g) return hipErrorStreamCaptureInvalidated;
+  e = hipGraphAddEventRecordNode(node, g, deps, nd, ev);
+  if (e != hipSuccess) return e;
+  return hipStreamUpdateCaptureDependencies(st, node, 1, hipStreamSetCaptureDependencies);
+}
 
 }  // namespace gsr
 
@@ -110,7 +131,10 @@ struct gsr_ctx {
 
   // captured mapping iteration
   gsr::GraphState* graph = nullptr;
-  gsr::CaptureHook* capture = nullptr;   // set while capturing
+  std::vector<gsr::TimedPair>* capture_timed = nullptr;   // set while capturing
+  // stage times harvested from replayed graphs, not yet reported
+  double acc_ms[GSR_NUM_STAGES] = {};
+  int64_t acc_n[GSR_NUM_STAGES] = {};
 };
 
 namespace gsr {
@@ -129,37 +153,45 @@ inline hipEvent_t take_event(gsr_ctx* ctx) {
 
 inline StageTimer::StageTimer(gsr_ctx* c, int s, hipStream_t stream) : ctx(c), stage(s), st(stream) {
   if (!((ctx->profile_mask >> s) & 1u)) return;
-  if (ctx->capture) {
-    ctx->capture->cut(s, false);
-    cut = true;
-    return;
-  }
   a = take_event(ctx);
   b = take_event(ctx);
-  if (a && b) (void)hipEventRecord(a, st);
+  if (!a || !b) return;
+  const hipError_t e = ctx->capture_timed ? capture_event_node(st, a, &na) : hipEventRecord(a, st);
+  if (e != hipSuccess) note_hip_failure(ctx, e, "stage timer start event", __FILE__, __LINE__);
 }
 
 inline StageTimer::~StageTimer() {
-  if (cut) {
-    ctx->capture->cut(stage, true);
-    return;
-  }
   if (!a || !b) return;
-  (void)hipEventRecord(b, st);
-  ctx->ev_pending[stage].emplace_back(a, b);
+  if (ctx->capture_timed) {
+    hipGraphNode_t nb = nullptr;
+    const hipError_t e = capture_event_node(st, b, &nb);
+    if (e != hipSuccess) note_hip_failure(ctx, e, "stage timer end event", __FILE__, __LINE__);
+    ctx->capture_timed->push_back(TimedPair{stage, a, b, na, nb});
+  } else {
+    (void)hipEventRecord(b, st);
+    ctx->ev_pending[stage].emplace_back(a, b);
+  }
 }
 
 }  // namespace gsr
 
 namespace gsr {
 
-#define HIP_TRY(ctx, expr)                      \
-  do {                                          \
-    hipError_t e_ = (expr);                     \
-    if (e_ != hipSuccess) {                     \
-      (ctx)->hip_err = (int)e_;                 \
-      return GSR_ERR_HIP;                       \
-    }                                           \
+// With GSR_DEBUG set in the environment, a failing HIP call is reported on
+// stderr with its source location.
+inline void note_hip_failure(gsr_ctx* ctx, hipError_t e, const char* expr, const char* file, int line) {
+  ctx->hip_err = (int)e;
+  static const bool verbose = std::getenv("GSR_DEBUG") != nullptr;
+  if (verbose) std::fprintf(stderr, "gsr: %s:%d: %s -> %d (%s)\n", file, line, expr, (int)e, hipGetErrorString(e));
+}
+
+#define HIP_TRY(ctx, expr)                                          \
+  do {                                                              \
+    hipError_t e_ = (expr);                                         \
+    if (e_ != hipSuccess) {                                         \
+      gsr::note_hip_failure((ctx), e_, #expr, __FILE__, __LINE__);  \
+      return GSR_ERR_HIP;                                           \
+    }                                                               \
   } while (0)
 
 #define CHECK_LAUNCH(ctx) HIP_TRY(ctx, hipGetLastError())
@@ -280,22 +312,33 @@ inline int bits_for(int64_t max_key) {
 //   plan_render: checks arguments, fills the plan's sizes and view descriptors.
 //   size_render: grows B for the plan (instance slots: plan.capacity) and
 //                uploads the view descriptors and output image pointers.
-//   launch_front: projection, depth sort, instance offsets; B.total[0] = count.
-//   launch_back:  instance emission (at most plan.capacity), tile sort, tile
-//                 ranges, compositing. Counts are read on the device.
+//   front_clears / back_clears: the scratch each half needs zeroed first
+//                 (B.total, the scan and depth-sort scratch; the tile-sort
+//                 scratch and the ranges).
+//   launch_front: projection (with the depth-key histograms), depth sort,
+//                 instance offsets; B.total[0] = count.
+//   launch_back:  instance emission (at most plan.capacity, with the tile-key
+//                 histograms), tile sort, tile ranges, compositing. Counts are
+//                 read on the device.
 //   launch_bwd:   blend backward and projection backward into grad_params,
-//                 image gradients from the descriptors in B.images2.
+//                 image gradients from the descriptors in B.images2; g2 is
+//                 zeroed first unless clear_g2 is false.
 // The launch_* functions make no allocation, copy or synchronisation, so a
 // stream capture can record them.
 int plan_render(gsr_ctx* ctx, const gsr_gaussians* g, int32_t nv, const gsr_camera* cams, RenderPlan* plan);
 int size_render(gsr_ctx* ctx, Buffers& B, RenderPlan& plan, const gsr_image* out, hipStream_t st);
+void front_clears(Buffers& B, const RenderPlan& plan, ClearList& L);
+void back_clears(Buffers& B, const RenderPlan& plan, ClearList& L);
 int launch_front(gsr_ctx* ctx, Buffers& B, RenderPlan& plan, const float* params, hipStream_t st);
 int launch_back(gsr_ctx* ctx, Buffers& B, RenderPlan& plan, hipStream_t st);
 int launch_bwd(gsr_ctx* ctx, Buffers& B, const RenderPlan& plan, const float* params, float* grad_params,
-               hipStream_t st);
+               bool clear_g2, hipStream_t st);
 int size_instances(gsr_ctx* ctx, Buffers& B, const RenderPlan& plan);
 void free_buffers(Buffers& B);
 // Frees the captured mapping iteration and its buffers (iteration.hip).
 void destroy_graph(gsr_ctx* ctx);
+// Waits for every replay still being timed and adds its stage times to the
+// context's accumulators (iteration.hip).
+int harvest_graph(gsr_ctx* ctx);
 
 }  // namespace gsr

@@ -44,7 +44,8 @@ constexpr float kTransMin = 1e-4f;
 // bits of z, 0xFFFFFFFF when culled); s = view * N + i.
 void launch_project(const float* params, int64_t n, int64_t stride, int deg, int num_views,
                     const ViewDesc* views, int tile_w, int tile_h, float znear, Splat* splats,
-                    int4* rect, uint32_t* ntiles, uint32_t* zkey, uint32_t* svals, hipStream_t st);
+                    int4* rect, uint32_t* ntiles, uint32_t* zkey, uint32_t* svals, uint32_t* zhist,
+                    hipStream_t st);
 // Chain rule from screen-space gradients g2[V*N][10] to grad_params (+=).
 void launch_project_backward(const float* params, int64_t n, int64_t stride, int deg, int num_views,
                              const ViewDesc* views, float znear, const float* g2, float* grad,
@@ -61,24 +62,51 @@ int64_t radix_scratch_elems(int64_t n);
 // at the sorted data and keys_alt/vals_alt at the other pair. The element
 // count is *n_dev when n_dev is not null (n is then the capacity the grid is
 // sized for), else n. *err becomes nonzero if a look-back wait hit its bound
-// (the result is then invalid).
+// (the result is then invalid). clear = false: the caller has zeroed the
+// scratch; hist_ready = true: the caller has accumulated the digit
+// histograms at radix_hist(scratch, n) (as the projection and the emission
+// kernels do), so the histogram kernel is skipped.
 void radix_sort_pairs(uint32_t*& keys, uint32_t*& vals, uint32_t*& keys_alt, uint32_t*& vals_alt, int64_t n,
-                      const uint32_t* n_dev, int bits, uint32_t* scratch, uint32_t* err, hipStream_t st);
-// Scan partials needed by scan_gather_exclusive for n elements.
+                      const uint32_t* n_dev, int bits, uint32_t* scratch, uint32_t* err, bool clear, bool hist_ready,
+                      hipStream_t st);
+// The digit histograms ([passes][256]) inside a sort scratch for n elements.
+uint32_t* radix_hist(uint32_t* scratch, int64_t n);
+// Scan scratch (u32 words) needed by scan_gather_exclusive for n elements.
 int64_t scan_partial_elems(int64_t n);
-// Exclusive scan out[r] = sum_{j<r} in[idx[r]] (idx may be null); total -> *total_dev.
+// Exclusive scan out[r] = sum_{j<r} in[idx[r]] (idx may be null); total ->
+// *total_dev. Single pass with decoupled look-back; clear = false: the
+// caller has zeroed the scratch. *err is raised if a bounded wait expired.
 void scan_gather_exclusive(const uint32_t* in, const uint32_t* idx, uint32_t* out, int64_t n,
-                           uint32_t* total_dev, uint32_t* partials, hipStream_t st);
+                           uint32_t* total_dev, uint32_t* scratch, uint32_t* err, bool clear, hipStream_t st);
 // Instance emission in depth order; writes beyond `capacity` are dropped and
-// set *overflow when the total exceeds it.
+// set *overflow when the total exceeds it. With hist (and 1 <= ceil(hist_bits
+// / 8) <= 2) the digit histograms of the written tile keys are accumulated
+// there.
 void launch_emit(const uint32_t* sorted_s, const uint32_t* offsets, const uint32_t* total_dev, const int4* rect,
                  int64_t count, int64_t n, const ViewDesc* views, int tile_w, int tile_h, uint32_t* keys,
-                 uint32_t* vals, int64_t capacity, uint32_t* overflow, hipStream_t st);
+                 uint32_t* vals, int64_t capacity, uint32_t* overflow, uint32_t* hist, int hist_bits,
+                 hipStream_t st);
 // ranges[t] = (start, end) of global tile t in the sorted key array of
-// min(*n_dev, count) instances (count if n_dev is null).
+// min(*n_dev, count) instances (count if n_dev is null); clear = false: the
+// caller has zeroed ranges.
 void launch_tile_ranges(const uint32_t* keys, const uint32_t* n_dev, int64_t count, uint2* ranges, int64_t num_tiles,
-                        hipStream_t st);
+                        bool clear, hipStream_t st);
 
+// Zeroes up to kMaxClear segments of 32-bit words in one launch.
+constexpr int kMaxClear = 10;
+struct ClearList {
+  uint32_t* p[kMaxClear];
+  int64_t n[kMaxClear];
+  int count;
+  void add(void* ptr, int64_t words) {
+    if (ptr && words > 0 && count < kMaxClear) {
+      p[count] = static_cast<uint32_t*>(ptr);
+      n[count] = words;
+      ++count;
+    }
+  }
+};
+void launch_clear(const ClearList& L, hipStream_t st);
 void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
 // out[0] = sum of last[0..npix); out[1+v] = number of nonzero ntiles in view v's segment of n.
 void launch_count_work(const uint32_t* last, int64_t npix, const uint32_t* ntiles, int64_t n, int num_views,
@@ -103,9 +131,10 @@ bool blend_supported(int tile_w, int tile_h);
 // ppt: pixels per thread (1, or 2 for tiles of at least 128 pixels)
 void launch_blend_forward(const BlendArgs& a, int tile_w, int tile_h, int ppt, hipStream_t st);
 void launch_blend_backward(const BlendArgs& a, int tile_w, int tile_h, int ppt, hipStream_t st);
+// clear_loss = false: the caller has zeroed *loss.
 void launch_loss_l1(const ViewDesc* views, const ViewImages* rendered, const ViewImages* target,
                     const ViewImages* grad, int num_views, int max_pixels, float depth_weight,
-                    float* loss, hipStream_t st);
+                    float* loss, bool clear_loss, hipStream_t st);
 // Adam; with step_dev the bias corrections are those of step *step_dev + 1
 // (bc1, bc2 ignored); skip[0] or skip[1] nonzero (if skip is not null) leaves
 // everything unchanged.

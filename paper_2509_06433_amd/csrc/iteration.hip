@@ -32,10 +32,6 @@ enum : int {
   kStatWords = 8
 };
 
-__global__ void iteration_begin_kernel(uint32_t* __restrict__ totals) {
-  if (threadIdx.x < 4) totals[threadIdx.x] = 0u;
-}
-
 __global__ void iteration_end_kernel(const uint32_t* __restrict__ totals, uint32_t* __restrict__ stats, int adam) {
   if (threadIdx.x != 0) return;
   const uint32_t count = totals[0];
@@ -76,17 +72,23 @@ struct GraphState {
   std::vector<float> lr;
   DevBuf tdesc, gimg, lrbuf, stats;
   uint32_t* host_stats = nullptr;      // pinned, written by the last node of each replay
-  // The iteration is one graph, or, with timed stages, a chain of graphs with
-  // an event recorded between consecutive pieces: mark k is recorded after
-  // the first marks[k].after pieces.
-  struct Mark {
-    size_t after;
-    int stage;
-    bool end;
+  // One captured graph, instantiated kRing times. With timed stages each
+  // instance's event-record nodes are given their own events, so a replay
+  // never touches an instance that may still run: instance k is reused only
+  // after its previous replay has finished, and its stage times are
+  // harvested then.
+  static constexpr int kRing = 4;
+  struct Instance {
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;
+    bool launched = false;
+    std::vector<TimedPair> events;   // stage, start, end
   };
-  std::vector<hipGraph_t> graphs;
-  std::vector<hipGraphExec_t> execs;
-  std::vector<Mark> marks;
+  hipGraph_t graph = nullptr;
+  Instance inst[kRing];
+  int next = 0;
+  std::vector<TimedPair> timed;      // the placeholder events captured in the graph
+  std::vector<std::pair<hipGraphNode_t, hipGraphNode_t>> timed_nodes;
   hipStream_t cap = nullptr;
   hipEvent_t done = nullptr;
   int64_t captures = 0;
@@ -96,18 +98,47 @@ struct GraphState {
 
 namespace {
 
-void drop_graph(GraphState* G) {
-  for (hipGraphExec_t e : G->execs) (void)hipGraphExecDestroy(e);
-  for (hipGraph_t g : G->graphs) (void)hipGraphDestroy(g);
-  G->execs.clear();
-  G->graphs.clear();
-  G->marks.clear();
+// Adds the stage times of instance k's finished replay to the context.
+int harvest(gsr_ctx* ctx, GraphState::Instance& I) {
+  if (!I.launched) return GSR_OK;
+  HIP_TRY(ctx, hipEventSynchronize(I.done));
+  for (const TimedPair& t : I.events) {
+    float ms = 0.f;
+    HIP_TRY(ctx, hipEventElapsedTime(&ms, t.a, t.b));
+    ctx->acc_ms[t.stage] += ms;
+    ctx->acc_n[t.stage] += 1;
+  }
+  I.launched = false;
+  return GSR_OK;
+}
+
+void drop_graph(gsr_ctx* ctx, GraphState* G) {
+  for (GraphState::Instance& I : G->inst) {
+    if (I.launched) (void)harvest(ctx, I);
+    if (I.exec) (void)hipGraphExecDestroy(I.exec);
+    I.exec = nullptr;
+    for (const TimedPair& t : I.events) {
+      ctx->ev_pool.push_back(t.a);
+      ctx->ev_pool.push_back(t.b);
+    }
+    I.events.clear();
+  }
+  if (G->graph) (void)hipGraphDestroy(G->graph);
+  G->graph = nullptr;
+  for (const TimedPair& t : G->timed) {
+    ctx->ev_pool.push_back(t.a);
+    ctx->ev_pool.push_back(t.b);
+  }
+  G->timed.clear();
+  G->timed_nodes.clear();
+  G->next = 0;
   G->captured = false;
 }
 
 int init_state(gsr_ctx* ctx, GraphState* G) {
   HIP_TRY(ctx, hipStreamCreateWithFlags(&G->cap, hipStreamNonBlocking));
   HIP_TRY(ctx, hipEventCreateWithFlags(&G->done, hipEventDisableTiming));
+  for (GraphState::Instance& I : G->inst) HIP_TRY(ctx, hipEventCreateWithFlags(&I.done, hipEventDisableTiming));
   HIP_TRY(ctx, hipHostMalloc((void**)&G->host_stats, sizeof(uint32_t) * kStatWords, hipHostMallocDefault));
   std::memset(G->host_stats, 0, sizeof(uint32_t) * kStatWords);
   RET_IF(ensure(ctx, G->stats, sizeof(uint32_t) * kStatWords));
@@ -123,7 +154,9 @@ int measure_instances(gsr_ctx* ctx, GraphState* G, const float* params, const gs
   RenderPlan& P = G->P;
   P.capacity = std::max<int64_t>(P.capacity, 0);
   RET_IF(size_render(ctx, G->B, P, out, st));
-  launch_fill_u32(as<uint32_t>(G->B.total), 0u, 4, st);
+  ClearList L{};
+  front_clears(G->B, P, L);
+  launch_clear(L, st);
   const uint32_t mask = ctx->profile_mask;
   ctx->profile_mask = 0;
   const int r = launch_front(ctx, G->B, P, params, st);
@@ -166,7 +199,17 @@ int record_iteration(gsr_ctx* ctx, GraphState* G, float* params, float* grad, fl
   Buffers& B = G->B;
   RenderPlan& P = G->P;
   uint32_t* totals = as<uint32_t>(B.total);
-  iteration_begin_kernel<<<1, 64, 0, st>>>(totals);
+  // one clear for everything the iteration accumulates into
+  ClearList L{};
+  front_clears(B, P, L);
+  back_clears(B, P, L);
+  if (loss) L.add(loss, 1);
+  L.add(grad, (int64_t)planes * P.stride);
+  L.add(B.g2.p, P.total * G2_N);
+  {
+    StageTimer tm(ctx, GSR_STAGE_ZERO, st);
+    launch_clear(L, st);
+  }
   CHECK_LAUNCH(ctx);
   RET_IF(launch_front(ctx, B, P, params, st));
   RET_IF(launch_back(ctx, B, P, st));
@@ -175,15 +218,10 @@ int record_iteration(gsr_ctx* ctx, GraphState* G, float* params, float* grad, fl
   {
     StageTimer tm(ctx, GSR_STAGE_LOSS, st);
     launch_loss_l1(as<ViewDesc>(B.views), as<ViewImages>(B.images), as<ViewImages>(G->tdesc),
-                   as<ViewImages>(B.images2), P.nv, maxpix, depth_weight, loss, st);
+                   as<ViewImages>(B.images2), P.nv, maxpix, depth_weight, loss, false, st);
   }
   CHECK_LAUNCH(ctx);
-  {
-    StageTimer tm(ctx, GSR_STAGE_ZERO, st);
-    launch_fill_f32(grad, 0.0f, (int64_t)planes * P.stride, st);
-  }
-  CHECK_LAUNCH(ctx);
-  RET_IF(launch_bwd(ctx, B, P, params, grad, st));
+  RET_IF(launch_bwd(ctx, B, P, params, grad, false, st));
   if (adam) {
     StageTimer tm(ctx, GSR_STAGE_ADAM, st);
     launch_adam(params, grad, adam->m, adam->v, P.num, P.stride, planes, as<float>(G->lrbuf), adam->beta1,
@@ -196,90 +234,67 @@ int record_iteration(gsr_ctx* ctx, GraphState* G, float* params, float* grad, fl
   return GSR_OK;
 }
 
-// Ends the current capture piece at each timed-stage boundary and starts
-// the next; empty pieces are dropped.
-struct Cutter : CaptureHook {
-  gsr_ctx* ctx;
-  GraphState* G;
-  hipError_t err = hipSuccess;
-  Cutter(gsr_ctx* c, GraphState* g) : ctx(c), G(g) {}
-  hipError_t close_piece() {
-    hipGraph_t g = nullptr;
-    hipError_t e = hipStreamEndCapture(G->cap, &g);
-    if (e != hipSuccess) return e;
-    size_t n = 0;
-    e = hipGraphGetNodes(g, nullptr, &n);
-    if (e != hipSuccess || n == 0) {
-      (void)hipGraphDestroy(g);
-      return e;
-    }
-    G->graphs.push_back(g);
-    return hipSuccess;
-  }
-  void cut(int stage, bool end) override {
-    if (err != hipSuccess) return;
-    err = close_piece();
-    if (err != hipSuccess) return;
-    G->marks.push_back(GraphState::Mark{G->graphs.size(), stage, end});
-    err = hipStreamBeginCapture(G->cap, hipStreamCaptureModeThreadLocal);
-  }
-};
-
 int capture(gsr_ctx* ctx, GraphState* G, float* params, float* grad, float* loss, const gsr_adam* adam,
             float depth_weight, int planes) {
-  drop_graph(G);
-  Cutter cutter(ctx, G);
-  HIP_TRY(ctx, hipStreamBeginCapture(G->cap, hipStreamCaptureModeThreadLocal));
-  ctx->capture = &cutter;
-  const int r = record_iteration(ctx, G, params, grad, loss, adam, depth_weight, planes, G->cap);
-  ctx->capture = nullptr;
-  hipError_t e = cutter.err;
-  if (e == hipSuccess) {
-    e = cutter.close_piece();
-  } else {
-    hipGraph_t g = nullptr;
-    (void)hipStreamEndCapture(G->cap, &g);
-    if (g) (void)hipGraphDestroy(g);
+  drop_graph(ctx, G);
+  // events are created before the capture: no event is created while it runs
+  const int want = 4 * (__builtin_popcount(ctx->profile_mask) + 2);
+  while ((int)ctx->ev_pool.size() < want) {
+    hipEvent_t e = nullptr;
+    HIP_TRY(ctx, hipEventCreate(&e));
+    ctx->ev_pool.push_back(e);
   }
+  std::vector<TimedPair> timed;
+  HIP_TRY(ctx, hipStreamBeginCapture(G->cap, hipStreamCaptureModeThreadLocal));
+  ctx->capture_timed = &timed;
+  const int r = record_iteration(ctx, G, params, grad, loss, adam, depth_weight, planes, G->cap);
+  ctx->capture_timed = nullptr;
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(G->cap, &graph);
+  G->timed = timed;
   if (r != GSR_OK || e != hipSuccess) {
-    drop_graph(G);
+    if (graph) (void)hipGraphDestroy(graph);
+    drop_graph(ctx, G);
     (void)hipGetLastError();
     if (r != GSR_OK) return r;
     ctx->hip_err = (int)e;
     return GSR_ERR_HIP;
   }
-  for (hipGraph_t g : G->graphs) {
-    hipGraphExec_t x = nullptr;
-    HIP_TRY(ctx, hipGraphInstantiate(&x, g, nullptr, nullptr, 0));
-    G->execs.push_back(x);
+  G->graph = graph;
+  for (const TimedPair& t : G->timed) {
+    if (!t.na || !t.nb) {
+      ctx->hip_err = (int)hipErrorInvalidValue;
+      return GSR_ERR_HIP;
+    }
+    G->timed_nodes.emplace_back(t.na, t.nb);
+  }
+  // instances, each with its own events (set while no replay can be running)
+  const int ring = G->timed.empty() ? 1 : GraphState::kRing;
+  for (int k = 0; k < ring; ++k) {
+    GraphState::Instance& I = G->inst[k];
+    HIP_TRY(ctx, hipGraphInstantiate(&I.exec, graph, nullptr, nullptr, 0));
+    for (size_t j = 0; j < G->timed.size(); ++j) {
+      hipEvent_t a = take_event(ctx), b = take_event(ctx);
+      if (!a || !b) return GSR_ERR_HIP;
+      I.events.push_back(TimedPair{G->timed[j].stage, a, b});
+      HIP_TRY(ctx, hipGraphExecEventRecordNodeSetEvent(I.exec, G->timed_nodes[j].first, a));
+      HIP_TRY(ctx, hipGraphExecEventRecordNodeSetEvent(I.exec, G->timed_nodes[j].second, b));
+    }
   }
   G->captured = true;
   G->captures += 1;
   return GSR_OK;
 }
 
-// Launches the pieces on `st`, recording a fresh pair of events around every
-// timed stage.
+// Launches the next instance on `st`, after harvesting its previous replay.
 int replay(gsr_ctx* ctx, GraphState* G, hipStream_t st) {
-  hipEvent_t open[GSR_NUM_STAGES] = {};
-  size_t m = 0;
-  for (size_t k = 0; k <= G->execs.size(); ++k) {
-    for (; m < G->marks.size() && G->marks[m].after == k; ++m) {
-      const GraphState::Mark& mk = G->marks[m];
-      hipEvent_t ev = take_event(ctx);
-      if (!ev) return GSR_ERR_HIP;
-      HIP_TRY(ctx, hipEventRecord(ev, st));
-      if (!mk.end) {
-        open[mk.stage] = ev;
-      } else if (open[mk.stage]) {
-        ctx->ev_pending[mk.stage].emplace_back(open[mk.stage], ev);
-        open[mk.stage] = nullptr;
-      } else {
-        ctx->ev_pool.push_back(ev);
-      }
-    }
-    if (k < G->execs.size()) HIP_TRY(ctx, hipGraphLaunch(G->execs[k], st));
-  }
+  const int ring = G->timed.empty() ? 1 : GraphState::kRing;
+  GraphState::Instance& I = G->inst[G->next];
+  G->next = (G->next + 1) % ring;
+  if (!G->timed.empty()) RET_IF(harvest(ctx, I));
+  HIP_TRY(ctx, hipGraphLaunch(I.exec, st));
+  HIP_TRY(ctx, hipEventRecord(I.done, st));
+  I.launched = !G->timed.empty();
   return GSR_OK;
 }
 
@@ -349,7 +364,7 @@ int iteration_impl(gsr_ctx* ctx, float* params, int64_t num, int64_t stride, int
   if (!same) {
     HIP_TRY(ctx, hipStreamSynchronize(st));
     HIP_TRY(ctx, hipDeviceSynchronize());
-    drop_graph(G);
+    drop_graph(ctx, G);
     const int64_t old_cap = G->capacity;
     const bool layout_same = G->num == num && G->deg == deg && G->sizes == sizes && G->P.nv == nv;
     plan.capacity = layout_same ? old_cap : 0;
@@ -421,6 +436,13 @@ int iteration_impl(gsr_ctx* ctx, float* params, int64_t num, int64_t stride, int
 
 }  // namespace
 
+int harvest_graph(gsr_ctx* ctx) {
+  GraphState* G = ctx->graph;
+  if (!G) return GSR_OK;
+  for (GraphState::Instance& I : G->inst) RET_IF(harvest(ctx, I));
+  return GSR_OK;
+}
+
 void destroy_graph(gsr_ctx* ctx) {
   GraphState* G = ctx->graph;
   if (!G) return;
@@ -428,7 +450,7 @@ void destroy_graph(gsr_ctx* ctx) {
     ctx->q_bufs = nullptr;
     ctx->q_plan = nullptr;
   }
-  drop_graph(G);
+  drop_graph(ctx, G);
   free_buffers(G->B);
   DevBuf* bufs[] = {&G->tdesc, &G->gimg, &G->lrbuf, &G->stats};
   for (DevBuf* b : bufs)
@@ -436,6 +458,8 @@ void destroy_graph(gsr_ctx* ctx) {
   if (G->host_stats) (void)hipHostFree(G->host_stats);
   if (G->done) (void)hipEventDestroy(G->done);
   if (G->cap) (void)hipStreamDestroy(G->cap);
+  for (GraphState::Instance& I : G->inst)
+    if (I.done) (void)hipEventDestroy(I.done);
   delete G;
   ctx->graph = nullptr;
 }

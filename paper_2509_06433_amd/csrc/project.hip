@@ -255,7 +255,13 @@ __global__ void __launch_bounds__(256) project_kernel(const float* __restrict__ 
                                                       int num_views, const ViewDesc* __restrict__ views, int tile_w,
                                                       int tile_h, float znear, Splat* __restrict__ splats,
                                                       int4* __restrict__ rect, uint32_t* __restrict__ ntiles,
-                                                      uint32_t* __restrict__ zkey, uint32_t* __restrict__ svals) {
+                                                      uint32_t* __restrict__ zkey, uint32_t* __restrict__ svals,
+                                                      uint32_t* __restrict__ zhist) {
+  // digit histograms of the depth keys for the radix sort that follows
+  __shared__ uint32_t s_hist[4][256];
+  if (zhist)
+    for (int e = threadIdx.x; e < 4 * 256; e += blockDim.x) (&s_hist[0][0])[e] = 0u;
+  __syncthreads();
   const int64_t total = n * (int64_t)num_views;
   for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < total; s += (int64_t)gridDim.x * blockDim.x) {
     const int view = (int)(s / n);
@@ -272,14 +278,14 @@ __global__ void __launch_bounds__(256) project_kernel(const float* __restrict__ 
     }
     svals[s] = (uint32_t)s;
     if (!vis) {
-      Splat z;
-      z.w0 = make_float4(0.f, 0.f, 0.f, 0.f);
-      z.w1 = z.w0;
-      z.w2 = z.w0;
-      splats[s] = z;
+      // no splat record: only listed splats are ever read
       rect[s] = make_int4(0, 0, -1, -1);
       ntiles[s] = 0u;
       zkey[s] = 0xFFFFFFFFu;
+      if (zhist) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) atomicAdd(&s_hist[p][255], 1u);
+      }
       continue;
     }
     Splat sp;
@@ -290,7 +296,19 @@ __global__ void __launch_bounds__(256) project_kernel(const float* __restrict__ 
     rect[s] = make_int4(g.x0, g.y0, g.x1, g.y1);
     const int tx0 = g.x0 / tile_w, tx1 = g.x1 / tile_w, ty0 = g.y0 / tile_h, ty1 = g.y1 / tile_h;
     ntiles[s] = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
-    zkey[s] = __float_as_uint(g.tz);
+    const uint32_t key = __float_as_uint(g.tz);
+    zkey[s] = key;
+    if (zhist) {
+#pragma unroll
+      for (int p = 0; p < 4; ++p) atomicAdd(&s_hist[p][(key >> (8 * p)) & 255u], 1u);
+    }
+  }
+  if (zhist) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < 4 * 256; e += blockDim.x) {
+      const uint32_t c = (&s_hist[0][0])[e];
+      if (c) atomicAdd(zhist + e, c);
+    }
   }
 }
 
@@ -592,10 +610,17 @@ __global__ void export_splats_kernel(const float* __restrict__ P, int64_t n, int
                                      const ViewDesc* __restrict__ view, float znear, const Splat* __restrict__ splats,
                                      const int4* __restrict__ rect, float* __restrict__ out) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const Splat s = splats[i];
     const int4 r = rect[i];
     float* o = out + i * 16;
     const bool vis = r.z >= r.x;
+    Splat s;
+    if (vis) {
+      s = splats[i];
+    } else {
+      s.w0 = make_float4(0.f, 0.f, 0.f, 0.f);
+      s.w1 = s.w0;
+      s.w2 = s.w0;
+    }
     ProjState g;
     const bool geo = vis && project_geometry(P, stride, i, *view, znear, g);
     o[0] = s.w0.x; o[1] = s.w0.y; o[2] = s.w0.z;
@@ -622,11 +647,11 @@ int grid_for(int64_t n, int block) {
 
 void launch_project(const float* params, int64_t n, int64_t stride, int deg, int num_views, const ViewDesc* views,
                     int tile_w, int tile_h, float znear, Splat* splats, int4* rect, uint32_t* ntiles,
-                    uint32_t* zkey, uint32_t* svals, hipStream_t st) {
+                    uint32_t* zkey, uint32_t* svals, uint32_t* zhist, hipStream_t st) {
   const int64_t total = n * num_views;
   if (total == 0) return;
   project_kernel<<<grid_for(total, 256), 256, 0, st>>>(params, n, stride, deg, num_views, views, tile_w, tile_h,
-                                                       znear, splats, rect, ntiles, zkey, svals);
+                                                       znear, splats, rect, ntiles, zkey, svals, zhist);
 }
 
 void launch_project_backward(const float* params, int64_t n, int64_t stride, int deg, int num_views,

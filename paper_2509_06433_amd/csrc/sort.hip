@@ -24,6 +24,7 @@ constexpr int kSortItems = 16;
 constexpr int kSortChunk = kSortThreads * kSortItems;      // 4096
 constexpr int kWaveChunk = 64 * kSortItems;                // 1024 keys per wave
 constexpr int kRadix = 256;
+constexpr uint32_t kSpinLimit = 1u << 20;   // bounded waits of the look-back kernels
 
 int blocks_for(int64_t n, int chunk) { return (int)((n + chunk - 1) / chunk); }
 
@@ -61,43 +62,26 @@ __device__ __forceinline__ uint32_t load_gather(const uint32_t* in, const uint32
   return idx ? in[idx[j]] : in[j];
 }
 
-__global__ void __launch_bounds__(kScanThreads) scan_reduce_kernel(const uint32_t* __restrict__ in,
-                                                                   const uint32_t* __restrict__ idx, int64_t n,
-                                                                   uint32_t* __restrict__ partials) {
-  const int64_t base = (int64_t)blockIdx.x * kScanChunk;
-  uint32_t s = 0;
-#pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    const int64_t j = base + k * kScanThreads + threadIdx.x;
-    if (j < n) s += load_gather(in, idx, j);
-  }
-  uint32_t total;
-  block_excl_scan(s, &total);
-  if (threadIdx.x == 0) partials[blockIdx.x] = total;
-}
+// Single-pass exclusive scan with decoupled look-back. Workgroups take
+// tickets (a lower ticket is always already running), publish their chunk
+// total, and the first wave looks back over the published totals of up to 64
+// predecessors per step until it meets an inclusive prefix. A wait is
+// bounded: past the spin limit the error flag is raised and the scan goes on,
+// so every wave exits. Status word per ticket: flag (1 = chunk total,
+// 2 = inclusive prefix) in the high half, the value in the low half.
+constexpr unsigned long long kScanAgg = 1ull << 32;
+constexpr unsigned long long kScanInc = 2ull << 32;
 
-// Single block: exclusive scan of the partials in place; grand total -> *total.
-__global__ void __launch_bounds__(kScanThreads) scan_partials_kernel(uint32_t* __restrict__ partials, int nparts,
-                                                                     uint32_t* __restrict__ total_out) {
-  uint32_t carry = 0;
-  for (int base = 0; base < nparts; base += kScanThreads) {
-    const int j = base + threadIdx.x;
-    const uint32_t x = j < nparts ? partials[j] : 0u;
-    uint32_t tot;
-    const uint32_t ex = block_excl_scan(x, &tot);
-    if (j < nparts) partials[j] = carry + ex;
-    carry += tot;
-  }
-  if (threadIdx.x == 0 && total_out) *total_out = carry;
-}
-
-__global__ void __launch_bounds__(kScanThreads) scan_down_kernel(const uint32_t* __restrict__ in,
-                                                                 const uint32_t* __restrict__ idx, int64_t n,
-                                                                 const uint32_t* __restrict__ partials,
-                                                                 uint32_t* __restrict__ out) {
-  // blocked arrangement: thread t owns items t*kScanItems .. +kScanItems-1 of the chunk
+__global__ void __launch_bounds__(kScanThreads) scan_lookback_kernel(
+    const uint32_t* __restrict__ in, const uint32_t* __restrict__ idx, int64_t n, uint32_t* __restrict__ out,
+    uint32_t* __restrict__ total_out, unsigned long long* __restrict__ status, uint32_t* __restrict__ ticket,
+    uint32_t* __restrict__ err) {
   __shared__ uint32_t tile[kScanChunk];
-  const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+  __shared__ uint32_t s_bid, s_excl;
+  if (threadIdx.x == 0) s_bid = atomicAdd(ticket, 1u);
+  __syncthreads();
+  const uint32_t bid = s_bid;
+  const int64_t base = (int64_t)bid * kScanChunk;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     const int local = k * kScanThreads + threadIdx.x;
@@ -113,7 +97,51 @@ __global__ void __launch_bounds__(kScanThreads) scan_down_kernel(const uint32_t*
     s += v[k];
   }
   uint32_t tot;
-  uint32_t run = block_excl_scan(s, &tot) + partials[blockIdx.x];
+  const uint32_t ex = block_excl_scan(s, &tot);
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    if (lane == 0)
+      __hip_atomic_store(status + bid, (bid == 0 ? kScanInc : kScanAgg) | tot, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t excl = 0;
+    if (bid > 0) {
+      int64_t p = (int64_t)bid - 1;          // nearest predecessor not yet summed
+      uint32_t spins = 0;
+      while (true) {
+        const int64_t q = p - lane;
+        const unsigned long long w =
+            q >= 0 ? __hip_atomic_load(status + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : kScanInc;
+        const uint32_t flag = (uint32_t)(w >> 32);
+        const uint64_t waiting = __ballot(flag == 0u);
+        const uint64_t inc = __ballot(flag == 2u);
+        const int first_inc = inc ? __ffsll((unsigned long long)inc) - 1 : 64;
+        const uint64_t need = first_inc >= 63 ? ~0ull : ((2ull << first_inc) - 1ull);
+        if (waiting & need) {
+          if (++spins > kSpinLimit) {
+            if (lane == 0) atomicOr(err, 1u);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+          continue;
+        }
+        uint32_t val = (lane <= first_inc) ? (uint32_t)w : 0u;
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) val += __shfl_xor(val, m, 64);
+        excl += val;
+        if (first_inc < 64) break;
+        p -= 64;
+      }
+      if (lane == 0)
+        __hip_atomic_store(status + bid, kScanInc | (unsigned long long)(excl + tot), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (lane == 0) {
+      s_excl = excl;
+      if (bid == gridDim.x - 1 && total_out) *total_out = excl + tot;
+    }
+  }
+  __syncthreads();
+  uint32_t run = s_excl + ex;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     tile[threadIdx.x * kScanItems + k] = run;
@@ -145,7 +173,6 @@ constexpr uint32_t kFlagAgg = 1u << 30;
 constexpr uint32_t kFlagInc = 2u << 30;
 constexpr uint32_t kCountMask = (1u << 30) - 1;
 constexpr int kMaxPasses = 4;
-constexpr uint32_t kSpinLimit = 1u << 20;
 
 __global__ void __launch_bounds__(kSortThreads) global_hist_kernel(const uint32_t* __restrict__ keys,
                                                                    const uint32_t* __restrict__ n_dev, int64_t n_host,
@@ -312,14 +339,20 @@ __global__ void __launch_bounds__(kEmitChunk) emit_kernel(const uint32_t* __rest
                                                          const int4* __restrict__ rect, int64_t count, int64_t n,
                                                          const ViewDesc* __restrict__ views, int tile_w, int tile_h,
                                                          uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
-                                                         int64_t capacity, uint32_t* __restrict__ overflow) {
+                                                         int64_t capacity, uint32_t* __restrict__ overflow,
+                                                         uint32_t* __restrict__ hist, int hist_passes) {
   __shared__ uint32_t s_off[kEmitChunk + 1];
+  __shared__ uint32_t s_hist[2][kRadix];
   __shared__ uint32_t s_sid[kEmitChunk];
   __shared__ int3 s_geo[kEmitChunk];      // first tile id of the rectangle, rectangle width, view row pitch
   const int64_t r0 = (int64_t)blockIdx.x * kEmitChunk;
   const uint32_t total = *total_dev;
   const int tid = threadIdx.x;
   if (blockIdx.x == 0 && tid == 0 && (int64_t)total > capacity) atomicOr(overflow, 1u);
+  if (hist) {
+    s_hist[0][tid] = 0u;
+    s_hist[1][tid] = 0u;
+  }
   const int64_t r = r0 + tid;
   s_off[tid] = r < count ? offsets[r] : total;
   const uint32_t sid = r < count ? sorted_s[r] : 0u;
@@ -347,9 +380,19 @@ __global__ void __launch_bounds__(kEmitChunk) emit_kernel(const uint32_t* __rest
     const uint32_t local = o - s_off[lo];
     const uint32_t dy = local / wdt, dx = local - dy * wdt;
     if ((int64_t)o < capacity) {
-      keys[o] = (uint32_t)geo.x + dy * (uint32_t)geo.z + dx;
+      const uint32_t key = (uint32_t)geo.x + dy * (uint32_t)geo.z + dx;
+      keys[o] = key;
       vals[o] = s_sid[lo];
+      if (hist) {
+        atomicAdd(&s_hist[0][key & (kRadix - 1)], 1u);
+        if (hist_passes > 1) atomicAdd(&s_hist[1][(key >> 8) & (kRadix - 1)], 1u);
+      }
     }
+  }
+  if (hist) {
+    __syncthreads();
+    for (int p = 0; p < hist_passes; ++p)
+      if (s_hist[p][tid]) atomicAdd(&hist[p * kRadix + tid], s_hist[p][tid]);
   }
 }
 
@@ -361,6 +404,23 @@ __global__ void tile_ranges_kernel(const uint32_t* __restrict__ keys, const uint
     if (k >= num_tiles) continue;
     if (i == 0 || keys[i - 1] != k) ranges[k].x = (uint32_t)i;
     if (i == count - 1 || keys[i + 1] != k) ranges[k].y = (uint32_t)(i + 1);
+  }
+}
+
+__global__ void clear_kernel(ClearList L) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  for (int s = 0; s < L.count; ++s) {
+    uint32_t* p = L.p[s];
+    const int64_t n = L.n[s];
+    // 16-byte stores over the aligned body
+    const int64_t head = (int64_t)(((16u - ((uintptr_t)p & 15u)) & 15u) / 4u);
+    const int64_t h = head < n ? head : n;
+    for (int64_t i = t; i < h; i += stride) p[i] = 0u;
+    const int64_t nv = (n - h) / 4;
+    uint4* q = reinterpret_cast<uint4*>(p + h);
+    for (int64_t i = t; i < nv; i += stride) q[i] = make_uint4(0u, 0u, 0u, 0u);
+    for (int64_t i = h + 4 * nv + t; i < n; i += stride) p[i] = 0u;
   }
 }
 
@@ -409,31 +469,38 @@ int64_t radix_scratch_elems(int64_t n) {
   return (int64_t)kMaxPasses * (nb > 0 ? nb : 1) * kRadix + kMaxPasses * kRadix + kMaxPasses;
 }
 
-int64_t scan_partial_elems(int64_t n) { return blocks_for(n > 0 ? n : 1, kScanChunk) + 1; }
+int64_t scan_partial_elems(int64_t n) { return 2 * (int64_t)blocks_for(n > 0 ? n : 1, kScanChunk) + 2; }
+
+uint32_t* radix_hist(uint32_t* scratch, int64_t n) {
+  const int64_t nb = blocks_for(n, kSortChunk);
+  return scratch + (int64_t)kMaxPasses * (nb > 0 ? nb : 1) * kRadix;
+}
 
 void scan_gather_exclusive(const uint32_t* in, const uint32_t* idx, uint32_t* out, int64_t n, uint32_t* total_dev,
-                           uint32_t* partials, hipStream_t st) {
+                           uint32_t* scratch, uint32_t* err, bool clear, hipStream_t st) {
   if (n == 0) {
     if (total_dev) fill_u32_kernel<<<1, 64, 0, st>>>(total_dev, 0u, 1);
     return;
   }
   const int nb = blocks_for(n, kScanChunk);
-  scan_reduce_kernel<<<nb, kScanThreads, 0, st>>>(in, idx, n, partials);
-  scan_partials_kernel<<<1, kScanThreads, 0, st>>>(partials, nb, total_dev);
-  scan_down_kernel<<<nb, kScanThreads, 0, st>>>(in, idx, n, partials, out);
+  if (clear) fill_u32_kernel<<<grid_cap(2 * nb + 2, 256), 256, 0, st>>>(scratch, 0u, 2 * nb + 2);
+  unsigned long long* status = reinterpret_cast<unsigned long long*>(scratch);
+  uint32_t* ticket = scratch + 2 * nb;
+  scan_lookback_kernel<<<nb, kScanThreads, 0, st>>>(in, idx, n, out, total_dev, status, ticket, err);
 }
 
 void radix_sort_pairs(uint32_t*& keys, uint32_t*& vals, uint32_t*& keys_alt, uint32_t*& vals_alt, int64_t n,
-                      const uint32_t* n_dev, int bits, uint32_t* scratch, uint32_t* err, hipStream_t st) {
+                      const uint32_t* n_dev, int bits, uint32_t* scratch, uint32_t* err, bool clear, bool hist_ready,
+                      hipStream_t st) {
   if (n <= 1 || bits <= 0) return;
   const int nb = blocks_for(n, kSortChunk);
   const int passes = (bits + 7) / 8;
   uint32_t* status = scratch;
   uint32_t* ghist = scratch + (int64_t)kMaxPasses * nb * kRadix;
   uint32_t* tickets = ghist + kMaxPasses * kRadix;
-  const int64_t clear = (int64_t)kMaxPasses * nb * kRadix + kMaxPasses * kRadix + kMaxPasses;
-  fill_u32_kernel<<<grid_cap(clear, 256), 256, 0, st>>>(scratch, 0u, clear);
-  global_hist_kernel<<<nb, kSortThreads, 0, st>>>(keys, n_dev, n, passes, ghist);
+  const int64_t clear_n = (int64_t)kMaxPasses * nb * kRadix + kMaxPasses * kRadix + kMaxPasses;
+  if (clear) fill_u32_kernel<<<grid_cap(clear_n, 256), 256, 0, st>>>(scratch, 0u, clear_n);
+  if (!hist_ready) global_hist_kernel<<<nb, kSortThreads, 0, st>>>(keys, n_dev, n, passes, ghist);
   for (int p = 0; p < passes; ++p) {
     onesweep_pass_kernel<<<nb, kSortThreads, 0, st>>>(keys, vals, n_dev, n, 8 * p, ghist + p * kRadix,
                                                       status + (int64_t)p * nb * kRadix, tickets + p, err, keys_alt,
@@ -445,21 +512,32 @@ void radix_sort_pairs(uint32_t*& keys, uint32_t*& vals, uint32_t*& keys_alt, uin
 
 void launch_emit(const uint32_t* sorted_s, const uint32_t* offsets, const uint32_t* total_dev, const int4* rect,
                  int64_t count, int64_t n, const ViewDesc* views, int tile_w, int tile_h, uint32_t* keys,
-                 uint32_t* vals, int64_t capacity, uint32_t* overflow, hipStream_t st) {
+                 uint32_t* vals, int64_t capacity, uint32_t* overflow, uint32_t* hist, int hist_bits,
+                 hipStream_t st) {
   if (count == 0) return;
+  const int hp = (hist_bits + 7) / 8;
   emit_kernel<<<blocks_for(count, kEmitChunk), kEmitChunk, 0, st>>>(sorted_s, offsets, total_dev, rect, count, n,
                                                                      views, tile_w, tile_h, keys, vals, capacity,
-                                                                     overflow);
+                                                                     overflow, hp >= 1 && hp <= 2 ? hist : nullptr,
+                                                                     hp);
 }
 
 void launch_tile_ranges(const uint32_t* keys, const uint32_t* n_dev, int64_t count, uint2* ranges, int64_t num_tiles,
-                        hipStream_t st) {
-  fill_u32_kernel<<<grid_cap(2 * num_tiles, 256), 256, 0, st>>>(reinterpret_cast<uint32_t*>(ranges), 0u,
-                                                                2 * num_tiles);
+                        bool clear, hipStream_t st) {
+  if (clear)
+    fill_u32_kernel<<<grid_cap(2 * num_tiles, 256), 256, 0, st>>>(reinterpret_cast<uint32_t*>(ranges), 0u,
+                                                                  2 * num_tiles);
   if (count == 0) return;
   tile_ranges_kernel<<<grid_cap(count, 256), 256, 0, st>>>(keys, n_dev, count, ranges, num_tiles);
 }
 
+
+void launch_clear(const ClearList& L, hipStream_t st) {
+  int64_t most = 0;
+  for (int k = 0; k < L.count; ++k) most = L.n[k] > most ? L.n[k] : most;
+  if (L.count == 0) return;
+  clear_kernel<<<grid_cap(most / 4 + 1, 256), 256, 0, st>>>(L);
+}
 
 void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st) {
   if (n == 0) return;
