@@ -75,6 +75,8 @@ struct TileShape {
 };
 
 // Front-to-back update of one pixel with one Gaussian whose alpha is known.
+// Branchy on purpose: most pairs are skipped (alpha below 1/255), and a wave
+// whose lanes all skip jumps over the update.
 __device__ __forceinline__ void composite_one(bool ok, float alpha, const float4& q1, const float4& q2, float& T,
                                               float& C0, float& C1, float& C2, float& D, bool& done,
                                               uint32_t& last, uint32_t pos) {
@@ -219,26 +221,44 @@ __device__ __forceinline__ float wave_sum_lane63(float x) {
 // wave sum turns them into (u, v, A, B, C) gradients.
 enum { M_R = 0, M_G, M_B, M_Z, M_O, M_X, M_Y, M_XX, M_XY, M_YY, M_N };
 
-// Reverse step of one pixel over one composited Gaussian: recover T_k,
-// accumulate the pair's moments, update the suffix sum.
+// Reverse step of one pixel over one Gaussian, without branches: recover
+// T_k, form the pair's moments, update the suffix sum. A pair that was not
+// composited (ok false) leaves T and S alone and contributes zero moments;
+// a clamped alpha passes no gradient to opacity or the exponent. FIRST: the
+// moments are assigned (the thread's first pixel) rather than accumulated.
+template <bool FIRST>
 __device__ __forceinline__ void reverse_one(bool ok, float alpha, float G, bool clamped, float dx, float dy,
                                             const float4& q1, const float4& q2, float gc0, float gc1, float gc2,
                                             float gd, float tb, float& T, float& S, float* m) {
-  if (!ok) return;
   const float r1m = __builtin_amdgcn_rcpf(1.0f - alpha);
-  T = T * r1m;                                          // T_k, transmittance before k
-  const float w = alpha * T;
-  m[M_R] = fmaf(w, gc0, m[M_R]);
-  m[M_G] = fmaf(w, gc1, m[M_G]);
-  m[M_B] = fmaf(w, gc2, m[M_B]);
-  m[M_Z] = fmaf(w, gd, m[M_Z]);
+  const float Tk = T * r1m;                              // T_k, transmittance before k
   const float x = fmaf(gc0, q2.x, fmaf(gc1, q2.y, fmaf(gc2, q2.z, gd * q1.z)));
-  const float galpha = fmaf(T, x - S, tb * r1m);
-  S = fmaf(alpha, x, (1.0f - alpha) * S);
-  if (!clamped) {
-    m[M_O] = fmaf(galpha, G, m[M_O]);
-    const float gpow = galpha * alpha;                  // dL/dpower
-    const float gx = gpow * dx, gy = gpow * dy;
+  const float galpha = fmaf(Tk, x - S, tb * r1m);
+  const float Sn = fmaf(alpha, x, (1.0f - alpha) * S);
+  const float w = ok ? alpha * Tk : 0.0f;
+  const bool live = ok && !clamped;
+  const float go = live ? galpha * G : 0.0f;
+  const float gpow = live ? galpha * alpha : 0.0f;     // dL/dpower
+  T = ok ? Tk : T;
+  S = ok ? Sn : S;
+  const float gx = gpow * dx, gy = gpow * dy;
+  if (FIRST) {
+    m[M_R] = w * gc0;
+    m[M_G] = w * gc1;
+    m[M_B] = w * gc2;
+    m[M_Z] = w * gd;
+    m[M_O] = go;
+    m[M_X] = gx;
+    m[M_Y] = gy;
+    m[M_XX] = gx * dx;
+    m[M_XY] = gx * dy;
+    m[M_YY] = gy * dy;
+  } else {
+    m[M_R] = fmaf(w, gc0, m[M_R]);
+    m[M_G] = fmaf(w, gc1, m[M_G]);
+    m[M_B] = fmaf(w, gc2, m[M_B]);
+    m[M_Z] = fmaf(w, gd, m[M_Z]);
+    m[M_O] += go;
     m[M_X] += gx;
     m[M_Y] += gy;
     m[M_XX] = fmaf(gx, dx, m[M_XX]);
@@ -267,11 +287,16 @@ __device__ __forceinline__ void row_sums(float* m) {
 template <int NW, int BATCH>
 __device__ __forceinline__ void publish(float* m, bool any, int lane, int wave, int k,
                                         float (*s_red)[4][M_N][BATCH]) {
-  if (any) row_sums(m);
-  if ((lane & 15) == 15) {
-    const int row = lane >> 4;
+  const int row = lane >> 4;
+  if (any) {
+    row_sums(m);
+    if ((lane & 15) == 15) {
 #pragma unroll
-    for (int c = 0; c < M_N; ++c) s_red[wave][row][c][k] = any ? m[c] : 0.0f;
+      for (int c = 0; c < M_N; ++c) s_red[wave][row][c][k] = m[c];
+    }
+  } else if ((lane & 15) == 15) {
+#pragma unroll
+    for (int c = 0; c < M_N; ++c) s_red[wave][row][c][k] = 0.0f;
   }
 }
 
@@ -349,39 +374,75 @@ blend_backward_kernel(BlendArgs a) {
       const float4 qa0 = s_q0[k], qa1 = s_q1[k], qa2 = s_q2[k];
       const float4 qb0 = s_q0[k - 1], qb1 = s_q1[k - 1], qb2 = s_q2[k - 1];
       float ma[M_N], mb[M_N];
-#pragma unroll
-      for (int c = 0; c < M_N; ++c) ma[c] = mb[c] = 0.0f;
       bool ca = false, cb = false;
+      bool okA[PPT], okB[PPT], clA[PPT], clB[PPT];
+      float alA[PPT], alB[PPT], GA[PPT], GB[PPT], dxA[PPT], dyA[PPT], dxB[PPT], dyB[PPT];
 #pragma unroll
       for (int i = 0; i < PPT; ++i) {
         float dxa, dya, Ga, ala, dxb, dyb, Gb, alb;
         bool cla, clb;
-        const bool oka = (lbase + k < mylast[i]) && pair_alpha(qa0, qa1, xs, ys[i], dxa, dya, Ga, ala, cla);
-        const bool okb = (lbase + k - 1 < mylast[i]) && pair_alpha(qb0, qb1, xs, ys[i], dxb, dyb, Gb, alb, clb);
+        const bool oka = pair_alpha(qa0, qa1, xs, ys[i], dxa, dya, Ga, ala, cla) && (lbase + k < mylast[i]);
+        const bool okb = pair_alpha(qb0, qb1, xs, ys[i], dxb, dyb, Gb, alb, clb) && (lbase + k - 1 < mylast[i]);
         ca = ca || oka;
         cb = cb || okb;
-        reverse_one(oka, ala, Ga, cla, dxa, dya, qa1, qa2, gc0[i], gc1[i], gc2[i], gd[i], tb[i], T[i], S[i], ma);
-        reverse_one(okb, alb, Gb, clb, dxb, dyb, qb1, qb2, gc0[i], gc1[i], gc2[i], gd[i], tb[i], T[i], S[i], mb);
+        okA[i] = oka; okB[i] = okb;
+        alA[i] = ala; alB[i] = alb;
+        GA[i] = Ga; GB[i] = Gb;
+        clA[i] = cla; clB[i] = clb;
+        dxA[i] = dxa; dyA[i] = dya; dxB[i] = dxb; dyB[i] = dyb;
       }
+      // a Gaussian no lane of the wave composited changes nothing: skip it
+      // with a wave-uniform branch
       const bool anya = __ballot(ca) != 0ull, anyb = __ballot(cb) != 0ull;
+      if (anya) {
+#pragma unroll
+        for (int i = 0; i < PPT; ++i) {
+          if (i == 0)
+            reverse_one<true>(okA[i], alA[i], GA[i], clA[i], dxA[i], dyA[i], qa1, qa2, gc0[i], gc1[i], gc2[i], gd[i],
+                              tb[i], T[i], S[i], ma);
+          else
+            reverse_one<false>(okA[i], alA[i], GA[i], clA[i], dxA[i], dyA[i], qa1, qa2, gc0[i], gc1[i], gc2[i],
+                               gd[i], tb[i], T[i], S[i], ma);
+        }
+      }
+      if (anyb) {
+#pragma unroll
+        for (int i = 0; i < PPT; ++i) {
+          if (i == 0)
+            reverse_one<true>(okB[i], alB[i], GB[i], clB[i], dxB[i], dyB[i], qb1, qb2, gc0[i], gc1[i], gc2[i], gd[i],
+                              tb[i], T[i], S[i], mb);
+          else
+            reverse_one<false>(okB[i], alB[i], GB[i], clB[i], dxB[i], dyB[i], qb1, qb2, gc0[i], gc1[i], gc2[i],
+                               gd[i], tb[i], T[i], S[i], mb);
+        }
+      }
       publish<NW, BATCH>(ma, anya, lane, wave, k, s_red);
       publish<NW, BATCH>(mb, anyb, lane, wave, k - 1, s_red);
     }
     if (k == 0) {
       const float4 q0 = s_q0[0], q1 = s_q1[0], q2 = s_q2[0];
       float m[M_N];
-#pragma unroll
-      for (int c = 0; c < M_N; ++c) m[c] = 0.0f;
       bool cc = false;
+      bool okc[PPT], clc[PPT];
+      float alc[PPT], Gc[PPT], dxc[PPT], dyc[PPT];
 #pragma unroll
       for (int i = 0; i < PPT; ++i) {
-        float dx, dy, G, al;
-        bool cl;
-        const bool ok = (lbase < mylast[i]) && pair_alpha(q0, q1, xs, ys[i], dx, dy, G, al, cl);
-        cc = cc || ok;
-        reverse_one(ok, al, G, cl, dx, dy, q1, q2, gc0[i], gc1[i], gc2[i], gd[i], tb[i], T[i], S[i], m);
+        okc[i] = pair_alpha(q0, q1, xs, ys[i], dxc[i], dyc[i], Gc[i], alc[i], clc[i]) && (lbase < mylast[i]);
+        cc = cc || okc[i];
       }
-      publish<NW, BATCH>(m, __ballot(cc) != 0ull, lane, wave, 0, s_red);
+      const bool anyc = __ballot(cc) != 0ull;
+      if (anyc) {
+#pragma unroll
+        for (int i = 0; i < PPT; ++i) {
+          if (i == 0)
+            reverse_one<true>(okc[i], alc[i], Gc[i], clc[i], dxc[i], dyc[i], q1, q2, gc0[i], gc1[i], gc2[i], gd[i],
+                              tb[i], T[i], S[i], m);
+          else
+            reverse_one<false>(okc[i], alc[i], Gc[i], clc[i], dxc[i], dyc[i], q1, q2, gc0[i], gc1[i], gc2[i], gd[i],
+                               tb[i], T[i], S[i], m);
+        }
+      }
+      publish<NW, BATCH>(m, anyc, lane, wave, 0, s_red);
     }
     __syncthreads();
     // sum the row partials of every wave into slot [0][0], then turn the
