@@ -66,7 +66,10 @@ typedef struct gsr_ctx gsr_ctx;
 
 typedef struct {
   int32_t tile_w, tile_h;   /* screen tile; 0 = 16 x 16. Supported: 16x16, 16x8, 8x8, 32x8 */
-  int32_t batch_depth;      /* Gaussians staged in LDS per batch; 0 = tile_w * tile_h */
+  int32_t batch_depth;      /* Gaussians staged in LDS per batch of the backward: 0 (default:
+                               32 for workgroups of 256 threads, else 64), 16, 32 or 64
+                               (capped at the workgroup's thread count). The forward stages
+                               one Gaussian per thread. */
   float bg[3];              /* background colour; default 0 */
   float znear;              /* near-plane cull distance; <= 0 means 0.2 */
   int32_t pixels_per_thread; /* blend kernels: 0 = default (1), 1, or 2 (tiles of >= 128 pixels) */

@@ -148,6 +148,7 @@ int launch_back(gsr_ctx* ctx, Buffers& B, RenderPlan& P, hipStream_t st) {
   ba.ranges = as<uint2>(B.ranges);
   ba.inst_vals = iv;
   ba.splats = as<Splat>(B.splats);
+  ba.rect = as<int4>(B.rect);
   ba.tfinal = as<float>(B.tfinal);
   ba.last = as<uint32_t>(B.last);
   ba.g2 = nullptr;
@@ -176,13 +177,14 @@ int launch_bwd(gsr_ctx* ctx, Buffers& B, const RenderPlan& P, const float* param
   ba.ranges = as<uint2>(B.ranges);
   ba.inst_vals = P.inst_vals;
   ba.splats = as<Splat>(B.splats);
+  ba.rect = as<int4>(B.rect);
   ba.tfinal = as<float>(B.tfinal);
   ba.last = as<uint32_t>(B.last);
   ba.g2 = as<float>(B.g2);
   for (int k = 0; k < 3; ++k) ba.bg[k] = ctx->bg[k];
   {
     StageTimer tm(ctx, GSR_STAGE_BLEND_BWD, st);
-    launch_blend_backward(ba, ctx->tile_w, ctx->tile_h, ctx->ppt, st);
+    launch_blend_backward(ba, ctx->tile_w, ctx->tile_h, ctx->ppt, ctx->batch_depth, st);
   }
   CHECK_LAUNCH(ctx);
   {
@@ -281,10 +283,11 @@ int gsr_create(gsr_ctx** out, const gsr_options* opt) {
       delete ctx;
       return GSR_ERR_UNSUPPORTED;
     }
-    if (opt->batch_depth != 0 && opt->batch_depth != tw * th) {
+    if (!batch_depth_supported(opt->batch_depth)) {
       delete ctx;
       return GSR_ERR_UNSUPPORTED;
     }
+    ctx->batch_depth = opt->batch_depth;
     ctx->tile_w = tw;
     ctx->tile_h = th;
     if (opt->pixels_per_thread < 0 || opt->pixels_per_thread > 2 ||

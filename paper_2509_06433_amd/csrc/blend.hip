@@ -287,27 +287,27 @@ __device__ __forceinline__ void row_sums(float* m) {
 template <int NW, int BATCH>
 __device__ __forceinline__ void publish(float* m, bool any, int lane, int wave, int k,
                                         float (*s_red)[4][M_N][BATCH]) {
+  // the wave's slots start each batch at zero: nothing to write when no lane
+  // composited the Gaussian
+  if (!any) return;
   const int row = lane >> 4;
-  if (any) {
-    row_sums(m);
-    if ((lane & 15) == 15) {
+  row_sums(m);
+  if ((lane & 15) == 15) {
 #pragma unroll
-      for (int c = 0; c < M_N; ++c) s_red[wave][row][c][k] = m[c];
-    }
-  } else if ((lane & 15) == 15) {
-#pragma unroll
-    for (int c = 0; c < M_N; ++c) s_red[wave][row][c][k] = 0.0f;
+    for (int c = 0; c < M_N; ++c) s_red[wave][row][c][k] = m[c];
   }
 }
 
-template <int TW, int TH, int PPT>
+// BATCH: Gaussians staged per round (the batch depth); the row partials take
+// NW * 4 * 10 * BATCH floats of LDS.
+template <int TW, int TH, int PPT, int BATCH>
 __global__ void __launch_bounds__(TW * TH / PPT) __attribute__((amdgpu_waves_per_eu(4)))
 blend_backward_kernel(BlendArgs a) {
   using Shape = TileShape<TW, TH, PPT>;
   constexpr int NT = Shape::NT;
   constexpr int ROWS = Shape::ROWS;
   constexpr int NW = NT / 64;
-  constexpr int BATCH = NW >= 4 ? 32 : 64;      // keeps the row partials at 20 KB of LDS
+  static_assert(BATCH <= NT, "one staged Gaussian per thread");
   __shared__ float4 s_q0[BATCH], s_q1[BATCH], s_q2[BATCH];
   __shared__ uint32_t s_id[BATCH];
   __shared__ float s_red[NW][4][M_N][BATCH];   // moments per (wave, 16-lane row)
@@ -355,6 +355,11 @@ blend_backward_kernel(BlendArgs a) {
     tmax = max(tmax, mylast[i]);
   }
   atomicMax(&s_maxlast, tmax);
+  // list positions at or past the wave's largest last position are skipped
+  uint32_t wmax = tmax;
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) wmax = max(wmax, (uint32_t)__shfl_xor((int)wmax, m, 64));
+  const uint32_t wlast = __builtin_amdgcn_readfirstlane(wmax);
   __syncthreads();
   const uint32_t maxlast = min(s_maxlast, rg.y - rg.x);
   for (int64_t bend = (int64_t)rg.x + maxlast; bend > (int64_t)rg.x; bend -= BATCH) {
@@ -366,11 +371,18 @@ blend_backward_kernel(BlendArgs a) {
       s_id[tid] = sid;
       stage_record(a.splats[sid], s_q0[tid], s_q1[tid], s_q2[tid]);
     }
+    {
+      float* mine = &s_red[wave][0][0][0];
+      for (int e = lane; e < 4 * M_N * BATCH; e += 64) mine[e] = 0.0f;
+    }
     __syncthreads();
     const uint32_t lbase = (uint32_t)(b0 - rg.x);
     int k = cnt - 1;
     for (; k >= 1; k -= 2) {
       // Gaussians k (nearer the back, processed first) and k - 1
+      const bool la = lbase + k < wlast;
+      const bool lb = lbase + k - 1 < wlast;
+      if (!la && !lb) continue;
       const float4 qa0 = s_q0[k], qa1 = s_q1[k], qa2 = s_q2[k];
       const float4 qb0 = s_q0[k - 1], qb1 = s_q1[k - 1], qb2 = s_q2[k - 1];
       float ma[M_N], mb[M_N];
@@ -381,8 +393,9 @@ blend_backward_kernel(BlendArgs a) {
       for (int i = 0; i < PPT; ++i) {
         float dxa, dya, Ga, ala, dxb, dyb, Gb, alb;
         bool cla, clb;
-        const bool oka = pair_alpha(qa0, qa1, xs, ys[i], dxa, dya, Ga, ala, cla) && (lbase + k < mylast[i]);
-        const bool okb = pair_alpha(qb0, qb1, xs, ys[i], dxb, dyb, Gb, alb, clb) && (lbase + k - 1 < mylast[i]);
+        const bool oka = la && pair_alpha(qa0, qa1, xs, ys[i], dxa, dya, Ga, ala, cla) && (lbase + k < mylast[i]);
+        const bool okb =
+            lb && pair_alpha(qb0, qb1, xs, ys[i], dxb, dyb, Gb, alb, clb) && (lbase + k - 1 < mylast[i]);
         ca = ca || oka;
         cb = cb || okb;
         okA[i] = oka; okB[i] = okb;
@@ -419,7 +432,7 @@ blend_backward_kernel(BlendArgs a) {
       publish<NW, BATCH>(ma, anya, lane, wave, k, s_red);
       publish<NW, BATCH>(mb, anyb, lane, wave, k - 1, s_red);
     }
-    if (k == 0) {
+    if (k == 0 && lbase < wlast) {
       const float4 q0 = s_q0[0], q1 = s_q1[0], q2 = s_q2[0];
       float m[M_N];
       bool cc = false;
@@ -488,10 +501,20 @@ void fwd_launch(const BlendArgs& a, int ppt, hipStream_t st) {
   if (ppt == 2 && TW * TH >= 128) blend_forward_kernel<TW, TH, (TW * TH >= 128 ? 2 : 1)><<<a.num_tiles, TW * TH / 2, 0, st>>>(a);
   else blend_forward_kernel<TW, TH, 1><<<a.num_tiles, TW * TH, 0, st>>>(a);
 }
+template <int TW, int TH, int PPT>
+void bwd_launch_depth(const BlendArgs& a, int depth, hipStream_t st) {
+  constexpr int NT = TW * TH / PPT;
+  constexpr int D64 = NT >= 64 ? 64 : NT;
+  if (depth == 0) depth = NT >= 256 ? 32 : 64;
+  if (depth == 16) blend_backward_kernel<TW, TH, PPT, 16><<<a.num_tiles, NT, 0, st>>>(a);
+  else if (depth == 32) blend_backward_kernel<TW, TH, PPT, 32><<<a.num_tiles, NT, 0, st>>>(a);
+  else blend_backward_kernel<TW, TH, PPT, D64><<<a.num_tiles, NT, 0, st>>>(a);
+}
+
 template <int TW, int TH>
-void bwd_launch(const BlendArgs& a, int ppt, hipStream_t st) {
-  if (ppt == 2 && TW * TH >= 128) blend_backward_kernel<TW, TH, (TW * TH >= 128 ? 2 : 1)><<<a.num_tiles, TW * TH / 2, 0, st>>>(a);
-  else blend_backward_kernel<TW, TH, 1><<<a.num_tiles, TW * TH, 0, st>>>(a);
+void bwd_launch(const BlendArgs& a, int ppt, int depth, hipStream_t st) {
+  if (ppt == 2 && TW * TH >= 128) bwd_launch_depth<TW, TH, (TW * TH >= 128 ? 2 : 1)>(a, depth, st);
+  else bwd_launch_depth<TW, TH, 1>(a, depth, st);
 }
 
 __global__ void __launch_bounds__(256) loss_l1_kernel(const ViewDesc* __restrict__ views,
@@ -572,12 +595,14 @@ void launch_blend_forward(const BlendArgs& a, int tile_w, int tile_h, int ppt, h
   else if (tile_w == 32 && tile_h == 8) fwd_launch<32, 8>(a, ppt, st);
 }
 
-void launch_blend_backward(const BlendArgs& a, int tile_w, int tile_h, int ppt, hipStream_t st) {
+bool batch_depth_supported(int depth) { return depth == 0 || depth == 16 || depth == 32 || depth == 64; }
+
+void launch_blend_backward(const BlendArgs& a, int tile_w, int tile_h, int ppt, int depth, hipStream_t st) {
   if (a.num_tiles == 0) return;
-  if (tile_w == 16 && tile_h == 16) bwd_launch<16, 16>(a, ppt, st);
-  else if (tile_w == 16 && tile_h == 8) bwd_launch<16, 8>(a, ppt, st);
-  else if (tile_w == 8 && tile_h == 8) bwd_launch<8, 8>(a, ppt, st);
-  else if (tile_w == 32 && tile_h == 8) bwd_launch<32, 8>(a, ppt, st);
+  if (tile_w == 16 && tile_h == 16) bwd_launch<16, 16>(a, ppt, depth, st);
+  else if (tile_w == 16 && tile_h == 8) bwd_launch<16, 8>(a, ppt, depth, st);
+  else if (tile_w == 8 && tile_h == 8) bwd_launch<8, 8>(a, ppt, depth, st);
+  else if (tile_w == 32 && tile_h == 8) bwd_launch<32, 8>(a, ppt, depth, st);
 }
 
 void launch_loss_l1(const ViewDesc* views, const ViewImages* rendered, const ViewImages* target,

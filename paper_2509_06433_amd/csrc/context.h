@@ -98,6 +98,7 @@ struct gsr_ctx {
   using ViewDesc = gsr::ViewDesc;
   int tile_w = 16, tile_h = 16;
   int ppt = 1;                          // pixels per thread in the blend kernels
+  int batch_depth = 0;                  // backward batch depth (0 = default)
   float bg[3] = {0.f, 0.f, 0.f};
   float znear = 0.2f;
   int hip_err = 0;

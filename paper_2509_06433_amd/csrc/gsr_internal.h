@@ -122,6 +122,7 @@ struct BlendArgs {
   const uint2* ranges;
   const uint32_t* inst_vals;    // splat index per sorted instance
   const Splat* splats;
+  const int4* rect;             // per splat: inclusive pixel rectangle of its binning extent
   float* tfinal;                // per pixel, all views
   uint32_t* last;               // per pixel: index (within the tile list) after the last composited
   float* g2;                    // backward: screen-space gradient accumulators [V*N][10]
@@ -130,7 +131,10 @@ struct BlendArgs {
 bool blend_supported(int tile_w, int tile_h);
 // ppt: pixels per thread (1, or 2 for tiles of at least 128 pixels)
 void launch_blend_forward(const BlendArgs& a, int tile_w, int tile_h, int ppt, hipStream_t st);
-void launch_blend_backward(const BlendArgs& a, int tile_w, int tile_h, int ppt, hipStream_t st);
+// depth: Gaussians per staged batch of the backward (0 = default, 16, 32 or 64;
+// capped at the workgroup's thread count)
+bool batch_depth_supported(int depth);
+void launch_blend_backward(const BlendArgs& a, int tile_w, int tile_h, int ppt, int depth, hipStream_t st);
 // clear_loss = false: the caller has zeroed *loss.
 void launch_loss_l1(const ViewDesc* views, const ViewImages* rendered, const ViewImages* target,
                     const ViewImages* grad, int num_views, int max_pixels, float depth_weight,

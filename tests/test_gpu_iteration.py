@@ -230,3 +230,21 @@ def test_eager_after_iteration_uses_own_buffers(gpu, orc):
     for view in range(2):
         for a, b in zip(outs[view], eo[view]):
             assert torch.equal(a, b)
+
+
+def test_autotuner_picks_a_timed_candidate(gpu, tmp_path, monkeypatch):
+    monkeypatch.setenv("GSR_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
+    from paper_2509_06433_amd import autotune
+    s = two_view_scene(sh_degree=0)
+    targets = targets_for(gpu, s)
+    p = to_dev(s.params)
+    p0 = p.clone()
+    cands = [(16, 16, 1, 0), (16, 8, 2, 32), (8, 8, 1, 64)]
+    res = autotune.tune(p, 0, s.cameras, targets, candidates=cands, warmup=1, steps=2)
+    say(res)
+    assert not res["cached"] and len(res["table"]) == 3
+    assert (res["tile_w"], res["tile_h"], res["pixels_per_thread"], res["batch_depth"]) in cands
+    assert res["ms"] == min(r[4] for r in res["table"]) and res["ms"] > 0
+    assert torch.equal(p, p0)
+    again = autotune.tune(p, 0, s.cameras, targets, candidates=cands)
+    assert again["cached"] and again["tile_w"] == res["tile_w"]

@@ -186,6 +186,19 @@ def test_backward_matches_fp64_oracle(gpu, orc, name, ppt):
     check_grads(g, ref32, name, ref64)
 
 
+@pytest.mark.parametrize("depth", [16, 32, 64])
+def test_backward_batch_depth(gpu, orc, depth):
+    s = CASES["small"]
+    say("batch depth", depth)
+    grads = masked_grads(orc, s, 4)
+    R = make(gpu, batch_depth=depth)
+    p = to_dev(s.params)
+    R.render(p, s.sh_degree, s.cameras)
+    g = R.render_backward(p, s.sh_degree, s.cameras, [tuple(to_dev(x) for x in gv) for gv in grads]).cpu().numpy()
+    ref32, ref64 = oracle_grads(orc, s, s.cameras, grads)
+    check_grads(g, ref32, f"depth {depth}", ref64)
+
+
 def test_backward_multiview_sums(gpu, orc):
     s = scenes.tiny_random(4, n=50, width=40, height=30)
     s.cameras = [s.cameras[0], scenes.look_at_camera([0.3, 0.1, -0.5], [0, 0, 2], 36, 28, 30.0)]
