@@ -37,7 +37,7 @@ int size_instances(gsr_ctx* ctx, Buffers& B, const RenderPlan& P) {
   RET_IF(ensure(ctx, B.ivals, i4));
   RET_IF(ensure(ctx, B.ikeys_alt, i4));
   RET_IF(ensure(ctx, B.ivals_alt, i4));
-  RET_IF(ensure(ctx, B.hist2, sizeof(uint32_t) * (size_t)radix_scratch_elems(P.capacity)));
+  RET_IF(ensure(ctx, B.hist2, sizeof(uint32_t) * (size_t)radix_scratch_elems(P.capacity, bits_for(P.ntiles - 1))));
   return GSR_OK;
 }
 
@@ -63,7 +63,7 @@ int size_render(gsr_ctx* ctx, Buffers& B, RenderPlan& P, const gsr_image* out, h
   RET_IF(ensure(ctx, B.last, sizeof(uint32_t) * (size_t)P.npix));
   RET_IF(ensure(ctx, B.g2, sizeof(float) * G2_N * (size_t)std::max<int64_t>(P.total, 1)));
   RET_IF(ensure(ctx, B.total, 64));
-  RET_IF(ensure(ctx, B.hist, sizeof(uint32_t) * (size_t)radix_scratch_elems(P.total)));
+  RET_IF(ensure(ctx, B.hist, sizeof(uint32_t) * (size_t)radix_scratch_elems(P.total, 32)));
   RET_IF(ensure(ctx, B.partials, sizeof(uint32_t) * (size_t)scan_partial_elems(P.total)));
   RET_IF(upload(ctx, B.views.p, P.views.data(), sizeof(ViewDesc) * nv, st));
   RET_IF(upload(ctx, B.images.p, ims.data(), sizeof(ViewImages) * nv, st));
@@ -73,23 +73,24 @@ int size_render(gsr_ctx* ctx, Buffers& B, RenderPlan& P, const gsr_image* out, h
 void front_clears(Buffers& B, const RenderPlan& P, ClearList& L) {
   L.add(B.total.p, 4);
   L.add(B.partials.p, scan_partial_elems(P.total));
-  if (P.total > 1) L.add(B.hist.p, radix_scratch_elems(P.total));
+  if (P.total > 1) L.add(B.hist.p, radix_scratch_elems(P.total, 32));
 }
 
 void back_clears(Buffers& B, const RenderPlan& P, ClearList& L) {
-  if (P.capacity > 1) L.add(B.hist2.p, radix_scratch_elems(P.capacity));
+  if (P.capacity > 1 && P.ntiles > 1) L.add(B.hist2.p, radix_scratch_elems(P.capacity, bits_for(P.ntiles - 1)));
   L.add(B.ranges.p, 2 * P.ntiles);
 }
 
 int launch_front(gsr_ctx* ctx, Buffers& B, RenderPlan& P, const float* params, hipStream_t st) {
   const int nv = P.nv;
   uint32_t* totals = as<uint32_t>(B.total);
-  uint32_t* zhist = P.total > 1 ? radix_hist(as<uint32_t>(B.hist), P.total) : nullptr;
+  int zrb = 8, zpasses = 0;
+  uint32_t* zhist = P.total > 1 ? radix_hist(as<uint32_t>(B.hist), P.total, 32, &zrb, &zpasses) : nullptr;
   {
     StageTimer tm(ctx, GSR_STAGE_PROJECT, st);
     launch_project(params, P.num, P.stride, P.deg, nv, as<ViewDesc>(B.views), ctx->tile_w, ctx->tile_h, ctx->znear,
                    as<Splat>(B.splats), as<int4>(B.rect), as<uint32_t>(B.ntiles), as<uint32_t>(B.zkey),
-                   as<uint32_t>(B.svals), zhist, st);
+                   as<uint32_t>(B.svals), zhist, zrb, zpasses, st);
   }
   CHECK_LAUNCH(ctx);
   uint32_t* zk = as<uint32_t>(B.zkey);
@@ -118,8 +119,9 @@ int launch_back(gsr_ctx* ctx, Buffers& B, RenderPlan& P, hipStream_t st) {
   uint32_t* ika = as<uint32_t>(B.ikeys_alt);
   uint32_t* iva = as<uint32_t>(B.ivals_alt);
   const int tbits = bits_for(P.ntiles - 1);
-  const bool hist_in_emit = P.capacity > 1 && tbits > 0 && tbits <= 16;
-  uint32_t* thist = hist_in_emit ? radix_hist(as<uint32_t>(B.hist2), P.capacity) : nullptr;
+  const bool hist_in_emit = P.capacity > 1 && tbits > 0 && emit_histogram_fits(tbits);
+  int trb = 8, tpasses = 0;
+  uint32_t* thist = hist_in_emit ? radix_hist(as<uint32_t>(B.hist2), P.capacity, tbits, &trb, &tpasses) : nullptr;
   {
     StageTimer tm(ctx, GSR_STAGE_EMIT, st);
     launch_emit(P.sorted_splats, as<uint32_t>(B.offsets), totals, as<int4>(B.rect), P.total, P.num,

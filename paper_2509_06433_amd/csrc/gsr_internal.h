@@ -45,7 +45,7 @@ constexpr float kTransMin = 1e-4f;
 void launch_project(const float* params, int64_t n, int64_t stride, int deg, int num_views,
                     const ViewDesc* views, int tile_w, int tile_h, float znear, Splat* splats,
                     int4* rect, uint32_t* ntiles, uint32_t* zkey, uint32_t* svals, uint32_t* zhist,
-                    hipStream_t st);
+                    int zrb, int zpasses, hipStream_t st);
 // Chain rule from screen-space gradients g2[V*N][10] to grad_params (+=).
 void launch_project_backward(const float* params, int64_t n, int64_t stride, int deg, int num_views,
                              const ViewDesc* views, float znear, const float* g2, float* grad,
@@ -56,9 +56,11 @@ void launch_export_splats(const float* params, int64_t n, int64_t stride, const 
 
 // ---- sort.hip --------------------------------------------------------------
 // Scratch (uint32 elements) a radix sort of n keys needs.
-int64_t radix_scratch_elems(int64_t n);
+// Scratch (u32 words) of radix_sort_pairs for n elements sorted on `bits` bits.
+int64_t radix_scratch_elems(int64_t n, int bits);
 // Stable LSD radix sort of (keys, vals) on the low `bits` bits of the keys,
-// 8 bits per pass, ping-ponging between the buffers; on return keys/vals point
+// 8 or 11 bits per pass (whichever takes fewer passes), ping-ponging between
+// the buffers; on return keys/vals point
 // at the sorted data and keys_alt/vals_alt at the other pair. The element
 // count is *n_dev when n_dev is not null (n is then the capacity the grid is
 // sized for), else n. *err becomes nonzero if a look-back wait hit its bound
@@ -69,8 +71,12 @@ int64_t radix_scratch_elems(int64_t n);
 void radix_sort_pairs(uint32_t*& keys, uint32_t*& vals, uint32_t*& keys_alt, uint32_t*& vals_alt, int64_t n,
                       const uint32_t* n_dev, int bits, uint32_t* scratch, uint32_t* err, bool clear, bool hist_ready,
                       hipStream_t st);
-// The digit histograms ([passes][256]) inside a sort scratch for n elements.
-uint32_t* radix_hist(uint32_t* scratch, int64_t n);
+// The digit histograms ([passes][2^rb]) inside a sort scratch for n elements
+// sorted on `bits` bits; *rb and *passes receive the digit width and count.
+uint32_t* radix_hist(uint32_t* scratch, int64_t n, int bits, int* rb, int* passes);
+// Whether the emission kernel can accumulate the histograms of a sort on
+// `bits` bits (passes * 2^rb <= 2048).
+bool emit_histogram_fits(int bits);
 // Scan scratch (u32 words) needed by scan_gather_exclusive for n elements.
 int64_t scan_partial_elems(int64_t n);
 // Exclusive scan out[r] = sum_{j<r} in[idx[r]] (idx may be null); total ->
@@ -79,9 +85,9 @@ int64_t scan_partial_elems(int64_t n);
 void scan_gather_exclusive(const uint32_t* in, const uint32_t* idx, uint32_t* out, int64_t n,
                            uint32_t* total_dev, uint32_t* scratch, uint32_t* err, bool clear, hipStream_t st);
 // Instance emission in depth order; writes beyond `capacity` are dropped and
-// set *overflow when the total exceeds it. With hist (and 1 <= ceil(hist_bits
-// / 8) <= 2) the digit histograms of the written tile keys are accumulated
-// there.
+// set *overflow when the total exceeds it. With hist (and
+// emit_histogram_fits(hist_bits)) the digit histograms of the written tile
+// keys, for a sort on hist_bits bits, are accumulated there.
 void launch_emit(const uint32_t* sorted_s, const uint32_t* offsets, const uint32_t* total_dev, const int4* rect,
                  int64_t count, int64_t n, const ViewDesc* views, int tile_w, int tile_h, uint32_t* keys,
                  uint32_t* vals, int64_t capacity, uint32_t* overflow, uint32_t* hist, int hist_bits,

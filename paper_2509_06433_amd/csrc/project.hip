@@ -256,11 +256,13 @@ __global__ void __launch_bounds__(256) project_kernel(const float* __restrict__ 
                                                       int tile_h, float znear, Splat* __restrict__ splats,
                                                       int4* __restrict__ rect, uint32_t* __restrict__ ntiles,
                                                       uint32_t* __restrict__ zkey, uint32_t* __restrict__ svals,
-                                                      uint32_t* __restrict__ zhist) {
+                                                      uint32_t* __restrict__ zhist, int zrb, int zpasses) {
   // digit histograms of the depth keys for the radix sort that follows
-  __shared__ uint32_t s_hist[4][256];
+  // (zpasses digits of zrb bits; zpasses * 2^zrb <= 3 * 2048)
+  __shared__ uint32_t s_hist[3 * 2048];
+  const int zR = 1 << zrb;
   if (zhist)
-    for (int e = threadIdx.x; e < 4 * 256; e += blockDim.x) (&s_hist[0][0])[e] = 0u;
+    for (int e = threadIdx.x; e < zpasses * zR; e += blockDim.x) s_hist[e] = 0u;
   __syncthreads();
   const int64_t total = n * (int64_t)num_views;
   for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < total; s += (int64_t)gridDim.x * blockDim.x) {
@@ -282,10 +284,8 @@ __global__ void __launch_bounds__(256) project_kernel(const float* __restrict__ 
       rect[s] = make_int4(0, 0, -1, -1);
       ntiles[s] = 0u;
       zkey[s] = 0xFFFFFFFFu;
-      if (zhist) {
-#pragma unroll
-        for (int p = 0; p < 4; ++p) atomicAdd(&s_hist[p][255], 1u);
-      }
+      if (zhist)
+        for (int p = 0; p < zpasses; ++p) atomicAdd(&s_hist[p * zR + ((0xFFFFFFFFu >> (zrb * p)) & (zR - 1))], 1u);
       continue;
     }
     Splat sp;
@@ -298,15 +298,13 @@ __global__ void __launch_bounds__(256) project_kernel(const float* __restrict__ 
     ntiles[s] = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
     const uint32_t key = __float_as_uint(g.tz);
     zkey[s] = key;
-    if (zhist) {
-#pragma unroll
-      for (int p = 0; p < 4; ++p) atomicAdd(&s_hist[p][(key >> (8 * p)) & 255u], 1u);
-    }
+    if (zhist)
+      for (int p = 0; p < zpasses; ++p) atomicAdd(&s_hist[p * zR + ((key >> (zrb * p)) & (zR - 1))], 1u);
   }
   if (zhist) {
     __syncthreads();
-    for (int e = threadIdx.x; e < 4 * 256; e += blockDim.x) {
-      const uint32_t c = (&s_hist[0][0])[e];
+    for (int e = threadIdx.x; e < zpasses * zR; e += blockDim.x) {
+      const uint32_t c = s_hist[e];
       if (c) atomicAdd(zhist + e, c);
     }
   }
@@ -647,11 +645,12 @@ int grid_for(int64_t n, int block) {
 
 void launch_project(const float* params, int64_t n, int64_t stride, int deg, int num_views, const ViewDesc* views,
                     int tile_w, int tile_h, float znear, Splat* splats, int4* rect, uint32_t* ntiles,
-                    uint32_t* zkey, uint32_t* svals, uint32_t* zhist, hipStream_t st) {
+                    uint32_t* zkey, uint32_t* svals, uint32_t* zhist, int zrb, int zpasses, hipStream_t st) {
   const int64_t total = n * num_views;
   if (total == 0) return;
+  if (zpasses * (1 << zrb) > 3 * 2048) zhist = nullptr;
   project_kernel<<<grid_for(total, 256), 256, 0, st>>>(params, n, stride, deg, num_views, views, tile_w, tile_h,
-                                                       znear, splats, rect, ntiles, zkey, svals, zhist);
+                                                       znear, splats, rect, ntiles, zkey, svals, zhist, zrb, zpasses);
 }
 
 void launch_project_backward(const float* params, int64_t n, int64_t stride, int deg, int num_views,

@@ -23,7 +23,6 @@ constexpr int kSortThreads = 256;                          // 4 wave64
 constexpr int kSortItems = 16;
 constexpr int kSortChunk = kSortThreads * kSortItems;      // 4096
 constexpr int kWaveChunk = 64 * kSortItems;                // 1024 keys per wave
-constexpr int kRadix = 256;
 constexpr uint32_t kSpinLimit = 1u << 20;   // bounded waits of the look-back kernels
 
 int blocks_for(int64_t n, int chunk) { return (int)((n + chunk - 1) / chunk); }
@@ -157,8 +156,11 @@ __global__ void __launch_bounds__(kScanThreads) scan_lookback_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// Onesweep LSD radix sort, 8-bit digits.
-//   global_hist: digit histograms of every pass in one read of the keys.
+// Onesweep LSD radix sort with RB-bit digits (RB = 8 or 11: 256 or 2048
+// buckets; 11-bit digits sort 32-bit depth keys in 3 passes and up to 2048
+// tiles in one).
+//   global_hist: digit histograms of every pass in one read of the keys
+//                (skipped when the producer of the keys accumulated them).
 //   pass:        one kernel per digit. Workgroups take tickets so that a lower
 //                ticket is always already running; each ranks its 4096 keys
 //                with wave ballots, publishes its per-digit counts, and gets
@@ -166,6 +168,7 @@ __global__ void __launch_bounds__(kScanThreads) scan_lookback_kernel(
 //                counts of lower tickets (decoupled look-back). A wait on a
 //                predecessor is bounded: past the spin limit the workgroup
 //                raises the error flag and goes on, so every wave exits.
+// Each thread owns R / 256 consecutive digits for the per-digit steps.
 // Status word per (ticket, digit): 2 flag bits (1 = count of this workgroup,
 // 2 = inclusive prefix up to this workgroup) over a 30-bit count.
 // ---------------------------------------------------------------------------
@@ -173,50 +176,65 @@ constexpr uint32_t kFlagAgg = 1u << 30;
 constexpr uint32_t kFlagInc = 2u << 30;
 constexpr uint32_t kCountMask = (1u << 30) - 1;
 constexpr int kMaxPasses = 4;
+constexpr int kMaxRadix = 2048;
+
+// Digit width and pass count for a sort on `bits` key bits. 8-bit digits:
+// measured on MI355X, an 11-bit pass (2048 buckets: 8x the published counts
+// and look-back traffic per workgroup) costs about three 8-bit passes, so it
+// never pays for the pass it saves.
+__host__ __device__ inline void radix_plan(int bits, int* rb, int* passes) {
+  *rb = 8;
+  *passes = (bits + 7) / 8;
+}
 
 __global__ void __launch_bounds__(kSortThreads) global_hist_kernel(const uint32_t* __restrict__ keys,
                                                                    const uint32_t* __restrict__ n_dev, int64_t n_host,
-                                                                   int passes, uint32_t* __restrict__ ghist) {
+                                                                   int rb, int passes, uint32_t* __restrict__ ghist) {
   const int64_t n = n_dev ? min((int64_t)*n_dev, n_host) : n_host;
-  __shared__ uint32_t h[kSortThreads / 64][kMaxPasses][kRadix];
-  const int wave = threadIdx.x >> 6;
-  for (int e = threadIdx.x; e < (kSortThreads / 64) * kMaxPasses * kRadix; e += kSortThreads)
-    (&h[0][0][0])[e] = 0;
+  __shared__ uint32_t h[3 * kMaxRadix];          // passes * radix <= 3 * 2048 (11-bit) or 4 * 256 (8-bit)
+  const int R = 1 << rb;
+  for (int e = threadIdx.x; e < passes * R; e += kSortThreads) h[e] = 0;
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * kSortChunk;
   for (int k = 0; k < kSortItems; ++k) {
     const int64_t j = base + k * kSortThreads + threadIdx.x;
     if (j < n) {
       const uint32_t key = keys[j];
-      for (int p = 0; p < passes; ++p) atomicAdd(&h[wave][p][(key >> (8 * p)) & (kRadix - 1)], 1u);
+      for (int p = 0; p < passes; ++p) atomicAdd(&h[p * R + ((key >> (rb * p)) & (R - 1))], 1u);
     }
   }
   __syncthreads();
-  for (int p = 0; p < passes; ++p) {
-    uint32_t c = 0;
-#pragma unroll
-    for (int w = 0; w < kSortThreads / 64; ++w) c += h[w][p][threadIdx.x];
-    if (c) atomicAdd(&ghist[p * kRadix + threadIdx.x], c);
-  }
+  for (int e = threadIdx.x; e < passes * R; e += kSortThreads)
+    if (h[e]) atomicAdd(&ghist[e], h[e]);
 }
 
+template <int RB>
 __global__ void __launch_bounds__(kSortThreads) onesweep_pass_kernel(
     const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals, const uint32_t* __restrict__ n_dev,
     int64_t n_host, int shift, const uint32_t* __restrict__ ghist, uint32_t* __restrict__ status,
     uint32_t* __restrict__ ticket, uint32_t* __restrict__ err, uint32_t* __restrict__ keys_out,
     uint32_t* __restrict__ vals_out) {
-  __shared__ uint32_t wcnt[kSortThreads / 64][kRadix];
-  __shared__ uint32_t gofs[kRadix];        // global start of each digit's run of this block
-  __shared__ uint32_t lstart[kRadix];      // block-local start of each digit's run
-  __shared__ uint32_t s_keys[kSortChunk], s_vals[kSortChunk];
+  constexpr int R = 1 << RB;
+  constexpr int NW = kSortThreads / 64;
+  constexpr int DPT = R / kSortThreads;          // digits owned per thread
+  static_assert(R % kSortThreads == 0, "whole digits per thread");
+  // wcnt (per-wave digit counts) is dead once each key has its block-local
+  // offset; the staged keys and values reuse its storage
+  static_assert(NW * R >= 2 * kSortChunk || RB == 8, "staging fits in the count storage");
+  constexpr int kCountWords = NW * R > 2 * kSortChunk ? NW * R : 2 * kSortChunk;
+  __shared__ uint32_t s_mem[kCountWords];
+  __shared__ uint32_t gofs[R];         // global start of each digit's run of this block (minus its local start)
+  __shared__ uint32_t lstart[R];       // block-local start of each digit's run
   __shared__ uint32_t s_bid;
-  __shared__ uint32_t s_wsum[2][kSortThreads / 64];
+  __shared__ uint32_t s_wsum[2][NW];
+  uint32_t (*wcnt)[R] = reinterpret_cast<uint32_t (*)[R]>(s_mem);
+  uint32_t* s_keys = s_mem;
+  uint32_t* s_vals = s_mem + kSortChunk;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int d0 = threadIdx.x;                       // the digit this thread publishes and looks back for
+  const int tid = threadIdx.x;
   const int64_t n = n_dev ? min((int64_t)*n_dev, n_host) : n_host;
-  if (threadIdx.x == 0) s_bid = atomicAdd(ticket, 1u);
-#pragma unroll
-  for (int w = 0; w < kSortThreads / 64; ++w) wcnt[w][threadIdx.x] = 0;
+  if (tid == 0) s_bid = atomicAdd(ticket, 1u);
+  for (int e = tid; e < NW * R; e += kSortThreads) (&wcnt[0][0])[e] = 0;
   __syncthreads();
   const uint32_t bid = s_bid;
   const int64_t base = (int64_t)bid * kSortChunk + (int64_t)wave * kWaveChunk;
@@ -229,10 +247,10 @@ __global__ void __launch_bounds__(kSortThreads) onesweep_pass_kernel(
     const uint32_t key = valid ? keys[j] : 0u;
     k_reg[r] = key;
     v_reg[r] = valid ? vals[j] : 0u;
-    const uint32_t d = (key >> shift) & (kRadix - 1);
+    const uint32_t d = (key >> shift) & (R - 1);
     uint64_t mask = __ballot(valid);
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
+    for (int b = 0; b < RB; ++b) {
       const bool bit = (d >> b) & 1u;
       const uint64_t bal = __ballot(bit);
       mask &= bit ? bal : ~bal;
@@ -244,25 +262,41 @@ __global__ void __launch_bounds__(kSortThreads) onesweep_pass_kernel(
     __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
-  // per digit: wave prefixes in place, block count
-  uint32_t mine = 0;
+  // owned digits: wave prefixes in place, block counts, aggregates published
+  uint32_t mine[DPT];
 #pragma unroll
-  for (int w = 0; w < kSortThreads / 64; ++w) {
-    const uint32_t c = wcnt[w][d0];
-    wcnt[w][d0] = mine;
-    mine += c;
+  for (int t = 0; t < DPT; ++t) {
+    const int d = tid * DPT + t;
+    uint32_t acc = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      const uint32_t c = wcnt[w][d];
+      wcnt[w][d] = acc;
+      acc += c;
+    }
+    mine[t] = acc;
+    __hip_atomic_store(status + (size_t)bid * R + d, (bid == 0 ? kFlagInc : kFlagAgg) | acc, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
   }
-  uint32_t* st = status + (size_t)bid * kRadix + d0;
-  __hip_atomic_store(st, (bid == 0 ? kFlagInc : kFlagAgg) | mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  // exclusive prefix over lower tickets
-  uint32_t excl = 0;
+  // exclusive prefixes over lower tickets, all owned digits walking together
+  uint32_t excl[DPT];
+#pragma unroll
+  for (int t = 0; t < DPT; ++t) excl[t] = 0;
   if (bid > 0) {
+    uint32_t pending = (DPT == 32 ? ~0u : ((1u << DPT) - 1u));
     int64_t p = (int64_t)bid - 1;
     uint32_t spins = 0;
-    while (p >= 0) {
-      const uint32_t v = __hip_atomic_load(status + (size_t)p * kRadix + d0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      const uint32_t flag = v & ~kCountMask;
-      if (flag == 0u) {
+    while (pending && p >= 0) {
+      uint32_t v[DPT];
+      bool wait = false;
+#pragma unroll
+      for (int t = 0; t < DPT; ++t) {
+        v[t] = ((pending >> t) & 1u)
+                   ? __hip_atomic_load(status + (size_t)p * R + tid * DPT + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                   : kFlagInc;
+        wait = wait || ((v[t] & ~kCountMask) == 0u);
+      }
+      if (wait) {
         if (++spins > kSpinLimit) {
           atomicOr(err, 1u);
           break;
@@ -270,17 +304,31 @@ __global__ void __launch_bounds__(kSortThreads) onesweep_pass_kernel(
         __builtin_amdgcn_s_sleep(1);
         continue;
       }
-      excl += v & kCountMask;
-      if (flag == kFlagInc) break;
+#pragma unroll
+      for (int t = 0; t < DPT; ++t) {
+        if (!((pending >> t) & 1u)) continue;
+        excl[t] += v[t] & kCountMask;
+        if ((v[t] & ~kCountMask) == kFlagInc) pending &= ~(1u << t);
+      }
       --p;
     }
-    __hip_atomic_store(st, kFlagInc | (excl + mine), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+    for (int t = 0; t < DPT; ++t)
+      __hip_atomic_store(status + (size_t)bid * R + tid * DPT + t, kFlagInc | (excl[t] + mine[t]), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
   }
-  // exclusive scans over the 256 digits: of the global histogram (start of
+  // exclusive scans over the R digits: of the global histogram (start of
   // each digit in the output) and of this block's counts (local runs)
   {
-    const uint32_t g = ghist[d0];
-    uint32_t x = g, y = mine;
+    uint32_t gs = 0, ms = 0, gpre[DPT], mpre[DPT];
+#pragma unroll
+    for (int t = 0; t < DPT; ++t) {
+      gpre[t] = gs;
+      mpre[t] = ms;
+      gs += ghist[tid * DPT + t];
+      ms += mine[t];
+    }
+    uint32_t x = gs, y = ms;
 #pragma unroll
     for (int dd = 1; dd < 64; dd <<= 1) {
       const uint32_t xs = __shfl_up(x, dd, 64), ys = __shfl_up(y, dd, 64);
@@ -296,31 +344,42 @@ __global__ void __launch_bounds__(kSortThreads) onesweep_pass_kernel(
     __syncthreads();
     uint32_t bx = 0, by = 0;
 #pragma unroll
-    for (int w = 0; w < kSortThreads / 64; ++w) {
+    for (int w = 0; w < NW; ++w) {
       bx += (w < wave) ? s_wsum[0][w] : 0u;
       by += (w < wave) ? s_wsum[1][w] : 0u;
     }
-    lstart[d0] = by + y - mine;
-    gofs[d0] = bx + x - g + excl;
+    const uint32_t gx0 = bx + x - gs, my0 = by + y - ms;
+#pragma unroll
+    for (int t = 0; t < DPT; ++t) {
+      const int d = tid * DPT + t;
+      lstart[d] = my0 + mpre[t];
+      gofs[d] = gx0 + gpre[t] + excl[t] - (my0 + mpre[t]);
+    }
   }
   __syncthreads();
-  // stage the block's keys in LDS in digit order
+  // block-local position of every key, then the count storage becomes the
+  // staging area
+  uint32_t lp[kSortItems];
 #pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
-    if (off[r] == 0xFFFFFFFFu) continue;
-    const uint32_t d = (k_reg[r] >> shift) & (kRadix - 1);
-    const uint32_t lp = lstart[d] + wcnt[wave][d] + off[r];
-    s_keys[lp] = k_reg[r];
-    s_vals[lp] = v_reg[r];
+    const uint32_t d = (k_reg[r] >> shift) & (R - 1);
+    lp[r] = off[r] == 0xFFFFFFFFu ? 0xFFFFFFFFu : lstart[d] + wcnt[wave][d] + off[r];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    if (lp[r] == 0xFFFFFFFFu) continue;
+    s_keys[lp[r]] = k_reg[r];
+    s_vals[lp[r]] = v_reg[r];
   }
   __syncthreads();
   // consecutive threads write consecutive positions of each digit's run
   const int64_t blk0 = (int64_t)bid * kSortChunk;
   const int cnt = (int)(n - blk0 < kSortChunk ? (n - blk0 > 0 ? n - blk0 : 0) : kSortChunk);
-  for (int j = threadIdx.x; j < cnt; j += kSortThreads) {
+  for (int j = tid; j < cnt; j += kSortThreads) {
     const uint32_t key = s_keys[j];
-    const uint32_t d = (key >> shift) & (kRadix - 1);
-    const uint32_t pos = gofs[d] + (uint32_t)j - lstart[d];
+    const uint32_t d = (key >> shift) & (R - 1);
+    const uint32_t pos = gofs[d] + (uint32_t)j;
     if (pos < n) {
       keys_out[pos] = key;
       vals_out[pos] = s_vals[j];
@@ -340,19 +399,18 @@ __global__ void __launch_bounds__(kEmitChunk) emit_kernel(const uint32_t* __rest
                                                          const ViewDesc* __restrict__ views, int tile_w, int tile_h,
                                                          uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
                                                          int64_t capacity, uint32_t* __restrict__ overflow,
-                                                         uint32_t* __restrict__ hist, int hist_passes) {
+                                                         uint32_t* __restrict__ hist, int hist_rb, int hist_passes) {
   __shared__ uint32_t s_off[kEmitChunk + 1];
-  __shared__ uint32_t s_hist[2][kRadix];
+  __shared__ uint32_t s_hist[kMaxRadix];       // hist_passes * 2^hist_rb <= 2048
   __shared__ uint32_t s_sid[kEmitChunk];
   __shared__ int3 s_geo[kEmitChunk];      // first tile id of the rectangle, rectangle width, view row pitch
   const int64_t r0 = (int64_t)blockIdx.x * kEmitChunk;
   const uint32_t total = *total_dev;
   const int tid = threadIdx.x;
   if (blockIdx.x == 0 && tid == 0 && (int64_t)total > capacity) atomicOr(overflow, 1u);
-  if (hist) {
-    s_hist[0][tid] = 0u;
-    s_hist[1][tid] = 0u;
-  }
+  const int hR = 1 << hist_rb;
+  if (hist)
+    for (int e = tid; e < hist_passes * hR; e += kEmitChunk) s_hist[e] = 0u;
   const int64_t r = r0 + tid;
   s_off[tid] = r < count ? offsets[r] : total;
   const uint32_t sid = r < count ? sorted_s[r] : 0u;
@@ -383,16 +441,14 @@ __global__ void __launch_bounds__(kEmitChunk) emit_kernel(const uint32_t* __rest
       const uint32_t key = (uint32_t)geo.x + dy * (uint32_t)geo.z + dx;
       keys[o] = key;
       vals[o] = s_sid[lo];
-      if (hist) {
-        atomicAdd(&s_hist[0][key & (kRadix - 1)], 1u);
-        if (hist_passes > 1) atomicAdd(&s_hist[1][(key >> 8) & (kRadix - 1)], 1u);
-      }
+      if (hist)
+        for (int p = 0; p < hist_passes; ++p) atomicAdd(&s_hist[p * hR + ((key >> (hist_rb * p)) & (hR - 1))], 1u);
     }
   }
   if (hist) {
     __syncthreads();
-    for (int p = 0; p < hist_passes; ++p)
-      if (s_hist[p][tid]) atomicAdd(&hist[p * kRadix + tid], s_hist[p][tid]);
+    for (int e = tid; e < hist_passes * hR; e += kEmitChunk)
+      if (s_hist[e]) atomicAdd(&hist[e], s_hist[e]);
   }
 }
 
@@ -463,17 +519,20 @@ int grid_cap(int64_t n, int block) {
 
 }  // namespace
 
-int64_t radix_scratch_elems(int64_t n) {
+int64_t radix_scratch_elems(int64_t n, int bits) {
+  int rb, passes;
+  radix_plan(bits, &rb, &passes);
   const int64_t nb = blocks_for(n, kSortChunk);
   // status words for every pass, global histograms, tickets
-  return (int64_t)kMaxPasses * (nb > 0 ? nb : 1) * kRadix + kMaxPasses * kRadix + kMaxPasses;
+  return (int64_t)passes * (nb > 0 ? nb : 1) * (1 << rb) + passes * (1 << rb) + kMaxPasses;
 }
 
 int64_t scan_partial_elems(int64_t n) { return 2 * (int64_t)blocks_for(n > 0 ? n : 1, kScanChunk) + 2; }
 
-uint32_t* radix_hist(uint32_t* scratch, int64_t n) {
+uint32_t* radix_hist(uint32_t* scratch, int64_t n, int bits, int* rb, int* passes) {
+  radix_plan(bits, rb, passes);
   const int64_t nb = blocks_for(n, kSortChunk);
-  return scratch + (int64_t)kMaxPasses * (nb > 0 ? nb : 1) * kRadix;
+  return scratch + (int64_t)*passes * (nb > 0 ? nb : 1) * (1 << *rb);
 }
 
 void scan_gather_exclusive(const uint32_t* in, const uint32_t* idx, uint32_t* out, int64_t n, uint32_t* total_dev,
@@ -493,18 +552,25 @@ void radix_sort_pairs(uint32_t*& keys, uint32_t*& vals, uint32_t*& keys_alt, uin
                       const uint32_t* n_dev, int bits, uint32_t* scratch, uint32_t* err, bool clear, bool hist_ready,
                       hipStream_t st) {
   if (n <= 1 || bits <= 0) return;
+  int rb, passes;
+  radix_plan(bits, &rb, &passes);
+  const int R = 1 << rb;
   const int nb = blocks_for(n, kSortChunk);
-  const int passes = (bits + 7) / 8;
   uint32_t* status = scratch;
-  uint32_t* ghist = scratch + (int64_t)kMaxPasses * nb * kRadix;
-  uint32_t* tickets = ghist + kMaxPasses * kRadix;
-  const int64_t clear_n = (int64_t)kMaxPasses * nb * kRadix + kMaxPasses * kRadix + kMaxPasses;
+  uint32_t* ghist = scratch + (int64_t)passes * nb * R;
+  uint32_t* tickets = ghist + passes * R;
+  const int64_t clear_n = radix_scratch_elems(n, bits);
   if (clear) fill_u32_kernel<<<grid_cap(clear_n, 256), 256, 0, st>>>(scratch, 0u, clear_n);
-  if (!hist_ready) global_hist_kernel<<<nb, kSortThreads, 0, st>>>(keys, n_dev, n, passes, ghist);
+  if (!hist_ready) global_hist_kernel<<<nb, kSortThreads, 0, st>>>(keys, n_dev, n, rb, passes, ghist);
   for (int p = 0; p < passes; ++p) {
-    onesweep_pass_kernel<<<nb, kSortThreads, 0, st>>>(keys, vals, n_dev, n, 8 * p, ghist + p * kRadix,
-                                                      status + (int64_t)p * nb * kRadix, tickets + p, err, keys_alt,
-                                                      vals_alt);
+    if (rb == 11)
+      onesweep_pass_kernel<11><<<nb, kSortThreads, 0, st>>>(keys, vals, n_dev, n, rb * p, ghist + p * R,
+                                                            status + (int64_t)p * nb * R, tickets + p, err, keys_alt,
+                                                            vals_alt);
+    else
+      onesweep_pass_kernel<8><<<nb, kSortThreads, 0, st>>>(keys, vals, n_dev, n, rb * p, ghist + p * R,
+                                                           status + (int64_t)p * nb * R, tickets + p, err, keys_alt,
+                                                           vals_alt);
     uint32_t* t = keys; keys = keys_alt; keys_alt = t;
     t = vals; vals = vals_alt; vals_alt = t;
   }
@@ -515,11 +581,18 @@ void launch_emit(const uint32_t* sorted_s, const uint32_t* offsets, const uint32
                  uint32_t* vals, int64_t capacity, uint32_t* overflow, uint32_t* hist, int hist_bits,
                  hipStream_t st) {
   if (count == 0) return;
-  const int hp = (hist_bits + 7) / 8;
+  int rb = 8, hp = 0;
+  if (hist_bits > 0) radix_plan(hist_bits, &rb, &hp);
+  const bool fits = hp >= 1 && hp * (1 << rb) <= kMaxRadix;
   emit_kernel<<<blocks_for(count, kEmitChunk), kEmitChunk, 0, st>>>(sorted_s, offsets, total_dev, rect, count, n,
                                                                      views, tile_w, tile_h, keys, vals, capacity,
-                                                                     overflow, hp >= 1 && hp <= 2 ? hist : nullptr,
-                                                                     hp);
+                                                                     overflow, fits ? hist : nullptr, rb, hp);
+}
+
+bool emit_histogram_fits(int bits) {
+  int rb, hp;
+  radix_plan(bits, &rb, &hp);
+  return bits > 0 && hp * (1 << rb) <= kMaxRadix;
 }
 
 void launch_tile_ranges(const uint32_t* keys, const uint32_t* n_dev, int64_t count, uint2* ranges, int64_t num_tiles,
