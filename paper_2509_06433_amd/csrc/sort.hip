@@ -282,7 +282,45 @@ __global__ void __launch_bounds__(kSortThreads) onesweep_pass_kernel(
   uint32_t excl[DPT];
 #pragma unroll
   for (int t = 0; t < DPT; ++t) excl[t] = 0;
-  if (bid > 0) {
+  if (bid > 0 && DPT == 1) {
+    // one digit per thread: read kLookChunk predecessors per round trip and
+    // take them in order until an inclusive prefix; an entry not yet
+    // published stops the round, which is retried from there
+    constexpr int kLookChunk = 16;
+    int64_t p = (int64_t)bid - 1;
+    uint32_t spins = 0;
+    const int d = tid;
+    while (true) {
+      uint32_t v[kLookChunk];
+#pragma unroll
+      for (int q = 0; q < kLookChunk; ++q)
+        v[q] = p - q >= 0 ? __hip_atomic_load(status + (size_t)(p - q) * R + d, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT)
+                          : kFlagInc;
+      int used = 0;
+      bool found = false;
+#pragma unroll
+      for (int q = 0; q < kLookChunk; ++q) {
+        if (found || used < q) continue;
+        const uint32_t flag = v[q] & ~kCountMask;
+        if (flag == 0u) continue;
+        excl[0] += v[q] & kCountMask;
+        used = q + 1;
+        found = flag == kFlagInc;
+      }
+      if (found) break;
+      p -= used;
+      if (used < kLookChunk) {
+        if (++spins > kSpinLimit) {
+          atomicOr(err, 1u);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+    __hip_atomic_store(status + (size_t)bid * R + d, kFlagInc | (excl[0] + mine[0]), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  } else if (bid > 0) {
     uint32_t pending = (DPT == 32 ? ~0u : ((1u << DPT) - 1u));
     int64_t p = (int64_t)bid - 1;
     uint32_t spins = 0;
