@@ -362,14 +362,32 @@ blend_backward_kernel(BlendArgs a) {
   const uint32_t wlast = __builtin_amdgcn_readfirstlane(wmax);
   __syncthreads();
   const uint32_t maxlast = min(s_maxlast, rg.y - rg.x);
+  // the next (earlier) batch's record is loaded into registers while this
+  // one is processed, so its global latency overlaps the arithmetic
+  uint32_t nsid = 0;
+  Splat nxt;
+  {
+    const int64_t bend = (int64_t)rg.x + maxlast;
+    const int64_t b0 = bend - BATCH > (int64_t)rg.x ? bend - BATCH : (int64_t)rg.x;
+    if (bend > (int64_t)rg.x && tid < (int)(bend - b0)) {
+      nsid = a.inst_vals[b0 + tid];
+      nxt = a.splats[nsid];
+    }
+  }
   for (int64_t bend = (int64_t)rg.x + maxlast; bend > (int64_t)rg.x; bend -= BATCH) {
     const int64_t b0 = bend - BATCH > (int64_t)rg.x ? bend - BATCH : (int64_t)rg.x;
     const int cnt = (int)(bend - b0);
     __syncthreads();
     if (tid < cnt) {
-      const uint32_t sid = a.inst_vals[b0 + tid];
-      s_id[tid] = sid;
-      stage_record(a.splats[sid], s_q0[tid], s_q1[tid], s_q2[tid]);
+      s_id[tid] = nsid;
+      stage_record(nxt, s_q0[tid], s_q1[tid], s_q2[tid]);
+    }
+    {
+      const int64_t pend = b0, pb0 = pend - BATCH > (int64_t)rg.x ? pend - BATCH : (int64_t)rg.x;
+      if (pend > (int64_t)rg.x && tid < (int)(pend - pb0)) {
+        nsid = a.inst_vals[pb0 + tid];
+        nxt = a.splats[nsid];
+      }
     }
     {
       float* mine = &s_red[wave][0][0][0];
