@@ -61,6 +61,8 @@ def parse():
     ap.add_argument("--tile", default="16x16")
     ap.add_argument("--ppt", type=int, default=0, help="pixels per thread in the blend kernels (0 = default)")
     ap.add_argument("--batch-depth", type=int, default=0, help="backward batch depth (0 = default)")
+    ap.add_argument("--tile-order", type=int, default=0,
+                    help="0 = automatic, 1 = longest tile lists first, 2 = tile order")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use --tile/--ppt/--batch-depth instead of the autotuner's choice")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -106,7 +108,8 @@ def main():
     scene = scenes.WORKLOADS[args.workload]()
     cams = scene.cameras
     deg = scene.sh_degree
-    R = Rasterizer(tile_w=tw, tile_h=th, pixels_per_thread=args.ppt, batch_depth=args.batch_depth)
+    R = Rasterizer(tile_w=tw, tile_h=th, pixels_per_thread=args.ppt, batch_depth=args.batch_depth,
+                   tile_order=args.tile_order)
     dev = torch.device("cuda:0")
     if args.calibrate_copy:
         src = torch.ones(64 * 1024 * 1024, device=dev)
@@ -139,7 +142,7 @@ def main():
                               log=(lambda msg: print(msg, file=sys.stderr)) if args.breakdown else None)
         R.close()
         R = Rasterizer(tile_w=tuned["tile_w"], tile_h=tuned["tile_h"], pixels_per_thread=tuned["pixels_per_thread"],
-                       batch_depth=tuned["batch_depth"])
+                       batch_depth=tuned["batch_depth"], tile_order=args.tile_order)
         outs = R.alloc_images(cams, dev)
     from paper_2509_06433_amd import _lib
     adam = dict(m=m, v=v, lr=lrs, beta1=0.9, beta2=0.999, eps=1e-15) if use_adam else None
@@ -243,7 +246,7 @@ def main():
                    "resolutions": sorted({f"{c.width}x{c.height}" for c in cams}),
                    "gaussians": scene.num, "sh_degree": deg, "tile": f"{R.tile_w}x{R.tile_h}",
                    "pixels_per_thread": R.pixels_per_thread or 1, "batch_depth": R.batch_depth or "default",
-                   "autotuned": tuned is not None,
+                   "autotuned": tuned is not None, "tile_order": ["auto", "longest first", "index"][R.tile_order],
                    "adam": use_adam, "mode": args.mode,
                    f"{other}_iters_s": round(1000.0 / other_ms, 3) if other_ms else None,
                    "render_mpix_s": round(mpix, 2) if mpix else None,

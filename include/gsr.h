@@ -73,6 +73,9 @@ typedef struct {
   float bg[3];              /* background colour; default 0 */
   float znear;              /* near-plane cull distance; <= 0 means 0.2 */
   int32_t pixels_per_thread; /* blend kernels: 0 = default (1), 1, or 2 (tiles of >= 128 pixels) */
+  int32_t tile_order;       /* order in which blend workgroups take tiles: 0 = automatic (longest
+                               list first when several views are rendered together, else
+                               tile order), 1 = longest list first, 2 = tile order */
 } gsr_options;
 
 typedef struct {

@@ -102,7 +102,7 @@ __global__ void __launch_bounds__(TW * TH / PPT) blend_forward_kernel(BlendArgs 
   constexpr int ROWS = Shape::ROWS;
   constexpr int BATCH = NT;
   __shared__ float4 s_q0[BATCH], s_q1[BATCH], s_q2[BATCH];
-  const int tile = blockIdx.x;
+  const int tile = a.order ? (int)a.order[blockIdx.x] : (int)blockIdx.x;
   const int view = find_view(a.views, a.num_views, tile);
   const ViewDesc& V = a.views[view];
   const int lt = tile - V.tile_offset;
@@ -312,7 +312,7 @@ blend_backward_kernel(BlendArgs a) {
   __shared__ uint32_t s_id[BATCH];
   __shared__ float s_red[NW][4][M_N][BATCH];   // moments per (wave, 16-lane row)
   __shared__ uint32_t s_maxlast;
-  const int tile = blockIdx.x;
+  const int tile = a.order ? (int)a.order[blockIdx.x] : (int)blockIdx.x;
   const int view = find_view(a.views, a.num_views, tile);
   const ViewDesc& V = a.views[view];
   const int lt = tile - V.tile_offset;

@@ -36,7 +36,7 @@ struct Buffers {
   DevBuf views, images, images2;
   DevBuf splats, rect, ntiles, zkey, svals, zkey_alt, svals_alt, offsets;
   DevBuf ikeys, ivals, ikeys_alt, ivals_alt;
-  DevBuf hist, hist2, partials, ranges, tfinal, last, g2;   // hist: depth sort, hist2: tile sort
+  DevBuf hist, hist2, partials, ranges, order, tfinal, last, g2;   // hist: depth sort, hist2: tile sort
   DevBuf total;   // [0] instance count, [1] sort wait expired, [2] instance overflow
 };
 
@@ -99,6 +99,7 @@ struct gsr_ctx {
   int tile_w = 16, tile_h = 16;
   int ppt = 1;                          // pixels per thread in the blend kernels
   int batch_depth = 0;                  // backward batch depth (0 = default)
+  int tile_order = 0;                   // 0 auto, 1 longest list first, 2 tile order
   float bg[3] = {0.f, 0.f, 0.f};
   float znear = 0.2f;
   int hip_err = 0;

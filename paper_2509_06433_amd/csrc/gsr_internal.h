@@ -98,6 +98,11 @@ void launch_emit(const uint32_t* sorted_s, const uint32_t* offsets, const uint32
 void launch_tile_ranges(const uint32_t* keys, const uint32_t* n_dev, int64_t count, uint2* ranges, int64_t num_tiles,
                         bool clear, hipStream_t st);
 
+// order[0..num_tiles) = the tiles by decreasing list length, in classes of
+// equal floor(log2(length)) (order within a class unspecified), so that the
+// longest tiles start first and the tail of a launch holds the short ones.
+void launch_tile_order(const uint2* ranges, int64_t num_tiles, uint32_t* order, hipStream_t st);
+
 // Zeroes up to kMaxClear segments of 32-bit words in one launch.
 constexpr int kMaxClear = 10;
 struct ClearList {
@@ -125,6 +130,7 @@ struct BlendArgs {
   const ViewImages* images;     // forward: outputs; backward: dL/dimage
   int32_t num_views;
   int32_t num_tiles;
+  const uint32_t* order;        // workgroup -> tile (longest lists first); null = identity
   const uint2* ranges;
   const uint32_t* inst_vals;    // splat index per sorted instance
   const Splat* splats;

@@ -501,6 +501,38 @@ __global__ void tile_ranges_kernel(const uint32_t* __restrict__ keys, const uint
   }
 }
 
+// One workgroup: bucket the tiles by floor(log2(list length)), longest class
+// first, with LDS counters.
+constexpr int kOrderThreads = 1024;
+__global__ void __launch_bounds__(kOrderThreads) tile_order_kernel(const uint2* __restrict__ ranges,
+                                                                   int64_t num_tiles, uint32_t* __restrict__ order) {
+  __shared__ uint32_t count[33], cursor[33];
+  const int tid = threadIdx.x;
+  if (tid < 33) count[tid] = 0u;
+  __syncthreads();
+  for (int64_t t = tid; t < num_tiles; t += kOrderThreads) {
+    const uint2 r = ranges[t];
+    const uint32_t len = r.y - r.x;
+    const int cls = len ? 32 - __clz(len) : 0;      // 0 (empty) .. 32
+    atomicAdd(&count[32 - cls], 1u);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t run = 0;
+    for (int c = 0; c < 33; ++c) {
+      cursor[c] = run;
+      run += count[c];
+    }
+  }
+  __syncthreads();
+  for (int64_t t = tid; t < num_tiles; t += kOrderThreads) {
+    const uint2 r = ranges[t];
+    const uint32_t len = r.y - r.x;
+    const int cls = len ? 32 - __clz(len) : 0;
+    order[atomicAdd(&cursor[32 - cls], 1u)] = (uint32_t)t;
+  }
+}
+
 __global__ void clear_kernel(ClearList L) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -642,6 +674,11 @@ void launch_tile_ranges(const uint32_t* keys, const uint32_t* n_dev, int64_t cou
   tile_ranges_kernel<<<grid_cap(count, 256), 256, 0, st>>>(keys, n_dev, count, ranges, num_tiles);
 }
 
+
+void launch_tile_order(const uint2* ranges, int64_t num_tiles, uint32_t* order, hipStream_t st) {
+  if (num_tiles == 0) return;
+  tile_order_kernel<<<1, kOrderThreads, 0, st>>>(ranges, num_tiles, order);
+}
 
 void launch_clear(const ClearList& L, hipStream_t st) {
   int64_t most = 0;

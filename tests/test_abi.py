@@ -44,12 +44,41 @@ def test_status_strings_without_gpu():
     assert _lib.gsr_status_string(12345) == "unknown status"
 
 
-def test_ctypes_struct_layout_matches_header():
+def test_ctypes_struct_layout_matches_header(tmp_path):
+    """Sizes and field offsets of every struct in include/gsr.h, as the C
+    compiler lays them out, against the ctypes mirrors of the binding."""
+    import shutil
+    import subprocess
     from paper_2509_06433_amd import _lib
-    assert ctypes.sizeof(_lib.gsr_camera) == 16 * 4 + 8
-    assert ctypes.sizeof(_lib.gsr_gaussians) == 32
-    assert ctypes.sizeof(_lib.gsr_image) == 24
-    assert ctypes.sizeof(_lib.gsr_options) == 4 * 3 + 12 + 4 + 4
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"gsr_options": _lib.gsr_options, "gsr_camera": _lib.gsr_camera, "gsr_gaussians": _lib.gsr_gaussians,
+               "gsr_image": _lib.gsr_image, "gsr_adam": _lib.gsr_adam, "gsr_mapping_stats": _lib.gsr_mapping_stats}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "gsr.h"', "int main(void) {"]
+    for name, ct in structs.items():
+        lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')
+        for field, _ in ct._fields_:
+            lines.append(f'  printf("{name} {field} %zu\\n", offsetof({name}, {field}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    seen = 0
+    for line in out:
+        parts = line.split()
+        if not parts:
+            continue
+        name, what, value = parts[0], parts[1], int(parts[2])
+        ct = structs[name]
+        if what == "size":
+            assert ctypes.sizeof(ct) == value, (name, ctypes.sizeof(ct), value)
+        else:
+            assert getattr(ct, what).offset == value, (name, what)
+        seen += 1
+    assert seen == sum(1 + len(ct._fields_) for ct in structs.values())
 
 
 def test_product_does_not_import_oracle():
