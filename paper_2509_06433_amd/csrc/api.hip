@@ -65,7 +65,7 @@ int size_render(gsr_ctx* ctx, Buffers& B, RenderPlan& P, const gsr_image* out, h
   RET_IF(ensure(ctx, B.g2, sizeof(float) * G2_N * (size_t)std::max<int64_t>(P.total, 1)));
   RET_IF(ensure(ctx, B.total, 64));
   RET_IF(ensure(ctx, B.hist, sizeof(uint32_t) * (size_t)radix_scratch_elems(P.total, 32)));
-  RET_IF(ensure(ctx, B.partials, sizeof(uint32_t) * (size_t)scan_partial_elems(P.total)));
+  RET_IF(ensure(ctx, B.partials, 2 * sizeof(uint32_t) * (size_t)scan_partial_elems(P.total)));
   RET_IF(upload(ctx, B.views.p, P.views.data(), sizeof(ViewDesc) * nv, st));
   RET_IF(upload(ctx, B.images.p, ims.data(), sizeof(ViewImages) * nv, st));
   return GSR_OK;
@@ -73,7 +73,7 @@ int size_render(gsr_ctx* ctx, Buffers& B, RenderPlan& P, const gsr_image* out, h
 
 void front_clears(Buffers& B, const RenderPlan& P, ClearList& L) {
   L.add(B.total.p, 4);
-  L.add(B.partials.p, scan_partial_elems(P.total));
+  L.add(B.partials.p, 2 * scan_partial_elems(P.total));
   if (P.total > 1) L.add(B.hist.p, radix_scratch_elems(P.total, 32));
 }
 
@@ -98,17 +98,22 @@ int launch_front(gsr_ctx* ctx, Buffers& B, RenderPlan& P, const float* params, h
   uint32_t* sv = as<uint32_t>(B.svals);
   uint32_t* zka = as<uint32_t>(B.zkey_alt);
   uint32_t* sva = as<uint32_t>(B.svals_alt);
+  uint32_t* cscan = as<uint32_t>(B.partials);
+  uint32_t* oscan = cscan + scan_partial_elems(P.total);
   {
+    // only the visible splats (count in totals[3]) are sorted and binned
     StageTimer tm(ctx, GSR_STAGE_DEPTH_SORT, st);
-    radix_sort_pairs(zk, sv, zka, sva, P.total, nullptr, 32, as<uint32_t>(B.hist), totals + 1, false, true, st);
+    launch_compact_visible(as<uint32_t>(B.ntiles), zk, P.total, zka, sva, totals + 3, cscan, totals + 1, false, st);
+    radix_sort_pairs(zka, sva, zk, sv, P.total, totals + 3, 32, as<uint32_t>(B.hist), totals + 1, false, true, st);
   }
   CHECK_LAUNCH(ctx);
   {
     StageTimer tm(ctx, GSR_STAGE_SCAN, st);
-    scan_gather_exclusive(as<uint32_t>(B.ntiles), sv, as<uint32_t>(B.offsets), P.total, totals,
-                          as<uint32_t>(B.partials), totals + 1, false, st);
+    scan_gather_exclusive(as<uint32_t>(B.ntiles), sva, as<uint32_t>(B.offsets), P.total, totals + 3, totals, oscan,
+                          totals + 1, false, st);
   }
   CHECK_LAUNCH(ctx);
+  sv = sva;
   P.sorted_splats = sv;
   return GSR_OK;
 }
@@ -131,7 +136,7 @@ int launch_back(gsr_ctx* ctx, Buffers& B, RenderPlan& P, hipStream_t st) {
   uint32_t* thist = hist_in_emit ? radix_hist(as<uint32_t>(B.hist2), P.capacity, tbits, &trb, &tpasses) : nullptr;
   {
     StageTimer tm(ctx, GSR_STAGE_EMIT, st);
-    launch_emit(P.sorted_splats, as<uint32_t>(B.offsets), totals, as<int4>(B.rect), P.total, P.num,
+    launch_emit(P.sorted_splats, as<uint32_t>(B.offsets), totals, totals + 3, as<int4>(B.rect), P.total, P.num,
                 as<ViewDesc>(B.views), ctx->tile_w, ctx->tile_h, ik, iv, P.capacity, totals + 2, thist, tbits, st);
   }
   CHECK_LAUNCH(ctx);
@@ -202,7 +207,7 @@ int launch_bwd(gsr_ctx* ctx, Buffers& B, const RenderPlan& P, const float* param
   {
     StageTimer tm(ctx, GSR_STAGE_PROJECT_BWD, st);
     launch_project_backward(params, P.num, P.stride, P.deg, P.nv, as<ViewDesc>(B.views), ctx->znear,
-                            as<float>(B.g2), grad_params, st);
+                            as<float>(B.g2), as<uint32_t>(B.ntiles), grad_params, st);
   }
   CHECK_LAUNCH(ctx);
   return GSR_OK;

@@ -47,9 +47,10 @@ void launch_project(const float* params, int64_t n, int64_t stride, int deg, int
                     int4* rect, uint32_t* ntiles, uint32_t* zkey, uint32_t* svals, uint32_t* zhist,
                     int zrb, int zpasses, hipStream_t st);
 // Chain rule from screen-space gradients g2[V*N][10] to grad_params (+=).
+// Only (view, Gaussian) pairs with a nonzero tile count (ntiles[V*N]) are visited.
 void launch_project_backward(const float* params, int64_t n, int64_t stride, int deg, int num_views,
-                             const ViewDesc* views, float znear, const float* g2, float* grad,
-                             hipStream_t st);
+                             const ViewDesc* views, float znear, const float* g2, const uint32_t* ntiles,
+                             float* grad, hipStream_t st);
 // Inspection copy of the splats of one view: out[n][16] (see gsr_copy_splats).
 void launch_export_splats(const float* params, int64_t n, int64_t stride, const ViewDesc* view, float znear,
                           const Splat* splats, const int4* rect, float* out, hipStream_t st);
@@ -79,17 +80,28 @@ uint32_t* radix_hist(uint32_t* scratch, int64_t n, int bits, int* rb, int* passe
 bool emit_histogram_fits(int bits);
 // Scan scratch (u32 words) needed by scan_gather_exclusive for n elements.
 int64_t scan_partial_elems(int64_t n);
-// Exclusive scan out[r] = sum_{j<r} in[idx[r]] (idx may be null); total ->
-// *total_dev. Single pass with decoupled look-back; clear = false: the
-// caller has zeroed the scratch. *err is raised if a bounded wait expired.
+// Exclusive scan out[r] = sum_{j<r} in[idx[r]] (idx may be null) over
+// min(*n_dev, n) elements (n if n_dev is null); total -> *total_dev. Single
+// pass with decoupled look-back; clear = false: the caller has zeroed the
+// scratch (scan_partial_elems(n) words). *err is raised if a bounded wait
+// expired.
 void scan_gather_exclusive(const uint32_t* in, const uint32_t* idx, uint32_t* out, int64_t n,
-                           uint32_t* total_dev, uint32_t* scratch, uint32_t* err, bool clear, hipStream_t st);
+                           const uint32_t* n_dev, uint32_t* total_dev, uint32_t* scratch, uint32_t* err, bool clear,
+                           hipStream_t st);
+// Order-preserving compaction of the n splats with a nonzero tile count:
+// out_keys/out_vals[r] = key and index of the r-th one, *count_out = their
+// number. Same scratch size and semantics as scan_gather_exclusive.
+void launch_compact_visible(const uint32_t* ntiles, const uint32_t* keys, int64_t n, uint32_t* out_keys,
+                            uint32_t* out_vals, uint32_t* count_out, uint32_t* scratch, uint32_t* err, bool clear,
+                            hipStream_t st);
 // Instance emission in depth order; writes beyond `capacity` are dropped and
 // set *overflow when the total exceeds it. With hist (and
 // emit_histogram_fits(hist_bits)) the digit histograms of the written tile
 // keys, for a sort on hist_bits bits, are accumulated there.
-void launch_emit(const uint32_t* sorted_s, const uint32_t* offsets, const uint32_t* total_dev, const int4* rect,
-                 int64_t count, int64_t n, const ViewDesc* views, int tile_w, int tile_h, uint32_t* keys,
+// The depth-sorted splats are sorted_s[0 .. min(*count_dev, count)).
+void launch_emit(const uint32_t* sorted_s, const uint32_t* offsets, const uint32_t* total_dev,
+                 const uint32_t* count_dev, const int4* rect, int64_t count, int64_t n, const ViewDesc* views,
+                 int tile_w, int tile_h, uint32_t* keys,
                  uint32_t* vals, int64_t capacity, uint32_t* overflow, uint32_t* hist, int hist_bits,
                  hipStream_t st);
 // ranges[t] = (start, end) of global tile t in the sorted key array of

@@ -224,6 +224,40 @@ __device__ __forceinline__ bool project_geometry(const float* __restrict__ P, in
   return true;
 }
 
+// Conservative early cull from the mean and the largest scale only: true
+// when the Gaussian is surely behind the near plane or surely projects
+// outside the image, so the full projection (which reads and transforms the
+// rotation and does the correctly rounded arithmetic) can be skipped. The
+// near-plane test repeats the projection's own float operations, so it takes
+// the same decision; the lateral test bounds the extent from above
+//   a <= |row 0 of J|^2 s_max^2 + 0.3 <= (fx / z)^2 (1 + lim_x^2) s_max^2 + 0.3
+// (W is a rotation) and keeps a margin of 1% and a pixel for rounding.
+__device__ __forceinline__ bool surely_culled(const float* __restrict__ P, int64_t stride, int64_t i,
+                                              const ViewDesc& V, float znear) {
+  const float mx = P[0 * stride + i], my = P[1 * stride + i], mz = P[2 * stride + i];
+  const float* W = V.R;
+  float tc[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    float acc = W[r * 3 + 0] * mx + W[r * 3 + 1] * my;
+    acc = acc + W[r * 3 + 2] * mz;
+    tc[r] = acc + V.t[r];
+  }
+  if (!(tc[2] >= znear)) return finitef(tc[2]);         // exactly the projection's near-plane cull
+  const float lmax = fmaxf(fmaxf(P[3 * stride + i], P[4 * stride + i]), P[5 * stride + i]);
+  if (!finitef(lmax) || lmax > 20.0f) return false;
+  const float smax = exp_cw(lmax) * 1.01f;
+  const float iz = 1.0f / tc[2];
+  const float limx = kClampFov * 0.5f * (float)V.width / V.fx, limy = kClampFov * 0.5f * (float)V.height / V.fy;
+  const float jx = V.fx * iz, jy = V.fy * iz;
+  const float ax = jx * jx * (1.0f + limx * limx) * smax * smax + kDilation;
+  const float ay = jy * jy * (1.0f + limy * limy) * smax * smax + kDilation;
+  const float exb = sqrtf(kQMax * ax) * 1.01f + 1.0f, eyb = sqrtf(kQMax * ay) * 1.01f + 1.0f;
+  const float u = V.fx * tc[0] * iz + V.cx, v = V.fy * tc[1] * iz + V.cy;
+  if (!finitef(u) || !finitef(v) || !finitef(exb) || !finitef(eyb)) return false;
+  return (u + exb < 0.0f) || (u - exb > (float)V.width) || (v + eyb < 0.0f) || (v - eyb > (float)V.height);
+}
+
 // Colour of one Gaussian seen from the view (before and after max(0, .)).
 __device__ __forceinline__ void project_colour(const float* __restrict__ P, int64_t stride, int64_t i, int deg,
                                                const ViewDesc& V, float* raw, float* col, float* dir,
@@ -257,8 +291,8 @@ __global__ void __launch_bounds__(256) project_kernel(const float* __restrict__ 
                                                       int4* __restrict__ rect, uint32_t* __restrict__ ntiles,
                                                       uint32_t* __restrict__ zkey, uint32_t* __restrict__ svals,
                                                       uint32_t* __restrict__ zhist, int zrb, int zpasses) {
-  // digit histograms of the depth keys for the radix sort that follows
-  // (zpasses digits of zrb bits; zpasses * 2^zrb <= 3 * 2048)
+  // digit histograms of the visible splats' depth keys for the radix sort
+  // that follows (zpasses digits of zrb bits; zpasses * 2^zrb <= 3 * 2048)
   __shared__ uint32_t s_hist[3 * 2048];
   const int zR = 1 << zrb;
   if (zhist)
@@ -270,7 +304,7 @@ __global__ void __launch_bounds__(256) project_kernel(const float* __restrict__ 
     const int64_t i = s - (int64_t)view * n;
     const ViewDesc& V = views[view];
     ProjState g;
-    bool vis = project_geometry(P, stride, i, V, znear, g);
+    bool vis = !surely_culled(P, stride, i, V, znear) && project_geometry(P, stride, i, V, znear, g);
     float raw[3], col[3], dir[3], dnorm;
     float o = 0.0f;
     if (vis) {
@@ -284,8 +318,6 @@ __global__ void __launch_bounds__(256) project_kernel(const float* __restrict__ 
       rect[s] = make_int4(0, 0, -1, -1);
       ntiles[s] = 0u;
       zkey[s] = 0xFFFFFFFFu;
-      if (zhist)
-        for (int p = 0; p < zpasses; ++p) atomicAdd(&s_hist[p * zR + ((0xFFFFFFFFu >> (zrb * p)) & (zR - 1))], 1u);
       continue;
     }
     Splat sp;
@@ -436,6 +468,7 @@ template <int DEG>
 __global__ void __launch_bounds__(256) project_backward_kernel(const float* __restrict__ P, int64_t n, int64_t stride,
                                                                int num_views, const ViewDesc* __restrict__ views,
                                                                const float* __restrict__ g2,
+                                                               const uint32_t* __restrict__ ntiles,
                                                                float* __restrict__ grad) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -449,8 +482,16 @@ __global__ void __launch_bounds__(256) project_backward_kernel(const float* __re
 #pragma unroll
       for (int ch = 0; ch < 3; ++ch) coef[ch][k] = P[(11 + 3 * k + ch) * stride + i];
     bool touched = false;
-    for (int view = 0; view < num_views; ++view) {
-      const float* gv = g2 + ((int64_t)view * n + i) * G2_N;
+    // Each lane walks its own list of views that see the Gaussian (nonzero
+    // tile count): the wave runs the chain rule once per step of the longest
+    // list, not once per view.
+    int view = 0;
+    while (true) {
+      while (view < num_views && ntiles[(int64_t)view * n + i] == 0u) ++view;
+      if (!__any(view < num_views)) break;
+      if (view >= num_views) continue;
+      const int cur = view++;
+      const float* gv = g2 + ((int64_t)cur * n + i) * G2_N;
       double G[G2_N];
       bool any = false;
 #pragma unroll
@@ -460,7 +501,7 @@ __global__ void __launch_bounds__(256) project_backward_kernel(const float* __re
       }
       if (!any) continue;
       touched = true;
-      const ViewDesc& V = views[view];
+      const ViewDesc& V = views[cur];
       ProjD g;
       geometry_f64(P, stride, i, V, g);
       // opacity
@@ -654,15 +695,16 @@ void launch_project(const float* params, int64_t n, int64_t stride, int deg, int
 }
 
 void launch_project_backward(const float* params, int64_t n, int64_t stride, int deg, int num_views,
-                             const ViewDesc* views, float znear, const float* g2, float* grad, hipStream_t st) {
+                             const ViewDesc* views, float znear, const float* g2, const uint32_t* ntiles, float* grad,
+                             hipStream_t st) {
   (void)znear;
   if (n == 0) return;
   const int gsz = grid_for(n, 256);
   switch (deg) {
-    case 0: project_backward_kernel<0><<<gsz, 256, 0, st>>>(params, n, stride, num_views, views, g2, grad); break;
-    case 1: project_backward_kernel<1><<<gsz, 256, 0, st>>>(params, n, stride, num_views, views, g2, grad); break;
-    case 2: project_backward_kernel<2><<<gsz, 256, 0, st>>>(params, n, stride, num_views, views, g2, grad); break;
-    default: project_backward_kernel<3><<<gsz, 256, 0, st>>>(params, n, stride, num_views, views, g2, grad); break;
+    case 0: project_backward_kernel<0><<<gsz, 256, 0, st>>>(params, n, stride, num_views, views, g2, ntiles, grad); break;
+    case 1: project_backward_kernel<1><<<gsz, 256, 0, st>>>(params, n, stride, num_views, views, g2, ntiles, grad); break;
+    case 2: project_backward_kernel<2><<<gsz, 256, 0, st>>>(params, n, stride, num_views, views, g2, ntiles, grad); break;
+    default: project_backward_kernel<3><<<gsz, 256, 0, st>>>(params, n, stride, num_views, views, g2, ntiles, grad); break;
   }
 }
 

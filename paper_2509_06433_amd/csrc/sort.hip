@@ -72,15 +72,20 @@ constexpr unsigned long long kScanAgg = 1ull << 32;
 constexpr unsigned long long kScanInc = 2ull << 32;
 
 __global__ void __launch_bounds__(kScanThreads) scan_lookback_kernel(
-    const uint32_t* __restrict__ in, const uint32_t* __restrict__ idx, int64_t n, uint32_t* __restrict__ out,
-    uint32_t* __restrict__ total_out, unsigned long long* __restrict__ status, uint32_t* __restrict__ ticket,
-    uint32_t* __restrict__ err) {
+    const uint32_t* __restrict__ in, const uint32_t* __restrict__ idx, const uint32_t* __restrict__ n_dev,
+    int64_t n_host, uint32_t* __restrict__ out, uint32_t* __restrict__ total_out,
+    unsigned long long* __restrict__ status, uint32_t* __restrict__ ticket, uint32_t* __restrict__ err) {
   __shared__ uint32_t tile[kScanChunk];
   __shared__ uint32_t s_bid, s_excl;
+  const int64_t n = n_dev ? min((int64_t)*n_dev, n_host) : n_host;
   if (threadIdx.x == 0) s_bid = atomicAdd(ticket, 1u);
   __syncthreads();
   const uint32_t bid = s_bid;
   const int64_t base = (int64_t)bid * kScanChunk;
+  // workgroups past the element count have nothing to do, and no workgroup
+  // that has looks at them
+  if (base >= n && bid > 0) return;
+  const bool last_block = base + kScanChunk >= n;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     const int local = k * kScanThreads + threadIdx.x;
@@ -136,7 +141,7 @@ __global__ void __launch_bounds__(kScanThreads) scan_lookback_kernel(
     }
     if (lane == 0) {
       s_excl = excl;
-      if (bid == gridDim.x - 1 && total_out) *total_out = excl + tot;
+      if (last_block && total_out) *total_out = excl + tot;
     }
   }
   __syncthreads();
@@ -152,6 +157,91 @@ __global__ void __launch_bounds__(kScanThreads) scan_lookback_kernel(
     const int local = k * kScanThreads + threadIdx.x;
     const int64_t j = base + local;
     if (j < n) out[j] = tile[local];
+  }
+}
+
+// Order-preserving compaction of the visible splats (nonzero tile count):
+// out_keys[r], out_vals[r] = key and index of the r-th visible splat; the
+// count -> *count_out. Single pass with the same ticketed look-back as the
+// scan.
+__global__ void __launch_bounds__(kScanThreads) compact_visible_kernel(
+    const uint32_t* __restrict__ ntiles, const uint32_t* __restrict__ keys, int64_t n,
+    uint32_t* __restrict__ out_keys, uint32_t* __restrict__ out_vals, uint32_t* __restrict__ count_out,
+    unsigned long long* __restrict__ status, uint32_t* __restrict__ ticket, uint32_t* __restrict__ err) {
+  __shared__ uint32_t s_bid, s_excl;
+  __shared__ uint32_t flags[kScanChunk];
+  if (threadIdx.x == 0) s_bid = atomicAdd(ticket, 1u);
+  __syncthreads();
+  const uint32_t bid = s_bid;
+  const int64_t base = (int64_t)bid * kScanChunk;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int local = k * kScanThreads + threadIdx.x;
+    const int64_t j = base + local;
+    flags[local] = (j < n && ntiles[j] != 0u) ? 1u : 0u;
+  }
+  __syncthreads();
+  uint32_t v[kScanItems];
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    v[k] = flags[threadIdx.x * kScanItems + k];
+    s += v[k];
+  }
+  uint32_t tot;
+  const uint32_t ex = block_excl_scan(s, &tot);
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    if (lane == 0)
+      __hip_atomic_store(status + bid, (bid == 0 ? kScanInc : kScanAgg) | tot, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t excl = 0;
+    if (bid > 0) {
+      int64_t p = (int64_t)bid - 1;
+      uint32_t spins = 0;
+      while (true) {
+        const int64_t q = p - lane;
+        const unsigned long long w =
+            q >= 0 ? __hip_atomic_load(status + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : kScanInc;
+        const uint32_t flag = (uint32_t)(w >> 32);
+        const uint64_t waiting = __ballot(flag == 0u);
+        const uint64_t inc = __ballot(flag == 2u);
+        const int first_inc = inc ? __ffsll((unsigned long long)inc) - 1 : 64;
+        const uint64_t need = first_inc >= 63 ? ~0ull : ((2ull << first_inc) - 1ull);
+        if (waiting & need) {
+          if (++spins > kSpinLimit) {
+            if (lane == 0) atomicOr(err, 1u);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+          continue;
+        }
+        uint32_t val = (lane <= first_inc) ? (uint32_t)w : 0u;
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) val += __shfl_xor(val, m, 64);
+        excl += val;
+        if (first_inc < 64) break;
+        p -= 64;
+      }
+      if (lane == 0)
+        __hip_atomic_store(status + bid, kScanInc | (unsigned long long)(excl + tot), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (lane == 0) {
+      s_excl = excl;
+      if (bid == gridDim.x - 1) *count_out = excl + tot;
+    }
+  }
+  __syncthreads();
+  uint32_t run = s_excl + ex;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    if (v[k]) {
+      const int64_t j = base + threadIdx.x * kScanItems + k;
+      out_keys[run] = keys[j];
+      out_vals[run] = (uint32_t)j;
+    }
+    run += v[k];
   }
 }
 
@@ -237,6 +327,9 @@ __global__ void __launch_bounds__(kSortThreads) onesweep_pass_kernel(
   for (int e = tid; e < NW * R; e += kSortThreads) (&wcnt[0][0])[e] = 0;
   __syncthreads();
   const uint32_t bid = s_bid;
+  // workgroups past the element count have nothing to do, and no workgroup
+  // that has looks at them
+  if ((int64_t)bid * kSortChunk >= n && bid > 0) return;
   const int64_t base = (int64_t)bid * kSortChunk + (int64_t)wave * kWaveChunk;
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   uint32_t k_reg[kSortItems], v_reg[kSortItems], off[kSortItems];
@@ -433,7 +526,8 @@ constexpr int kEmitChunk = 256;
 __global__ void __launch_bounds__(kEmitChunk) emit_kernel(const uint32_t* __restrict__ sorted_s,
                                                          const uint32_t* __restrict__ offsets,
                                                          const uint32_t* __restrict__ total_dev,
-                                                         const int4* __restrict__ rect, int64_t count, int64_t n,
+                                                         const uint32_t* __restrict__ count_dev,
+                                                         const int4* __restrict__ rect, int64_t count_host, int64_t n,
                                                          const ViewDesc* __restrict__ views, int tile_w, int tile_h,
                                                          uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
                                                          int64_t capacity, uint32_t* __restrict__ overflow,
@@ -443,6 +537,8 @@ __global__ void __launch_bounds__(kEmitChunk) emit_kernel(const uint32_t* __rest
   __shared__ uint32_t s_sid[kEmitChunk];
   __shared__ int3 s_geo[kEmitChunk];      // first tile id of the rectangle, rectangle width, view row pitch
   const int64_t r0 = (int64_t)blockIdx.x * kEmitChunk;
+  const int64_t count = count_dev ? min((int64_t)*count_dev, count_host) : count_host;
+  if (r0 >= count && blockIdx.x > 0) return;
   const uint32_t total = *total_dev;
   const int tid = threadIdx.x;
   if (blockIdx.x == 0 && tid == 0 && (int64_t)total > capacity) atomicOr(overflow, 1u);
@@ -605,8 +701,9 @@ uint32_t* radix_hist(uint32_t* scratch, int64_t n, int bits, int* rb, int* passe
   return scratch + (int64_t)*passes * (nb > 0 ? nb : 1) * (1 << *rb);
 }
 
-void scan_gather_exclusive(const uint32_t* in, const uint32_t* idx, uint32_t* out, int64_t n, uint32_t* total_dev,
-                           uint32_t* scratch, uint32_t* err, bool clear, hipStream_t st) {
+void scan_gather_exclusive(const uint32_t* in, const uint32_t* idx, uint32_t* out, int64_t n,
+                           const uint32_t* n_dev, uint32_t* total_dev, uint32_t* scratch, uint32_t* err, bool clear,
+                           hipStream_t st) {
   if (n == 0) {
     if (total_dev) fill_u32_kernel<<<1, 64, 0, st>>>(total_dev, 0u, 1);
     return;
@@ -615,7 +712,22 @@ void scan_gather_exclusive(const uint32_t* in, const uint32_t* idx, uint32_t* ou
   if (clear) fill_u32_kernel<<<grid_cap(2 * nb + 2, 256), 256, 0, st>>>(scratch, 0u, 2 * nb + 2);
   unsigned long long* status = reinterpret_cast<unsigned long long*>(scratch);
   uint32_t* ticket = scratch + 2 * nb;
-  scan_lookback_kernel<<<nb, kScanThreads, 0, st>>>(in, idx, n, out, total_dev, status, ticket, err);
+  scan_lookback_kernel<<<nb, kScanThreads, 0, st>>>(in, idx, n_dev, n, out, total_dev, status, ticket, err);
+}
+
+void launch_compact_visible(const uint32_t* ntiles, const uint32_t* keys, int64_t n, uint32_t* out_keys,
+                            uint32_t* out_vals, uint32_t* count_out, uint32_t* scratch, uint32_t* err, bool clear,
+                            hipStream_t st) {
+  if (n == 0) {
+    fill_u32_kernel<<<1, 64, 0, st>>>(count_out, 0u, 1);
+    return;
+  }
+  const int nb = blocks_for(n, kScanChunk);
+  if (clear) fill_u32_kernel<<<grid_cap(2 * nb + 2, 256), 256, 0, st>>>(scratch, 0u, 2 * nb + 2);
+  unsigned long long* status = reinterpret_cast<unsigned long long*>(scratch);
+  uint32_t* ticket = scratch + 2 * nb;
+  compact_visible_kernel<<<nb, kScanThreads, 0, st>>>(ntiles, keys, n, out_keys, out_vals, count_out, status, ticket,
+                                                      err);
 }
 
 void radix_sort_pairs(uint32_t*& keys, uint32_t*& vals, uint32_t*& keys_alt, uint32_t*& vals_alt, int64_t n,
@@ -646,15 +758,17 @@ void radix_sort_pairs(uint32_t*& keys, uint32_t*& vals, uint32_t*& keys_alt, uin
   }
 }
 
-void launch_emit(const uint32_t* sorted_s, const uint32_t* offsets, const uint32_t* total_dev, const int4* rect,
-                 int64_t count, int64_t n, const ViewDesc* views, int tile_w, int tile_h, uint32_t* keys,
+void launch_emit(const uint32_t* sorted_s, const uint32_t* offsets, const uint32_t* total_dev,
+                 const uint32_t* count_dev, const int4* rect, int64_t count, int64_t n, const ViewDesc* views,
+                 int tile_w, int tile_h, uint32_t* keys,
                  uint32_t* vals, int64_t capacity, uint32_t* overflow, uint32_t* hist, int hist_bits,
                  hipStream_t st) {
   if (count == 0) return;
   int rb = 8, hp = 0;
   if (hist_bits > 0) radix_plan(hist_bits, &rb, &hp);
   const bool fits = hp >= 1 && hp * (1 << rb) <= kMaxRadix;
-  emit_kernel<<<blocks_for(count, kEmitChunk), kEmitChunk, 0, st>>>(sorted_s, offsets, total_dev, rect, count, n,
+  emit_kernel<<<blocks_for(count, kEmitChunk), kEmitChunk, 0, st>>>(sorted_s, offsets, total_dev, count_dev, rect,
+                                                                     count, n,
                                                                      views, tile_w, tile_h, keys, vals, capacity,
                                                                      overflow, fits ? hist : nullptr, rb, hp);
 }
