@@ -72,7 +72,7 @@ int size_render(gsr_ctx* ctx, Buffers& B, RenderPlan& P, const gsr_image* out, h
 }
 
 void front_clears(Buffers& B, const RenderPlan& P, ClearList& L) {
-  L.add(B.total.p, 4);
+  L.add(B.total.p, 8);
   L.add(B.partials.p, 2 * scan_partial_elems(P.total));
   if (P.total > 1) L.add(B.hist.p, radix_scratch_elems(P.total, 32));
 }
@@ -90,8 +90,8 @@ int launch_front(gsr_ctx* ctx, Buffers& B, RenderPlan& P, const float* params, h
   {
     StageTimer tm(ctx, GSR_STAGE_PROJECT, st);
     launch_project(params, P.num, P.stride, P.deg, nv, as<ViewDesc>(B.views), ctx->tile_w, ctx->tile_h, ctx->znear,
-                   as<Splat>(B.splats), as<int4>(B.rect), as<uint32_t>(B.ntiles), as<uint32_t>(B.zkey),
-                   as<uint32_t>(B.svals), zhist, zrb, zpasses, st);
+                   as<Splat>(B.splats), as<int4>(B.rect), as<uint32_t>(B.ntiles), as<uint32_t>(B.zkey), zhist, zrb,
+                   zpasses, st);
   }
   CHECK_LAUNCH(ctx);
   uint32_t* zk = as<uint32_t>(B.zkey);

@@ -37,7 +37,7 @@ struct Buffers {
   DevBuf splats, rect, ntiles, zkey, svals, zkey_alt, svals_alt, offsets;
   DevBuf ikeys, ivals, ikeys_alt, ivals_alt;
   DevBuf hist, hist2, partials, ranges, order, tfinal, last, g2;   // hist: depth sort, hist2: tile sort
-  DevBuf total;   // [0] instance count, [1] sort wait expired, [2] instance overflow
+  DevBuf total;   // [0] instance count, [1] wait expired, [2] instance overflow, [3] visible splats
 };
 
 // Sizes and final buffer roles of one forward render.

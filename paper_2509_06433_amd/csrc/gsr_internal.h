@@ -42,12 +42,16 @@ constexpr float kTransMin = 1e-4f;
 // One thread per (view, Gaussian). Writes splats[s], rect[s] (pixel rectangle,
 // inclusive; x1 < x0 when culled), ntiles[s] and depth key zkey[s] (raw float
 // bits of z, 0xFFFFFFFF when culled); s = view * N + i.
+// Projection of every (view, Gaussian) splat into splats, rect, ntiles and
+// zkey (indexed view * n + Gaussian); with zhist the digit histograms of the
+// visible splats' depth keys are accumulated there.
 void launch_project(const float* params, int64_t n, int64_t stride, int deg, int num_views,
                     const ViewDesc* views, int tile_w, int tile_h, float znear, Splat* splats,
-                    int4* rect, uint32_t* ntiles, uint32_t* zkey, uint32_t* svals, uint32_t* zhist,
-                    int zrb, int zpasses, hipStream_t st);
+                    int4* rect, uint32_t* ntiles, uint32_t* zkey, uint32_t* zhist, int zrb, int zpasses,
+                    hipStream_t st);
 // Chain rule from screen-space gradients g2[V*N][10] to grad_params (+=).
-// Only (view, Gaussian) pairs with a nonzero tile count (ntiles[V*N]) are visited.
+// Only (view, Gaussian) pairs with a nonzero tile count (ntiles[V*N]) are
+// visited: one thread per Gaussian walks its own visible views.
 void launch_project_backward(const float* params, int64_t n, int64_t stride, int deg, int num_views,
                              const ViewDesc* views, float znear, const float* g2, const uint32_t* ntiles,
                              float* grad, hipStream_t st);

@@ -285,12 +285,54 @@ __device__ __forceinline__ void project_colour(const float* __restrict__ P, int6
   }
 }
 
+// Projection of one (view, Gaussian) splat s into its records; returns
+// whether it is visible (and then its depth key).
+__device__ __forceinline__ bool project_splat(const float* __restrict__ P, int64_t stride, int deg, int64_t i,
+                                              int64_t s, const ViewDesc& V, int tile_w, int tile_h, float znear,
+                                              bool skip_geometry, Splat* __restrict__ splats, int4* __restrict__ rect,
+                                              uint32_t* __restrict__ ntiles, uint32_t* __restrict__ zkey,
+                                              uint32_t* key_out) {
+  ProjState g;
+  bool vis = !skip_geometry && project_geometry(P, stride, i, V, znear, g);
+  float raw[3], col[3], dir[3], dnorm;
+  float o = 0.0f;
+  if (vis) {
+    o = 1.0f / (1.0f + exp_cw(-P[10 * stride + i]));
+    project_colour(P, stride, i, deg, V, raw, col, dir, &dnorm);
+    vis = finitef(col[0]) && finitef(col[1]) && finitef(col[2]);
+  }
+  if (!vis) {
+    // no splat record: only listed splats are ever read
+    rect[s] = make_int4(0, 0, -1, -1);
+    ntiles[s] = 0u;
+    zkey[s] = 0xFFFFFFFFu;
+    return false;
+  }
+  Splat sp;
+  sp.w0 = make_float4(g.u, g.v, g.tz, o);
+  sp.w1 = make_float4(g.A, g.B, g.C, 0.0f);
+  sp.w2 = make_float4(col[0], col[1], col[2], 0.0f);
+  splats[s] = sp;
+  rect[s] = make_int4(g.x0, g.y0, g.x1, g.y1);
+  const int tx0 = g.x0 / tile_w, tx1 = g.x1 / tile_w, ty0 = g.y0 / tile_h, ty1 = g.y1 / tile_h;
+  ntiles[s] = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+  const uint32_t key = __float_as_uint(g.tz);
+  zkey[s] = key;
+  *key_out = key;
+  return true;
+}
+
+// One view: one thread per Gaussian. Several views: one thread per Gaussian
+// walks its own list of views that may see it (the conservative early cull
+// marks the others), so the full projection runs with the wavefront's lanes
+// busy even where most splats are culled, and the parameter reads stay
+// coalesced.
 __global__ void __launch_bounds__(256) project_kernel(const float* __restrict__ P, int64_t n, int64_t stride, int deg,
                                                       int num_views, const ViewDesc* __restrict__ views, int tile_w,
                                                       int tile_h, float znear, Splat* __restrict__ splats,
                                                       int4* __restrict__ rect, uint32_t* __restrict__ ntiles,
-                                                      uint32_t* __restrict__ zkey, uint32_t* __restrict__ svals,
-                                                      uint32_t* __restrict__ zhist, int zrb, int zpasses) {
+                                                      uint32_t* __restrict__ zkey, uint32_t* __restrict__ zhist,
+                                                      int zrb, int zpasses) {
   // digit histograms of the visible splats' depth keys for the radix sort
   // that follows (zpasses digits of zrb bits; zpasses * 2^zrb <= 3 * 2048)
   __shared__ uint32_t s_hist[3 * 2048];
@@ -298,40 +340,40 @@ __global__ void __launch_bounds__(256) project_kernel(const float* __restrict__ 
   if (zhist)
     for (int e = threadIdx.x; e < zpasses * zR; e += blockDim.x) s_hist[e] = 0u;
   __syncthreads();
-  const int64_t total = n * (int64_t)num_views;
-  for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < total; s += (int64_t)gridDim.x * blockDim.x) {
-    const int view = (int)(s / n);
-    const int64_t i = s - (int64_t)view * n;
-    const ViewDesc& V = views[view];
-    ProjState g;
-    bool vis = !surely_culled(P, stride, i, V, znear) && project_geometry(P, stride, i, V, znear, g);
-    float raw[3], col[3], dir[3], dnorm;
-    float o = 0.0f;
-    if (vis) {
-      o = 1.0f / (1.0f + exp_cw(-P[10 * stride + i]));
-      project_colour(P, stride, i, deg, V, raw, col, dir, &dnorm);
-      vis = finitef(col[0]) && finitef(col[1]) && finitef(col[2]);
-    }
-    svals[s] = (uint32_t)s;
-    if (!vis) {
-      // no splat record: only listed splats are ever read
-      rect[s] = make_int4(0, 0, -1, -1);
-      ntiles[s] = 0u;
-      zkey[s] = 0xFFFFFFFFu;
-      continue;
-    }
-    Splat sp;
-    sp.w0 = make_float4(g.u, g.v, g.tz, o);
-    sp.w1 = make_float4(g.A, g.B, g.C, 0.0f);
-    sp.w2 = make_float4(col[0], col[1], col[2], 0.0f);
-    splats[s] = sp;
-    rect[s] = make_int4(g.x0, g.y0, g.x1, g.y1);
-    const int tx0 = g.x0 / tile_w, tx1 = g.x1 / tile_w, ty0 = g.y0 / tile_h, ty1 = g.y1 / tile_h;
-    ntiles[s] = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
-    const uint32_t key = __float_as_uint(g.tz);
-    zkey[s] = key;
+  auto count_key = [&](uint32_t key) {
     if (zhist)
       for (int p = 0; p < zpasses; ++p) atomicAdd(&s_hist[p * zR + ((key >> (zrb * p)) & (zR - 1))], 1u);
+  };
+  const int64_t stride_t = (int64_t)gridDim.x * blockDim.x;
+  // the loop runs the same number of times on every lane, so the wave-wide
+  // votes below see all lanes
+  for (int64_t i0 = blockIdx.x * (int64_t)blockDim.x; i0 < n; i0 += stride_t) {
+    const int64_t i = i0 + threadIdx.x;
+    const bool mine = i < n;
+    if (num_views == 1) {
+      uint32_t key;
+      if (mine && project_splat(P, stride, deg, i, i, views[0], tile_w, tile_h, znear,
+                                surely_culled(P, stride, i, views[0], znear), splats, rect, ntiles, zkey, &key))
+        count_key(key);
+      continue;
+    }
+    int view = mine ? 0 : num_views;
+    while (true) {
+      while (view < num_views && surely_culled(P, stride, i, views[view], znear)) {
+        const int64_t s = (int64_t)view * n + i;
+        rect[s] = make_int4(0, 0, -1, -1);
+        ntiles[s] = 0u;
+        zkey[s] = 0xFFFFFFFFu;
+        ++view;
+      }
+      if (!__any(view < num_views)) break;
+      if (view >= num_views) continue;
+      const int cur = view++;
+      uint32_t key;
+      if (project_splat(P, stride, deg, i, (int64_t)cur * n + i, views[cur], tile_w, tile_h, znear, false, splats,
+                        rect, ntiles, zkey, &key))
+        count_key(key);
+    }
   }
   if (zhist) {
     __syncthreads();
@@ -464,6 +506,145 @@ __device__ __forceinline__ void sh_dir_grad_d(int deg, double x, double y, doubl
 // Chain rule from the screen-space gradients (u, v, conic, opacity, colour,
 // depth) of every view to the parameters, summed over views, in double.
 // One thread per Gaussian, so the parameter gradients need no atomics.
+// Chain rule of one (view, Gaussian) pair: adds to the Gaussian's parameter
+// gradients (in double) what the pair's screen-space gradient G implies.
+template <int DEG>
+__device__ __forceinline__ void chain_view(const float* __restrict__ P, int64_t stride, int64_t i, const ViewDesc& V,
+                                           const double* G, const float* coef, double* gmean, double* gls,
+                                           double* gq, double& glogit, float* gsh) {
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  ProjD g;
+  geometry_f64(P, stride, i, V, g);
+  // opacity
+  const double o = 1.0 / (1.0 + exp(-(double)P[10 * stride + i]));
+  glogit += G[G2_O] * o * (1.0 - o);
+  // colour
+  double dir[3] = {0.0, 0.0, 0.0}, dnorm = 1.0;
+  if (DEG > 0) {
+    dir[0] = (double)P[0 * stride + i] - (double)V.campos[0];
+    dir[1] = (double)P[1 * stride + i] - (double)V.campos[1];
+    dir[2] = (double)P[2 * stride + i] - (double)V.campos[2];
+    dnorm = sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
+    dir[0] /= dnorm; dir[1] /= dnorm; dir[2] /= dnorm;
+  }
+  double Y[16];
+  sh_basis_d(DEG, dir[0], dir[1], dir[2], Y);
+  double gdir[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) {
+    double cc[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) cc[k] = coef[3 * k + ch];
+    double raw = 0.5;
+#pragma unroll
+    for (int k = 0; k < K; ++k) raw += cc[k] * Y[k];
+    if (raw < 0.0) continue;
+    const double gc = G[G2_R + ch];
+#pragma unroll
+    for (int k = 0; k < K; ++k) gsh[3 * k + ch] += (float)(gc * Y[k]);
+    if (DEG > 0) {
+      double gd[3];
+      sh_dir_grad_d(DEG, dir[0], dir[1], dir[2], cc, gd);
+      gdir[0] += gc * gd[0];
+      gdir[1] += gc * gd[1];
+      gdir[2] += gc * gd[2];
+    }
+  }
+  if (DEG > 0) {
+    const double dot = dir[0] * gdir[0] + dir[1] * gdir[1] + dir[2] * gdir[2];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) gmean[j] += (gdir[j] - dir[j] * dot) / dnorm;
+  }
+  // conic (A, B, C) = (c, -b, a) / det
+  const double a = g.a, b = g.b, c = g.c, det = g.det;
+  const double id = 1.0 / det, id2 = id * id;
+  const double gA = G[G2_A], gB = G[G2_B], gC = G[G2_C];
+  const double ga = (-gA * c * c + gB * b * c - gC * b * b) * id2;
+  const double gb = (2.0 * gA * b * c - 2.0 * gB * b * b + 2.0 * gC * a * b) * id2 - gB * id;
+  const double gc_ = (-gA * b * b + gB * a * b - gC * a * a) * id2;
+  // Sigma' = T Sigma T^T
+  const double* T0 = g.Tm;
+  const double* T1 = g.Tm + 3;
+  const double* S = g.Sig;
+  double ST0[3], ST1[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    ST0[r] = S[r * 3 + 0] * T0[0] + S[r * 3 + 1] * T0[1] + S[r * 3 + 2] * T0[2];
+    ST1[r] = S[r * 3 + 0] * T1[0] + S[r * 3 + 1] * T1[1] + S[r * 3 + 2] * T1[2];
+  }
+  double gT0[3], gT1[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    gT0[r] = 2.0 * ga * ST0[r] + gb * ST1[r];
+    gT1[r] = gb * ST0[r] + 2.0 * gc_ * ST1[r];
+  }
+  double gSS[9];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      gSS[r * 3 + k] = 2.0 * ga * T0[r] * T0[k] + gb * (T0[r] * T1[k] + T1[r] * T0[k]) +
+                       2.0 * gc_ * T1[r] * T1[k];
+  const float* W = V.R;
+  double gJ00 = 0, gJ02 = 0, gJ11 = 0, gJ12 = 0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    gJ00 += gT0[k] * W[k];
+    gJ02 += gT0[k] * W[6 + k];
+    gJ11 += gT1[k] * W[3 + k];
+    gJ12 += gT1[k] * W[6 + k];
+  }
+  const double tx = g.tx, ty = g.ty, tz = g.tz, fx = V.fx, fy = V.fy;
+  const double itz = 1.0 / tz, itz2 = itz * itz;
+  double gtx = 0, gty = 0, gtz = 0;
+  gtz += -gJ00 * fx * itz2 - gJ11 * fy * itz2 + gJ02 * fx * g.xi * itz2 + gJ12 * fy * g.yi * itz2;
+  if (!g.xclamp) {
+    const double gxi = -gJ02 * fx * itz;
+    gtx += gxi * itz;
+    gtz += -gxi * tx * itz2;
+  }
+  if (!g.yclamp) {
+    const double gyi = -gJ12 * fy * itz;
+    gty += gyi * itz;
+    gtz += -gyi * ty * itz2;
+  }
+  gtx += G[G2_U] * fx * itz;
+  gtz += -G[G2_U] * fx * tx * itz2;
+  gty += G[G2_V] * fy * itz;
+  gtz += -G[G2_V] * fy * ty * itz2;
+  gtz += G[G2_Z];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) gmean[j] += W[j] * gtx + W[3 + j] * gty + W[6 + j] * gtz;
+  // Sigma = M M^T, M = R diag(s)
+  double gM[9];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      gM[r * 3 + k] = gSS[r * 3 + 0] * g.M[k] + gSS[r * 3 + 1] * g.M[3 + k] + gSS[r * 3 + 2] * g.M[6 + k];
+  double gR[9];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) gR[r * 3 + k] = gM[r * 3 + k] * g.s[k];
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    gls[k] += (gM[k] * g.R[k] + gM[3 + k] * g.R[3 + k] + gM[6 + k] * g.R[6 + k]) * g.s[k];
+  const double w = g.qh[0], x = g.qh[1], y = g.qh[2], z = g.qh[3];
+  const double gw = 2.0 * (-z * gR[1] + y * gR[2] + z * gR[3] - x * gR[5] - y * gR[6] + x * gR[7]);
+  const double gx = 2.0 * (y * gR[1] + z * gR[2] + y * gR[3] - 2.0 * x * gR[4] - w * gR[5] + z * gR[6] +
+                           w * gR[7] - 2.0 * x * gR[8]);
+  const double gy = 2.0 * (-2.0 * y * gR[0] + x * gR[1] + w * gR[2] + x * gR[3] + z * gR[5] - w * gR[6] +
+                           z * gR[7] - 2.0 * y * gR[8]);
+  const double gz = 2.0 * (-2.0 * z * gR[0] - w * gR[1] + x * gR[2] + w * gR[3] - 2.0 * z * gR[4] +
+                           y * gR[5] + x * gR[6] + y * gR[7]);
+  const double dot = w * gw + x * gx + y * gy + z * gz;
+  gq[0] += (gw - w * dot) / g.qn;
+  gq[1] += (gx - x * dot) / g.qn;
+  gq[2] += (gy - y * dot) / g.qn;
+  gq[3] += (gz - z * dot) / g.qn;
+}
+
 template <int DEG>
 __global__ void __launch_bounds__(256) project_backward_kernel(const float* __restrict__ P, int64_t n, int64_t stride,
                                                                int num_views, const ViewDesc* __restrict__ views,
@@ -473,24 +654,17 @@ __global__ void __launch_bounds__(256) project_backward_kernel(const float* __re
   constexpr int K = (DEG + 1) * (DEG + 1);
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     double gmean[3] = {0, 0, 0}, gls[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, glogit = 0.0;
-    double gsh[3 * K];
+    float gsh[3 * K];          // SH gradients: one term per view, float is enough
 #pragma unroll
-    for (int k = 0; k < 3 * K; ++k) gsh[k] = 0.0;
-    double coef[3][K];
+    for (int k = 0; k < 3 * K; ++k) gsh[k] = 0.0f;
+    float coef[3 * K];         // SH coefficients, read once (float keeps the register footprint down)
 #pragma unroll
-    for (int k = 0; k < K; ++k)
-#pragma unroll
-      for (int ch = 0; ch < 3; ++ch) coef[ch][k] = P[(11 + 3 * k + ch) * stride + i];
+    for (int k = 0; k < 3 * K; ++k) coef[k] = P[(11 + k) * stride + i];
     bool touched = false;
-    // Each lane walks its own list of views that see the Gaussian (nonzero
-    // tile count): the wave runs the chain rule once per step of the longest
-    // list, not once per view.
-    int view = 0;
-    while (true) {
-      while (view < num_views && ntiles[(int64_t)view * n + i] == 0u) ++view;
-      if (!__any(view < num_views)) break;
-      if (view >= num_views) continue;
-      const int cur = view++;
+    // views in lockstep (the view descriptor stays wave-uniform, in scalar
+    // registers); a lane skips the views that do not see its Gaussian
+    for (int cur = 0; cur < num_views; ++cur) {
+      if (ntiles[(int64_t)cur * n + i] == 0u) continue;
       const float* gv = g2 + ((int64_t)cur * n + i) * G2_N;
       double G[G2_N];
       bool any = false;
@@ -502,133 +676,7 @@ __global__ void __launch_bounds__(256) project_backward_kernel(const float* __re
       if (!any) continue;
       touched = true;
       const ViewDesc& V = views[cur];
-      ProjD g;
-      geometry_f64(P, stride, i, V, g);
-      // opacity
-      const double o = 1.0 / (1.0 + exp(-(double)P[10 * stride + i]));
-      glogit += G[G2_O] * o * (1.0 - o);
-      // colour
-      double dir[3] = {0.0, 0.0, 0.0}, dnorm = 1.0;
-      if (DEG > 0) {
-        dir[0] = (double)P[0 * stride + i] - (double)V.campos[0];
-        dir[1] = (double)P[1 * stride + i] - (double)V.campos[1];
-        dir[2] = (double)P[2 * stride + i] - (double)V.campos[2];
-        dnorm = sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
-        dir[0] /= dnorm; dir[1] /= dnorm; dir[2] /= dnorm;
-      }
-      double Y[16];
-      sh_basis_d(DEG, dir[0], dir[1], dir[2], Y);
-      double gdir[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-      for (int ch = 0; ch < 3; ++ch) {
-        double raw = 0.5;
-#pragma unroll
-        for (int k = 0; k < K; ++k) raw += coef[ch][k] * Y[k];
-        if (raw < 0.0) continue;
-        const double gc = G[G2_R + ch];
-#pragma unroll
-        for (int k = 0; k < K; ++k) gsh[3 * k + ch] += gc * Y[k];
-        if (DEG > 0) {
-          double gd[3];
-          sh_dir_grad_d(DEG, dir[0], dir[1], dir[2], coef[ch], gd);
-          gdir[0] += gc * gd[0];
-          gdir[1] += gc * gd[1];
-          gdir[2] += gc * gd[2];
-        }
-      }
-      if (DEG > 0) {
-        const double dot = dir[0] * gdir[0] + dir[1] * gdir[1] + dir[2] * gdir[2];
-#pragma unroll
-        for (int j = 0; j < 3; ++j) gmean[j] += (gdir[j] - dir[j] * dot) / dnorm;
-      }
-      // conic (A, B, C) = (c, -b, a) / det
-      const double a = g.a, b = g.b, c = g.c, det = g.det;
-      const double id = 1.0 / det, id2 = id * id;
-      const double gA = G[G2_A], gB = G[G2_B], gC = G[G2_C];
-      const double ga = (-gA * c * c + gB * b * c - gC * b * b) * id2;
-      const double gb = (2.0 * gA * b * c - 2.0 * gB * b * b + 2.0 * gC * a * b) * id2 - gB * id;
-      const double gc_ = (-gA * b * b + gB * a * b - gC * a * a) * id2;
-      // Sigma' = T Sigma T^T
-      const double* T0 = g.Tm;
-      const double* T1 = g.Tm + 3;
-      const double* S = g.Sig;
-      double ST0[3], ST1[3];
-#pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        ST0[r] = S[r * 3 + 0] * T0[0] + S[r * 3 + 1] * T0[1] + S[r * 3 + 2] * T0[2];
-        ST1[r] = S[r * 3 + 0] * T1[0] + S[r * 3 + 1] * T1[1] + S[r * 3 + 2] * T1[2];
-      }
-      double gT0[3], gT1[3];
-#pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        gT0[r] = 2.0 * ga * ST0[r] + gb * ST1[r];
-        gT1[r] = gb * ST0[r] + 2.0 * gc_ * ST1[r];
-      }
-      double gSS[9];
-#pragma unroll
-      for (int r = 0; r < 3; ++r)
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-          gSS[r * 3 + k] = 2.0 * ga * T0[r] * T0[k] + gb * (T0[r] * T1[k] + T1[r] * T0[k]) +
-                           2.0 * gc_ * T1[r] * T1[k];
-      const float* W = V.R;
-      double gJ00 = 0, gJ02 = 0, gJ11 = 0, gJ12 = 0;
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        gJ00 += gT0[k] * W[k];
-        gJ02 += gT0[k] * W[6 + k];
-        gJ11 += gT1[k] * W[3 + k];
-        gJ12 += gT1[k] * W[6 + k];
-      }
-      const double tx = g.tx, ty = g.ty, tz = g.tz, fx = V.fx, fy = V.fy;
-      const double itz = 1.0 / tz, itz2 = itz * itz;
-      double gtx = 0, gty = 0, gtz = 0;
-      gtz += -gJ00 * fx * itz2 - gJ11 * fy * itz2 + gJ02 * fx * g.xi * itz2 + gJ12 * fy * g.yi * itz2;
-      if (!g.xclamp) {
-        const double gxi = -gJ02 * fx * itz;
-        gtx += gxi * itz;
-        gtz += -gxi * tx * itz2;
-      }
-      if (!g.yclamp) {
-        const double gyi = -gJ12 * fy * itz;
-        gty += gyi * itz;
-        gtz += -gyi * ty * itz2;
-      }
-      gtx += G[G2_U] * fx * itz;
-      gtz += -G[G2_U] * fx * tx * itz2;
-      gty += G[G2_V] * fy * itz;
-      gtz += -G[G2_V] * fy * ty * itz2;
-      gtz += G[G2_Z];
-#pragma unroll
-      for (int j = 0; j < 3; ++j) gmean[j] += W[j] * gtx + W[3 + j] * gty + W[6 + j] * gtz;
-      // Sigma = M M^T, M = R diag(s)
-      double gM[9];
-#pragma unroll
-      for (int r = 0; r < 3; ++r)
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-          gM[r * 3 + k] = gSS[r * 3 + 0] * g.M[k] + gSS[r * 3 + 1] * g.M[3 + k] + gSS[r * 3 + 2] * g.M[6 + k];
-      double gR[9];
-#pragma unroll
-      for (int r = 0; r < 3; ++r)
-#pragma unroll
-        for (int k = 0; k < 3; ++k) gR[r * 3 + k] = gM[r * 3 + k] * g.s[k];
-#pragma unroll
-      for (int k = 0; k < 3; ++k)
-        gls[k] += (gM[k] * g.R[k] + gM[3 + k] * g.R[3 + k] + gM[6 + k] * g.R[6 + k]) * g.s[k];
-      const double w = g.qh[0], x = g.qh[1], y = g.qh[2], z = g.qh[3];
-      const double gw = 2.0 * (-z * gR[1] + y * gR[2] + z * gR[3] - x * gR[5] - y * gR[6] + x * gR[7]);
-      const double gx = 2.0 * (y * gR[1] + z * gR[2] + y * gR[3] - 2.0 * x * gR[4] - w * gR[5] + z * gR[6] +
-                               w * gR[7] - 2.0 * x * gR[8]);
-      const double gy = 2.0 * (-2.0 * y * gR[0] + x * gR[1] + w * gR[2] + x * gR[3] + z * gR[5] - w * gR[6] +
-                               z * gR[7] - 2.0 * y * gR[8]);
-      const double gz = 2.0 * (-2.0 * z * gR[0] - w * gR[1] + x * gR[2] + w * gR[3] - 2.0 * z * gR[4] +
-                               y * gR[5] + x * gR[6] + y * gR[7]);
-      const double dot = w * gw + x * gx + y * gy + z * gz;
-      gq[0] += (gw - w * dot) / g.qn;
-      gq[1] += (gx - x * dot) / g.qn;
-      gq[2] += (gy - y * dot) / g.qn;
-      gq[3] += (gz - z * dot) / g.qn;
+      chain_view<DEG>(P, stride, i, V, G, coef, gmean, gls, gq, glogit, gsh);
     }
     if (!touched) continue;
 #pragma unroll
@@ -639,7 +687,7 @@ __global__ void __launch_bounds__(256) project_backward_kernel(const float* __re
     for (int j = 0; j < 4; ++j) grad[(6 + j) * stride + i] += (float)gq[j];
     grad[10 * stride + i] += (float)glogit;
 #pragma unroll
-    for (int k = 0; k < 3 * K; ++k) grad[(11 + k) * stride + i] += (float)gsh[k];
+    for (int k = 0; k < 3 * K; ++k) grad[(11 + k) * stride + i] += gsh[k];
   }
 }
 
@@ -686,12 +734,11 @@ int grid_for(int64_t n, int block) {
 
 void launch_project(const float* params, int64_t n, int64_t stride, int deg, int num_views, const ViewDesc* views,
                     int tile_w, int tile_h, float znear, Splat* splats, int4* rect, uint32_t* ntiles,
-                    uint32_t* zkey, uint32_t* svals, uint32_t* zhist, int zrb, int zpasses, hipStream_t st) {
-  const int64_t total = n * num_views;
-  if (total == 0) return;
+                    uint32_t* zkey, uint32_t* zhist, int zrb, int zpasses, hipStream_t st) {
+  if (n == 0 || num_views == 0) return;
   if (zpasses * (1 << zrb) > 3 * 2048) zhist = nullptr;
-  project_kernel<<<grid_for(total, 256), 256, 0, st>>>(params, n, stride, deg, num_views, views, tile_w, tile_h,
-                                                       znear, splats, rect, ntiles, zkey, svals, zhist, zrb, zpasses);
+  project_kernel<<<grid_for(n, 256), 256, 0, st>>>(params, n, stride, deg, num_views, views, tile_w, tile_h, znear,
+                                                   splats, rect, ntiles, zkey, zhist, zrb, zpasses);
 }
 
 void launch_project_backward(const float* params, int64_t n, int64_t stride, int deg, int num_views,
