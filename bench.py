@@ -46,10 +46,13 @@ OPS_PER_PAIR_FWD = 23.0
 
 
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE on this workload, each scaled by what the counter reads for a
-# 256 MiB device copy (FETCH x2.0, WRITE x1.0); cleared whenever the kernel
-# changes.
-TRAFFIC = {}
+# WRITE_SIZE (profiles/mapping_iteration_<workload>.txt), each scaled by what
+# the counter reads for a 256 MiB device copy (FETCH x2.0, WRITE x1.0). An
+# entry is removed whenever its kernel changes.
+MiB = 1024 * 1024
+TRAFFIC = {
+    ("keyframe_640x480_200k", "blend_bwd"): (27.66 * MiB, 56.99 * MiB),   # read, write
+}
 
 
 def parse():
@@ -254,7 +257,10 @@ def main():
                    "stage_ms": {k: round(x, 4) for k, x in stages.items()}},
         "roofline": {"bound": "alu", "kernel": dominant, "achieved": round(achieved, 3),
                      "peak": round(PEAK_VALU_TOPS, 2), "unit": "TOP/s (FP32 VALU lane ops)",
-                     "frac": round(achieved / PEAK_VALU_TOPS, 4), "traffic": TRAFFIC.get(dominant),
+                     "frac": round(achieved / PEAK_VALU_TOPS, 4),
+                     "traffic": (round(sum(TRAFFIC[(scene.name, dominant)])) if (scene.name, dominant) in TRAFFIC
+                                 else None),
+                     "traffic_read_write": TRAFFIC.get((scene.name, dominant)),
                      "avg_ms": round(dom_avg_ms, 4), "launches": dom_n, "pairs": pairs,
                      "ops_per_pair": ops_per_pair},
     }
