@@ -50,9 +50,7 @@ OPS_PER_PAIR_FWD = 23.0
 # the counter reads for a 256 MiB device copy (FETCH x2.0, WRITE x1.0). An
 # entry is removed whenever its kernel changes.
 MiB = 1024 * 1024
-TRAFFIC = {
-    ("keyframe_640x480_200k", "blend_bwd"): (27.66 * MiB, 56.99 * MiB),   # read, write
-}
+TRAFFIC = {}
 
 
 def parse():
@@ -64,6 +62,9 @@ def parse():
     ap.add_argument("--tile", default="16x16")
     ap.add_argument("--ppt", type=int, default=0, help="pixels per thread in the blend kernels (0 = default)")
     ap.add_argument("--batch-depth", type=int, default=0, help="backward batch depth (0 = default)")
+    ap.add_argument("--chunk-len", type=int, default=0,
+                    help="backward work unit in list positions (0 = automatic, -1 = whole tile lists)")
+    ap.add_argument("--max-chunks", type=int, default=0, help="backward chunks per tile (0 = default)")
     ap.add_argument("--tile-order", type=int, default=0,
                     help="0 = automatic, 1 = longest tile lists first, 2 = tile order")
     ap.add_argument("--no-autotune", action="store_true",
@@ -112,7 +113,7 @@ def main():
     cams = scene.cameras
     deg = scene.sh_degree
     R = Rasterizer(tile_w=tw, tile_h=th, pixels_per_thread=args.ppt, batch_depth=args.batch_depth,
-                   tile_order=args.tile_order)
+                   tile_order=args.tile_order, chunk_len=args.chunk_len, max_chunks=args.max_chunks)
     dev = torch.device("cuda:0")
     if args.calibrate_copy:
         src = torch.ones(64 * 1024 * 1024, device=dev)
@@ -145,7 +146,8 @@ def main():
                               log=(lambda msg: print(msg, file=sys.stderr)) if args.breakdown else None)
         R.close()
         R = Rasterizer(tile_w=tuned["tile_w"], tile_h=tuned["tile_h"], pixels_per_thread=tuned["pixels_per_thread"],
-                       batch_depth=tuned["batch_depth"], tile_order=args.tile_order)
+                       batch_depth=tuned["batch_depth"], tile_order=args.tile_order, chunk_len=tuned["chunk_len"],
+                       max_chunks=tuned["max_chunks"])
         outs = R.alloc_images(cams, dev)
     from paper_2509_06433_amd import _lib
     adam = dict(m=m, v=v, lr=lrs, beta1=0.9, beta2=0.999, eps=1e-15) if use_adam else None
@@ -249,6 +251,8 @@ def main():
                    "resolutions": sorted({f"{c.width}x{c.height}" for c in cams}),
                    "gaussians": scene.num, "sh_degree": deg, "tile": f"{R.tile_w}x{R.tile_h}",
                    "pixels_per_thread": R.pixels_per_thread or 1, "batch_depth": R.batch_depth or "default",
+                   "chunk_len": {0: "auto", -1: "whole list"}.get(R.chunk_len, R.chunk_len),
+                   "max_chunks": R.max_chunks or "default",
                    "autotuned": tuned is not None, "tile_order": ["auto", "longest first", "index"][R.tile_order],
                    "adam": use_adam, "mode": args.mode,
                    f"{other}_iters_s": round(1000.0 / other_ms, 3) if other_ms else None,

@@ -76,6 +76,14 @@ typedef struct {
   int32_t tile_order;       /* order in which blend workgroups take tiles: 0 = automatic (longest
                                list first when several views are rendered together, else
                                tile order), 1 = longest list first, 2 = tile order */
+  int32_t chunk_len;        /* work unit of the blend backward, in list positions: 0 = automatic
+                               (chunks of 128 when a launch covers fewer than 4096 tiles, else
+                               whole lists), -1 = whole tile lists, else a multiple of 16 up to
+                               2^20. With chunks, the forward records each pixel's transmittance
+                               and its colour and depth composited per chunk, so the chunks of
+                               one tile are walked in reverse by independent workgroups. */
+  int32_t max_chunks;       /* chunks per tile: 0 = default (4), else 1 .. 64; the last chunk
+                               takes the rest of the list */
 } gsr_options;
 
 typedef struct {

@@ -13,6 +13,15 @@ using namespace gsr;
 
 namespace gsr {
 
+// Chunks of the tile lists as the backward's work unit pay off when a launch
+// has too few tiles to keep every CU busy to the end (measured: 1200 tiles
+// -16 % backward time, 3225 tiles -8 %, 9600 tiles +1 %, 57k tiles +6 %).
+int chunk_len_for(const gsr_ctx* ctx, const RenderPlan& P) {
+  if (ctx->chunk_len > 0) return ctx->chunk_len;
+  if (ctx->chunk_len < 0) return 0;
+  return P.ntiles < kAutoChunkTiles ? kAutoChunk : 0;
+}
+
 int plan_render(gsr_ctx* ctx, const gsr_gaussians* g, int32_t nv, const gsr_camera* cams, RenderPlan* plan) {
   RET_IF(check_gaussians(g));
   RET_IF(check_cams(cams, nv));
@@ -62,6 +71,9 @@ int size_render(gsr_ctx* ctx, Buffers& B, RenderPlan& P, const gsr_image* out, h
   RET_IF(ensure(ctx, B.order, sizeof(uint32_t) * (size_t)std::max<int64_t>(P.ntiles, 1)));
   RET_IF(ensure(ctx, B.tfinal, sizeof(float) * (size_t)P.npix));
   RET_IF(ensure(ctx, B.last, sizeof(uint32_t) * (size_t)P.npix));
+  RET_IF(ensure(ctx, B.tile_last, sizeof(uint32_t) * (size_t)std::max<int64_t>(P.ntiles, 1)));
+  if (chunk_len_for(ctx, P) > 0)
+    RET_IF(ensure(ctx, B.ckpt, sizeof(float) * kCkptFields * (size_t)ctx->max_chunks * (size_t)P.npix));
   RET_IF(ensure(ctx, B.g2, sizeof(float) * G2_N * (size_t)std::max<int64_t>(P.total, 1)));
   RET_IF(ensure(ctx, B.total, 64));
   RET_IF(ensure(ctx, B.hist, sizeof(uint32_t) * (size_t)radix_scratch_elems(P.total, 32)));
@@ -124,6 +136,15 @@ static bool use_lpt(const gsr_ctx* ctx, const RenderPlan& P) {
   return ctx->tile_order == 1 || (ctx->tile_order == 0 && P.nv > 1);
 }
 
+static void set_chunking(const gsr_ctx* ctx, Buffers& B, const RenderPlan& P, BlendArgs& ba) {
+  const int cl = chunk_len_for(ctx, P);
+  ba.tile_last = as<uint32_t>(B.tile_last);
+  ba.chunk_len = cl;
+  ba.max_chunks = cl > 0 ? ctx->max_chunks : 1;
+  ba.ckpt = cl > 0 ? as<float>(B.ckpt) : nullptr;
+  ba.ckpt_stride = P.npix;
+}
+
 int launch_back(gsr_ctx* ctx, Buffers& B, RenderPlan& P, hipStream_t st) {
   uint32_t* totals = as<uint32_t>(B.total);
   uint32_t* ik = as<uint32_t>(B.ikeys);
@@ -169,6 +190,7 @@ int launch_back(gsr_ctx* ctx, Buffers& B, RenderPlan& P, hipStream_t st) {
   ba.last = as<uint32_t>(B.last);
   ba.g2 = nullptr;
   for (int k = 0; k < 3; ++k) ba.bg[k] = ctx->bg[k];
+  set_chunking(ctx, B, P, ba);
   {
     StageTimer tm(ctx, GSR_STAGE_BLEND_FWD, st);
     launch_blend_forward(ba, ctx->tile_w, ctx->tile_h, ctx->ppt, st);
@@ -199,6 +221,7 @@ int launch_bwd(gsr_ctx* ctx, Buffers& B, const RenderPlan& P, const float* param
   ba.last = as<uint32_t>(B.last);
   ba.g2 = as<float>(B.g2);
   for (int k = 0; k < 3; ++k) ba.bg[k] = ctx->bg[k];
+  set_chunking(ctx, B, P, ba);
   {
     StageTimer tm(ctx, GSR_STAGE_BLEND_BWD, st);
     launch_blend_backward(ba, ctx->tile_w, ctx->tile_h, ctx->ppt, ctx->batch_depth, st);
@@ -216,7 +239,8 @@ int launch_bwd(gsr_ctx* ctx, Buffers& B, const RenderPlan& P, const float* param
 void free_buffers(Buffers& B) {
   DevBuf* bufs[] = {&B.views, &B.images, &B.images2, &B.splats, &B.rect, &B.ntiles, &B.zkey, &B.svals,
                     &B.zkey_alt, &B.svals_alt, &B.offsets, &B.ikeys, &B.ivals, &B.ikeys_alt, &B.ivals_alt,
-                    &B.hist, &B.hist2, &B.partials, &B.ranges, &B.order, &B.tfinal, &B.last, &B.g2, &B.total};
+                    &B.hist, &B.hist2, &B.partials, &B.ranges, &B.order, &B.tfinal, &B.last, &B.g2, &B.total,
+                    &B.tile_last, &B.ckpt};
   for (DevBuf* b : bufs) {
     if (b->p) (void)hipFree(b->p);
     b->p = nullptr;
@@ -318,6 +342,13 @@ int gsr_create(gsr_ctx** out, const gsr_options* opt) {
       return GSR_ERR_UNSUPPORTED;
     }
     ctx->tile_order = opt->tile_order;
+    const int mc = opt->max_chunks == 0 ? ctx->max_chunks : opt->max_chunks;
+    if (opt->chunk_len < -1 || !chunking_supported(opt->chunk_len > 0 ? opt->chunk_len : kAutoChunk, mc)) {
+      delete ctx;
+      return GSR_ERR_UNSUPPORTED;
+    }
+    ctx->chunk_len = opt->chunk_len;
+    ctx->max_chunks = mc;
     for (int k = 0; k < 3; ++k) ctx->bg[k] = opt->bg[k];
     ctx->znear = opt->znear > 0.f ? opt->znear : 0.2f;
   }

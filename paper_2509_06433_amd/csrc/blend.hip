@@ -77,8 +77,10 @@ struct TileShape {
 // Front-to-back update of one pixel with one Gaussian whose alpha is known.
 // Branchy on purpose: most pairs are skipped (alpha below 1/255), and a wave
 // whose lanes all skip jumps over the update.
+// CK: the sums of the current backward chunk (dC) are kept as well.
+template <bool CK>
 __device__ __forceinline__ void composite_one(bool ok, float alpha, const float4& q1, const float4& q2, float& T,
-                                              float& C0, float& C1, float& C2, float& D, bool& done,
+                                              float& C0, float& C1, float& C2, float& D, float* dC, bool& done,
                                               uint32_t& last, uint32_t pos) {
   if (done || !ok) return;
   const float Tn = T * (1.0f - alpha);
@@ -91,17 +93,63 @@ __device__ __forceinline__ void composite_one(bool ok, float alpha, const float4
   C1 = fmaf(w, q2.y, C1);
   C2 = fmaf(w, q2.z, C2);
   D = fmaf(w, q1.z, D);
+  if (CK) {
+    dC[0] = fmaf(w, q2.x, dC[0]);
+    dC[1] = fmaf(w, q2.y, dC[1]);
+    dC[2] = fmaf(w, q2.z, dC[2]);
+    dC[3] = fmaf(w, q1.z, dC[3]);
+  }
   T = Tn;
   last = pos;
 }
 
-template <int TW, int TH, int PPT>
+// Chunked backward state of one pixel: slot s holds (T before chunk s,
+// colour and depth composited within chunk s).
+__device__ __forceinline__ void write_ckpt_T(const BlendArgs& a, uint32_t slot, int64_t pix, float T) {
+  a.ckpt[(int64_t)slot * kCkptFields * a.ckpt_stride + pix] = T;
+}
+__device__ __forceinline__ void write_ckpt_sums(const BlendArgs& a, uint32_t slot, int64_t pix, const float* dC) {
+  const int64_t st = a.ckpt_stride;
+  float* c = a.ckpt + (int64_t)slot * kCkptFields * st + pix;
+#pragma unroll
+  for (int f = 0; f < 4; ++f) c[(f + 1) * st] = dC[f];
+}
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) x = max(x, (uint32_t)__shfl_xor((int)x, m, 64));
+  return x;
+}
+
+// At list position `pos` = s * chunk_len (s >= 1): every pixel still
+// compositing records T into slot s and the sums of chunk s - 1 into slot
+// s - 1, and starts chunk s. A stopped pixel's last composited position lies
+// before pos, so the backward never reads these slots for it.
+template <int PPT>
+__device__ __forceinline__ void chunk_boundary(const BlendArgs& a, uint32_t& pos, uint32_t end, const bool* done,
+                                               const int64_t* pix, const float* T, float (*dC)[4], uint32_t* mych) {
+  const uint32_t s = pos / (uint32_t)a.chunk_len;
+#pragma unroll
+  for (int i = 0; i < PPT; ++i) {
+    if (done[i]) continue;
+    write_ckpt_T(a, s, pix[i], T[i]);
+    write_ckpt_sums(a, s - 1, pix[i], dC[i]);
+    dC[i][0] = dC[i][1] = dC[i][2] = dC[i][3] = 0.0f;
+    mych[i] = s;
+  }
+  pos += (uint32_t)a.chunk_len;
+  if (pos >= end) pos = 0xFFFFFFFFu;
+}
+
+// CK: record the chunked backward's per-pixel state (a.chunk_len > 0).
+template <int TW, int TH, int PPT, bool CK>
 __global__ void __launch_bounds__(TW * TH / PPT) blend_forward_kernel(BlendArgs a) {
   using Shape = TileShape<TW, TH, PPT>;
   constexpr int NT = Shape::NT;
   constexpr int ROWS = Shape::ROWS;
   constexpr int BATCH = NT;
   __shared__ float4 s_q0[BATCH], s_q1[BATCH], s_q2[BATCH];
+  __shared__ uint32_t s_tl;
   const int tile = a.order ? (int)a.order[blockIdx.x] : (int)blockIdx.x;
   const int view = find_view(a.views, a.num_views, tile);
   const ViewDesc& V = a.views[view];
@@ -112,7 +160,8 @@ __global__ void __launch_bounds__(TW * TH / PPT) blend_forward_kernel(BlendArgs 
   int py[PPT];
   bool inside[PPT], done[PPT];
   float ys[PPT], T[PPT], C0[PPT], C1[PPT], C2[PPT], D[PPT];
-  uint32_t last[PPT];
+  float dC[PPT][4];
+  uint32_t last[PPT], mych[PPT];
 #pragma unroll
   for (int i = 0; i < PPT; ++i) {
     py[i] = ty * TH + (tid / TW) + i * ROWS;
@@ -121,10 +170,20 @@ __global__ void __launch_bounds__(TW * TH / PPT) blend_forward_kernel(BlendArgs 
     ys[i] = (float)py[i] + 0.5f;
     T[i] = 1.0f;
     C0[i] = C1[i] = C2[i] = D[i] = 0.0f;
+    dC[i][0] = dC[i][1] = dC[i][2] = dC[i][3] = 0.0f;
     last[i] = 0;
+    mych[i] = 0;
   }
   const float xs = (float)px + 0.5f;
   const uint2 rg = a.ranges[tile];
+  int64_t pix[PPT];
+#pragma unroll
+  for (int i = 0; i < PPT; ++i) pix[i] = V.pix_offset + (int64_t)py[i] * V.width + px;
+  // next list position whose state the chunked backward starts from
+  const uint32_t ck_end = CK ? (uint32_t)a.chunk_len * (uint32_t)a.max_chunks : 0u;
+  uint32_t nextck = CK && a.max_chunks > 1 ? (uint32_t)a.chunk_len : 0xFFFFFFFFu;
+  if (tid == 0) s_tl = 0;
+  __syncthreads();
   for (uint32_t b0 = rg.x; b0 < rg.y; b0 += BATCH) {
     bool all_done = true;
 #pragma unroll
@@ -144,6 +203,9 @@ __global__ void __launch_bounds__(TW * TH / PPT) blend_forward_kernel(BlendArgs 
 #pragma unroll
       for (int i = 0; i < PPT; ++i) busy = busy || !done[i];
       if (!busy) break;
+      if (CK && b0 - rg.x + k == nextck) {
+        chunk_boundary<PPT>(a, nextck, ck_end, done, pix, T, dC, mych);
+      }
       const float4 qa0 = s_q0[k], qa1 = s_q1[k], qb0 = s_q0[k + 1], qb1 = s_q1[k + 1];
       float al_a[PPT], al_b[PPT];
       bool ok_a[PPT], ok_b[PPT];
@@ -157,23 +219,29 @@ __global__ void __launch_bounds__(TW * TH / PPT) blend_forward_kernel(BlendArgs 
       const float4 qa2 = s_q2[k], qb2 = s_q2[k + 1];
 #pragma unroll
       for (int i = 0; i < PPT; ++i) {
-        composite_one(ok_a[i], al_a[i], qa1, qa2, T[i], C0[i], C1[i], C2[i], D[i], done[i], last[i], pos0 + k);
-        composite_one(ok_b[i], al_b[i], qb1, qb2, T[i], C0[i], C1[i], C2[i], D[i], done[i], last[i], pos0 + k + 1);
+        composite_one<CK>(ok_a[i], al_a[i], qa1, qa2, T[i], C0[i], C1[i], C2[i], D[i], dC[i], done[i], last[i],
+                          pos0 + k);
+        composite_one<CK>(ok_b[i], al_b[i], qb1, qb2, T[i], C0[i], C1[i], C2[i], D[i], dC[i], done[i], last[i],
+                          pos0 + k + 1);
       }
     }
     if (k < cnt) {
+      if (CK && b0 - rg.x + k == nextck) {
+        chunk_boundary<PPT>(a, nextck, ck_end, done, pix, T, dC, mych);
+      }
       const float4 q0 = s_q0[k], q1 = s_q1[k], q2 = s_q2[k];
 #pragma unroll
       for (int i = 0; i < PPT; ++i) {
         float dx, dy, G, al;
         bool cl;
         const bool ok = pair_alpha(q0, q1, xs, ys[i], dx, dy, G, al, cl);
-        composite_one(ok, al, q1, q2, T[i], C0[i], C1[i], C2[i], D[i], done[i], last[i], pos0 + k);
+        composite_one<CK>(ok, al, q1, q2, T[i], C0[i], C1[i], C2[i], D[i], dC[i], done[i], last[i], pos0 + k);
       }
     }
   }
   const ViewImages im = a.images[view];
   const int64_t HW = (int64_t)V.width * V.height;
+  uint32_t tl = 0;
 #pragma unroll
   for (int i = 0; i < PPT; ++i) {
     if (!inside[i]) continue;
@@ -183,9 +251,17 @@ __global__ void __launch_bounds__(TW * TH / PPT) blend_forward_kernel(BlendArgs 
     im.rgb[2 * HW + p] = fmaf(T[i], a.bg[2], C2[i]);
     im.depth[p] = D[i];
     im.alpha[p] = 1.0f - T[i];
-    a.tfinal[V.pix_offset + p] = T[i];
-    a.last[V.pix_offset + p] = last[i];
+    a.tfinal[pix[i]] = T[i];
+    a.last[pix[i]] = last[i];
+    tl = max(tl, last[i]);
+    // the sums of the chunk the pixel ended in; read only when an earlier
+    // chunk's walk starts past its own end, i.e. last > chunk_len
+    if (CK && last[i] > (uint32_t)a.chunk_len) write_ckpt_sums(a, mych[i], pix[i], dC[i]);
   }
+  tl = wave_max_u32(tl);
+  if ((tid & 63) == 0) atomicMax(&s_tl, tl);
+  __syncthreads();
+  if (tid == 0) a.tile_last[tile] = s_tl;
 }
 
 __device__ __forceinline__ float wave_sum(float x) {
@@ -311,8 +387,24 @@ blend_backward_kernel(BlendArgs a) {
   __shared__ float4 s_q0[BATCH], s_q1[BATCH], s_q2[BATCH];
   __shared__ uint32_t s_id[BATCH];
   __shared__ float s_red[NW][4][M_N][BATCH];   // moments per (wave, 16-lane row)
-  __shared__ uint32_t s_maxlast;
-  const int tile = a.order ? (int)a.order[blockIdx.x] : (int)blockIdx.x;
+  // work unit: a tile, or with chunking one chunk of a tile's list; the
+  // chunk that takes the rest of the list (the longest) comes first, then
+  // chunks 0, 1, ... of every tile
+  int unit = (int)blockIdx.x;
+  uint32_t lo = 0, hi = 0xFFFFFFFFu;
+  int chunk = 0;
+  if (a.chunk_len > 0) {
+    const int cu = unit / a.num_tiles;
+    unit -= cu * a.num_tiles;
+    chunk = cu == 0 ? a.max_chunks - 1 : cu - 1;
+    lo = (uint32_t)chunk * (uint32_t)a.chunk_len;
+    if (chunk < a.max_chunks - 1) hi = lo + (uint32_t)a.chunk_len;
+  }
+  const int tile = a.order ? (int)a.order[unit] : unit;
+  const uint2 rg = a.ranges[tile];
+  const uint32_t maxlast = min(a.tile_last[tile], rg.y - rg.x);
+  if (lo >= maxlast) return;   // nothing composited in this unit's positions
+  const uint32_t top = min(hi, maxlast);
   const int view = find_view(a.views, a.num_views, tile);
   const ViewDesc& V = a.views[view];
   const int lt = tile - V.tile_offset;
@@ -321,13 +413,10 @@ blend_backward_kernel(BlendArgs a) {
   const int lane = tid & 63, wave = tid >> 6;
   const int px = tx * TW + (tid % TW);
   const float xs = (float)px + 0.5f;
-  const uint2 rg = a.ranges[tile];
   const int64_t HW = (int64_t)V.width * V.height;
   const ViewImages gimg = a.images[view];
   float ys[PPT], T[PPT], S[PPT], gc0[PPT], gc1[PPT], gc2[PPT], gd[PPT], tb[PPT];
   uint32_t mylast[PPT];
-  if (tid == 0) s_maxlast = 0;
-  __syncthreads();
   uint32_t tmax = 0;
 #pragma unroll
   for (int i = 0; i < PPT; ++i) {
@@ -352,30 +441,45 @@ blend_backward_kernel(BlendArgs a) {
     }
     // T_final (dL/dalpha_out - dL/drgb . bg): the background term of dL/dalpha_k
     tb[i] = T[i] * (ga - (gc0[i] * a.bg[0] + gc1[i] * a.bg[1] + gc2[i] * a.bg[2]));
+    if (mylast[i] > hi) {
+      // composited Gaussians lie past this chunk: start from the state the
+      // forward recorded at the chunk's end. The suffix the walk carries is
+      // normalised by the transmittance, S = sum_{j >= hi} x_j w_j / T_hi with
+      // x_j = dL/drgb . rgb_j + dL/ddepth z_j; the sum is taken over the
+      // per-chunk sums of the later chunks up to the one holding the pixel's
+      // last composited Gaussian.
+      const int64_t st = a.ckpt_stride;
+      const int64_t pix = V.pix_offset + (int64_t)(ty * TH + (tid / TW) + i * ROWS) * V.width + px;
+      const uint32_t clast = min((mylast[i] - 1) / (uint32_t)a.chunk_len, (uint32_t)a.max_chunks - 1);
+      float rest = 0.0f;
+      for (uint32_t c = chunk + 1; c <= clast; ++c) {
+        const float* ck = a.ckpt + (int64_t)c * kCkptFields * st + pix;
+        rest += fmaf(gc0[i], ck[st], fmaf(gc1[i], ck[2 * st], fmaf(gc2[i], ck[3 * st], gd[i] * ck[4 * st])));
+      }
+      const float Th = a.ckpt[(int64_t)(chunk + 1) * kCkptFields * st + pix];
+      T[i] = Th;
+      S[i] = rest / Th;
+    }
     tmax = max(tmax, mylast[i]);
   }
-  atomicMax(&s_maxlast, tmax);
   // list positions at or past the wave's largest last position are skipped
-  uint32_t wmax = tmax;
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) wmax = max(wmax, (uint32_t)__shfl_xor((int)wmax, m, 64));
-  const uint32_t wlast = __builtin_amdgcn_readfirstlane(wmax);
-  __syncthreads();
-  const uint32_t maxlast = min(s_maxlast, rg.y - rg.x);
+  const uint32_t wlast = __builtin_amdgcn_readfirstlane(wave_max_u32(tmax));
+  // the unit walks positions [lo, top) from the back
+  const int64_t base = (int64_t)rg.x + lo;
   // the next (earlier) batch's record is loaded into registers while this
   // one is processed, so its global latency overlaps the arithmetic
   uint32_t nsid = 0;
   Splat nxt;
   {
-    const int64_t bend = (int64_t)rg.x + maxlast;
-    const int64_t b0 = bend - BATCH > (int64_t)rg.x ? bend - BATCH : (int64_t)rg.x;
-    if (bend > (int64_t)rg.x && tid < (int)(bend - b0)) {
+    const int64_t bend = (int64_t)rg.x + top;
+    const int64_t b0 = bend - BATCH > base ? bend - BATCH : base;
+    if (tid < (int)(bend - b0)) {
       nsid = a.inst_vals[b0 + tid];
       nxt = a.splats[nsid];
     }
   }
-  for (int64_t bend = (int64_t)rg.x + maxlast; bend > (int64_t)rg.x; bend -= BATCH) {
-    const int64_t b0 = bend - BATCH > (int64_t)rg.x ? bend - BATCH : (int64_t)rg.x;
+  for (int64_t bend = (int64_t)rg.x + top; bend > base; bend -= BATCH) {
+    const int64_t b0 = bend - BATCH > base ? bend - BATCH : base;
     const int cnt = (int)(bend - b0);
     __syncthreads();
     if (tid < cnt) {
@@ -383,8 +487,8 @@ blend_backward_kernel(BlendArgs a) {
       stage_record(nxt, s_q0[tid], s_q1[tid], s_q2[tid]);
     }
     {
-      const int64_t pend = b0, pb0 = pend - BATCH > (int64_t)rg.x ? pend - BATCH : (int64_t)rg.x;
-      if (pend > (int64_t)rg.x && tid < (int)(pend - pb0)) {
+      const int64_t pend = b0, pb0 = pend - BATCH > base ? pend - BATCH : base;
+      if (pend > base && tid < (int)(pend - pb0)) {
         nsid = a.inst_vals[pb0 + tid];
         nxt = a.splats[nsid];
       }
@@ -516,17 +620,26 @@ blend_backward_kernel(BlendArgs a) {
 
 template <int TW, int TH>
 void fwd_launch(const BlendArgs& a, int ppt, hipStream_t st) {
-  if (ppt == 2 && TW * TH >= 128) blend_forward_kernel<TW, TH, (TW * TH >= 128 ? 2 : 1)><<<a.num_tiles, TW * TH / 2, 0, st>>>(a);
-  else blend_forward_kernel<TW, TH, 1><<<a.num_tiles, TW * TH, 0, st>>>(a);
+  constexpr int P2 = TW * TH >= 128 ? 2 : 1;
+  const bool ck = a.chunk_len > 0;
+  if (ppt == 2 && P2 == 2) {
+    if (ck) blend_forward_kernel<TW, TH, P2, true><<<a.num_tiles, TW * TH / P2, 0, st>>>(a);
+    else blend_forward_kernel<TW, TH, P2, false><<<a.num_tiles, TW * TH / P2, 0, st>>>(a);
+  } else {
+    if (ck) blend_forward_kernel<TW, TH, 1, true><<<a.num_tiles, TW * TH, 0, st>>>(a);
+    else blend_forward_kernel<TW, TH, 1, false><<<a.num_tiles, TW * TH, 0, st>>>(a);
+  }
 }
 template <int TW, int TH, int PPT>
 void bwd_launch_depth(const BlendArgs& a, int depth, hipStream_t st) {
   constexpr int NT = TW * TH / PPT;
   constexpr int D64 = NT >= 64 ? 64 : NT;
   if (depth == 0) depth = NT >= 256 ? 32 : 64;
-  if (depth == 16) blend_backward_kernel<TW, TH, PPT, 16><<<a.num_tiles, NT, 0, st>>>(a);
-  else if (depth == 32) blend_backward_kernel<TW, TH, PPT, 32><<<a.num_tiles, NT, 0, st>>>(a);
-  else blend_backward_kernel<TW, TH, PPT, D64><<<a.num_tiles, NT, 0, st>>>(a);
+  const int64_t units = (int64_t)a.num_tiles * (a.chunk_len > 0 ? a.max_chunks : 1);
+  const dim3 grid((unsigned)units);
+  if (depth == 16) blend_backward_kernel<TW, TH, PPT, 16><<<grid, NT, 0, st>>>(a);
+  else if (depth == 32) blend_backward_kernel<TW, TH, PPT, 32><<<grid, NT, 0, st>>>(a);
+  else blend_backward_kernel<TW, TH, PPT, D64><<<grid, NT, 0, st>>>(a);
 }
 
 template <int TW, int TH>
@@ -614,6 +727,11 @@ void launch_blend_forward(const BlendArgs& a, int tile_w, int tile_h, int ppt, h
 }
 
 bool batch_depth_supported(int depth) { return depth == 0 || depth == 16 || depth == 32 || depth == 64; }
+
+bool chunking_supported(int chunk_len, int max_chunks) {
+  if (chunk_len == 0) return true;
+  return chunk_len > 0 && chunk_len % 16 == 0 && chunk_len <= (1 << 20) && max_chunks >= 1 && max_chunks <= 64;
+}
 
 void launch_blend_backward(const BlendArgs& a, int tile_w, int tile_h, int ppt, int depth, hipStream_t st) {
   if (a.num_tiles == 0) return;

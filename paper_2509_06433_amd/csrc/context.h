@@ -38,6 +38,7 @@ struct Buffers {
   DevBuf ikeys, ivals, ikeys_alt, ivals_alt;
   DevBuf hist, hist2, partials, ranges, order, tfinal, last, g2;   // hist: depth sort, hist2: tile sort
   DevBuf total;   // [0] instance count, [1] wait expired, [2] instance overflow, [3] visible splats
+  DevBuf tile_last, ckpt;   // per tile: longest walk; per pixel: state at the backward's chunk boundaries
 };
 
 // Sizes and final buffer roles of one forward render.
@@ -54,6 +55,12 @@ struct RenderPlan {
 };
 
 struct GraphState;   // captured mapping iteration
+
+// Automatic backward chunking: chunks of kAutoChunk list positions when a
+// launch covers fewer than kAutoChunkTiles tiles.
+constexpr int kAutoChunk = 128;
+constexpr int64_t kAutoChunkTiles = 4096;
+int chunk_len_for(const gsr_ctx* ctx, const RenderPlan& P);
 
 // Brackets one stage's launches with events when profiling is on. While a
 // mapping iteration is being captured, the events become event-record nodes
@@ -100,6 +107,8 @@ struct gsr_ctx {
   int ppt = 1;                          // pixels per thread in the blend kernels
   int batch_depth = 0;                  // backward batch depth (0 = default)
   int tile_order = 0;                   // 0 auto, 1 longest list first, 2 tile order
+  int chunk_len = 0;                    // backward work unit in list positions: 0 automatic, -1 whole lists
+  int max_chunks = 4;                   // chunks per tile (the last takes the rest)
   float bg[3] = {0.f, 0.f, 0.f};
   float znear = 0.2f;
   int hip_err = 0;

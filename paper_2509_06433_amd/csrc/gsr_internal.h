@@ -155,7 +155,19 @@ struct BlendArgs {
   uint32_t* last;               // per pixel: index (within the tile list) after the last composited
   float* g2;                    // backward: screen-space gradient accumulators [V*N][10]
   float bg[3];
+  // Chunked backward (chunk_len > 0): the backward's work unit is a chunk of
+  // chunk_len list positions of one tile (the last of max_chunks chunks takes
+  // the rest of the list). The forward records per pixel, in
+  // ckpt[(slot * kCkptFields + f) * ckpt_stride + pixel], slot s =
+  // (T before chunk s, then the colour and depth composited within chunk s),
+  // from which every chunk starts its reverse walk.
+  float* ckpt;
+  int64_t ckpt_stride;
+  int32_t chunk_len;
+  int32_t max_chunks;
+  uint32_t* tile_last;          // per tile: largest last position of its pixels (forward writes)
 };
+constexpr int kCkptFields = 5;
 bool blend_supported(int tile_w, int tile_h);
 // ppt: pixels per thread (1, or 2 for tiles of at least 128 pixels)
 void launch_blend_forward(const BlendArgs& a, int tile_w, int tile_h, int ppt, hipStream_t st);
@@ -163,6 +175,9 @@ void launch_blend_forward(const BlendArgs& a, int tile_w, int tile_h, int ppt, h
 // capped at the workgroup's thread count)
 bool batch_depth_supported(int depth);
 void launch_blend_backward(const BlendArgs& a, int tile_w, int tile_h, int ppt, int depth, hipStream_t st);
+// Valid chunk settings: chunk_len 0 (whole tile lists) or a multiple of 16
+// up to 1 << 20, with 1 <= max_chunks <= 64.
+bool chunking_supported(int chunk_len, int max_chunks);
 // clear_loss = false: the caller has zeroed *loss.
 void launch_loss_l1(const ViewDesc* views, const ViewImages* rendered, const ViewImages* target,
                     const ViewImages* grad, int num_views, int max_pixels, float depth_weight,

@@ -69,11 +69,14 @@ def check_grad_close(g, ref, label):
         assert nbad == 0, (label, grp, worst)
 
 
-def test_replays_match_eager(gpu, orc):
+@pytest.mark.parametrize("chunk", [(0, 0), (16, 5)])
+def test_replays_match_eager(gpu, orc, chunk):
     s = two_view_scene()
     deg, cams = s.sh_degree, s.cameras
     targets = targets_for(gpu, s)
-    R, E = gpu.Rasterizer(), gpu.Rasterizer()
+    say("backward chunks", chunk)
+    opts = dict(chunk_len=chunk[0], max_chunks=chunk[1])
+    R, E = gpu.Rasterizer(**opts), gpu.Rasterizer(**opts)
     p = to_dev(s.params)
     m, v = torch.zeros_like(p), torch.zeros_like(p)
     grad = torch.full_like(p, 7.0)
@@ -239,12 +242,12 @@ def test_autotuner_picks_a_timed_candidate(gpu, tmp_path, monkeypatch):
     targets = targets_for(gpu, s)
     p = to_dev(s.params)
     p0 = p.clone()
-    cands = [(16, 16, 1, 0), (16, 8, 2, 32), (8, 8, 1, 64)]
+    cands = [(16, 16, 1, 0, 0, 0), (16, 8, 2, 32, -1, 0), (8, 8, 1, 64, 16, 8)]
     res = autotune.tune(p, 0, s.cameras, targets, candidates=cands, warmup=1, steps=2)
     say(res)
     assert not res["cached"] and len(res["table"]) == 3
-    assert (res["tile_w"], res["tile_h"], res["pixels_per_thread"], res["batch_depth"]) in cands
-    assert res["ms"] == min(r[4] for r in res["table"]) and res["ms"] > 0
+    assert tuple(res[f] for f in autotune.FIELDS) in cands
+    assert res["ms"] == min(r[-1] for r in res["table"]) and res["ms"] > 0
     assert torch.equal(p, p0)
     again = autotune.tune(p, 0, s.cameras, targets, candidates=cands)
     assert again["cached"] and again["tile_w"] == res["tile_w"]

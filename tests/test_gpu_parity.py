@@ -199,6 +199,45 @@ def test_backward_batch_depth(gpu, orc, depth):
     check_grads(g, ref32, f"depth {depth}", ref64)
 
 
+@pytest.mark.parametrize("chunk,nchunks,ppt", [(16, 4, 1), (16, 64, 1), (32, 3, 2), (16, 1, 1), (-1, 0, 1)])
+def test_backward_chunked(gpu, orc, chunk, nchunks, ppt):
+    """The backward split into chunks of the tile lists (each chunk's reverse
+    walk starts from the state the forward recorded at its end) against the
+    FP64 oracle; -1 walks whole tile lists."""
+    s = CASES["small"]
+    say("chunk", chunk, "chunks", nchunks, "pixels per thread", ppt)
+    grads = masked_grads(orc, s, 6)
+    R = make(gpu, chunk_len=chunk, max_chunks=nchunks, pixels_per_thread=ppt)
+    p = to_dev(s.params)
+    R.render(p, s.sh_degree, s.cameras)
+    g = R.render_backward(p, s.sh_degree, s.cameras, [tuple(to_dev(x) for x in gv) for gv in grads]).cpu().numpy()
+    ref32, ref64 = oracle_grads(orc, s, s.cameras, grads)
+    check_grads(g, ref32, f"chunk {chunk}x{nchunks}", ref64)
+
+
+def test_backward_chunked_background_multiview(gpu, orc):
+    s = scenes.tiny_random(4, n=50, width=40, height=30)
+    s.cameras = [s.cameras[0], scenes.look_at_camera([0.3, 0.1, -0.5], [0, 0, 2], 36, 28, 30.0)]
+    bg = (0.2, 0.5, 0.8)
+    grads = masked_grads(orc, s, 7)
+    R = make(gpu, chunk_len=16, max_chunks=3, bg=bg)
+    p = to_dev(s.params)
+    R.render(p, 0, s.cameras)
+    g = R.render_backward(p, 0, s.cameras, [tuple(to_dev(x) for x in gv) for gv in grads]).cpu().numpy()
+    ref32 = orc.backward(s.params, 0, s.cameras, grads, pinned="splats32", bg=bg)
+    ref64 = orc.backward(s.params, 0, s.cameras, grads, pinned=True, bg=bg)
+    check_grads(g, ref32, "chunked, background, two views", ref64)
+
+
+def test_chunking_leaves_forward_unchanged(gpu):
+    s = CASES["small"]
+    p = to_dev(s.params)
+    a = make(gpu, chunk_len=-1).render(p, s.sh_degree, s.cameras)[0]
+    b = make(gpu, chunk_len=16, max_chunks=8).render(p, s.sh_degree, s.cameras)[0]
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+
+
 def test_backward_multiview_sums(gpu, orc):
     s = scenes.tiny_random(4, n=50, width=40, height=30)
     s.cameras = [s.cameras[0], scenes.look_at_camera([0.3, 0.1, -0.5], [0, 0, 2], 36, 28, 30.0)]
@@ -367,6 +406,10 @@ def test_invalid_arguments(gpu):
     with pytest.raises(_lib.GsrError) as e:
         _lib.gsr_create(tile_w=12, tile_h=12)
     assert e.value.status == -6
+    for kw in (dict(chunk_len=24), dict(chunk_len=-2), dict(chunk_len=64, max_chunks=65), dict(max_chunks=-1)):
+        with pytest.raises(_lib.GsrError) as e:
+            _lib.gsr_create(**kw)
+        assert e.value.status == -6, kw
     R = make(gpu)
     bad = identity_camera(0, 10, 10.0)
     with pytest.raises(_lib.GsrError) as e:
