@@ -20,9 +20,12 @@ constexpr int kScanItems = 8;
 constexpr int kScanChunk = kScanThreads * kScanItems;      // 2048
 
 constexpr int kSortThreads = 256;                          // 4 wave64
-constexpr int kSortItems = 16;
+constexpr int kSortItems = 16;                             // histogram kernel
 constexpr int kSortChunk = kSortThreads * kSortItems;      // 4096
-constexpr int kWaveChunk = 64 * kSortItems;                // 1024 keys per wave
+// element count up to which a sort pass takes 4 keys per thread instead of
+// 16 (measured on MI355X: 200k depth keys 89 -> 74 us over four passes; at
+// 1.9M tile keys 4 and 8 keys per thread are 70 % and 17 % slower than 16)
+constexpr int64_t kSortSmall = int64_t(1) << 19;
 constexpr uint32_t kSpinLimit = 1u << 20;   // bounded waits of the look-back kernels
 
 int blocks_for(int64_t n, int chunk) { return (int)((n + chunk - 1) / chunk); }
@@ -252,8 +255,9 @@ __global__ void __launch_bounds__(kScanThreads) compact_visible_kernel(
 //   global_hist: digit histograms of every pass in one read of the keys
 //                (skipped when the producer of the keys accumulated them).
 //   pass:        one kernel per digit. Workgroups take tickets so that a lower
-//                ticket is always already running; each ranks its 4096 keys
-//                with wave ballots, publishes its per-digit counts, and gets
+//                ticket is always already running; each ranks its chunk of
+//                keys (256 threads x 4 or 16 keys, 4 for small sorts so
+//                that a pass spreads over more CUs) with wave ballots, publishes its per-digit counts, and gets
 //                its per-digit offset by looking back over the published
 //                counts of lower tickets (decoupled look-back). A wait on a
 //                predecessor is bounded: past the spin limit the workgroup
@@ -298,7 +302,7 @@ __global__ void __launch_bounds__(kSortThreads) global_hist_kernel(const uint32_
     if (h[e]) atomicAdd(&ghist[e], h[e]);
 }
 
-template <int RB>
+template <int RB, int ITEMS>
 __global__ void __launch_bounds__(kSortThreads) onesweep_pass_kernel(
     const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals, const uint32_t* __restrict__ n_dev,
     int64_t n_host, int shift, const uint32_t* __restrict__ ghist, uint32_t* __restrict__ status,
@@ -306,12 +310,14 @@ __global__ void __launch_bounds__(kSortThreads) onesweep_pass_kernel(
     uint32_t* __restrict__ vals_out) {
   constexpr int R = 1 << RB;
   constexpr int NW = kSortThreads / 64;
+  constexpr int CHUNK = kSortThreads * ITEMS;    // keys per workgroup
+  constexpr int WCHUNK = 64 * ITEMS;             // keys per wave
   constexpr int DPT = R / kSortThreads;          // digits owned per thread
   static_assert(R % kSortThreads == 0, "whole digits per thread");
   // wcnt (per-wave digit counts) is dead once each key has its block-local
   // offset; the staged keys and values reuse its storage
-  static_assert(NW * R >= 2 * kSortChunk || RB == 8, "staging fits in the count storage");
-  constexpr int kCountWords = NW * R > 2 * kSortChunk ? NW * R : 2 * kSortChunk;
+  static_assert(NW * R >= 2 * CHUNK || RB == 8, "staging fits in the count storage");
+  constexpr int kCountWords = NW * R > 2 * CHUNK ? NW * R : 2 * CHUNK;
   __shared__ uint32_t s_mem[kCountWords];
   __shared__ uint32_t gofs[R];         // global start of each digit's run of this block (minus its local start)
   __shared__ uint32_t lstart[R];       // block-local start of each digit's run
@@ -319,7 +325,7 @@ __global__ void __launch_bounds__(kSortThreads) onesweep_pass_kernel(
   __shared__ uint32_t s_wsum[2][NW];
   uint32_t (*wcnt)[R] = reinterpret_cast<uint32_t (*)[R]>(s_mem);
   uint32_t* s_keys = s_mem;
-  uint32_t* s_vals = s_mem + kSortChunk;
+  uint32_t* s_vals = s_mem + CHUNK;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int tid = threadIdx.x;
   const int64_t n = n_dev ? min((int64_t)*n_dev, n_host) : n_host;
@@ -329,12 +335,12 @@ __global__ void __launch_bounds__(kSortThreads) onesweep_pass_kernel(
   const uint32_t bid = s_bid;
   // workgroups past the element count have nothing to do, and no workgroup
   // that has looks at them
-  if ((int64_t)bid * kSortChunk >= n && bid > 0) return;
-  const int64_t base = (int64_t)bid * kSortChunk + (int64_t)wave * kWaveChunk;
+  if ((int64_t)bid * CHUNK >= n && bid > 0) return;
+  const int64_t base = (int64_t)bid * CHUNK + (int64_t)wave * WCHUNK;
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  uint32_t k_reg[kSortItems], v_reg[kSortItems], off[kSortItems];
+  uint32_t k_reg[ITEMS], v_reg[ITEMS], off[ITEMS];
 #pragma unroll
-  for (int r = 0; r < kSortItems; ++r) {
+  for (int r = 0; r < ITEMS; ++r) {
     const int64_t j = base + r * 64 + lane;
     const bool valid = j < n;
     const uint32_t key = valid ? keys[j] : 0u;
@@ -490,23 +496,23 @@ __global__ void __launch_bounds__(kSortThreads) onesweep_pass_kernel(
   __syncthreads();
   // block-local position of every key, then the count storage becomes the
   // staging area
-  uint32_t lp[kSortItems];
+  uint32_t lp[ITEMS];
 #pragma unroll
-  for (int r = 0; r < kSortItems; ++r) {
+  for (int r = 0; r < ITEMS; ++r) {
     const uint32_t d = (k_reg[r] >> shift) & (R - 1);
     lp[r] = off[r] == 0xFFFFFFFFu ? 0xFFFFFFFFu : lstart[d] + wcnt[wave][d] + off[r];
   }
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < kSortItems; ++r) {
+  for (int r = 0; r < ITEMS; ++r) {
     if (lp[r] == 0xFFFFFFFFu) continue;
     s_keys[lp[r]] = k_reg[r];
     s_vals[lp[r]] = v_reg[r];
   }
   __syncthreads();
   // consecutive threads write consecutive positions of each digit's run
-  const int64_t blk0 = (int64_t)bid * kSortChunk;
-  const int cnt = (int)(n - blk0 < kSortChunk ? (n - blk0 > 0 ? n - blk0 : 0) : kSortChunk);
+  const int64_t blk0 = (int64_t)bid * CHUNK;
+  const int cnt = (int)(n - blk0 < CHUNK ? (n - blk0 > 0 ? n - blk0 : 0) : CHUNK);
   for (int j = tid; j < cnt; j += kSortThreads) {
     const uint32_t key = s_keys[j];
     const uint32_t d = (key >> shift) & (R - 1);
@@ -685,10 +691,15 @@ int grid_cap(int64_t n, int block) {
 
 }  // namespace
 
+// Keys per thread of a sort pass: small sorts take short chunks, so that the
+// pass spreads over more workgroups with less serial ranking work each.
+static int sort_items(int64_t n) { return n <= kSortSmall ? 4 : 16; }
+static int64_t sort_chunk(int64_t n) { return (int64_t)kSortThreads * sort_items(n); }
+
 int64_t radix_scratch_elems(int64_t n, int bits) {
   int rb, passes;
   radix_plan(bits, &rb, &passes);
-  const int64_t nb = blocks_for(n, kSortChunk);
+  const int64_t nb = blocks_for(n, sort_chunk(n));
   // status words for every pass, global histograms, tickets
   return (int64_t)passes * (nb > 0 ? nb : 1) * (1 << rb) + passes * (1 << rb) + kMaxPasses;
 }
@@ -697,7 +708,7 @@ int64_t scan_partial_elems(int64_t n) { return 2 * (int64_t)blocks_for(n > 0 ? n
 
 uint32_t* radix_hist(uint32_t* scratch, int64_t n, int bits, int* rb, int* passes) {
   radix_plan(bits, rb, passes);
-  const int64_t nb = blocks_for(n, kSortChunk);
+  const int64_t nb = blocks_for(n, sort_chunk(n));
   return scratch + (int64_t)*passes * (nb > 0 ? nb : 1) * (1 << *rb);
 }
 
@@ -737,22 +748,27 @@ void radix_sort_pairs(uint32_t*& keys, uint32_t*& vals, uint32_t*& keys_alt, uin
   int rb, passes;
   radix_plan(bits, &rb, &passes);
   const int R = 1 << rb;
-  const int nb = blocks_for(n, kSortChunk);
+  const int items = sort_items(n);
+  const int nb = blocks_for(n, sort_chunk(n));
   uint32_t* status = scratch;
   uint32_t* ghist = scratch + (int64_t)passes * nb * R;
   uint32_t* tickets = ghist + passes * R;
   const int64_t clear_n = radix_scratch_elems(n, bits);
   if (clear) fill_u32_kernel<<<grid_cap(clear_n, 256), 256, 0, st>>>(scratch, 0u, clear_n);
-  if (!hist_ready) global_hist_kernel<<<nb, kSortThreads, 0, st>>>(keys, n_dev, n, rb, passes, ghist);
+  if (!hist_ready)
+    global_hist_kernel<<<blocks_for(n, kSortChunk), kSortThreads, 0, st>>>(keys, n_dev, n, rb, passes, ghist);
   for (int p = 0; p < passes; ++p) {
+    uint32_t* stp = status + (int64_t)p * nb * R;
+    const int sh = rb * p;
     if (rb == 11)
-      onesweep_pass_kernel<11><<<nb, kSortThreads, 0, st>>>(keys, vals, n_dev, n, rb * p, ghist + p * R,
-                                                            status + (int64_t)p * nb * R, tickets + p, err, keys_alt,
-                                                            vals_alt);
+      onesweep_pass_kernel<11, 16><<<nb, kSortThreads, 0, st>>>(keys, vals, n_dev, n, sh, ghist + p * R, stp,
+                                                                tickets + p, err, keys_alt, vals_alt);
+    else if (items == 4)
+      onesweep_pass_kernel<8, 4><<<nb, kSortThreads, 0, st>>>(keys, vals, n_dev, n, sh, ghist + p * R, stp,
+                                                              tickets + p, err, keys_alt, vals_alt);
     else
-      onesweep_pass_kernel<8><<<nb, kSortThreads, 0, st>>>(keys, vals, n_dev, n, rb * p, ghist + p * R,
-                                                           status + (int64_t)p * nb * R, tickets + p, err, keys_alt,
-                                                           vals_alt);
+      onesweep_pass_kernel<8, 16><<<nb, kSortThreads, 0, st>>>(keys, vals, n_dev, n, sh, ghist + p * R, stp,
+                                                               tickets + p, err, keys_alt, vals_alt);
     uint32_t* t = keys; keys = keys_alt; keys_alt = t;
     t = vals; vals = vals_alt; vals_alt = t;
   }
