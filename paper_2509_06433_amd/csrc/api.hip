@@ -145,7 +145,7 @@ static void set_chunking(const gsr_ctx* ctx, Buffers& B, const RenderPlan& P, Bl
   ba.ckpt_stride = P.npix;
 }
 
-int launch_back(gsr_ctx* ctx, Buffers& B, RenderPlan& P, hipStream_t st) {
+int launch_back(gsr_ctx* ctx, Buffers& B, RenderPlan& P, hipStream_t st, const FusedLoss* loss) {
   uint32_t* totals = as<uint32_t>(B.total);
   uint32_t* ik = as<uint32_t>(B.ikeys);
   uint32_t* iv = as<uint32_t>(B.ivals);
@@ -191,6 +191,12 @@ int launch_back(gsr_ctx* ctx, Buffers& B, RenderPlan& P, hipStream_t st) {
   ba.g2 = nullptr;
   for (int k = 0; k < 3; ++k) ba.bg[k] = ctx->bg[k];
   set_chunking(ctx, B, P, ba);
+  if (loss) {
+    ba.loss_target = loss->targets;
+    ba.loss_grad = as<ViewImages>(B.images2);
+    ba.depth_weight = loss->depth_weight;
+    ba.loss = loss->loss;
+  }
   {
     StageTimer tm(ctx, GSR_STAGE_BLEND_FWD, st);
     launch_blend_forward(ba, ctx->tile_w, ctx->tile_h, ctx->ppt, st);
@@ -200,7 +206,7 @@ int launch_back(gsr_ctx* ctx, Buffers& B, RenderPlan& P, hipStream_t st) {
 }
 
 int launch_bwd(gsr_ctx* ctx, Buffers& B, const RenderPlan& P, const float* params, float* grad_params,
-               bool clear_g2, hipStream_t st) {
+               bool clear_g2, bool overwrite_grad, hipStream_t st) {
   if (P.total == 0) return GSR_OK;
   if (clear_g2) {
     StageTimer tm(ctx, GSR_STAGE_ZERO, st);
@@ -230,7 +236,7 @@ int launch_bwd(gsr_ctx* ctx, Buffers& B, const RenderPlan& P, const float* param
   {
     StageTimer tm(ctx, GSR_STAGE_PROJECT_BWD, st);
     launch_project_backward(params, P.num, P.stride, P.deg, P.nv, as<ViewDesc>(B.views), ctx->znear,
-                            as<float>(B.g2), as<uint32_t>(B.ntiles), grad_params, st);
+                            as<float>(B.g2), as<uint32_t>(B.ntiles), grad_params, overwrite_grad, st);
   }
   CHECK_LAUNCH(ctx);
   return GSR_OK;
@@ -306,7 +312,7 @@ int backward_impl(gsr_ctx* ctx, const gsr_gaussians* g, int32_t nv, const gsr_ca
   std::vector<ViewImages> ims(nv);
   for (int v = 0; v < nv; ++v) ims[v] = ViewImages{grad_out[v].rgb, grad_out[v].depth, grad_out[v].alpha};
   RET_IF(upload(ctx, B.images2.p, ims.data(), sizeof(ViewImages) * nv, st));
-  return launch_bwd(ctx, B, P, g->params, grad_params, true, st);
+  return launch_bwd(ctx, B, P, g->params, grad_params, true, false, st);
 }
 
 }  // namespace

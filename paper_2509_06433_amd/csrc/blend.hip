@@ -115,6 +115,12 @@ __device__ __forceinline__ void write_ckpt_sums(const BlendArgs& a, uint32_t slo
   for (int f = 0; f < 4; ++f) c[(f + 1) * st] = dC[f];
 }
 
+__device__ __forceinline__ float wave_sum(float x) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, 64);
+  return x;
+}
+
 __device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) x = max(x, (uint32_t)__shfl_xor((int)x, m, 64));
@@ -150,6 +156,7 @@ __global__ void __launch_bounds__(TW * TH / PPT) blend_forward_kernel(BlendArgs 
   constexpr int BATCH = NT;
   __shared__ float4 s_q0[BATCH], s_q1[BATCH], s_q2[BATCH];
   __shared__ uint32_t s_tl;
+  __shared__ float s_loss[NT / 64];
   const int tile = a.order ? (int)a.order[blockIdx.x] : (int)blockIdx.x;
   const int view = find_view(a.views, a.num_views, tile);
   const ViewDesc& V = a.views[view];
@@ -260,14 +267,41 @@ __global__ void __launch_bounds__(TW * TH / PPT) blend_forward_kernel(BlendArgs 
   }
   tl = wave_max_u32(tl);
   if ((tid & 63) == 0) atomicMax(&s_tl, tl);
-  __syncthreads();
-  if (tid == 0) a.tile_last[tile] = s_tl;
-}
-
-__device__ __forceinline__ float wave_sum(float x) {
+  if (a.loss_target) {
+    // the L1 mapping loss of the composited pixels, with the same float
+    // operations as loss_l1_kernel, so the image gradients are identical
+    const ViewImages tg = a.loss_target[view], gr = a.loss_grad[view];
+    const float inv3 = 1.0f / (3.0f * (float)HW), inv1 = a.depth_weight / (float)HW;
+    float acc = 0.0f;
 #pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, 64);
-  return x;
+    for (int i = 0; i < PPT; ++i) {
+      if (!inside[i]) continue;
+      const int64_t p = (int64_t)py[i] * V.width + px;
+      const float out[3] = {fmaf(T[i], a.bg[0], C0[i]), fmaf(T[i], a.bg[1], C1[i]), fmaf(T[i], a.bg[2], C2[i])};
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) {
+        const float d = out[ch] - tg.rgb[ch * HW + p];
+        gr.rgb[ch * HW + p] = d > 0.0f ? inv3 : (d < 0.0f ? -inv3 : 0.0f);
+        acc += fabsf(d) * inv3;
+      }
+      const float dd = D[i] - tg.depth[p];
+      gr.depth[p] = dd > 0.0f ? inv1 : (dd < 0.0f ? -inv1 : 0.0f);
+      acc += fabsf(dd) * inv1;
+      if (gr.alpha) gr.alpha[p] = 0.0f;
+    }
+    acc = wave_sum(acc);
+    if ((tid & 63) == 0) s_loss[tid >> 6] = acc;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    a.tile_last[tile] = s_tl;
+    if (a.loss_target && a.loss) {
+      float sum = 0.0f;
+#pragma unroll
+      for (int w = 0; w < NT / 64; ++w) sum += s_loss[w];
+      unsafeAtomicAdd(a.loss, sum);
+    }
+  }
 }
 
 template <int CTRL, int ROW_MASK>

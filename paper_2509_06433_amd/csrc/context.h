@@ -330,10 +330,13 @@ inline int bits_for(int64_t max_key) {
 //                 instance offsets; B.total[0] = count.
 //   launch_back:  instance emission (at most plan.capacity, with the tile-key
 //                 histograms), tile sort, tile ranges, compositing. Counts are
-//                 read on the device.
-//   launch_bwd:   blend backward and projection backward into grad_params,
-//                 image gradients from the descriptors in B.images2; g2 is
-//                 zeroed first unless clear_g2 is false.
+//                 read on the device. With loss, the compositing also forms
+//                 the L1 loss against loss->targets and writes its image
+//                 gradients through the descriptors in B.images2.
+//   launch_bwd:   blend backward and projection backward into grad_params
+//                 (added, or overwritten with overwrite_grad), image
+//                 gradients from the descriptors in B.images2; g2 is zeroed
+//                 first unless clear_g2 is false.
 // The launch_* functions make no allocation, copy or synchronisation, so a
 // stream capture can record them.
 int plan_render(gsr_ctx* ctx, const gsr_gaussians* g, int32_t nv, const gsr_camera* cams, RenderPlan* plan);
@@ -341,9 +344,14 @@ int size_render(gsr_ctx* ctx, Buffers& B, RenderPlan& plan, const gsr_image* out
 void front_clears(Buffers& B, const RenderPlan& plan, ClearList& L);
 void back_clears(Buffers& B, const RenderPlan& plan, ClearList& L);
 int launch_front(gsr_ctx* ctx, Buffers& B, RenderPlan& plan, const float* params, hipStream_t st);
-int launch_back(gsr_ctx* ctx, Buffers& B, RenderPlan& plan, hipStream_t st);
+struct FusedLoss {
+  const ViewImages* targets;   // device descriptors, per view (rgb, depth)
+  float depth_weight;
+  float* loss;                 // added to; may be null
+};
+int launch_back(gsr_ctx* ctx, Buffers& B, RenderPlan& plan, hipStream_t st, const FusedLoss* loss = nullptr);
 int launch_bwd(gsr_ctx* ctx, Buffers& B, const RenderPlan& plan, const float* params, float* grad_params,
-               bool clear_g2, hipStream_t st);
+               bool clear_g2, bool overwrite_grad, hipStream_t st);
 int size_instances(gsr_ctx* ctx, Buffers& B, const RenderPlan& plan);
 void free_buffers(Buffers& B);
 // Frees the captured mapping iteration and its buffers (iteration.hip).

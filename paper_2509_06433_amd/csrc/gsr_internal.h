@@ -49,12 +49,13 @@ void launch_project(const float* params, int64_t n, int64_t stride, int deg, int
                     const ViewDesc* views, int tile_w, int tile_h, float znear, Splat* splats,
                     int4* rect, uint32_t* ntiles, uint32_t* zkey, uint32_t* zhist, int zrb, int zpasses,
                     hipStream_t st);
-// Chain rule from screen-space gradients g2[V*N][10] to grad_params (+=).
+// Chain rule from screen-space gradients g2[V*N][10] to grad_params (+=, or
+// with overwrite = every plane written, zero where no view contributed).
 // Only (view, Gaussian) pairs with a nonzero tile count (ntiles[V*N]) are
 // visited: one thread per Gaussian walks its own visible views.
 void launch_project_backward(const float* params, int64_t n, int64_t stride, int deg, int num_views,
                              const ViewDesc* views, float znear, const float* g2, const uint32_t* ntiles,
-                             float* grad, hipStream_t st);
+                             float* grad, bool overwrite, hipStream_t st);
 // Inspection copy of the splats of one view: out[n][16] (see gsr_copy_splats).
 void launch_export_splats(const float* params, int64_t n, int64_t stride, const ViewDesc* view, float znear,
                           const Splat* splats, const int4* rect, float* out, hipStream_t st);
@@ -166,6 +167,13 @@ struct BlendArgs {
   int32_t chunk_len;
   int32_t max_chunks;
   uint32_t* tile_last;          // per tile: largest last position of its pixels (forward writes)
+  // Forward only, optional: the L1 mapping loss fused into the compositing
+  // (as launch_loss_l1 computes it): targets per view (rgb, depth), gradient
+  // images written per view, the loss added to *loss.
+  const ViewImages* loss_target;
+  const ViewImages* loss_grad;
+  float depth_weight;
+  float* loss;
 };
 constexpr int kCkptFields = 5;
 bool blend_supported(int tile_w, int tile_h);

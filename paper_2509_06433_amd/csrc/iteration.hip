@@ -203,8 +203,9 @@ int record_iteration(gsr_ctx* ctx, GraphState* G, float* params, float* grad, fl
   ClearList L{};
   front_clears(B, P, L);
   back_clears(B, P, L);
+  // (the gradient is overwritten by the projection backward, so it is not
+  // cleared)
   if (loss) L.add(loss, 1);
-  L.add(grad, (int64_t)planes * P.stride);
   L.add(B.g2.p, P.total * G2_N);
   {
     StageTimer tm(ctx, GSR_STAGE_ZERO, st);
@@ -212,16 +213,10 @@ int record_iteration(gsr_ctx* ctx, GraphState* G, float* params, float* grad, fl
   }
   CHECK_LAUNCH(ctx);
   RET_IF(launch_front(ctx, B, P, params, st));
-  RET_IF(launch_back(ctx, B, P, st));
-  int maxpix = 0;
-  for (int v = 0; v < P.nv; ++v) maxpix = std::max(maxpix, P.views[v].width * P.views[v].height);
-  {
-    StageTimer tm(ctx, GSR_STAGE_LOSS, st);
-    launch_loss_l1(as<ViewDesc>(B.views), as<ViewImages>(B.images), as<ViewImages>(G->tdesc),
-                   as<ViewImages>(B.images2), P.nv, maxpix, depth_weight, loss, false, st);
-  }
-  CHECK_LAUNCH(ctx);
-  RET_IF(launch_bwd(ctx, B, P, params, grad, false, st));
+  // the L1 loss and its image gradients are formed by the compositing itself
+  const FusedLoss fl{as<ViewImages>(G->tdesc), depth_weight, loss};
+  RET_IF(launch_back(ctx, B, P, st, &fl));
+  RET_IF(launch_bwd(ctx, B, P, params, grad, false, true, st));
   if (adam) {
     StageTimer tm(ctx, GSR_STAGE_ADAM, st);
     launch_adam(params, grad, adam->m, adam->v, P.num, P.stride, planes, as<float>(G->lrbuf), adam->beta1,

@@ -650,7 +650,7 @@ __global__ void __launch_bounds__(256) project_backward_kernel(const float* __re
                                                                int num_views, const ViewDesc* __restrict__ views,
                                                                const float* __restrict__ g2,
                                                                const uint32_t* __restrict__ ntiles,
-                                                               float* __restrict__ grad) {
+                                                               float* __restrict__ grad, bool overwrite) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     double gmean[3] = {0, 0, 0}, gls[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, glogit = 0.0;
@@ -677,6 +677,19 @@ __global__ void __launch_bounds__(256) project_backward_kernel(const float* __re
       touched = true;
       const ViewDesc& V = views[cur];
       chain_view<DEG>(P, stride, i, V, G, coef, gmean, gls, gq, glogit, gsh);
+    }
+    if (overwrite) {
+      // every plane is written (zero for a Gaussian no view composited)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) grad[(0 + j) * stride + i] = (float)gmean[j];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) grad[(3 + j) * stride + i] = (float)gls[j];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) grad[(6 + j) * stride + i] = (float)gq[j];
+      grad[10 * stride + i] = (float)glogit;
+#pragma unroll
+      for (int k = 0; k < 3 * K; ++k) grad[(11 + k) * stride + i] = gsh[k];
+      continue;
     }
     if (!touched) continue;
 #pragma unroll
@@ -743,15 +756,23 @@ void launch_project(const float* params, int64_t n, int64_t stride, int deg, int
 
 void launch_project_backward(const float* params, int64_t n, int64_t stride, int deg, int num_views,
                              const ViewDesc* views, float znear, const float* g2, const uint32_t* ntiles, float* grad,
-                             hipStream_t st) {
+                             bool overwrite, hipStream_t st) {
   (void)znear;
   if (n == 0) return;
   const int gsz = grid_for(n, 256);
   switch (deg) {
-    case 0: project_backward_kernel<0><<<gsz, 256, 0, st>>>(params, n, stride, num_views, views, g2, ntiles, grad); break;
-    case 1: project_backward_kernel<1><<<gsz, 256, 0, st>>>(params, n, stride, num_views, views, g2, ntiles, grad); break;
-    case 2: project_backward_kernel<2><<<gsz, 256, 0, st>>>(params, n, stride, num_views, views, g2, ntiles, grad); break;
-    default: project_backward_kernel<3><<<gsz, 256, 0, st>>>(params, n, stride, num_views, views, g2, ntiles, grad); break;
+    case 0:
+      project_backward_kernel<0><<<gsz, 256, 0, st>>>(params, n, stride, num_views, views, g2, ntiles, grad, overwrite);
+      break;
+    case 1:
+      project_backward_kernel<1><<<gsz, 256, 0, st>>>(params, n, stride, num_views, views, g2, ntiles, grad, overwrite);
+      break;
+    case 2:
+      project_backward_kernel<2><<<gsz, 256, 0, st>>>(params, n, stride, num_views, views, g2, ntiles, grad, overwrite);
+      break;
+    default:
+      project_backward_kernel<3><<<gsz, 256, 0, st>>>(params, n, stride, num_views, views, g2, ntiles, grad, overwrite);
+      break;
   }
 }
 
