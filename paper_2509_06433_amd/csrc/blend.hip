@@ -206,10 +206,12 @@ __global__ void __launch_bounds__(TW * TH / PPT) blend_forward_kernel(BlendArgs 
     const uint32_t pos0 = b0 - rg.x + 1;
     int k = 0;
     for (; k + 1 < cnt; k += 2) {
+      // the wave leaves the batch when all its pixels have stopped; the exit
+      // is wave-uniform so that the loop state stays in scalar registers
       bool busy = false;
 #pragma unroll
       for (int i = 0; i < PPT; ++i) busy = busy || !done[i];
-      if (!busy) break;
+      if (__ballot(busy) == 0ull) break;
       if (CK && b0 - rg.x + k == nextck) {
         chunk_boundary<PPT>(a, nextck, ck_end, done, pix, T, dC, mych);
       }
