@@ -47,6 +47,7 @@ int size_instances(gsr_ctx* ctx, Buffers& B, const RenderPlan& P) {
   RET_IF(ensure(ctx, B.ikeys_alt, i4));
   RET_IF(ensure(ctx, B.ivals_alt, i4));
   RET_IF(ensure(ctx, B.hist2, sizeof(uint32_t) * (size_t)radix_scratch_elems(P.capacity, bits_for(P.ntiles - 1))));
+  RET_IF(ensure(ctx, B.block_rank, sizeof(uint32_t) * (size_t)emit_plan_elems(P.capacity)));
   return GSR_OK;
 }
 
@@ -158,7 +159,8 @@ int launch_back(gsr_ctx* ctx, Buffers& B, RenderPlan& P, hipStream_t st, const F
   {
     StageTimer tm(ctx, GSR_STAGE_EMIT, st);
     launch_emit(P.sorted_splats, as<uint32_t>(B.offsets), totals, totals + 3, as<int4>(B.rect), P.total, P.num,
-                as<ViewDesc>(B.views), ctx->tile_w, ctx->tile_h, ik, iv, P.capacity, totals + 2, thist, tbits, st);
+                as<ViewDesc>(B.views), ctx->tile_w, ctx->tile_h, ik, iv, P.capacity, totals + 2, thist, tbits,
+                as<uint32_t>(B.block_rank), st);
   }
   CHECK_LAUNCH(ctx);
   {
@@ -246,7 +248,7 @@ void free_buffers(Buffers& B) {
   DevBuf* bufs[] = {&B.views, &B.images, &B.images2, &B.splats, &B.rect, &B.ntiles, &B.zkey, &B.svals,
                     &B.zkey_alt, &B.svals_alt, &B.offsets, &B.ikeys, &B.ivals, &B.ikeys_alt, &B.ivals_alt,
                     &B.hist, &B.hist2, &B.partials, &B.ranges, &B.order, &B.tfinal, &B.last, &B.g2, &B.total,
-                    &B.tile_last, &B.ckpt};
+                    &B.tile_last, &B.ckpt, &B.block_rank};
   for (DevBuf* b : bufs) {
     if (b->p) (void)hipFree(b->p);
     b->p = nullptr;

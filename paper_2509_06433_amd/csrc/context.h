@@ -39,6 +39,7 @@ struct Buffers {
   DevBuf hist, hist2, partials, ranges, order, tfinal, last, g2;   // hist: depth sort, hist2: tile sort
   DevBuf total;   // [0] instance count, [1] wait expired, [2] instance overflow, [3] visible splats
   DevBuf tile_last, ckpt;   // per tile: longest walk; per pixel: state at the backward's chunk boundaries
+  DevBuf block_rank;        // emission: first depth rank of every block of output positions
 };
 
 // Sizes and final buffer roles of one forward render.

@@ -104,11 +104,13 @@ void launch_compact_visible(const uint32_t* ntiles, const uint32_t* keys, int64_
 // emit_histogram_fits(hist_bits)) the digit histograms of the written tile
 // keys, for a sort on hist_bits bits, are accumulated there.
 // The depth-sorted splats are sorted_s[0 .. min(*count_dev, count)).
+// block_rank: scratch of emit_plan_elems(capacity) words.
+int64_t emit_plan_elems(int64_t capacity);
 void launch_emit(const uint32_t* sorted_s, const uint32_t* offsets, const uint32_t* total_dev,
                  const uint32_t* count_dev, const int4* rect, int64_t count, int64_t n, const ViewDesc* views,
                  int tile_w, int tile_h, uint32_t* keys,
                  uint32_t* vals, int64_t capacity, uint32_t* overflow, uint32_t* hist, int hist_bits,
-                 hipStream_t st);
+                 uint32_t* block_rank, hipStream_t st);
 // ranges[t] = (start, end) of global tile t in the sorted key array of
 // min(*n_dev, count) instances (count if n_dev is null); clear = false: the
 // caller has zeroed ranges.

@@ -524,70 +524,95 @@ __global__ void __launch_bounds__(kSortThreads) onesweep_pass_kernel(
   }
 }
 
-// Instance emission, load-balanced: workgroup b owns the 256 depth ranks
-// [256 b, 256 b + 256) and the contiguous output range of their instances;
-// each thread writes output positions round-robin and finds the owning
-// Gaussian by binary search over the 257 staged offsets.
-constexpr int kEmitChunk = 256;
-__global__ void __launch_bounds__(kEmitChunk) emit_kernel(const uint32_t* __restrict__ sorted_s,
-                                                         const uint32_t* __restrict__ offsets,
-                                                         const uint32_t* __restrict__ total_dev,
-                                                         const uint32_t* __restrict__ count_dev,
-                                                         const int4* __restrict__ rect, int64_t count_host, int64_t n,
-                                                         const ViewDesc* __restrict__ views, int tile_w, int tile_h,
-                                                         uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
-                                                         int64_t capacity, uint32_t* __restrict__ overflow,
-                                                         uint32_t* __restrict__ hist, int hist_rb, int hist_passes) {
-  __shared__ uint32_t s_off[kEmitChunk + 1];
-  __shared__ uint32_t s_hist[kMaxRadix];       // hist_passes * 2^hist_rb <= 2048
-  __shared__ uint32_t s_sid[kEmitChunk];
-  __shared__ int3 s_geo[kEmitChunk];      // first tile id of the rectangle, rectangle width, view row pitch
-  const int64_t r0 = (int64_t)blockIdx.x * kEmitChunk;
+// Instance emission, balanced over the output: workgroup b writes the
+// output positions [1024 b, 1024 b + 1024). emit_plan_kernel first records,
+// per block, the depth rank whose instances hold the block's first position;
+// the block's ranks (at most 1024, every listed splat has at least one
+// instance) are staged with their offsets, and each thread writes output
+// positions round-robin, finding the owning rank by binary search over the
+// staged offsets. Positions past `capacity` are dropped and flagged.
+constexpr int kEmitBlock = 1024;
+constexpr int kEmitThreads = 256;
+
+__global__ void __launch_bounds__(256) emit_plan_kernel(const uint32_t* __restrict__ offsets,
+                                                        const uint32_t* __restrict__ total_dev,
+                                                        const uint32_t* __restrict__ count_dev, int64_t count_host,
+                                                        int64_t nblocks, uint32_t* __restrict__ block_rank) {
   const int64_t count = count_dev ? min((int64_t)*count_dev, count_host) : count_host;
-  if (r0 >= count && blockIdx.x > 0) return;
   const uint32_t total = *total_dev;
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < count; r += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t a = offsets[r], b = r + 1 < count ? offsets[r + 1] : total;
+    // blocks whose first position lies in [a, b)
+    for (int64_t blk = ((int64_t)a + kEmitBlock - 1) / kEmitBlock; blk * kEmitBlock < (int64_t)b && blk < nblocks; ++blk)
+      block_rank[blk] = (uint32_t)r;
+  }
+}
+
+__global__ void __launch_bounds__(kEmitThreads) emit_kernel(const uint32_t* __restrict__ sorted_s,
+                                                           const uint32_t* __restrict__ offsets,
+                                                           const uint32_t* __restrict__ total_dev,
+                                                           const uint32_t* __restrict__ count_dev,
+                                                           const uint32_t* __restrict__ block_rank,
+                                                           const int4* __restrict__ rect, int64_t count_host, int64_t n,
+                                                           const ViewDesc* __restrict__ views, int tile_w, int tile_h,
+                                                           uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                                                           int64_t capacity, uint32_t* __restrict__ overflow,
+                                                           uint32_t* __restrict__ hist, int hist_rb, int hist_passes) {
+  __shared__ uint32_t s_off[kEmitBlock + 1];
+  __shared__ uint32_t s_sid[kEmitBlock];
+  __shared__ int3 s_geo[kEmitBlock];      // first tile id of the rectangle, rectangle width, view row pitch
+  __shared__ uint32_t s_hist[kMaxRadix];  // hist_passes * 2^hist_rb <= 2048
   const int tid = threadIdx.x;
+  const uint32_t total = *total_dev;
   if (blockIdx.x == 0 && tid == 0 && (int64_t)total > capacity) atomicOr(overflow, 1u);
+  const int64_t count = count_dev ? min((int64_t)*count_dev, count_host) : count_host;
+  const int64_t o0 = (int64_t)blockIdx.x * kEmitBlock;
+  const int64_t written = min((int64_t)total, capacity);
+  const int64_t oend = min(o0 + kEmitBlock, written);
+  if (o0 >= oend || count == 0) return;
   const int hR = 1 << hist_rb;
   if (hist)
-    for (int e = tid; e < hist_passes * hR; e += kEmitChunk) s_hist[e] = 0u;
-  const int64_t r = r0 + tid;
-  s_off[tid] = r < count ? offsets[r] : total;
-  const uint32_t sid = r < count ? sorted_s[r] : 0u;
-  s_sid[tid] = sid;
-  if (r < count) {
+    for (int e = tid; e < hist_passes * hR; e += kEmitThreads) s_hist[e] = 0u;
+  // ranks [r0, r_end) hold this block's positions
+  // (block b + 1's start is read only if that block exists and starts
+  // inside the output; it holds the rank of position 1024 (b + 1))
+  const int64_t r0 = block_rank[blockIdx.x];
+  const bool next = (int64_t)blockIdx.x + 1 < (int64_t)gridDim.x && o0 + kEmitBlock < written;
+  const int64_t r_end = next ? min((int64_t)block_rank[blockIdx.x + 1] + 1, count) : count;
+  const int nr = (int)min(r_end - r0, (int64_t)kEmitBlock);
+  if (r0 >= count || nr <= 0) return;
+  for (int j = tid; j < nr; j += kEmitThreads) {
+    const int64_t r = r0 + j;
+    s_off[j] = offsets[r];
+    const uint32_t sid = sorted_s[r];
+    s_sid[j] = sid;
     const int4 pr = rect[sid];
-    if (pr.z >= pr.x) {
-      const ViewDesc& V = views[(int)(sid / (uint64_t)n)];
-      const int tx0 = pr.x / tile_w, tx1 = pr.z / tile_w, ty0 = pr.y / tile_h;
-      s_geo[tid] = make_int3(V.tile_offset + ty0 * V.tiles_x + tx0, tx1 - tx0 + 1, V.tiles_x);
-    }
+    const ViewDesc& V = views[(int)(sid / (uint64_t)n)];
+    const int tx0 = pr.x / tile_w, tx1 = pr.z / tile_w, ty0 = pr.y / tile_h;
+    s_geo[j] = make_int3(V.tile_offset + ty0 * V.tiles_x + tx0, tx1 - tx0 + 1, V.tiles_x);
   }
-  if (tid == 0) s_off[kEmitChunk] = (r0 + kEmitChunk < count) ? offsets[r0 + kEmitChunk] : total;
+  if (tid == 0) s_off[nr] = r0 + nr < count ? offsets[r0 + nr] : total;
   __syncthreads();
-  const uint32_t start = s_off[0], end = s_off[kEmitChunk];
-  for (uint32_t o = start + tid; o < end; o += kEmitChunk) {
-    int lo = 0, hi = kEmitChunk;                  // s_off[lo] <= o < s_off[hi]
+  for (int64_t o = o0 + tid; o < oend; o += kEmitThreads) {
+    int lo = 0, hi = nr;                  // s_off[lo] <= o < s_off[hi]
     while (hi - lo > 1) {
       const int mid = (lo + hi) >> 1;
-      if (s_off[mid] <= o) lo = mid;
+      if (s_off[mid] <= (uint32_t)o) lo = mid;
       else hi = mid;
     }
     const int3 geo = s_geo[lo];
     const uint32_t wdt = (uint32_t)geo.y;
-    const uint32_t local = o - s_off[lo];
+    const uint32_t local = (uint32_t)o - s_off[lo];
     const uint32_t dy = local / wdt, dx = local - dy * wdt;
-    if ((int64_t)o < capacity) {
-      const uint32_t key = (uint32_t)geo.x + dy * (uint32_t)geo.z + dx;
-      keys[o] = key;
-      vals[o] = s_sid[lo];
-      if (hist)
-        for (int p = 0; p < hist_passes; ++p) atomicAdd(&s_hist[p * hR + ((key >> (hist_rb * p)) & (hR - 1))], 1u);
-    }
+    const uint32_t key = (uint32_t)geo.x + dy * (uint32_t)geo.z + dx;
+    keys[o] = key;
+    vals[o] = s_sid[lo];
+    if (hist)
+      for (int p = 0; p < hist_passes; ++p) atomicAdd(&s_hist[p * hR + ((key >> (hist_rb * p)) & (hR - 1))], 1u);
   }
   if (hist) {
     __syncthreads();
-    for (int e = tid; e < hist_passes * hR; e += kEmitChunk)
+    for (int e = tid; e < hist_passes * hR; e += kEmitThreads)
       if (s_hist[e]) atomicAdd(&hist[e], s_hist[e]);
   }
 }
@@ -774,19 +799,28 @@ void radix_sort_pairs(uint32_t*& keys, uint32_t*& vals, uint32_t*& keys_alt, uin
   }
 }
 
+int64_t emit_plan_elems(int64_t capacity) { return (capacity + kEmitBlock - 1) / kEmitBlock + 1; }
+
 void launch_emit(const uint32_t* sorted_s, const uint32_t* offsets, const uint32_t* total_dev,
                  const uint32_t* count_dev, const int4* rect, int64_t count, int64_t n, const ViewDesc* views,
                  int tile_w, int tile_h, uint32_t* keys,
                  uint32_t* vals, int64_t capacity, uint32_t* overflow, uint32_t* hist, int hist_bits,
-                 hipStream_t st) {
+                 uint32_t* block_rank, hipStream_t st) {
   if (count == 0) return;
   int rb = 8, hp = 0;
   if (hist_bits > 0) radix_plan(hist_bits, &rb, &hp);
   const bool fits = hp >= 1 && hp * (1 << rb) <= kMaxRadix;
-  emit_kernel<<<blocks_for(count, kEmitChunk), kEmitChunk, 0, st>>>(sorted_s, offsets, total_dev, count_dev, rect,
-                                                                     count, n,
-                                                                     views, tile_w, tile_h, keys, vals, capacity,
-                                                                     overflow, fits ? hist : nullptr, rb, hp);
+  const int64_t nblocks = (capacity + kEmitBlock - 1) / kEmitBlock;
+  if (nblocks == 0) {
+    // no instance slot: only the overflow flag can be raised
+    emit_kernel<<<1, kEmitThreads, 0, st>>>(sorted_s, offsets, total_dev, count_dev, block_rank, rect, count, n, views,
+                                            tile_w, tile_h, keys, vals, capacity, overflow, nullptr, rb, hp);
+    return;
+  }
+  emit_plan_kernel<<<grid_cap(count, 256), 256, 0, st>>>(offsets, total_dev, count_dev, count, nblocks, block_rank);
+  emit_kernel<<<(unsigned)nblocks, kEmitThreads, 0, st>>>(sorted_s, offsets, total_dev, count_dev, block_rank, rect,
+                                                          count, n, views, tile_w, tile_h, keys, vals, capacity,
+                                                          overflow, fits ? hist : nullptr, rb, hp);
 }
 
 bool emit_histogram_fits(int bits) {
