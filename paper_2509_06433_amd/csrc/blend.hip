@@ -35,10 +35,11 @@ constexpr float kLog2e = 1.4426950408889634f;
 // q1 = (-C/2, opacity, z, 0), q2 = (r, g, b, 0). Halving and negating are
 // exact, so ((-A/2 dx) dx + (-C/2 dy) dy) + (-B dx) dy rounds exactly like
 // -((A dx) dx + (C dy) dy)/2 - (B dx) dy.
-__device__ __forceinline__ void stage_record(const Splat& sp, float4& q0, float4& q1, float4& q2) {
-  q0 = make_float4(sp.w0.x, sp.w0.y, -0.5f * sp.w1.x, -sp.w1.y);
-  q1 = make_float4(-0.5f * sp.w1.z, sp.w0.w, sp.w0.z, 0.0f);
-  q2 = sp.w2;
+__device__ __forceinline__ void stage_record(const float4& w0, const float4& w1, const float4& w2, float4& q0,
+                                             float4& q1, float4& q2) {
+  q0 = make_float4(w0.x, w0.y, -0.5f * w1.x, -w1.y);
+  q1 = make_float4(-0.5f * w1.z, w0.w, w0.z, 0.0f);
+  q2 = make_float4(w2.x, w2.y, w2.z, 0.0f);
 }
 
 // Alpha of one pair. Returns false when the pair is skipped (exponent
@@ -198,8 +199,8 @@ __global__ void __launch_bounds__(TW * TH / PPT) blend_forward_kernel(BlendArgs 
     if (__syncthreads_count(all_done) == NT) break;
     const uint32_t j = b0 + tid;
     if (j < rg.y) {
-      const Splat sp = a.splats[a.inst_vals[j]];
-      stage_record(sp, s_q0[tid], s_q1[tid], s_q2[tid]);
+      const Splat* sp = a.splats + a.inst_vals[j];
+      stage_record(sp->w0, sp->w1, sp->w2, s_q0[tid], s_q1[tid], s_q2[tid]);
     }
     __syncthreads();
     const int cnt = (int)min((uint32_t)BATCH, rg.y - b0);
@@ -502,32 +503,15 @@ blend_backward_kernel(BlendArgs a) {
   const uint32_t wlast = __builtin_amdgcn_readfirstlane(wave_max_u32(tmax));
   // the unit walks positions [lo, top) from the back
   const int64_t base = (int64_t)rg.x + lo;
-  // the next (earlier) batch's record is loaded into registers while this
-  // one is processed, so its global latency overlaps the arithmetic
-  uint32_t nsid = 0;
-  Splat nxt;
-  {
-    const int64_t bend = (int64_t)rg.x + top;
-    const int64_t b0 = bend - BATCH > base ? bend - BATCH : base;
-    if (tid < (int)(bend - b0)) {
-      nsid = a.inst_vals[b0 + tid];
-      nxt = a.splats[nsid];
-    }
-  }
   for (int64_t bend = (int64_t)rg.x + top; bend > base; bend -= BATCH) {
     const int64_t b0 = bend - BATCH > base ? bend - BATCH : base;
     const int cnt = (int)(bend - b0);
     __syncthreads();
     if (tid < cnt) {
-      s_id[tid] = nsid;
-      stage_record(nxt, s_q0[tid], s_q1[tid], s_q2[tid]);
-    }
-    {
-      const int64_t pend = b0, pb0 = pend - BATCH > base ? pend - BATCH : base;
-      if (pend > base && tid < (int)(pend - pb0)) {
-        nsid = a.inst_vals[pb0 + tid];
-        nxt = a.splats[nsid];
-      }
+      const uint32_t sid = a.inst_vals[b0 + tid];
+      s_id[tid] = sid;
+      const Splat* sp = a.splats + sid;
+      stage_record(sp->w0, sp->w1, sp->w2, s_q0[tid], s_q1[tid], s_q2[tid]);
     }
     {
       float* mine = &s_red[wave][0][0][0];
