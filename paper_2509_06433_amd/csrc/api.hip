@@ -158,8 +158,8 @@ int launch_back(gsr_ctx* ctx, Buffers& B, RenderPlan& P, hipStream_t st, const F
   uint32_t* thist = hist_in_emit ? radix_hist(as<uint32_t>(B.hist2), P.capacity, tbits, &trb, &tpasses) : nullptr;
   {
     StageTimer tm(ctx, GSR_STAGE_EMIT, st);
-    launch_emit(P.sorted_splats, as<uint32_t>(B.offsets), totals, totals + 3, as<int4>(B.rect), P.total, P.num,
-                as<ViewDesc>(B.views), ctx->tile_w, ctx->tile_h, ik, iv, P.capacity, totals + 2, thist, tbits,
+    launch_emit(P.sorted_splats, as<uint32_t>(B.offsets), totals, totals + 3, as<Splat>(B.splats), P.total, ik, iv,
+                P.capacity, totals + 2, thist, tbits,
                 as<uint32_t>(B.block_rank), st);
   }
   CHECK_LAUNCH(ctx);

@@ -26,7 +26,9 @@ struct ViewImages {
 };
 
 // Projected splat of one (view, Gaussian): three 16-byte words.
-//   w0 = (u, v, z, opacity)  w1 = (A, B, C, 0) conic  w2 = (r, g, b, 0)
+//   w0 = (u, v, z, opacity)  w1 = (A, B, C, tile0) conic  w2 = (r, g, b, tgeo)
+// tile0, tgeo (integer bits, for the emission only): the first global tile id
+// of the splat's tile rectangle; its width | the view's tile pitch << 16.
 struct Splat {
   float4 w0, w1, w2;
 };
@@ -107,8 +109,7 @@ void launch_compact_visible(const uint32_t* ntiles, const uint32_t* keys, int64_
 // block_rank: scratch of emit_plan_elems(capacity) words.
 int64_t emit_plan_elems(int64_t capacity);
 void launch_emit(const uint32_t* sorted_s, const uint32_t* offsets, const uint32_t* total_dev,
-                 const uint32_t* count_dev, const int4* rect, int64_t count, int64_t n, const ViewDesc* views,
-                 int tile_w, int tile_h, uint32_t* keys,
+                 const uint32_t* count_dev, const Splat* splats, int64_t count, uint32_t* keys,
                  uint32_t* vals, int64_t capacity, uint32_t* overflow, uint32_t* hist, int hist_bits,
                  uint32_t* block_rank, hipStream_t st);
 // ranges[t] = (start, end) of global tile t in the sorted key array of

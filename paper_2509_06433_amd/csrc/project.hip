@@ -308,13 +308,15 @@ __device__ __forceinline__ bool project_splat(const float* __restrict__ P, int64
     zkey[s] = 0xFFFFFFFFu;
     return false;
   }
+  const int tx0 = g.x0 / tile_w, tx1 = g.x1 / tile_w, ty0 = g.y0 / tile_h, ty1 = g.y1 / tile_h;
   Splat sp;
   sp.w0 = make_float4(g.u, g.v, g.tz, o);
-  sp.w1 = make_float4(g.A, g.B, g.C, 0.0f);
-  sp.w2 = make_float4(col[0], col[1], col[2], 0.0f);
+  // spare words: the tile rectangle for the emission (first global tile id;
+  // width | the view's tile pitch << 16)
+  sp.w1 = make_float4(g.A, g.B, g.C, __uint_as_float((uint32_t)(V.tile_offset + ty0 * V.tiles_x + tx0)));
+  sp.w2 = make_float4(col[0], col[1], col[2], __uint_as_float((uint32_t)(tx1 - tx0 + 1) | ((uint32_t)V.tiles_x << 16)));
   splats[s] = sp;
   rect[s] = make_int4(g.x0, g.y0, g.x1, g.y1);
-  const int tx0 = g.x0 / tile_w, tx1 = g.x1 / tile_w, ty0 = g.y0 / tile_h, ty1 = g.y1 / tile_h;
   ntiles[s] = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
   const uint32_t key = __float_as_uint(g.tz);
   zkey[s] = key;

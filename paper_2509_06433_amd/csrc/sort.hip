@@ -533,6 +533,7 @@ __global__ void __launch_bounds__(kSortThreads) onesweep_pass_kernel(
 // staged offsets. Positions past `capacity` are dropped and flagged.
 constexpr int kEmitBlock = 1024;
 constexpr int kEmitThreads = 256;
+constexpr int kEmitHist = 1024;   // histogram words the emission can accumulate (4 passes of 8 bits)
 
 __global__ void __launch_bounds__(256) emit_plan_kernel(const uint32_t* __restrict__ offsets,
                                                         const uint32_t* __restrict__ total_dev,
@@ -553,15 +554,14 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(const uint32_t* __re
                                                            const uint32_t* __restrict__ total_dev,
                                                            const uint32_t* __restrict__ count_dev,
                                                            const uint32_t* __restrict__ block_rank,
-                                                           const int4* __restrict__ rect, int64_t count_host, int64_t n,
-                                                           const ViewDesc* __restrict__ views, int tile_w, int tile_h,
+                                                           const Splat* __restrict__ splats, int64_t count_host,
                                                            uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
                                                            int64_t capacity, uint32_t* __restrict__ overflow,
                                                            uint32_t* __restrict__ hist, int hist_rb, int hist_passes) {
   __shared__ uint32_t s_off[kEmitBlock + 1];
   __shared__ uint32_t s_sid[kEmitBlock];
-  __shared__ int3 s_geo[kEmitBlock];      // first tile id of the rectangle, rectangle width, view row pitch
-  __shared__ uint32_t s_hist[kMaxRadix];  // hist_passes * 2^hist_rb <= 2048
+  __shared__ int2 s_geo[kEmitBlock];      // first tile id of the rectangle; rectangle width | view row pitch << 16
+  __shared__ uint32_t s_hist[kEmitHist];  // hist_passes * 2^hist_rb <= kEmitHist
   const int tid = threadIdx.x;
   const uint32_t total = *total_dev;
   if (blockIdx.x == 0 && tid == 0 && (int64_t)total > capacity) atomicOr(overflow, 1u);
@@ -586,10 +586,8 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(const uint32_t* __re
     s_off[j] = offsets[r];
     const uint32_t sid = sorted_s[r];
     s_sid[j] = sid;
-    const int4 pr = rect[sid];
-    const ViewDesc& V = views[(int)(sid / (uint64_t)n)];
-    const int tx0 = pr.x / tile_w, tx1 = pr.z / tile_w, ty0 = pr.y / tile_h;
-    s_geo[j] = make_int3(V.tile_offset + ty0 * V.tiles_x + tx0, tx1 - tx0 + 1, V.tiles_x);
+    // the tile rectangle the projection stored in the record's spare words
+    s_geo[j] = make_int2((int)__float_as_uint(splats[sid].w1.w), (int)__float_as_uint(splats[sid].w2.w));
   }
   if (tid == 0) s_off[nr] = r0 + nr < count ? offsets[r0 + nr] : total;
   __syncthreads();
@@ -600,11 +598,11 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(const uint32_t* __re
       if (s_off[mid] <= (uint32_t)o) lo = mid;
       else hi = mid;
     }
-    const int3 geo = s_geo[lo];
-    const uint32_t wdt = (uint32_t)geo.y;
+    const int2 geo = s_geo[lo];
+    const uint32_t wdt = (uint32_t)geo.y & 0xFFFFu, pitch = (uint32_t)geo.y >> 16;
     const uint32_t local = (uint32_t)o - s_off[lo];
     const uint32_t dy = local / wdt, dx = local - dy * wdt;
-    const uint32_t key = (uint32_t)geo.x + dy * (uint32_t)geo.z + dx;
+    const uint32_t key = (uint32_t)geo.x + dy * pitch + dx;
     keys[o] = key;
     vals[o] = s_sid[lo];
     if (hist)
@@ -802,31 +800,30 @@ void radix_sort_pairs(uint32_t*& keys, uint32_t*& vals, uint32_t*& keys_alt, uin
 int64_t emit_plan_elems(int64_t capacity) { return (capacity + kEmitBlock - 1) / kEmitBlock + 1; }
 
 void launch_emit(const uint32_t* sorted_s, const uint32_t* offsets, const uint32_t* total_dev,
-                 const uint32_t* count_dev, const int4* rect, int64_t count, int64_t n, const ViewDesc* views,
-                 int tile_w, int tile_h, uint32_t* keys,
+                 const uint32_t* count_dev, const Splat* splats, int64_t count, uint32_t* keys,
                  uint32_t* vals, int64_t capacity, uint32_t* overflow, uint32_t* hist, int hist_bits,
                  uint32_t* block_rank, hipStream_t st) {
   if (count == 0) return;
   int rb = 8, hp = 0;
   if (hist_bits > 0) radix_plan(hist_bits, &rb, &hp);
-  const bool fits = hp >= 1 && hp * (1 << rb) <= kMaxRadix;
+  const bool fits = hp >= 1 && hp * (1 << rb) <= kEmitHist;
   const int64_t nblocks = (capacity + kEmitBlock - 1) / kEmitBlock;
   if (nblocks == 0) {
     // no instance slot: only the overflow flag can be raised
-    emit_kernel<<<1, kEmitThreads, 0, st>>>(sorted_s, offsets, total_dev, count_dev, block_rank, rect, count, n, views,
-                                            tile_w, tile_h, keys, vals, capacity, overflow, nullptr, rb, hp);
+    emit_kernel<<<1, kEmitThreads, 0, st>>>(sorted_s, offsets, total_dev, count_dev, block_rank, splats, count, keys,
+                                            vals, capacity, overflow, nullptr, rb, hp);
     return;
   }
   emit_plan_kernel<<<grid_cap(count, 256), 256, 0, st>>>(offsets, total_dev, count_dev, count, nblocks, block_rank);
-  emit_kernel<<<(unsigned)nblocks, kEmitThreads, 0, st>>>(sorted_s, offsets, total_dev, count_dev, block_rank, rect,
-                                                          count, n, views, tile_w, tile_h, keys, vals, capacity,
-                                                          overflow, fits ? hist : nullptr, rb, hp);
+  emit_kernel<<<(unsigned)nblocks, kEmitThreads, 0, st>>>(sorted_s, offsets, total_dev, count_dev, block_rank, splats,
+                                                          count, keys, vals, capacity, overflow, fits ? hist : nullptr,
+                                                          rb, hp);
 }
 
 bool emit_histogram_fits(int bits) {
   int rb, hp;
   radix_plan(bits, &rb, &hp);
-  return bits > 0 && hp * (1 << rb) <= kMaxRadix;
+  return bits > 0 && hp * (1 << rb) <= kEmitHist;
 }
 
 void launch_tile_ranges(const uint32_t* keys, const uint32_t* n_dev, int64_t count, uint2* ranges, int64_t num_tiles,
