@@ -379,9 +379,10 @@ __global__ void __launch_bounds__(256) project_kernel(const float* __restrict__ 
   }
   if (zhist) {
     __syncthreads();
+    uint32_t* dst = zhist + (size_t)(blockIdx.x % kHistCopies) * (zpasses * zR);
     for (int e = threadIdx.x; e < zpasses * zR; e += blockDim.x) {
       const uint32_t c = s_hist[e];
-      if (c) atomicAdd(zhist + e, c);
+      if (c) atomicAdd(dst + e, c);
     }
   }
 }

@@ -298,14 +298,15 @@ __global__ void __launch_bounds__(kSortThreads) global_hist_kernel(const uint32_
     }
   }
   __syncthreads();
+  uint32_t* dst = ghist + (size_t)(blockIdx.x % kHistCopies) * (passes * R);
   for (int e = threadIdx.x; e < passes * R; e += kSortThreads)
-    if (h[e]) atomicAdd(&ghist[e], h[e]);
+    if (h[e]) atomicAdd(&dst[e], h[e]);
 }
 
 template <int RB, int ITEMS>
 __global__ void __launch_bounds__(kSortThreads) onesweep_pass_kernel(
     const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals, const uint32_t* __restrict__ n_dev,
-    int64_t n_host, int shift, const uint32_t* __restrict__ ghist, uint32_t* __restrict__ status,
+    int64_t n_host, int shift, const uint32_t* __restrict__ ghist, int ghist_stride, uint32_t* __restrict__ status,
     uint32_t* __restrict__ ticket, uint32_t* __restrict__ err, uint32_t* __restrict__ keys_out,
     uint32_t* __restrict__ vals_out) {
   constexpr int R = 1 << RB;
@@ -462,7 +463,10 @@ __global__ void __launch_bounds__(kSortThreads) onesweep_pass_kernel(
     for (int t = 0; t < DPT; ++t) {
       gpre[t] = gs;
       mpre[t] = ms;
-      gs += ghist[tid * DPT + t];
+      uint32_t h = 0;
+#pragma unroll
+      for (int c = 0; c < kHistCopies; ++c) h += ghist[(size_t)c * ghist_stride + tid * DPT + t];
+      gs += h;
       ms += mine[t];
     }
     uint32_t x = gs, y = ms;
@@ -610,8 +614,9 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(const uint32_t* __re
   }
   if (hist) {
     __syncthreads();
+    uint32_t* dst = hist + (size_t)(blockIdx.x % kHistCopies) * (hist_passes * hR);
     for (int e = tid; e < hist_passes * hR; e += kEmitThreads)
-      if (s_hist[e]) atomicAdd(&hist[e], s_hist[e]);
+      if (s_hist[e]) atomicAdd(&dst[e], s_hist[e]);
   }
 }
 
@@ -723,8 +728,8 @@ int64_t radix_scratch_elems(int64_t n, int bits) {
   int rb, passes;
   radix_plan(bits, &rb, &passes);
   const int64_t nb = blocks_for(n, sort_chunk(n));
-  // status words for every pass, global histograms, tickets
-  return (int64_t)passes * (nb > 0 ? nb : 1) * (1 << rb) + passes * (1 << rb) + kMaxPasses;
+  // status words for every pass, the copies of the global histograms, tickets
+  return (int64_t)passes * (nb > 0 ? nb : 1) * (1 << rb) + (int64_t)kHistCopies * passes * (1 << rb) + kMaxPasses;
 }
 
 int64_t scan_partial_elems(int64_t n) { return 2 * (int64_t)blocks_for(n > 0 ? n : 1, kScanChunk) + 2; }
@@ -775,7 +780,8 @@ void radix_sort_pairs(uint32_t*& keys, uint32_t*& vals, uint32_t*& keys_alt, uin
   const int nb = blocks_for(n, sort_chunk(n));
   uint32_t* status = scratch;
   uint32_t* ghist = scratch + (int64_t)passes * nb * R;
-  uint32_t* tickets = ghist + passes * R;
+  uint32_t* tickets = ghist + (int64_t)kHistCopies * passes * R;
+  const int gstride = passes * R;
   const int64_t clear_n = radix_scratch_elems(n, bits);
   if (clear) fill_u32_kernel<<<grid_cap(clear_n, 256), 256, 0, st>>>(scratch, 0u, clear_n);
   if (!hist_ready)
@@ -784,13 +790,13 @@ void radix_sort_pairs(uint32_t*& keys, uint32_t*& vals, uint32_t*& keys_alt, uin
     uint32_t* stp = status + (int64_t)p * nb * R;
     const int sh = rb * p;
     if (rb == 11)
-      onesweep_pass_kernel<11, 16><<<nb, kSortThreads, 0, st>>>(keys, vals, n_dev, n, sh, ghist + p * R, stp,
+      onesweep_pass_kernel<11, 16><<<nb, kSortThreads, 0, st>>>(keys, vals, n_dev, n, sh, ghist + p * R, gstride, stp,
                                                                 tickets + p, err, keys_alt, vals_alt);
     else if (items == 4)
-      onesweep_pass_kernel<8, 4><<<nb, kSortThreads, 0, st>>>(keys, vals, n_dev, n, sh, ghist + p * R, stp,
+      onesweep_pass_kernel<8, 4><<<nb, kSortThreads, 0, st>>>(keys, vals, n_dev, n, sh, ghist + p * R, gstride, stp,
                                                               tickets + p, err, keys_alt, vals_alt);
     else
-      onesweep_pass_kernel<8, 16><<<nb, kSortThreads, 0, st>>>(keys, vals, n_dev, n, sh, ghist + p * R, stp,
+      onesweep_pass_kernel<8, 16><<<nb, kSortThreads, 0, st>>>(keys, vals, n_dev, n, sh, ghist + p * R, gstride, stp,
                                                                tickets + p, err, keys_alt, vals_alt);
     uint32_t* t = keys; keys = keys_alt; keys_alt = t;
     t = vals; vals = vals_alt; vals_alt = t;
