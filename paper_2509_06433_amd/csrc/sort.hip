@@ -64,26 +64,29 @@ __device__ __forceinline__ uint32_t load_gather(const uint32_t* in, const uint32
   return idx ? in[idx[j]] : in[j];
 }
 
-// Single-pass exclusive scan with decoupled look-back. Workgroups take
-// tickets (a lower ticket is always already running), publish their chunk
-// total, and the first wave looks back over the published totals of up to 64
-// predecessors per step until it meets an inclusive prefix. A wait is
-// bounded: past the spin limit the error flag is raised and the scan goes on,
-// so every wave exits. Status word per ticket: flag (1 = chunk total,
-// 2 = inclusive prefix) in the high half, the value in the low half.
+// Single-pass exclusive scan with decoupled look-back. Workgroups publish
+// their chunk total, and the first wave looks back over the published totals
+// of up to 64 predecessors per step until it meets an inclusive prefix. A
+// workgroup waits only on lower workgroup indices, which the dispatcher has
+// already placed: each XCD dispatches its workgroups in index order, so the
+// lowest workgroup not yet placed only waits for placed ones, which finish
+// and free its XCD's slots. (Ticket counters would guarantee this order too,
+// but hundreds of workgroups incrementing one word serialise on it: 7 us of a
+// 65 us tile sort.) A wait is still bounded: past the spin limit the error
+// flag is raised and the scan goes on, so every wave exits. Status word per
+// workgroup: flag (1 = chunk total, 2 = inclusive prefix) in the high half,
+// the value in the low half.
 constexpr unsigned long long kScanAgg = 1ull << 32;
 constexpr unsigned long long kScanInc = 2ull << 32;
 
 __global__ void __launch_bounds__(kScanThreads) scan_lookback_kernel(
     const uint32_t* __restrict__ in, const uint32_t* __restrict__ idx, const uint32_t* __restrict__ n_dev,
     int64_t n_host, uint32_t* __restrict__ out, uint32_t* __restrict__ total_out,
-    unsigned long long* __restrict__ status, uint32_t* __restrict__ ticket, uint32_t* __restrict__ err) {
+    unsigned long long* __restrict__ status, uint32_t* __restrict__ err) {
   __shared__ uint32_t tile[kScanChunk];
-  __shared__ uint32_t s_bid, s_excl;
+  __shared__ uint32_t s_excl;
   const int64_t n = n_dev ? min((int64_t)*n_dev, n_host) : n_host;
-  if (threadIdx.x == 0) s_bid = atomicAdd(ticket, 1u);
-  __syncthreads();
-  const uint32_t bid = s_bid;
+  const uint32_t bid = blockIdx.x;
   const int64_t base = (int64_t)bid * kScanChunk;
   // workgroups past the element count have nothing to do, and no workgroup
   // that has looks at them
@@ -165,17 +168,14 @@ __global__ void __launch_bounds__(kScanThreads) scan_lookback_kernel(
 
 // Order-preserving compaction of the visible splats (nonzero tile count):
 // out_keys[r], out_vals[r] = key and index of the r-th visible splat; the
-// count -> *count_out. Single pass with the same ticketed look-back as the
-// scan.
+// count -> *count_out. Single pass with the same look-back as the scan.
 __global__ void __launch_bounds__(kScanThreads) compact_visible_kernel(
     const uint32_t* __restrict__ ntiles, const uint32_t* __restrict__ keys, int64_t n,
     uint32_t* __restrict__ out_keys, uint32_t* __restrict__ out_vals, uint32_t* __restrict__ count_out,
-    unsigned long long* __restrict__ status, uint32_t* __restrict__ ticket, uint32_t* __restrict__ err) {
-  __shared__ uint32_t s_bid, s_excl;
+    unsigned long long* __restrict__ status, uint32_t* __restrict__ err) {
+  __shared__ uint32_t s_excl;
   __shared__ uint32_t flags[kScanChunk];
-  if (threadIdx.x == 0) s_bid = atomicAdd(ticket, 1u);
-  __syncthreads();
-  const uint32_t bid = s_bid;
+  const uint32_t bid = blockIdx.x;
   const int64_t base = (int64_t)bid * kScanChunk;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
@@ -254,17 +254,18 @@ __global__ void __launch_bounds__(kScanThreads) compact_visible_kernel(
 // tiles in one).
 //   global_hist: digit histograms of every pass in one read of the keys
 //                (skipped when the producer of the keys accumulated them).
-//   pass:        one kernel per digit. Workgroups take tickets so that a lower
-//                ticket is always already running; each ranks its chunk of
-//                keys (256 threads x 4 or 16 keys, 4 for small sorts so
-//                that a pass spreads over more CUs) with wave ballots, publishes its per-digit counts, and gets
-//                its per-digit offset by looking back over the published
-//                counts of lower tickets (decoupled look-back). A wait on a
-//                predecessor is bounded: past the spin limit the workgroup
-//                raises the error flag and goes on, so every wave exits.
+//   pass:        one kernel per digit. Each workgroup ranks its chunk of
+//                keys (256 threads x 4 or 16 keys, 4 for small sorts so that
+//                a pass spreads over more CUs) with wave ballots, publishes
+//                its per-digit counts, and gets its per-digit offset by
+//                looking back over the published counts of lower workgroup
+//                indices (decoupled look-back; the dispatch order makes this
+//                safe, as for the scan above). A wait on a predecessor is
+//                bounded: past the spin limit the workgroup raises the error
+//                flag and goes on, so every wave exits.
 // Each thread owns R / 256 consecutive digits for the per-digit steps.
-// Status word per (ticket, digit): 2 flag bits (1 = count of this workgroup,
-// 2 = inclusive prefix up to this workgroup) over a 30-bit count.
+// Status word per (workgroup, digit): 2 flag bits (1 = count of this
+// workgroup, 2 = inclusive prefix up to this workgroup) over a 30-bit count.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kFlagAgg = 1u << 30;
 constexpr uint32_t kFlagInc = 2u << 30;
@@ -307,7 +308,7 @@ template <int RB, int ITEMS>
 __global__ void __launch_bounds__(kSortThreads) onesweep_pass_kernel(
     const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals, const uint32_t* __restrict__ n_dev,
     int64_t n_host, int shift, const uint32_t* __restrict__ ghist, int ghist_stride, uint32_t* __restrict__ status,
-    uint32_t* __restrict__ ticket, uint32_t* __restrict__ err, uint32_t* __restrict__ keys_out,
+    uint32_t* __restrict__ err, uint32_t* __restrict__ keys_out,
     uint32_t* __restrict__ vals_out) {
   constexpr int R = 1 << RB;
   constexpr int NW = kSortThreads / 64;
@@ -322,7 +323,6 @@ __global__ void __launch_bounds__(kSortThreads) onesweep_pass_kernel(
   __shared__ uint32_t s_mem[kCountWords];
   __shared__ uint32_t gofs[R];         // global start of each digit's run of this block (minus its local start)
   __shared__ uint32_t lstart[R];       // block-local start of each digit's run
-  __shared__ uint32_t s_bid;
   __shared__ uint32_t s_wsum[2][NW];
   uint32_t (*wcnt)[R] = reinterpret_cast<uint32_t (*)[R]>(s_mem);
   uint32_t* s_keys = s_mem;
@@ -330,10 +330,9 @@ __global__ void __launch_bounds__(kSortThreads) onesweep_pass_kernel(
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int tid = threadIdx.x;
   const int64_t n = n_dev ? min((int64_t)*n_dev, n_host) : n_host;
-  if (tid == 0) s_bid = atomicAdd(ticket, 1u);
   for (int e = tid; e < NW * R; e += kSortThreads) (&wcnt[0][0])[e] = 0;
   __syncthreads();
-  const uint32_t bid = s_bid;
+  const uint32_t bid = blockIdx.x;
   // workgroups past the element count have nothing to do, and no workgroup
   // that has looks at them
   if ((int64_t)bid * CHUNK >= n && bid > 0) return;
@@ -378,7 +377,7 @@ __global__ void __launch_bounds__(kSortThreads) onesweep_pass_kernel(
     __hip_atomic_store(status + (size_t)bid * R + d, (bid == 0 ? kFlagInc : kFlagAgg) | acc, __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
   }
-  // exclusive prefixes over lower tickets, all owned digits walking together
+  // exclusive prefixes over lower workgroups, all owned digits walking together
   uint32_t excl[DPT];
 #pragma unroll
   for (int t = 0; t < DPT; ++t) excl[t] = 0;
@@ -728,11 +727,11 @@ int64_t radix_scratch_elems(int64_t n, int bits) {
   int rb, passes;
   radix_plan(bits, &rb, &passes);
   const int64_t nb = blocks_for(n, sort_chunk(n));
-  // status words for every pass, the copies of the global histograms, tickets
-  return (int64_t)passes * (nb > 0 ? nb : 1) * (1 << rb) + (int64_t)kHistCopies * passes * (1 << rb) + kMaxPasses;
+  // status words for every pass, the copies of the global histograms
+  return (int64_t)passes * (nb > 0 ? nb : 1) * (1 << rb) + (int64_t)kHistCopies * passes * (1 << rb);
 }
 
-int64_t scan_partial_elems(int64_t n) { return 2 * (int64_t)blocks_for(n > 0 ? n : 1, kScanChunk) + 2; }
+int64_t scan_partial_elems(int64_t n) { return 2 * (int64_t)blocks_for(n > 0 ? n : 1, kScanChunk); }
 
 uint32_t* radix_hist(uint32_t* scratch, int64_t n, int bits, int* rb, int* passes) {
   radix_plan(bits, rb, passes);
@@ -748,10 +747,9 @@ void scan_gather_exclusive(const uint32_t* in, const uint32_t* idx, uint32_t* ou
     return;
   }
   const int nb = blocks_for(n, kScanChunk);
-  if (clear) fill_u32_kernel<<<grid_cap(2 * nb + 2, 256), 256, 0, st>>>(scratch, 0u, 2 * nb + 2);
+  if (clear) fill_u32_kernel<<<grid_cap(2 * nb, 256), 256, 0, st>>>(scratch, 0u, 2 * nb);
   unsigned long long* status = reinterpret_cast<unsigned long long*>(scratch);
-  uint32_t* ticket = scratch + 2 * nb;
-  scan_lookback_kernel<<<nb, kScanThreads, 0, st>>>(in, idx, n_dev, n, out, total_dev, status, ticket, err);
+  scan_lookback_kernel<<<nb, kScanThreads, 0, st>>>(in, idx, n_dev, n, out, total_dev, status, err);
 }
 
 void launch_compact_visible(const uint32_t* ntiles, const uint32_t* keys, int64_t n, uint32_t* out_keys,
@@ -762,11 +760,9 @@ void launch_compact_visible(const uint32_t* ntiles, const uint32_t* keys, int64_
     return;
   }
   const int nb = blocks_for(n, kScanChunk);
-  if (clear) fill_u32_kernel<<<grid_cap(2 * nb + 2, 256), 256, 0, st>>>(scratch, 0u, 2 * nb + 2);
+  if (clear) fill_u32_kernel<<<grid_cap(2 * nb, 256), 256, 0, st>>>(scratch, 0u, 2 * nb);
   unsigned long long* status = reinterpret_cast<unsigned long long*>(scratch);
-  uint32_t* ticket = scratch + 2 * nb;
-  compact_visible_kernel<<<nb, kScanThreads, 0, st>>>(ntiles, keys, n, out_keys, out_vals, count_out, status, ticket,
-                                                      err);
+  compact_visible_kernel<<<nb, kScanThreads, 0, st>>>(ntiles, keys, n, out_keys, out_vals, count_out, status, err);
 }
 
 void radix_sort_pairs(uint32_t*& keys, uint32_t*& vals, uint32_t*& keys_alt, uint32_t*& vals_alt, int64_t n,
@@ -780,7 +776,6 @@ void radix_sort_pairs(uint32_t*& keys, uint32_t*& vals, uint32_t*& keys_alt, uin
   const int nb = blocks_for(n, sort_chunk(n));
   uint32_t* status = scratch;
   uint32_t* ghist = scratch + (int64_t)passes * nb * R;
-  uint32_t* tickets = ghist + (int64_t)kHistCopies * passes * R;
   const int gstride = passes * R;
   const int64_t clear_n = radix_scratch_elems(n, bits);
   if (clear) fill_u32_kernel<<<grid_cap(clear_n, 256), 256, 0, st>>>(scratch, 0u, clear_n);
@@ -791,13 +786,13 @@ void radix_sort_pairs(uint32_t*& keys, uint32_t*& vals, uint32_t*& keys_alt, uin
     const int sh = rb * p;
     if (rb == 11)
       onesweep_pass_kernel<11, 16><<<nb, kSortThreads, 0, st>>>(keys, vals, n_dev, n, sh, ghist + p * R, gstride, stp,
-                                                                tickets + p, err, keys_alt, vals_alt);
+                                                                err, keys_alt, vals_alt);
     else if (items == 4)
       onesweep_pass_kernel<8, 4><<<nb, kSortThreads, 0, st>>>(keys, vals, n_dev, n, sh, ghist + p * R, gstride, stp,
-                                                              tickets + p, err, keys_alt, vals_alt);
+                                                              err, keys_alt, vals_alt);
     else
       onesweep_pass_kernel<8, 16><<<nb, kSortThreads, 0, st>>>(keys, vals, n_dev, n, sh, ghist + p * R, gstride, stp,
-                                                               tickets + p, err, keys_alt, vals_alt);
+                                                               err, keys_alt, vals_alt);
     uint32_t* t = keys; keys = keys_alt; keys_alt = t;
     t = vals; vals = vals_alt; vals_alt = t;
   }
