@@ -238,7 +238,8 @@ int launch_bwd(gsr_ctx* ctx, Buffers& B, const RenderPlan& P, const float* param
   {
     StageTimer tm(ctx, GSR_STAGE_PROJECT_BWD, st);
     launch_project_backward(params, P.num, P.stride, P.deg, P.nv, as<ViewDesc>(B.views), ctx->znear,
-                            as<float>(B.g2), as<uint32_t>(B.ntiles), grad_params, overwrite_grad, st);
+                            as<float>(B.g2), as<uint32_t>(B.ntiles), grad_params, overwrite_grad,
+                            overwrite_grad && !clear_g2, st);
   }
   CHECK_LAUNCH(ctx);
   return GSR_OK;

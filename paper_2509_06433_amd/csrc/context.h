@@ -337,7 +337,10 @@ inline int bits_for(int64_t max_key) {
 //   launch_bwd:   blend backward and projection backward into grad_params
 //                 (added, or overwritten with overwrite_grad), image
 //                 gradients from the descriptors in B.images2; g2 is zeroed
-//                 first unless clear_g2 is false.
+//                 first unless clear_g2 is false. With overwrite_grad and not
+//                 clear_g2 (the mapping iteration) the projection backward
+//                 zeroes the g2 rows it reads, so g2 stays clean between
+//                 replays.
 // The launch_* functions make no allocation, copy or synchronisation, so a
 // stream capture can record them.
 int plan_render(gsr_ctx* ctx, const gsr_gaussians* g, int32_t nv, const gsr_camera* cams, RenderPlan* plan);

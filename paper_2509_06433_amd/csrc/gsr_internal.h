@@ -54,10 +54,11 @@ void launch_project(const float* params, int64_t n, int64_t stride, int deg, int
 // Chain rule from screen-space gradients g2[V*N][10] to grad_params (+=, or
 // with overwrite = every plane written, zero where no view contributed).
 // Only (view, Gaussian) pairs with a nonzero tile count (ntiles[V*N]) are
-// visited: one thread per Gaussian walks its own visible views.
+// visited: one thread per Gaussian walks its own visible views. zero_g2: the
+// rows read are zeroed, so g2 is all zero again afterwards.
 void launch_project_backward(const float* params, int64_t n, int64_t stride, int deg, int num_views,
-                             const ViewDesc* views, float znear, const float* g2, const uint32_t* ntiles,
-                             float* grad, bool overwrite, hipStream_t st);
+                             const ViewDesc* views, float znear, float* g2, const uint32_t* ntiles,
+                             float* grad, bool overwrite, bool zero_g2, hipStream_t st);
 // Inspection copy of the splats of one view: out[n][16] (see gsr_copy_splats).
 void launch_export_splats(const float* params, int64_t n, int64_t stride, const ViewDesc* view, float znear,
                           const Splat* splats, const int4* rect, float* out, hipStream_t st);

@@ -205,8 +205,9 @@ int record_iteration(gsr_ctx* ctx, GraphState* G, float* params, float* grad, fl
   back_clears(B, P, L);
   // (the gradient is overwritten by the projection backward, so it is not
   // cleared)
+  // (g2 is not cleared: it is zero before the first replay and the
+  // projection backward zeroes the rows it reads)
   if (loss) L.add(loss, 1);
-  L.add(B.g2.p, P.total * G2_N);
   {
     StageTimer tm(ctx, GSR_STAGE_ZERO, st);
     launch_clear(L, st);
@@ -240,6 +241,11 @@ int capture(gsr_ctx* ctx, GraphState* G, float* params, float* grad, float* loss
     ctx->ev_pool.push_back(e);
   }
   std::vector<TimedPair> timed;
+  // the screen-space gradient accumulators start at zero; each replay leaves
+  // them zero again
+  launch_fill_f32(as<float>(G->B.g2), 0.0f, G->P.total * G2_N, G->cap);
+  CHECK_LAUNCH(ctx);
+  HIP_TRY(ctx, hipStreamSynchronize(G->cap));
   HIP_TRY(ctx, hipStreamBeginCapture(G->cap, hipStreamCaptureModeThreadLocal));
   ctx->capture_timed = &timed;
   const int r = record_iteration(ctx, G, params, grad, loss, adam, depth_weight, planes, G->cap);

@@ -651,9 +651,10 @@ __device__ __forceinline__ void chain_view(const float* __restrict__ P, int64_t 
 template <int DEG>
 __global__ void __launch_bounds__(256) project_backward_kernel(const float* __restrict__ P, int64_t n, int64_t stride,
                                                                int num_views, const ViewDesc* __restrict__ views,
-                                                               const float* __restrict__ g2,
+                                                               float* __restrict__ g2,
                                                                const uint32_t* __restrict__ ntiles,
-                                                               float* __restrict__ grad, bool overwrite) {
+                                                               float* __restrict__ grad, bool overwrite,
+                                                               bool zero_g2) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     double gmean[3] = {0, 0, 0}, gls[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, glogit = 0.0;
@@ -668,7 +669,7 @@ __global__ void __launch_bounds__(256) project_backward_kernel(const float* __re
     // registers); a lane skips the views that do not see its Gaussian
     for (int cur = 0; cur < num_views; ++cur) {
       if (ntiles[(int64_t)cur * n + i] == 0u) continue;
-      const float* gv = g2 + ((int64_t)cur * n + i) * G2_N;
+      float* gv = g2 + ((int64_t)cur * n + i) * G2_N;
       double G[G2_N];
       bool any = false;
 #pragma unroll
@@ -677,6 +678,12 @@ __global__ void __launch_bounds__(256) project_backward_kernel(const float* __re
         any = any || (G[k] != 0.0);
       }
       if (!any) continue;
+      // the mapping iteration leaves the accumulators clean for its next
+      // replay: only rows of splats with tiles ever receive gradients
+      if (zero_g2) {
+#pragma unroll
+        for (int k = 0; k < G2_N; ++k) gv[k] = 0.0f;
+      }
       touched = true;
       const ViewDesc& V = views[cur];
       chain_view<DEG>(P, stride, i, V, G, coef, gmean, gls, gq, glogit, gsh);
@@ -758,23 +765,23 @@ void launch_project(const float* params, int64_t n, int64_t stride, int deg, int
 }
 
 void launch_project_backward(const float* params, int64_t n, int64_t stride, int deg, int num_views,
-                             const ViewDesc* views, float znear, const float* g2, const uint32_t* ntiles, float* grad,
-                             bool overwrite, hipStream_t st) {
+                             const ViewDesc* views, float znear, float* g2, const uint32_t* ntiles, float* grad,
+                             bool overwrite, bool zero_g2, hipStream_t st) {
   (void)znear;
   if (n == 0) return;
   const int gsz = grid_for(n, 256);
   switch (deg) {
     case 0:
-      project_backward_kernel<0><<<gsz, 256, 0, st>>>(params, n, stride, num_views, views, g2, ntiles, grad, overwrite);
+      project_backward_kernel<0><<<gsz, 256, 0, st>>>(params, n, stride, num_views, views, g2, ntiles, grad, overwrite, zero_g2);
       break;
     case 1:
-      project_backward_kernel<1><<<gsz, 256, 0, st>>>(params, n, stride, num_views, views, g2, ntiles, grad, overwrite);
+      project_backward_kernel<1><<<gsz, 256, 0, st>>>(params, n, stride, num_views, views, g2, ntiles, grad, overwrite, zero_g2);
       break;
     case 2:
-      project_backward_kernel<2><<<gsz, 256, 0, st>>>(params, n, stride, num_views, views, g2, ntiles, grad, overwrite);
+      project_backward_kernel<2><<<gsz, 256, 0, st>>>(params, n, stride, num_views, views, g2, ntiles, grad, overwrite, zero_g2);
       break;
     default:
-      project_backward_kernel<3><<<gsz, 256, 0, st>>>(params, n, stride, num_views, views, g2, ntiles, grad, overwrite);
+      project_backward_kernel<3><<<gsz, 256, 0, st>>>(params, n, stride, num_views, views, g2, ntiles, grad, overwrite, zero_g2);
       break;
   }
 }
