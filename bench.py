@@ -43,6 +43,10 @@ OPS_PER_PAIR_BWD = 59.0
 # Blend forward: 20 for the alpha, 3 for the transmittance test and update
 # (the colour and depth accumulation happens once per composited pair).
 OPS_PER_PAIR_FWD = 23.0
+# The fused launch (forward and backward of every tile in one grid) is
+# credited with both per pair walked by the backward; the forward's pairs
+# past each pixel's last composited Gaussian are not counted.
+OPS_PER_PAIR_FUSED = OPS_PER_PAIR_FWD + OPS_PER_PAIR_BWD
 
 
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
@@ -67,6 +71,8 @@ def parse():
     ap.add_argument("--chunk-len", type=int, default=0,
                     help="backward work unit in list positions (0 = automatic, -1 = whole tile lists)")
     ap.add_argument("--max-chunks", type=int, default=0, help="backward chunks per tile (0 = default)")
+    ap.add_argument("--fuse-blend", type=int, default=0,
+                    help="graph mode: 0 = automatic, 1 = blend forward and backward in one launch, -1 = two launches")
     ap.add_argument("--tile-order", type=int, default=0,
                     help="0 = automatic, 1 = longest tile lists first, 2 = tile order")
     ap.add_argument("--no-autotune", action="store_true",
@@ -121,7 +127,8 @@ def main():
     cams = scene.cameras
     deg = scene.sh_degree
     R = Rasterizer(tile_w=tw, tile_h=th, pixels_per_thread=args.ppt, batch_depth=args.batch_depth,
-                   tile_order=args.tile_order, chunk_len=args.chunk_len, max_chunks=args.max_chunks)
+                   tile_order=args.tile_order, chunk_len=args.chunk_len, max_chunks=args.max_chunks,
+                   fuse_blend=args.fuse_blend)
     dev = torch.device("cuda:0")
     if args.calibrate_copy:
         src = torch.ones(64 * 1024 * 1024, device=dev)
@@ -155,7 +162,7 @@ def main():
         R.close()
         R = Rasterizer(tile_w=tuned["tile_w"], tile_h=tuned["tile_h"], pixels_per_thread=tuned["pixels_per_thread"],
                        batch_depth=tuned["batch_depth"], tile_order=args.tile_order, chunk_len=tuned["chunk_len"],
-                       max_chunks=tuned["max_chunks"])
+                       max_chunks=tuned["max_chunks"], fuse_blend=args.fuse_blend)
         outs = R.alloc_images(cams, dev)
     from paper_2509_06433_amd import _lib
     adam = dict(m=m, v=v, lr=lrs, beta1=0.9, beta2=0.999, eps=1e-15) if use_adam else None
@@ -180,12 +187,13 @@ def main():
     steps = {"graph": graph_step, "eager": eager_step}
     if forward_only:          # a render-only workload: both modes time the forward
         steps = {"graph": render_step, "eager": render_step}
-    dominant = "blend_fwd" if forward_only else "blend_bwd"
+    # the blend backward, or the fused blend launch when the iteration uses it
+    candidates = ["blend_fwd"] if forward_only else ["blend_bwd", "blend"]
 
     def timed(mode, n_steps, n_warm, profile):
-        """Warm up, then time n_steps; returns (ms per step, dominant-stage profile)."""
+        """Warm up, then time n_steps; returns (ms per step, {stage: (ms, launches)})."""
         fn = steps[mode]
-        R.set_profiling([dominant] if profile else [])
+        R.set_profiling(candidates if profile else [])
         it0 = timed.it
         for _ in range(n_warm):
             timed.it += 1
@@ -198,17 +206,19 @@ def main():
             fn(timed.it - it0)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        return (t1 - t0) * 1e3 / max(n_steps, 1), R.profile(reset=True)[dominant]
+        return (t1 - t0) * 1e3 / max(n_steps, 1), R.profile(reset=True)
 
     timed.it = 0
-    ms_per_step, (dom_ms, dom_n) = timed(args.mode, args.steps, args.warmup, True)
+    ms_per_step, prof = timed(args.mode, args.steps, args.warmup, True)
+    dominant = max(candidates, key=lambda k: prof[k][1])
+    dom_ms, dom_n = prof[dominant]
     if args.mode == "graph":
         mst = R.mapping_status()
         if mst["skipped"]:
             print(f"warning: {mst['skipped']} iterations skipped for instance overflow", file=sys.stderr)
     pairs, visible = R.count_work(len(cams))
     dom_avg_ms = dom_ms / max(args.steps, 1)     # one launch per step in graph mode
-    ops_per_pair = OPS_PER_PAIR_FWD if forward_only else OPS_PER_PAIR_BWD
+    ops_per_pair = {"blend_fwd": OPS_PER_PAIR_FWD, "blend_bwd": OPS_PER_PAIR_BWD, "blend": OPS_PER_PAIR_FUSED}[dominant]
     achieved = ops_per_pair * pairs / (dom_avg_ms * 1e-3) / 1e12
 
     other = "eager" if args.mode == "graph" else "graph"
@@ -233,8 +243,9 @@ def main():
     torch.cuda.synchronize()
     stages = {k: ms / 3 for k, (ms, n) in R.profile(reset=True).items() if n}     # ms per step
     R.set_profiling([])
-    render_ms = sum(stages.get(k, 0.0) for k in ["project", "depth_sort", "scan", "emit", "tile_sort", "ranges",
-                                                   "blend_fwd"])
+    # (with the fused blend launch the forward has no time of its own)
+    render_ms = (sum(stages.get(k, 0.0) for k in ["project", "depth_sort", "scan", "emit", "tile_sort", "ranges",
+                                                    "blend_fwd"]) if "blend_fwd" in stages else 0.0)
     pix = sum(c.width * c.height for c in cams)
     mpix = pix / (render_ms * 1e-3) / 1e6 if render_ms > 0 else None
     st = R.status()
@@ -261,6 +272,7 @@ def main():
                    "pixels_per_thread": R.pixels_per_thread or 1, "batch_depth": R.batch_depth or "default",
                    "chunk_len": {0: "auto", -1: "whole list"}.get(R.chunk_len, R.chunk_len),
                    "max_chunks": R.max_chunks or "default",
+                   "blend_launch": "fused" if dominant == "blend" else "separate",
                    "autotuned": tuned is not None, "tile_order": ["auto", "longest first", "index"][R.tile_order],
                    "adam": use_adam, "mode": args.mode,
                    f"{other}_iters_s": round(1000.0 / other_ms, 3) if other_ms else None,

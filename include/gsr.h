@@ -84,6 +84,12 @@ typedef struct {
                                one tile are walked in reverse by independent workgroups. */
   int32_t max_chunks;       /* chunks per tile: 0 = default (4), else 1 .. 64; the last chunk
                                takes the rest of the list */
+  int32_t fuse_blend;       /* mapping iteration: 0 = automatic (fused when the backward is
+                               chunked and the batch depth is the default), 1 = fused whenever
+                               the batch depth is the default, -1 = never. Fused, the blend
+                               forward and backward are one launch whose backward work units
+                               each wait for their tile's forward, so they fill the forward's
+                               tail; results are identical to the two launches. */
 } gsr_options;
 
 typedef struct {
@@ -246,6 +252,7 @@ typedef enum {
   GSR_STAGE_PROJECT = 0, GSR_STAGE_DEPTH_SORT, GSR_STAGE_SCAN, GSR_STAGE_EMIT,
   GSR_STAGE_TILE_SORT, GSR_STAGE_RANGES, GSR_STAGE_BLEND_FWD, GSR_STAGE_LOSS,
   GSR_STAGE_BLEND_BWD, GSR_STAGE_PROJECT_BWD, GSR_STAGE_ADAM, GSR_STAGE_ZERO,
+  GSR_STAGE_BLEND,          /* fused blend forward and backward (mapping iteration) */
   GSR_NUM_STAGES
 } gsr_stage;
 

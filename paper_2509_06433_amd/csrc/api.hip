@@ -73,6 +73,7 @@ int size_render(gsr_ctx* ctx, Buffers& B, RenderPlan& P, const gsr_image* out, h
   RET_IF(ensure(ctx, B.tfinal, sizeof(float) * (size_t)P.npix));
   RET_IF(ensure(ctx, B.last, sizeof(uint32_t) * (size_t)P.npix));
   RET_IF(ensure(ctx, B.tile_last, sizeof(uint32_t) * (size_t)std::max<int64_t>(P.ntiles, 1)));
+  RET_IF(ensure(ctx, B.tile_done, sizeof(uint32_t) * (size_t)std::max<int64_t>(P.ntiles, 1)));
   if (chunk_len_for(ctx, P) > 0)
     RET_IF(ensure(ctx, B.ckpt, sizeof(float) * kCkptFields * (size_t)ctx->max_chunks * (size_t)P.npix));
   RET_IF(ensure(ctx, B.g2, sizeof(float) * G2_N * (size_t)std::max<int64_t>(P.total, 1)));
@@ -146,7 +147,12 @@ static void set_chunking(const gsr_ctx* ctx, Buffers& B, const RenderPlan& P, Bl
   ba.ckpt_stride = P.npix;
 }
 
-int launch_back(gsr_ctx* ctx, Buffers& B, RenderPlan& P, hipStream_t st, const FusedLoss* loss) {
+bool use_fused_blend(const gsr_ctx* ctx, const RenderPlan& P) {
+  if (ctx->fuse_blend < 0 || ctx->batch_depth != 0) return false;
+  return ctx->fuse_blend > 0 || chunk_len_for(ctx, P) > 0;
+}
+
+int launch_back(gsr_ctx* ctx, Buffers& B, RenderPlan& P, hipStream_t st, const FusedLoss* loss, bool fused) {
   uint32_t* totals = as<uint32_t>(B.total);
   uint32_t* ik = as<uint32_t>(B.ikeys);
   uint32_t* iv = as<uint32_t>(B.ivals);
@@ -199,7 +205,13 @@ int launch_back(gsr_ctx* ctx, Buffers& B, RenderPlan& P, hipStream_t st, const F
     ba.depth_weight = loss->depth_weight;
     ba.loss = loss->loss;
   }
-  {
+  if (fused && loss) {
+    ba.g2 = as<float>(B.g2);
+    ba.tile_done = as<uint32_t>(B.tile_done);
+    ba.err = totals + 1;
+    StageTimer tm(ctx, GSR_STAGE_BLEND, st);
+    launch_blend_fused(ba, ctx->tile_w, ctx->tile_h, ctx->ppt, st);
+  } else {
     StageTimer tm(ctx, GSR_STAGE_BLEND_FWD, st);
     launch_blend_forward(ba, ctx->tile_w, ctx->tile_h, ctx->ppt, st);
   }
@@ -208,7 +220,7 @@ int launch_back(gsr_ctx* ctx, Buffers& B, RenderPlan& P, hipStream_t st, const F
 }
 
 int launch_bwd(gsr_ctx* ctx, Buffers& B, const RenderPlan& P, const float* params, float* grad_params,
-               bool clear_g2, bool overwrite_grad, hipStream_t st) {
+               bool clear_g2, bool overwrite_grad, hipStream_t st, bool blend_done) {
   if (P.total == 0) return GSR_OK;
   if (clear_g2) {
     StageTimer tm(ctx, GSR_STAGE_ZERO, st);
@@ -230,7 +242,7 @@ int launch_bwd(gsr_ctx* ctx, Buffers& B, const RenderPlan& P, const float* param
   ba.g2 = as<float>(B.g2);
   for (int k = 0; k < 3; ++k) ba.bg[k] = ctx->bg[k];
   set_chunking(ctx, B, P, ba);
-  {
+  if (!blend_done) {
     StageTimer tm(ctx, GSR_STAGE_BLEND_BWD, st);
     launch_blend_backward(ba, ctx->tile_w, ctx->tile_h, ctx->ppt, ctx->batch_depth, st);
   }
@@ -249,7 +261,7 @@ void free_buffers(Buffers& B) {
   DevBuf* bufs[] = {&B.views, &B.images, &B.images2, &B.splats, &B.rect, &B.ntiles, &B.zkey, &B.svals,
                     &B.zkey_alt, &B.svals_alt, &B.offsets, &B.ikeys, &B.ivals, &B.ikeys_alt, &B.ivals_alt,
                     &B.hist, &B.hist2, &B.partials, &B.ranges, &B.order, &B.tfinal, &B.last, &B.g2, &B.total,
-                    &B.tile_last, &B.ckpt, &B.block_rank};
+                    &B.tile_last, &B.ckpt, &B.block_rank, &B.tile_done};
   for (DevBuf* b : bufs) {
     if (b->p) (void)hipFree(b->p);
     b->p = nullptr;
@@ -358,6 +370,11 @@ int gsr_create(gsr_ctx** out, const gsr_options* opt) {
     }
     ctx->chunk_len = opt->chunk_len;
     ctx->max_chunks = mc;
+    if (opt->fuse_blend < -1 || opt->fuse_blend > 1) {
+      delete ctx;
+      return GSR_ERR_UNSUPPORTED;
+    }
+    ctx->fuse_blend = opt->fuse_blend;
     for (int k = 0; k < 3; ++k) ctx->bg[k] = opt->bg[k];
     ctx->znear = opt->znear > 0.f ? opt->znear : 0.2f;
   }

@@ -39,6 +39,7 @@ struct Buffers {
   DevBuf hist, hist2, partials, ranges, order, tfinal, last, g2;   // hist: depth sort, hist2: tile sort
   DevBuf total;   // [0] instance count, [1] wait expired, [2] instance overflow, [3] visible splats
   DevBuf tile_last, ckpt;   // per tile: longest walk; per pixel: state at the backward's chunk boundaries
+  DevBuf tile_done;         // fused blend: per tile, its forward is done
   DevBuf block_rank;        // emission: first depth rank of every block of output positions
 };
 
@@ -110,6 +111,7 @@ struct gsr_ctx {
   int tile_order = 0;                   // 0 auto, 1 longest list first, 2 tile order
   int chunk_len = 0;                    // backward work unit in list positions: 0 automatic, -1 whole lists
   int max_chunks = 4;                   // chunks per tile (the last takes the rest)
+  int fuse_blend = 0;                   // mapping iteration: 0 automatic, 1 fused, -1 two launches
   float bg[3] = {0.f, 0.f, 0.f};
   float znear = 0.2f;
   int hip_err = 0;
@@ -334,6 +336,9 @@ inline int bits_for(int64_t max_key) {
 //                 read on the device. With loss, the compositing also forms
 //                 the L1 loss against loss->targets and writes its image
 //                 gradients through the descriptors in B.images2.
+//                 With fused (needs loss), the compositing and the blend
+//                 backward are one launch (launch_bwd then skips the blend
+//                 backward); B.tile_done must be zero.
 //   launch_bwd:   blend backward and projection backward into grad_params
 //                 (added, or overwritten with overwrite_grad), image
 //                 gradients from the descriptors in B.images2; g2 is zeroed
@@ -353,9 +358,12 @@ struct FusedLoss {
   float depth_weight;
   float* loss;                 // added to; may be null
 };
-int launch_back(gsr_ctx* ctx, Buffers& B, RenderPlan& plan, hipStream_t st, const FusedLoss* loss = nullptr);
+int launch_back(gsr_ctx* ctx, Buffers& B, RenderPlan& plan, hipStream_t st, const FusedLoss* loss = nullptr,
+                bool fused = false);
 int launch_bwd(gsr_ctx* ctx, Buffers& B, const RenderPlan& plan, const float* params, float* grad_params,
-               bool clear_g2, bool overwrite_grad, hipStream_t st);
+               bool clear_g2, bool overwrite_grad, hipStream_t st, bool blend_done = false);
+// Whether the mapping iteration fuses the blend forward and backward.
+bool use_fused_blend(const gsr_ctx* ctx, const RenderPlan& plan);
 int size_instances(gsr_ctx* ctx, Buffers& B, const RenderPlan& plan);
 void free_buffers(Buffers& B);
 // Frees the captured mapping iteration and its buffers (iteration.hip).

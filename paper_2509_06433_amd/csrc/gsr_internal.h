@@ -184,6 +184,12 @@ struct BlendArgs {
   const ViewImages* loss_grad;
   float depth_weight;
   float* loss;
+  // Fused forward and backward (launch_blend_fused): per tile, set once its
+  // forward's state is written (zero before the launch); the error word set
+  // when a backward unit's bounded wait expires. The backward reads the
+  // image gradients from loss_grad.
+  uint32_t* tile_done;
+  uint32_t* err;
 };
 constexpr int kCkptFields = 5;
 bool blend_supported(int tile_w, int tile_h);
@@ -193,6 +199,9 @@ void launch_blend_forward(const BlendArgs& a, int tile_w, int tile_h, int ppt, h
 // capped at the workgroup's thread count)
 bool batch_depth_supported(int depth);
 void launch_blend_backward(const BlendArgs& a, int tile_w, int tile_h, int ppt, int depth, hipStream_t st);
+// Forward (with the fused loss) and backward in one launch, at the default
+// batch depth; needs loss_target, loss_grad, g2, tile_done and err.
+void launch_blend_fused(const BlendArgs& a, int tile_w, int tile_h, int ppt, hipStream_t st);
 // Valid chunk settings: chunk_len 0 (whole tile lists) or a multiple of 16
 // up to 1 << 20, with 1 <= max_chunks <= 64.
 bool chunking_supported(int chunk_len, int max_chunks);

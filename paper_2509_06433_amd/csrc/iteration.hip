@@ -208,6 +208,8 @@ int record_iteration(gsr_ctx* ctx, GraphState* G, float* params, float* grad, fl
   // (g2 is not cleared: it is zero before the first replay and the
   // projection backward zeroes the rows it reads)
   if (loss) L.add(loss, 1);
+  const bool fused = use_fused_blend(ctx, P);
+  if (fused) L.add(as<uint32_t>(B.tile_done), P.ntiles);
   {
     StageTimer tm(ctx, GSR_STAGE_ZERO, st);
     launch_clear(L, st);
@@ -216,8 +218,8 @@ int record_iteration(gsr_ctx* ctx, GraphState* G, float* params, float* grad, fl
   RET_IF(launch_front(ctx, B, P, params, st));
   // the L1 loss and its image gradients are formed by the compositing itself
   const FusedLoss fl{as<ViewImages>(G->tdesc), depth_weight, loss};
-  RET_IF(launch_back(ctx, B, P, st, &fl));
-  RET_IF(launch_bwd(ctx, B, P, params, grad, false, true, st));
+  RET_IF(launch_back(ctx, B, P, st, &fl, fused));
+  RET_IF(launch_bwd(ctx, B, P, params, grad, false, true, st, fused));
   if (adam) {
     StageTimer tm(ctx, GSR_STAGE_ADAM, st);
     launch_adam(params, grad, adam->m, adam->v, P.num, P.stride, planes, as<float>(G->lrbuf), adam->beta1,

@@ -69,14 +69,16 @@ def check_grad_close(g, ref, label):
         assert nbad == 0, (label, grp, worst)
 
 
-@pytest.mark.parametrize("chunk", [(0, 0), (16, 5)])
+# (chunk_len, max_chunks, fuse_blend): automatic (chunked and fused at this
+# size), explicit chunks fused, whole lists fused, and two launches
+@pytest.mark.parametrize("chunk", [(0, 0, 0), (16, 5, 0), (-1, 0, 1), (0, 0, -1)])
 def test_replays_match_eager(gpu, orc, chunk):
     s = two_view_scene()
     deg, cams = s.sh_degree, s.cameras
     targets = targets_for(gpu, s)
-    say("backward chunks", chunk)
+    say("backward chunks, fused", chunk)
     opts = dict(chunk_len=chunk[0], max_chunks=chunk[1])
-    R, E = gpu.Rasterizer(**opts), gpu.Rasterizer(**opts)
+    R, E = gpu.Rasterizer(fuse_blend=chunk[2], **opts), gpu.Rasterizer(**opts)
     p = to_dev(s.params)
     m, v = torch.zeros_like(p), torch.zeros_like(p)
     grad = torch.full_like(p, 7.0)
@@ -193,22 +195,26 @@ def test_overflow_skips_then_recaptures(gpu):
     check_grad_close(grad, eg, "after recapture")
 
 
-def test_profiled_replays(gpu):
+@pytest.mark.parametrize("fuse", [0, -1])
+def test_profiled_replays(gpu, fuse):
+    # with the fused blend launch (automatic at this size) its time is the
+    # "blend" stage, else "blend_bwd"
     s = two_view_scene(sh_degree=0)
     targets = targets_for(gpu, s)
-    R = gpu.Rasterizer()
+    R = gpu.Rasterizer(fuse_blend=fuse)
     p = to_dev(s.params)
     grad = torch.zeros_like(p)
     outs = R.alloc_images(s.cameras)
-    R.set_profiling(["blend_bwd", "project"])
+    blend = "blend" if fuse == 0 else "blend_bwd"
+    R.set_profiling([blend, "project"])
     R.profile(reset=True)
     for _ in range(3):
         R.mapping_iteration(p, 0, s.cameras, outs, targets, grad)
     torch.cuda.synchronize()
     prof = R.profile(reset=True)
     say(prof)
-    assert prof["blend_bwd"][1] == 3 and prof["project"][1] == 3
-    assert prof["blend_bwd"][0] > 0 and prof["project"][0] > 0
+    assert prof[blend][1] == 3 and prof["project"][1] == 3
+    assert prof[blend][0] > 0 and prof["project"][0] > 0
     assert prof["blend_fwd"][1] == 0
 
 
