@@ -188,8 +188,9 @@ struct FwdShared {
 // Forward of one tile. CK: record the chunked backward's per-pixel state
 // (a.chunk_len > 0). X: the backward runs in the same launch (the state is
 // written device-coherently and the tile is marked done at the end).
+// Returns the tile's largest last position (every thread).
 template <int TW, int TH, int PPT, bool CK, bool X>
-__device__ __forceinline__ void forward_tile(const BlendArgs& a, FwdShared<TW * TH / PPT>& sh, int tile) {
+__device__ __forceinline__ uint32_t forward_tile(const BlendArgs& a, FwdShared<TW * TH / PPT>& sh, int tile) {
   using Shape = TileShape<TW, TH, PPT>;
   constexpr int NT = Shape::NT;
   constexpr int ROWS = Shape::ROWS;
@@ -349,6 +350,7 @@ __device__ __forceinline__ void forward_tile(const BlendArgs& a, FwdShared<TW * 
     }
     if (X) __hip_atomic_store(a.tile_done + tile, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   }
+  return s_tl;
 }
 
 template <int TW, int TH, int PPT, bool CK>
@@ -471,19 +473,15 @@ struct BwdShared {
   uint32_t fail;
 };
 
-// Backward of one work unit: a tile, or with chunking one chunk of a tile's
-// list. Alone, the chunk that takes the rest of the list (the longest
-// possible) comes first, then chunks 0, 1, ... of every tile. BATCH: Gaussians
-// staged per round (the batch depth). X: the tile's forward runs in the same
-// launch; the unit waits until it is marked done and reads its state
-// device-coherently. Units then come in chunk order 0, 1, ..., the rest of
-// the list last: a unit whose positions lie past its tile's walk only learns
-// so from its forward, and such units (mostly the last chunk's) would hold
-// workgroup slots waiting while chunk 0 units with work queue behind them
-// (measured: fused blend 281 -> 257 us at 1200 tiles).
+// Backward of one work unit: a tile's whole list, or with chunking chunk
+// `chunk` of it. BATCH: Gaussians staged per round (the batch depth). X: the
+// tile's forward runs in the same launch and the state is read
+// device-coherently; with wait the unit first waits until the tile is marked
+// done and reads the tile's longest walk from memory, else the caller is the
+// tile's own forward workgroup and passes it (tile_last).
 template <int TW, int TH, int PPT, int BATCH, bool X>
 __device__ __forceinline__ void backward_unit(const BlendArgs& a, BwdShared<TW * TH / PPT / 64, BATCH>& sh,
-                                              int unit) {
+                                              int tile, int chunk, bool wait, uint32_t tile_last) {
   using Shape = TileShape<TW, TH, PPT>;
   constexpr int NT = Shape::NT;
   constexpr int ROWS = Shape::ROWS;
@@ -495,16 +493,11 @@ __device__ __forceinline__ void backward_unit(const BlendArgs& a, BwdShared<TW *
   uint32_t* s_id = sh.id;
   float (*s_red)[4][M_N][BATCH] = sh.red;
   uint32_t lo = 0, hi = 0xFFFFFFFFu;
-  int chunk = 0;
   if (a.chunk_len > 0) {
-    const int cu = unit / a.num_tiles;
-    unit -= cu * a.num_tiles;
-    chunk = X ? cu : (cu == 0 ? a.max_chunks - 1 : cu - 1);
     lo = (uint32_t)chunk * (uint32_t)a.chunk_len;
     if (chunk < a.max_chunks - 1) hi = lo + (uint32_t)a.chunk_len;
   }
-  const int tile = a.order ? (int)a.order[unit] : unit;
-  if (X) {
+  if (X && wait) {
     // Wait for the tile's forward. Workgroups are dispatched in index order
     // and every forward precedes every backward unit, so the forward this
     // unit waits for is resident or done, and forwards wait for nothing. The
@@ -527,7 +520,7 @@ __device__ __forceinline__ void backward_unit(const BlendArgs& a, BwdShared<TW *
     if (sh.fail) return;
   }
   const uint2 rg = a.ranges[tile];
-  const uint32_t maxlast = min(ld_u32<X>(a.tile_last + tile), rg.y - rg.x);
+  const uint32_t maxlast = min(wait || !X ? ld_u32<X>(a.tile_last + tile) : tile_last, rg.y - rg.x);
   if (lo >= maxlast) return;   // nothing composited in this unit's positions
   const uint32_t top = min(hi, maxlast);
   const int view = find_view(a.views, a.num_views, tile);
@@ -728,11 +721,19 @@ __device__ __forceinline__ void backward_unit(const BlendArgs& a, BwdShared<TW *
   }
 }
 
+// Work units alone: the chunk that takes the rest of the list (the longest
+// possible) of every tile first, then chunks 0, 1, ... of every tile.
 template <int TW, int TH, int PPT, int BATCH>
 __global__ void __launch_bounds__(TW * TH / PPT) __attribute__((amdgpu_waves_per_eu(4)))
 blend_backward_kernel(BlendArgs a) {
   __shared__ BwdShared<TW * TH / PPT / 64, BATCH> sh;
-  backward_unit<TW, TH, PPT, BATCH, false>(a, sh, (int)blockIdx.x);
+  int unit = (int)blockIdx.x, chunk = 0;
+  if (a.chunk_len > 0) {
+    const int cu = unit / a.num_tiles;
+    unit -= cu * a.num_tiles;
+    chunk = cu == 0 ? a.max_chunks - 1 : cu - 1;
+  }
+  backward_unit<TW, TH, PPT, BATCH, false>(a, sh, a.order ? (int)a.order[unit] : unit, chunk, false, 0u);
 }
 
 // Forward and backward of every tile in one launch: workgroups below
@@ -748,8 +749,22 @@ blend_fused_kernel(BlendArgs a) {
   using B = BwdShared<TW * TH / PPT / 64, BATCH>;
   __shared__ __align__(16) unsigned char smem[sizeof(F) > sizeof(B) ? sizeof(F) : sizeof(B)];
   const int b = (int)blockIdx.x;
-  if (b < a.num_tiles) forward_tile<TW, TH, PPT, CK, true>(a, *reinterpret_cast<F*>(smem), a.order ? (int)a.order[b] : b);
-  else backward_unit<TW, TH, PPT, BATCH, true>(a, *reinterpret_cast<B*>(smem), b - a.num_tiles);
+  if (b < a.num_tiles) {
+    // the tile's forward, then the first chunk of its backward (the whole
+    // list when unchunked) without waiting: each thread reads back only its
+    // own pixels' state, and the tile's longest walk comes from LDS
+    const int tile = a.order ? (int)a.order[b] : b;
+    const uint32_t tl = forward_tile<TW, TH, PPT, CK, true>(a, *reinterpret_cast<F*>(smem), tile);
+    __syncthreads();   // every thread has read the forward's LDS before the backward reuses it
+    backward_unit<TW, TH, PPT, BATCH, true>(a, *reinterpret_cast<B*>(smem), tile, 0, false, tl);
+  } else {
+    // chunks 1, 2, ... of every tile, in chunk order, each waiting for its
+    // tile's forward
+    const int unit = b - a.num_tiles;
+    const int cu = unit / a.num_tiles, t = unit - cu * a.num_tiles;
+    backward_unit<TW, TH, PPT, BATCH, true>(a, *reinterpret_cast<B*>(smem), a.order ? (int)a.order[t] : t, cu + 1,
+                                            true, 0u);
+  }
 }
 
 template <int TW, int TH>
@@ -780,7 +795,8 @@ template <int TW, int TH, int PPT>
 void fused_launch_ppt(const BlendArgs& a, hipStream_t st) {
   constexpr int NT = TW * TH / PPT;
   constexpr int D = NT >= 256 ? 32 : (NT >= 64 ? 64 : NT);
-  const int64_t units = (int64_t)a.num_tiles * (a.chunk_len > 0 ? a.max_chunks : 1);
+  // a workgroup per tile (forward and the first chunk), one per later chunk
+  const int64_t units = (int64_t)a.num_tiles * (a.chunk_len > 0 ? a.max_chunks - 1 : 0);
   const dim3 grid((unsigned)(a.num_tiles + units));
   if (a.chunk_len > 0) blend_fused_kernel<TW, TH, PPT, D, true><<<grid, NT, 0, st>>>(a);
   else blend_fused_kernel<TW, TH, PPT, D, false><<<grid, NT, 0, st>>>(a);
