@@ -313,24 +313,33 @@ def batch8_640x480(n=500_000, seed_offset=0, traj_seed=BATCH8_TRAJ_SEED) -> Scen
 MIXED16_RESOLUTIONS = [(320, 240)] * 5 + [(640, 480)] * 6 + [(1280, 720)] * 5
 
 
-def mixed16_2m(n=2_000_000, seed_offset=0, traj_seed=0) -> Scene:
+def mixed16_2m(n=2_000_000, seed_offset=0, traj_seed=0, res_div=1, logscale_mean=-4.0) -> Scene:
     """16 views at mixed resolutions (5x 320x240, 6x 640x480, 5x 1280x720, seeded
-    order) over a 2M-Gaussian SH-degree-3 room scaled to 10 m (depths 0.5-10 m)."""
+    order) over a 2M-Gaussian SH-degree-3 room scaled to 10 m (depths 0.5-10 m).
+    res_div divides every resolution (and so the focal length)."""
     rng = np.random.default_rng(SEED_BASE + 4 + seed_offset)
     size = (10.0, 10.0, 4.0)
     mean = _room_points(rng, n, size, 0.85)
-    logscale = rng.normal(-4.0, 0.7, (n, 3))
+    logscale = rng.normal(logscale_mean, 0.7, (n, 3))
     quat = rng.normal(0.0, 1.0, (n, 4))
     logit = rng.normal(0.0, 1.0, n)
     sh = _sh_block(rng, n, 3, dc_uniform=False, sigma=0.2)
     params = _assemble(mean, logscale, quat, logit, sh)
     trng = np.random.default_rng(SEED_BASE + 4 + 1000 + traj_seed)
-    res = list(MIXED16_RESOLUTIONS)
+    res = [(w // res_div, h // res_div) for w, h in MIXED16_RESOLUTIONS]
     trng.shuffle(res)
     poses = _room_trajectory(trng, 16, size, stride=3)
     cams = [look_at_camera(e, t, w, h, 0.8203 * w) for (e, t), (w, h) in zip(poses, res)]
     target = perturb(rng, params, 3)
-    return Scene("mixed16_2M_sh3", params, 3, cams, target)
+    name = "mixed16_2M_sh3" if (n, res_div) == (2_000_000, 1) else f"mixed16_{n}_div{res_div}_sh3"
+    return Scene(name, params, 3, cams, target)
+
+
+def mixed16_small() -> Scene:
+    """The 16-view mixed-resolution room at 1/8 of every resolution with 20k
+    Gaussians ten times larger (the same image coverage), for checks against
+    the CPU oracle that need many renders."""
+    return mixed16_2m(n=20_000, res_div=8, logscale_mean=-4.0 + np.log(10.0))
 
 
 def tiny_random(k: int, n=12, width=32, height=32, sh_degree=0, anisotropic=True) -> Scene:
