@@ -85,11 +85,13 @@ typedef struct {
   int32_t max_chunks;       /* chunks per tile: 0 = default (4), else 1 .. 64; the last chunk
                                takes the rest of the list */
   int32_t fuse_blend;       /* mapping iteration: 0 = automatic (fused when the backward is
-                               chunked and the batch depth is the default), 1 = fused whenever
-                               the batch depth is the default, -1 = never. Fused, the blend
-                               forward and backward are one launch whose backward work units
-                               each wait for their tile's forward, so they fill the forward's
-                               tail; results are identical to the two launches. */
+                               chunked, the batch depth is the default and the device holds
+                               every tile's forward workgroup at once), 1 = fused whenever the
+                               batch depth is the default, -1 = never. Fused, the blend forward
+                               and backward are one launch: each tile's workgroup composites it
+                               and walks its first chunk back, the later chunks' workgroups
+                               wait for the tile's forward, so they fill the forward's tail.
+                               Images and loss are identical to the two launches. */
 } gsr_options;
 
 typedef struct {

@@ -802,6 +802,25 @@ void fused_launch_ppt(const BlendArgs& a, hipStream_t st) {
   else blend_fused_kernel<TW, TH, PPT, D, false><<<grid, NT, 0, st>>>(a);
 }
 
+template <int TW, int TH, int PPT>
+int64_t fused_resident_ppt() {
+  constexpr int NT = TW * TH / PPT;
+  constexpr int D = NT >= 256 ? 32 : (NT >= 64 ? 64 : NT);
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, blend_fused_kernel<TW, TH, PPT, D, true>, NT, 0) !=
+      hipSuccess)
+    return 0;
+  return (int64_t)cus * per_cu;
+}
+
+template <int TW, int TH>
+int64_t fused_resident(int ppt) {
+  if (ppt == 2 && TW * TH >= 128) return fused_resident_ppt<TW, TH, (TW * TH >= 128 ? 2 : 1)>();
+  return fused_resident_ppt<TW, TH, 1>();
+}
+
 template <int TW, int TH>
 void fused_launch(const BlendArgs& a, int ppt, hipStream_t st) {
   if (ppt == 2 && TW * TH >= 128) fused_launch_ppt<TW, TH, (TW * TH >= 128 ? 2 : 1)>(a, st);
@@ -898,6 +917,16 @@ void launch_blend_fused(const BlendArgs& a, int tile_w, int tile_h, int ppt, hip
   else if (tile_w == 16 && tile_h == 8) fused_launch<16, 8>(a, ppt, st);
   else if (tile_w == 8 && tile_h == 8) fused_launch<8, 8>(a, ppt, st);
   else if (tile_w == 32 && tile_h == 8) fused_launch<32, 8>(a, ppt, st);
+}
+
+int64_t blend_fused_resident(int tile_w, int tile_h, int ppt) {
+  int64_t r = 0;
+  if (tile_w == 16 && tile_h == 16) r = fused_resident<16, 16>(ppt);
+  else if (tile_w == 16 && tile_h == 8) r = fused_resident<16, 8>(ppt);
+  else if (tile_w == 8 && tile_h == 8) r = fused_resident<8, 8>(ppt);
+  else if (tile_w == 32 && tile_h == 8) r = fused_resident<32, 8>(ppt);
+  (void)hipGetLastError();
+  return r;
 }
 
 bool batch_depth_supported(int depth) { return depth == 0 || depth == 16 || depth == 32 || depth == 64; }

@@ -112,6 +112,7 @@ struct gsr_ctx {
   int chunk_len = 0;                    // backward work unit in list positions: 0 automatic, -1 whole lists
   int max_chunks = 4;                   // chunks per tile (the last takes the rest)
   int fuse_blend = 0;                   // mapping iteration: 0 automatic, 1 fused, -1 two launches
+  int64_t fused_resident = 0;           // workgroups of the fused blend launch the device holds at once
   float bg[3] = {0.f, 0.f, 0.f};
   float znear = 0.2f;
   int hip_err = 0;

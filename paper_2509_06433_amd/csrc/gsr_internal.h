@@ -202,6 +202,9 @@ void launch_blend_backward(const BlendArgs& a, int tile_w, int tile_h, int ppt, 
 // Forward (with the fused loss) and backward in one launch, at the default
 // batch depth; needs loss_target, loss_grad, g2, tile_done and err.
 void launch_blend_fused(const BlendArgs& a, int tile_w, int tile_h, int ppt, hipStream_t st);
+// Workgroups of the fused launch the current device holds at once (its CU
+// count times the kernel's occupancy per CU); 0 if the device cannot say.
+int64_t blend_fused_resident(int tile_w, int tile_h, int ppt);
 // Valid chunk settings: chunk_len 0 (whole tile lists) or a multiple of 16
 // up to 1 << 20, with 1 <= max_chunks <= 64.
 bool chunking_supported(int chunk_len, int max_chunks);
