@@ -227,7 +227,7 @@ int launch_back(gsr_ctx* ctx, Buffers& B, RenderPlan& P, hipStream_t st, const F
 }
 
 int launch_bwd(gsr_ctx* ctx, Buffers& B, const RenderPlan& P, const float* params, float* grad_params,
-               bool clear_g2, bool overwrite_grad, hipStream_t st, bool blend_done) {
+               bool clear_g2, bool overwrite_grad, hipStream_t st, bool blend_done, const IterCounters* counters) {
   if (P.total == 0) return GSR_OK;
   if (clear_g2) {
     StageTimer tm(ctx, GSR_STAGE_ZERO, st);
@@ -258,7 +258,7 @@ int launch_bwd(gsr_ctx* ctx, Buffers& B, const RenderPlan& P, const float* param
     StageTimer tm(ctx, GSR_STAGE_PROJECT_BWD, st);
     launch_project_backward(params, P.num, P.stride, P.deg, P.nv, as<ViewDesc>(B.views), ctx->znear,
                             as<float>(B.g2), as<uint32_t>(B.ntiles), grad_params, overwrite_grad,
-                            overwrite_grad && !clear_g2, st);
+                            overwrite_grad && !clear_g2, counters, st);
   }
   CHECK_LAUNCH(ctx);
   return GSR_OK;

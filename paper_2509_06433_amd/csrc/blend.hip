@@ -872,7 +872,7 @@ __global__ void __launch_bounds__(256) adam_kernel(float* __restrict__ p, const 
   if (skip && (skip[0] | skip[1])) return;
   if (step_dev) {
     // in double, as the host does: 1 - b^step cancels badly in float
-    const int step = *step_dev + 1;
+    const int step = *step_dev;
     bc1 = (float)(1.0 - pow((double)b1, (double)step));
     bc2 = (float)(1.0 - pow((double)b2, (double)step));
   }

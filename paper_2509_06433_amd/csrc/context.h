@@ -346,7 +346,8 @@ inline int bits_for(int64_t max_key) {
 //                 first unless clear_g2 is false. With overwrite_grad and not
 //                 clear_g2 (the mapping iteration) the projection backward
 //                 zeroes the g2 rows it reads, so g2 stays clean between
-//                 replays.
+//                 replays. With counters (and at least one Gaussian) the
+//                 projection backward also counts the iteration.
 // The launch_* functions make no allocation, copy or synchronisation, so a
 // stream capture can record them.
 int plan_render(gsr_ctx* ctx, const gsr_gaussians* g, int32_t nv, const gsr_camera* cams, RenderPlan* plan);
@@ -362,7 +363,8 @@ struct FusedLoss {
 int launch_back(gsr_ctx* ctx, Buffers& B, RenderPlan& plan, hipStream_t st, const FusedLoss* loss = nullptr,
                 bool fused = false);
 int launch_bwd(gsr_ctx* ctx, Buffers& B, const RenderPlan& plan, const float* params, float* grad_params,
-               bool clear_g2, bool overwrite_grad, hipStream_t st, bool blend_done = false);
+               bool clear_g2, bool overwrite_grad, hipStream_t st, bool blend_done = false,
+               const IterCounters* counters = nullptr);
 // Whether the mapping iteration fuses the blend forward and backward.
 bool use_fused_blend(const gsr_ctx* ctx, const RenderPlan& plan);
 int size_instances(gsr_ctx* ctx, Buffers& B, const RenderPlan& plan);

@@ -53,12 +53,52 @@ void launch_project(const float* params, int64_t n, int64_t stride, int deg, int
                     hipStream_t st);
 // Chain rule from screen-space gradients g2[V*N][10] to grad_params (+=, or
 // with overwrite = every plane written, zero where no view contributed).
+// Counters of the replayed mapping iteration (stats words).
+enum : int {
+  kStatAdamSteps = 0,
+  kStatIterations = 1,
+  kStatSkipped = 2,
+  kStatMaxInstances = 3,
+  kStatLastInstances = 4,
+  kStatErrors = 5,
+  kStatWords = 8
+};
+struct IterCounters {
+  const uint32_t* totals;   // [0] instance count, [1] error word, [2] instance overflow flag
+  uint32_t* stats;          // device counters, kStatWords
+  uint32_t* host;           // device address of the pinned host copy, or null
+  int adam;                 // the iteration ends with an Adam step
+};
+// One thread, after every kernel that can raise the error or overflow flag:
+// counts the replay (as skipped when a flag is set, and then not as an Adam
+// step), keeps the instance counts, and copies the counters to the host.
+__device__ inline void count_iteration(const IterCounters& c) {
+  const uint32_t count = c.totals[0];
+  const bool err = c.totals[1] != 0u, over = c.totals[2] != 0u;
+  uint32_t* s = c.stats;
+  if (err || over) {
+    s[kStatSkipped] += 1u;
+    if (err) s[kStatErrors] += 1u;
+  } else {
+    s[kStatIterations] += 1u;
+    if (c.adam) s[kStatAdamSteps] += 1u;
+  }
+  s[kStatMaxInstances] = max(s[kStatMaxInstances], count);
+  s[kStatLastInstances] = count;
+  if (c.host) {
+    for (int k = 0; k < kStatWords; ++k) c.host[k] = s[k];
+    __threadfence_system();
+  }
+}
+
 // Only (view, Gaussian) pairs with a nonzero tile count (ntiles[V*N]) are
 // visited: one thread per Gaussian walks its own visible views. zero_g2: the
-// rows read are zeroed, so g2 is all zero again afterwards.
+// rows read are zeroed, so g2 is all zero again afterwards. counters (may be
+// null): the first workgroup also counts the iteration (count_iteration).
 void launch_project_backward(const float* params, int64_t n, int64_t stride, int deg, int num_views,
                              const ViewDesc* views, float znear, float* g2, const uint32_t* ntiles,
-                             float* grad, bool overwrite, bool zero_g2, hipStream_t st);
+                             float* grad, bool overwrite, bool zero_g2, const IterCounters* counters,
+                             hipStream_t st);
 // Inspection copy of the splats of one view: out[n][16] (see gsr_copy_splats).
 void launch_export_splats(const float* params, int64_t n, int64_t stride, const ViewDesc* view, float znear,
                           const Splat* splats, const int4* rect, float* out, hipStream_t st);
@@ -212,9 +252,9 @@ bool chunking_supported(int chunk_len, int max_chunks);
 void launch_loss_l1(const ViewDesc* views, const ViewImages* rendered, const ViewImages* target,
                     const ViewImages* grad, int num_views, int max_pixels, float depth_weight,
                     float* loss, bool clear_loss, hipStream_t st);
-// Adam; with step_dev the bias corrections are those of step *step_dev + 1
-// (bc1, bc2 ignored); skip[0] or skip[1] nonzero (if skip is not null) leaves
-// everything unchanged.
+// Adam; with step_dev the bias corrections are those of step *step_dev, the
+// step count including this step (bc1, bc2 ignored); skip[0] or skip[1]
+// nonzero (if skip is not null) leaves everything unchanged.
 void launch_adam(float* p, const float* g, float* m, float* v, int64_t num, int64_t stride,
                  int planes, const float* lr_dev, float b1, float b2, float eps, float bc1,
                  float bc2, const uint32_t* step_dev, const uint32_t* skip, hipStream_t st);

@@ -21,30 +21,10 @@ namespace gsr {
 
 namespace {
 
-// stats words (device, copied to host at the end of each replay)
-enum : int {
-  kStatAdamSteps = 0,
-  kStatIterations = 1,
-  kStatSkipped = 2,
-  kStatMaxInstances = 3,
-  kStatLastInstances = 4,
-  kStatErrors = 5,
-  kStatWords = 8
-};
-
-__global__ void iteration_end_kernel(const uint32_t* __restrict__ totals, uint32_t* __restrict__ stats, int adam) {
-  if (threadIdx.x != 0) return;
-  const uint32_t count = totals[0];
-  const bool err = totals[1] != 0u, over = totals[2] != 0u;
-  if (err || over) {
-    stats[kStatSkipped] += 1u;
-    if (err) stats[kStatErrors] += 1u;
-  } else {
-    stats[kStatIterations] += 1u;
-    if (adam) stats[kStatAdamSteps] += 1u;
-  }
-  stats[kStatMaxInstances] = max(stats[kStatMaxInstances], count);
-  stats[kStatLastInstances] = count;
+// Counts an iteration without Gaussians (otherwise the projection backward
+// does, in its first workgroup, which saves a node per replay).
+__global__ void iteration_end_kernel(IterCounters c) {
+  if (threadIdx.x == 0) count_iteration(c);
 }
 
 }  // namespace
@@ -71,7 +51,8 @@ struct GraphState {
   std::vector<ViewImages> outs, targets;
   std::vector<float> lr;
   DevBuf tdesc, gimg, lrbuf, stats;
-  uint32_t* host_stats = nullptr;      // pinned, written by the last node of each replay
+  uint32_t* host_stats = nullptr;      // pinned, written by the node that counts each replay
+  uint32_t* host_stats_dev = nullptr;  // its device address
   // One captured graph, instantiated kRing times. With timed stages each
   // instance's event-record nodes are given their own events, so a replay
   // never touches an instance that may still run: instance k is reused only
@@ -141,6 +122,7 @@ int init_state(gsr_ctx* ctx, GraphState* G) {
   for (GraphState::Instance& I : G->inst) HIP_TRY(ctx, hipEventCreateWithFlags(&I.done, hipEventDisableTiming));
   HIP_TRY(ctx, hipHostMalloc((void**)&G->host_stats, sizeof(uint32_t) * kStatWords, hipHostMallocDefault));
   std::memset(G->host_stats, 0, sizeof(uint32_t) * kStatWords);
+  HIP_TRY(ctx, hipHostGetDevicePointer((void**)&G->host_stats_dev, G->host_stats, 0));
   RET_IF(ensure(ctx, G->stats, sizeof(uint32_t) * kStatWords));
   HIP_TRY(ctx, hipMemset(G->stats.p, 0, sizeof(uint32_t) * kStatWords));
   HIP_TRY(ctx, hipDeviceSynchronize());
@@ -219,16 +201,21 @@ int record_iteration(gsr_ctx* ctx, GraphState* G, float* params, float* grad, fl
   // the L1 loss and its image gradients are formed by the compositing itself
   const FusedLoss fl{as<ViewImages>(G->tdesc), depth_weight, loss};
   RET_IF(launch_back(ctx, B, P, st, &fl, fused));
-  RET_IF(launch_bwd(ctx, B, P, params, grad, false, true, st, fused));
+  // the iteration is counted (and the counters reach the pinned host copy)
+  // by the projection backward, after every kernel that can raise the error
+  // or overflow flag and before Adam, which reads the step count
+  const IterCounters ic{totals, as<uint32_t>(G->stats), G->host_stats_dev, adam ? 1 : 0};
+  RET_IF(launch_bwd(ctx, B, P, params, grad, false, true, st, fused, &ic));
+  if (P.num == 0) {
+    iteration_end_kernel<<<1, 64, 0, st>>>(ic);
+    CHECK_LAUNCH(ctx);
+  }
   if (adam) {
     StageTimer tm(ctx, GSR_STAGE_ADAM, st);
     launch_adam(params, grad, adam->m, adam->v, P.num, P.stride, planes, as<float>(G->lrbuf), adam->beta1,
                 adam->beta2, adam->eps, 1.0f, 1.0f, as<uint32_t>(G->stats) + kStatAdamSteps, totals + 1, st);
   }
   CHECK_LAUNCH(ctx);
-  iteration_end_kernel<<<1, 64, 0, st>>>(totals, as<uint32_t>(G->stats), adam ? 1 : 0);
-  CHECK_LAUNCH(ctx);
-  HIP_TRY(ctx, hipMemcpyAsync(G->host_stats, G->stats.p, sizeof(uint32_t) * kStatWords, hipMemcpyDeviceToHost, st));
   return GSR_OK;
 }
 

@@ -654,8 +654,9 @@ __global__ void __launch_bounds__(256) project_backward_kernel(const float* __re
                                                                float* __restrict__ g2,
                                                                const uint32_t* __restrict__ ntiles,
                                                                float* __restrict__ grad, bool overwrite,
-                                                               bool zero_g2) {
+                                                               bool zero_g2, IterCounters counters) {
   constexpr int K = (DEG + 1) * (DEG + 1);
+  if (counters.stats && blockIdx.x == 0 && threadIdx.x == 0) count_iteration(counters);
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     double gmean[3] = {0, 0, 0}, gls[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, glogit = 0.0;
     float gsh[3 * K];          // SH gradients: one term per view, float is enough
@@ -766,22 +767,27 @@ void launch_project(const float* params, int64_t n, int64_t stride, int deg, int
 
 void launch_project_backward(const float* params, int64_t n, int64_t stride, int deg, int num_views,
                              const ViewDesc* views, float znear, float* g2, const uint32_t* ntiles, float* grad,
-                             bool overwrite, bool zero_g2, hipStream_t st) {
+                             bool overwrite, bool zero_g2, const IterCounters* counters, hipStream_t st) {
   (void)znear;
   if (n == 0) return;
+  const IterCounters ic = counters ? *counters : IterCounters{nullptr, nullptr, nullptr, 0};
   const int gsz = grid_for(n, 256);
   switch (deg) {
     case 0:
-      project_backward_kernel<0><<<gsz, 256, 0, st>>>(params, n, stride, num_views, views, g2, ntiles, grad, overwrite, zero_g2);
+      project_backward_kernel<0><<<gsz, 256, 0, st>>>(params, n, stride, num_views, views, g2, ntiles, grad, overwrite,
+                                                          zero_g2, ic);
       break;
     case 1:
-      project_backward_kernel<1><<<gsz, 256, 0, st>>>(params, n, stride, num_views, views, g2, ntiles, grad, overwrite, zero_g2);
+      project_backward_kernel<1><<<gsz, 256, 0, st>>>(params, n, stride, num_views, views, g2, ntiles, grad, overwrite,
+                                                          zero_g2, ic);
       break;
     case 2:
-      project_backward_kernel<2><<<gsz, 256, 0, st>>>(params, n, stride, num_views, views, g2, ntiles, grad, overwrite, zero_g2);
+      project_backward_kernel<2><<<gsz, 256, 0, st>>>(params, n, stride, num_views, views, g2, ntiles, grad, overwrite,
+                                                          zero_g2, ic);
       break;
     default:
-      project_backward_kernel<3><<<gsz, 256, 0, st>>>(params, n, stride, num_views, views, g2, ntiles, grad, overwrite, zero_g2);
+      project_backward_kernel<3><<<gsz, 256, 0, st>>>(params, n, stride, num_views, views, g2, ntiles, grad, overwrite,
+                                                          zero_g2, ic);
       break;
   }
 }
