@@ -123,8 +123,11 @@ int launch_front(gsr_ctx* ctx, Buffers& B, RenderPlan& P, const float* params, h
   CHECK_LAUNCH(ctx);
   {
     StageTimer tm(ctx, GSR_STAGE_SCAN, st);
+    // with the instance capacity fixed ahead (the captured iteration) the
+    // scan also writes the emission plan
+    P.plan_ready = P.capacity > 0;
     scan_gather_exclusive(as<uint32_t>(B.ntiles), sva, as<uint32_t>(B.offsets), P.total, totals + 3, totals, oscan,
-                          totals + 1, false, st);
+                          totals + 1, false, st, P.plan_ready ? as<uint32_t>(B.block_rank) : nullptr, P.capacity);
   }
   CHECK_LAUNCH(ctx);
   sv = sva;
@@ -173,7 +176,7 @@ int launch_back(gsr_ctx* ctx, Buffers& B, RenderPlan& P, hipStream_t st, const F
     StageTimer tm(ctx, GSR_STAGE_EMIT, st);
     launch_emit(P.sorted_splats, as<uint32_t>(B.offsets), totals, totals + 3, as<Splat>(B.splats), P.total, ik, iv,
                 P.capacity, totals + 2, thist, tbits,
-                as<uint32_t>(B.block_rank), st);
+                as<uint32_t>(B.block_rank), P.plan_ready, st);
   }
   CHECK_LAUNCH(ctx);
   {

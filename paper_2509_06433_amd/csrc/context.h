@@ -52,6 +52,7 @@ struct RenderPlan {
   int64_t capacity = 0;                // instance slots (eager: exactly the count)
   std::vector<ViewDesc> views;
   uint32_t* sorted_splats = nullptr;   // depth-sorted splat indices
+  bool plan_ready = false;             // the offsets scan wrote the emission plan
   uint32_t* inst_keys = nullptr;       // sorted instance list
   uint32_t* inst_vals = nullptr;
 };

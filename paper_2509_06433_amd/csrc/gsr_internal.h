@@ -138,10 +138,14 @@ int64_t scan_partial_elems(int64_t n);
 // min(*n_dev, n) elements (n if n_dev is null); total -> *total_dev. Single
 // pass with decoupled look-back; clear = false: the caller has zeroed the
 // scratch (scan_partial_elems(n) words). *err is raised if a bounded wait
-// expired.
+// expired. With block_rank (the emission's plan for `capacity` instance
+// slots, emit_plan_elems(capacity) words) the scan also records, for every
+// block of emission output positions below the capacity, the element whose
+// run holds the block's first position, so that launch_emit needs no plan
+// kernel (plan_ready).
 void scan_gather_exclusive(const uint32_t* in, const uint32_t* idx, uint32_t* out, int64_t n,
                            const uint32_t* n_dev, uint32_t* total_dev, uint32_t* scratch, uint32_t* err, bool clear,
-                           hipStream_t st);
+                           hipStream_t st, uint32_t* block_rank = nullptr, int64_t capacity = 0);
 // Order-preserving compaction of the n splats with a nonzero tile count:
 // out_keys/out_vals[r] = key and index of the r-th one, *count_out = their
 // number. Same scratch size and semantics as scan_gather_exclusive.
@@ -158,7 +162,7 @@ int64_t emit_plan_elems(int64_t capacity);
 void launch_emit(const uint32_t* sorted_s, const uint32_t* offsets, const uint32_t* total_dev,
                  const uint32_t* count_dev, const Splat* splats, int64_t count, uint32_t* keys,
                  uint32_t* vals, int64_t capacity, uint32_t* overflow, uint32_t* hist, int hist_bits,
-                 uint32_t* block_rank, hipStream_t st);
+                 uint32_t* block_rank, bool plan_ready, hipStream_t st);
 // ranges[t] = (start, end) of global tile t in the sorted key array of
 // min(*n_dev, count) instances (count if n_dev is null); clear = false: the
 // caller has zeroed ranges.

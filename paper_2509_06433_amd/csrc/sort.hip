@@ -18,6 +18,11 @@ namespace {
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanChunk = kScanThreads * kScanItems;      // 2048
+// emission: output positions per workgroup, its threads, and the histogram
+// words it can accumulate (4 passes of 8 bits)
+constexpr int kEmitBlock = 1024;
+constexpr int kEmitThreads = 256;
+constexpr int kEmitHist = 1024;
 
 constexpr int kSortThreads = 256;                          // 4 wave64
 constexpr int kSortItems = 16;                             // histogram kernel
@@ -82,7 +87,8 @@ constexpr unsigned long long kScanInc = 2ull << 32;
 __global__ void __launch_bounds__(kScanThreads) scan_lookback_kernel(
     const uint32_t* __restrict__ in, const uint32_t* __restrict__ idx, const uint32_t* __restrict__ n_dev,
     int64_t n_host, uint32_t* __restrict__ out, uint32_t* __restrict__ total_out,
-    unsigned long long* __restrict__ status, uint32_t* __restrict__ err) {
+    unsigned long long* __restrict__ status, uint32_t* __restrict__ err, uint32_t* __restrict__ block_rank,
+    int64_t plan_blocks) {
   __shared__ uint32_t tile[kScanChunk];
   __shared__ uint32_t s_excl;
   const int64_t n = n_dev ? min((int64_t)*n_dev, n_host) : n_host;
@@ -155,6 +161,14 @@ __global__ void __launch_bounds__(kScanThreads) scan_lookback_kernel(
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     tile[threadIdx.x * kScanItems + k] = run;
+    // the emission plan: element j's run [run, run + v) holds the first
+    // position of every output block starting in it
+    if (block_rank) {
+      const uint32_t j = (uint32_t)(base + threadIdx.x * kScanItems + k);
+      for (int64_t b = ((int64_t)run + kEmitBlock - 1) / kEmitBlock;
+           b < plan_blocks && b * kEmitBlock < (int64_t)run + v[k]; ++b)
+        block_rank[b] = j;
+    }
     run += v[k];
   }
   __syncthreads();
@@ -534,9 +548,6 @@ __global__ void __launch_bounds__(kSortThreads) onesweep_pass_kernel(
 // instance) are staged with their offsets, and each thread writes output
 // positions round-robin, finding the owning rank by binary search over the
 // staged offsets. Positions past `capacity` are dropped and flagged.
-constexpr int kEmitBlock = 1024;
-constexpr int kEmitThreads = 256;
-constexpr int kEmitHist = 1024;   // histogram words the emission can accumulate (4 passes of 8 bits)
 
 __global__ void __launch_bounds__(256) emit_plan_kernel(const uint32_t* __restrict__ offsets,
                                                         const uint32_t* __restrict__ total_dev,
@@ -743,7 +754,7 @@ uint32_t* radix_hist(uint32_t* scratch, int64_t n, int bits, int* rb, int* passe
 
 void scan_gather_exclusive(const uint32_t* in, const uint32_t* idx, uint32_t* out, int64_t n,
                            const uint32_t* n_dev, uint32_t* total_dev, uint32_t* scratch, uint32_t* err, bool clear,
-                           hipStream_t st) {
+                           hipStream_t st, uint32_t* block_rank, int64_t capacity) {
   if (n == 0) {
     if (total_dev) fill_u32_kernel<<<1, 64, 0, st>>>(total_dev, 0u, 1);
     return;
@@ -751,7 +762,8 @@ void scan_gather_exclusive(const uint32_t* in, const uint32_t* idx, uint32_t* ou
   const int nb = blocks_for(n, kScanChunk);
   if (clear) fill_u32_kernel<<<grid_cap(2 * nb, 256), 256, 0, st>>>(scratch, 0u, 2 * nb);
   unsigned long long* status = reinterpret_cast<unsigned long long*>(scratch);
-  scan_lookback_kernel<<<nb, kScanThreads, 0, st>>>(in, idx, n_dev, n, out, total_dev, status, err);
+  scan_lookback_kernel<<<nb, kScanThreads, 0, st>>>(in, idx, n_dev, n, out, total_dev, status, err, block_rank,
+                                                    (capacity + kEmitBlock - 1) / kEmitBlock);
 }
 
 void launch_compact_visible(const uint32_t* ntiles, const uint32_t* keys, int64_t n, uint32_t* out_keys,
@@ -802,7 +814,7 @@ int64_t emit_plan_elems(int64_t capacity) { return (capacity + kEmitBlock - 1) /
 void launch_emit(const uint32_t* sorted_s, const uint32_t* offsets, const uint32_t* total_dev,
                  const uint32_t* count_dev, const Splat* splats, int64_t count, uint32_t* keys,
                  uint32_t* vals, int64_t capacity, uint32_t* overflow, uint32_t* hist, int hist_bits,
-                 uint32_t* block_rank, hipStream_t st) {
+                 uint32_t* block_rank, bool plan_ready, hipStream_t st) {
   if (count == 0) return;
   int rb = 8, hp = 0;
   if (hist_bits > 0) radix_plan(hist_bits, &rb, &hp);
@@ -814,7 +826,8 @@ void launch_emit(const uint32_t* sorted_s, const uint32_t* offsets, const uint32
                                             vals, capacity, overflow, nullptr, rb, hp);
     return;
   }
-  emit_plan_kernel<<<grid_cap(count, 256), 256, 0, st>>>(offsets, total_dev, count_dev, count, nblocks, block_rank);
+  if (!plan_ready)
+    emit_plan_kernel<<<grid_cap(count, 256), 256, 0, st>>>(offsets, total_dev, count_dev, count, nblocks, block_rank);
   emit_kernel<<<(unsigned)nblocks, kEmitThreads, 0, st>>>(sorted_s, offsets, total_dev, count_dev, block_rank, splats,
                                                           count, keys, vals, capacity, overflow, fits ? hist : nullptr,
                                                           rb, hp);
