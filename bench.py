@@ -71,6 +71,8 @@ def parse():
     ap.add_argument("--chunk-len", type=int, default=0,
                     help="backward work unit in list positions (0 = automatic, -1 = whole tile lists)")
     ap.add_argument("--max-chunks", type=int, default=0, help="backward chunks per tile (0 = default)")
+    ap.add_argument("--depth-sort", type=int, default=0,
+                    help="0 = automatic, 1 = per tile after binning, 2 = once over all splats before binning")
     ap.add_argument("--fuse-blend", type=int, default=0,
                     help="graph mode: 0 = automatic, 1 = blend forward and backward in one launch, -1 = two launches")
     ap.add_argument("--tile-order", type=int, default=0,
@@ -128,7 +130,7 @@ def main():
     deg = scene.sh_degree
     R = Rasterizer(tile_w=tw, tile_h=th, pixels_per_thread=args.ppt, batch_depth=args.batch_depth,
                    tile_order=args.tile_order, chunk_len=args.chunk_len, max_chunks=args.max_chunks,
-                   fuse_blend=args.fuse_blend)
+                   fuse_blend=args.fuse_blend, depth_sort=args.depth_sort)
     dev = torch.device("cuda:0")
     if args.calibrate_copy:
         src = torch.ones(64 * 1024 * 1024, device=dev)
@@ -162,7 +164,7 @@ def main():
         R.close()
         R = Rasterizer(tile_w=tuned["tile_w"], tile_h=tuned["tile_h"], pixels_per_thread=tuned["pixels_per_thread"],
                        batch_depth=tuned["batch_depth"], tile_order=args.tile_order, chunk_len=tuned["chunk_len"],
-                       max_chunks=tuned["max_chunks"], fuse_blend=args.fuse_blend)
+                       max_chunks=tuned["max_chunks"], fuse_blend=args.fuse_blend, depth_sort=args.depth_sort)
         outs = R.alloc_images(cams, dev)
     from paper_2509_06433_amd import _lib
     adam = dict(m=m, v=v, lr=lrs, beta1=0.9, beta2=0.999, eps=1e-15) if use_adam else None
@@ -252,7 +254,7 @@ def main():
         # blend launches (same kernels up to the forward)
         R2 = Rasterizer(tile_w=R.tile_w, tile_h=R.tile_h, pixels_per_thread=R.pixels_per_thread,
                         batch_depth=R.batch_depth, tile_order=R.tile_order, chunk_len=R.chunk_len,
-                        max_chunks=R.max_chunks, fuse_blend=-1)
+                        max_chunks=R.max_chunks, fuse_blend=-1, depth_sort=R.depth_sort)
         outs2 = R2.alloc_images(cams, dev)
         p2 = params0.clone()
         g2 = torch.zeros_like(p2)

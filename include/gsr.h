@@ -92,6 +92,11 @@ typedef struct {
                                and walks its first chunk back, the later chunks' workgroups
                                wait for the tile's forward, so they fill the forward's tail.
                                Images and loss are identical to the two launches. */
+  int32_t depth_sort;       /* 0 = automatic (per tile when the views hold at most 2^19 splats,
+                               N x views, else once globally), 1 = each tile's list is sorted by
+                               depth after binning (the splats are binned in index order),
+                               2 = all visible splats are sorted by depth once before binning.
+                               The lists are identical. */
 } gsr_options;
 
 typedef struct {
@@ -255,6 +260,7 @@ typedef enum {
   GSR_STAGE_TILE_SORT, GSR_STAGE_RANGES, GSR_STAGE_BLEND_FWD, GSR_STAGE_LOSS,
   GSR_STAGE_BLEND_BWD, GSR_STAGE_PROJECT_BWD, GSR_STAGE_ADAM, GSR_STAGE_ZERO,
   GSR_STAGE_BLEND,          /* fused blend forward and backward (mapping iteration) */
+  GSR_STAGE_TILE_DEPTH,     /* per-tile depth sort */
   GSR_NUM_STAGES
 } gsr_stage;
 

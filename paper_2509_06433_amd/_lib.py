@@ -25,7 +25,7 @@ EXPORTED = sorted(["gsr_create", "gsr_destroy", "gsr_render", "gsr_render1", "gs
                    "gsr_status_string", "gsr_mapping_iteration", "gsr_mapping_status"])
 
 STAGES = ["project", "depth_sort", "scan", "emit", "tile_sort", "ranges", "blend_fwd", "loss", "blend_bwd",
-          "project_bwd", "adam", "zero", "blend"]
+          "project_bwd", "adam", "zero", "blend", "tile_depth"]
 
 
 class GsrError(RuntimeError):
@@ -41,7 +41,7 @@ class gsr_options(ctypes.Structure):
     _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("batch_depth", ctypes.c_int32),
                 ("bg", ctypes.c_float * 3), ("znear", ctypes.c_float), ("pixels_per_thread", ctypes.c_int32),
                 ("tile_order", ctypes.c_int32), ("chunk_len", ctypes.c_int32), ("max_chunks", ctypes.c_int32),
-                ("fuse_blend", ctypes.c_int32)]
+                ("fuse_blend", ctypes.c_int32), ("depth_sort", ctypes.c_int32)]
 
 
 class gsr_camera(ctypes.Structure):
@@ -171,9 +171,9 @@ def _check(ctx, fn, rc):
 # --- one wrapper per C entry point ------------------------------------------
 
 def gsr_create(tile_w=16, tile_h=16, batch_depth=0, bg=(0.0, 0.0, 0.0), znear=0.2, pixels_per_thread=0,
-               tile_order=0, chunk_len=0, max_chunks=0, fuse_blend=0):
+               tile_order=0, chunk_len=0, max_chunks=0, fuse_blend=0, depth_sort=0):
     opt = gsr_options(tile_w, tile_h, batch_depth, (ctypes.c_float * 3)(*bg), znear, pixels_per_thread, tile_order,
-                      chunk_len, max_chunks, fuse_blend)
+                      chunk_len, max_chunks, fuse_blend, depth_sort)
     h = ctypes.c_void_p()
     _check(None, "gsr_create", load().gsr_create(ctypes.byref(h), ctypes.byref(opt)))
     return h

@@ -99,8 +99,11 @@ void back_clears(Buffers& B, const RenderPlan& P, ClearList& L) {
 int launch_front(gsr_ctx* ctx, Buffers& B, RenderPlan& P, const float* params, hipStream_t st) {
   const int nv = P.nv;
   uint32_t* totals = as<uint32_t>(B.total);
+  // with the global depth sort the projection also forms its digit histograms
+  const bool global_depth = !per_tile_depth(ctx, P);
   int zrb = 8, zpasses = 0;
-  uint32_t* zhist = P.total > 1 ? radix_hist(as<uint32_t>(B.hist), P.total, 32, &zrb, &zpasses) : nullptr;
+  uint32_t* zhist =
+      global_depth && P.total > 1 ? radix_hist(as<uint32_t>(B.hist), P.total, 32, &zrb, &zpasses) : nullptr;
   {
     StageTimer tm(ctx, GSR_STAGE_PROJECT, st);
     launch_project(params, P.num, P.stride, P.deg, nv, as<ViewDesc>(B.views), ctx->tile_w, ctx->tile_h, ctx->znear,
@@ -115,10 +118,13 @@ int launch_front(gsr_ctx* ctx, Buffers& B, RenderPlan& P, const float* params, h
   uint32_t* cscan = as<uint32_t>(B.partials);
   uint32_t* oscan = cscan + scan_partial_elems(P.total);
   {
-    // only the visible splats (count in totals[3]) are sorted and binned
+    // only the visible splats (count in totals[3]) are binned; with the
+    // global depth sort they are sorted by depth first, else they are binned
+    // in index order and each tile's list is sorted after binning
     StageTimer tm(ctx, GSR_STAGE_DEPTH_SORT, st);
     launch_compact_visible(as<uint32_t>(B.ntiles), zk, P.total, zka, sva, totals + 3, cscan, totals + 1, false, st);
-    radix_sort_pairs(zka, sva, zk, sv, P.total, totals + 3, 32, as<uint32_t>(B.hist), totals + 1, false, true, st);
+    if (global_depth)
+      radix_sort_pairs(zka, sva, zk, sv, P.total, totals + 3, 32, as<uint32_t>(B.hist), totals + 1, false, true, st);
   }
   CHECK_LAUNCH(ctx);
   {
@@ -156,6 +162,16 @@ static void set_chunking(const gsr_ctx* ctx, Buffers& B, const RenderPlan& P, Bl
 // holding its slot through its own first chunk, and the waiting units queue
 // behind all of them (measured at 3225 tiles: 1336 us fused against
 // 422 + 705 us in two launches; at 1200 tiles: 244 against 287).
+// Automatic: per tile for at most 2^19 splats. The global sort's four passes
+// are latency-bound at such sizes (14 us each at 200k), while sorting every
+// tile's list in LDS costs in proportion to the instances (640x480/200k:
+// 58 -> 37 us); with millions of splats the global passes are the cheaper
+// (8 views, 500k: 124 against 356 us; 1200x680/1M: 92 against 494 us).
+bool per_tile_depth(const gsr_ctx* ctx, const RenderPlan& P) {
+  if (ctx->depth_sort != 0) return ctx->depth_sort == 1;
+  return P.total <= (int64_t(1) << 19);
+}
+
 bool use_fused_blend(const gsr_ctx* ctx, const RenderPlan& P) {
   if (ctx->fuse_blend < 0 || ctx->batch_depth != 0) return false;
   if (ctx->fuse_blend > 0) return true;
@@ -189,6 +205,11 @@ int launch_back(gsr_ctx* ctx, Buffers& B, RenderPlan& P, hipStream_t st, const F
     StageTimer tm(ctx, GSR_STAGE_RANGES, st);
     launch_tile_ranges(ik, totals, P.capacity, as<uint2>(B.ranges), P.ntiles, false, st);
     if (use_lpt(ctx, P)) launch_tile_order(as<uint2>(B.ranges), P.ntiles, as<uint32_t>(B.order), st);
+  }
+  CHECK_LAUNCH(ctx);
+  if (per_tile_depth(ctx, P)) {
+    StageTimer tm(ctx, GSR_STAGE_TILE_DEPTH, st);
+    launch_tile_depth_sort(as<uint2>(B.ranges), P.ntiles, as<Splat>(B.splats), ik, iv, ika, iva, st);
   }
   CHECK_LAUNCH(ctx);
   P.inst_keys = ik;
@@ -385,6 +406,11 @@ int gsr_create(gsr_ctx** out, const gsr_options* opt) {
       return GSR_ERR_UNSUPPORTED;
     }
     ctx->fuse_blend = opt->fuse_blend;
+    if (opt->depth_sort < 0 || opt->depth_sort > 2) {
+      delete ctx;
+      return GSR_ERR_UNSUPPORTED;
+    }
+    ctx->depth_sort = opt->depth_sort;
     for (int k = 0; k < 3; ++k) ctx->bg[k] = opt->bg[k];
     ctx->znear = opt->znear > 0.f ? opt->znear : 0.2f;
   }

@@ -114,6 +114,7 @@ struct gsr_ctx {
   int max_chunks = 4;                   // chunks per tile (the last takes the rest)
   int fuse_blend = 0;                   // mapping iteration: 0 automatic, 1 fused, -1 two launches
   int64_t fused_resident = 0;           // workgroups of the fused blend launch the device holds at once
+  int depth_sort = 0;                   // 0 automatic, 1 per-tile sort after binning, 2 one global sort before
   float bg[3] = {0.f, 0.f, 0.f};
   float znear = 0.2f;
   int hip_err = 0;
@@ -368,6 +369,9 @@ int launch_bwd(gsr_ctx* ctx, Buffers& B, const RenderPlan& plan, const float* pa
                const IterCounters* counters = nullptr);
 // Whether the mapping iteration fuses the blend forward and backward.
 bool use_fused_blend(const gsr_ctx* ctx, const RenderPlan& plan);
+// Whether each tile's list is sorted by depth after binning (else all visible
+// splats are sorted once before binning).
+bool per_tile_depth(const gsr_ctx* ctx, const RenderPlan& plan);
 int size_instances(gsr_ctx* ctx, Buffers& B, const RenderPlan& plan);
 void free_buffers(Buffers& B);
 // Frees the captured mapping iteration and its buffers (iteration.hip).

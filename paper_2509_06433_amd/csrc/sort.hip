@@ -673,6 +673,214 @@ __global__ void __launch_bounds__(kOrderThreads) tile_order_kernel(const uint2* 
   }
 }
 
+// Per-tile depth order. The instances of a tile arrive in splat-index order
+// (emission in index order, then a stable sort by tile); a stable LSD radix
+// sort of each tile's list on the raw bits of z (positive floats order like
+// their bits) then gives the order (tile, z bits, index). One workgroup per
+// tile; four 8-bit passes. Every wave ranks rows of 64 keys in list order
+// with ballots (the rank among equal digits in the row, plus the wave's
+// running count of that digit), so the scatter keeps equal digits in list
+// order. A list of at most kTileSortCap entries is sorted in LDS; a longer one
+// chunk by chunk through the alternate key/value buffers, its tile keys used
+// as scratch and rewritten at the end.
+// Ranks one chunk of n <= kTileSortCap keys held in registers, wave w owning
+// the chunk's entries [w R 64, (w + 1) R 64) with R = kTileSortRows, row r its
+// entries w R 64 + 64 r + lane: off[r] = the entry's rank among the wave's
+// earlier entries of its digit; wcnt[w][d] = the wave's count of digit d.
+constexpr int kTileSortThreads = 256;
+constexpr int kTileSortWaves = kTileSortThreads / 64;
+// rows of 64 per wave per chunk: 6 keeps the kernel at 86 VGPRs and 29.7 KB of
+// LDS, five workgroups per CU (8: 102 VGPRs, 38 KB, four; 640x480/200k:
+// 43 -> 37 us)
+constexpr int kTileSortRows = 6;
+constexpr int kTileSortCap = kTileSortThreads * kTileSortRows;            // 1536 entries per chunk
+
+__device__ __forceinline__ void tile_sort_rank(const uint32_t* k, int n, int shift, uint32_t* off,
+                                               uint32_t (*wcnt)[256], int wave, int lane) {
+  const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+  for (int r = 0; r < kTileSortRows; ++r) {
+    const int e = wave * (64 * kTileSortRows) + r * 64 + lane;
+    const bool valid = e < n;
+    const uint32_t d = (k[r] >> shift) & 255u;
+    uint64_t mask = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t bal = __ballot(bit);
+      mask &= bit ? bal : ~bal;
+    }
+    const uint32_t rank = (uint32_t)__popcll(mask & lt_mask);
+    const uint32_t before = wcnt[wave][d];
+    off[r] = valid ? before + rank : 0xFFFFFFFFu;
+    if (valid && rank == 0) wcnt[wave][d] = before + (uint32_t)__popcll(mask);
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+__global__ void __launch_bounds__(kTileSortThreads) tile_depth_sort_kernel(
+    const uint2* __restrict__ ranges, int64_t num_tiles, const Splat* __restrict__ splats,
+    uint32_t* __restrict__ keys, uint32_t* __restrict__ vals, uint32_t* __restrict__ keys_alt,
+    uint32_t* __restrict__ vals_alt) {
+  __shared__ uint32_t s_k[2][kTileSortCap], s_v[2][kTileSortCap];
+  __shared__ uint32_t wcnt[kTileSortWaves][256];
+  __shared__ uint32_t s_start[256];     // the digit's first position (whole list) plus earlier chunks' count
+  __shared__ uint32_t s_wsum[kTileSortWaves];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int64_t tile = blockIdx.x; tile < num_tiles; tile += gridDim.x) {
+    const uint2 rg = ranges[tile];
+    const int n = (int)(rg.y - rg.x);
+    if (n < 2) continue;
+    uint32_t k[kTileSortRows], v[kTileSortRows], off[kTileSortRows];
+    if (n <= kTileSortCap) {
+      // in LDS: load, then four passes between the two buffers
+#pragma unroll
+      for (int r = 0; r < kTileSortRows; ++r) {
+        const int e = wave * (64 * kTileSortRows) + r * 64 + lane;
+        v[r] = e < n ? vals[rg.x + e] : 0u;
+        k[r] = e < n ? __float_as_uint(splats[v[r]].w0.z) : 0xFFFFFFFFu;
+      }
+      for (int pass = 0; pass < 4; ++pass) {
+        const int shift = 8 * pass;
+        for (int w = 0; w < kTileSortWaves; ++w) wcnt[w][tid] = 0u;
+        __syncthreads();
+        tile_sort_rank(k, n, shift, off, wcnt, wave, lane);
+        __syncthreads();
+        // per digit: exclusive prefix over the waves, and the digit total
+        uint32_t acc = 0;
+        for (int w = 0; w < kTileSortWaves; ++w) {
+          const uint32_t c = wcnt[w][tid];
+          wcnt[w][tid] = acc;
+          acc += c;
+        }
+        // exclusive scan of the totals over the 256 digits (one per thread)
+        uint32_t x = acc;
+#pragma unroll
+        for (int dd = 1; dd < 64; dd <<= 1) {
+          const uint32_t y = __shfl_up(x, dd, 64);
+          if (lane >= dd) x += y;
+        }
+        if (lane == 63) s_wsum[wave] = x;
+        __syncthreads();
+        uint32_t base = 0;
+        for (int w = 0; w < wave; ++w) base += s_wsum[w];
+        s_start[tid] = base + x - acc;
+        __syncthreads();
+        const int dst = (pass + 1) & 1;
+#pragma unroll
+        for (int r = 0; r < kTileSortRows; ++r) {
+          if (off[r] == 0xFFFFFFFFu) continue;
+          const uint32_t d = (k[r] >> shift) & 255u;
+          const uint32_t pos = s_start[d] + wcnt[wave][d] + off[r];
+          if (pos < (uint32_t)n) {     // always, when the counts are right; never outside the list
+            s_k[dst][pos] = k[r];
+            s_v[dst][pos] = v[r];
+          }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kTileSortRows; ++r) {
+          const int e = wave * (64 * kTileSortRows) + r * 64 + lane;
+          if (e < n) {
+            k[r] = s_k[dst][e];
+            v[r] = s_v[dst][e];
+          }
+        }
+        __syncthreads();
+      }
+#pragma unroll
+      for (int r = 0; r < kTileSortRows; ++r) {
+        const int e = wave * (64 * kTileSortRows) + r * 64 + lane;
+        if (e < n) vals[rg.x + e] = v[r];
+      }
+    } else {
+      // longer lists, through global memory: per pass, the digit totals of
+      // the whole list, then every chunk in list order scattered after the
+      // earlier chunks' entries of each digit; passes alternate between
+      // (keys, vals) and (keys_alt, vals_alt) over the tile's range
+      for (int pass = 0; pass < 4; ++pass) {
+        const int shift = 8 * pass;
+        const uint32_t* ks = (pass & 1) ? keys_alt : keys;
+        const uint32_t* vs = (pass & 1) ? vals_alt : vals;
+        uint32_t* kd = (pass & 1) ? keys : keys_alt;
+        uint32_t* vd = (pass & 1) ? vals : vals_alt;
+        // digit totals of the whole list (the ranking's counts, chunk by chunk)
+        uint32_t total = 0;
+        for (int c0 = 0; c0 < n; c0 += kTileSortCap) {
+          const int cn = min(kTileSortCap, n - c0);
+#pragma unroll
+          for (int r = 0; r < kTileSortRows; ++r) {
+            const int e = wave * (64 * kTileSortRows) + r * 64 + lane;
+            k[r] = e < cn ? (pass == 0 ? __float_as_uint(splats[vs[rg.x + c0 + e]].w0.z) : ks[rg.x + c0 + e])
+                          : 0xFFFFFFFFu;
+          }
+          for (int w = 0; w < kTileSortWaves; ++w) wcnt[w][tid] = 0u;
+          __syncthreads();
+          tile_sort_rank(k, cn, shift, off, wcnt, wave, lane);
+          __syncthreads();
+          for (int w = 0; w < kTileSortWaves; ++w) total += wcnt[w][tid];
+          __syncthreads();
+        }
+        s_start[tid] = total;
+        __syncthreads();
+        {
+          const uint32_t acc = s_start[tid];
+          uint32_t x = acc;
+#pragma unroll
+          for (int dd = 1; dd < 64; dd <<= 1) {
+            const uint32_t y = __shfl_up(x, dd, 64);
+            if (lane >= dd) x += y;
+          }
+          if (lane == 63) s_wsum[wave] = x;
+          __syncthreads();
+          uint32_t base = 0;
+          for (int w = 0; w < wave; ++w) base += s_wsum[w];
+          __syncthreads();
+          s_start[tid] = base + x - acc;
+        }
+        __syncthreads();
+        for (int c0 = 0; c0 < n; c0 += kTileSortCap) {
+          const int cn = min(kTileSortCap, n - c0);
+#pragma unroll
+          for (int r = 0; r < kTileSortRows; ++r) {
+            const int e = wave * (64 * kTileSortRows) + r * 64 + lane;
+            v[r] = e < cn ? vs[rg.x + c0 + e] : 0u;
+            k[r] = e < cn ? (pass == 0 ? __float_as_uint(splats[v[r]].w0.z) : ks[rg.x + c0 + e]) : 0xFFFFFFFFu;
+          }
+          for (int w = 0; w < kTileSortWaves; ++w) wcnt[w][tid] = 0u;
+          __syncthreads();
+          tile_sort_rank(k, cn, shift, off, wcnt, wave, lane);
+          __syncthreads();
+          uint32_t acc = 0;
+          for (int w = 0; w < kTileSortWaves; ++w) {
+            const uint32_t c = wcnt[w][tid];
+            wcnt[w][tid] = acc;
+            acc += c;
+          }
+          __syncthreads();
+#pragma unroll
+          for (int r = 0; r < kTileSortRows; ++r) {
+            if (off[r] == 0xFFFFFFFFu) continue;
+            const uint32_t d = (k[r] >> shift) & 255u;
+            const uint32_t pos = s_start[d] + wcnt[wave][d] + off[r];
+            if (pos < (uint32_t)n) {   // always, when the counts are right; never outside the tile's range
+              kd[rg.x + pos] = k[r];
+              vd[rg.x + pos] = v[r];
+            }
+          }
+          __syncthreads();
+          s_start[tid] += acc;          // this chunk's entries of each digit precede the next chunk's
+          __syncthreads();
+        }
+      }
+      // four passes end in (keys, vals); the keys held depth bits: restore
+      // the tile key
+      for (int e = tid; e < n; e += kTileSortThreads) keys[rg.x + e] = (uint32_t)tile;
+    }
+    __syncthreads();
+  }
+}
+
 __global__ void clear_kernel(ClearList L) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -848,6 +1056,14 @@ void launch_tile_ranges(const uint32_t* keys, const uint32_t* n_dev, int64_t cou
   tile_ranges_kernel<<<grid_cap(count, 256), 256, 0, st>>>(keys, n_dev, count, ranges, num_tiles);
 }
 
+
+void launch_tile_depth_sort(const uint2* ranges, int64_t num_tiles, const Splat* splats, uint32_t* keys,
+                            uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, hipStream_t st) {
+  if (num_tiles == 0) return;
+  const unsigned grid = (unsigned)(num_tiles < 65536 ? num_tiles : 65536);
+  tile_depth_sort_kernel<<<grid, kTileSortThreads, 0, st>>>(ranges, num_tiles, splats, keys, vals, keys_alt,
+                                                             vals_alt);
+}
 
 void launch_tile_order(const uint2* ranges, int64_t num_tiles, uint32_t* order, hipStream_t st) {
   if (num_tiles == 0) return;

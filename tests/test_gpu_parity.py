@@ -87,6 +87,41 @@ def test_tile_list_bit_exact(gpu, orc, name, tile):
     assert np.array_equal(g_gpu, g_ref)
 
 
+@pytest.mark.parametrize("depth_sort", [1, 2])
+@pytest.mark.parametrize("big", [False, True])
+def test_tile_list_depth_sort_modes(gpu, orc, depth_sort, big):
+    """Both depth orders (per tile after binning; once over all splats before
+    binning) against the oracle's list, bit-exact. big: 5000 Gaussians large
+    enough to cover every tile of a 40x24 view, so every list is longer than
+    the 1536 entries a tile sorts in LDS; ten of them share one depth, so the
+    index breaks their tie."""
+    if big:
+        s = scenes.tiny_random(23, n=5000, width=40, height=24)
+        p = s.params.copy()
+        p[3:6] = np.log(0.6)
+        p[0:3, 1:10] = p[0:3, 0:1]
+    else:
+        s = scenes.tiny_random(24, n=300, width=70, height=45)
+        p = s.params
+    R = make(gpu, depth_sort=depth_sort)
+    outs = R.render(to_dev(p), s.sh_degree, s.cameras)
+    torch.cuda.synchronize()
+    t_gpu, g_gpu = R.instances()
+    t_ref, g_ref = orc.tile_list(p, s.sh_degree, s.cameras, 16, 16)
+    say("depth sort", depth_sort, "big", big, "instances", len(t_gpu), "longest list",
+        int(np.bincount(t_ref.astype(np.int64)).max()))
+    if big:
+        assert np.bincount(t_ref.astype(np.int64)).min() > 1536
+    assert len(t_gpu) == len(t_ref)
+    assert np.array_equal(t_gpu, t_ref) and np.array_equal(g_gpu, g_ref)
+    # the other order gives bit-identical images
+    O = make(gpu, depth_sort=3 - depth_sort)
+    other = O.render(to_dev(p), s.sh_degree, s.cameras)
+    torch.cuda.synchronize()
+    for a, b in zip(outs[0], other[0]):
+        assert torch.equal(a, b)
+
+
 def test_tile_list_multiview_bit_exact(gpu, orc):
     s = scenes.tiny_random(4, n=80, width=45, height=37)
     cams = [s.cameras[0], identity_camera(29, 21, 25.0), scenes.look_at_camera([0.3, 0.1, -0.5], [0, 0, 2], 64, 33, 40.0)]
@@ -406,7 +441,8 @@ def test_invalid_arguments(gpu):
     with pytest.raises(_lib.GsrError) as e:
         _lib.gsr_create(tile_w=12, tile_h=12)
     assert e.value.status == -6
-    for kw in (dict(chunk_len=24), dict(chunk_len=-2), dict(chunk_len=64, max_chunks=65), dict(max_chunks=-1)):
+    for kw in (dict(chunk_len=24), dict(chunk_len=-2), dict(chunk_len=64, max_chunks=65), dict(max_chunks=-1),
+               dict(fuse_blend=2), dict(depth_sort=3), dict(depth_sort=-1)):
         with pytest.raises(_lib.GsrError) as e:
             _lib.gsr_create(**kw)
         assert e.value.status == -6, kw
