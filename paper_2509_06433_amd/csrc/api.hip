@@ -209,7 +209,7 @@ int launch_back(gsr_ctx* ctx, Buffers& B, RenderPlan& P, hipStream_t st, const F
   CHECK_LAUNCH(ctx);
   if (per_tile_depth(ctx, P)) {
     StageTimer tm(ctx, GSR_STAGE_TILE_DEPTH, st);
-    launch_tile_depth_sort(as<uint2>(B.ranges), P.ntiles, as<Splat>(B.splats), ik, iv, ika, iva, st);
+    launch_tile_depth_sort(as<uint2>(B.ranges), P.ntiles, as<uint32_t>(B.zkey), ik, iv, ika, iva, st);
   }
   CHECK_LAUNCH(ctx);
   P.inst_keys = ik;

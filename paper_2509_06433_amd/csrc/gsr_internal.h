@@ -174,10 +174,11 @@ void launch_tile_ranges(const uint32_t* keys, const uint32_t* n_dev, int64_t cou
 // longest tiles start first and the tail of a launch holds the short ones.
 void launch_tile_order(const uint2* ranges, int64_t num_tiles, uint32_t* order, hipStream_t st);
 // Sorts each tile's instances (whose splats arrive in index order) by the raw
-// bits of the splat's depth, stably: the list order becomes (tile, z bits,
+// bits of the splat's depth (zkey, per splat, from the projection), stably:
+// the list order becomes (tile, z bits,
 // index). keys/vals: the tile-sorted instances; keys_alt/vals_alt: scratch of
 // the same size (tiles of more than 1536 instances go through it).
-void launch_tile_depth_sort(const uint2* ranges, int64_t num_tiles, const Splat* splats, uint32_t* keys,
+void launch_tile_depth_sort(const uint2* ranges, int64_t num_tiles, const uint32_t* zkey, uint32_t* keys,
                             uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, hipStream_t st);
 
 // Zeroes up to kMaxClear segments of 32-bit words in one launch.

@@ -676,7 +676,8 @@ __global__ void __launch_bounds__(kOrderThreads) tile_order_kernel(const uint2* 
 // Per-tile depth order. The instances of a tile arrive in splat-index order
 // (emission in index order, then a stable sort by tile); a stable LSD radix
 // sort of each tile's list on the raw bits of z (positive floats order like
-// their bits) then gives the order (tile, z bits, index). One workgroup per
+// their bits; zkey[s], as the projection stores them) then gives the order
+// (tile, z bits, index). One workgroup per
 // tile; four 8-bit passes. Every wave ranks rows of 64 keys in list order
 // with ballots (the rank among equal digits in the row, plus the wave's
 // running count of that digit), so the scatter keeps equal digits in list
@@ -719,7 +720,7 @@ __device__ __forceinline__ void tile_sort_rank(const uint32_t* k, int n, int shi
 }
 
 __global__ void __launch_bounds__(kTileSortThreads) tile_depth_sort_kernel(
-    const uint2* __restrict__ ranges, int64_t num_tiles, const Splat* __restrict__ splats,
+    const uint2* __restrict__ ranges, int64_t num_tiles, const uint32_t* __restrict__ zkey,
     uint32_t* __restrict__ keys, uint32_t* __restrict__ vals, uint32_t* __restrict__ keys_alt,
     uint32_t* __restrict__ vals_alt) {
   __shared__ uint32_t s_k[2][kTileSortCap], s_v[2][kTileSortCap];
@@ -738,7 +739,7 @@ __global__ void __launch_bounds__(kTileSortThreads) tile_depth_sort_kernel(
       for (int r = 0; r < kTileSortRows; ++r) {
         const int e = wave * (64 * kTileSortRows) + r * 64 + lane;
         v[r] = e < n ? vals[rg.x + e] : 0u;
-        k[r] = e < n ? __float_as_uint(splats[v[r]].w0.z) : 0xFFFFFFFFu;
+        k[r] = e < n ? zkey[v[r]] : 0xFFFFFFFFu;
       }
       for (int pass = 0; pass < 4; ++pass) {
         const int shift = 8 * pass;
@@ -811,7 +812,7 @@ __global__ void __launch_bounds__(kTileSortThreads) tile_depth_sort_kernel(
 #pragma unroll
           for (int r = 0; r < kTileSortRows; ++r) {
             const int e = wave * (64 * kTileSortRows) + r * 64 + lane;
-            k[r] = e < cn ? (pass == 0 ? __float_as_uint(splats[vs[rg.x + c0 + e]].w0.z) : ks[rg.x + c0 + e])
+            k[r] = e < cn ? (pass == 0 ? zkey[vs[rg.x + c0 + e]] : ks[rg.x + c0 + e])
                           : 0xFFFFFFFFu;
           }
           for (int w = 0; w < kTileSortWaves; ++w) wcnt[w][tid] = 0u;
@@ -845,7 +846,7 @@ __global__ void __launch_bounds__(kTileSortThreads) tile_depth_sort_kernel(
           for (int r = 0; r < kTileSortRows; ++r) {
             const int e = wave * (64 * kTileSortRows) + r * 64 + lane;
             v[r] = e < cn ? vs[rg.x + c0 + e] : 0u;
-            k[r] = e < cn ? (pass == 0 ? __float_as_uint(splats[v[r]].w0.z) : ks[rg.x + c0 + e]) : 0xFFFFFFFFu;
+            k[r] = e < cn ? (pass == 0 ? zkey[v[r]] : ks[rg.x + c0 + e]) : 0xFFFFFFFFu;
           }
           for (int w = 0; w < kTileSortWaves; ++w) wcnt[w][tid] = 0u;
           __syncthreads();
@@ -1057,11 +1058,11 @@ void launch_tile_ranges(const uint32_t* keys, const uint32_t* n_dev, int64_t cou
 }
 
 
-void launch_tile_depth_sort(const uint2* ranges, int64_t num_tiles, const Splat* splats, uint32_t* keys,
+void launch_tile_depth_sort(const uint2* ranges, int64_t num_tiles, const uint32_t* zkey, uint32_t* keys,
                             uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, hipStream_t st) {
   if (num_tiles == 0) return;
   const unsigned grid = (unsigned)(num_tiles < 65536 ? num_tiles : 65536);
-  tile_depth_sort_kernel<<<grid, kTileSortThreads, 0, st>>>(ranges, num_tiles, splats, keys, vals, keys_alt,
+  tile_depth_sort_kernel<<<grid, kTileSortThreads, 0, st>>>(ranges, num_tiles, zkey, keys, vals, keys_alt,
                                                              vals_alt);
 }
 
