@@ -88,18 +88,33 @@ def test_tile_list_bit_exact(gpu, orc, name, tile):
 
 
 @pytest.mark.parametrize("depth_sort", [1, 2])
-@pytest.mark.parametrize("big", [False, True])
+@pytest.mark.parametrize("big", ["none", "all", "mixed"])
 def test_tile_list_depth_sort_modes(gpu, orc, depth_sort, big):
     """Both depth orders (per tile after binning; once over all splats before
-    binning) against the oracle's list, bit-exact. big: 5000 Gaussians large
+    binning) against the oracle's list, bit-exact. all: 5000 Gaussians large
     enough to cover every tile of a 40x24 view, so every list is longer than
     the 1536 entries a tile sorts in LDS; ten of them share one depth, so the
-    index breaks their tie."""
-    if big:
+    index breaks their tie. mixed: on a 96x32 view 2000 Gaussians crowd the
+    four left tiles (over 2000 entries each) while 2000 small ones spread over
+    the rest (under 700), so both paths meet in one launch."""
+    if big == "all":
         s = scenes.tiny_random(23, n=5000, width=40, height=24)
         p = s.params.copy()
         p[3:6] = np.log(0.6)
         p[0:3, 1:10] = p[0:3, 0:1]
+    elif big == "mixed":
+        s = scenes.tiny_random(25, n=4000, width=96, height=32)
+        p = s.params.copy()
+        cam = s.cameras[0]
+        rng = np.random.default_rng(scenes.SEED_BASE + 25)
+        k = 2000
+        z = 2.0 + rng.uniform(-0.2, 0.2, k)
+        u, v = 16 + rng.uniform(-4, 4, k), 16 + rng.uniform(-4, 4, k)
+        p[0, :k] = (u - cam.cx) / cam.fx * z
+        p[1, :k] = (v - cam.cy) / cam.fy * z
+        p[2, :k] = z
+        p[3:6, :k] = np.log(0.09)
+        p[3:6, k:] = np.log(0.03)
     else:
         s = scenes.tiny_random(24, n=300, width=70, height=45)
         p = s.params
@@ -108,10 +123,13 @@ def test_tile_list_depth_sort_modes(gpu, orc, depth_sort, big):
     torch.cuda.synchronize()
     t_gpu, g_gpu = R.instances()
     t_ref, g_ref = orc.tile_list(p, s.sh_degree, s.cameras, 16, 16)
-    say("depth sort", depth_sort, "big", big, "instances", len(t_gpu), "longest list",
-        int(np.bincount(t_ref.astype(np.int64)).max()))
-    if big:
-        assert np.bincount(t_ref.astype(np.int64)).min() > 1536
+    say("depth sort", depth_sort, "big", big, "instances", len(t_gpu), "lists",
+        np.bincount(t_ref.astype(np.int64)).tolist())
+    counts = np.bincount(t_ref.astype(np.int64))
+    if big == "all":
+        assert counts.min() > 1536
+    elif big == "mixed":
+        assert counts.max() > 1536 and counts[counts > 0].min() <= 1536
     assert len(t_gpu) == len(t_ref)
     assert np.array_equal(t_gpu, t_ref) and np.array_equal(g_gpu, g_ref)
     # the other order gives bit-identical images
