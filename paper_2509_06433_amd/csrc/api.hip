@@ -117,23 +117,30 @@ int launch_front(gsr_ctx* ctx, Buffers& B, RenderPlan& P, const float* params, h
   uint32_t* sva = as<uint32_t>(B.svals_alt);
   uint32_t* cscan = as<uint32_t>(B.partials);
   uint32_t* oscan = cscan + scan_partial_elems(P.total);
-  {
-    // only the visible splats (count in totals[3]) are binned; with the
-    // global depth sort they are sorted by depth first, else they are binned
-    // in index order and each tile's list is sorted after binning
-    StageTimer tm(ctx, GSR_STAGE_DEPTH_SORT, st);
-    launch_compact_visible(as<uint32_t>(B.ntiles), zk, P.total, zka, sva, totals + 3, cscan, totals + 1, false, st);
-    if (global_depth)
+  // only the visible splats (count in totals[3]) are binned. With the global
+  // depth sort they are compacted, sorted by depth and then scanned for their
+  // instance offsets; else they are binned in index order (each tile's list
+  // is sorted after binning), and one pass compacts them and forms the
+  // offsets. With the instance capacity fixed ahead (the captured iteration)
+  // the offsets scan also writes the emission plan.
+  P.plan_ready = P.capacity > 0;
+  uint32_t* plan = P.plan_ready ? as<uint32_t>(B.block_rank) : nullptr;
+  if (global_depth) {
+    {
+      StageTimer tm(ctx, GSR_STAGE_DEPTH_SORT, st);
+      launch_compact_visible(as<uint32_t>(B.ntiles), zk, P.total, zka, sva, totals + 3, cscan, totals + 1, false, st);
       radix_sort_pairs(zka, sva, zk, sv, P.total, totals + 3, 32, as<uint32_t>(B.hist), totals + 1, false, true, st);
-  }
-  CHECK_LAUNCH(ctx);
-  {
+    }
+    CHECK_LAUNCH(ctx);
+    {
+      StageTimer tm(ctx, GSR_STAGE_SCAN, st);
+      scan_gather_exclusive(as<uint32_t>(B.ntiles), sva, as<uint32_t>(B.offsets), P.total, totals + 3, totals, oscan,
+                            totals + 1, false, st, plan, P.capacity);
+    }
+  } else {
     StageTimer tm(ctx, GSR_STAGE_SCAN, st);
-    // with the instance capacity fixed ahead (the captured iteration) the
-    // scan also writes the emission plan
-    P.plan_ready = P.capacity > 0;
-    scan_gather_exclusive(as<uint32_t>(B.ntiles), sva, as<uint32_t>(B.offsets), P.total, totals + 3, totals, oscan,
-                          totals + 1, false, st, P.plan_ready ? as<uint32_t>(B.block_rank) : nullptr, P.capacity);
+    launch_compact_scan(as<uint32_t>(B.ntiles), P.total, sva, as<uint32_t>(B.offsets), totals + 3, totals, cscan,
+                        totals + 1, plan, P.capacity, st);
   }
   CHECK_LAUNCH(ctx);
   sv = sva;

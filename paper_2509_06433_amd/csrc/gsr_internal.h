@@ -146,6 +146,16 @@ int64_t scan_partial_elems(int64_t n);
 void scan_gather_exclusive(const uint32_t* in, const uint32_t* idx, uint32_t* out, int64_t n,
                            const uint32_t* n_dev, uint32_t* total_dev, uint32_t* scratch, uint32_t* err, bool clear,
                            hipStream_t st, uint32_t* block_rank = nullptr, int64_t capacity = 0);
+// Order-preserving compaction of the visible splats (nonzero tile count) and
+// their instance offsets in one pass over the n splats in index order:
+// vals[r] = index of the r-th visible splat, offsets[r] = the tile counts of
+// the visible splats before it, *count_out = their number, *total_out = the
+// instance total; with block_rank the emission plan for `capacity` slots, as
+// scan_gather_exclusive writes it. Needs n < 2^30. The scratch (zeroed by
+// the caller) is that of scan_gather_exclusive.
+void launch_compact_scan(const uint32_t* ntiles, int64_t n, uint32_t* vals, uint32_t* offsets, uint32_t* count_out,
+                         uint32_t* total_out, uint32_t* scratch, uint32_t* err, uint32_t* block_rank, int64_t capacity,
+                         hipStream_t st);
 // Order-preserving compaction of the n splats with a nonzero tile count:
 // out_keys/out_vals[r] = key and index of the r-th one, *count_out = their
 // number. Same scratch size and semantics as scan_gather_exclusive.

@@ -180,6 +180,114 @@ __global__ void __launch_bounds__(kScanThreads) scan_lookback_kernel(
   }
 }
 
+// Compaction of the visible splats and their instance offsets in one
+// single-pass scan over all splats in index order (the order the per-tile
+// depth path bins them in): vals[r] = index of the r-th splat with a nonzero
+// tile count, offsets[r] = the tile counts of the visible splats before it,
+// *count_out = their number, *total_out = the instance total; with block_rank
+// also the emission plan (as scan_lookback_kernel writes it). Status word per
+// workgroup: flag (1 = chunk totals, 2 = inclusive) in bits 62-63, the
+// visible count in bits 32-61 and the instance count in bits 0-31; sums of
+// such words stay exact while there are fewer than 2^30 splats and 2^32
+// instances. Look-back and bounded wait as in scan_lookback_kernel.
+constexpr unsigned long long kCsAgg = 1ull << 62;
+constexpr unsigned long long kCsInc = 2ull << 62;
+constexpr unsigned long long kCsPayload = (1ull << 62) - 1ull;
+
+__global__ void __launch_bounds__(kScanThreads) compact_scan_kernel(
+    const uint32_t* __restrict__ ntiles, int64_t n, uint32_t* __restrict__ vals, uint32_t* __restrict__ offsets,
+    uint32_t* __restrict__ count_out, uint32_t* __restrict__ total_out, unsigned long long* __restrict__ status,
+    uint32_t* __restrict__ err, uint32_t* __restrict__ block_rank, int64_t plan_blocks) {
+  __shared__ uint32_t tile[kScanChunk];
+  __shared__ unsigned long long s_excl;
+  const uint32_t bid = blockIdx.x;
+  const int64_t base = (int64_t)bid * kScanChunk;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int local = k * kScanThreads + threadIdx.x;
+    const int64_t j = base + local;
+    tile[local] = j < n ? ntiles[j] : 0u;
+  }
+  __syncthreads();
+  uint32_t v[kScanItems];
+  uint32_t sc = 0, st = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    v[k] = tile[threadIdx.x * kScanItems + k];
+    sc += v[k] != 0u ? 1u : 0u;
+    st += v[k];
+  }
+  uint32_t totc, tott;
+  const uint32_t exc = block_excl_scan(sc, &totc);
+  const uint32_t ext = block_excl_scan(st, &tott);
+  const unsigned long long mine = ((unsigned long long)totc << 32) | tott;
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    if (lane == 0)
+      __hip_atomic_store(status + bid, (bid == 0 ? kCsInc : kCsAgg) | mine, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    unsigned long long excl = 0;
+    if (bid > 0) {
+      int64_t p = (int64_t)bid - 1;          // nearest predecessor not yet summed
+      uint32_t spins = 0;
+      while (true) {
+        const int64_t q = p - lane;
+        const unsigned long long w =
+            q >= 0 ? __hip_atomic_load(status + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : kCsInc;
+        const uint32_t flag = (uint32_t)(w >> 62);
+        const uint64_t waiting = __ballot(flag == 0u);
+        const uint64_t inc = __ballot(flag == 2u);
+        const int first_inc = inc ? __ffsll((unsigned long long)inc) - 1 : 64;
+        const uint64_t need = first_inc >= 63 ? ~0ull : ((2ull << first_inc) - 1ull);
+        if (waiting & need) {
+          if (++spins > kSpinLimit) {
+            if (lane == 0) atomicOr(err, 1u);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+          continue;
+        }
+        const unsigned long long val = (lane <= first_inc) ? (w & kCsPayload) : 0ull;
+        uint32_t lo = (uint32_t)val, hi = (uint32_t)(val >> 32);
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) {
+          lo += __shfl_xor(lo, m, 64);
+          hi += __shfl_xor(hi, m, 64);
+        }
+        excl += ((unsigned long long)hi << 32) + lo;
+        if (first_inc < 64) break;
+        p -= 64;
+      }
+      if (lane == 0)
+        __hip_atomic_store(status + bid, kCsInc | (excl + mine), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (lane == 0) {
+      s_excl = excl;
+      if (bid == gridDim.x - 1) {
+        *count_out = (uint32_t)((excl + mine) >> 32);
+        *total_out = (uint32_t)(excl + mine);
+      }
+    }
+  }
+  __syncthreads();
+  uint32_t rc = (uint32_t)(s_excl >> 32) + exc, rt = (uint32_t)s_excl + ext;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    if (v[k]) {
+      vals[rc] = (uint32_t)(base + threadIdx.x * kScanItems + k);
+      offsets[rc] = rt;
+      // the emission plan: rank rc's run [rt, rt + v) holds the first position
+      // of every output block starting in it
+      if (block_rank)
+        for (int64_t b = ((int64_t)rt + kEmitBlock - 1) / kEmitBlock; b < plan_blocks && b * kEmitBlock < (int64_t)rt + v[k];
+             ++b)
+          block_rank[b] = rc;
+      ++rc;
+    }
+    rt += v[k];
+  }
+}
+
 // Order-preserving compaction of the visible splats (nonzero tile count):
 // out_keys[r], out_vals[r] = key and index of the r-th visible splat; the
 // count -> *count_out. Single pass with the same look-back as the scan.
@@ -973,6 +1081,20 @@ void scan_gather_exclusive(const uint32_t* in, const uint32_t* idx, uint32_t* ou
   unsigned long long* status = reinterpret_cast<unsigned long long*>(scratch);
   scan_lookback_kernel<<<nb, kScanThreads, 0, st>>>(in, idx, n_dev, n, out, total_dev, status, err, block_rank,
                                                     (capacity + kEmitBlock - 1) / kEmitBlock);
+}
+
+void launch_compact_scan(const uint32_t* ntiles, int64_t n, uint32_t* vals, uint32_t* offsets, uint32_t* count_out,
+                         uint32_t* total_out, uint32_t* scratch, uint32_t* err, uint32_t* block_rank, int64_t capacity,
+                         hipStream_t st) {
+  if (n == 0) {
+    fill_u32_kernel<<<1, 64, 0, st>>>(count_out, 0u, 1);
+    fill_u32_kernel<<<1, 64, 0, st>>>(total_out, 0u, 1);
+    return;
+  }
+  const int nb = blocks_for(n, kScanChunk);
+  unsigned long long* status = reinterpret_cast<unsigned long long*>(scratch);
+  compact_scan_kernel<<<nb, kScanThreads, 0, st>>>(ntiles, n, vals, offsets, count_out, total_out, status, err,
+                                                   block_rank, (capacity + kEmitBlock - 1) / kEmitBlock);
 }
 
 void launch_compact_visible(const uint32_t* ntiles, const uint32_t* keys, int64_t n, uint32_t* out_keys,
