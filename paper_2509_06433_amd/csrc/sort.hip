@@ -65,9 +65,6 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* total)
   return before + incl - x;
 }
 
-__device__ __forceinline__ uint32_t load_gather(const uint32_t* in, const uint32_t* idx, int64_t j) {
-  return idx ? in[idx[j]] : in[j];
-}
 
 // Single-pass exclusive scan with decoupled look-back. Workgroups publish
 // their chunk total, and the first wave looks back over the published totals
@@ -98,11 +95,31 @@ __global__ void __launch_bounds__(kScanThreads) scan_lookback_kernel(
   // that has looks at them
   if (base >= n && bid > 0) return;
   const bool last_block = base + kScanChunk >= n;
+  // loads at in-bounds addresses for every lane (element 0 past the end),
+  // all issued before the first wait
+  uint32_t ld[kScanItems];
+  if (idx) {
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+      const int64_t j = base + k * kScanThreads + threadIdx.x;
+      ld[k] = idx[j < n ? j : 0];
+    }
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+      const int64_t j = base + k * kScanThreads + threadIdx.x;
+      ld[k] = in[j < n ? ld[k] : 0u];
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+      const int64_t j = base + k * kScanThreads + threadIdx.x;
+      ld[k] = in[j < n ? j : 0];
+    }
+  }
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     const int local = k * kScanThreads + threadIdx.x;
-    const int64_t j = base + local;
-    tile[local] = j < n ? load_gather(in, idx, j) : 0u;
+    tile[local] = base + local < n ? ld[k] : 0u;
   }
   __syncthreads();
   uint32_t v[kScanItems];
@@ -202,11 +219,18 @@ __global__ void __launch_bounds__(kScanThreads) compact_scan_kernel(
   __shared__ unsigned long long s_excl;
   const uint32_t bid = blockIdx.x;
   const int64_t base = (int64_t)bid * kScanChunk;
+  // loads at in-bounds addresses for every lane, all issued before the
+  // first wait
+  uint32_t ld[kScanItems];
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t j = base + k * kScanThreads + threadIdx.x;
+    ld[k] = ntiles[j < n ? j : 0];
+  }
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     const int local = k * kScanThreads + threadIdx.x;
-    const int64_t j = base + local;
-    tile[local] = j < n ? ntiles[j] : 0u;
+    tile[local] = base + local < n ? ld[k] : 0u;
   }
   __syncthreads();
   uint32_t v[kScanItems];
@@ -299,11 +323,16 @@ __global__ void __launch_bounds__(kScanThreads) compact_visible_kernel(
   __shared__ uint32_t flags[kScanChunk];
   const uint32_t bid = blockIdx.x;
   const int64_t base = (int64_t)bid * kScanChunk;
+  uint32_t ld[kScanItems];
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t j = base + k * kScanThreads + threadIdx.x;
+    ld[k] = ntiles[j < n ? j : 0];
+  }
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     const int local = k * kScanThreads + threadIdx.x;
-    const int64_t j = base + local;
-    flags[local] = (j < n && ntiles[j] != 0u) ? 1u : 0u;
+    flags[local] = (base + local < n && ld[k] != 0u) ? 1u : 0u;
   }
   __syncthreads();
   uint32_t v[kScanItems];
@@ -461,13 +490,22 @@ __global__ void __launch_bounds__(kSortThreads) onesweep_pass_kernel(
   const int64_t base = (int64_t)bid * CHUNK + (int64_t)wave * WCHUNK;
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   uint32_t k_reg[ITEMS], v_reg[ITEMS], off[ITEMS];
+  // every lane loads from an address in bounds (element 0 past the end), so
+  // all of the workgroup's loads are in flight before the first wait; a
+  // guarded load per item would cost one memory round trip per item
+#pragma unroll
+  for (int r = 0; r < ITEMS; ++r) {
+    const int64_t j = base + r * 64 + lane;
+    const int64_t jc = j < n ? j : 0;
+    k_reg[r] = keys[jc];
+    v_reg[r] = vals[jc];
+  }
 #pragma unroll
   for (int r = 0; r < ITEMS; ++r) {
     const int64_t j = base + r * 64 + lane;
     const bool valid = j < n;
-    const uint32_t key = valid ? keys[j] : 0u;
+    const uint32_t key = valid ? k_reg[r] : 0u;
     k_reg[r] = key;
-    v_reg[r] = valid ? vals[j] : 0u;
     const uint32_t d = (key >> shift) & (R - 1);
     uint64_t mask = __ballot(valid);
 #pragma unroll
@@ -842,12 +880,24 @@ __global__ void __launch_bounds__(kTileSortThreads) tile_depth_sort_kernel(
     if (n < 2) continue;
     uint32_t k[kTileSortRows], v[kTileSortRows], off[kTileSortRows];
     if (n <= kTileSortCap) {
-      // in LDS: load, then four passes between the two buffers
+      // in LDS: load, then four passes between the two buffers. Lanes past
+      // the list read its first entry (a listed splat, so its depth key is
+      // in bounds too): every row's id and key loads are in flight at once
+      // rather than one guarded round trip after another
 #pragma unroll
       for (int r = 0; r < kTileSortRows; ++r) {
         const int e = wave * (64 * kTileSortRows) + r * 64 + lane;
-        v[r] = e < n ? vals[rg.x + e] : 0u;
-        k[r] = e < n ? zkey[v[r]] : 0xFFFFFFFFu;
+        v[r] = vals[rg.x + (e < n ? e : 0)];
+      }
+#pragma unroll
+      for (int r = 0; r < kTileSortRows; ++r) k[r] = zkey[v[r]];
+#pragma unroll
+      for (int r = 0; r < kTileSortRows; ++r) {
+        const int e = wave * (64 * kTileSortRows) + r * 64 + lane;
+        if (e >= n) {
+          v[r] = 0u;
+          k[r] = 0xFFFFFFFFu;
+        }
       }
       for (int pass = 0; pass < 4; ++pass) {
         const int shift = 8 * pass;
@@ -917,12 +967,21 @@ __global__ void __launch_bounds__(kTileSortThreads) tile_depth_sort_kernel(
         uint32_t total = 0;
         for (int c0 = 0; c0 < n; c0 += kTileSortCap) {
           const int cn = min(kTileSortCap, n - c0);
+          // loads at in-bounds positions for every lane (the chunk's first
+          // entry past its end), masked afterwards
 #pragma unroll
           for (int r = 0; r < kTileSortRows; ++r) {
             const int e = wave * (64 * kTileSortRows) + r * 64 + lane;
-            k[r] = e < cn ? (pass == 0 ? zkey[vs[rg.x + c0 + e]] : ks[rg.x + c0 + e])
-                          : 0xFFFFFFFFu;
+            const uint32_t at = rg.x + c0 + (e < cn ? e : 0);
+            k[r] = pass == 0 ? vs[at] : ks[at];
           }
+          if (pass == 0) {
+#pragma unroll
+            for (int r = 0; r < kTileSortRows; ++r) k[r] = zkey[k[r]];
+          }
+#pragma unroll
+          for (int r = 0; r < kTileSortRows; ++r)
+            if (wave * (64 * kTileSortRows) + r * 64 + lane >= cn) k[r] = 0xFFFFFFFFu;
           for (int w = 0; w < kTileSortWaves; ++w) wcnt[w][tid] = 0u;
           __syncthreads();
           tile_sort_rank(k, cn, shift, off, wcnt, wave, lane);
@@ -953,8 +1012,20 @@ __global__ void __launch_bounds__(kTileSortThreads) tile_depth_sort_kernel(
 #pragma unroll
           for (int r = 0; r < kTileSortRows; ++r) {
             const int e = wave * (64 * kTileSortRows) + r * 64 + lane;
-            v[r] = e < cn ? vs[rg.x + c0 + e] : 0u;
-            k[r] = e < cn ? (pass == 0 ? zkey[v[r]] : ks[rg.x + c0 + e]) : 0xFFFFFFFFu;
+            const uint32_t at = rg.x + c0 + (e < cn ? e : 0);
+            v[r] = vs[at];
+            if (pass != 0) k[r] = ks[at];
+          }
+          if (pass == 0) {
+#pragma unroll
+            for (int r = 0; r < kTileSortRows; ++r) k[r] = zkey[v[r]];
+          }
+#pragma unroll
+          for (int r = 0; r < kTileSortRows; ++r) {
+            if (wave * (64 * kTileSortRows) + r * 64 + lane >= cn) {
+              v[r] = 0u;
+              k[r] = 0xFFFFFFFFu;
+            }
           }
           for (int w = 0; w < kTileSortWaves; ++w) wcnt[w][tid] = 0u;
           __syncthreads();
