@@ -73,9 +73,13 @@ struct IterCounters {
 // counts the replay (as skipped when a flag is set, and then not as an Adam
 // step), keeps the instance counts, and copies the counters to the host.
 __device__ inline void count_iteration(const IterCounters& c) {
+  // the counters are read once, updated in registers and written to the
+  // device copy and the host mirror: no load waits behind a store
+  uint32_t s[kStatWords];
+#pragma unroll
+  for (int k = 0; k < kStatWords; ++k) s[k] = c.stats[k];
   const uint32_t count = c.totals[0];
   const bool err = c.totals[1] != 0u, over = c.totals[2] != 0u;
-  uint32_t* s = c.stats;
   if (err || over) {
     s[kStatSkipped] += 1u;
     if (err) s[kStatErrors] += 1u;
@@ -85,7 +89,10 @@ __device__ inline void count_iteration(const IterCounters& c) {
   }
   s[kStatMaxInstances] = max(s[kStatMaxInstances], count);
   s[kStatLastInstances] = count;
+#pragma unroll
+  for (int k = 0; k < kStatWords; ++k) c.stats[k] = s[k];
   if (c.host) {
+#pragma unroll
     for (int k = 0; k < kStatWords; ++k) c.host[k] = s[k];
     __threadfence_system();
   }
@@ -110,13 +117,11 @@ void launch_export_splats(const float* params, int64_t n, int64_t stride, const 
 // Hundreds of workgroups adding into the same few hundred words serialise on
 // those addresses (measured: 22 us of a 41 us emission at 1470 workgroups).
 constexpr int kHistCopies = 16;
-// Scratch (uint32 elements) a radix sort of n keys needs.
 // Scratch (u32 words) of radix_sort_pairs for n elements sorted on `bits` bits.
 int64_t radix_scratch_elems(int64_t n, int bits);
 // Stable LSD radix sort of (keys, vals) on the low `bits` bits of the keys,
-// 8 or 11 bits per pass (whichever takes fewer passes), ping-ponging between
-// the buffers; on return keys/vals point
-// at the sorted data and keys_alt/vals_alt at the other pair. The element
+// 8 bits per pass, ping-ponging between the buffers; on return keys/vals
+// point at the sorted data and keys_alt/vals_alt at the other pair. The element
 // count is *n_dev when n_dev is not null (n is then the capacity the grid is
 // sized for), else n. *err becomes nonzero if a look-back wait hit its bound
 // (the result is then invalid). clear = false: the caller has zeroed the

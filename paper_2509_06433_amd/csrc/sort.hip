@@ -780,10 +780,13 @@ __global__ void tile_ranges_kernel(const uint32_t* __restrict__ keys, const uint
                                    int64_t n_host, uint2* __restrict__ ranges, int64_t num_tiles) {
   const int64_t count = n_dev ? min((int64_t)*n_dev, n_host) : n_host;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
+    // the key and both neighbours loaded together (clamped at the ends)
     const uint32_t k = keys[i];
+    const uint32_t kp = keys[i > 0 ? i - 1 : 0];
+    const uint32_t kn = keys[i + 1 < count ? i + 1 : i];
     if (k >= num_tiles) continue;
-    if (i == 0 || keys[i - 1] != k) ranges[k].x = (uint32_t)i;
-    if (i == count - 1 || keys[i + 1] != k) ranges[k].y = (uint32_t)(i + 1);
+    if (i == 0 || kp != k) ranges[k].x = (uint32_t)i;
+    if (i == count - 1 || kn != k) ranges[k].y = (uint32_t)(i + 1);
   }
 }
 
