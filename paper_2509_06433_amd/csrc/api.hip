@@ -99,9 +99,11 @@ void back_clears(Buffers& B, const RenderPlan& P, ClearList& L) {
 int launch_front(gsr_ctx* ctx, Buffers& B, RenderPlan& P, const float* params, hipStream_t st) {
   const int nv = P.nv;
   uint32_t* totals = as<uint32_t>(B.total);
-  // with the global depth sort the projection also forms its digit histograms
   const bool global_depth = !per_tile_depth(ctx, P);
   int zrb = 8, zpasses = 0;
+  // the global depth sort keeps look-back passes at every size, with its
+  // histograms formed by the projection (reduce-then-scan passes measured
+  // slower there: 16 views of 2M Gaussians, 245 -> 353 us)
   uint32_t* zhist =
       global_depth && P.total > 1 ? radix_hist(as<uint32_t>(B.hist), P.total, 32, &zrb, &zpasses) : nullptr;
   {
@@ -192,7 +194,10 @@ int launch_back(gsr_ctx* ctx, Buffers& B, RenderPlan& P, hipStream_t st, const F
   uint32_t* ika = as<uint32_t>(B.ikeys_alt);
   uint32_t* iva = as<uint32_t>(B.ivals_alt);
   const int tbits = bits_for(P.ntiles - 1);
-  const bool hist_in_emit = P.capacity > 1 && tbits > 0 && emit_histogram_fits(tbits);
+  // large sorts take reduce-then-scan passes; small ones the look-back
+  // passes, whose global histogram the emission accumulates
+  const bool scanned = radix_prefers_scan(P.capacity);
+  const bool hist_in_emit = !scanned && P.capacity > 1 && tbits > 0 && emit_histogram_fits(tbits);
   int trb = 8, tpasses = 0;
   uint32_t* thist = hist_in_emit ? radix_hist(as<uint32_t>(B.hist2), P.capacity, tbits, &trb, &tpasses) : nullptr;
   {
@@ -204,8 +209,11 @@ int launch_back(gsr_ctx* ctx, Buffers& B, RenderPlan& P, hipStream_t st, const F
   CHECK_LAUNCH(ctx);
   {
     StageTimer tm(ctx, GSR_STAGE_TILE_SORT, st);
-    radix_sort_pairs(ik, iv, ika, iva, P.capacity, totals, tbits, as<uint32_t>(B.hist2), totals + 1, false,
-                     hist_in_emit, st);
+    if (scanned)
+      radix_sort_pairs_scanned(ik, iv, ika, iva, P.capacity, totals, tbits, as<uint32_t>(B.hist2), totals + 1, st);
+    else
+      radix_sort_pairs(ik, iv, ika, iva, P.capacity, totals, tbits, as<uint32_t>(B.hist2), totals + 1, false,
+                       hist_in_emit, st);
   }
   CHECK_LAUNCH(ctx);
   {

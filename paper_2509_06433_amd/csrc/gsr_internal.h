@@ -131,6 +131,14 @@ int64_t radix_scratch_elems(int64_t n, int bits);
 void radix_sort_pairs(uint32_t*& keys, uint32_t*& vals, uint32_t*& keys_alt, uint32_t*& vals_alt, int64_t n,
                       const uint32_t* n_dev, int bits, uint32_t* scratch, uint32_t* err, bool clear, bool hist_ready,
                       hipStream_t st);
+// The same sort with reduce-then-scan passes: per pass, digit counts per
+// workgroup, one exclusive scan over them, then the ranking and scatter. No
+// global histogram and no serial look-back between the workgroups.
+void radix_sort_pairs_scanned(uint32_t*& keys, uint32_t*& vals, uint32_t*& keys_alt, uint32_t*& vals_alt,
+                              int64_t n, const uint32_t* n_dev, int bits, uint32_t* scratch, uint32_t* err,
+                              hipStream_t st);
+// Whether a sort of n keys is faster with reduce-then-scan passes.
+bool radix_prefers_scan(int64_t n);
 // The digit histograms ([passes][2^rb]) inside a sort scratch for n elements
 // sorted on `bits` bits; *rb and *passes receive the digit width and count.
 uint32_t* radix_hist(uint32_t* scratch, int64_t n, int bits, int* rb, int* passes);

@@ -455,7 +455,51 @@ __global__ void __launch_bounds__(kSortThreads) global_hist_kernel(const uint32_
     if (h[e]) atomicAdd(&dst[e], h[e]);
 }
 
-template <int RB, int ITEMS>
+// Counting half of a reduce-then-scan digit pass: workgroup b counts the
+// digits of keys [b CHUNK, (b + 1) CHUNK) and stores them digit-major,
+// counts[d * nb + b], so that one exclusive scan over the array gives each
+// (digit, workgroup) run its first output position. Workgroups past the
+// element count store zeros.
+template <int ITEMS>
+__global__ void __launch_bounds__(kSortThreads) digit_count_kernel(const uint32_t* __restrict__ keys,
+                                                                   const uint32_t* __restrict__ n_dev, int64_t n_host,
+                                                                   int shift, uint32_t* __restrict__ counts) {
+  constexpr int R = 256;
+  constexpr int NW = kSortThreads / 64;
+  constexpr int CHUNK = kSortThreads * ITEMS;
+  static_assert(R == kSortThreads, "one digit per thread");
+  __shared__ uint32_t h[NW][R];
+  const int tid = threadIdx.x, wave = tid >> 6;
+  const int64_t n = n_dev ? min((int64_t)*n_dev, n_host) : n_host;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) h[w][tid] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * CHUNK;
+  // all loads in flight before the first wait (in-bounds addresses, element
+  // 0 past the end), then the counts of the valid items
+  uint32_t k[ITEMS];
+#pragma unroll
+  for (int r = 0; r < ITEMS; ++r) {
+    const int64_t j = base + r * kSortThreads + tid;
+    k[r] = keys[j < n ? j : 0];
+  }
+#pragma unroll
+  for (int r = 0; r < ITEMS; ++r)
+    if (base + r * kSortThreads + tid < n) atomicAdd(&h[wave][(k[r] >> shift) & (R - 1)], 1u);
+  __syncthreads();
+  uint32_t c = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) c += h[w][tid];
+  counts[(size_t)tid * gridDim.x + blockIdx.x] = c;
+}
+
+// One digit pass: rank each key within its workgroup, find the output
+// position of the workgroup's run of each digit, scatter. The run starts
+// come either from a decoupled look-back over the workgroups' published
+// digit counts plus the global histogram (SCANNED false: `status` holds the
+// published counts), or, SCANNED true, from the exclusive scan of
+// digit_count_kernel's counts (`status` holds that scan, digit-major).
+template <int RB, int ITEMS, bool SCANNED = false>
 __global__ void __launch_bounds__(kSortThreads) onesweep_pass_kernel(
     const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals, const uint32_t* __restrict__ n_dev,
     int64_t n_host, int shift, const uint32_t* __restrict__ ghist, int ghist_stride, uint32_t* __restrict__ status,
@@ -534,14 +578,15 @@ __global__ void __launch_bounds__(kSortThreads) onesweep_pass_kernel(
       acc += c;
     }
     mine[t] = acc;
-    __hip_atomic_store(status + (size_t)bid * R + d, (bid == 0 ? kFlagInc : kFlagAgg) | acc, __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
+    if (!SCANNED)
+      __hip_atomic_store(status + (size_t)bid * R + d, (bid == 0 ? kFlagInc : kFlagAgg) | acc, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
   }
   // exclusive prefixes over lower workgroups, all owned digits walking together
   uint32_t excl[DPT];
 #pragma unroll
   for (int t = 0; t < DPT; ++t) excl[t] = 0;
-  if (bid > 0 && DPT == 1) {
+  if (!SCANNED && bid > 0 && DPT == 1) {
     // one digit per thread: read kLookChunk predecessors per round trip and
     // take them in order until an inclusive prefix; an entry not yet
     // published stops the round, which is retried from there
@@ -579,7 +624,7 @@ __global__ void __launch_bounds__(kSortThreads) onesweep_pass_kernel(
     }
     __hip_atomic_store(status + (size_t)bid * R + d, kFlagInc | (excl[0] + mine[0]), __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
-  } else if (bid > 0) {
+  } else if (!SCANNED && bid > 0) {
     uint32_t pending = (DPT == 32 ? ~0u : ((1u << DPT) - 1u));
     int64_t p = (int64_t)bid - 1;
     uint32_t spins = 0;
@@ -623,8 +668,10 @@ __global__ void __launch_bounds__(kSortThreads) onesweep_pass_kernel(
       gpre[t] = gs;
       mpre[t] = ms;
       uint32_t h = 0;
+      if (!SCANNED) {
 #pragma unroll
-      for (int c = 0; c < kHistCopies; ++c) h += ghist[(size_t)c * ghist_stride + tid * DPT + t];
+        for (int c = 0; c < kHistCopies; ++c) h += ghist[(size_t)c * ghist_stride + tid * DPT + t];
+      }
       gs += h;
       ms += mine[t];
     }
@@ -653,7 +700,7 @@ __global__ void __launch_bounds__(kSortThreads) onesweep_pass_kernel(
     for (int t = 0; t < DPT; ++t) {
       const int d = tid * DPT + t;
       lstart[d] = my0 + mpre[t];
-      gofs[d] = gx0 + gpre[t] + excl[t] - (my0 + mpre[t]);
+      gofs[d] = (SCANNED ? status[(size_t)d * gridDim.x + bid] : gx0 + gpre[t] + excl[t]) - (my0 + mpre[t]);
     }
   }
   __syncthreads();
@@ -1125,14 +1172,25 @@ int grid_cap(int64_t n, int block) {
 // (measured at 200k keys: 2 and 8 slower than 4; at 1.5M and 12M: 12 faster
 // than 16 by 1-2 %, 8 slower at 12M).
 static int sort_items(int64_t n) { return n <= kSortSmall ? 4 : 12; }
+
 static int64_t sort_chunk(int64_t n) { return (int64_t)kSortThreads * sort_items(n); }
+
+// Reduce-then-scan passes launch three kernels per pass instead of one and
+// need no global histogram. Measured on the tile sort: slower at small
+// sizes (128x96, 2k Gaussians: 8.6 -> 14.1 us), faster above 2^19 keys
+// (1.5M: the same sort and 2 us less emission; 11.8M: 202 -> 189 us;
+// 17.5M: 296 -> 260 us).
+bool radix_prefers_scan(int64_t n) { return n > kSortSmall; }
 
 int64_t radix_scratch_elems(int64_t n, int bits) {
   int rb, passes;
   radix_plan(bits, &rb, &passes);
   const int64_t nb = blocks_for(n, sort_chunk(n));
-  // status words for every pass, the copies of the global histograms
-  return (int64_t)passes * (nb > 0 ? nb : 1) * (1 << rb) + (int64_t)kHistCopies * passes * (1 << rb);
+  // status words for every pass (or the digit counts and their scan), the
+  // copies of the global histograms, the look-back words of the count scans
+  const int64_t words = (int64_t)(nb > 0 ? nb : 1) * (1 << rb);
+  return (int64_t)(passes > 2 ? passes : 2) * words + (int64_t)kHistCopies * passes * (1 << rb) +
+         (int64_t)passes * 2 * blocks_for(words, kScanChunk);
 }
 
 int64_t scan_partial_elems(int64_t n) { return 2 * (int64_t)blocks_for(n > 0 ? n : 1, kScanChunk); }
@@ -1209,6 +1267,40 @@ void radix_sort_pairs(uint32_t*& keys, uint32_t*& vals, uint32_t*& keys_alt, uin
     else
       onesweep_pass_kernel<8, 12><<<nb, kSortThreads, 0, st>>>(keys, vals, n_dev, n, sh, ghist + p * R, gstride, stp,
                                                                err, keys_alt, vals_alt);
+    uint32_t* t = keys; keys = keys_alt; keys_alt = t;
+    t = vals; vals = vals_alt; vals_alt = t;
+  }
+}
+
+void radix_sort_pairs_scanned(uint32_t*& keys, uint32_t*& vals, uint32_t*& keys_alt, uint32_t*& vals_alt,
+                              int64_t n, const uint32_t* n_dev, int bits, uint32_t* scratch, uint32_t* err,
+                              hipStream_t st) {
+  if (n <= 1 || bits <= 0) return;
+  int rb, passes;
+  radix_plan(bits, &rb, &passes);
+  const int R = 1 << rb;
+  const int items = sort_items(n);
+  const int nb = blocks_for(n, sort_chunk(n));
+  const int64_t words = (int64_t)nb * R;
+  // counts and their scan reused by every pass; the scans' look-back words
+  // (cleared with the rest of the scratch) one set per pass
+  uint32_t* counts = scratch;
+  uint32_t* starts = scratch + words;
+  uint32_t* scan_status = scratch + (int64_t)(passes > 2 ? passes : 2) * words + (int64_t)kHistCopies * passes * R;
+  for (int p = 0; p < passes; ++p) {
+    const int sh = rb * p;
+    if (items == 4)
+      digit_count_kernel<4><<<nb, kSortThreads, 0, st>>>(keys, n_dev, n, sh, counts);
+    else
+      digit_count_kernel<12><<<nb, kSortThreads, 0, st>>>(keys, n_dev, n, sh, counts);
+    scan_gather_exclusive(counts, nullptr, starts, words, nullptr, nullptr,
+                          scan_status + (int64_t)p * 2 * blocks_for(words, kScanChunk), err, false, st);
+    if (items == 4)
+      onesweep_pass_kernel<8, 4, true><<<nb, kSortThreads, 0, st>>>(keys, vals, n_dev, n, sh, nullptr, 0, starts,
+                                                                    err, keys_alt, vals_alt);
+    else
+      onesweep_pass_kernel<8, 12, true><<<nb, kSortThreads, 0, st>>>(keys, vals, n_dev, n, sh, nullptr, 0, starts,
+                                                                     err, keys_alt, vals_alt);
     uint32_t* t = keys; keys = keys_alt; keys_alt = t;
     t = vals; vals = vals_alt; vals_alt = t;
   }

@@ -140,6 +140,25 @@ def test_tile_list_depth_sort_modes(gpu, orc, depth_sort, big):
         assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("depth_sort", [1, 2])
+def test_tile_list_bit_exact_large_sorts(gpu, orc, depth_sort):
+    """600k Gaussians at 640x480, 4.5M instances: the tile sort takes
+    reduce-then-scan passes (more than 2^19 keys) in both modes, the global
+    depth sort its look-back passes over 600k keys, and lists of up to 4265
+    entries reach the per-tile sort's path through global memory. Lists
+    bit-exact against the oracle."""
+    s = scenes.keyframe_640x480(n=600_000, seed_offset=7)
+    say("large sorts, depth sort", depth_sort)
+    R = make(gpu, depth_sort=depth_sort)
+    R.render(to_dev(s.params), s.sh_degree, s.cameras)
+    torch.cuda.synchronize()
+    t_gpu, g_gpu = R.instances()
+    t_ref, g_ref = orc.tile_list(s.params, s.sh_degree, s.cameras, 16, 16)
+    assert s.num > 2**19 and len(t_ref) > 2**19
+    assert len(t_gpu) == len(t_ref)
+    assert np.array_equal(t_gpu, t_ref) and np.array_equal(g_gpu, g_ref)
+
+
 def test_tile_list_multiview_bit_exact(gpu, orc):
     s = scenes.tiny_random(4, n=80, width=45, height=37)
     cams = [s.cameras[0], identity_camera(29, 21, 25.0), scenes.look_at_camera([0.3, 0.1, -0.5], [0, 0, 2], 64, 33, 40.0)]
