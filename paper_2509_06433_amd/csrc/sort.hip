@@ -463,7 +463,8 @@ __global__ void __launch_bounds__(kSortThreads) global_hist_kernel(const uint32_
 template <int ITEMS>
 __global__ void __launch_bounds__(kSortThreads) digit_count_kernel(const uint32_t* __restrict__ keys,
                                                                    const uint32_t* __restrict__ n_dev, int64_t n_host,
-                                                                   int shift, uint32_t* __restrict__ counts) {
+                                                                   int shift, int dbits,
+                                                                   uint32_t* __restrict__ counts) {
   constexpr int R = 256;
   constexpr int NW = kSortThreads / 64;
   constexpr int CHUNK = kSortThreads * ITEMS;
@@ -485,12 +486,12 @@ __global__ void __launch_bounds__(kSortThreads) digit_count_kernel(const uint32_
   }
 #pragma unroll
   for (int r = 0; r < ITEMS; ++r)
-    if (base + r * kSortThreads + tid < n) atomicAdd(&h[wave][(k[r] >> shift) & (R - 1)], 1u);
+    if (base + r * kSortThreads + tid < n) atomicAdd(&h[wave][(k[r] >> shift) & ((1u << dbits) - 1u)], 1u);
   __syncthreads();
   uint32_t c = 0;
 #pragma unroll
   for (int w = 0; w < NW; ++w) c += h[w][tid];
-  counts[(size_t)tid * gridDim.x + blockIdx.x] = c;
+  if (tid < (1 << dbits)) counts[(size_t)tid * gridDim.x + blockIdx.x] = c;
 }
 
 // One digit pass: rank each key within its workgroup, find the output
@@ -502,7 +503,8 @@ __global__ void __launch_bounds__(kSortThreads) digit_count_kernel(const uint32_
 template <int RB, int ITEMS, bool SCANNED = false>
 __global__ void __launch_bounds__(kSortThreads) onesweep_pass_kernel(
     const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals, const uint32_t* __restrict__ n_dev,
-    int64_t n_host, int shift, const uint32_t* __restrict__ ghist, int ghist_stride, uint32_t* __restrict__ status,
+    int64_t n_host, int shift, int dbits, const uint32_t* __restrict__ ghist, int ghist_stride,
+    uint32_t* __restrict__ status,
     uint32_t* __restrict__ err, uint32_t* __restrict__ keys_out,
     uint32_t* __restrict__ vals_out) {
   constexpr int R = 1 << RB;
@@ -525,6 +527,9 @@ __global__ void __launch_bounds__(kSortThreads) onesweep_pass_kernel(
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int tid = threadIdx.x;
   const int64_t n = n_dev ? min((int64_t)*n_dev, n_host) : n_host;
+  // the digit's low `dbits` bits (all RB but in the top pass of a sort on a
+  // bit count that is no multiple of RB, whose keys leave the rest zero)
+  const uint32_t dmask = (1u << dbits) - 1u;
   for (int e = tid; e < NW * R; e += kSortThreads) (&wcnt[0][0])[e] = 0;
   __syncthreads();
   const uint32_t bid = blockIdx.x;
@@ -550,10 +555,11 @@ __global__ void __launch_bounds__(kSortThreads) onesweep_pass_kernel(
     const bool valid = j < n;
     const uint32_t key = valid ? k_reg[r] : 0u;
     k_reg[r] = key;
-    const uint32_t d = (key >> shift) & (R - 1);
+    const uint32_t d = (key >> shift) & dmask;
     uint64_t mask = __ballot(valid);
 #pragma unroll
     for (int b = 0; b < RB; ++b) {
+      if (b >= dbits) break;
       const bool bit = (d >> b) & 1u;
       const uint64_t bal = __ballot(bit);
       mask &= bit ? bal : ~bal;
@@ -700,7 +706,10 @@ __global__ void __launch_bounds__(kSortThreads) onesweep_pass_kernel(
     for (int t = 0; t < DPT; ++t) {
       const int d = tid * DPT + t;
       lstart[d] = my0 + mpre[t];
-      gofs[d] = (SCANNED ? status[(size_t)d * gridDim.x + bid] : gx0 + gpre[t] + excl[t]) - (my0 + mpre[t]);
+      // (the scanned starts exist for the live digits only; no key has another)
+      const uint32_t start =
+          SCANNED ? ((uint32_t)d <= dmask ? status[(size_t)d * gridDim.x + bid] : 0u) : gx0 + gpre[t] + excl[t];
+      gofs[d] = start - (my0 + mpre[t]);
     }
   }
   __syncthreads();
@@ -709,7 +718,7 @@ __global__ void __launch_bounds__(kSortThreads) onesweep_pass_kernel(
   uint32_t lp[ITEMS];
 #pragma unroll
   for (int r = 0; r < ITEMS; ++r) {
-    const uint32_t d = (k_reg[r] >> shift) & (R - 1);
+    const uint32_t d = (k_reg[r] >> shift) & dmask;
     lp[r] = off[r] == 0xFFFFFFFFu ? 0xFFFFFFFFu : lstart[d] + wcnt[wave][d] + off[r];
   }
   __syncthreads();
@@ -725,7 +734,7 @@ __global__ void __launch_bounds__(kSortThreads) onesweep_pass_kernel(
   const int cnt = (int)(n - blk0 < CHUNK ? (n - blk0 > 0 ? n - blk0 : 0) : CHUNK);
   for (int j = tid; j < cnt; j += kSortThreads) {
     const uint32_t key = s_keys[j];
-    const uint32_t d = (key >> shift) & (R - 1);
+    const uint32_t d = (key >> shift) & dmask;
     const uint32_t pos = gofs[d] + (uint32_t)j;
     if (pos < n) {
       keys_out[pos] = key;
@@ -1262,10 +1271,10 @@ void radix_sort_pairs(uint32_t*& keys, uint32_t*& vals, uint32_t*& keys_alt, uin
     uint32_t* stp = status + (int64_t)p * nb * R;
     const int sh = rb * p;
     if (items == 4)
-      onesweep_pass_kernel<8, 4><<<nb, kSortThreads, 0, st>>>(keys, vals, n_dev, n, sh, ghist + p * R, gstride, stp,
+      onesweep_pass_kernel<8, 4><<<nb, kSortThreads, 0, st>>>(keys, vals, n_dev, n, sh, rb, ghist + p * R, gstride, stp,
                                                               err, keys_alt, vals_alt);
     else
-      onesweep_pass_kernel<8, 12><<<nb, kSortThreads, 0, st>>>(keys, vals, n_dev, n, sh, ghist + p * R, gstride, stp,
+      onesweep_pass_kernel<8, 12><<<nb, kSortThreads, 0, st>>>(keys, vals, n_dev, n, sh, rb, ghist + p * R, gstride, stp,
                                                                err, keys_alt, vals_alt);
     uint32_t* t = keys; keys = keys_alt; keys_alt = t;
     t = vals; vals = vals_alt; vals_alt = t;
@@ -1289,17 +1298,20 @@ void radix_sort_pairs_scanned(uint32_t*& keys, uint32_t*& vals, uint32_t*& keys_
   uint32_t* scan_status = scratch + (int64_t)(passes > 2 ? passes : 2) * words + (int64_t)kHistCopies * passes * R;
   for (int p = 0; p < passes; ++p) {
     const int sh = rb * p;
+    // digits that can occur: keys lie below 2^bits
+    const int db = bits - sh < rb ? bits - sh : rb;
+    const int64_t live_words = (int64_t)nb << db;
     if (items == 4)
-      digit_count_kernel<4><<<nb, kSortThreads, 0, st>>>(keys, n_dev, n, sh, counts);
+      digit_count_kernel<4><<<nb, kSortThreads, 0, st>>>(keys, n_dev, n, sh, db, counts);
     else
-      digit_count_kernel<12><<<nb, kSortThreads, 0, st>>>(keys, n_dev, n, sh, counts);
-    scan_gather_exclusive(counts, nullptr, starts, words, nullptr, nullptr,
+      digit_count_kernel<12><<<nb, kSortThreads, 0, st>>>(keys, n_dev, n, sh, db, counts);
+    scan_gather_exclusive(counts, nullptr, starts, live_words, nullptr, nullptr,
                           scan_status + (int64_t)p * 2 * blocks_for(words, kScanChunk), err, false, st);
     if (items == 4)
-      onesweep_pass_kernel<8, 4, true><<<nb, kSortThreads, 0, st>>>(keys, vals, n_dev, n, sh, nullptr, 0, starts,
+      onesweep_pass_kernel<8, 4, true><<<nb, kSortThreads, 0, st>>>(keys, vals, n_dev, n, sh, db, nullptr, 0, starts,
                                                                     err, keys_alt, vals_alt);
     else
-      onesweep_pass_kernel<8, 12, true><<<nb, kSortThreads, 0, st>>>(keys, vals, n_dev, n, sh, nullptr, 0, starts,
+      onesweep_pass_kernel<8, 12, true><<<nb, kSortThreads, 0, st>>>(keys, vals, n_dev, n, sh, db, nullptr, 0, starts,
                                                                      err, keys_alt, vals_alt);
     uint32_t* t = keys; keys = keys_alt; keys_alt = t;
     t = vals; vals = vals_alt; vals_alt = t;
