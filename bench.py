@@ -28,8 +28,8 @@ METRIC = "mapping iters/sec (fwd+bwd) 640x480, 200k Gaussians; render Mpix/s"
 ADAM_WORKLOADS = {"surfaces_1200x680_1M_sh3", "mixed16_2M_sh3"}
 
 # MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz issue 39.3e12 FP32 VALU lane
-# operations per second without packed FP32 math (which this build does not
-# emit); the 157.3 TFLOP/s vector figure counts packed FMAs as four FLOPs.
+# operations per second without packed FP32 math (which the library's
+# kernels are compiled not to emit); the 157.3 TFLOP/s vector figure counts packed FMAs as four FLOPs.
 PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
 PEAK_HBM_GBS = 8000.0
 
@@ -115,7 +115,7 @@ def cpu_baseline(scene, cams, targets_np, min_seconds=10.0, max_iters=30):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(the path would shard by view)", file=sys.stderr)
         sys.exit(2)
     import numpy as np

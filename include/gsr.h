@@ -58,7 +58,7 @@ typedef enum {
   GSR_ERR_HIP = -3,          /* a HIP runtime call failed */
   GSR_ERR_STATE = -4,        /* call order violated (backward without matching forward) */
   GSR_ERR_CAPACITY = -5,     /* fixed-capacity scratch too small (mapping iteration) */
-  GSR_ERR_UNSUPPORTED = -6, /* option not supported by this build */
+  GSR_ERR_UNSUPPORTED = -6, /* option not supported by the library */
   GSR_ERR_DEVICE = -7        /* a bounded device-side wait expired; the call's results are invalid */
 } gsr_status;
 
