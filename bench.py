@@ -27,26 +27,35 @@ sys.path.insert(0, ROOT)
 METRIC = "mapping iters/sec (fwd+bwd) 640x480, 200k Gaussians; render Mpix/s"
 ADAM_WORKLOADS = {"surfaces_1200x680_1M_sh3", "mixed16_2M_sh3"}
 
-# MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz issue 39.3e12 FP32 VALU lane
-# operations per second without packed FP32 math (which the library's
-# kernels are compiled not to emit); the 157.3 TFLOP/s vector figure counts packed FMAs as four FLOPs.
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz issue 39.3e12 FP32 VALU lane
+# instructions per second without packed FP32 math (which the library's
+# kernels are compiled not to emit). AMD's published 157.3 TFLOP/s FP32 vector
+# figure counts a packed FMA (two lanes' FMAs in one instruction) as four
+# FLOPs: 256 x 64 x 2 x 2 x 2.4e9.
 PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
+PEAK_FP32_PUBLISHED_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 
-# Algorithmic VALU lane operations per (pixel, Gaussian) pair walked by the
-# blend backward: 20 for the alpha (10 for the exponent in its definition's
-# float order, 1 scaling, the exp counted as 4 for its quarter issue rate,
-# 5 for opacity, clamp and the skip tests), 29 for the reverse step (rcp
-# likewise counted as 4), 10 for the wave sums of the ten per-Gaussian moments
-# (63 adds per 64 lanes each).
+# Algorithmic work per (pixel, Gaussian) pair walked, in two countings.
+#  Issue slots (the roofline's unit): one per VALU lane instruction, the
+#  transcendentals (exp, rcp) counted as 4 for their quarter issue rate.
+#   backward 59: the alpha 20 (exponent in its definition's float order 10,
+#     scaling by log2 e 1, exp 4, opacity, clamp and skip tests 5), the reverse
+#     step 29 (rcp 4), the wave sums of the ten per-Gaussian moments 10 (63
+#     adds per 64 lanes each);
+#   forward 23: the alpha 20 and the transmittance test and update 3 (the
+#     colour and depth accumulation happens once per composited pair).
+#  Plain operations (each FP32 operation once, exp and rcp included), for
+#  the published FLOP figure: backward 53, forward 20.
 OPS_PER_PAIR_BWD = 59.0
-# Blend forward: 20 for the alpha, 3 for the transmittance test and update
-# (the colour and depth accumulation happens once per composited pair).
 OPS_PER_PAIR_FWD = 23.0
+PLAIN_OPS_PER_PAIR_BWD = 53.0
+PLAIN_OPS_PER_PAIR_FWD = 20.0
 # The fused launch (forward and backward of every tile in one grid) is
 # credited with both per pair walked by the backward; the forward's pairs
 # past each pixel's last composited Gaussian are not counted.
 OPS_PER_PAIR_FUSED = OPS_PER_PAIR_FWD + OPS_PER_PAIR_BWD
+PLAIN_OPS_PER_PAIR_FUSED = PLAIN_OPS_PER_PAIR_FWD + PLAIN_OPS_PER_PAIR_BWD
 
 
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
@@ -82,34 +91,74 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 256 MiB device copy (reference for HBM byte counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-peaks", action="store_true", help="skip the achievable-peak probes")
     ap.add_argument("--breakdown", action="store_true", help="print a per-stage time breakdown to stderr")
     ap.add_argument("--mode", choices=["graph", "eager"], default="graph")
     ap.add_argument("--compare-steps", type=int, default=20, help="steps of the other mode (0 = skip)")
     return ap.parse_args()
 
 
-def cpu_baseline(scene, cams, targets_np, min_seconds=10.0, max_iters=30):
-    """The CPU oracle as it stands: full mapping iterations of the workload's first view, repeated until
-    about min_seconds of CPU work have been timed."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(scene, cams, targets_np, repeats=3, single_row_step=8):
+    """The CPU oracle as it stands: one mapping iteration (FP32 brute-force
+    forward, L1 loss, FP64 analytic backward) of the workload's first view.
+    All cores: the median of `repeats` whole iterations. One thread: the median
+    of `repeats` iterations over every single_row_step-th pixel row (forward
+    and backward restricted to those rows), extrapolated to the whole view."""
     import numpy as np
     import oracle
     cores = oracle.set_threads(0)
     cam = cams[0]
-    iters = 0
-    t0 = time.perf_counter()
-    while True:
-        r = oracle.render(scene.params, scene.sh_degree, cam, mode="f32")
+
+    def one(window):
+        t0 = time.perf_counter()
+        r = oracle.render(scene.params, scene.sh_degree, cam, mode="f32", window=window)
         L, grgb, gdep = oracle.l1_loss_and_grad(r["rgb"], r["depth"], targets_np[0][0], targets_np[0][1])
         oracle.backward(scene.params, scene.sh_degree, [cam],
                         [(grgb.astype(np.float32), gdep.astype(np.float32), np.zeros_like(gdep, np.float32))],
-                        pinned=True)
-        iters += 1
-        dt = time.perf_counter() - t0
-        if dt >= min_seconds or iters >= max_iters:
-            break
-    return {"value": round(iters / dt, 5), "unit": "iters/s", "cores": cores, "kind": "oracle",
-            "sample": f"{iters} mapping iterations (FP32 brute-force forward, L1 loss, FP64 analytic backward) of "
-                      f"view 0 of {scene.name}, {cam.width}x{cam.height}, {scene.num} Gaussians; {dt:.2f} s"}
+                        pinned=True, windows=[window])
+        return time.perf_counter() - t0
+
+    t_all = sorted(one(None) for _ in range(repeats))[repeats // 2]
+    oracle.set_threads(1)
+    win = (0, 0, cam.width, cam.height, single_row_step)
+    rows = len(range(0, cam.height, single_row_step))
+    t_one = sorted(one(win) for _ in range(repeats))[repeats // 2] * cam.height / rows
+    oracle.set_threads(cores)
+    return {"value": round(1.0 / t_all, 5), "unit": "iters/s", "cores": cores, "kind": "oracle",
+            "single_thread_value": round(1.0 / t_one, 6), "single_thread_extrapolated": True,
+            "cpu_model": cpu_model(),
+            "sample": f"one mapping iteration (FP32 brute-force forward, L1 loss, FP64 analytic backward) of view 0 "
+                      f"of {scene.name}, {cam.width}x{cam.height}, {scene.num} Gaussians; median of {repeats} on "
+                      f"{cores} threads ({t_all:.2f} s); one thread: median of {repeats} over every "
+                      f"{single_row_step}th pixel row, extrapolated to the view ({t_one:.1f} s)"}
+
+
+def achievable_peaks():
+    """The device's achievable rates from the library's probe kernels
+    (include/gsr_peaks.h): HBM copy, FP32 VALU issue, the 2^x rate, LDS reads."""
+    import ctypes
+    from paper_2509_06433_amd import _lib
+    L = _lib.load()
+    out = {}
+    d = ctypes.c_double()
+    for name, fn, args, scale, unit in (
+            ("hbm_copy", L.gsr_peak_copy, (2 << 30, 20), 1e-9, "GB/s"),
+            ("valu_fp32", L.gsr_peak_valu, (20,), 1e-12, "T lane-instr/s"),
+            ("exp2", L.gsr_peak_exp, (20,), 1e-12, "T lane-ops/s"),
+            ("lds_read", L.gsr_peak_lds, (20,), 1e-12, "TB/s")):
+        rc = fn(*args, None, ctypes.byref(d))
+        out[name] = {"value": round(d.value * scale, 3) if rc == 0 else None, "unit": unit}
+    return out
 
 
 def main():
@@ -221,7 +270,10 @@ def main():
     pairs, visible = R.count_work(len(cams))
     dom_avg_ms = dom_ms / max(args.steps, 1)     # one launch per step in graph mode
     ops_per_pair = {"blend_fwd": OPS_PER_PAIR_FWD, "blend_bwd": OPS_PER_PAIR_BWD, "blend": OPS_PER_PAIR_FUSED}[dominant]
+    plain_per_pair = {"blend_fwd": PLAIN_OPS_PER_PAIR_FWD, "blend_bwd": PLAIN_OPS_PER_PAIR_BWD,
+                      "blend": PLAIN_OPS_PER_PAIR_FUSED}[dominant]
     achieved = ops_per_pair * pairs / (dom_avg_ms * 1e-3) / 1e12
+    achieved_plain = plain_per_pair * pairs / (dom_avg_ms * 1e-3) / 1e12
 
     other = "eager" if args.mode == "graph" else "graph"
     other_ms = None
@@ -245,7 +297,8 @@ def main():
     torch.cuda.synchronize()
     stages = {k: ms / 3 for k, (ms, n) in R.profile(reset=True).items() if n}     # ms per step
     R.set_profiling([])
-    front = ["project", "depth_sort", "scan", "emit", "tile_sort", "ranges", "blend_fwd"]
+    # the whole forward: the clear, projection, binning, both sorts, ranges, compositing
+    front = ["zero", "project", "depth_sort", "scan", "emit", "tile_sort", "ranges", "tile_depth", "blend_fwd"]
     render_ms = sum(stages.get(k, 0.0) for k in front) if "blend_fwd" in stages else 0.0
     render_from = "iteration stages"
     if "blend_fwd" not in stages and "blend" in stages and args.mode == "graph":
@@ -304,14 +357,26 @@ def main():
                    "instances": st["instances"], "visible_per_view": visible,
                    "stage_ms": {k: round(x, 4) for k, x in stages.items()}},
         "roofline": {"bound": "alu", "kernel": dominant, "achieved": round(achieved, 3),
-                     "peak": round(PEAK_VALU_TOPS, 2), "unit": "TOP/s (FP32 VALU lane ops)",
+                     "peak": round(PEAK_VALU_TOPS, 2), "unit": "T issue slots/s (FP32 VALU lane instructions)",
                      "frac": round(achieved / PEAK_VALU_TOPS, 4),
+                     "peak_derivation": "256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, non-packed FP32 issue; "
+                                        f"{ops_per_pair:g} slots per pair walked (exp and rcp 4 each)",
+                     "achieved_plain_tflops": round(achieved_plain, 3),
+                     "frac_published": round(achieved_plain / PEAK_FP32_PUBLISHED_TFLOPS, 4),
+                     "published_peak": f"{PEAK_FP32_PUBLISHED_TFLOPS} TFLOP/s FP32 vector (packed FMA as 4 FLOPs); "
+                                       f"{plain_per_pair:g} plain FP32 ops per pair",
                      "traffic": (round(sum(TRAFFIC[(scene.name, dominant)])) if (scene.name, dominant) in TRAFFIC
                                  else None),
                      "traffic_read_write": TRAFFIC.get((scene.name, dominant)),
                      "avg_ms": round(dom_avg_ms, 4), "launches": dom_n, "pairs": pairs,
                      "ops_per_pair": ops_per_pair},
     }
+    if not args.no_peaks:
+        peaks = achievable_peaks()
+        out["roofline"]["achievable"] = peaks
+        v = peaks["valu_fp32"]["value"]
+        if v:
+            out["roofline"]["frac_achievable"] = round(achieved / v, 4)
     if not args.no_cpu_baseline and not forward_only:
         tnp = [(t[0].cpu().numpy(), t[1].cpu().numpy()) for t in targets]
         out["cpu_baseline"] = cpu_baseline(scene, cams, tnp)

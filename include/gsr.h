@@ -97,6 +97,14 @@ typedef struct {
                                depth after binning (the splats are binned in index order),
                                2 = all visible splats are sorted by depth once before binning.
                                The lists are identical. */
+  int32_t backward_schedule; /* blend backward: 0 = pixel-parallel (default: a thread per pixel
+                               walks its list in reverse; per-Gaussian sums reduced over each
+                               wavefront and workgroup before the atomics), 1 = splat-parallel
+                               (a wavefront per tile, a Gaussian per lane, the tile's pixels
+                               streamed through the lanes; one set of atomics per (tile,
+                               Gaussian); the lists are walked whole, so chunk_len and
+                               fuse_blend do not apply). Same gradient up to float summation
+                               order. */
 } gsr_options;
 
 typedef struct {
@@ -154,6 +162,28 @@ int gsr_render1(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_camera* cam,
 int gsr_render_backward(gsr_ctx* ctx, const gsr_gaussians* g, int32_t num_views,
                         const gsr_camera* cams, const gsr_image* grad_out,
                         float* grad_params, void* stream);
+
+/* Backward of the last gsr_render with respect to the cameras as well: the
+ * gradient that tracking against a single map needs (paper Sec. II-B: SLAM
+ * systems that track and map on the same Gaussian map). Same image gradients,
+ * call order and GSR_ERR_STATE rule as gsr_render_backward.
+ *   grad_params  device [P][stride] float32, += dL/dparams; NULL = not formed
+ *   grad_cams    device [num_views][12] float64, += per view dL/dR (the nine
+ *                entries of gsr_camera.R, row-major, each taken as free) and
+ *                dL/dt (gsr_camera.t), for x_cam = R x + t. R acts through the
+ *                camera-space means, the screen covariance J R Sigma R^T J^T
+ *                and, for view-dependent colour (sh_degree >= 1), the camera
+ *                centre -R^T t. Required.
+ *   grad_twist   device [num_views][6] float64 or NULL: += the gradient with
+ *                respect to a left perturbation of the pose, [R | t] <-
+ *                exp(xi^) [R | t] with xi = (rho, phi) (rho translation, phi
+ *                rotation vector): dL/drho = dL/dt, dL/dphi = (A21 - A12,
+ *                A02 - A20, A10 - A01) with A = dL/dR R^T + dL/dt t^T.
+ * Each view's sums are formed per workgroup in double and added with float64
+ * atomics (the order of the additions varies from call to call). */
+int gsr_render_backward_pose(gsr_ctx* ctx, const gsr_gaussians* g, int32_t num_views,
+                             const gsr_camera* cams, const gsr_image* grad_out, float* grad_params,
+                             double* grad_cams, double* grad_twist, void* stream);
 
 /* Mapping loss of one or more rendered views against targets:
  *   L = sum_v [ mean|rgb_v - rgb*_v| + depth_weight * mean|depth_v - depth*_v| ]
@@ -213,6 +243,37 @@ int gsr_mapping_iteration(gsr_ctx* ctx, float* params, int64_t num, int64_t stri
                           const gsr_image* targets, float depth_weight, float* grad_params,
                           float* loss, const gsr_adam* adam, void* stream);
 
+/* Keyframe insertion (paper Fig. "GS_SLAM": keyframe management grows the
+ * map): new Gaussians seeded from one RGB-D keyframe, appended to the map.
+ * On the grid of every step-th pixel (pixels (gx*step, gy*step)), a pixel
+ * seeds a Gaussian when its observed depth d lies in [depth_min, depth_max]
+ * and, if coverage is given, the current map's rendered alpha there is below
+ * alpha_below. The Gaussian: mean = the back-projection R^T (d ray - t) of
+ * the pixel centre's ray ((px + 0.5 - cx)/fx, (py + 0.5 - cy)/fy, 1); three
+ * equal log-scales log(scale_factor * d * step / ((fx + fy)/2)); quaternion
+ * (1, 0, 0, 0); opacity logit opacity_logit; SH coefficient 0 of each channel
+ * (rgb - 0.5) / Y_00 (so its colour is the observed one), the others 0. */
+typedef struct {
+  int32_t step;             /* grid spacing in pixels, >= 1 */
+  float alpha_below;        /* seed only where coverage < alpha_below (ignored without coverage) */
+  float depth_min, depth_max;
+  float scale_factor;       /* > 0 */
+  float opacity_logit;
+} gsr_densify_options;
+
+/* params: device [P][stride] float32 (P from sh_degree) holding num
+ * Gaussians; the new ones are written at indices num, num + 1, ... in pixel
+ * order (row-major over the grid), at most stride - num of them. rgb, depth:
+ * device [3][H][W], [H][W] of the keyframe (cam's size); coverage: device
+ * [H][W] (the alpha gsr_render gave for this view) or NULL. *appended (host)
+ * receives the number written, *wanted (host, may be NULL) the number of
+ * seeding pixels, so a caller whose buffer was too small can grow it (stride)
+ * and call again with num + *appended. Synchronises `stream`. A mapping
+ * iteration called with the new size captures its graph again. */
+int gsr_densify(gsr_ctx* ctx, float* params, int64_t num, int64_t stride, int32_t sh_degree,
+                const gsr_camera* cam, const float* rgb, const float* depth, const float* coverage,
+                const gsr_densify_options* opt, int64_t* appended, int64_t* wanted, void* stream);
+
 /* Counters of the context's mapping iterations (synchronises the stream of
  * the last iteration). Returns GSR_ERR_DEVICE if any iteration's sort wait
  * expired. */
@@ -227,12 +288,32 @@ typedef struct {
 int gsr_mapping_status(gsr_ctx* ctx, gsr_mapping_stats* out);
 
 /* Status of the last render (gsr_render or gsr_mapping_iteration) on this
- * context (synchronises the context's last stream): number of (tile,
- * Gaussian) instances over all views, -1 for the number of visible splats
- * (see gsr_count_work), and the number of tiles. Any pointer may be NULL.
+ * context (synchronises the context's last stream). Any pointer may be NULL.
+ *   num_instances     (tile, Gaussian) instances the render required over all
+ *                     views; a mapping iteration whose count exceeds its
+ *                     fixed capacity was skipped (gsr_mapping_status)
+ *   num_visible       (view, Gaussian) splats with at least one tile
+ *   num_tiles         tiles over all views
+ *   nonfinite_culled  Gaussians culled for their values alone: a non-finite
+ *                     mean, log-scale, rotation or opacity logit, or a
+ *                     rotation quaternion of zero norm (counted once per
+ *                     Gaussian, whatever the number of views). Such Gaussians
+ *                     are not an error: they are drawn in no view and receive
+ *                     no gradient. (A splat whose colour is non-finite is
+ *                     culled in that view and not counted here.)
  * GSR_ERR_DEVICE if that render's sort wait expired. */
 int gsr_query_status(gsr_ctx* ctx, int64_t* num_instances, int64_t* num_visible,
-                     int64_t* num_tiles);
+                     int64_t* num_tiles, int64_t* nonfinite_culled);
+
+/* Activations of the parameters as the projection computes them (paper
+ * Sec. II-A: each Gaussian's covariance comes from its per-axis scales and
+ * rotation, and it carries an opacity): scale[k][num] = exp(log-scale k) and
+ * opacity[num] = 1 / (1 + exp(-logit)), in float, with exp correctly rounded
+ * to float and the + and / of the sigmoid one correctly rounded float
+ * operation each, exactly the values the projection uses. Reads planes 3..5
+ * and 10 of g only. scale: device [3][g->num] (plane stride g->num) or NULL;
+ * opacity: device [g->num] or NULL. Asynchronous on `stream`. */
+int gsr_activations(gsr_ctx* ctx, const gsr_gaussians* g, float* scale, float* opacity, void* stream);
 
 /* Copy the sorted instance list of the last render to host: tile[k] is the
  * global tile id (view tile offset + ty * tiles_x + tx, views in order),
@@ -253,6 +334,33 @@ int gsr_copy_splats(gsr_ctx* ctx, int32_t view, float* out, int64_t num);
  * including the last composited Gaussian (the pairs the backward walks);
  * visible[num_views] (may be NULL) = Gaussians with at least one tile per view. */
 int gsr_count_work(gsr_ctx* ctx, int64_t* pairs, int64_t* visible, int32_t num_views);
+
+/* ---- Sharing the live map with a viewer process on the same GPU ---------
+ * The paper's viewer is a separate process that reads the map directly from
+ * GPU memory through inter-process handles, so rendering for the operator
+ * neither copies the map nor stalls the mapping loop (paper Sec. III,
+ * Fig. "CUDA_IPC"). A handle is 64 opaque bytes to pass between processes
+ * (a file, a pipe). None of these calls allocates device memory except the
+ * event; all return GSR_ERR_HIP when the runtime refuses. */
+typedef struct {
+  unsigned char bytes[64];
+} gsr_ipc_handle;
+
+/* Export the device allocation holding dev_ptr: *out the handle of the whole
+ * allocation, *offset the byte offset of dev_ptr inside it, *alloc_bytes (may
+ * be NULL) its size. GSR_ERR_UNSUPPORTED for allocations above 1 GiB. */
+int gsr_ipc_export_memory(const void* dev_ptr, gsr_ipc_handle* out, int64_t* offset, int64_t* alloc_bytes);
+/* In another process: map the exported allocation; *dev_ptr = its base plus
+ * offset (the exporter's pointer), *base the mapping to close. */
+int gsr_ipc_open_memory(const gsr_ipc_handle* h, int64_t offset, void** dev_ptr, void** base);
+int gsr_ipc_close_memory(void* base);
+/* An inter-process event (no timing) and its handle; the other process
+ * opens it, and gsr_ipc_event_wait makes a stream wait for its last record. */
+int gsr_ipc_event_create(void** event, gsr_ipc_handle* out);
+int gsr_ipc_event_open(const gsr_ipc_handle* h, void** event);
+int gsr_ipc_event_record(void* event, void* stream);
+int gsr_ipc_event_wait(void* event, void* stream);
+int gsr_ipc_event_destroy(void* event);
 
 /* Stages timed when profiling is on. */
 typedef enum {

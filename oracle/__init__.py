@@ -3,7 +3,7 @@
 Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
 import this package. It shares no code with the HIP library; it loads its own
 C++ reference (oracle.cpp, built by oracle/build.py) and adds the parts that
-are plain NumPy: the L1 mapping loss and Adam.
+are plain NumPy: the L1 mapping loss, Adam and keyframe insertion.
 
 Parity status: every function here is pinned in tests/test_oracle_*.py by a
 closed form, a library routine, an invariant, torch autograd or finite
@@ -43,8 +43,10 @@ def lib():
         c_i64, c_int, c_f = ctypes.c_int64, ctypes.c_int, ctypes.c_float
         L.orc_num_threads.argtypes = [c_int]
         L.orc_num_threads.restype = c_int
-        L.orc_exp32.argtypes = [F32P, F32P, c_i64]
+        L.orc_exp32.argtypes = [F32P, F32P, ctypes.c_void_p, c_i64]
         L.orc_exp32.restype = None
+        L.orc_activations.argtypes = [F32P, F32P, F32P, F32P, c_i64]
+        L.orc_activations.restype = None
         L.orc_sh_basis.argtypes = [c_int, F64P, c_i64, F64P, ctypes.c_void_p]
         L.orc_sh_basis.restype = None
         L.orc_project.argtypes = [c_int, F32P, c_i64, c_i64, c_int, F32P, c_int, c_int, c_f, F64P, I32P]
@@ -53,10 +55,10 @@ def lib():
                                     c_i64, U32P, U32P, ctypes.POINTER(c_i64)]
         L.orc_tile_list.restype = c_int
         L.orc_render.argtypes = [c_int, c_int, F32P, c_i64, c_i64, c_int, F32P, c_int, c_int, c_f, F32P,
-                                 F64P, F64P, F64P, F64P, I32P, F64P]
+                                 F64P, F64P, F64P, F64P, I32P, F64P, ctypes.c_void_p]
         L.orc_render.restype = c_int
         L.orc_backward.argtypes = [c_int, F32P, c_i64, c_i64, c_int, c_int, F32P, I32P, c_f, F32P,
-                                   F32P, F32P, F32P, F64P, ctypes.c_void_p]
+                                   F32P, F32P, F32P, F64P, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         L.orc_backward.restype = c_int
         _lib = L
     return _lib
@@ -71,12 +73,29 @@ def _cam_floats(cam) -> np.ndarray:
     return np.ascontiguousarray(cam.as_floats(), np.float32)
 
 
-def exp32(x) -> np.ndarray:
-    """The oracle's own FP32 exponential (Cody-Waite reduction + degree-7 polynomial)."""
+def exp32(x, with_tie=False):
+    """The FP32 mode's exponential: exp(x) rounded to the nearest float (the
+    library's double exp rounded to float, recomputed from its long double exp
+    where the double result lies within 2^-50 of a rounding midpoint). With
+    with_tie, also the relative distance of the long double exp from the
+    nearest rounding midpoint, per element."""
     x = np.ascontiguousarray(x, np.float32).ravel()
     y = np.empty_like(x)
-    lib().orc_exp32(x, y, x.size)
-    return y
+    tie = np.empty(x.size, np.float64) if with_tie else None
+    lib().orc_exp32(x, y, tie.ctypes.data if with_tie else None, x.size)
+    return (y, tie) if with_tie else y
+
+
+def activations(logscale, logit):
+    """The FP32 activations of O1, element by element: (exp(logscale),
+    1 / (1 + exp(-logit))) in float with the exponential above."""
+    ls = np.ascontiguousarray(logscale, np.float32).ravel()
+    lg = np.ascontiguousarray(logit, np.float32).ravel()
+    assert ls.size == lg.size
+    s = np.empty_like(ls)
+    o = np.empty_like(lg)
+    lib().orc_activations(ls, lg, s, o, ls.size)
+    return s, o
 
 
 def sh_basis(deg: int, dirs, with_grad=False):
@@ -130,32 +149,50 @@ def tile_list(params, sh_degree, cams, tile_w=16, tile_h=16, znear=0.2):
 MODES = {"f32": 0, "f64pin": 1, "f64": 2}
 
 
-def render(params, sh_degree, cam, mode="f32", prefilter=True, bg=(0.0, 0.0, 0.0), znear=0.2):
+def _window(window, cam):
+    """(x0, y0, x1, y1, row_step) as int32, or None for the whole image."""
+    if window is None:
+        return None
+    w = list(window) + [1] * (5 - len(window))
+    return np.ascontiguousarray(w[:5], np.int32)
+
+
+def render(params, sh_degree, cam, mode="f32", prefilter=True, bg=(0.0, 0.0, 0.0), znear=0.2, window=None):
     """Brute-force per-pixel render of one view. Returns dict with rgb [3,H,W],
     depth [H,W], alpha [H,W], tfinal [H,W], ncomp [H,W] (number of composited
     Gaussians) and margin [H,W] (smallest relative distance of any decision to
-    its threshold, from the deciding precision)."""
+    its threshold, from the deciding precision). window = (x0, y0, x1, y1[,
+    row_step]): only the pixels of [x0, x1) x [y0, y1) in every row_step-th
+    row are composited (each pixel exactly as in the whole render); the others
+    are left at 0 (margin +inf)."""
     p = np.ascontiguousarray(params, np.float32)
     n = p.shape[1]
     H, W = cam.height, cam.width
-    rgb = np.empty((3, H, W), np.float64)
-    depth = np.empty((H, W), np.float64)
-    alpha = np.empty((H, W), np.float64)
-    tfin = np.empty((H, W), np.float64)
-    ncomp = np.empty((H, W), np.int32)
-    margin = np.empty((H, W), np.float64)
+    rgb = np.zeros((3, H, W), np.float64)
+    depth = np.zeros((H, W), np.float64)
+    alpha = np.zeros((H, W), np.float64)
+    tfin = np.zeros((H, W), np.float64)
+    ncomp = np.zeros((H, W), np.int32)
+    margin = np.full((H, W), np.inf, np.float64)
+    win = _window(window, cam)
     rc = lib().orc_render(MODES[mode], int(bool(prefilter)), p, n, n, int(sh_degree), _cam_floats(cam), W, H,
-                          float(znear), np.ascontiguousarray(bg, np.float32), rgb, depth, alpha, tfin, ncomp, margin)
+                          float(znear), np.ascontiguousarray(bg, np.float32), rgb, depth, alpha, tfin, ncomp, margin,
+                          win.ctypes.data if win is not None else None)
     assert rc == 0
     return dict(rgb=rgb, depth=depth, alpha=alpha, tfinal=tfin, ncomp=ncomp, margin=margin)
 
 
-def backward(params, sh_degree, cams, grads, pinned=True, bg=(0.0, 0.0, 0.0), znear=0.2, want_2d=False):
+def backward(params, sh_degree, cams, grads, pinned=True, bg=(0.0, 0.0, 0.0), znear=0.2, want_2d=False,
+             windows=None, want_cam=False):
     """FP64 analytic gradient of sum_v <grads_v, (rgb_v, depth_v, alpha_v)> with respect
     to the parameters [P, N]. grads: list of (g_rgb [3,H,W], g_depth [H,W], g_alpha [H,W]).
     pinned: False = FP64 decisions; True = decisions from the FP32 recurrence;
     "splats32" = FP32 decisions and FP32-rounded screen-space splat values
-    (u, v, conic, opacity, colour, depth), FP64 arithmetic."""
+    (u, v, conic, opacity, colour, depth), FP64 arithmetic. windows: per view a
+    window as render's (or None): only its pixels are walked, which equals the
+    gradient with the upstream gradient zeroed outside it. want_cam: also
+    return each view's camera gradient [V, 12] (dL/dR row-major, then dL/dt)
+    for x_cam = R x + t."""
     p = np.ascontiguousarray(params, np.float32)
     P, n = p.shape
     camf = np.ascontiguousarray(np.stack([_cam_floats(c) for c in cams]), np.float32)
@@ -166,12 +203,24 @@ def backward(params, sh_degree, cams, grads, pinned=True, bg=(0.0, 0.0, 0.0), zn
     galp = np.ascontiguousarray(np.concatenate([np.asarray(g[2], np.float32).ravel() for g in grads]))
     grad = np.empty((P, n), np.float64)
     g2 = np.empty((len(cams), n, 10), np.float64) if want_2d else None
+    win = None
+    if windows is not None:
+        win = np.ascontiguousarray(np.stack([_window(w, c) if w is not None else
+                                             np.array([0, 0, c.width, c.height, 1], np.int32)
+                                             for w, c in zip(windows, cams)]), np.int32)
     mode = 2 if pinned == "splats32" else int(bool(pinned))
+    gcam = np.zeros((len(cams), 12), np.float64) if want_cam else None
     rc = lib().orc_backward(mode, p, n, n, int(sh_degree), len(cams), camf, wh, float(znear),
                             np.ascontiguousarray(bg, np.float32), grgb, gdep, galp, grad,
-                            g2.ctypes.data if want_2d else None)
+                            g2.ctypes.data if want_2d else None, win.ctypes.data if win is not None else None,
+                            gcam.ctypes.data if want_cam else None)
     assert rc == 0
-    return (grad, g2) if want_2d else grad
+    out = (grad,)
+    if want_2d:
+        out += (g2,)
+    if want_cam:
+        out += (gcam,)
+    return out if len(out) > 1 else grad
 
 
 # ---------------------------------------------------------------------------
@@ -202,3 +251,46 @@ def adam_step(param, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-15):
     if lr.ndim == 1:
         lr = lr[:, None]
     return param - lr * mhat / (np.sqrt(vhat) + eps), m, v
+
+
+# ---------------------------------------------------------------------------
+# Keyframe insertion (plain NumPy, float64)
+# ---------------------------------------------------------------------------
+
+Y00 = 0.5 / np.sqrt(np.pi)      # the constant real spherical harmonic
+
+
+def densify(sh_degree, cam, rgb, depth, coverage=None, step=4, alpha_below=0.5, depth_min=0.2, depth_max=100.0,
+            scale_factor=1.0, opacity_logit=0.0):
+    """New Gaussians seeded from one RGB-D keyframe, in seeding order, as
+    (params [P, M] float64, pixel coordinates [M, 2]). A grid pixel (gx*step,
+    gy*step), taken in row-major order, seeds one Gaussian when its depth d
+    lies in [depth_min, depth_max] and (with coverage) coverage < alpha_below:
+    mean = R^T (d * ray - t) for the ray ((px + 0.5 - cx)/fx, (py + 0.5 - cy)/fy,
+    1) through the pixel centre; log-scales log(scale_factor d step / ((fx +
+    fy)/2)); quaternion (1, 0, 0, 0); the given opacity logit; SH coefficient
+    0 = (rgb - 0.5) / Y_00 per channel, the rest 0."""
+    H, W = cam.height, cam.width
+    depth = np.asarray(depth, np.float64)
+    rgb = np.asarray(rgb, np.float64)
+    ys = np.arange(0, H, step)
+    xs = np.arange(0, W, step)
+    py, px = [a.ravel() for a in np.meshgrid(ys, xs, indexing="ij")]      # row-major over the grid
+    d = depth[py, px]
+    keep = (d >= depth_min) & (d <= depth_max)
+    if coverage is not None:
+        keep &= np.asarray(coverage, np.float64)[py, px] < alpha_below
+    px, py, d = px[keep], py[keep], d[keep]
+    R = np.asarray(cam.R, np.float64)
+    t = np.asarray(cam.t, np.float64)
+    xcam = np.stack([(px + 0.5 - cam.cx) / cam.fx * d, (py + 0.5 - cam.cy) / cam.fy * d, d], axis=1)
+    mean = (xcam - t) @ R                      # rows: R^T (x - t)
+    m = len(d)
+    P = 11 + 3 * (sh_degree + 1) ** 2
+    out = np.zeros((P, m), np.float64)
+    out[0:3] = mean.T
+    out[3:6] = np.log(scale_factor * d * step / (0.5 * (cam.fx + cam.fy)))[None, :]
+    out[6] = 1.0
+    out[10] = opacity_logit
+    out[11:14] = (rgb[:, py, px] - 0.5) / Y00
+    return out, np.stack([px, py], axis=1)

@@ -18,9 +18,10 @@
 // Three scalar modes:
 //   FP32        the reference for tile lists (bit-exact) and colour/depth.
 //               Its projection follows a fixed sequence of IEEE-754 float
-//               operations (no contraction, correctly rounded / and sqrt, and a
-//               Cody-Waite exponential written here) so that an independent
-//               implementation of the same sequence reproduces it bit for bit.
+//               operations (no contraction; correctly rounded /, sqrt and
+//               exp, the last being the library exp rounded to float) so that
+//               an independent implementation of the same sequence
+//               reproduces it bit for bit.
 //   FP64 pinned the reference for gradients: values in double, every discrete
 //               decision (cull, depth order, skip, clamp, stop) taken from the
 //               FP32 recurrence evaluated alongside. A stricter variant also
@@ -55,26 +56,36 @@ const float kClampFov = 1.3f;            // Jacobian clamp, multiple of the half
 const float kQMax = 11.2f;
 
 // ---------------------------------------------------------------------------
-// Exponential, FP32: Cody-Waite range reduction x = n ln2 + r with ln2 split
-// in a 15-bit head and a tail, degree-7 Taylor polynomial for e^r on
-// |r| <= ln2/2 (Horner, separate multiply and add), scaled by 2^n.
+// Exponential in the FP32 mode: exp(x) rounded to the nearest float (O1 uses
+// it for the scales and the opacity). The library's double exp is rounded to
+// float; that second rounding can only go wrong when the double result lies
+// within its own error of a midpoint between two floats, so such results are
+// recomputed from the library's long double exp (64 significant bits).
+// exp32_tie_distance reports how close the long double result comes to a
+// midpoint, so that tests can check that no input of the ranges in use is
+// undecided even at that precision.
 // ---------------------------------------------------------------------------
-float exp_cw(float x) {
-  x = std::fmin(std::fmax(x, -87.0f), 88.0f);
-  float n = std::rint(x * 1.44269504088896341f);
-  float r = x - n * 0.693145751953125f;
-  r = r - n * 1.4286068203094173e-06f;
-  float p = 1.98412698412698413e-4f;     // 1/7!
-  p = p * r + 1.38888888888888889e-3f;   // 1/6!
-  p = p * r + 8.33333333333333333e-3f;   // 1/5!
-  p = p * r + 4.16666666666666667e-2f;   // 1/4!
-  p = p * r + 1.66666666666666667e-1f;   // 1/3!
-  p = p * r + 0.5f;                      // 1/2!
-  p = p * r + 1.0f;
-  p = p * r + 1.0f;
-  return std::ldexp(p, (int)n);
+long double float_midpoint_near(float f, long double y) {
+  // midpoint between f and its neighbour on y's side (exact in long double)
+  const float nb = y >= (long double)f ? std::nextafter(f, INFINITY) : std::nextafter(f, -INFINITY);
+  return 0.5L * ((long double)f + (long double)nb);
 }
-double exp_cw(double x) { return std::exp(x); }
+float exp32(float x) {
+  const double y = std::exp((double)x);
+  const float f = (float)y;
+  if (!std::isfinite(f) || f == 0.0f) return f;
+  const long double mid = float_midpoint_near(f, (long double)y);
+  if (std::fabs((long double)y - mid) > 0x1p-50L * (long double)y) return f;
+  return (float)std::exp((long double)x);
+}
+double exp32_tie_distance(float x) {
+  const long double y = std::exp((long double)x);
+  const float f = (float)y;
+  if (!std::isfinite(f) || f == 0.0f) return INFINITY;
+  return (double)(std::fabs(y - float_midpoint_near(f, y)) / y);
+}
+float exp_t(float x) { return exp32(x); }
+double exp_t(double x) { return std::exp(x); }
 
 template <class T> T sqrt_t(T x) { return std::sqrt(x); }
 
@@ -191,7 +202,7 @@ Proj<T> project_one(const float* P, int64_t stride, int64_t i, int deg, const Ca
   for (int k = 0; k < 11; ++k) if (!std::isfinite(*raw[k])) return g;
   const T mx = (T)*raw[0], my = (T)*raw[1], mz = (T)*raw[2];
   // O1 activations: scale = exp(log-scale), unit quaternion, rotation matrix
-  for (int k = 0; k < 3; ++k) g.s[k] = exp_cw((T)*raw[3 + k]);
+  for (int k = 0; k < 3; ++k) g.s[k] = exp_t((T)*raw[3 + k]);
   const T qw = (T)*raw[6], qx = (T)*raw[7], qy = (T)*raw[8], qz = (T)*raw[9];
   T ss = qw * qw + qx * qx;
   ss = ss + qy * qy;
@@ -284,7 +295,7 @@ Proj<T> project_one(const float* P, int64_t stride, int64_t i, int deg, const Ca
   if (x0 > x1 || y0 > y1) return g;
   g.px0 = (int)x0; g.px1 = (int)x1; g.py0 = (int)y0; g.py1 = (int)y1;
   // O1 opacity = sigmoid(logit)
-  g.o = (T)1 / ((T)1 + exp_cw(-(T)*raw[10]));
+  g.o = (T)1 / ((T)1 + exp_t(-(T)*raw[10]));
   // O5 colour from spherical harmonics (evaluated in double)
   const int K = (deg + 1) * (deg + 1);
   Dual3 dd[3];
@@ -409,10 +420,28 @@ PixelResult<TD, TV> composite_pixel(const std::vector<Proj<TD>>& pd, const std::
   return res;
 }
 
+// The pixels a call covers: the window [x0, x1) x [y0, y1), every row_step-th
+// row of it. The whole image by default. Restricting the pixels changes no
+// pixel's value: each is composited on its own.
+struct PixelSet {
+  int x0, y0, x1, y1, row_step;
+};
+PixelSet pixel_set(const int32_t* win, int width, int height) {
+  PixelSet s{0, 0, width, height, 1};
+  if (win) {
+    s.x0 = std::max(0, win[0]);
+    s.y0 = std::max(0, win[1]);
+    s.x1 = std::min(width, win[2]);
+    s.y1 = std::min(height, win[3]);
+    s.row_step = std::max(1, win[4]);
+  }
+  return s;
+}
+
 template <class TD, class TV>
 void render_view(const float* P, int64_t n, int64_t stride, int deg, const float* camf, int width, int height,
                  float znear, const float* bg, bool prefilter, double* rgb, double* depth, double* alpha,
-                 double* tfinal, int32_t* ncomp, double* margin) {
+                 double* tfinal, int32_t* ncomp, double* margin, const PixelSet& ps) {
   Cam<float> c32 = make_cam<float>(camf, width, height);
   std::vector<Proj<float>> p32 = project_all<float>(P, n, stride, deg, c32, znear);
   std::vector<int64_t> order = depth_order(p32);
@@ -438,8 +467,8 @@ void render_view(const float* P, int64_t n, int64_t stride, int deg, const float
   }
   const int64_t HW = (int64_t)width * height;
 #pragma omp parallel for schedule(dynamic, 1)
-  for (int py = 0; py < height; ++py) {
-    for (int px = 0; px < width; ++px) {
+  for (int py = ps.y0; py < ps.y1; py += ps.row_step) {
+    for (int px = ps.x0; px < ps.x1; ++px) {
       PixelResult<TD, TV> r = composite_pixel<TD, TV>(*pd, *pv, order, p32, prefilter, px, py, bg, nullptr);
       int64_t o = (int64_t)py * width + px;
       for (int ch = 0; ch < 3; ++ch) rgb[ch * HW + o] = (double)r.rgb[ch];
@@ -459,8 +488,15 @@ void render_view(const float* P, int64_t n, int64_t stride, int deg, const float
 enum { G2_U = 0, G2_V, G2_A, G2_B, G2_C, G2_O, G2_R, G2_G, G2_BL, G2_Z, G2_N };
 
 // Chain rule from the per-Gaussian screen-space gradients to the parameters.
+// With gcam (not null), also adds this Gaussian's part of the gradient with
+// respect to the view's camera: gcam[0..8] = dL/dR (row-major), gcam[9..11] =
+// dL/dt, for the world-to-camera transform x_cam = R x + t. R enters through
+// the camera-space mean, through T = J R (the screen covariance J R Sigma
+// R^T J^T) and, for view-dependent colour, through the camera centre -R^T t;
+// t through the mean and the centre.
 void project_backward_one(const float* P, int64_t stride, int64_t i, int deg, const Cam<double>& cam,
-                          const Proj<double>& g, const double* g2, double* grad, int64_t gstride) {
+                          const Proj<double>& g, const double* g2, double* grad, int64_t gstride,
+                          double* gcam = nullptr) {
   const double gu = g2[G2_U], gv = g2[G2_V], gA = g2[G2_A], gB = g2[G2_B], gC = g2[G2_C];
   const double gz = g2[G2_Z];
   double gcol[3] = {g2[G2_R], g2[G2_G], g2[G2_BL]};
@@ -484,10 +520,12 @@ void project_backward_one(const float* P, int64_t stride, int64_t i, int deg, co
     }
   }
   double gmean[3] = {0, 0, 0};
+  double gview[3] = {0, 0, 0};   // dL/dv through the colour, v = mean - campos
   if (deg > 0) {
     // d = v/|v|, v = mean - campos:  dL/dv = (I - d d^T) dL/dd / |v|
     double dot = g.dir[0] * gdir[0] + g.dir[1] * gdir[1] + g.dir[2] * gdir[2];
-    for (int j = 0; j < 3; ++j) gmean[j] += (gdir[j] - g.dir[j] * dot) / g.dnorm;
+    for (int j = 0; j < 3; ++j) gview[j] = (gdir[j] - g.dir[j] * dot) / g.dnorm;
+    for (int j = 0; j < 3; ++j) gmean[j] += gview[j];
   }
   // conic (A, B, C) = (c, -b, a) / det,  det = a c - b^2
   const double a = g.a, b = g.b, c = g.c, det = g.det, d2 = det * det;
@@ -548,6 +586,28 @@ void project_backward_one(const float* P, int64_t stride, int64_t i, int deg, co
   // t = W mean + t_cw
   for (int j = 0; j < 3; ++j) gmean[j] += W[0 * 3 + j] * gtx + W[1 * 3 + j] * gty + W[2 * 3 + j] * gtz;
   for (int j = 0; j < 3; ++j) grad[j * gstride + i] += gmean[j];
+  if (gcam) {
+    const double mu[3] = {(double)P[0 * stride + i], (double)P[1 * stride + i], (double)P[2 * stride + i]};
+    const double gt[3] = {gtx, gty, gtz};
+    // x_cam = W mu + t_cw
+    for (int r = 0; r < 3; ++r) {
+      for (int k = 0; k < 3; ++k) gcam[r * 3 + k] += gt[r] * mu[k];
+      gcam[9 + r] += gt[r];
+    }
+    // T = J W with J = [[J00, 0, J02], [0, J11, J12]]: dL/dW = J^T dL/dT
+    for (int k = 0; k < 3; ++k) {
+      gcam[0 * 3 + k] += g.J00 * gT0[k];
+      gcam[1 * 3 + k] += g.J11 * gT1[k];
+      gcam[2 * 3 + k] += g.J02 * gT0[k] + g.J12 * gT1[k];
+    }
+    // campos = -W^T t_cw and v = mu - campos: dL/dcampos = -gview
+    for (int r = 0; r < 3; ++r) {
+      for (int k = 0; k < 3; ++k) gcam[r * 3 + k] += gview[k] * cam.t[r];
+      double s = 0.0;
+      for (int k = 0; k < 3; ++k) s += W[r * 3 + k] * gview[k];
+      gcam[9 + r] += s;
+    }
+  }
   // Sigma = M M^T: dL/dM = (gS + gS^T) M
   double gM[9];
   for (int r = 0; r < 3; ++r)
@@ -581,7 +641,8 @@ void project_backward_one(const float* P, int64_t stride, int64_t i, int deg, co
 // with `splats32` the compositing values are the FP32 projection's.
 void blend_backward_view(const float* P, int64_t n, int64_t stride, int deg, const float* camf, int width, int height,
                          float znear, const float* bg, const float* grgb, const float* gdepth, const float* galpha,
-                         bool pinned, bool splats32, std::vector<double>& g2out, std::vector<Proj<double>>& p64out) {
+                         bool pinned, bool splats32, std::vector<double>& g2out, std::vector<Proj<double>>& p64out,
+                         const PixelSet& ps) {
   Cam<float> c32 = make_cam<float>(camf, width, height);
   Cam<double> c64 = make_cam<double>(camf, width, height);
   std::vector<Proj<float>> p32 = project_all<float>(P, n, stride, deg, c32, znear);
@@ -613,8 +674,8 @@ void blend_backward_view(const float* P, int64_t n, int64_t stride, int deg, con
     std::vector<double>& mine = acc[omp_get_thread_num()];
     std::vector<Composited> trace;
 #pragma omp for schedule(dynamic, 1)
-    for (int py = 0; py < height; ++py) {
-      for (int px = 0; px < width; ++px) {
+    for (int py = ps.y0; py < ps.y1; py += ps.row_step) {
+      for (int px = ps.x0; px < ps.x1; ++px) {
         trace.clear();
         double Tfin;
         if (pinned) {
@@ -673,9 +734,24 @@ int orc_num_threads(int n) {
   return omp_get_max_threads();
 }
 
-// Own FP32 exponential, exposed for its accuracy test.
-void orc_exp32(const float* x, float* y, int64_t n) {
-  for (int64_t i = 0; i < n; ++i) y[i] = exp_cw(x[i]);
+// The FP32-mode exponential and, if tie is not null, the relative distance
+// of the long double exp from the nearest float rounding midpoint.
+void orc_exp32(const float* x, float* y, double* tie, int64_t n) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    y[i] = exp32(x[i]);
+    if (tie) tie[i] = exp32_tie_distance(x[i]);
+  }
+}
+
+// The FP32-mode activations (O1): scale = exp(log-scale) and opacity =
+// 1 / (1 + exp(-logit)) in float, element by element.
+void orc_activations(const float* logscale, const float* logit, float* scale, float* opacity, int64_t n) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    if (scale) scale[i] = exp32(logscale[i]);
+    if (opacity) opacity[i] = 1.0f / (1.0f + exp32(-logit[i]));
+  }
 }
 
 // Real SH basis values Y_k(dir) for k < (deg+1)^2, dirs unit vectors [n][3].
@@ -757,15 +833,17 @@ int orc_tile_list(const float* params, int64_t n, int64_t stride, int deg, int n
 // Brute-force render of one view. mode 0: FP32; 1: FP64 values with FP32
 // decisions; 2: FP64 values and decisions. prefilter skips pairs outside the
 // Gaussian's FP32 pixel rectangle (exact by containment; modes 0 and 1 only).
+// window (x0, y0, x1, y1, row_step) or null: only those pixels are written.
 int orc_render(int mode, int prefilter, const float* params, int64_t n, int64_t stride, int deg, const float* cam,
                int width, int height, float znear, const float* bg, double* rgb, double* depth, double* alpha,
-               double* tfinal, int32_t* ncomp, double* margin) {
+               double* tfinal, int32_t* ncomp, double* margin, const int32_t* window) {
+  const PixelSet ps = pixel_set(window, width, height);
   if (mode == 0)
-    render_view<float, float>(params, n, stride, deg, cam, width, height, znear, bg, prefilter != 0, rgb, depth, alpha, tfinal, ncomp, margin);
+    render_view<float, float>(params, n, stride, deg, cam, width, height, znear, bg, prefilter != 0, rgb, depth, alpha, tfinal, ncomp, margin, ps);
   else if (mode == 1)
-    render_view<float, double>(params, n, stride, deg, cam, width, height, znear, bg, prefilter != 0, rgb, depth, alpha, tfinal, ncomp, margin);
+    render_view<float, double>(params, n, stride, deg, cam, width, height, znear, bg, prefilter != 0, rgb, depth, alpha, tfinal, ncomp, margin, ps);
   else if (mode == 2)
-    render_view<double, double>(params, n, stride, deg, cam, width, height, znear, bg, false, rgb, depth, alpha, tfinal, ncomp, margin);
+    render_view<double, double>(params, n, stride, deg, cam, width, height, znear, bg, false, rgb, depth, alpha, tfinal, ncomp, margin, ps);
   else return -1;
   return 0;
 }
@@ -777,20 +855,29 @@ int orc_render(int mode, int prefilter, const float* params, int64_t n, int64_t 
 // img_off[v] (pixels) in grgb ([3][H][W] per view), gdepth and galpha
 // ([H][W] per view). grad[P][n] is overwritten. If g2 is not null it
 // receives the screen-space gradients [V][n][10] (u v A B C o r g b z).
+// windows ([V][5] as orc_render's window, or null): only those pixels are
+// walked, as if the upstream gradient were zero elsewhere. gcam ([V][12] or
+// null) receives each view's camera gradient: dL/dR row-major, then dL/dt.
 int orc_backward(int pinned, const float* params, int64_t n, int64_t stride, int deg, int num_views,
                  const float* cams, const int32_t* wh, float znear, const float* bg, const float* grgb,
-                 const float* gdepth, const float* galpha, double* grad, double* g2) {
+                 const float* gdepth, const float* galpha, double* grad, double* g2, const int32_t* windows,
+                 double* gcam) {
   const int P = 11 + 3 * (deg + 1) * (deg + 1);
   for (int64_t k = 0; k < (int64_t)P * n; ++k) grad[k] = 0.0;
+  if (gcam)
+    for (int k = 0; k < 12 * num_views; ++k) gcam[k] = 0.0;
   int64_t off = 0;
   for (int v = 0; v < num_views; ++v) {
     const int W = wh[2 * v], H = wh[2 * v + 1];
     std::vector<double> g2v;
     std::vector<Proj<double>> p64;
     blend_backward_view(params, n, stride, deg, cams + 16 * v, W, H, znear, bg, grgb + 3 * off, gdepth + off,
-                        galpha + off, pinned != 0, pinned == 2, g2v, p64);
+                        galpha + off, pinned != 0, pinned == 2, g2v, p64,
+                        pixel_set(windows ? windows + 5 * v : nullptr, W, H));
     if (g2) std::memcpy(g2 + (size_t)v * n * G2_N, g2v.data(), sizeof(double) * n * G2_N);
     Cam<double> c64 = make_cam<double>(cams + 16 * v, W, H);
+    const int nt = omp_get_max_threads();
+    std::vector<double> gc((size_t)nt * 12, 0.0);
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
       if (!p64[i].vis) continue;
@@ -798,8 +885,12 @@ int orc_backward(int pinned, const float* params, int64_t n, int64_t stride, int
       bool any = false;
       for (int k = 0; k < G2_N; ++k) any = any || gi[k] != 0.0;
       if (!any) continue;
-      project_backward_one(params, stride, i, deg, c64, p64[i], gi, grad, n);
+      project_backward_one(params, stride, i, deg, c64, p64[i], gi, grad, n,
+                           gcam ? &gc[(size_t)omp_get_thread_num() * 12] : nullptr);
     }
+    if (gcam)
+      for (int t = 0; t < nt; ++t)
+        for (int k = 0; k < 12; ++k) gcam[v * 12 + k] += gc[(size_t)t * 12 + k];
     off += (int64_t)W * H;
   }
   return 0;

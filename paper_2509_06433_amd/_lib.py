@@ -22,7 +22,12 @@ STATUS_NAMES = {0: "GSR_OK", -1: "GSR_ERR_INVALID", -2: "GSR_ERR_OOM", -3: "GSR_
 EXPORTED = sorted(["gsr_create", "gsr_destroy", "gsr_render", "gsr_render1", "gsr_render_backward", "gsr_loss_l1",
                    "gsr_adam_step", "gsr_query_status", "gsr_copy_instances", "gsr_copy_splats",
                    "gsr_count_work", "gsr_set_profiling", "gsr_get_profile", "gsr_last_hip_error",
-                   "gsr_status_string", "gsr_mapping_iteration", "gsr_mapping_status"])
+                   "gsr_status_string", "gsr_mapping_iteration", "gsr_mapping_status", "gsr_activations",
+                   "gsr_render_backward_pose", "gsr_densify",
+                   "gsr_ipc_export_memory", "gsr_ipc_open_memory", "gsr_ipc_close_memory", "gsr_ipc_event_create",
+                   "gsr_ipc_event_open", "gsr_ipc_event_record", "gsr_ipc_event_wait", "gsr_ipc_event_destroy",
+                   # achievable-peak probes (include/gsr_peaks.h)
+                   "gsr_peak_copy", "gsr_peak_valu", "gsr_peak_exp", "gsr_peak_lds"])
 
 STAGES = ["project", "depth_sort", "scan", "emit", "tile_sort", "ranges", "blend_fwd", "loss", "blend_bwd",
           "project_bwd", "adam", "zero", "blend", "tile_depth"]
@@ -41,7 +46,8 @@ class gsr_options(ctypes.Structure):
     _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("batch_depth", ctypes.c_int32),
                 ("bg", ctypes.c_float * 3), ("znear", ctypes.c_float), ("pixels_per_thread", ctypes.c_int32),
                 ("tile_order", ctypes.c_int32), ("chunk_len", ctypes.c_int32), ("max_chunks", ctypes.c_int32),
-                ("fuse_blend", ctypes.c_int32), ("depth_sort", ctypes.c_int32)]
+                ("fuse_blend", ctypes.c_int32), ("depth_sort", ctypes.c_int32),
+                ("backward_schedule", ctypes.c_int32)]
 
 
 class gsr_camera(ctypes.Structure):
@@ -65,6 +71,15 @@ class gsr_adam(ctypes.Structure):
                 ("step", ctypes.c_int32)]
 
 
+class gsr_densify_options(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_int32), ("alpha_below", ctypes.c_float), ("depth_min", ctypes.c_float),
+                ("depth_max", ctypes.c_float), ("scale_factor", ctypes.c_float), ("opacity_logit", ctypes.c_float)]
+
+
+class gsr_ipc_handle(ctypes.Structure):
+    _fields_ = [("bytes", ctypes.c_ubyte * 64)]
+
+
 class gsr_mapping_stats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int64), ("skipped", ctypes.c_int64), ("captures", ctypes.c_int64),
                 ("capacity", ctypes.c_int64), ("last_instances", ctypes.c_int64), ("adam_steps", ctypes.c_int64)]
@@ -86,12 +101,15 @@ def load():
             "gsr_destroy": ([vp], None),
             "gsr_render": ([vp, P(gsr_gaussians), i32, P(gsr_camera), P(gsr_image), vp], ctypes.c_int),
             "gsr_render1": ([vp, P(gsr_gaussians), P(gsr_camera), P(gsr_image), vp], ctypes.c_int),
+            "gsr_render_backward_pose": ([vp, P(gsr_gaussians), i32, P(gsr_camera), P(gsr_image), vp, vp, vp, vp],
+                                         ctypes.c_int),
             "gsr_render_backward": ([vp, P(gsr_gaussians), i32, P(gsr_camera), P(gsr_image), vp, vp],
                                     ctypes.c_int),
             "gsr_loss_l1": ([vp, i32, P(gsr_camera), P(gsr_image), P(gsr_image), f32, P(gsr_image), vp, vp],
                             ctypes.c_int),
             "gsr_adam_step": ([vp, vp, vp, vp, vp, i64, i64, i32, P(f32), f32, f32, f32, i32, vp], ctypes.c_int),
-            "gsr_query_status": ([vp, P(i64), P(i64), P(i64)], ctypes.c_int),
+            "gsr_query_status": ([vp, P(i64), P(i64), P(i64), P(i64)], ctypes.c_int),
+            "gsr_activations": ([vp, P(gsr_gaussians), vp, vp, vp], ctypes.c_int),
             "gsr_copy_instances": ([vp, P(ctypes.c_uint32), P(ctypes.c_uint32), i64, P(i64)], ctypes.c_int),
             "gsr_copy_splats": ([vp, i32, P(f32), i64], ctypes.c_int),
             "gsr_count_work": ([vp, P(i64), P(i64), i32], ctypes.c_int),
@@ -102,6 +120,20 @@ def load():
             "gsr_mapping_iteration": ([vp, vp, i64, i64, i32, i32, P(gsr_camera), P(gsr_image), P(gsr_image), f32,
                                        vp, vp, P(gsr_adam), vp], ctypes.c_int),
             "gsr_mapping_status": ([vp, P(gsr_mapping_stats)], ctypes.c_int),
+            "gsr_densify": ([vp, vp, i64, i64, i32, P(gsr_camera), vp, vp, vp, P(gsr_densify_options), P(i64),
+                             P(i64), vp], ctypes.c_int),
+            "gsr_ipc_export_memory": ([vp, P(gsr_ipc_handle), P(i64), P(i64)], ctypes.c_int),
+            "gsr_ipc_open_memory": ([P(gsr_ipc_handle), i64, P(vp), P(vp)], ctypes.c_int),
+            "gsr_ipc_close_memory": ([vp], ctypes.c_int),
+            "gsr_ipc_event_create": ([P(vp), P(gsr_ipc_handle)], ctypes.c_int),
+            "gsr_ipc_event_open": ([P(gsr_ipc_handle), P(vp)], ctypes.c_int),
+            "gsr_ipc_event_record": ([vp, vp], ctypes.c_int),
+            "gsr_ipc_event_wait": ([vp, vp], ctypes.c_int),
+            "gsr_ipc_event_destroy": ([vp], ctypes.c_int),
+            "gsr_peak_copy": ([i64, i32, vp, P(ctypes.c_double)], ctypes.c_int),
+            "gsr_peak_valu": ([i32, vp, P(ctypes.c_double)], ctypes.c_int),
+            "gsr_peak_exp": ([i32, vp, P(ctypes.c_double)], ctypes.c_int),
+            "gsr_peak_lds": ([i32, vp, P(ctypes.c_double)], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -143,15 +175,65 @@ def _cams(cams):
     return arr
 
 
-def _images(imgs):
+def _check_tensor(t, shape, name, device=None):
+    """A device buffer handed to the library as a raw pointer: it must be a CUDA
+    float32 tensor, contiguous, of exactly `shape` (and on `device` if given),
+    or the kernels would read or write outside it."""
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name} must be a torch tensor")
+    if t.dtype != torch.float32:
+        raise ValueError(f"{name} must be float32, got {t.dtype}")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA tensor")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+def _check_out(t, shape, name, device=None):
+    if t is not None:
+        _check_tensor(t, shape, name, device)
+
+
+def _cam_hw(c):
+    return (int(c.height), int(c.width))
+
+
+def _images(imgs, cams, name, optional=(), device=None):
+    """Descriptors of one (rgb [3,H,W], depth [H,W], alpha [H,W]) triple per camera;
+    planes named in `optional` ("rgb", "depth", "alpha") may be None (NULL)."""
+    imgs = list(imgs)
+    if len(imgs) != len(cams):
+        raise ValueError(f"{name}: {len(imgs)} images for {len(cams)} cameras")
     arr = (gsr_image * len(imgs))()
-    for i, (rgb, depth, alpha) in enumerate(imgs):
-        arr[i] = gsr_image(_ptr(rgb), _ptr(depth), _ptr(alpha))
+    for i, (im, cam) in enumerate(zip(imgs, cams)):
+        if len(im) != 3:
+            raise ValueError(f"{name}[{i}] must be (rgb, depth, alpha)")
+        H, W = _cam_hw(cam)
+        for plane, t, shape in zip(("rgb", "depth", "alpha"), im, ((3, H, W), (H, W), (H, W))):
+            if t is None:
+                if plane not in optional:
+                    raise ValueError(f"{name}[{i}].{plane} is required")
+                continue
+            _check_tensor(t, shape, f"{name}[{i}].{plane}", device)
+        arr[i] = gsr_image(_ptr(im[0]), _ptr(im[1]), _ptr(im[2]))
     return arr
 
 
+def _check_like_params(t, params, name):
+    """A gradient or optimiser-state tensor laid out like params (same shape and plane stride)."""
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float32 or not t.is_cuda or t.device != params.device:
+        raise ValueError(f"{name} must be a float32 tensor on {params.device}")
+    if t.shape != params.shape or t.stride() != params.stride():
+        raise ValueError(f"{name} must match params in shape and stride")
+
+
 def _gauss(params: torch.Tensor, sh_degree: int, num=None, stride=None) -> gsr_gaussians:
-    if params.dtype != torch.float32 or not params.is_cuda or params.dim() != 2:
+    if not isinstance(params, torch.Tensor) or params.dtype != torch.float32 or not params.is_cuda \
+            or params.dim() != 2:
         raise ValueError("params must be a CUDA float32 tensor [P, N]")
     if params.stride(1) != 1:
         raise ValueError("params planes must be contiguous")
@@ -171,9 +253,9 @@ def _check(ctx, fn, rc):
 # --- one wrapper per C entry point ------------------------------------------
 
 def gsr_create(tile_w=16, tile_h=16, batch_depth=0, bg=(0.0, 0.0, 0.0), znear=0.2, pixels_per_thread=0,
-               tile_order=0, chunk_len=0, max_chunks=0, fuse_blend=0, depth_sort=0):
+               tile_order=0, chunk_len=0, max_chunks=0, fuse_blend=0, depth_sort=0, backward_schedule=0):
     opt = gsr_options(tile_w, tile_h, batch_depth, (ctypes.c_float * 3)(*bg), znear, pixels_per_thread, tile_order,
-                      chunk_len, max_chunks, fuse_blend, depth_sort)
+                      chunk_len, max_chunks, fuse_blend, depth_sort, backward_schedule)
     h = ctypes.c_void_p()
     _check(None, "gsr_create", load().gsr_create(ctypes.byref(h), ctypes.byref(opt)))
     return h
@@ -186,38 +268,68 @@ def gsr_destroy(ctx):
 def gsr_render(ctx, params, sh_degree, cams, outs, stream=None):
     """outs: list of (rgb [3,H,W], depth [H,W], alpha [H,W]) CUDA float32 tensors, written."""
     g = _gauss(params, sh_degree)
-    _check(ctx, "gsr_render", load().gsr_render(ctx, ctypes.byref(g), len(cams), _cams(cams), _images(outs),
-                                                _stream(stream)))
+    ims = _images(outs, cams, "outs", device=params.device)
+    _check(ctx, "gsr_render", load().gsr_render(ctx, ctypes.byref(g), len(cams), _cams(cams), ims, _stream(stream)))
 
 
 def gsr_render1(ctx, params, sh_degree, cam, out, stream=None):
     g = _gauss(params, sh_degree)
-    _check(ctx, "gsr_render1", load().gsr_render1(ctx, ctypes.byref(g), _cams([cam]), _images([out]),
-                                                  _stream(stream)))
+    ims = _images([out], [cam], "out", device=params.device)
+    _check(ctx, "gsr_render1", load().gsr_render1(ctx, ctypes.byref(g), _cams([cam]), ims, _stream(stream)))
 
 
 def gsr_render_backward(ctx, params, sh_degree, cams, grads, grad_params, stream=None):
     """grads: list of (dL/drgb, dL/ddepth, dL/dalpha), entries may be None. grad_params += dL/dparams."""
     g = _gauss(params, sh_degree)
-    if grad_params.shape != params.shape or grad_params.stride() != params.stride():
-        raise ValueError("grad_params must match params in shape and stride")
+    _check_like_params(grad_params, params, "grad_params")
+    ims = _images(grads, cams, "grads", optional=("rgb", "depth", "alpha"), device=params.device)
     _check(ctx, "gsr_render_backward",
-           load().gsr_render_backward(ctx, ctypes.byref(g), len(cams), _cams(cams), _images(grads),
-                                      _ptr(grad_params), _stream(stream)))
+           load().gsr_render_backward(ctx, ctypes.byref(g), len(cams), _cams(cams), ims, _ptr(grad_params),
+                                      _stream(stream)))
+
+
+def gsr_render_backward_pose(ctx, params, sh_degree, cams, grads, grad_cams, grad_params=None, grad_twist=None,
+                             stream=None):
+    """Backward with camera gradients: grad_cams [V, 12] (CUDA float64) += dL/dR (row-major), dL/dt per
+    view; grad_twist [V, 6] (float64) or None += the left-perturbation gradient; grad_params like
+    params or None."""
+    g = _gauss(params, sh_degree)
+    if grad_params is not None:
+        _check_like_params(grad_params, params, "grad_params")
+    nv = len(cams)
+    for name, t, w in (("grad_cams", grad_cams, 12), ("grad_twist", grad_twist, 6)):
+        if t is None and name == "grad_twist":
+            continue
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or t.device != params.device \
+                or not t.is_contiguous() or tuple(t.shape) != (nv, w):
+            raise ValueError(f"{name} must be a contiguous float64 tensor [{nv}, {w}] on {params.device}")
+    ims = _images(grads, cams, "grads", optional=("rgb", "depth", "alpha"), device=params.device)
+    _check(ctx, "gsr_render_backward_pose",
+           load().gsr_render_backward_pose(ctx, ctypes.byref(g), nv, _cams(cams), ims, _ptr(grad_params),
+                                           _ptr(grad_cams), _ptr(grad_twist), _stream(stream)))
 
 
 def gsr_loss_l1(ctx, cams, rendered, targets, grads, depth_weight=0.5, loss=None, stream=None):
+    dev = rendered[0][0].device if len(rendered) and isinstance(rendered[0][0], torch.Tensor) else None
+    r = _images(rendered, cams, "rendered", optional=("alpha",), device=dev)
+    t = _images(targets, cams, "targets", optional=("alpha",), device=dev)
+    gi = _images(grads, cams, "grads", optional=("alpha",), device=dev)
+    _check_out(loss, (1,), "loss", dev)
     _check(ctx, "gsr_loss_l1",
-           load().gsr_loss_l1(ctx, len(cams), _cams(cams), _images(rendered), _images(targets),
-                              float(depth_weight), _images(grads), _ptr(loss), _stream(stream)))
+           load().gsr_loss_l1(ctx, len(cams), _cams(cams), r, t, float(depth_weight), gi, _ptr(loss),
+                              _stream(stream)))
 
 
 def gsr_adam_step(ctx, params, grads, m, v, lr_per_plane, step, beta1=0.9, beta2=0.999, eps=1e-15,
                   stream=None):
+    if not isinstance(params, torch.Tensor) or params.dtype != torch.float32 or not params.is_cuda \
+            or params.dim() != 2 or params.stride(1) != 1:
+        raise ValueError("params must be a CUDA float32 tensor [P, N] with contiguous planes")
     P, n = params.shape
-    for t in (grads, m, v):
-        if t.shape != params.shape or t.stride() != params.stride():
-            raise ValueError("Adam tensors must match params in shape and stride")
+    for name, t in (("grads", grads), ("m", m), ("v", v)):
+        _check_like_params(t, params, name)
+    if len(lr_per_plane) != P:
+        raise ValueError("one learning rate per parameter plane")
     lr = (ctypes.c_float * P)(*[float(x) for x in lr_per_plane])
     _check(ctx, "gsr_adam_step",
            load().gsr_adam_step(ctx, _ptr(params), _ptr(grads), _ptr(m), _ptr(v), n, params.stride(0), P, lr,
@@ -225,9 +337,21 @@ def gsr_adam_step(ctx, params, grads, m, v, lr_per_plane, step, beta1=0.9, beta2
 
 
 def gsr_query_status(ctx):
-    a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
-    _check(ctx, "gsr_query_status", load().gsr_query_status(ctx, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
-    return {"instances": a.value, "visible": b.value, "tiles": c.value}
+    a, b, c, d = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(ctx, "gsr_query_status", load().gsr_query_status(ctx, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                                                            ctypes.byref(d)))
+    return {"instances": a.value, "visible": b.value, "tiles": c.value, "nonfinite_culled": d.value}
+
+
+def gsr_activations(ctx, params, sh_degree, scale=None, opacity=None, stream=None):
+    """scale [3, N] and opacity [N] (CUDA float32, contiguous; either may be None) = the activations
+    the projection uses for params [P, N]."""
+    g = _gauss(params, sh_degree)
+    n = params.shape[1]
+    _check_out(scale, (3, n), "scale")
+    _check_out(opacity, (n,), "opacity")
+    _check(ctx, "gsr_activations", load().gsr_activations(ctx, ctypes.byref(g), _ptr(scale), _ptr(opacity),
+                                                          _stream(stream)))
 
 
 def gsr_copy_instances(ctx):
@@ -279,16 +403,19 @@ def gsr_get_profile(ctx, reset=True):
 
 def gsr_mapping_iteration(ctx, params, sh_degree, cams, outs, targets, depth_weight, grad_params, loss=None,
                           adam=None, stream=None):
-    """One graph-replayed mapping iteration. adam: None or a dict with m, v (tensors like params),
-    lr (per-plane list), beta1, beta2, eps, step (0 = continue the device count)."""
+    """One graph-replayed mapping iteration. targets: per view (rgb [3,H,W], depth [H,W]).
+    adam: None or a dict with m, v (tensors like params), lr (per-plane list), beta1, beta2, eps,
+    step (0 = continue the device count)."""
     g = _gauss(params, sh_degree)
-    if grad_params.shape != params.shape or grad_params.stride() != params.stride():
-        raise ValueError("grad_params must match params in shape and stride")
+    _check_like_params(grad_params, params, "grad_params")
+    dev = params.device
+    ims = _images(outs, cams, "outs", device=dev)
+    tg = _images([(t[0], t[1], None) for t in targets], cams, "targets", optional=("alpha",), device=dev)
+    _check_out(loss, (1,), "loss", dev)
     a = None
     if adam is not None:
-        for t in (adam["m"], adam["v"]):
-            if t.shape != params.shape or t.stride() != params.stride():
-                raise ValueError("Adam tensors must match params in shape and stride")
+        for name in ("m", "v"):
+            _check_like_params(adam[name], params, "adam." + name)
         lr = adam["lr"]
         if len(lr) != params.shape[0]:
             raise ValueError("one learning rate per parameter plane")
@@ -296,16 +423,69 @@ def gsr_mapping_iteration(ctx, params, sh_degree, cams, outs, targets, depth_wei
         a = gsr_adam(_ptr(adam["m"]), _ptr(adam["v"]), lr_arr, float(adam.get("beta1", 0.9)),
                      float(adam.get("beta2", 0.999)), float(adam.get("eps", 1e-15)), int(adam.get("step", 0)))
     _check(ctx, "gsr_mapping_iteration",
-           load().gsr_mapping_iteration(ctx, g.params, g.num, g.stride, sh_degree, len(cams), _cams(cams),
-                                        _images(outs), _images([(t[0], t[1], None) for t in targets]),
+           load().gsr_mapping_iteration(ctx, g.params, g.num, g.stride, sh_degree, len(cams), _cams(cams), ims, tg,
                                         float(depth_weight), _ptr(grad_params), _ptr(loss),
                                         ctypes.byref(a) if a is not None else None, _stream(stream)))
+
+
+def gsr_densify(ctx, params, num, sh_degree, cam, rgb, depth, coverage=None, step=4, alpha_below=0.5,
+                depth_min=0.2, depth_max=100.0, scale_factor=1.0, opacity_logit=0.0, stream=None):
+    """Append Gaussians seeded from an RGB-D keyframe to the map buffer params [P, stride] (CUDA
+    float32, contiguous; its first num Gaussians are the map) at indices num, num + 1, ...;
+    returns (appended, wanted)."""
+    if not isinstance(params, torch.Tensor) or params.dtype != torch.float32 or not params.is_cuda \
+            or params.dim() != 2 or params.stride(1) != 1:
+        raise ValueError("params must be a CUDA float32 tensor [P, stride] with contiguous planes")
+    if params.shape[0] != 11 + 3 * (sh_degree + 1) ** 2:
+        raise ValueError("params has the wrong number of planes for sh_degree")
+    stride = params.stride(0)
+    if params.shape[1] != stride:
+        raise ValueError("params must be the whole [P, stride] buffer (new Gaussians go up to index stride - 1)")
+    if not (0 <= num <= stride):
+        raise ValueError("num must lie within params")
+    H, W = int(cam.height), int(cam.width)
+    _check_tensor(rgb, (3, H, W), "rgb", params.device)
+    _check_tensor(depth, (H, W), "depth", params.device)
+    _check_out(coverage, (H, W), "coverage", params.device)
+    opt = gsr_densify_options(int(step), float(alpha_below), float(depth_min), float(depth_max), float(scale_factor),
+                              float(opacity_logit))
+    app, want = ctypes.c_int64(), ctypes.c_int64()
+    _check(ctx, "gsr_densify",
+           load().gsr_densify(ctx, _ptr(params), int(num), int(stride), int(sh_degree), _cams([cam]),
+                              _ptr(rgb), _ptr(depth), _ptr(coverage), ctypes.byref(opt), ctypes.byref(app),
+                              ctypes.byref(want), _stream(stream)))
+    return app.value, want.value
 
 
 def gsr_mapping_status(ctx):
     s = gsr_mapping_stats()
     _check(ctx, "gsr_mapping_status", load().gsr_mapping_status(ctx, ctypes.byref(s)))
     return {k: getattr(s, k) for k, _ in gsr_mapping_stats._fields_}
+
+
+def gsr_ipc_export_memory(t):
+    """(handle bytes, offset, allocation bytes) of the CUDA tensor t's device allocation."""
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError("a CUDA tensor is required")
+    h, off, size = gsr_ipc_handle(), ctypes.c_int64(), ctypes.c_int64()
+    _check(None, "gsr_ipc_export_memory",
+           load().gsr_ipc_export_memory(_ptr(t), ctypes.byref(h), ctypes.byref(off), ctypes.byref(size)))
+    return bytes(h.bytes), off.value, size.value
+
+
+def gsr_ipc_event_create():
+    """(event handle as an int, its 64 handle bytes)."""
+    ev, h = ctypes.c_void_p(), gsr_ipc_handle()
+    _check(None, "gsr_ipc_event_create", load().gsr_ipc_event_create(ctypes.byref(ev), ctypes.byref(h)))
+    return ev.value, bytes(h.bytes)
+
+
+def gsr_ipc_event_record(event, stream=None):
+    _check(None, "gsr_ipc_event_record", load().gsr_ipc_event_record(ctypes.c_void_p(event), _stream(stream)))
+
+
+def gsr_ipc_event_destroy(event):
+    _check(None, "gsr_ipc_event_destroy", load().gsr_ipc_event_destroy(ctypes.c_void_p(event)))
 
 
 def gsr_status_string(status: int) -> str:

@@ -34,6 +34,9 @@ SOURCES = {
     "sort.hip": [],
     "api.hip": [],
     "iteration.hip": [],
+    "peaks.hip": [],
+    "densify.hip": STRICT,
+    "ipc.hip": [],
 }
 
 

@@ -17,6 +17,7 @@ namespace gsr {
 // has too few tiles to keep every CU busy to the end (measured: 1200 tiles
 // -16 % backward time, 3225 tiles -8 %, 9600 tiles +1 %, 57k tiles +6 %).
 int chunk_len_for(const gsr_ctx* ctx, const RenderPlan& P) {
+  if (ctx->bwd_schedule == 1) return 0;     // the splat-parallel backward walks whole lists
   if (ctx->chunk_len > 0) return ctx->chunk_len;
   if (ctx->chunk_len < 0) return 0;
   return P.ntiles < kAutoChunkTiles ? kAutoChunk : 0;
@@ -58,7 +59,6 @@ int size_render(gsr_ctx* ctx, Buffers& B, RenderPlan& P, const gsr_image* out, h
   const size_t t4 = sizeof(uint32_t) * (size_t)std::max<int64_t>(P.total, 1);
   RET_IF(ensure(ctx, B.views, sizeof(ViewDesc) * nv));
   RET_IF(ensure(ctx, B.images, sizeof(ViewImages) * nv));
-  RET_IF(ensure(ctx, B.images2, sizeof(ViewImages) * nv));
   RET_IF(ensure(ctx, B.splats, sizeof(Splat) * (size_t)std::max<int64_t>(P.total, 1)));
   RET_IF(ensure(ctx, B.rect, sizeof(int4) * (size_t)std::max<int64_t>(P.total, 1)));
   RET_IF(ensure(ctx, B.ntiles, t4));
@@ -73,10 +73,13 @@ int size_render(gsr_ctx* ctx, Buffers& B, RenderPlan& P, const gsr_image* out, h
   RET_IF(ensure(ctx, B.tfinal, sizeof(float) * (size_t)P.npix));
   RET_IF(ensure(ctx, B.last, sizeof(uint32_t) * (size_t)P.npix));
   RET_IF(ensure(ctx, B.tile_last, sizeof(uint32_t) * (size_t)std::max<int64_t>(P.ntiles, 1)));
-  RET_IF(ensure(ctx, B.tile_done, sizeof(uint32_t) * (size_t)std::max<int64_t>(P.ntiles, 1)));
-  if (chunk_len_for(ctx, P) > 0)
-    RET_IF(ensure(ctx, B.ckpt, sizeof(float) * kCkptFields * (size_t)ctx->max_chunks * (size_t)P.npix));
-  RET_IF(ensure(ctx, B.g2, sizeof(float) * G2_N * (size_t)std::max<int64_t>(P.total, 1)));
+  if (!P.forward_only) {
+    RET_IF(ensure(ctx, B.images2, sizeof(ViewImages) * nv));
+    RET_IF(ensure(ctx, B.tile_done, sizeof(uint32_t) * (size_t)std::max<int64_t>(P.ntiles, 1)));
+    if (chunk_len_for(ctx, P) > 0)
+      RET_IF(ensure(ctx, B.ckpt, sizeof(float) * kCkptFields * (size_t)ctx->max_chunks * (size_t)P.npix));
+    RET_IF(ensure(ctx, B.g2, sizeof(float) * G2_N * (size_t)std::max<int64_t>(P.total, 1)));
+  }
   RET_IF(ensure(ctx, B.total, 64));
   RET_IF(ensure(ctx, B.hist, sizeof(uint32_t) * (size_t)radix_scratch_elems(P.total, 32)));
   RET_IF(ensure(ctx, B.partials, 2 * sizeof(uint32_t) * (size_t)scan_partial_elems(P.total)));
@@ -110,7 +113,7 @@ int launch_front(gsr_ctx* ctx, Buffers& B, RenderPlan& P, const float* params, h
     StageTimer tm(ctx, GSR_STAGE_PROJECT, st);
     launch_project(params, P.num, P.stride, P.deg, nv, as<ViewDesc>(B.views), ctx->tile_w, ctx->tile_h, ctx->znear,
                    as<Splat>(B.splats), as<int4>(B.rect), as<uint32_t>(B.ntiles), as<uint32_t>(B.zkey), zhist, zrb,
-                   zpasses, st);
+                   zpasses, totals + 4, st);
   }
   CHECK_LAUNCH(ctx);
   uint32_t* zk = as<uint32_t>(B.zkey);
@@ -157,7 +160,7 @@ static bool use_lpt(const gsr_ctx* ctx, const RenderPlan& P) {
 }
 
 static void set_chunking(const gsr_ctx* ctx, Buffers& B, const RenderPlan& P, BlendArgs& ba) {
-  const int cl = chunk_len_for(ctx, P);
+  const int cl = P.forward_only ? 0 : chunk_len_for(ctx, P);
   ba.tile_last = as<uint32_t>(B.tile_last);
   ba.chunk_len = cl;
   ba.max_chunks = cl > 0 ? ctx->max_chunks : 1;
@@ -182,7 +185,7 @@ bool per_tile_depth(const gsr_ctx* ctx, const RenderPlan& P) {
 }
 
 bool use_fused_blend(const gsr_ctx* ctx, const RenderPlan& P) {
-  if (ctx->fuse_blend < 0 || ctx->batch_depth != 0) return false;
+  if (ctx->fuse_blend < 0 || ctx->batch_depth != 0 || ctx->bwd_schedule != 0) return false;
   if (ctx->fuse_blend > 0) return true;
   return chunk_len_for(ctx, P) > 0 && P.ntiles <= ctx->fused_resident;
 }
@@ -290,10 +293,11 @@ int launch_bwd(gsr_ctx* ctx, Buffers& B, const RenderPlan& P, const float* param
   set_chunking(ctx, B, P, ba);
   if (!blend_done) {
     StageTimer tm(ctx, GSR_STAGE_BLEND_BWD, st);
-    launch_blend_backward(ba, ctx->tile_w, ctx->tile_h, ctx->ppt, ctx->batch_depth, st);
+    if (ctx->bwd_schedule == 1) launch_blend_backward_splat(ba, ctx->tile_w, ctx->tile_h, st);
+    else launch_blend_backward(ba, ctx->tile_w, ctx->tile_h, ctx->ppt, ctx->batch_depth, st);
   }
   CHECK_LAUNCH(ctx);
-  {
+  if (grad_params) {
     StageTimer tm(ctx, GSR_STAGE_PROJECT_BWD, st);
     launch_project_backward(params, P.num, P.stride, P.deg, P.nv, as<ViewDesc>(B.views), ctx->znear,
                             as<float>(B.g2), as<uint32_t>(B.ntiles), grad_params, overwrite_grad,
@@ -376,9 +380,48 @@ int backward_impl(gsr_ctx* ctx, const gsr_gaussians* g, int32_t nv, const gsr_ca
   return launch_bwd(ctx, B, P, g->params, grad_params, true, false, st);
 }
 
+int backward_pose_impl(gsr_ctx* ctx, const gsr_gaussians* g, int32_t nv, const gsr_camera* cams,
+                       const gsr_image* grad_out, float* grad_params, double* grad_cams, double* grad_twist,
+                       hipStream_t st) {
+  RET_IF(check_gaussians(g));
+  RET_IF(check_cams(cams, nv));
+  if (!grad_out || !grad_cams) return GSR_ERR_INVALID;
+  const RenderPlan& P = ctx->fw;
+  if (!ctx->have_forward || ctx->fw_params != g->params || P.num != g->num || P.stride != g->stride ||
+      P.deg != g->sh_degree || (int)ctx->fw_cams.size() != nv ||
+      std::memcmp(ctx->fw_cams.data(), cams, sizeof(gsr_camera) * nv) != 0)
+    return GSR_ERR_STATE;
+  ctx->last_stream = st;
+  Buffers& B = ctx->eager;
+  std::vector<ViewImages> ims(nv);
+  for (int v = 0; v < nv; ++v) ims[v] = ViewImages{grad_out[v].rgb, grad_out[v].depth, grad_out[v].alpha};
+  RET_IF(upload(ctx, B.images2.p, ims.data(), sizeof(ViewImages) * nv, st));
+  RET_IF(launch_bwd(ctx, B, P, g->params, grad_params, true, false, st));
+  if (P.total > 0) {
+    launch_pose_backward(g->params, P.num, P.stride, P.deg, P.nv, as<ViewDesc>(B.views), as<float>(B.g2),
+                         as<uint32_t>(B.ntiles), grad_cams, grad_twist, st);
+    CHECK_LAUNCH(ctx);
+  }
+  return GSR_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+int gsr_render_backward_pose(gsr_ctx* ctx, const gsr_gaussians* g, int32_t num_views, const gsr_camera* cams,
+                             const gsr_image* grad_out, float* grad_params, double* grad_cams, double* grad_twist,
+                             void* stream) {
+  if (!ctx) return GSR_ERR_INVALID;
+  try {
+    return backward_pose_impl(ctx, g, num_views, cams, grad_out, grad_params, grad_cams, grad_twist,
+                              (hipStream_t)stream);
+  } catch (const std::bad_alloc&) {
+    return GSR_ERR_OOM;
+  } catch (...) {
+    return GSR_ERR_INVALID;
+  }
+}
 
 int gsr_create(gsr_ctx** out, const gsr_options* opt) {
   if (!out) return GSR_ERR_INVALID;
@@ -426,6 +469,11 @@ int gsr_create(gsr_ctx** out, const gsr_options* opt) {
       return GSR_ERR_UNSUPPORTED;
     }
     ctx->depth_sort = opt->depth_sort;
+    if (opt->backward_schedule < 0 || opt->backward_schedule > 1) {
+      delete ctx;
+      return GSR_ERR_UNSUPPORTED;
+    }
+    ctx->bwd_schedule = opt->backward_schedule;
     for (int k = 0; k < 3; ++k) ctx->bg[k] = opt->bg[k];
     ctx->znear = opt->znear > 0.f ? opt->znear : 0.2f;
   }
@@ -449,7 +497,7 @@ void gsr_destroy(gsr_ctx* ctx) {
   (void)hipDeviceSynchronize();
   destroy_graph(ctx);
   free_buffers(ctx->eager);
-  DevBuf* bufs[] = {&ctx->images3, &ctx->lr, &ctx->splat_out, &ctx->counts};
+  DevBuf* bufs[] = {&ctx->images3, &ctx->lr, &ctx->splat_out, &ctx->counts, &ctx->seed_buf};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   for (int k = 0; k < kSlots; ++k) {
@@ -556,19 +604,27 @@ int gsr_adam_step(gsr_ctx* ctx, float* params, const float* grads, float* m, flo
   return GSR_OK;
 }
 
-int gsr_query_status(gsr_ctx* ctx, int64_t* num_instances, int64_t* num_visible, int64_t* num_tiles) {
+int gsr_query_status(gsr_ctx* ctx, int64_t* num_instances, int64_t* num_visible, int64_t* num_tiles,
+                     int64_t* nonfinite_culled) {
   if (!ctx) return GSR_ERR_INVALID;
   HIP_TRY(ctx, hipStreamSynchronize(ctx->last_stream));
-  int64_t I = 0;
-  if (ctx->q_bufs) {
-    uint32_t t[3] = {0, 0, 0};
-    HIP_TRY(ctx, hipMemcpy(t, ctx->q_bufs->total.p, sizeof(t), hipMemcpyDeviceToHost));
-    if (t[1]) return GSR_ERR_DEVICE;
-    I = std::min<int64_t>((int64_t)t[0], ctx->q_plan->capacity);
-  }
-  if (num_instances) *num_instances = I;
-  if (num_visible) *num_visible = -1;
+  uint32_t t[5] = {0, 0, 0, 0, 0};
+  if (ctx->q_bufs) HIP_TRY(ctx, hipMemcpy(t, ctx->q_bufs->total.p, sizeof(t), hipMemcpyDeviceToHost));
+  if (num_instances) *num_instances = (int64_t)t[0];
+  if (num_visible) *num_visible = (int64_t)t[3];
   if (num_tiles) *num_tiles = ctx->q_plan ? ctx->q_plan->ntiles : 0;
+  if (nonfinite_culled) *nonfinite_culled = (int64_t)t[4];
+  if (t[1]) return GSR_ERR_DEVICE;
+  return GSR_OK;
+}
+
+int gsr_activations(gsr_ctx* ctx, const gsr_gaussians* g, float* scale, float* opacity, void* stream) {
+  if (!ctx) return GSR_ERR_INVALID;
+  RET_IF(check_gaussians(g));
+  hipStream_t st = (hipStream_t)stream;
+  ctx->last_stream = st;
+  launch_activations(g->params, g->num, g->stride, scale, opacity, st);
+  CHECK_LAUNCH(ctx);
   return GSR_OK;
 }
 
@@ -576,7 +632,8 @@ int gsr_copy_instances(gsr_ctx* ctx, uint32_t* tile, uint32_t* gid, int64_t capa
   if (!ctx || !count || capacity < 0) return GSR_ERR_INVALID;
   if (!ctx->q_bufs) return GSR_ERR_STATE;
   int64_t I = 0;
-  RET_IF(gsr_query_status(ctx, &I, nullptr, nullptr));
+  RET_IF(gsr_query_status(ctx, &I, nullptr, nullptr, nullptr));
+  I = std::min<int64_t>(I, ctx->q_plan->capacity);
   *count = I;
   const int64_t m = std::min(capacity, I);
   if (m == 0) return GSR_OK;

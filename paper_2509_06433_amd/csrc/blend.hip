@@ -767,6 +767,145 @@ blend_fused_kernel(BlendArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Splat-parallel backward (a selectable schedule). One wavefront per tile.
+// The tile's list is walked back to front in batches of 64 positions; lane j
+// owns position hi - 1 - j of the batch [lo, hi) and accumulates that
+// Gaussian's gradient over the tile's pixels in registers. The pixels stream
+// through the lanes as a software pipeline: at step t lane j takes pixel
+// t - j, so the pixel meets the batch's Gaussians back to front, and its
+// reverse-walk state (transmittance, suffix) moves one lane up per step by a
+// DPP wave shift. Lane 0 takes a pixel's state from LDS, lane 63 leaves it
+// there for the next batch. The pixels are ordered by their walk length
+// (longest first), so a batch streams only the pixels whose walks reach it.
+// No wave reduction: one set of atomics per (tile, Gaussian).
+// ---------------------------------------------------------------------------
+template <int NPIX>
+struct SplatShared {
+  float4 pix[NPIX];      // per ranked pixel: (x, y sample point, background term of dL/dalpha, last as bits)
+  float4 grad[NPIX];     // per ranked pixel: dL/d(r, g, b, depth)
+  float2 state[NPIX];    // per ranked pixel: (T, S) entering the current batch
+  uint32_t last[NPIX];   // per pixel of the tile, in tile order
+};
+
+__device__ __forceinline__ float lane_shift_up(float x) {
+  // lane i receives lane i - 1's value (wave_shr:1); lane 0 receives 0
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x138, 0xF, 0xF, false));
+}
+
+template <int TW, int TH>
+__global__ void __launch_bounds__(64) blend_backward_splat_kernel(BlendArgs a) {
+  constexpr int NPIX = TW * TH;
+  __shared__ SplatShared<NPIX> sh;
+  const int lane = threadIdx.x;
+  const int tile = a.order ? (int)a.order[blockIdx.x] : (int)blockIdx.x;
+  const uint2 rg = a.ranges[tile];
+  const uint32_t top = min(a.tile_last[tile], rg.y - rg.x);
+  if (top == 0) return;
+  const int view = find_view(a.views, a.num_views, tile);
+  const ViewDesc& V = a.views[view];
+  const int lt = tile - V.tile_offset;
+  const int tx = lt % V.tiles_x, ty = lt / V.tiles_x;
+  const ViewImages gimg = a.images[view];
+  const int64_t HW = (int64_t)V.width * V.height;
+  for (int q = lane; q < NPIX; q += 64) {
+    const int px = tx * TW + q % TW, py = ty * TH + q / TW;
+    sh.last[q] = (px < V.width && py < V.height) ? a.last[V.pix_offset + (int64_t)py * V.width + px] : 0u;
+  }
+  __syncthreads();
+  // rank of every pixel by walk length, longest first (ties by tile order)
+  for (int q = lane; q < NPIX; q += 64) {
+    const uint32_t lq = sh.last[q];
+    int r = 0;
+    for (int o = 0; o < NPIX; ++o) {
+      const uint32_t lo = sh.last[o];
+      r += (lo > lq || (lo == lq && o < q)) ? 1 : 0;
+    }
+    const int px = tx * TW + q % TW, py = ty * TH + q / TW;
+    float T = 1.0f, g0 = 0.0f, g1 = 0.0f, g2 = 0.0f, gd = 0.0f, ga = 0.0f;
+    if (lq > 0) {
+      const int64_t p = (int64_t)py * V.width + px;
+      T = a.tfinal[V.pix_offset + p];
+      if (gimg.rgb) {
+        g0 = gimg.rgb[p];
+        g1 = gimg.rgb[HW + p];
+        g2 = gimg.rgb[2 * HW + p];
+      }
+      if (gimg.depth) gd = gimg.depth[p];
+      if (gimg.alpha) ga = gimg.alpha[p];
+    }
+    const float tb = T * (ga - (g0 * a.bg[0] + g1 * a.bg[1] + g2 * a.bg[2]));
+    sh.pix[r] = make_float4((float)px + 0.5f, (float)py + 0.5f, tb, __uint_as_float(lq));
+    sh.grad[r] = make_float4(g0, g1, g2, gd);
+    sh.state[r] = make_float2(T, 0.0f);
+  }
+  __syncthreads();
+  for (int hi = (int)top; hi > 0; hi -= 64) {
+    const int lo = hi > 64 ? hi - 64 : 0;
+    // pixels whose walk reaches this batch (last > lo): a prefix of the ranking
+    int n = 0;
+    for (int r0 = 0; r0 < NPIX; r0 += 64)
+      n += __popcll(__ballot(__float_as_uint(sh.pix[r0 + lane].w) > (uint32_t)lo));
+    const int pos = hi - 1 - lane;
+    const bool have = pos >= lo;
+    float4 q0 = make_float4(0.f, 0.f, 0.f, 0.f), q1 = q0, q2 = q0;
+    uint32_t sid = 0;
+    if (have) {
+      sid = a.inst_vals[rg.x + pos];
+      const Splat* sp = a.splats + sid;
+      stage_record(sp->w0, sp->w1, sp->w2, q0, q1, q2);
+    }
+    float m[M_N];
+#pragma unroll
+    for (int c = 0; c < M_N; ++c) m[c] = 0.0f;
+    float Tin = 0.0f, Sin = 0.0f;
+    for (int t = 0; t < n + 63; ++t) {
+      const int r = t - lane;
+      const bool valid = r >= 0 && r < n;
+      const int rr = valid ? r : 0;
+      const float4 pa = sh.pix[rr];
+      const float4 pg = sh.grad[rr];
+      float T = Tin, S = Sin;
+      if (lane == 0) {
+        const float2 st = sh.state[rr];
+        T = st.x;
+        S = st.y;
+      }
+      float dx, dy, G, alpha;
+      bool clamped;
+      const bool ok = pair_alpha(q0, q1, pa.x, pa.y, dx, dy, G, alpha, clamped) && valid && have &&
+                      (uint32_t)pos < __float_as_uint(pa.w);
+      reverse_one<false>(ok, alpha, G, clamped, dx, dy, q1, q2, pg.x, pg.y, pg.z, pg.w, pa.z, T, S, m);
+      if (lane == 63 && valid) sh.state[r] = make_float2(T, S);
+      Tin = lane_shift_up(T);
+      Sin = lane_shift_up(S);
+    }
+    if (have) {
+      float g[G2_N];
+      g[G2_U] = 2.0f * q0.z * m[M_X] + q0.w * m[M_Y];
+      g[G2_V] = q0.w * m[M_X] + 2.0f * q1.x * m[M_Y];
+      g[G2_A] = -0.5f * m[M_XX];
+      g[G2_B] = -m[M_XY];
+      g[G2_C] = -0.5f * m[M_YY];
+      g[G2_O] = m[M_O];
+      g[G2_R] = m[M_R];
+      g[G2_G] = m[M_G];
+      g[G2_BL] = m[M_B];
+      g[G2_Z] = m[M_Z];
+      float* dst = a.g2 + (int64_t)sid * G2_N;
+#pragma unroll
+      for (int c = 0; c < G2_N; ++c)
+        if (g[c] != 0.0f) unsafeAtomicAdd(dst + c, g[c]);
+    }
+    __syncthreads();   // lane 63's states reach LDS before the next batch reads them
+  }
+}
+
+template <int TW, int TH>
+void splat_launch(const BlendArgs& a, hipStream_t st) {
+  blend_backward_splat_kernel<TW, TH><<<a.num_tiles, 64, 0, st>>>(a);
+}
+
 template <int TW, int TH>
 void fwd_launch(const BlendArgs& a, int ppt, hipStream_t st) {
   constexpr int P2 = TW * TH >= 128 ? 2 : 1;
@@ -942,6 +1081,14 @@ void launch_blend_backward(const BlendArgs& a, int tile_w, int tile_h, int ppt, 
   else if (tile_w == 16 && tile_h == 8) bwd_launch<16, 8>(a, ppt, depth, st);
   else if (tile_w == 8 && tile_h == 8) bwd_launch<8, 8>(a, ppt, depth, st);
   else if (tile_w == 32 && tile_h == 8) bwd_launch<32, 8>(a, ppt, depth, st);
+}
+
+void launch_blend_backward_splat(const BlendArgs& a, int tile_w, int tile_h, hipStream_t st) {
+  if (a.num_tiles == 0) return;
+  if (tile_w == 16 && tile_h == 16) splat_launch<16, 16>(a, st);
+  else if (tile_w == 16 && tile_h == 8) splat_launch<16, 8>(a, st);
+  else if (tile_w == 8 && tile_h == 8) splat_launch<8, 8>(a, st);
+  else if (tile_w == 32 && tile_h == 8) splat_launch<32, 8>(a, st);
 }
 
 void launch_loss_l1(const ViewDesc* views, const ViewImages* rendered, const ViewImages* target,

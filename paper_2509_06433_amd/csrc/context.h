@@ -22,6 +22,7 @@ inline void note_hip_failure(gsr_ctx* ctx, hipError_t e, const char* expr, const
 struct DevBuf {
   void* p = nullptr;
   size_t cap = 0;
+  bool fixed = false;   // a window of memory the context does not own: never freed or grown
 };
 
 // Pinned staging slots for host->device uploads of small descriptor arrays;
@@ -37,7 +38,8 @@ struct Buffers {
   DevBuf splats, rect, ntiles, zkey, svals, zkey_alt, svals_alt, offsets;
   DevBuf ikeys, ivals, ikeys_alt, ivals_alt;
   DevBuf hist, hist2, partials, ranges, order, tfinal, last, g2;   // hist: depth sort, hist2: tile sort
-  DevBuf total;   // [0] instance count, [1] wait expired, [2] instance overflow, [3] visible splats
+  DevBuf total;   // [0] instance count, [1] wait expired, [2] instance overflow, [3] visible splats,
+                  // [4] Gaussians culled as non-finite or degenerate
   DevBuf tile_last, ckpt;   // per tile: longest walk; per pixel: state at the backward's chunk boundaries
   DevBuf tile_done;         // fused blend: per tile, its forward is done
   DevBuf block_rank;        // emission: first depth rank of every block of output positions
@@ -55,6 +57,7 @@ struct RenderPlan {
   bool plan_ready = false;             // the offsets scan wrote the emission plan
   uint32_t* inst_keys = nullptr;       // sorted instance list
   uint32_t* inst_vals = nullptr;
+  bool forward_only = false;           // no backward follows: no per-chunk state, no gradient scratch
 };
 
 struct GraphState;   // captured mapping iteration
@@ -115,6 +118,7 @@ struct gsr_ctx {
   int fuse_blend = 0;                   // mapping iteration: 0 automatic, 1 fused, -1 two launches
   int64_t fused_resident = 0;           // workgroups of the fused blend launch the device holds at once
   int depth_sort = 0;                   // 0 automatic, 1 per-tile sort after binning, 2 one global sort before
+  int bwd_schedule = 0;                 // blend backward: 0 pixel-parallel, 1 splat-parallel
   float bg[3] = {0.f, 0.f, 0.f};
   float znear = 0.2f;
   int hip_err = 0;
@@ -122,6 +126,7 @@ struct gsr_ctx {
 
   gsr::Buffers eager;                   // buffers of gsr_render / gsr_render_backward
   DevBuf images3, lr, splat_out;
+  DevBuf seed_buf;                      // gsr_densify: seed flags, offsets, scan scratch
   uint32_t* host_total = nullptr;
   void* slots[gsr::kSlots] = {};
   hipEvent_t slot_ev[gsr::kSlots] = {};
@@ -215,6 +220,7 @@ inline void note_hip_failure(gsr_ctx* ctx, hipError_t e, const char* expr, const
 
 inline int ensure(gsr_ctx* ctx, DevBuf& b, size_t bytes) {
   if (bytes <= b.cap) return GSR_OK;
+  if (b.fixed) return GSR_ERR_CAPACITY;
   size_t want = std::max<size_t>(bytes + bytes / 4, 256);
   if (b.p) {
     HIP_TRY(ctx, hipDeviceSynchronize());
@@ -289,33 +295,39 @@ inline int check_cams(const gsr_camera* cams, int32_t num_views) {
   return GSR_OK;
 }
 
+// The descriptor of one view whose tiles start at global tile toff and whose
+// pixels start at poff in the per-pixel scratch.
+inline void fill_view(const gsr_ctx* ctx, const gsr_camera& c, int64_t toff, int64_t poff, ViewDesc& d);
+
 // Per-view descriptors; returns total tiles and pixels.
 inline std::vector<ViewDesc> make_views(const gsr_ctx* ctx, const gsr_camera* cams, int nv, int64_t* tiles,
                                  int64_t* pixels) {
   std::vector<ViewDesc> out(nv);
   int64_t toff = 0, poff = 0;
   for (int v = 0; v < nv; ++v) {
-    const gsr_camera& c = cams[v];
-    ViewDesc& d = out[v];
-    std::memcpy(d.R, c.R, sizeof(d.R));
-    std::memcpy(d.t, c.t, sizeof(d.t));
-    d.fx = c.fx; d.fy = c.fy; d.cx = c.cx; d.cy = c.cy;
-    for (int j = 0; j < 3; ++j) {
-      double s = 0.0;
-      for (int i = 0; i < 3; ++i) s -= (double)c.R[i * 3 + j] * (double)c.t[i];
-      d.campos[j] = (float)s;
-    }
-    d.width = c.width; d.height = c.height;
-    d.tiles_x = (c.width + ctx->tile_w - 1) / ctx->tile_w;
-    d.tiles_y = (c.height + ctx->tile_h - 1) / ctx->tile_h;
-    d.tile_offset = (int32_t)toff;
-    d.pix_offset = (int32_t)poff;
-    toff += (int64_t)d.tiles_x * d.tiles_y;
-    poff += (int64_t)c.width * c.height;
+    fill_view(ctx, cams[v], toff, poff, out[v]);
+    toff += (int64_t)out[v].tiles_x * out[v].tiles_y;
+    poff += (int64_t)cams[v].width * cams[v].height;
   }
   *tiles = toff;
   *pixels = poff;
   return out;
+}
+
+inline void fill_view(const gsr_ctx* ctx, const gsr_camera& c, int64_t toff, int64_t poff, ViewDesc& d) {
+  std::memcpy(d.R, c.R, sizeof(d.R));
+  std::memcpy(d.t, c.t, sizeof(d.t));
+  d.fx = c.fx; d.fy = c.fy; d.cx = c.cx; d.cy = c.cy;
+  for (int j = 0; j < 3; ++j) {
+    double s = 0.0;
+    for (int i = 0; i < 3; ++i) s -= (double)c.R[i * 3 + j] * (double)c.t[i];
+    d.campos[j] = (float)s;
+  }
+  d.width = c.width; d.height = c.height;
+  d.tiles_x = (c.width + ctx->tile_w - 1) / ctx->tile_w;
+  d.tiles_y = (c.height + ctx->tile_h - 1) / ctx->tile_h;
+  d.tile_offset = (int32_t)toff;
+  d.pix_offset = (int32_t)poff;
 }
 
 inline int bits_for(int64_t max_key) {

@@ -46,11 +46,17 @@ constexpr float kTransMin = 1e-4f;
 // bits of z, 0xFFFFFFFF when culled); s = view * N + i.
 // Projection of every (view, Gaussian) splat into splats, rect, ntiles and
 // zkey (indexed view * n + Gaussian); with zhist the digit histograms of the
-// visible splats' depth keys are accumulated there.
+// visible splats' depth keys are accumulated there; with nonfinite, the number
+// of Gaussians with a non-finite mean, log-scale, rotation or opacity logit,
+// or a zero rotation quaternion, is added there (once per Gaussian).
 void launch_project(const float* params, int64_t n, int64_t stride, int deg, int num_views,
                     const ViewDesc* views, int tile_w, int tile_h, float znear, Splat* splats,
                     int4* rect, uint32_t* ntiles, uint32_t* zkey, uint32_t* zhist, int zrb, int zpasses,
-                    hipStream_t st);
+                    uint32_t* nonfinite, hipStream_t st);
+// scale[k][n] = exp(log-scale k) and opacity[n] = sigmoid(logit) of the n
+// Gaussians, as the projection computes them (either output may be null).
+void launch_activations(const float* params, int64_t n, int64_t stride, float* scale, float* opacity,
+                        hipStream_t st);
 // Chain rule from screen-space gradients g2[V*N][10] to grad_params (+=, or
 // with overwrite = every plane written, zero where no view contributed).
 // Counters of the replayed mapping iteration (stats words).
@@ -106,6 +112,12 @@ void launch_project_backward(const float* params, int64_t n, int64_t stride, int
                              const ViewDesc* views, float znear, float* g2, const uint32_t* ntiles,
                              float* grad, bool overwrite, bool zero_g2, const IterCounters* counters,
                              hipStream_t st);
+// Camera gradient of every view from the screen-space gradients g2:
+// gcam[v][12] += dL/dR (row-major), dL/dt; twist[v][6] (may be null) += the
+// gradient with respect to a left perturbation (rho, phi) of the pose.
+void launch_pose_backward(const float* params, int64_t n, int64_t stride, int deg, int num_views,
+                          const ViewDesc* views, const float* g2, const uint32_t* ntiles, double* gcam, double* twist,
+                          hipStream_t st);
 // Inspection copy of the splats of one view: out[n][16] (see gsr_copy_splats).
 void launch_export_splats(const float* params, int64_t n, int64_t stride, const ViewDesc* view, float znear,
                           const Splat* splats, const int4* rect, float* out, hipStream_t st);
@@ -273,6 +285,10 @@ void launch_blend_forward(const BlendArgs& a, int tile_w, int tile_h, int ppt, h
 // capped at the workgroup's thread count)
 bool batch_depth_supported(int depth);
 void launch_blend_backward(const BlendArgs& a, int tile_w, int tile_h, int ppt, int depth, hipStream_t st);
+// The splat-parallel schedule of the same backward: one wavefront per tile,
+// a Gaussian per lane, the pixels pipelined through the lanes; needs
+// unchunked forward state (chunk_len 0) and a.tile_last.
+void launch_blend_backward_splat(const BlendArgs& a, int tile_w, int tile_h, hipStream_t st);
 // Forward (with the fused loss) and backward in one launch, at the default
 // batch depth; needs loss_target, loss_grad, g2, tile_done and err.
 void launch_blend_fused(const BlendArgs& a, int tile_w, int tile_h, int ppt, hipStream_t st);

@@ -26,26 +26,95 @@ constexpr float kDilation = 0.3f;
 constexpr float kClampFov = 1.3f;
 constexpr float kQMax = 11.2f;
 
-// Exponential by Cody-Waite reduction: x = n ln2 + r, ln2 split into a head
-// with 15 significant bits (so n * head is exact) and a tail; e^r by its
-// degree-7 Taylor polynomial in Horner form; result scaled by 2^n.
-__device__ __forceinline__ float exp_cw(float x) {
-  x = fminf(fmaxf(x, -87.0f), 88.0f);
-  const float n = rintf(x * 1.44269504088896341f);
-  float r = x - n * 0.693145751953125f;
-  r = r - n * 1.4286068203094173e-06f;
-  float p = 1.98412698412698413e-4f;
-  p = p * r + 1.38888888888888889e-3f;
-  p = p * r + 8.33333333333333333e-3f;
-  p = p * r + 4.16666666666666667e-2f;
-  p = p * r + 1.66666666666666667e-1f;
-  p = p * r + 0.5f;
-  p = p * r + 1.0f;
-  p = p * r + 1.0f;
-  return ldexpf(p, (int)n);
+__device__ __forceinline__ bool finitef(float x) { return __builtin_isfinite(x); }
+
+// ---------------------------------------------------------------------------
+// exp(x) correctly rounded to float, for the scales and the opacity.
+//
+// The device's double-precision exp (a few ulp of double at most) is rounded
+// to float. That is the correctly rounded result unless the double lies so
+// close to a midpoint between two neighbouring floats that its own error
+// could put it on the wrong side; only then is exp evaluated again in
+// double-double arithmetic (about 100 significant bits) and the side of that
+// midpoint decided from it. Every float input gets the float nearest to its
+// exact exponential.
+// ---------------------------------------------------------------------------
+struct DD {
+  double hi, lo;
+};
+
+// hi + lo exactly, for |a| >= |b| or a == 0
+__device__ __forceinline__ DD dd_fast(double a, double b) {
+  const double s = a + b;
+  return DD{s, b - (s - a)};
+}
+// a + b exactly, any order of magnitude
+__device__ __forceinline__ DD dd_sum(double a, double b) {
+  const double s = a + b;
+  const double bv = s - a;
+  return DD{s, (a - (s - bv)) + (b - bv)};
+}
+__device__ __forceinline__ DD dd_add(DD a, DD b) {
+  DD s = dd_sum(a.hi, b.hi);
+  return dd_fast(s.hi, s.lo + (a.lo + b.lo));
+}
+__device__ __forceinline__ DD dd_mul(DD a, DD b) {
+  const double p = a.hi * b.hi;
+  const double e = fma(a.hi, b.hi, -p);          // exact low part of a.hi * b.hi
+  return dd_fast(p, e + (a.hi * b.lo + a.lo * b.hi));
+}
+__device__ __forceinline__ DD dd_div_small(DD a, double k) {
+  const double q = a.hi / k;
+  const double r = fma(-q, k, a.hi);             // exact remainder
+  return dd_fast(q, (r + a.lo) / k);
 }
 
-__device__ __forceinline__ bool finitef(float x) { return __builtin_isfinite(x); }
+// exp(x) as hi + lo for a float x with a finite, nonzero float exponential.
+// x = n ln2 + r with |r| <= ln2/2 (ln2 in two doubles whose sum is within
+// 2^-106 of it; n ln2_hi formed exactly with an fma), then e^r from its
+// Taylor series summed to 24 terms (the remainder is below 2^-110), scaled
+// by 2^n.
+__device__ __noinline__ DD exp_dd(float xf) {
+  const double ln2_hi = 0x1.62e42fefa39efp-1;
+  const double ln2_lo = 0x1.abc9e3b39803fp-56;
+  const double x = (double)xf;
+  const double n = rint(x * 0x1.71547652b82fep+0);
+  const double p = n * ln2_hi;
+  const double pe = fma(n, ln2_hi, -p);
+  DD r = dd_sum(x, -p);
+  r = dd_add(r, dd_sum(-pe, -(n * ln2_lo)));
+  DD term{1.0, 0.0}, sum{1.0, 0.0};
+  for (int k = 1; k <= 24; ++k) {
+    term = dd_div_small(dd_mul(term, r), (double)k);
+    sum = dd_add(sum, term);
+  }
+  const int e = (int)n;
+  return DD{ldexp(sum.hi, e), ldexp(sum.lo, e)};
+}
+
+__device__ __forceinline__ float exp32_rn(float x) {
+  const double y = exp((double)x);
+  const float f = (float)y;
+  if (!finitef(f)) return f;                     // overflow to inf, or a NaN input
+  const double fd = (double)f;
+  const uint32_t fb = __float_as_uint(f);        // f >= 0
+  // the neighbour of f on y's side and the midpoint between them (exact)
+  double nb;
+  if (y >= fd) nb = (double)__uint_as_float(fb + 1u);
+  else nb = f == 0.0f ? -0x1p-149 : (double)__uint_as_float(fb - 1u);
+  const double mid = 0.5 * (fd + nb);
+  if (fabs(y - mid) > 0x1p-48 * y) return f;
+  const DD e = exp_dd(x);
+  const double side = (e.hi - mid) + e.lo;       // e.hi - mid is exact (Sterbenz)
+  const double lo = fmin(fd, nb), hi = fmax(fd, nb);
+  if (side > 0.0) return (float)hi;
+  if (side < 0.0) return (float)lo;
+  return (__float_as_uint((float)lo) & 1u) ? (float)hi : (float)lo;   // exact tie: even
+}
+
+// Opacity = sigmoid(logit): one correctly rounded float operation per step.
+__device__ __forceinline__ float opacity_of(float logit) { return 1.0f / (1.0f + exp32_rn(-logit)); }
+
 
 // Correctly rounded square root. The hardware square root is within one ulp;
 // the result is moved to the neighbour whose rounding interval contains the
@@ -105,6 +174,22 @@ __device__ __forceinline__ void sh_basis(int deg, float x, float y, float z, flo
   Y[15] = -SH_K0 * x * (xx - 3.0f * yy);
 }
 
+// A Gaussian the projection can never draw for its values alone: a
+// non-finite mean, log-scale, rotation or opacity logit, or a rotation
+// quaternion of zero (or non-finite) norm. Such Gaussians are culled in
+// every view and counted once per render.
+__device__ __forceinline__ bool degenerate_gaussian(const float* __restrict__ P, int64_t stride, int64_t i) {
+  bool ok = true;
+#pragma unroll
+  for (int k = 0; k < 11; ++k) ok = ok && finitef(P[k * stride + i]);
+  if (!ok) return true;
+  const float qw = P[6 * stride + i], qx = P[7 * stride + i], qy = P[8 * stride + i], qz = P[9 * stride + i];
+  float ss = qw * qw + qx * qx;
+  ss = ss + qy * qy;
+  ss = ss + qz * qz;
+  return !(ss > 0.0f) || !finitef(ss);
+}
+
 // Everything the projection computes for one (view, Gaussian).
 struct ProjState {
   float s[3], qn, qh[4], R[9], M[9], Sig[9];
@@ -128,7 +213,7 @@ __device__ __forceinline__ bool project_geometry(const float* __restrict__ P, in
   if (!ok) return false;
   const float mx = raw[0], my = raw[1], mz = raw[2];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) g.s[k] = exp_cw(raw[3 + k]);
+  for (int k = 0; k < 3; ++k) g.s[k] = exp32_rn(raw[3 + k]);
   const float qw = raw[6], qx = raw[7], qy = raw[8], qz = raw[9];
   float ss = qw * qw + qx * qx;
   ss = ss + qy * qy;
@@ -246,7 +331,7 @@ __device__ __forceinline__ bool surely_culled(const float* __restrict__ P, int64
   if (!(tc[2] >= znear)) return finitef(tc[2]);         // exactly the projection's near-plane cull
   const float lmax = fmaxf(fmaxf(P[3 * stride + i], P[4 * stride + i]), P[5 * stride + i]);
   if (!finitef(lmax) || lmax > 20.0f) return false;
-  const float smax = exp_cw(lmax) * 1.01f;
+  const float smax = __expf(lmax) * 1.01f;    // a bound: 1 % covers the fast exp's error
   const float iz = 1.0f / tc[2];
   const float limx = kClampFov * 0.5f * (float)V.width / V.fx, limy = kClampFov * 0.5f * (float)V.height / V.fy;
   const float jx = V.fx * iz, jy = V.fy * iz;
@@ -297,7 +382,7 @@ __device__ __forceinline__ bool project_splat(const float* __restrict__ P, int64
   float raw[3], col[3], dir[3], dnorm;
   float o = 0.0f;
   if (vis) {
-    o = 1.0f / (1.0f + exp_cw(-P[10 * stride + i]));
+    o = opacity_of(P[10 * stride + i]);
     project_colour(P, stride, i, deg, V, raw, col, dir, &dnorm);
     vis = finitef(col[0]) && finitef(col[1]) && finitef(col[2]);
   }
@@ -334,7 +419,7 @@ __global__ void __launch_bounds__(256) project_kernel(const float* __restrict__ 
                                                       int tile_h, float znear, Splat* __restrict__ splats,
                                                       int4* __restrict__ rect, uint32_t* __restrict__ ntiles,
                                                       uint32_t* __restrict__ zkey, uint32_t* __restrict__ zhist,
-                                                      int zrb, int zpasses) {
+                                                      int zrb, int zpasses, uint32_t* __restrict__ nonfinite) {
   // digit histograms of the visible splats' depth keys for the radix sort
   // that follows (zpasses digits of zrb bits; zpasses * 2^zrb <= 3 * 2048)
   __shared__ uint32_t s_hist[3 * 2048];
@@ -352,6 +437,10 @@ __global__ void __launch_bounds__(256) project_kernel(const float* __restrict__ 
   for (int64_t i0 = blockIdx.x * (int64_t)blockDim.x; i0 < n; i0 += stride_t) {
     const int64_t i = i0 + threadIdx.x;
     const bool mine = i < n;
+    if (nonfinite) {
+      const unsigned long long bad = __ballot(mine && degenerate_gaussian(P, stride, i));
+      if (bad && (threadIdx.x & 63) == 0) atomicAdd(nonfinite, (uint32_t)__popcll(bad));
+    }
     if (num_views == 1) {
       uint32_t key;
       if (mine && project_splat(P, stride, deg, i, i, views[0], tile_w, tile_h, znear,
@@ -511,10 +600,14 @@ __device__ __forceinline__ void sh_dir_grad_d(int deg, double x, double y, doubl
 // One thread per Gaussian, so the parameter gradients need no atomics.
 // Chain rule of one (view, Gaussian) pair: adds to the Gaussian's parameter
 // gradients (in double) what the pair's screen-space gradient G implies.
-template <int DEG>
+// POSE: also adds the pair's part of the gradient with respect to the view's
+// camera to gpose[12]: dL/dR (row-major) and dL/dt of x_cam = R x + t. R acts
+// through the camera-space mean, through T = J R and, for view-dependent
+// colour, through the camera centre -R^T t.
+template <int DEG, bool POSE = false>
 __device__ __forceinline__ void chain_view(const float* __restrict__ P, int64_t stride, int64_t i, const ViewDesc& V,
                                            const double* G, const float* coef, double* gmean, double* gls,
-                                           double* gq, double& glogit, float* gsh) {
+                                           double* gq, double& glogit, float* gsh, double* gpose = nullptr) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   ProjD g;
   geometry_f64(P, stride, i, V, g);
@@ -553,10 +646,14 @@ __device__ __forceinline__ void chain_view(const float* __restrict__ P, int64_t 
       gdir[2] += gc * gd[2];
     }
   }
+  double gview[3] = {0.0, 0.0, 0.0};   // dL/d(mean - camera centre) through the colour
   if (DEG > 0) {
     const double dot = dir[0] * gdir[0] + dir[1] * gdir[1] + dir[2] * gdir[2];
 #pragma unroll
-    for (int j = 0; j < 3; ++j) gmean[j] += (gdir[j] - dir[j] * dot) / dnorm;
+    for (int j = 0; j < 3; ++j) {
+      gview[j] = (gdir[j] - dir[j] * dot) / dnorm;
+      gmean[j] += gview[j];
+    }
   }
   // conic (A, B, C) = (c, -b, a) / det
   const double a = g.a, b = g.b, c = g.c, det = g.det;
@@ -618,6 +715,23 @@ __device__ __forceinline__ void chain_view(const float* __restrict__ P, int64_t 
   gtz += G[G2_Z];
 #pragma unroll
   for (int j = 0; j < 3; ++j) gmean[j] += W[j] * gtx + W[3 + j] * gty + W[6 + j] * gtz;
+  if (POSE) {
+    const double mu[3] = {(double)P[0 * stride + i], (double)P[1 * stride + i], (double)P[2 * stride + i]};
+    const double gt[3] = {gtx, gty, gtz};
+    const double J00 = fx * itz, J02 = -(fx * g.xi) * itz, J11 = fy * itz, J12 = -(fy * g.yi) * itz;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      // x_cam = R mu + t; T = J R with J's rows (J00, 0, J02), (0, J11, J12);
+      // centre c = -R^T t and dL/dc = -gview
+      gpose[0 * 3 + k] += gt[0] * mu[k] + J00 * gT0[k] + gview[k] * (double)V.t[0];
+      gpose[1 * 3 + k] += gt[1] * mu[k] + J11 * gT1[k] + gview[k] * (double)V.t[1];
+      gpose[2 * 3 + k] += gt[2] * mu[k] + J02 * gT0[k] + J12 * gT1[k] + gview[k] * (double)V.t[2];
+    }
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+      gpose[9 + r] += gt[r] + (double)W[r * 3 + 0] * gview[0] + (double)W[r * 3 + 1] * gview[1] +
+                      (double)W[r * 3 + 2] * gview[2];
+  }
   // Sigma = M M^T, M = R diag(s)
   double gM[9];
 #pragma unroll
@@ -715,6 +829,85 @@ __global__ void __launch_bounds__(256) project_backward_kernel(const float* __re
   }
 }
 
+// Camera gradient of every view: per (view, Gaussian) the chain rule of
+// chain_view with the pose terms, summed over each workgroup (in double) and
+// added with one atomic per (workgroup, view, component). gcam[v][12] += dL/dR
+// (row-major), dL/dt; twist[v][6] (if not null) += the gradient with respect
+// to a left perturbation exp(xi^) [R | t] of the pose, xi = (rho, phi): dL/drho
+// = dL/dt and dL/dphi = the axial vector of A - A^T, A = dL/dR R^T + dL/dt t^T.
+// The loops are uniform over each workgroup (every thread reaches every
+// reduction).
+template <int DEG>
+__global__ void __launch_bounds__(256) pose_backward_kernel(const float* __restrict__ P, int64_t n, int64_t stride,
+                                                            int num_views, const ViewDesc* __restrict__ views,
+                                                            const float* __restrict__ g2,
+                                                            const uint32_t* __restrict__ ntiles,
+                                                            double* __restrict__ gcam, double* __restrict__ twist) {
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  __shared__ double red[4][12];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int64_t i0 = blockIdx.x * (int64_t)blockDim.x; i0 < n; i0 += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = i0 + threadIdx.x;
+    const bool mine = i < n;
+    float coef[3 * K];
+#pragma unroll
+    for (int k = 0; k < 3 * K; ++k) coef[k] = mine ? P[(11 + k) * stride + i] : 0.0f;
+    for (int cur = 0; cur < num_views; ++cur) {
+      double gp[12];
+#pragma unroll
+      for (int k = 0; k < 12; ++k) gp[k] = 0.0;
+      if (mine && ntiles[(int64_t)cur * n + i] != 0u) {
+        const float* gv = g2 + ((int64_t)cur * n + i) * G2_N;
+        double G[G2_N];
+        bool any = false;
+#pragma unroll
+        for (int k = 0; k < G2_N; ++k) {
+          G[k] = gv[k];
+          any = any || (G[k] != 0.0);
+        }
+        if (any) {
+          double gmean[3] = {0, 0, 0}, gls[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, glogit = 0.0;
+          float gsh[3 * K];
+#pragma unroll
+          for (int k = 0; k < 3 * K; ++k) gsh[k] = 0.0f;
+          chain_view<DEG, true>(P, stride, i, views[cur], G, coef, gmean, gls, gq, glogit, gsh, gp);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 12; ++k) {
+        double x = gp[k];
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, 64);
+        if (lane == 0) red[wave][k] = x;
+      }
+      __syncthreads();
+      if (threadIdx.x < 12) {
+        const int k = threadIdx.x;
+        const double sum = red[0][k] + red[1][k] + red[2][k] + red[3][k];
+        if (sum != 0.0) atomicAdd(gcam + cur * 12 + k, sum);
+      }
+      if (twist && threadIdx.x == 0) {
+        double Gs[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) Gs[k] = red[0][k] + red[1][k] + red[2][k] + red[3][k];
+        const ViewDesc& V = views[cur];
+        double A[9];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+          for (int c = 0; c < 3; ++c)
+            A[r * 3 + c] = Gs[r * 3 + 0] * (double)V.R[c * 3 + 0] + Gs[r * 3 + 1] * (double)V.R[c * 3 + 1] +
+                           Gs[r * 3 + 2] * (double)V.R[c * 3 + 2] + Gs[9 + r] * (double)V.t[c];
+        const double tw[6] = {Gs[9], Gs[10], Gs[11], A[7] - A[5], A[2] - A[6], A[3] - A[1]};
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+          if (tw[k] != 0.0) atomicAdd(twist + cur * 6 + k, tw[k]);
+      }
+      __syncthreads();
+    }
+  }
+}
+
 // Inspection copy of one view's splats; the screen covariance (a, b, c) is
 // not kept by the forward, so it is recomputed here by the same projection.
 __global__ void export_splats_kernel(const float* __restrict__ P, int64_t n, int64_t stride,
@@ -747,6 +940,20 @@ __global__ void export_splats_kernel(const float* __restrict__ P, int64_t n, int
   }
 }
 
+// The activations of O1 as the projection computes them: scale[k][n] =
+// exp(log-scale k) and opacity[n] = sigmoid(logit), each correctly rounded
+// where the projection's float operations are.
+__global__ void __launch_bounds__(256) activations_kernel(const float* __restrict__ P, int64_t n, int64_t stride,
+                                                          float* __restrict__ scale, float* __restrict__ opacity) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    if (scale) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) scale[k * n + i] = exp32_rn(P[(3 + k) * stride + i]);
+    }
+    if (opacity) opacity[i] = opacity_of(P[10 * stride + i]);
+  }
+}
+
 int grid_for(int64_t n, int block) {
   int64_t g = (n + block - 1) / block;
   if (g < 1) g = 1;
@@ -758,11 +965,17 @@ int grid_for(int64_t n, int block) {
 
 void launch_project(const float* params, int64_t n, int64_t stride, int deg, int num_views, const ViewDesc* views,
                     int tile_w, int tile_h, float znear, Splat* splats, int4* rect, uint32_t* ntiles,
-                    uint32_t* zkey, uint32_t* zhist, int zrb, int zpasses, hipStream_t st) {
+                    uint32_t* zkey, uint32_t* zhist, int zrb, int zpasses, uint32_t* nonfinite, hipStream_t st) {
   if (n == 0 || num_views == 0) return;
   if (zpasses * (1 << zrb) > 3 * 2048) zhist = nullptr;
   project_kernel<<<grid_for(n, 256), 256, 0, st>>>(params, n, stride, deg, num_views, views, tile_w, tile_h, znear,
-                                                   splats, rect, ntiles, zkey, zhist, zrb, zpasses);
+                                                   splats, rect, ntiles, zkey, zhist, zrb, zpasses, nonfinite);
+}
+
+void launch_activations(const float* params, int64_t n, int64_t stride, float* scale, float* opacity,
+                        hipStream_t st) {
+  if (n == 0 || (!scale && !opacity)) return;
+  activations_kernel<<<grid_for(n, 256), 256, 0, st>>>(params, n, stride, scale, opacity);
 }
 
 void launch_project_backward(const float* params, int64_t n, int64_t stride, int deg, int num_views,
@@ -789,6 +1002,19 @@ void launch_project_backward(const float* params, int64_t n, int64_t stride, int
       project_backward_kernel<3><<<gsz, 256, 0, st>>>(params, n, stride, num_views, views, g2, ntiles, grad, overwrite,
                                                           zero_g2, ic);
       break;
+  }
+}
+
+void launch_pose_backward(const float* params, int64_t n, int64_t stride, int deg, int num_views,
+                          const ViewDesc* views, const float* g2, const uint32_t* ntiles, double* gcam, double* twist,
+                          hipStream_t st) {
+  if (n == 0) return;
+  const int gsz = grid_for(n, 256);
+  switch (deg) {
+    case 0: pose_backward_kernel<0><<<gsz, 256, 0, st>>>(params, n, stride, num_views, views, g2, ntiles, gcam, twist); break;
+    case 1: pose_backward_kernel<1><<<gsz, 256, 0, st>>>(params, n, stride, num_views, views, g2, ntiles, gcam, twist); break;
+    case 2: pose_backward_kernel<2><<<gsz, 256, 0, st>>>(params, n, stride, num_views, views, g2, ntiles, gcam, twist); break;
+    default: pose_backward_kernel<3><<<gsz, 256, 0, st>>>(params, n, stride, num_views, views, g2, ntiles, gcam, twist); break;
   }
 }
 

@@ -16,15 +16,15 @@ class Rasterizer:
     """Owns one gsr context (device scratch) and its options."""
 
     def __init__(self, tile_w=16, tile_h=16, bg=(0.0, 0.0, 0.0), znear=0.2, pixels_per_thread=0, batch_depth=0,
-                 tile_order=0, chunk_len=0, max_chunks=0, fuse_blend=0, depth_sort=0):
+                 tile_order=0, chunk_len=0, max_chunks=0, fuse_blend=0, depth_sort=0, backward_schedule=0):
         self.tile_w, self.tile_h = tile_w, tile_h
         self.pixels_per_thread, self.batch_depth, self.tile_order = pixels_per_thread, batch_depth, tile_order
         self.chunk_len, self.max_chunks, self.fuse_blend = chunk_len, max_chunks, fuse_blend
-        self.depth_sort = depth_sort
+        self.depth_sort, self.backward_schedule = depth_sort, backward_schedule
         self.bg = tuple(float(x) for x in bg)
         self.znear = znear
         self.handle = _lib.gsr_create(tile_w, tile_h, batch_depth, self.bg, znear, pixels_per_thread, tile_order,
-                                      chunk_len, max_chunks, fuse_blend, depth_sort)
+                                      chunk_len, max_chunks, fuse_blend, depth_sort, backward_schedule)
 
     def close(self):
         if self.handle is not None:
@@ -54,6 +54,15 @@ class Rasterizer:
             grad_params = torch.zeros_like(params)
         _lib.gsr_render_backward(self.handle, params, sh_degree, cams, grads, grad_params)
         return grad_params
+
+    def render_backward_pose(self, params, sh_degree, cams, grads, grad_params=None, twist=True):
+        """Camera gradients of the last render: (dL/d(R, t) [V, 12] float64, twist [V, 6] or None); with
+        grad_params (a tensor like params) the parameter gradient is added there as well."""
+        nv = len(cams)
+        gc = torch.zeros(nv, 12, dtype=torch.float64, device=params.device)
+        tw = torch.zeros(nv, 6, dtype=torch.float64, device=params.device) if twist else None
+        _lib.gsr_render_backward_pose(self.handle, params, sh_degree, cams, grads, gc, grad_params, tw)
+        return gc, tw
 
     def loss_l1(self, cams, rendered, targets, depth_weight=0.5):
         grads = [(torch.empty_like(r[0]), torch.empty_like(r[1]), torch.empty_like(r[2])) for r in rendered]
@@ -116,3 +125,63 @@ def rasterize(params, sh_degree, cams, rasterizer):
     """List of (rgb, depth, alpha) per view, differentiable with respect to params."""
     flat = Rasterize.apply(params, sh_degree, cams, rasterizer)
     return [tuple(flat[3 * v:3 * v + 3]) for v in range(len(cams))]
+
+
+class GaussianMap:
+    """A map that grows by keyframe insertion: parameters and Adam moments in
+    buffers [P, capacity] with spare room, the first `num` Gaussians being the
+    map. params/m/v are [P, num] views with the buffers' plane stride, which
+    every entry point accepts. Growing moves the buffers, so the next mapping
+    iteration captures its graph again."""
+
+    def __init__(self, params, sh_degree, capacity=None, growth=1.5):
+        P, n = params.shape
+        self.sh_degree, self.growth, self.num = sh_degree, growth, n
+        cap = max(int(capacity or n), n, 1)
+        self._p = torch.zeros(P, cap, dtype=torch.float32, device=params.device)
+        self._p[:, :n] = params
+        self._m = torch.zeros_like(self._p)
+        self._v = torch.zeros_like(self._p)
+
+    @property
+    def capacity(self):
+        return self._p.shape[1]
+
+    @property
+    def params(self):
+        return self._p[:, :self.num]
+
+    @property
+    def m(self):
+        return self._m[:, :self.num]
+
+    @property
+    def v(self):
+        return self._v[:, :self.num]
+
+    def zeros(self):
+        """A zero tensor laid out like params (same plane stride), e.g. for the gradient."""
+        return torch.zeros(self._p.shape[0], self.capacity, dtype=torch.float32, device=self._p.device)[:, :self.num]
+
+    def reserve(self, n):
+        if n <= self.capacity:
+            return
+        cap = max(n, int(self.capacity * self.growth) + 1)
+        for name in ("_p", "_m", "_v"):
+            old = getattr(self, name)
+            new = torch.zeros(old.shape[0], cap, dtype=old.dtype, device=old.device)
+            new[:, :self.num] = old[:, :self.num]
+            setattr(self, name, new)
+
+    def insert_keyframe(self, rasterizer, cam, rgb, depth, coverage=None, **options):
+        """Seed Gaussians from an RGB-D keyframe (gsr_densify) and append them,
+        growing the buffers when they are full. Returns the number added."""
+        added, wanted = _lib.gsr_densify(rasterizer.handle, self._p, self.num, self.sh_degree, cam, rgb, depth,
+                                         coverage, **options)
+        if wanted > added:
+            self.reserve(self.num + wanted)
+            added, wanted = _lib.gsr_densify(rasterizer.handle, self._p, self.num, self.sh_degree, cam, rgb, depth,
+                                             coverage, **options)
+        assert added == wanted
+        self.num += added
+        return added

@@ -9,7 +9,12 @@ from the oracle's) may take the other branch.
 
 Gradients: per parameter group, |g - ref| <= 1e-3 * max(|ref|, 0.01 * rms(ref_group),
 1e-6 * rms(ref_all)); the last floor only matters for groups whose exact
-gradient vanishes (rotations of isotropic Gaussians).
+gradient vanishes (rotations of isotropic Gaussians). The reference is the
+oracle's FP64 backward at the FP32 projection's splat values (the values the
+method composites). Against the FP64 backward at FP64 splat values the same
+bar holds per element after adding that element's own sensitivity to the FP32
+rounding of the splats, |ref_splats32 - ref_fp64|, which the oracle measures
+without the GPU (grad_violations_conditioned).
 """
 import numpy as np
 
@@ -54,4 +59,33 @@ def grad_violations(g, ref, rtol=GRAD_RTOL):
         rel = np.abs(a - b) / scale
         l2 = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-6 * rms_all * np.sqrt(b.size), 1e-300)
         out[name] = (int((rel > rtol).sum()), float(rel.max(initial=0.0)), float(l2))
+    return out
+
+
+def grad_violations_conditioned(g, ref64, ref32, rtol=GRAD_RTOL):
+    """Per-element check against the FP64 backward at FP64 splat values:
+    |g - ref64| <= rtol * max(|ref64|, floors) + |ref32 - ref64|, where ref32 is
+    the oracle's FP64 backward at the FP32-rounded splat values. The added
+    term is how far rounding the screen-space values (u, v, conic, opacity,
+    colour, depth) to float moves this element's exact gradient: any method
+    that composites FP32 splats carries it. Returns {group: (violations, worst
+    |g - ref64| / tolerance, relative L2 vs ref64, elements that pass only
+    with the added term)}."""
+    out = {}
+    P = ref64.shape[0]
+    ref64 = np.asarray(ref64, np.float64)
+    ref32 = np.asarray(ref32, np.float64)
+    rms_all = np.sqrt(np.mean(ref64 * ref64)) if ref64.size else 0.0
+    for name, sl in grad_groups(P).items():
+        a = np.asarray(g[sl], np.float64).ravel()
+        b = ref64[sl].ravel()
+        c = ref32[sl].ravel()
+        rms = np.sqrt(np.mean(b * b)) if b.size else 0.0
+        base = rtol * np.maximum(np.abs(b), max(0.01 * rms, 1e-6 * rms_all))
+        cond = np.abs(c - b)
+        err = np.abs(a - b)
+        tol = np.where(base + cond > 0, base + cond, 1e-300)
+        l2 = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-6 * rms_all * np.sqrt(b.size), 1e-300)
+        widened = int(((err > base) & (err <= tol)).sum())
+        out[name] = (int((err > tol).sum()), float((err / tol).max(initial=0.0)), float(l2), widened)
     return out

@@ -13,7 +13,7 @@ import torch
 
 import scenes
 from scenes import identity_camera
-from parity import AMBIGUOUS_MARGIN, grad_violations, image_violations
+from parity import AMBIGUOUS_MARGIN, grad_violations, grad_violations_conditioned, image_violations
 
 pytestmark = pytest.mark.gpu
 
@@ -178,7 +178,7 @@ def check_images(outs, ref, label):
     mask = ref["margin"] >= AMBIGUOUS_MARGIN
     amb = int((~mask).sum())
     say(label, "ambiguous pixels", amb, "of", mask.size)
-    assert amb <= max(2, 2e-3 * mask.size)
+    assert amb <= max(2, 1e-3 * mask.size)
     worst = {}
     for ch in range(3):
         nbad, worst[f"rgb{ch}"] = image_violations(rgb[ch], ref["rgb"][ch], mask)
@@ -225,17 +225,19 @@ def masked_grads(orc, s, seed):
 
 
 def check_grads(g, ref, label, ref64=None):
-    """Strict per-parameter check against the FP64 backward at the FP32 splats;
-    against the FP64 backward at FP64 splats, the relative L2 per group."""
+    """Per element against the FP64 backward at the FP32 splats (1e-3); per
+    element against the FP64 backward at FP64 splats (1e-3 plus the element's
+    own sensitivity to the FP32 rounding of the splats, measured by the
+    oracle), and relative L2 within 1e-4 there."""
     res = grad_violations(g, ref)
     say(label, "vs FP64 at FP32 splats", res)
     for grp, (nbad, worst, l2) in res.items():
         assert nbad == 0, (label, grp, nbad, worst, l2)
     if ref64 is not None:
-        res = grad_violations(g, ref64)
+        res = grad_violations_conditioned(g, ref64, ref)
         say(label, "vs FP64", res)
-        for grp, (nbad, worst, l2) in res.items():
-            assert l2 <= 1e-4, (label, grp, l2)
+        for grp, (nbad, worst, l2, widened) in res.items():
+            assert nbad == 0 and l2 <= 1e-4, (label, grp, nbad, worst, l2)
 
 
 def oracle_grads(orc, s, cams, grads):
@@ -299,6 +301,59 @@ def test_backward_chunked_background_multiview(gpu, orc):
     ref32 = orc.backward(s.params, 0, s.cameras, grads, pinned="splats32", bg=bg)
     ref64 = orc.backward(s.params, 0, s.cameras, grads, pinned=True, bg=bg)
     check_grads(g, ref32, "chunked, background, two views", ref64)
+
+
+@pytest.mark.parametrize("tile", [(16, 16), (16, 8), (8, 8), (32, 8)])
+@pytest.mark.parametrize("name", list(CASES))
+def test_backward_splat_parallel_matches_fp64_oracle(gpu, orc, name, tile):
+    """The splat-parallel schedule (a wavefront per tile, a Gaussian per lane,
+    the pixels pipelined through the lanes) against the FP64 oracle."""
+    s = CASES[name]
+    say("splat-parallel backward", name, tile)
+    grads = masked_grads(orc, s, 12)
+    R = make(gpu, tile_w=tile[0], tile_h=tile[1], backward_schedule=1)
+    p = to_dev(s.params)
+    R.render(p, s.sh_degree, s.cameras)
+    g = R.render_backward(p, s.sh_degree, s.cameras, [tuple(to_dev(x) for x in gv) for gv in grads]).cpu().numpy()
+    ref32, ref64 = oracle_grads(orc, s, s.cameras, grads)
+    check_grads(g, ref32, f"splat-parallel {name} {tile}", ref64)
+
+
+def test_backward_splat_parallel_background_multiview_alpha(gpu, orc):
+    """Splat-parallel: two views, a background colour and an alpha-image gradient."""
+    s = scenes.tiny_random(4, n=50, width=40, height=30)
+    s.cameras = [s.cameras[0], scenes.look_at_camera([0.3, 0.1, -0.5], [0, 0, 2], 36, 28, 30.0)]
+    bg = (0.2, 0.5, 0.8)
+    grads = masked_grads(orc, s, 13)
+    R = make(gpu, bg=bg, backward_schedule=1)
+    p = to_dev(s.params)
+    R.render(p, 0, s.cameras)
+    g = R.render_backward(p, 0, s.cameras, [tuple(to_dev(x) for x in gv) for gv in grads]).cpu().numpy()
+    ref32 = orc.backward(s.params, 0, s.cameras, grads, pinned="splats32", bg=bg)
+    ref64 = orc.backward(s.params, 0, s.cameras, grads, pinned=True, bg=bg)
+    check_grads(g, ref32, "splat-parallel, background, two views", ref64)
+
+
+def test_backward_splat_parallel_long_lists(gpu, orc):
+    """Splat-parallel with tile lists of several hundred Gaussians (many
+    64-entry batches, pixels whose walks end in different batches)."""
+    rng = np.random.default_rng(21)
+    cam = identity_camera(64, 48, 60.0)
+    n = 1500
+    mean = scenes.volume_uniform_in_frustum(rng, n, cam, 1.0, 4.0)
+    p = scenes._assemble(mean, rng.normal(-3.2, 0.5, (n, 3)), rng.normal(size=(n, 4)), rng.normal(-1.5, 1.0, n),
+                         rng.uniform(-0.5, 0.5, (n, 1, 3)))
+    s = scenes.Scene("long_lists", p, 0, [cam])
+    grads = masked_grads(orc, s, 14)
+    R = make(gpu, backward_schedule=1)
+    dp = to_dev(p)
+    R.render(dp, 0, s.cameras)
+    lens = np.bincount(R.instances()[0])
+    say("list lengths: max", int(lens.max()), "mean", float(lens.mean()))
+    assert lens.max() > 300
+    g = R.render_backward(dp, 0, s.cameras, [tuple(to_dev(x) for x in gv) for gv in grads]).cpu().numpy()
+    ref32, ref64 = oracle_grads(orc, s, s.cameras, grads)
+    check_grads(g, ref32, "splat-parallel long lists", ref64)
 
 
 def test_chunking_leaves_forward_unchanged(gpu):
@@ -441,6 +496,40 @@ def test_empty_and_culled(gpu, orc):
     outs = R.render(to_dev(q), 0, [cam])
     assert (outs[0][2] == 0).all()
     assert R.status()["instances"] == 0
+
+
+def test_nonfinite_gaussians_culled_and_counted(gpu, orc):
+    """Gaussians with a NaN or infinite parameter or a zero quaternion, placed
+    in view, are culled (the images equal the oracle's, which culls them and
+    draws the rest), counted once each by gsr_query_status in every render,
+    and get zero gradient; a non-finite SH coefficient culls the splat but is
+    not counted."""
+    s = scenes.tiny_random(5, n=60, width=48, height=40)
+    p = s.params.copy()
+    planted = {0: (1, np.nan), 1: (4, np.inf), 2: (10, -np.inf), 3: (8, np.nan), 5: (0, -np.inf)}
+    for i, (plane, val) in planted.items():
+        p[plane, i] = val
+    p[6:10, 4] = 0.0                                 # zero quaternion
+    p[12, 6] = np.inf                                # SH coefficient: culled, not counted
+    counted = len(planted) + 1
+    for nv in (1, 2):
+        cams = s.cameras * nv
+        R = make(gpu)
+        dp = to_dev(p)
+        outs = R.render(dp, 0, cams)
+        st = R.status()
+        say("status", nv, st)
+        assert st["nonfinite_culled"] == counted
+        ref = orc.render(p, 0, s.cameras[0], mode="f32")
+        for v in range(nv):
+            check_images(outs[v], ref, f"nonfinite view {v}")
+        pr = orc.project(p, 0, s.cameras[0])
+        assert not pr["vis"][[0, 1, 2, 3, 4, 5, 6]].any()
+        gimg = [(torch.ones(3, 40, 48, device="cuda"), torch.ones(40, 48, device="cuda"), None)] * nv
+        g = R.render_backward(dp, 0, cams, gimg).cpu().numpy()
+        assert np.isfinite(g).all()
+        assert (g[:, :7] == 0).all()
+        R.close()
 
 
 def test_one_pixel_and_huge_gaussian(gpu, orc):

@@ -1,0 +1,139 @@
+"""Camera-pose gradients (gsr_render_backward_pose) through the C ABI:
+dL/dR and dL/dt per view against the FP64 oracle's camera gradient, and the
+6-DoF left-perturbation gradient against central differences of the FP64
+oracle's render under exp(xi^) perturbations of the pose."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import scenes
+from parity import AMBIGUOUS_MARGIN
+from scenes import Camera
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    from paper_2509_06433_amd import rasterize
+    return rasterize
+
+
+def to_dev(p):
+    return torch.from_numpy(np.ascontiguousarray(p)).cuda()
+
+
+def masked_grads(orc, s, seed, margin=AMBIGUOUS_MARGIN):
+    out = []
+    for cam, (gr, gd, ga) in zip(s.cameras, scenes.random_image_grads(seed, s.cameras)):
+        keep = (orc.render(s.params, s.sh_degree, cam, mode="f32")["margin"] >= margin).astype(np.float32)
+        out.append((gr * keep[None], gd * keep, ga * keep))
+    return out
+
+
+def check_cam_grad(g, ref32, ref64, label):
+    """Per view and component: within 1e-3 of the FP64 oracle at the FP32
+    splats (floor 1 % of the view's largest component), and within that plus
+    the component's FP32-splat sensitivity of the FP64 oracle at FP64 splats."""
+    for v in range(ref32.shape[0]):
+        floor = 0.01 * np.abs(ref32[v]).max()
+        tol = 1e-3 * np.maximum(np.abs(ref32[v]), floor)
+        err = np.abs(g[v] - ref32[v])
+        say(label, "view", v, "worst ratio", float((err / tol).max()))
+        assert (err <= tol).all(), (label, v, g[v], ref32[v])
+        tol64 = 1e-3 * np.maximum(np.abs(ref64[v]), floor) + np.abs(ref32[v] - ref64[v])
+        assert (np.abs(g[v] - ref64[v]) <= tol64).all(), (label, v)
+
+
+def two_view_scene(k, deg):
+    s = scenes.tiny_random(k, n=60, width=48, height=40, sh_degree=deg)
+    s.cameras = [scenes.look_at_camera([0.2, -0.1, -0.3], [0.05, 0.0, 2.0], 48, 40, 40.0),
+                 scenes.look_at_camera([-0.3, 0.15, -0.2], [0.0, 0.1, 2.1], 44, 36, 38.0)]
+    return s
+
+
+@pytest.mark.parametrize("deg", [0, 3])
+def test_camera_gradient_matches_oracle(gpu, orc, deg):
+    s = two_view_scene(21 + deg, deg)
+    grads = masked_grads(orc, s, 3)
+    R = gpu.Rasterizer()
+    p = to_dev(s.params)
+    R.render(p, deg, s.cameras)
+    dgr = [tuple(to_dev(x) for x in gv) for gv in grads]
+    gp = torch.zeros_like(p)
+    gc, tw = R.render_backward_pose(p, deg, s.cameras, dgr, grad_params=gp)
+    _, ref32 = orc.backward(s.params, deg, s.cameras, grads, pinned="splats32", want_cam=True)
+    g64, ref64 = orc.backward(s.params, deg, s.cameras, grads, pinned=True, want_cam=True)
+    check_cam_grad(gc.cpu().numpy(), ref32, ref64, f"deg {deg}")
+    # the parameter gradient of the same call equals gsr_render_backward's
+    gpar = R.render_backward(p, deg, s.cameras, dgr)
+    assert torch.allclose(gp, gpar, rtol=1e-5, atol=1e-7 * float(gpar.abs().max()))
+    # without the parameter gradient, the camera gradient is the same
+    R.render(p, deg, s.cameras)
+    gc2, _ = R.render_backward_pose(p, deg, s.cameras, dgr)
+    assert torch.allclose(gc2, gc, rtol=1e-9, atol=1e-12 * float(gc.abs().max()))
+
+
+def rodrigues(phi):
+    th = np.linalg.norm(phi)
+    K = np.array([[0, -phi[2], phi[1]], [phi[2], 0, -phi[0]], [-phi[1], phi[0], 0]])
+    if th < 1e-300:
+        return np.eye(3)
+    return np.eye(3) + np.sin(th) / th * K + (1 - np.cos(th)) / th ** 2 * K @ K
+
+
+def twist_reference(gcam, R0, t0, h=1e-6):
+    """dL/dxi for [R | t] <- exp(xi^) [R | t], xi = (rho, phi), from the
+    camera gradient (dL/dR, dL/dt) and the derivative of that map taken by
+    central differences in double (Rodrigues' formula for exp(phi^))."""
+    out = np.zeros(6)
+    GR, Gt = gcam[:9].reshape(3, 3), gcam[9:]
+    for k in range(6):
+        xi = np.zeros(6)
+        xi[k] = h
+        Rp, tp = rodrigues(xi[3:]) @ R0, rodrigues(xi[3:]) @ t0 + xi[:3]
+        Rm, tm = rodrigues(-xi[3:]) @ R0, rodrigues(-xi[3:]) @ t0 - xi[:3]
+        out[k] = (GR * (Rp - Rm)).sum() / (2 * h) + (Gt * (tp - tm)).sum() / (2 * h)
+    return out
+
+
+def test_twist_matches_exp_map_derivative(gpu, orc):
+    """The left-perturbation gradient against the chain rule through the
+    numerically differentiated exponential map, from the oracle's camera
+    gradients; two views, SH degree 1 (the camera centre enters the colour)."""
+    s = two_view_scene(25, 1)
+    grads = masked_grads(orc, s, 4)
+    R = gpu.Rasterizer()
+    p = to_dev(s.params)
+    R.render(p, 1, s.cameras)
+    _, tw = R.render_backward_pose(p, 1, s.cameras, [tuple(to_dev(x) for x in gv) for gv in grads])
+    tw = tw.cpu().numpy()
+    _, ref32 = orc.backward(s.params, 1, s.cameras, grads, pinned="splats32", want_cam=True)
+    _, ref64 = orc.backward(s.params, 1, s.cameras, grads, pinned=True, want_cam=True)
+    r32 = np.stack([twist_reference(ref32[v], np.asarray(c.R, np.float64), np.asarray(c.t, np.float64))
+                    for v, c in enumerate(s.cameras)])
+    r64 = np.stack([twist_reference(ref64[v], np.asarray(c.R, np.float64), np.asarray(c.t, np.float64))
+                    for v, c in enumerate(s.cameras)])
+    say("twist", tw, "reference", r32)
+    check_cam_grad(tw, r32, r64, "twist")
+
+
+def test_camera_gradient_at_640x480_200k(gpu, orc):
+    s = scenes.keyframe_640x480()
+    grads = masked_grads(orc, s, 6)
+    R = gpu.Rasterizer()
+    p = to_dev(s.params)
+    R.render(p, 0, s.cameras)
+    gc, _ = R.render_backward_pose(p, 0, s.cameras, [tuple(to_dev(x) for x in gv) for gv in grads], twist=False)
+    _, ref32 = orc.backward(s.params, 0, s.cameras, grads, pinned="splats32", want_cam=True)
+    _, ref64 = orc.backward(s.params, 0, s.cameras, grads, pinned=True, want_cam=True)
+    check_cam_grad(gc.cpu().numpy(), ref32, ref64, "640x480/200k")

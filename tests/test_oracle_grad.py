@@ -135,11 +135,106 @@ def test_adam_matches_torch(orc):
 
 def test_fp32_splat_rounding_changes_gradients_only_at_rounding_level(orc):
     # the FP32-splat reference differs from the FP64 one only by the rounding
-    # of u, v, conic, opacity, colour and depth to float
+    # of u, v, conic, opacity, colour and depth to float: per element by up to
+    # about 1e-3 where the gradient is ill-conditioned (measured 1.2e-3 on this
+    # scene), in relative L2 by about 1e-6
     from parity import grad_violations
     s = scenes.small_128x96()
     grads = _masked_grads(orc, s, 1, margin_floor=1e-5)
     a = orc.backward(s.params, 0, s.cameras, grads, pinned=True)
     b = orc.backward(s.params, 0, s.cameras, grads, pinned="splats32")
-    for grp, (nbad, worst, l2) in grad_violations(b, a, rtol=1e-2).items():
+    for grp, (nbad, worst, l2) in grad_violations(b, a, rtol=3e-3).items():
         assert nbad == 0 and l2 < 1e-5, grp
+
+
+@pytest.mark.parametrize("k,deg", [(5, 0), (6, 3)])
+def test_splats32_matches_torch_at_fp32_splats(orc, k, deg):
+    """The oracle's "splats32" gradient is the FP64 derivative of the
+    compositing evaluated at the FP32 projection's splat values, chained
+    through the FP64 projection: here torch autograd forms the same thing
+    independently (the compositing of the FP32 splat values as float64 leaf
+    tensors, its gradient pushed back through the float64 torch projection),
+    on pixels away from every decision threshold."""
+    s = scenes.tiny_random(k, n=14, width=30, height=26, sh_degree=deg)
+    cam = s.cameras[0]
+    grads = _masked_grads(orc, s, k, margin_floor=1e-3)
+    g = orc.backward(s.params, deg, s.cameras, grads, pinned="splats32")
+    p = torch.tensor(s.params, dtype=torch.float64, requires_grad=True)
+    sp64 = torch_ref.project(p, deg, cam)
+    pr = orc.project(s.params, deg, cam, prec=32)
+    leaf = {}
+    for key, src in (("u", "u"), ("v", "v"), ("A", "A"), ("B", "B"), ("C", "C"), ("o", "o"), ("z", "z")):
+        leaf[key] = torch.tensor(np.where(pr["vis"], pr[src], sp64[key].detach().numpy()), requires_grad=True)
+    col32 = np.stack([pr["r"], pr["g"], pr["b_"]], 1)
+    leaf["col"] = torch.tensor(np.where(pr["vis"][:, None], col32, sp64["col"].detach().numpy()),
+                               requires_grad=True)
+    leaf["tz"], leaf["det"] = sp64["tz"].detach(), sp64["det"].detach()
+    rgb, depth, alpha = torch_ref.composite(leaf, cam)
+    gr, gd, ga = grads[0]
+    L = (torch.tensor(gr, dtype=torch.float64) * rgb).sum() + (torch.tensor(gd, dtype=torch.float64) * depth).sum() \
+        + (torch.tensor(ga, dtype=torch.float64) * alpha).sum()
+    keys = ["u", "v", "A", "B", "C", "o", "col", "z"]
+    dsp = torch.autograd.grad(L, [leaf[k2] for k2 in keys], allow_unused=True)
+    outs = [sp64[k2] for k2 in keys]
+    gsp = [d if d is not None else torch.zeros_like(o) for d, o in zip(dsp, outs)]
+    torch.autograd.backward(outs, gsp)
+    ref = p.grad.numpy()
+    assert np.abs(ref).max() > 0
+    assert np.allclose(g, ref, rtol=1e-9, atol=1e-11 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("k,deg", [(15, 0), (16, 3)])
+def test_camera_gradient_matches_torch_autograd(orc, k, deg):
+    """The oracle's camera gradient (dL/dR, dL/dt of x_cam = R x + t) against
+    torch float64 autograd through the independent renderer."""
+    s = scenes.tiny_random(k, n=14, width=30, height=26, sh_degree=deg)
+    s.cameras = [scenes.look_at_camera([0.2, -0.1, -0.3], [0.05, 0.0, 2.0], 30, 26, 28.0)]
+    cam = s.cameras[0]
+    grads = _masked_grads(orc, s, k, margin_floor=1e-3)
+    _, gcam = orc.backward(s.params, deg, s.cameras, grads, pinned=False, want_cam=True)
+    p = torch.tensor(s.params, dtype=torch.float64)
+    Rt = torch.tensor(np.asarray(cam.R, np.float32).astype(np.float64), requires_grad=True)
+    tt = torch.tensor(np.asarray(cam.t, np.float32).astype(np.float64), requires_grad=True)
+    rgb, depth, alpha = torch_ref.render(p, deg, cam, pose_R=Rt, pose_t=tt)
+    gr, gd, ga = grads[0]
+    L = (torch.tensor(gr, dtype=torch.float64) * rgb).sum() + (torch.tensor(gd, dtype=torch.float64) * depth).sum() \
+        + (torch.tensor(ga, dtype=torch.float64) * alpha).sum()
+    L.backward()
+    ref = np.concatenate([Rt.grad.numpy().ravel(), tt.grad.numpy()])
+    assert np.abs(ref).max() > 0
+    assert np.allclose(gcam[0], ref, rtol=1e-9, atol=1e-11 * np.abs(ref).max()), (gcam[0], ref)
+
+
+def test_camera_gradient_matches_central_differences(orc):
+    """Each of the 12 camera entries (the rotation's nine entries taken as
+    free, as the forward uses them) against central differences of the FP64
+    oracle's render."""
+    from scenes import Camera
+    s = scenes.tiny_random(17, n=12, width=28, height=24, sh_degree=1)
+    cam = scenes.look_at_camera([0.15, 0.1, -0.25], [0.0, 0.05, 2.0], 28, 24, 26.0)
+    s.cameras = [cam]
+    grads = _masked_grads(orc, s, 17, margin_floor=1e-3)
+    _, gcam = orc.backward(s.params, 1, s.cameras, grads, pinned=False, want_cam=True)
+    base = np.concatenate([np.asarray(cam.R, np.float32).ravel(), np.asarray(cam.t, np.float32)])
+    checked = 0
+    for k in range(12):
+        # a camera step moves every splat: 2^-16 (exact in float for entries
+        # below 1) keeps every pixel's decisions where they are
+        h = 2.0 ** -16
+        vals = []
+        for sgn in (+1, -1, +2, -2):
+            x = base.astype(np.float64).copy()
+            x[k] += sgn * h
+            x = x.astype(np.float32)
+            c = Camera(x[:9].reshape(3, 3), x[9:], cam.fx, cam.fy, cam.cx, cam.cy, cam.width, cam.height)
+            r = orc.render(s.params, 1, c, mode="f64")
+            gr, gd, ga = grads[0]
+            vals.append((gr * r["rgb"]).sum() + (gd * r["depth"]).sum() + (ga * r["alpha"]).sum())
+        fd1 = (vals[0] - vals[1]) / (2 * h)
+        fd2 = (vals[2] - vals[3]) / (4 * h)
+        if abs(fd1 - fd2) > 1e-3 * max(abs(fd1), 1e-6):
+            continue
+        checked += 1
+        scale = max(abs(fd1), 1e-2 * np.abs(gcam[0]).max())
+        assert abs(gcam[0, k] - fd1) <= 1e-3 * scale, (k, gcam[0, k], fd1)
+    assert checked >= 11

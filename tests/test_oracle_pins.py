@@ -47,18 +47,78 @@ Y00 = 1.0 / math.sqrt(4.0 * math.pi)          # constant real spherical harmonic
 
 
 # --------------------------------------------------------------------------
-# Own FP32 exponential
+# FP32 exponential: exp(x) correctly rounded to float
 # --------------------------------------------------------------------------
 
-def test_exp32_within_two_ulp(orc):
+def exp_rounded_to_float(x):
+    """exp(x) rounded to the nearest float32 from a 60-digit decimal exp
+    (Python's decimal module: an arbitrary-precision library routine), by
+    comparing the exact value with the midpoints between neighbouring floats."""
+    from decimal import Decimal, localcontext
+    with localcontext() as ctx:
+        ctx.prec = 60
+        e = Decimal(float(x)).exp()
+        c = np.float32(float(e))
+        for _ in range(3):
+            up = np.nextafter(c, np.float32(np.inf))
+            dn = np.nextafter(c, np.float32(0))
+            if e > (Decimal(float(c)) + Decimal(float(up))) / 2:
+                c = up
+            elif c > 0 and e < (Decimal(float(c)) + Decimal(float(dn))) / 2:
+                c = dn
+            else:
+                break
+        return c
+
+
+def near_tie_inputs(lo_bits, hi_bits, below=2.0 ** -50):
+    """Floats (bit patterns in [lo_bits, hi_bits)) whose double-precision exp
+    lies within `below` (relative) of a midpoint between two floats."""
+    x = np.arange(lo_bits, hi_bits, dtype=np.uint32).view(np.float32)
+    y = np.exp(x.astype(np.float64))
+    f = y.astype(np.float32)
+    nb = np.where(y >= f, np.nextafter(f, np.float32(np.inf)), np.nextafter(f, np.float32(-np.inf)))
+    d = np.abs(y - 0.5 * (f.astype(np.float64) + nb)) / y
+    return x[d < below]
+
+
+def test_exp32_correctly_rounded(orc):
+    """The oracle's FP32 exp equals exp(x) correctly rounded to float on random
+    inputs across the whole finite range, on the activation ranges, at special
+    values, and on inputs whose double exp sits within 2^-50 of a rounding
+    midpoint (where the oracle falls back to the long double exp)."""
     rng = np.random.default_rng(1)
-    x = np.concatenate([rng.uniform(-87, 88, 500_000), rng.uniform(-12, 1, 500_000)]).astype(np.float32)
-    y = orc.exp32(x).astype(np.float64)
-    ref = np.exp(x.astype(np.float64))
-    ulp = np.spacing(ref.astype(np.float32)).astype(np.float64)
-    err = np.abs(y - ref) / ulp
-    assert err.max() <= 2.0, err.max()
+    ties = np.concatenate([near_tie_inputs(0x40000000, 0x40800000),     # [2, 4)
+                           near_tie_inputs(0xC0000000, 0xC0800000),     # [-4, -2)
+                           near_tie_inputs(0xB3000000, 0xB3400000)])    # around -2^-25
+    assert ties.size >= 2, ties
+    special = np.array([0.0, -0.0, 1.0, -1.0, 2.0 ** -25, -(2.0 ** -25), 2.0 ** -24, -(2.0 ** -24), 88.0, 88.72,
+                        -87.0, -103.0, -104.5, 1e-30, -1e-30], np.float32)
+    x = np.concatenate([rng.uniform(-104, 88.7, 4000), rng.uniform(-9, 7, 4000), rng.normal(-4, 0.7, 2000),
+                        rng.normal(0, 1, 2000)]).astype(np.float32)
+    x = np.concatenate([x, special, ties])
+    y, tie = orc.exp32(x, with_tie=True)
+    ref = np.array([exp_rounded_to_float(v) for v in x], np.float32)
+    bad = np.flatnonzero(y.view(np.uint32) != ref.view(np.uint32))
+    assert bad.size == 0, list(zip(x[bad], y[bad], ref[bad]))
+    # the long double exp decides every one of these far from a midpoint
+    assert np.all(tie[np.isfinite(tie)] > 2.0 ** -60)
     assert orc.exp32(np.array([0.0], np.float32))[0] == 1.0
+
+
+def test_activations_are_exp_and_sigmoid_in_float(orc):
+    """orc.activations: scale = exp32(log-scale) and opacity = 1 / (1 + exp32(-logit))
+    with one correctly rounded float operation per step (numpy float32 + and /)."""
+    rng = np.random.default_rng(2)
+    ls = rng.normal(-4, 0.7, 5000).astype(np.float32)
+    lg = rng.normal(0, 1, 5000).astype(np.float32)
+    s, o = orc.activations(ls, lg)
+    assert np.array_equal(s.view(np.uint32), orc.exp32(ls).view(np.uint32))
+    e = orc.exp32(-lg)
+    ref = np.float32(1.0) / (np.float32(1.0) + e)
+    assert ref.dtype == np.float32
+    assert np.array_equal(o.view(np.uint32), ref.view(np.uint32))
+    assert np.all((o > 0) & (o < 1))
 
 
 # --------------------------------------------------------------------------
@@ -378,6 +438,43 @@ def test_p7_prefilter_equals_brute_force(orc, which):
         assert np.array_equal(a[k], b[k]), k
 
 
+@pytest.mark.parametrize("mode", ["f32", "f64pin", "f64"])
+def test_window_render_equals_whole_render(orc, mode):
+    """A window (and a row subset of it) renders exactly the pixels of the
+    whole render: every pixel is composited on its own."""
+    s = scenes.tiny_random(6, n=40, width=45, height=37)
+    full = orc.render(s.params, 0, s.cameras[0], mode=mode)
+    for win in [(5, 3, 40, 30), (0, 0, 45, 37, 4), (7, 2, 19, 37, 3)]:
+        part = orc.render(s.params, 0, s.cameras[0], mode=mode, window=win)
+        x0, y0, x1, y1 = win[:4]
+        step = win[4] if len(win) > 4 else 1
+        sel = np.zeros((37, 45), bool)
+        sel[y0:y1:step, x0:x1] = True
+        for k in ("depth", "alpha", "tfinal", "ncomp", "margin"):
+            assert np.array_equal(part[k][sel], full[k][sel]), (k, win)
+        assert np.array_equal(part["rgb"][:, sel], full["rgb"][:, sel])
+        assert (part["alpha"][~sel] == 0).all() and np.isinf(part["margin"][~sel]).all()
+
+
+def test_window_backward_equals_zeroed_upstream(orc):
+    """Walking only a window's pixels equals the whole backward with the
+    upstream gradient zeroed outside the window (same terms, other order)."""
+    s = scenes.tiny_random(7, n=30, width=40, height=30)
+    cams = [s.cameras[0], identity_camera(40, 30, 28.0, cx=19.0, cy=14.0)]
+    grads = scenes.random_image_grads(3, cams)
+    wins = [(4, 2, 33, 29, 3), (10, 0, 40, 20)]
+    zeroed = []
+    for (gr, gd, ga), w in zip(grads, wins):
+        sel = np.zeros((30, 40), bool)
+        sel[w[1]:w[3]:(w[4] if len(w) > 4 else 1), w[0]:w[2]] = True
+        zeroed.append((gr * sel[None], gd * sel, ga * sel))
+    for pinned in (True, "splats32", False):
+        a = orc.backward(s.params, 0, cams, grads, pinned=pinned, windows=wins)
+        b = orc.backward(s.params, 0, cams, zeroed, pinned=pinned)
+        assert np.abs(b).max() > 0
+        assert np.allclose(a, b, rtol=1e-12, atol=1e-15 * np.abs(b).max()), pinned
+
+
 def test_tile_list_brute_force(orc):
     s = scenes.tiny_random(4, n=30, width=45, height=37)
     cams = [s.cameras[0], identity_camera(29, 21, 25.0)]
@@ -442,3 +539,47 @@ def test_fp32_close_to_fp64(orc):
     b = orc.render(s.params, 0, s.cameras[0], mode="f64pin")
     assert np.abs(a["rgb"] - b["rgb"]).max() < 1e-4
     assert np.abs(a["depth"] - b["depth"]).max() < 5e-4
+
+
+# --------------------------------------------------------------------------
+# Keyframe insertion
+# --------------------------------------------------------------------------
+
+def test_densify_seeds_reproject_to_their_pixels(orc):
+    """Every seeded Gaussian projects back to its pixel centre at the
+    observed depth, has the observed colour, and a scale of scale_factor grid
+    cells at that depth (the FP64 projection)."""
+    rng = np.random.default_rng(31)
+    cam = scenes.look_at_camera([0.3, -0.2, -0.4], [0.1, 0.0, 2.5], 50, 40, 45.0)
+    depth = rng.uniform(1.0, 4.0, (40, 50)).astype(np.float32)
+    rgb = rng.uniform(0.0, 1.0, (3, 40, 50)).astype(np.float32)
+    new, pix = orc.densify(1, cam, rgb, depth, step=3, scale_factor=0.7)
+    assert new.shape[1] == len(range(0, 40, 3)) * len(range(0, 50, 3))
+    pr = orc.project(new.astype(np.float32), 1, cam, prec=64)
+    # the means go through float32 here: reprojection to 1e-5 px
+    assert np.allclose(pr["u"], pix[:, 0] + 0.5, atol=1e-4) and np.allclose(pr["v"], pix[:, 1] + 0.5, atol=1e-4)
+    assert np.allclose(pr["z"], depth[pix[:, 1], pix[:, 0]], rtol=1e-6)
+    col = np.stack([pr["r"], pr["g"], pr["b_"]])
+    assert np.allclose(col, rgb[:, pix[:, 1], pix[:, 0]], atol=1e-6)
+    s = np.exp(new[3])
+    assert np.allclose(s * 0.5 * (cam.fx + cam.fy) / depth[pix[:, 1], pix[:, 0]], 0.7 * 3)
+    assert (new[6] == 1).all() and (new[7:10] == 0).all() and (new[14:] == 0).all()
+
+
+def test_densify_selection_rule(orc):
+    """Seeding pixels: valid depth (NaN, too near and too far excluded) and,
+    with coverage, coverage below the threshold; in row-major grid order."""
+    cam = identity_camera(8, 6, 10.0)
+    depth = np.full((6, 8), 2.0, np.float32)
+    depth[0, 0] = np.nan
+    depth[0, 2] = 0.1
+    depth[2, 4] = 50.0
+    cov = np.zeros((6, 8), np.float32)
+    cov[4, 0] = 0.5
+    cov[4, 2] = 0.49
+    rgb = np.full((3, 6, 8), 0.5, np.float32)
+    new, pix = orc.densify(0, cam, rgb, depth, coverage=cov, step=2, depth_min=0.2, depth_max=10.0, alpha_below=0.5)
+    expect = [(x, y) for y in (0, 2, 4) for x in (0, 2, 4, 6)
+              if not ((x, y) in [(0, 0), (2, 0), (4, 2), (0, 4)])]
+    assert [tuple(p) for p in pix] == expect
+    assert np.allclose(new[11:14], 0.0)

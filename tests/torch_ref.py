@@ -51,8 +51,11 @@ def quat_to_rot(q):
     return R
 
 
-def render(params, deg, cam, bg=(0.0, 0.0, 0.0), znear=0.2):
-    """params: float64 tensor [P, N] (may require grad). Returns rgb [3,H,W], depth, alpha."""
+def project(params, deg, cam, pose_R=None, pose_t=None):
+    """Screen-space splats of every Gaussian, float64 and differentiable:
+    dict with u, v, A, B, C (conic), o (opacity), col [n, 3], z, and the
+    culling inputs tz and det. pose_R [3, 3] and pose_t [3] (float64 tensors,
+    may require grad) replace the camera's pose."""
     P, n = params.shape
     mean = params[0:3].T
     scale = torch.exp(params[3:6].T)
@@ -60,8 +63,8 @@ def render(params, deg, cam, bg=(0.0, 0.0, 0.0), znear=0.2):
     opac = torch.sigmoid(params[10])
     K = (deg + 1) ** 2
     sh = params[11:].T.reshape(n, K, 3)
-    W = torch.tensor(cam.R, dtype=torch.float64)
-    t = torch.tensor(cam.t, dtype=torch.float64)
+    W = torch.tensor(cam.R, dtype=torch.float64) if pose_R is None else pose_R
+    t = torch.tensor(cam.t, dtype=torch.float64) if pose_t is None else pose_t
     fx, fy, cx, cy = cam.fx, cam.fy, cam.cx, cam.cy
     Wd, Hd = cam.width, cam.height
     pc = mean @ W.T + t
@@ -88,7 +91,16 @@ def render(params, deg, cam, bg=(0.0, 0.0, 0.0), znear=0.2):
     d = dvec / dvec.norm(dim=1, keepdim=True)
     Y = sh_poly(deg, d)
     col = torch.clamp((Y[:, :, None] * sh).sum(1) + 0.5, min=0.0)
-    order = torch.argsort(tz.detach())
+    return dict(u=u, v=v, A=A, B=B, C=C, o=opac, col=col, z=tz, tz=tz, det=det)
+
+
+def composite(sp, cam, bg=(0.0, 0.0, 0.0), znear=0.2):
+    """Front-to-back compositing of given splat values (dict as project returns),
+    vectorised over the pixels. Returns rgb [3,H,W], depth, alpha."""
+    u, v, A, B, C, opac, col, z = (sp[k] for k in ("u", "v", "A", "B", "C", "o", "col", "z"))
+    tz, det = sp["tz"], sp["det"]
+    Wd, Hd = cam.width, cam.height
+    order = torch.argsort(z.detach())
     ys, xs = torch.meshgrid(torch.arange(Hd, dtype=torch.float64) + 0.5,
                             torch.arange(Wd, dtype=torch.float64) + 0.5, indexing="ij")
     T = torch.ones(Hd, Wd, dtype=torch.float64)
@@ -96,7 +108,7 @@ def render(params, deg, cam, bg=(0.0, 0.0, 0.0), znear=0.2):
     Cacc = torch.zeros(3, Hd, Wd, dtype=torch.float64)
     D = torch.zeros(Hd, Wd, dtype=torch.float64)
     for i in order.tolist():
-        if not (tz[i].item() >= znear) or not (det[i].item() > 0):
+        if not (float(tz[i].detach()) >= znear) or not (float(det[i].detach()) > 0):
             continue
         dx = u[i] - xs
         dy = v[i] - ys
@@ -110,7 +122,13 @@ def render(params, deg, cam, bg=(0.0, 0.0, 0.0), znear=0.2):
         done = done | stop
         w = torch.where(use, alpha * T, torch.zeros_like(T))
         Cacc = Cacc + w[None] * col[i][:, None, None]
-        D = D + w * tz[i]
+        D = D + w * z[i]
         T = torch.where(use, Tn, T)
     bgt = torch.tensor(bg, dtype=torch.float64)[:, None, None]
     return Cacc + T[None] * bgt, D, 1 - T
+
+
+def render(params, deg, cam, bg=(0.0, 0.0, 0.0), znear=0.2, pose_R=None, pose_t=None):
+    """params: float64 tensor [P, N] (may require grad). Returns rgb [3,H,W], depth, alpha.
+    pose_R, pose_t: optional pose tensors (may require grad) in place of the camera's."""
+    return composite(project(params, deg, cam, pose_R, pose_t), cam, bg, znear)
