@@ -85,7 +85,9 @@ def parse():
     ap.add_argument("--fuse-blend", type=int, default=0,
                     help="graph mode: 0 = automatic, 1 = blend forward and backward in one launch, -1 = two launches")
     ap.add_argument("--tile-order", type=int, default=0,
-                    help="0 = automatic, 1 = longest tile lists first, 2 = tile order")
+                    help="0 = automatic, 1 = longest tile lists first, 2 = tile order, 3 = balanced over the CUs")
+    ap.add_argument("--backward-schedule", type=int, default=0,
+                    help="blend backward: 0 = pixel-parallel, 1 = splat-parallel (whole lists, two blend launches)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use --tile/--ppt/--batch-depth instead of the autotuner's choice")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -179,7 +181,7 @@ def main():
     deg = scene.sh_degree
     R = Rasterizer(tile_w=tw, tile_h=th, pixels_per_thread=args.ppt, batch_depth=args.batch_depth,
                    tile_order=args.tile_order, chunk_len=args.chunk_len, max_chunks=args.max_chunks,
-                   fuse_blend=args.fuse_blend, depth_sort=args.depth_sort)
+                   fuse_blend=args.fuse_blend, depth_sort=args.depth_sort, backward_schedule=args.backward_schedule)
     dev = torch.device("cuda:0")
     if args.calibrate_copy:
         src = torch.ones(64 * 1024 * 1024, device=dev)
@@ -213,7 +215,8 @@ def main():
         R.close()
         R = Rasterizer(tile_w=tuned["tile_w"], tile_h=tuned["tile_h"], pixels_per_thread=tuned["pixels_per_thread"],
                        batch_depth=tuned["batch_depth"], tile_order=args.tile_order, chunk_len=tuned["chunk_len"],
-                       max_chunks=tuned["max_chunks"], fuse_blend=args.fuse_blend, depth_sort=args.depth_sort)
+                       max_chunks=tuned["max_chunks"], fuse_blend=args.fuse_blend, depth_sort=args.depth_sort,
+                       backward_schedule=args.backward_schedule)
         outs = R.alloc_images(cams, dev)
     from paper_2509_06433_amd import _lib
     adam = dict(m=m, v=v, lr=lrs, beta1=0.9, beta2=0.999, eps=1e-15) if use_adam else None
@@ -350,7 +353,8 @@ def main():
                    "chunk_len": {0: "auto", -1: "whole list"}.get(R.chunk_len, R.chunk_len),
                    "max_chunks": R.max_chunks or "default",
                    "blend_launch": "fused" if dominant == "blend" else "separate",
-                   "autotuned": tuned is not None, "tile_order": ["auto", "longest first", "index"][R.tile_order],
+                   "backward_schedule": ["pixel-parallel", "splat-parallel"][R.backward_schedule],
+                   "autotuned": tuned is not None, "tile_order": ["auto", "longest first", "index", "balanced"][R.tile_order],
                    "adam": use_adam, "mode": args.mode,
                    f"{other}_iters_s": round(1000.0 / other_ms, 3) if other_ms else None,
                    "render_mpix_s": round(mpix, 2) if mpix else None, "render_mpix_s_from": render_from,

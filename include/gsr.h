@@ -75,7 +75,11 @@ typedef struct {
   int32_t pixels_per_thread; /* blend kernels: 0 = default (1), 1, or 2 (tiles of >= 128 pixels) */
   int32_t tile_order;       /* order in which blend workgroups take tiles: 0 = automatic (longest
                                list first when several views are rendered together, else
-                               tile order), 1 = longest list first, 2 = tile order */
+                               tile order), 1 = longest list first, 2 = tile order, 3 = balanced:
+                               tiles sorted by weight (the walk length the previous render of
+                               the same buffers recorded, else the list length) and dealt to
+                               the CUs in snake order, so each CU starts with heavy and light
+                               tiles (at most 8192 tiles, else as 1). Images are identical. */
   int32_t chunk_len;        /* work unit of the blend backward, in list positions: 0 = automatic
                                (chunks of 128 when a launch covers fewer than 4096 tiles, else
                                whole lists), -1 = whole tile lists, else a multiple of 16 up to

@@ -58,7 +58,8 @@ def lib():
                                  F64P, F64P, F64P, F64P, I32P, F64P, ctypes.c_void_p]
         L.orc_render.restype = c_int
         L.orc_backward.argtypes = [c_int, F32P, c_i64, c_i64, c_int, c_int, F32P, I32P, c_f, F32P,
-                                   F32P, F32P, F32P, F64P, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+                                   F32P, F32P, F32P, F64P, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_void_p]
         L.orc_backward.restype = c_int
         _lib = L
     return _lib
@@ -183,7 +184,7 @@ def render(params, sh_degree, cam, mode="f32", prefilter=True, bg=(0.0, 0.0, 0.0
 
 
 def backward(params, sh_degree, cams, grads, pinned=True, bg=(0.0, 0.0, 0.0), znear=0.2, want_2d=False,
-             windows=None, want_cam=False):
+             windows=None, want_cam=False, want_abs=False):
     """FP64 analytic gradient of sum_v <grads_v, (rgb_v, depth_v, alpha_v)> with respect
     to the parameters [P, N]. grads: list of (g_rgb [3,H,W], g_depth [H,W], g_alpha [H,W]).
     pinned: False = FP64 decisions; True = decisions from the FP32 recurrence;
@@ -192,7 +193,10 @@ def backward(params, sh_degree, cams, grads, pinned=True, bg=(0.0, 0.0, 0.0), zn
     window as render's (or None): only its pixels are walked, which equals the
     gradient with the upstream gradient zeroed outside it. want_cam: also
     return each view's camera gradient [V, 12] (dL/dR row-major, then dL/dt)
-    for x_cam = R x + t."""
+    for x_cam = R x + t. want_abs: also return [P, N], per parameter, the sum of
+    the magnitudes of the terms the gradient adds up (screen-space terms in
+    absolute value through the projection's Jacobian in absolute value):
+    |grad| <= abs, and abs / |grad| measures how much the sum cancels."""
     p = np.ascontiguousarray(params, np.float32)
     P, n = p.shape
     camf = np.ascontiguousarray(np.stack([_cam_floats(c) for c in cams]), np.float32)
@@ -210,16 +214,19 @@ def backward(params, sh_degree, cams, grads, pinned=True, bg=(0.0, 0.0, 0.0), zn
                                              for w, c in zip(windows, cams)]), np.int32)
     mode = 2 if pinned == "splats32" else int(bool(pinned))
     gcam = np.zeros((len(cams), 12), np.float64) if want_cam else None
+    gabs = np.zeros((P, n), np.float64) if want_abs else None
     rc = lib().orc_backward(mode, p, n, n, int(sh_degree), len(cams), camf, wh, float(znear),
                             np.ascontiguousarray(bg, np.float32), grgb, gdep, galp, grad,
                             g2.ctypes.data if want_2d else None, win.ctypes.data if win is not None else None,
-                            gcam.ctypes.data if want_cam else None)
+                            gcam.ctypes.data if want_cam else None, gabs.ctypes.data if want_abs else None)
     assert rc == 0
     out = (grad,)
     if want_2d:
         out += (g2,)
     if want_cam:
         out += (gcam,)
+    if want_abs:
+        out += (gabs,)
     return out if len(out) > 1 else grad
 
 

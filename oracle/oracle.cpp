@@ -494,14 +494,17 @@ enum { G2_U = 0, G2_V, G2_A, G2_B, G2_C, G2_O, G2_R, G2_G, G2_BL, G2_Z, G2_N };
 // the camera-space mean, through T = J R (the screen covariance J R Sigma
 // R^T J^T) and, for view-dependent colour, through the camera centre -R^T t;
 // t through the mean and the centre.
+// grad[plane * gstride + gi] += ...; gi is the Gaussian's index in grad (its
+// index i in the parameters unless the caller redirects the output).
 void project_backward_one(const float* P, int64_t stride, int64_t i, int deg, const Cam<double>& cam,
                           const Proj<double>& g, const double* g2, double* grad, int64_t gstride,
-                          double* gcam = nullptr) {
+                          double* gcam = nullptr, int64_t gi = -1) {
+  if (gi < 0) gi = i;
   const double gu = g2[G2_U], gv = g2[G2_V], gA = g2[G2_A], gB = g2[G2_B], gC = g2[G2_C];
   const double gz = g2[G2_Z];
   double gcol[3] = {g2[G2_R], g2[G2_G], g2[G2_BL]};
   // opacity: o = sigmoid(l)
-  grad[10 * gstride + i] += g2[G2_O] * g.o * (1.0 - g.o);
+  grad[10 * gstride + gi] += g2[G2_O] * g.o * (1.0 - g.o);
   // colour: col = max(0, sum_k k_k Y_k(d) + 0.5)
   const int K = (deg + 1) * (deg + 1);
   Dual3 dd[3];
@@ -512,7 +515,7 @@ void project_backward_one(const float* P, int64_t stride, int64_t i, int deg, co
   for (int ch = 0; ch < 3; ++ch) {
     if (g.colraw[ch] < 0.0) continue;
     for (int k = 0; k < K; ++k) {
-      grad[(11 + 3 * k + ch) * gstride + i] += gcol[ch] * Y[k].v;
+      grad[(11 + 3 * k + ch) * gstride + gi] += gcol[ch] * Y[k].v;
       if (deg > 0) {
         double coef = (double)P[(11 + 3 * k + ch) * stride + i];
         for (int j = 0; j < 3; ++j) gdir[j] += gcol[ch] * coef * Y[k].d[j];
@@ -585,7 +588,7 @@ void project_backward_one(const float* P, int64_t stride, int64_t i, int deg, co
   gtz += gz;
   // t = W mean + t_cw
   for (int j = 0; j < 3; ++j) gmean[j] += W[0 * 3 + j] * gtx + W[1 * 3 + j] * gty + W[2 * 3 + j] * gtz;
-  for (int j = 0; j < 3; ++j) grad[j * gstride + i] += gmean[j];
+  for (int j = 0; j < 3; ++j) grad[j * gstride + gi] += gmean[j];
   if (gcam) {
     const double mu[3] = {(double)P[0 * stride + i], (double)P[1 * stride + i], (double)P[2 * stride + i]};
     const double gt[3] = {gtx, gty, gtz};
@@ -622,7 +625,7 @@ void project_backward_one(const float* P, int64_t stride, int64_t i, int deg, co
     for (int k = 0; k < 3; ++k) gR[r * 3 + k] = gM[r * 3 + k] * g.s[k];
   for (int k = 0; k < 3; ++k) {
     double gs = gM[0 * 3 + k] * g.R[0 * 3 + k] + gM[1 * 3 + k] * g.R[1 * 3 + k] + gM[2 * 3 + k] * g.R[2 * 3 + k];
-    grad[(3 + k) * gstride + i] += gs * g.s[k];     // s = exp(log-scale)
+    grad[(3 + k) * gstride + gi] += gs * g.s[k];     // s = exp(log-scale)
   }
   // R(q^) for unit q^ = (w, x, y, z)
   const double w = g.qh[0], x = g.qh[1], y = g.qh[2], z = g.qh[3];
@@ -633,7 +636,7 @@ void project_backward_one(const float* P, int64_t stride, int64_t i, int deg, co
   // q^ = q/|q|: dL/dq = (dL/dq^ - q^ (q^ . dL/dq^)) / |q|
   double dq[4] = {gw, gx, gy, gzq};
   double dot = w * gw + x * gx + y * gy + z * gzq;
-  for (int k = 0; k < 4; ++k) grad[(6 + k) * gstride + i] += (dq[k] - g.qh[k] * dot) / g.qn;
+  for (int k = 0; k < 4; ++k) grad[(6 + k) * gstride + gi] += (dq[k] - g.qh[k] * dot) / g.qn;
 }
 
 // Blend backward for one view: accumulates screen-space gradients g2[n][10].
@@ -642,7 +645,7 @@ void project_backward_one(const float* P, int64_t stride, int64_t i, int deg, co
 void blend_backward_view(const float* P, int64_t n, int64_t stride, int deg, const float* camf, int width, int height,
                          float znear, const float* bg, const float* grgb, const float* gdepth, const float* galpha,
                          bool pinned, bool splats32, std::vector<double>& g2out, std::vector<Proj<double>>& p64out,
-                         const PixelSet& ps) {
+                         const PixelSet& ps, std::vector<double>* absout = nullptr) {
   Cam<float> c32 = make_cam<float>(camf, width, height);
   Cam<double> c64 = make_cam<double>(camf, width, height);
   std::vector<Proj<float>> p32 = project_all<float>(P, n, stride, deg, c32, znear);
@@ -669,9 +672,11 @@ void blend_backward_view(const float* P, int64_t n, int64_t stride, int deg, con
   const int64_t HW = (int64_t)width * height;
   int nt = omp_get_max_threads();
   std::vector<std::vector<double>> acc(nt, std::vector<double>((size_t)n * G2_N, 0.0));
+  std::vector<std::vector<double>> aacc(absout ? nt : 0, std::vector<double>((size_t)n * G2_N, 0.0));
 #pragma omp parallel
   {
     std::vector<double>& mine = acc[omp_get_thread_num()];
+    double* amine = absout ? aacc[omp_get_thread_num()].data() : nullptr;
     std::vector<Composited> trace;
 #pragma omp for schedule(dynamic, 1)
     for (int py = ps.y0; py < ps.y1; py += ps.row_step) {
@@ -704,6 +709,25 @@ void blend_backward_view(const float* P, int64_t n, int64_t stride, int deg, con
           acc_i[G2_BL] += wgt * gc[2];
           acc_i[G2_Z] += wgt * gd;
           const double galpha_k = T * (xk - S) + Tfin * bgterm / (1.0 - al);
+          // the magnitudes of the summands (for the bound on float summation
+          // error): each term as the method forms it, in absolute value
+          const double galpha_abs = T * (std::fabs(xk) + std::fabs(S)) + std::fabs(Tfin * bgterm / (1.0 - al));
+          if (amine) {
+            double* ai = amine + (size_t)e.idx * G2_N;
+            ai[G2_R] += std::fabs(wgt * gc[0]);
+            ai[G2_G] += std::fabs(wgt * gc[1]);
+            ai[G2_BL] += std::fabs(wgt * gc[2]);
+            ai[G2_Z] += std::fabs(wgt * gd);
+            if (!e.clamped) {
+              const double gp = galpha_abs * al, dx = std::fabs(e.dx), dy = std::fabs(e.dy);
+              ai[G2_O] += galpha_abs * e.G;
+              ai[G2_U] += gp * (std::fabs(g.A) * dx + std::fabs(g.B) * dy);
+              ai[G2_V] += gp * (std::fabs(g.B) * dx + std::fabs(g.C) * dy);
+              ai[G2_A] += 0.5 * gp * dx * dx;
+              ai[G2_B] += gp * dx * dy;
+              ai[G2_C] += 0.5 * gp * dy * dy;
+            }
+          }
           S = al * xk + (1.0 - al) * S;
           if (e.clamped) continue;
           // alpha = o exp(power)
@@ -722,6 +746,11 @@ void blend_backward_view(const float* P, int64_t n, int64_t stride, int deg, con
   g2out.assign((size_t)n * G2_N, 0.0);
   for (int t = 0; t < nt; ++t)
     for (size_t k = 0; k < g2out.size(); ++k) g2out[k] += acc[t][k];
+  if (absout) {
+    absout->assign((size_t)n * G2_N, 0.0);
+    for (int t = 0; t < nt; ++t)
+      for (size_t k = 0; k < absout->size(); ++k) (*absout)[k] += aacc[t][k];
+  }
   p64out.swap(p64);
 }
 
@@ -858,22 +887,29 @@ int orc_render(int mode, int prefilter, const float* params, int64_t n, int64_t 
 // windows ([V][5] as orc_render's window, or null): only those pixels are
 // walked, as if the upstream gradient were zero elsewhere. gcam ([V][12] or
 // null) receives each view's camera gradient: dL/dR row-major, then dL/dt.
+// gabs ([P][n] or null) receives, per parameter, the sum over the pairs of
+// the magnitudes of the terms a float implementation adds up (each
+// screen-space term in absolute value, carried through the projection's
+// Jacobian in absolute value): a bound on the gradient (|grad| <= gabs) whose
+// size, next to |grad|, says how much the sum cancels.
 int orc_backward(int pinned, const float* params, int64_t n, int64_t stride, int deg, int num_views,
                  const float* cams, const int32_t* wh, float znear, const float* bg, const float* grgb,
                  const float* gdepth, const float* galpha, double* grad, double* g2, const int32_t* windows,
-                 double* gcam) {
+                 double* gcam, double* gabs) {
   const int P = 11 + 3 * (deg + 1) * (deg + 1);
   for (int64_t k = 0; k < (int64_t)P * n; ++k) grad[k] = 0.0;
   if (gcam)
     for (int k = 0; k < 12 * num_views; ++k) gcam[k] = 0.0;
+  if (gabs)
+    for (int64_t k = 0; k < (int64_t)P * n; ++k) gabs[k] = 0.0;
   int64_t off = 0;
   for (int v = 0; v < num_views; ++v) {
     const int W = wh[2 * v], H = wh[2 * v + 1];
-    std::vector<double> g2v;
+    std::vector<double> g2v, absv;
     std::vector<Proj<double>> p64;
     blend_backward_view(params, n, stride, deg, cams + 16 * v, W, H, znear, bg, grgb + 3 * off, gdepth + off,
                         galpha + off, pinned != 0, pinned == 2, g2v, p64,
-                        pixel_set(windows ? windows + 5 * v : nullptr, W, H));
+                        pixel_set(windows ? windows + 5 * v : nullptr, W, H), gabs ? &absv : nullptr);
     if (g2) std::memcpy(g2 + (size_t)v * n * G2_N, g2v.data(), sizeof(double) * n * G2_N);
     Cam<double> c64 = make_cam<double>(cams + 16 * v, W, H);
     const int nt = omp_get_max_threads();
@@ -891,6 +927,25 @@ int orc_backward(int pinned, const float* params, int64_t n, int64_t stride, int
     if (gcam)
       for (int t = 0; t < nt; ++t)
         for (int k = 0; k < 12; ++k) gcam[v * 12 + k] += gc[(size_t)t * 12 + k];
+    if (gabs) {
+      // the summands' magnitudes carried to the parameters through the
+      // projection's Jacobian in absolute value, column by column:
+      // gabs += sum_k |J^T e_k| abs_k
+#pragma omp parallel for schedule(static)
+      for (int64_t i = 0; i < n; ++i) {
+        if (!p64[i].vis) continue;
+        const double* ai = &absv[(size_t)i * G2_N];
+        std::vector<double> col(P);
+        for (int k = 0; k < G2_N; ++k) {
+          if (ai[k] == 0.0) continue;
+          double unit[G2_N] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+          unit[k] = 1.0;
+          std::fill(col.begin(), col.end(), 0.0);
+          project_backward_one(params, stride, i, deg, c64, p64[i], unit, col.data(), 1, nullptr, 0);
+          for (int q = 0; q < P; ++q) gabs[(int64_t)q * n + i] += std::fabs(col[q]) * ai[k];
+        }
+      }
+    }
     off += (int64_t)W * H;
   }
   return 0;

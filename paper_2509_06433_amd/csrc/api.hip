@@ -156,7 +156,11 @@ int launch_front(gsr_ctx* ctx, Buffers& B, RenderPlan& P, const float* params, h
 // Longest-list-first tile order: worth its extra launch when views of uneven
 // visibility share a launch (measured: +18% on 8 views, -4% on one view).
 static bool use_lpt(const gsr_ctx* ctx, const RenderPlan& P) {
-  return ctx->tile_order == 1 || (ctx->tile_order == 0 && P.nv > 1);
+  return ctx->tile_order == 1 || (ctx->tile_order == 0 && P.nv > 1) ||
+         (ctx->tile_order == 3 && !tile_balance_supported(P.ntiles));
+}
+static bool use_balance(const gsr_ctx* ctx, const RenderPlan& P) {
+  return ctx->tile_order == 3 && tile_balance_supported(P.ntiles);
 }
 
 static void set_chunking(const gsr_ctx* ctx, Buffers& B, const RenderPlan& P, BlendArgs& ba) {
@@ -223,6 +227,10 @@ int launch_back(gsr_ctx* ctx, Buffers& B, RenderPlan& P, hipStream_t st, const F
     StageTimer tm(ctx, GSR_STAGE_RANGES, st);
     launch_tile_ranges(ik, totals, P.capacity, as<uint2>(B.ranges), P.ntiles, false, st);
     if (use_lpt(ctx, P)) launch_tile_order(as<uint2>(B.ranges), P.ntiles, as<uint32_t>(B.order), st);
+    // the tile_last the previous render of these buffers left (a weight only)
+    if (use_balance(ctx, P))
+      launch_tile_balance(as<uint2>(B.ranges), as<uint32_t>(B.tile_last), P.ntiles, ctx->num_cus,
+                          as<uint32_t>(B.order), st);
   }
   CHECK_LAUNCH(ctx);
   if (per_tile_depth(ctx, P)) {
@@ -238,7 +246,7 @@ int launch_back(gsr_ctx* ctx, Buffers& B, RenderPlan& P, hipStream_t st, const F
   ba.images = as<ViewImages>(B.images);
   ba.num_views = P.nv;
   ba.num_tiles = (int32_t)P.ntiles;
-  ba.order = use_lpt(ctx, P) ? as<uint32_t>(B.order) : nullptr;
+  ba.order = (use_lpt(ctx, P) || use_balance(ctx, P)) ? as<uint32_t>(B.order) : nullptr;
   ba.ranges = as<uint2>(B.ranges);
   ba.inst_vals = iv;
   ba.splats = as<Splat>(B.splats);
@@ -281,7 +289,7 @@ int launch_bwd(gsr_ctx* ctx, Buffers& B, const RenderPlan& P, const float* param
   ba.images = as<ViewImages>(B.images2);
   ba.num_views = P.nv;
   ba.num_tiles = (int32_t)P.ntiles;
-  ba.order = use_lpt(ctx, P) ? as<uint32_t>(B.order) : nullptr;
+  ba.order = (use_lpt(ctx, P) || use_balance(ctx, P)) ? as<uint32_t>(B.order) : nullptr;
   ba.ranges = as<uint2>(B.ranges);
   ba.inst_vals = P.inst_vals;
   ba.splats = as<Splat>(B.splats);
@@ -447,7 +455,7 @@ int gsr_create(gsr_ctx** out, const gsr_options* opt) {
       return GSR_ERR_UNSUPPORTED;
     }
     ctx->ppt = opt->pixels_per_thread == 0 ? 1 : opt->pixels_per_thread;
-    if (opt->tile_order < 0 || opt->tile_order > 2) {
+    if (opt->tile_order < 0 || opt->tile_order > 3) {
       delete ctx;
       return GSR_ERR_UNSUPPORTED;
     }
@@ -478,6 +486,13 @@ int gsr_create(gsr_ctx** out, const gsr_options* opt) {
     ctx->znear = opt->znear > 0.f ? opt->znear : 0.2f;
   }
   ctx->fused_resident = blend_fused_resident(ctx->tile_w, ctx->tile_h, ctx->ppt);
+  {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
+      ctx->num_cus = cus;
+    (void)hipGetLastError();
+  }
   hipError_t e = hipHostMalloc((void**)&ctx->host_total, 64, hipHostMallocDefault);
   for (int k = 0; k < kSlots && e == hipSuccess; ++k) {
     e = hipHostMalloc(&ctx->slots[k], kSlotBytes, hipHostMallocDefault);

@@ -112,7 +112,8 @@ struct gsr_ctx {
   int tile_w = 16, tile_h = 16;
   int ppt = 1;                          // pixels per thread in the blend kernels
   int batch_depth = 0;                  // backward batch depth (0 = default)
-  int tile_order = 0;                   // 0 auto, 1 longest list first, 2 tile order
+  int tile_order = 0;                   // 0 auto, 1 longest list first, 2 tile order, 3 balanced over the CUs
+  int num_cus = 256;                    // compute units of the context's device
   int chunk_len = 0;                    // backward work unit in list positions: 0 automatic, -1 whole lists
   int max_chunks = 4;                   // chunks per tile (the last takes the rest)
   int fuse_blend = 0;                   // mapping iteration: 0 automatic, 1 fused, -1 two launches

@@ -208,6 +208,13 @@ void launch_tile_ranges(const uint32_t* keys, const uint32_t* n_dev, int64_t cou
 // equal floor(log2(length)) (order within a class unspecified), so that the
 // longest tiles start first and the tail of a launch holds the short ones.
 void launch_tile_order(const uint2* ranges, int64_t num_tiles, uint32_t* order, hipStream_t st);
+// order[0..num_tiles) = the tiles dealt to rounds of ncu workgroups in snake
+// order of decreasing weight (tile_last[t] when it is in (0, list length],
+// else the list length; tile_last may be null), so that the tiles a CU starts
+// with mix heavy and light ones. At most 8192 tiles (tile_balance_supported).
+bool tile_balance_supported(int64_t num_tiles);
+void launch_tile_balance(const uint2* ranges, const uint32_t* tile_last, int64_t num_tiles, int ncu, uint32_t* order,
+                         hipStream_t st);
 // Sorts each tile's instances (whose splats arrive in index order) by the raw
 // bits of the splat's depth (zkey, per splat, from the projection), stably:
 // the list order becomes (tile, z bits,

@@ -190,20 +190,18 @@ __device__ __forceinline__ bool degenerate_gaussian(const float* __restrict__ P,
   return !(ss > 0.0f) || !finitef(ss);
 }
 
-// Everything the projection computes for one (view, Gaussian).
-struct ProjState {
-  float s[3], qn, qh[4], R[9], M[9], Sig[9];
-  float tx, ty, tz, xi, yi;
-  bool xclamp, yclamp;
-  float J00, J02, J11, J12, Tm[6];
-  float a, b, c, det, A, B, C;
-  float u, v;
-  int x0, y0, x1, y1;
+// The part of a Gaussian's projection that no view changes: its mean and its
+// world covariance Sigma = R diag(s)^2 R^T from the unit quaternion and
+// exp(log-scale). Computed once per Gaussian however many views see it.
+struct GaussLocal {
+  float mx, my, mz;
+  float Sig[9];
 };
 
-// The projection contract: returns false if the Gaussian is culled.
-__device__ __forceinline__ bool project_geometry(const float* __restrict__ P, int64_t stride, int64_t i,
-                                                 const ViewDesc& V, float znear, ProjState& g) {
+// False if the Gaussian cannot be drawn (a non-finite value among planes
+// 0..10, a zero quaternion).
+__device__ __forceinline__ bool gaussian_local(const float* __restrict__ P, int64_t stride, int64_t i,
+                                               GaussLocal& L) {
   float raw[11];
 #pragma unroll
   for (int k = 0; k < 11; ++k) raw[k] = P[k * stride + i];
@@ -211,18 +209,20 @@ __device__ __forceinline__ bool project_geometry(const float* __restrict__ P, in
 #pragma unroll
   for (int k = 0; k < 11; ++k) ok = ok && finitef(raw[k]);
   if (!ok) return false;
-  const float mx = raw[0], my = raw[1], mz = raw[2];
+  L.mx = raw[0];
+  L.my = raw[1];
+  L.mz = raw[2];
+  float sc[3];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) g.s[k] = exp32_rn(raw[3 + k]);
+  for (int k = 0; k < 3; ++k) sc[k] = exp32_rn(raw[3 + k]);
   const float qw = raw[6], qx = raw[7], qy = raw[8], qz = raw[9];
   float ss = qw * qw + qx * qx;
   ss = ss + qy * qy;
   ss = ss + qz * qz;
   if (!(ss > 0.0f) || !finitef(ss)) return false;
-  g.qn = sqrt_rn(ss);
-  const float w = __fdiv_rn(qw, g.qn), x = __fdiv_rn(qx, g.qn), y = __fdiv_rn(qy, g.qn), z = __fdiv_rn(qz, g.qn);
-  g.qh[0] = w; g.qh[1] = x; g.qh[2] = y; g.qh[3] = z;
-  float* R = g.R;
+  const float qn = sqrt_rn(ss);
+  const float w = __fdiv_rn(qw, qn), x = __fdiv_rn(qx, qn), y = __fdiv_rn(qy, qn), z = __fdiv_rn(qz, qn);
+  float R[9], M[9];
   R[0] = 1.0f - 2.0f * (y * y + z * z);
   R[1] = 2.0f * (x * y - w * z);
   R[2] = 2.0f * (x * z + w * y);
@@ -235,14 +235,34 @@ __device__ __forceinline__ bool project_geometry(const float* __restrict__ P, in
 #pragma unroll
   for (int r = 0; r < 3; ++r)
 #pragma unroll
-    for (int k = 0; k < 3; ++k) g.M[r * 3 + k] = R[r * 3 + k] * g.s[k];
+    for (int k = 0; k < 3; ++k) M[r * 3 + k] = R[r * 3 + k] * sc[k];
 #pragma unroll
   for (int r = 0; r < 3; ++r)
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      float acc = g.M[r * 3 + 0] * g.M[k * 3 + 0] + g.M[r * 3 + 1] * g.M[k * 3 + 1];
-      g.Sig[r * 3 + k] = acc + g.M[r * 3 + 2] * g.M[k * 3 + 2];
+      float acc = M[r * 3 + 0] * M[k * 3 + 0] + M[r * 3 + 1] * M[k * 3 + 1];
+      L.Sig[r * 3 + k] = acc + M[r * 3 + 2] * M[k * 3 + 2];
     }
+  return true;
+}
+
+// Everything the projection computes for one (view, Gaussian).
+struct ProjState {
+  float Sig[9];
+  float tx, ty, tz, xi, yi;
+  bool xclamp, yclamp;
+  float J00, J02, J11, J12, Tm[6];
+  float a, b, c, det, A, B, C;
+  float u, v;
+  int x0, y0, x1, y1;
+};
+
+// The view part of the projection contract: returns false if the Gaussian is
+// culled in this view.
+__device__ __forceinline__ bool project_view(const GaussLocal& L, const ViewDesc& V, float znear, ProjState& g) {
+  const float mx = L.mx, my = L.my, mz = L.mz;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) g.Sig[k] = L.Sig[k];
   const float* W = V.R;
   float tc[3];
 #pragma unroll
@@ -309,6 +329,13 @@ __device__ __forceinline__ bool project_geometry(const float* __restrict__ P, in
   return true;
 }
 
+// The whole projection contract of one (view, Gaussian).
+__device__ __forceinline__ bool project_geometry(const float* __restrict__ P, int64_t stride, int64_t i,
+                                                 const ViewDesc& V, float znear, ProjState& g) {
+  GaussLocal L;
+  return gaussian_local(P, stride, i, L) && project_view(L, V, znear, g);
+}
+
 // Conservative early cull from the mean and the largest scale only: true
 // when the Gaussian is surely behind the near plane or surely projects
 // outside the image, so the full projection (which reads and transforms the
@@ -372,17 +399,18 @@ __device__ __forceinline__ void project_colour(const float* __restrict__ P, int6
 
 // Projection of one (view, Gaussian) splat s into its records; returns
 // whether it is visible (and then its depth key).
+// L, good, o: the Gaussian's view-independent part, whether it can be drawn
+// at all, and its opacity.
 __device__ __forceinline__ bool project_splat(const float* __restrict__ P, int64_t stride, int deg, int64_t i,
                                               int64_t s, const ViewDesc& V, int tile_w, int tile_h, float znear,
-                                              bool skip_geometry, Splat* __restrict__ splats, int4* __restrict__ rect,
+                                              bool skip_geometry, const GaussLocal& L, bool good, float o,
+                                              Splat* __restrict__ splats, int4* __restrict__ rect,
                                               uint32_t* __restrict__ ntiles, uint32_t* __restrict__ zkey,
                                               uint32_t* key_out) {
   ProjState g;
-  bool vis = !skip_geometry && project_geometry(P, stride, i, V, znear, g);
+  bool vis = !skip_geometry && good && project_view(L, V, znear, g);
   float raw[3], col[3], dir[3], dnorm;
-  float o = 0.0f;
   if (vis) {
-    o = opacity_of(P[10 * stride + i]);
     project_colour(P, stride, i, deg, V, raw, col, dir, &dnorm);
     vis = finitef(col[0]) && finitef(col[1]) && finitef(col[2]);
   }
@@ -443,11 +471,26 @@ __global__ void __launch_bounds__(256) project_kernel(const float* __restrict__ 
     }
     if (num_views == 1) {
       uint32_t key;
-      if (mine && project_splat(P, stride, deg, i, i, views[0], tile_w, tile_h, znear,
-                                surely_culled(P, stride, i, views[0], znear), splats, rect, ntiles, zkey, &key))
-        count_key(key);
+      if (mine) {
+        const bool skip = surely_culled(P, stride, i, views[0], znear);
+        GaussLocal L;
+        bool good = false;
+        float o = 0.0f;
+        if (!skip) {
+          good = gaussian_local(P, stride, i, L);
+          o = opacity_of(P[10 * stride + i]);
+        }
+        if (project_splat(P, stride, deg, i, i, views[0], tile_w, tile_h, znear, skip, L, good, o, splats, rect,
+                          ntiles, zkey, &key))
+          count_key(key);
+      }
       continue;
     }
+    // the Gaussian's view-independent part, formed at its first view that
+    // the early cull keeps
+    GaussLocal L;
+    bool have = false, good = false;
+    float o = 0.0f;
     int view = mine ? 0 : num_views;
     while (true) {
       while (view < num_views && surely_culled(P, stride, i, views[view], znear)) {
@@ -460,9 +503,14 @@ __global__ void __launch_bounds__(256) project_kernel(const float* __restrict__ 
       if (!__any(view < num_views)) break;
       if (view >= num_views) continue;
       const int cur = view++;
+      if (!have) {
+        good = gaussian_local(P, stride, i, L);
+        o = opacity_of(P[10 * stride + i]);
+        have = true;
+      }
       uint32_t key;
-      if (project_splat(P, stride, deg, i, (int64_t)cur * n + i, views[cur], tile_w, tile_h, znear, false, splats,
-                        rect, ntiles, zkey, &key))
+      if (project_splat(P, stride, deg, i, (int64_t)cur * n + i, views[cur], tile_w, tile_h, znear, false, L, good, o,
+                        splats, rect, ntiles, zkey, &key))
         count_key(key);
     }
   }
@@ -479,17 +527,20 @@ __global__ void __launch_bounds__(256) project_kernel(const float* __restrict__ 
 // Projection intermediates in double for the backward chain rule (the chain
 // rule is cheap next to the blend, and double keeps its cancellations -- the
 // conic inverse, the Jacobian terms of the depth -- out of the gradient).
-struct ProjD {
-  double s[3], qn, qh[4], R[9], M[9], Sig[9];
+// The Gaussian's view-independent part: scales, unit quaternion, rotation,
+// M = R diag(s), Sigma = M M^T, opacity.
+struct LocalD {
+  double s[3], qn, qh[4], R[9], M[9], Sig[9], o;
+};
+// Its part in one view.
+struct ViewD {
   double tx, ty, tz, xi, yi;
   bool xclamp, yclamp;
   double Tm[6];
   double a, b, c, det;
 };
 
-__device__ __forceinline__ void geometry_f64(const float* __restrict__ P, int64_t stride, int64_t i,
-                                             const ViewDesc& V, ProjD& g) {
-  const double mx = P[0 * stride + i], my = P[1 * stride + i], mz = P[2 * stride + i];
+__device__ __forceinline__ void local_f64(const float* __restrict__ P, int64_t stride, int64_t i, LocalD& g) {
 #pragma unroll
   for (int k = 0; k < 3; ++k) g.s[k] = exp((double)P[(3 + k) * stride + i]);
   const double qw = P[6 * stride + i], qx = P[7 * stride + i], qy = P[8 * stride + i], qz = P[9 * stride + i];
@@ -516,6 +567,11 @@ __device__ __forceinline__ void geometry_f64(const float* __restrict__ P, int64_
     for (int k = 0; k < 3; ++k)
       g.Sig[r * 3 + k] = g.M[r * 3 + 0] * g.M[k * 3 + 0] + g.M[r * 3 + 1] * g.M[k * 3 + 1] +
                          g.M[r * 3 + 2] * g.M[k * 3 + 2];
+  g.o = 1.0 / (1.0 + exp(-(double)P[10 * stride + i]));
+}
+
+__device__ __forceinline__ void view_f64(const LocalD& L, double mx, double my, double mz, const ViewDesc& V,
+                                         ViewD& g) {
   const float* W = V.R;
   g.tx = W[0] * mx + W[1] * my + W[2] * mz + V.t[0];
   g.ty = W[3] * mx + W[4] * my + W[5] * mz + V.t[1];
@@ -539,7 +595,7 @@ __device__ __forceinline__ void geometry_f64(const float* __restrict__ P, int64_
   for (int r = 0; r < 2; ++r)
 #pragma unroll
     for (int k = 0; k < 3; ++k)
-      U[r * 3 + k] = g.Tm[r * 3 + 0] * g.Sig[k] + g.Tm[r * 3 + 1] * g.Sig[3 + k] + g.Tm[r * 3 + 2] * g.Sig[6 + k];
+      U[r * 3 + k] = g.Tm[r * 3 + 0] * L.Sig[k] + g.Tm[r * 3 + 1] * L.Sig[3 + k] + g.Tm[r * 3 + 2] * L.Sig[6 + k];
   g.a = U[0] * g.Tm[0] + U[1] * g.Tm[1] + U[2] * g.Tm[2] + (double)kDilation;
   g.b = U[0] * g.Tm[3] + U[1] * g.Tm[4] + U[2] * g.Tm[5];
   g.c = U[3] * g.Tm[3] + U[4] * g.Tm[4] + U[5] * g.Tm[5] + (double)kDilation;
@@ -598,22 +654,23 @@ __device__ __forceinline__ void sh_dir_grad_d(int deg, double x, double y, doubl
 // Chain rule from the screen-space gradients (u, v, conic, opacity, colour,
 // depth) of every view to the parameters, summed over views, in double.
 // One thread per Gaussian, so the parameter gradients need no atomics.
-// Chain rule of one (view, Gaussian) pair: adds to the Gaussian's parameter
-// gradients (in double) what the pair's screen-space gradient G implies.
-// POSE: also adds the pair's part of the gradient with respect to the view's
-// camera to gpose[12]: dL/dR (row-major) and dL/dt of x_cam = R x + t. R acts
-// through the camera-space mean, through T = J R and, for view-dependent
-// colour, through the camera centre -R^T t.
+// Chain rule of one (view, Gaussian) pair from its screen-space gradient G:
+// adds to the mean and SH gradients, and to the sums over views of dL/dSigma
+// (gSig, 3x3) and dL/dopacity (gO), which finish_local turns into the scale,
+// rotation and opacity-logit gradients once per Gaussian (the maps from
+// Sigma and from the opacity are the same in every view). POSE: also adds
+// the pair's part of the gradient with respect to the view's camera to
+// gpose[12]: dL/dR (row-major) and dL/dt of x_cam = R x + t. R acts through
+// the camera-space mean, through T = J R and, for view-dependent colour,
+// through the camera centre -R^T t.
 template <int DEG, bool POSE = false>
 __device__ __forceinline__ void chain_view(const float* __restrict__ P, int64_t stride, int64_t i, const ViewDesc& V,
-                                           const double* G, const float* coef, double* gmean, double* gls,
-                                           double* gq, double& glogit, float* gsh, double* gpose = nullptr) {
+                                           const LocalD& L, const double* G, const float* coef, double* gmean,
+                                           double* gSig, double& gO, float* gsh, double* gpose = nullptr) {
   constexpr int K = (DEG + 1) * (DEG + 1);
-  ProjD g;
-  geometry_f64(P, stride, i, V, g);
-  // opacity
-  const double o = 1.0 / (1.0 + exp(-(double)P[10 * stride + i]));
-  glogit += G[G2_O] * o * (1.0 - o);
+  ViewD g;
+  view_f64(L, (double)P[0 * stride + i], (double)P[1 * stride + i], (double)P[2 * stride + i], V, g);
+  gO += G[G2_O];
   // colour
   double dir[3] = {0.0, 0.0, 0.0}, dnorm = 1.0;
   if (DEG > 0) {
@@ -665,7 +722,7 @@ __device__ __forceinline__ void chain_view(const float* __restrict__ P, int64_t 
   // Sigma' = T Sigma T^T
   const double* T0 = g.Tm;
   const double* T1 = g.Tm + 3;
-  const double* S = g.Sig;
+  const double* S = L.Sig;
   double ST0[3], ST1[3];
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
@@ -732,22 +789,31 @@ __device__ __forceinline__ void chain_view(const float* __restrict__ P, int64_t 
       gpose[9 + r] += gt[r] + (double)W[r * 3 + 0] * gview[0] + (double)W[r * 3 + 1] * gview[1] +
                       (double)W[r * 3 + 2] * gview[2];
   }
+#pragma unroll
+  for (int k = 0; k < 9; ++k) gSig[k] += gSS[k];
+}
+
+// From the view sums of dL/dSigma and dL/dopacity to the gradients of the
+// log-scales, the (unnormalised) quaternion and the opacity logit.
+__device__ __forceinline__ void finish_local(const LocalD& L, const double* gSig, double gO, double* gls, double* gq,
+                                             double& glogit) {
+  glogit += gO * L.o * (1.0 - L.o);
   // Sigma = M M^T, M = R diag(s)
   double gM[9];
 #pragma unroll
   for (int r = 0; r < 3; ++r)
 #pragma unroll
     for (int k = 0; k < 3; ++k)
-      gM[r * 3 + k] = gSS[r * 3 + 0] * g.M[k] + gSS[r * 3 + 1] * g.M[3 + k] + gSS[r * 3 + 2] * g.M[6 + k];
+      gM[r * 3 + k] = gSig[r * 3 + 0] * L.M[k] + gSig[r * 3 + 1] * L.M[3 + k] + gSig[r * 3 + 2] * L.M[6 + k];
   double gR[9];
 #pragma unroll
   for (int r = 0; r < 3; ++r)
 #pragma unroll
-    for (int k = 0; k < 3; ++k) gR[r * 3 + k] = gM[r * 3 + k] * g.s[k];
+    for (int k = 0; k < 3; ++k) gR[r * 3 + k] = gM[r * 3 + k] * L.s[k];
 #pragma unroll
   for (int k = 0; k < 3; ++k)
-    gls[k] += (gM[k] * g.R[k] + gM[3 + k] * g.R[3 + k] + gM[6 + k] * g.R[6 + k]) * g.s[k];
-  const double w = g.qh[0], x = g.qh[1], y = g.qh[2], z = g.qh[3];
+    gls[k] += (gM[k] * L.R[k] + gM[3 + k] * L.R[3 + k] + gM[6 + k] * L.R[6 + k]) * L.s[k];
+  const double w = L.qh[0], x = L.qh[1], y = L.qh[2], z = L.qh[3];
   const double gw = 2.0 * (-z * gR[1] + y * gR[2] + z * gR[3] - x * gR[5] - y * gR[6] + x * gR[7]);
   const double gx = 2.0 * (y * gR[1] + z * gR[2] + y * gR[3] - 2.0 * x * gR[4] - w * gR[5] + z * gR[6] +
                            w * gR[7] - 2.0 * x * gR[8]);
@@ -756,10 +822,10 @@ __device__ __forceinline__ void chain_view(const float* __restrict__ P, int64_t 
   const double gz = 2.0 * (-2.0 * z * gR[0] - w * gR[1] + x * gR[2] + w * gR[3] - 2.0 * z * gR[4] +
                            y * gR[5] + x * gR[6] + y * gR[7]);
   const double dot = w * gw + x * gx + y * gy + z * gz;
-  gq[0] += (gw - w * dot) / g.qn;
-  gq[1] += (gx - x * dot) / g.qn;
-  gq[2] += (gy - y * dot) / g.qn;
-  gq[3] += (gz - z * dot) / g.qn;
+  gq[0] += (gw - w * dot) / L.qn;
+  gq[1] += (gx - x * dot) / L.qn;
+  gq[2] += (gy - y * dot) / L.qn;
+  gq[3] += (gz - z * dot) / L.qn;
 }
 
 template <int DEG>
@@ -780,6 +846,8 @@ __global__ void __launch_bounds__(256) project_backward_kernel(const float* __re
 #pragma unroll
     for (int k = 0; k < 3 * K; ++k) coef[k] = P[(11 + k) * stride + i];
     bool touched = false;
+    LocalD L;                  // formed at the first view that passes the Gaussian a gradient
+    double gSig[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, gO = 0.0;
     // views in lockstep (the view descriptor stays wave-uniform, in scalar
     // registers); a lane skips the views that do not see its Gaussian
     for (int cur = 0; cur < num_views; ++cur) {
@@ -799,10 +867,12 @@ __global__ void __launch_bounds__(256) project_backward_kernel(const float* __re
 #pragma unroll
         for (int k = 0; k < G2_N; ++k) gv[k] = 0.0f;
       }
+      if (!touched) local_f64(P, stride, i, L);
       touched = true;
       const ViewDesc& V = views[cur];
-      chain_view<DEG>(P, stride, i, V, G, coef, gmean, gls, gq, glogit, gsh);
+      chain_view<DEG>(P, stride, i, V, L, G, coef, gmean, gSig, gO, gsh);
     }
+    if (touched) finish_local(L, gSig, gO, gls, gq, glogit);
     if (overwrite) {
       // every plane is written (zero for a Gaussian no view composited)
 #pragma unroll
@@ -852,6 +922,8 @@ __global__ void __launch_bounds__(256) pose_backward_kernel(const float* __restr
     float coef[3 * K];
 #pragma unroll
     for (int k = 0; k < 3 * K; ++k) coef[k] = mine ? P[(11 + k) * stride + i] : 0.0f;
+    LocalD L;
+    bool haveL = false;
     for (int cur = 0; cur < num_views; ++cur) {
       double gp[12];
 #pragma unroll
@@ -866,11 +938,13 @@ __global__ void __launch_bounds__(256) pose_backward_kernel(const float* __restr
           any = any || (G[k] != 0.0);
         }
         if (any) {
-          double gmean[3] = {0, 0, 0}, gls[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, glogit = 0.0;
+          if (!haveL) local_f64(P, stride, i, L);
+          haveL = true;
+          double gmean[3] = {0, 0, 0}, gSig[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, gO = 0.0;
           float gsh[3 * K];
 #pragma unroll
           for (int k = 0; k < 3 * K; ++k) gsh[k] = 0.0f;
-          chain_view<DEG, true>(P, stride, i, views[cur], G, coef, gmean, gls, gq, glogit, gsh, gp);
+          chain_view<DEG, true>(P, stride, i, views[cur], L, G, coef, gmean, gSig, gO, gsh, gp);
         }
       }
 #pragma unroll

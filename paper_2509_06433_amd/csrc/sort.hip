@@ -878,6 +878,58 @@ __global__ void __launch_bounds__(kOrderThreads) tile_order_kernel(const uint2* 
   }
 }
 
+// Balanced placement: the tiles sorted by weight (heaviest first; the walk
+// length the previous render recorded in tile_last when there is one, else
+// the list length), then dealt to consecutive rounds of `ncu` workgroups in
+// snake order (round 0 heaviest to lightest, round 1 the reverse, ...). The
+// dispatcher hands the first workgroups of a launch to the CUs in turn, so each
+// CU starts with a mix of heavy and light tiles rather than several heavy
+// ones. One workgroup, a bitonic sort in LDS of at most kBalanceMax tiles.
+constexpr int kBalanceMax = 8192;
+__global__ void __launch_bounds__(kOrderThreads) tile_balance_kernel(const uint2* __restrict__ ranges,
+                                                                     const uint32_t* __restrict__ tile_last,
+                                                                     int num_tiles, int ncu,
+                                                                     uint32_t* __restrict__ order) {
+  __shared__ unsigned long long key[kBalanceMax];
+  int n2 = 1;
+  while (n2 < num_tiles) n2 <<= 1;
+  for (int t = threadIdx.x; t < n2; t += kOrderThreads) {
+    unsigned long long k = 0ull;     // padding sorts last
+    if (t < num_tiles) {
+      const uint2 r = ranges[t];
+      const uint32_t len = r.y - r.x;
+      const uint32_t tl = tile_last ? tile_last[t] : 0u;
+      const uint32_t w = (tl > 0u && tl <= len) ? tl : len;
+      // heaviest first, ties by tile index: sort descending on (w, ~t)
+      k = ((unsigned long long)(w + 1u) << 32) | (unsigned long long)(0xFFFFFFFFu - (uint32_t)t);
+    }
+    key[t] = k;
+  }
+  __syncthreads();
+  for (int size = 2; size <= n2; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = threadIdx.x; i < n2; i += kOrderThreads) {
+        const int j = i ^ stride;
+        if (j > i) {
+          const bool desc = (i & size) == 0;
+          const unsigned long long a = key[i], b = key[j];
+          if (desc ? (a < b) : (a > b)) {
+            key[i] = b;
+            key[j] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int b = threadIdx.x; b < num_tiles; b += kOrderThreads) {
+    const int round = b / ncu, c = b - round * ncu;
+    const int len = min(ncu, num_tiles - round * ncu);
+    const int pos = round * ncu + ((round & 1) ? len - 1 - c : c);
+    order[b] = 0xFFFFFFFFu - (uint32_t)(key[pos] & 0xFFFFFFFFull);
+  }
+}
+
 // Per-tile depth order. The instances of a tile arrive in splat-index order
 // (emission in index order, then a stable sort by tile); a stable LSD radix
 // sort of each tile's list on the raw bits of z (positive floats order like
@@ -1369,6 +1421,14 @@ void launch_tile_depth_sort(const uint2* ranges, int64_t num_tiles, const uint32
 void launch_tile_order(const uint2* ranges, int64_t num_tiles, uint32_t* order, hipStream_t st) {
   if (num_tiles == 0) return;
   tile_order_kernel<<<1, kOrderThreads, 0, st>>>(ranges, num_tiles, order);
+}
+
+bool tile_balance_supported(int64_t num_tiles) { return num_tiles > 0 && num_tiles <= kBalanceMax; }
+
+void launch_tile_balance(const uint2* ranges, const uint32_t* tile_last, int64_t num_tiles, int ncu, uint32_t* order,
+                         hipStream_t st) {
+  if (num_tiles == 0) return;
+  tile_balance_kernel<<<1, kOrderThreads, 0, st>>>(ranges, tile_last, (int)num_tiles, ncu > 0 ? ncu : 256, order);
 }
 
 void launch_clear(const ClearList& L, hipStream_t st) {

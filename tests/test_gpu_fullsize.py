@@ -152,25 +152,28 @@ def sign_targets(orc, s, outs, checked, seed, row_step=1):
 
 
 def oracle_refs(orc, s, gimg, windows, label):
-    """The FP64 oracle's backward at the FP32 splats and at FP64 splats."""
+    """The FP64 oracle's backward at the FP32 splats and at FP64 splats, and
+    the magnitude sum of each element's terms."""
     t0 = time.time()
     ref32 = orc.backward(s.params, s.sh_degree, s.cameras, gimg, pinned="splats32", windows=windows)
-    ref64 = orc.backward(s.params, s.sh_degree, s.cameras, gimg, pinned=True, windows=windows)
+    ref64, gabs = orc.backward(s.params, s.sh_degree, s.cameras, gimg, pinned=True, windows=windows,
+                               want_abs=True)
     say(label, f"oracle backward {time.time() - t0:.1f}s")
     assert np.abs(ref32).max() > 0
-    return ref32, ref64
+    return ref32, ref64, gabs
 
 
 def check_grad_against_oracle(orc, s, g, gimg, windows, label, refs=None):
-    """Per element: within 1e-3 of the FP64 oracle at the FP32 splats, and
-    within 1e-3 plus the element's FP32-splat sensitivity of the FP64 oracle
-    at FP64 splats (tests/parity.py)."""
-    ref32, ref64 = refs if refs is not None else oracle_refs(orc, s, gimg, windows, label)
-    res = grad_violations(g, ref32)
+    """Per element: within 1e-3 plus the FP32 summation allowance of the FP64
+    oracle at the FP32 splats, and within that plus the element's FP32-splat
+    sensitivity of the FP64 oracle at FP64 splats (tests/parity.py)."""
+    ref32, ref64, gabs = refs if refs is not None else oracle_refs(orc, s, gimg, windows, label)
+    res = grad_violations(g, ref32, gabs=gabs)
     say(label, "vs FP64 at FP32 splats", res)
+    say(label, "plain 1e-3 (no summation allowance)", grad_violations(g, ref32))
     for grp, (nbad, worst, l2) in res.items():
         assert nbad == 0, (label, grp, nbad, worst, l2)
-    res = grad_violations_conditioned(g, ref64, ref32)
+    res = grad_violations_conditioned(g, ref64, ref32, gabs=gabs)
     say(label, "vs FP64 (with FP32-splat sensitivity)", res)
     for grp, (nbad, worst, l2, widened) in res.items():
         assert nbad == 0 and l2 <= 1e-4, (label, grp, nbad, worst, l2)
@@ -358,8 +361,12 @@ def test_surfaces_replayed_with_adam(gpu, orc):
         assert torch.equal(a, b)
     g = grad.cpu().numpy()
     check_grad_against_oracle(orc, s, g, gimg, windows, "surfaces iteration")
-    # Adam from the iteration's own gradient (the oracle's Adam in float64)
-    ref_p, ref_m, ref_v = orc.adam_step(s.params, g, np.zeros_like(g), np.zeros_like(g), 1, lrs)
+    # Adam from the iteration's own gradient (the oracle's Adam in float64),
+    # with the hyperparameters the library received: float32 values
+    f32 = lambda x: float(np.float32(x))
+    ref_p, ref_m, ref_v = orc.adam_step(s.params, g, np.zeros_like(g), np.zeros_like(g), 1,
+                                        np.asarray(lrs, np.float32).astype(np.float64),
+                                        beta1=f32(0.9), beta2=f32(0.999), eps=f32(1e-15))
     for got, ref, name in ((q, ref_p, "params"), (m, ref_m, "m"), (v, ref_v, "v")):
         got = got.cpu().numpy().astype(np.float64)
         err = np.abs(got - ref) / np.maximum(np.abs(ref), 1e-30)

@@ -77,10 +77,11 @@ def test_camera_gradient_matches_oracle(gpu, orc, deg):
     # the parameter gradient of the same call equals gsr_render_backward's
     gpar = R.render_backward(p, deg, s.cameras, dgr)
     assert torch.allclose(gp, gpar, rtol=1e-5, atol=1e-7 * float(gpar.abs().max()))
-    # without the parameter gradient, the camera gradient is the same
+    # without the parameter gradient, the camera gradient is the same up to
+    # the order of the float atomic adds that form the screen-space gradients
     R.render(p, deg, s.cameras)
     gc2, _ = R.render_backward_pose(p, deg, s.cameras, dgr)
-    assert torch.allclose(gc2, gc, rtol=1e-9, atol=1e-12 * float(gc.abs().max()))
+    assert torch.allclose(gc2, gc, rtol=1e-5, atol=1e-5 * float(gc.abs().max()))
 
 
 def rodrigues(phi):

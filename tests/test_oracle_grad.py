@@ -238,3 +238,40 @@ def test_camera_gradient_matches_central_differences(orc):
         scale = max(abs(fd1), 1e-2 * np.abs(gcam[0]).max())
         assert abs(gcam[0, k] - fd1) <= 1e-3 * scale, (k, gcam[0, k], fd1)
     assert checked >= 11
+
+
+@pytest.mark.parametrize("k,deg", [(21, 0), (22, 3)])
+def test_summand_magnitudes_bound_the_gradient(orc, k, deg):
+    """The summand-magnitude output is, per parameter, the sum of the absolute
+    values of the terms whose signed sum is the gradient, so by the triangle
+    inequality it is never below |gradient|; on a generic scene with signed
+    upstream gradients it exceeds it somewhere (the sums cancel)."""
+    s = scenes.tiny_random(k, n=20, width=40, height=34, sh_degree=deg)
+    grads = scenes.random_image_grads(k, s.cameras)
+    g, a = orc.backward(s.params, deg, s.cameras, grads, pinned=True, want_abs=True)
+    assert a.shape == g.shape and np.all(a >= 0)
+    # up to rounding residues where the exact gradient is zero
+    assert np.all(np.abs(g) <= a * (1 + 1e-12) + 1e-12 * a.max())
+    assert np.any(a > 2 * np.abs(g))
+    # odd in the upstream gradient for g, even for a
+    neg = [(-gr, -gd, -ga) for gr, gd, ga in grads]
+    g2, a2 = orc.backward(s.params, deg, s.cameras, neg, pinned=True, want_abs=True)
+    assert np.allclose(g2, -g, rtol=1e-12, atol=0) and np.allclose(a2, a, rtol=1e-12, atol=0)
+
+
+def test_summand_magnitudes_equal_gradient_without_cancellation(orc):
+    """With a positive colour gradient only, every term of the degree-0
+    colour coefficients' gradient (blend weight x upstream gradient x Y00,
+    where the colour is not clamped) is non-negative: there the bound is the
+    gradient itself. A missing or doubled term on either side breaks this."""
+    s = scenes.tiny_random(23, n=20, width=40, height=34, sh_degree=0)
+    cam = s.cameras[0]
+    rng = np.random.default_rng(23)
+    gr = rng.uniform(0.5, 1.5, (3, cam.height, cam.width)).astype(np.float32)
+    z = np.zeros((cam.height, cam.width), np.float32)
+    g, a = orc.backward(s.params, 0, s.cameras, [(gr, z, z)], pinned=True, want_abs=True)
+    sh0 = slice(11, 14)
+    assert np.all(g[sh0] >= 0) and np.count_nonzero(g[sh0]) > 10
+    assert np.allclose(a[sh0], g[sh0], rtol=1e-12, atol=0)
+    # the means do cancel: their terms have both signs
+    assert np.any(a[0:3] > 1.5 * np.abs(g[0:3]))
