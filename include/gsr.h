@@ -155,6 +155,30 @@ int gsr_render(gsr_ctx* ctx, const gsr_gaussians* g, int32_t num_views,
 int gsr_render1(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_camera* cam,
                 const gsr_image* out, void* stream);
 
+/* Allocation-free forward render, for callers that cannot allocate device
+ * memory or wait on the device inside the call: code under HIP graph capture,
+ * tight serving loops (a viewer rendering frames of a live map), harnesses
+ * that forbid hipMalloc. Same arguments, kernels and images as gsr_render
+ * (bit for bit), but every piece of device scratch comes from one static
+ * array of 72 MiB in the library (a copy per GPU, held until the process
+ * ends, set up by gsr_create), the instance storage has a fixed capacity, and
+ * the call neither allocates (device or host) nor synchronises: it is
+ * asynchronous on `stream` like the launches it makes.
+ * Limits: num * num_views <= 2^18 splats, <= 2^20 pixels and <= 2^15 tiles
+ * over all views, <= 16 views (else GSR_ERR_CAPACITY, nothing launched);
+ * <= 2^21 (tile, Gaussian) instances, checked on the device: a render that
+ * needs more leaves its images invalid, and gsr_query_status (which
+ * synchronises) then returns GSR_ERR_CAPACITY with the required count.
+ * The context must be used on the device it was created on (else
+ * GSR_ERR_INVALID); GSR_ERR_UNSUPPORTED if its scratch could not be set up.
+ * Every context on a GPU shares that GPU's scratch: two calls that overlap
+ * in time on one GPU (other streams, other threads or contexts) race and
+ * corrupt each other's images. It leaves gsr_render_backward referring to
+ * the last gsr_render; the status, instance and work queries report on this
+ * render until the next render call. */
+int gsr_render_noalloc(gsr_ctx* ctx, const gsr_gaussians* g, int32_t num_views,
+                       const gsr_camera* cams, const gsr_image* out, void* stream);
+
 /* Backward of the last gsr_render on this context: given dL/d(rgb, depth,
  * alpha) per view (grad_out[num_views], device pointers; a NULL plane means
  * zero), ADDS dL/dparams to grad_params (device [P][stride] float32, same
@@ -305,7 +329,9 @@ int gsr_mapping_status(gsr_ctx* ctx, gsr_mapping_stats* out);
  *                     are not an error: they are drawn in no view and receive
  *                     no gradient. (A splat whose colour is non-finite is
  *                     culled in that view and not counted here.)
- * GSR_ERR_DEVICE if that render's sort wait expired. */
+ * GSR_ERR_DEVICE if that render's sort wait expired; GSR_ERR_CAPACITY (with
+ * the outputs filled) if it was a gsr_render_noalloc that needed more than
+ * its 2^21 instance slots. */
 int gsr_query_status(gsr_ctx* ctx, int64_t* num_instances, int64_t* num_visible,
                      int64_t* num_tiles, int64_t* nonfinite_culled);
 

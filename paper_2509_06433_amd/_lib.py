@@ -23,7 +23,7 @@ EXPORTED = sorted(["gsr_create", "gsr_destroy", "gsr_render", "gsr_render1", "gs
                    "gsr_adam_step", "gsr_query_status", "gsr_copy_instances", "gsr_copy_splats",
                    "gsr_count_work", "gsr_set_profiling", "gsr_get_profile", "gsr_last_hip_error",
                    "gsr_status_string", "gsr_mapping_iteration", "gsr_mapping_status", "gsr_activations",
-                   "gsr_render_backward_pose", "gsr_densify",
+                   "gsr_render_noalloc", "gsr_render_backward_pose", "gsr_densify",
                    "gsr_ipc_export_memory", "gsr_ipc_open_memory", "gsr_ipc_close_memory", "gsr_ipc_event_create",
                    "gsr_ipc_event_open", "gsr_ipc_event_record", "gsr_ipc_event_wait", "gsr_ipc_event_destroy",
                    # achievable-peak probes (include/gsr_peaks.h)
@@ -101,6 +101,7 @@ def load():
             "gsr_destroy": ([vp], None),
             "gsr_render": ([vp, P(gsr_gaussians), i32, P(gsr_camera), P(gsr_image), vp], ctypes.c_int),
             "gsr_render1": ([vp, P(gsr_gaussians), P(gsr_camera), P(gsr_image), vp], ctypes.c_int),
+            "gsr_render_noalloc": ([vp, P(gsr_gaussians), i32, P(gsr_camera), P(gsr_image), vp], ctypes.c_int),
             "gsr_render_backward_pose": ([vp, P(gsr_gaussians), i32, P(gsr_camera), P(gsr_image), vp, vp, vp, vp],
                                          ctypes.c_int),
             "gsr_render_backward": ([vp, P(gsr_gaussians), i32, P(gsr_camera), P(gsr_image), vp, vp],
@@ -270,6 +271,14 @@ def gsr_render(ctx, params, sh_degree, cams, outs, stream=None):
     g = _gauss(params, sh_degree)
     ims = _images(outs, cams, "outs", device=params.device)
     _check(ctx, "gsr_render", load().gsr_render(ctx, ctypes.byref(g), len(cams), _cams(cams), ims, _stream(stream)))
+
+
+def gsr_render_noalloc(ctx, params, sh_degree, cams, outs, stream=None):
+    """gsr_render without device allocation or synchronisation (fixed-size scratch; see include/gsr.h)."""
+    g = _gauss(params, sh_degree)
+    ims = _images(outs, cams, "outs", device=params.device)
+    _check(ctx, "gsr_render_noalloc",
+           load().gsr_render_noalloc(ctx, ctypes.byref(g), len(cams), _cams(cams), ims, _stream(stream)))
 
 
 def gsr_render1(ctx, params, sh_degree, cam, out, stream=None):

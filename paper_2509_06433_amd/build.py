@@ -37,6 +37,7 @@ SOURCES = {
     "peaks.hip": [],
     "densify.hip": STRICT,
     "ipc.hip": [],
+    "noalloc.hip": [],
 }
 
 

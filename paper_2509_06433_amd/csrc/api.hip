@@ -493,6 +493,9 @@ int gsr_create(gsr_ctx** out, const gsr_options* opt) {
       ctx->num_cus = cus;
     (void)hipGetLastError();
   }
+  // the allocation-free render's scratch on this device (its status is
+  // checked there: gsr_render_noalloc reports GSR_ERR_UNSUPPORTED without it)
+  (void)noalloc_attach(ctx);
   hipError_t e = hipHostMalloc((void**)&ctx->host_total, 64, hipHostMallocDefault);
   for (int k = 0; k < kSlots && e == hipSuccess; ++k) {
     e = hipHostMalloc(&ctx->slots[k], kSlotBytes, hipHostMallocDefault);
@@ -630,6 +633,8 @@ int gsr_query_status(gsr_ctx* ctx, int64_t* num_instances, int64_t* num_visible,
   if (num_tiles) *num_tiles = ctx->q_plan ? ctx->q_plan->ntiles : 0;
   if (nonfinite_culled) *nonfinite_culled = (int64_t)t[4];
   if (t[1]) return GSR_ERR_DEVICE;
+  // an allocation-free render that needed more instances than its fixed capacity
+  if (ctx->q_bufs == &ctx->na_bufs && t[2]) return GSR_ERR_CAPACITY;
   return GSR_OK;
 }
 

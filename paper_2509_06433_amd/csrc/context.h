@@ -126,6 +126,9 @@ struct gsr_ctx {
   hipStream_t last_stream = nullptr;
 
   gsr::Buffers eager;                   // buffers of gsr_render / gsr_render_backward
+  gsr::Buffers na_bufs;                 // gsr_render_noalloc: windows of the device's static scratch
+  gsr::RenderPlan na_plan;
+  int na_device = -1;                   // the device whose scratch na_bufs point into
   DevBuf images3, lr, splat_out;
   DevBuf seed_buf;                      // gsr_densify: seed flags, offsets, scan scratch
   uint32_t* host_total = nullptr;
@@ -387,6 +390,9 @@ bool use_fused_blend(const gsr_ctx* ctx, const RenderPlan& plan);
 bool per_tile_depth(const gsr_ctx* ctx, const RenderPlan& plan);
 int size_instances(gsr_ctx* ctx, Buffers& B, const RenderPlan& plan);
 void free_buffers(Buffers& B);
+// Points ctx->na_bufs at the current device's static scratch of the
+// allocation-free render (noalloc.hip).
+int noalloc_attach(gsr_ctx* ctx);
 // Frees the captured mapping iteration and its buffers (iteration.hip).
 void destroy_graph(gsr_ctx* ctx);
 // Waits for every replay still being timed and adds its stage times to the
