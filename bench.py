@@ -88,6 +88,8 @@ def parse():
                     help="0 = automatic, 1 = longest tile lists first, 2 = tile order, 3 = balanced over the CUs")
     ap.add_argument("--backward-schedule", type=int, default=0,
                     help="blend backward: 0 = pixel-parallel, 1 = splat-parallel (whole lists, two blend launches)")
+    ap.add_argument("--binning", type=int, default=0,
+                    help="instances by tile: 0 = radix sort of tile keys, 1 = counting where it applies")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use --tile/--ppt/--batch-depth instead of the autotuner's choice")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -181,7 +183,8 @@ def main():
     deg = scene.sh_degree
     R = Rasterizer(tile_w=tw, tile_h=th, pixels_per_thread=args.ppt, batch_depth=args.batch_depth,
                    tile_order=args.tile_order, chunk_len=args.chunk_len, max_chunks=args.max_chunks,
-                   fuse_blend=args.fuse_blend, depth_sort=args.depth_sort, backward_schedule=args.backward_schedule)
+                   fuse_blend=args.fuse_blend, depth_sort=args.depth_sort, backward_schedule=args.backward_schedule,
+                   binning=args.binning)
     dev = torch.device("cuda:0")
     if args.calibrate_copy:
         src = torch.ones(64 * 1024 * 1024, device=dev)
@@ -216,7 +219,7 @@ def main():
         R = Rasterizer(tile_w=tuned["tile_w"], tile_h=tuned["tile_h"], pixels_per_thread=tuned["pixels_per_thread"],
                        batch_depth=tuned["batch_depth"], tile_order=args.tile_order, chunk_len=tuned["chunk_len"],
                        max_chunks=tuned["max_chunks"], fuse_blend=args.fuse_blend, depth_sort=args.depth_sort,
-                       backward_schedule=args.backward_schedule)
+                       backward_schedule=args.backward_schedule, binning=args.binning)
         outs = R.alloc_images(cams, dev)
     from paper_2509_06433_amd import _lib
     adam = dict(m=m, v=v, lr=lrs, beta1=0.9, beta2=0.999, eps=1e-15) if use_adam else None
@@ -310,7 +313,7 @@ def main():
         # blend launches (same kernels up to the forward)
         R2 = Rasterizer(tile_w=R.tile_w, tile_h=R.tile_h, pixels_per_thread=R.pixels_per_thread,
                         batch_depth=R.batch_depth, tile_order=R.tile_order, chunk_len=R.chunk_len,
-                        max_chunks=R.max_chunks, fuse_blend=-1, depth_sort=R.depth_sort)
+                        max_chunks=R.max_chunks, fuse_blend=-1, depth_sort=R.depth_sort, binning=R.binning)
         outs2 = R2.alloc_images(cams, dev)
         p2 = params0.clone()
         g2 = torch.zeros_like(p2)
@@ -354,6 +357,7 @@ def main():
                    "max_chunks": R.max_chunks or "default",
                    "blend_launch": "fused" if dominant == "blend" else "separate",
                    "backward_schedule": ["pixel-parallel", "splat-parallel"][R.backward_schedule],
+                   "binning": ["radix sort of tile keys", "counting"][R.binning],
                    "autotuned": tuned is not None, "tile_order": ["auto", "longest first", "index", "balanced"][R.tile_order],
                    "adam": use_adam, "mode": args.mode,
                    f"{other}_iters_s": round(1000.0 / other_ms, 3) if other_ms else None,

@@ -109,6 +109,13 @@ typedef struct {
                                Gaussian); the lists are walked whole, so chunk_len and
                                fuse_blend do not apply). Same gradient up to float summation
                                order. */
+  int32_t binning;          /* grouping of the instances by tile: 0 = emission in splat order
+                               and a radix sort of the tile keys (default), 1 = by counting
+                               where each tile's list is sorted by depth afterwards and every
+                               view has at most 8192 tiles (per-workgroup tile counts in LDS,
+                               one scan, a scatter; equal depths then ordered by index), else
+                               as 0. The lists are identical; 1 is slower on the benchmark
+                               workloads (its scatter writes are not coalesced). */
 } gsr_options;
 
 typedef struct {
@@ -412,7 +419,8 @@ int gsr_set_profiling(gsr_ctx* ctx, uint32_t stage_mask);
  * clears the stage's record afterwards. */
 int gsr_get_profile(gsr_ctx* ctx, int32_t stage, double* total_ms, int64_t* launches, int32_t reset);
 
-/* HIP error code recorded by the last GSR_ERR_HIP on this context. */
+/* HIP error code recorded by the last GSR_ERR_HIP on this context; with ctx
+ * NULL, that of the calling thread's last failed gsr_ipc_* call (0 if none). */
 int gsr_last_hip_error(gsr_ctx* ctx);
 
 /* Static description of a status code. */

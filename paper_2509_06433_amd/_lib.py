@@ -36,6 +36,7 @@ STAGES = ["project", "depth_sort", "scan", "emit", "tile_sort", "ranges", "blend
 class GsrError(RuntimeError):
     def __init__(self, fn, status, hip=0):
         self.status = status
+        self.hip = hip
         msg = f"{fn} failed: {STATUS_NAMES.get(status, status)}"
         if hip:
             msg += f" (hipError {hip})"
@@ -47,7 +48,7 @@ class gsr_options(ctypes.Structure):
                 ("bg", ctypes.c_float * 3), ("znear", ctypes.c_float), ("pixels_per_thread", ctypes.c_int32),
                 ("tile_order", ctypes.c_int32), ("chunk_len", ctypes.c_int32), ("max_chunks", ctypes.c_int32),
                 ("fuse_blend", ctypes.c_int32), ("depth_sort", ctypes.c_int32),
-                ("backward_schedule", ctypes.c_int32)]
+                ("backward_schedule", ctypes.c_int32), ("binning", ctypes.c_int32)]
 
 
 class gsr_camera(ctypes.Structure):
@@ -247,16 +248,16 @@ def _gauss(params: torch.Tensor, sh_degree: int, num=None, stride=None) -> gsr_g
 
 def _check(ctx, fn, rc):
     if rc != GSR_OK:
-        hip = load().gsr_last_hip_error(ctx) if ctx else 0
+        hip = load().gsr_last_hip_error(ctx)
         raise GsrError(fn, rc, hip)
 
 
 # --- one wrapper per C entry point ------------------------------------------
 
 def gsr_create(tile_w=16, tile_h=16, batch_depth=0, bg=(0.0, 0.0, 0.0), znear=0.2, pixels_per_thread=0,
-               tile_order=0, chunk_len=0, max_chunks=0, fuse_blend=0, depth_sort=0, backward_schedule=0):
+               tile_order=0, chunk_len=0, max_chunks=0, fuse_blend=0, depth_sort=0, backward_schedule=0, binning=0):
     opt = gsr_options(tile_w, tile_h, batch_depth, (ctypes.c_float * 3)(*bg), znear, pixels_per_thread, tile_order,
-                      chunk_len, max_chunks, fuse_blend, depth_sort, backward_schedule)
+                      chunk_len, max_chunks, fuse_blend, depth_sort, backward_schedule, binning)
     h = ctypes.c_void_p()
     _check(None, "gsr_create", load().gsr_create(ctypes.byref(h), ctypes.byref(opt)))
     return h
@@ -480,6 +481,35 @@ def gsr_ipc_export_memory(t):
     _check(None, "gsr_ipc_export_memory",
            load().gsr_ipc_export_memory(_ptr(t), ctypes.byref(h), ctypes.byref(off), ctypes.byref(size)))
     return bytes(h.bytes), off.value, size.value
+
+
+def gsr_ipc_open_memory(handle: bytes, offset: int):
+    """(device address, base to close) of a buffer exported by another process."""
+    if len(handle) != 64 or offset < 0:
+        raise ValueError("a 64-byte handle and a non-negative offset are required")
+    h = gsr_ipc_handle()
+    ctypes.memmove(ctypes.addressof(h), handle, 64)
+    ptr, base = ctypes.c_void_p(), ctypes.c_void_p()
+    _check(None, "gsr_ipc_open_memory",
+           load().gsr_ipc_open_memory(ctypes.byref(h), ctypes.c_int64(offset), ctypes.byref(ptr), ctypes.byref(base)))
+    return ptr.value, base.value
+
+
+def gsr_ipc_close_memory(base: int):
+    _check(None, "gsr_ipc_close_memory", load().gsr_ipc_close_memory(ctypes.c_void_p(base)))
+
+
+def gsr_ipc_event_open(handle: bytes):
+    if len(handle) != 64:
+        raise ValueError("a 64-byte handle is required")
+    h, ev = gsr_ipc_handle(), ctypes.c_void_p()
+    ctypes.memmove(ctypes.addressof(h), handle, 64)
+    _check(None, "gsr_ipc_event_open", load().gsr_ipc_event_open(ctypes.byref(h), ctypes.byref(ev)))
+    return ev.value
+
+
+def gsr_ipc_event_wait(event, stream=None):
+    _check(None, "gsr_ipc_event_wait", load().gsr_ipc_event_wait(ctypes.c_void_p(event), _stream(stream)))
 
 
 def gsr_ipc_event_create():

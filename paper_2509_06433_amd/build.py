@@ -77,6 +77,3 @@ def build(verbose: bool = False) -> str:
     os.replace(tmp, LIB)
     return LIB
 
-
-if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))

@@ -23,6 +23,8 @@ int chunk_len_for(const gsr_ctx* ctx, const RenderPlan& P) {
   return P.ntiles < kAutoChunkTiles ? kAutoChunk : 0;
 }
 
+static int64_t scan_elems(const gsr_ctx* ctx, const Buffers& B, const RenderPlan& P);
+
 int plan_render(gsr_ctx* ctx, const gsr_gaussians* g, int32_t nv, const gsr_camera* cams, RenderPlan* plan) {
   RET_IF(check_gaussians(g));
   RET_IF(check_cams(cams, nv));
@@ -75,22 +77,28 @@ int size_render(gsr_ctx* ctx, Buffers& B, RenderPlan& P, const gsr_image* out, h
   RET_IF(ensure(ctx, B.tile_last, sizeof(uint32_t) * (size_t)std::max<int64_t>(P.ntiles, 1)));
   if (!P.forward_only) {
     RET_IF(ensure(ctx, B.images2, sizeof(ViewImages) * nv));
-    RET_IF(ensure(ctx, B.tile_done, sizeof(uint32_t) * (size_t)std::max<int64_t>(P.ntiles, 1)));
+    // per tile a forward-done flag, then the work-queue counter of the fused launch
+    RET_IF(ensure(ctx, B.tile_done, sizeof(uint32_t) * (size_t)(P.ntiles + 1)));
     if (chunk_len_for(ctx, P) > 0)
       RET_IF(ensure(ctx, B.ckpt, sizeof(float) * kCkptFields * (size_t)ctx->max_chunks * (size_t)P.npix));
     RET_IF(ensure(ctx, B.g2, sizeof(float) * G2_N * (size_t)std::max<int64_t>(P.total, 1)));
   }
   RET_IF(ensure(ctx, B.total, 64));
   RET_IF(ensure(ctx, B.hist, sizeof(uint32_t) * (size_t)radix_scratch_elems(P.total, 32)));
-  RET_IF(ensure(ctx, B.partials, 2 * sizeof(uint32_t) * (size_t)scan_partial_elems(P.total)));
+  {
+    int64_t m = 0;
+    int mt = 0;
+    if (use_bins(ctx, B, P, &m, &mt)) RET_IF(ensure(ctx, B.bins, sizeof(uint32_t) * (size_t)m));
+  }
+  RET_IF(ensure(ctx, B.partials, 2 * sizeof(uint32_t) * (size_t)scan_partial_elems(scan_elems(ctx, B, P))));
   RET_IF(upload(ctx, B.views.p, P.views.data(), sizeof(ViewDesc) * nv, st));
   RET_IF(upload(ctx, B.images.p, ims.data(), sizeof(ViewImages) * nv, st));
   return GSR_OK;
 }
 
-void front_clears(Buffers& B, const RenderPlan& P, ClearList& L) {
+void front_clears(const gsr_ctx* ctx, Buffers& B, const RenderPlan& P, ClearList& L) {
   L.add(B.total.p, 8);
-  L.add(B.partials.p, 2 * scan_partial_elems(P.total));
+  L.add(B.partials.p, 2 * scan_partial_elems(scan_elems(ctx, B, P)));
   if (P.total > 1) L.add(B.hist.p, radix_scratch_elems(P.total, 32));
 }
 
@@ -128,6 +136,21 @@ int launch_front(gsr_ctx* ctx, Buffers& B, RenderPlan& P, const float* params, h
   // is sorted after binning), and one pass compacts them and forms the
   // offsets. With the instance capacity fixed ahead (the captured iteration)
   // the offsets scan also writes the emission plan.
+  int64_t bin_entries = 0;
+  int bin_tiles = 0;
+  if (use_bins(ctx, B, P, &bin_entries, &bin_tiles)) {
+    // binning by counting: the per-(tile, workgroup) counts and their scan,
+    // whose total is the instance count
+    P.plan_ready = false;
+    StageTimer tm(ctx, GSR_STAGE_SCAN, st);
+    uint32_t* counts = as<uint32_t>(B.bins);
+    launch_bin_count(as<uint32_t>(B.ntiles), as<int4>(B.rect), as<ViewDesc>(B.views), nv, P.num, bin_tiles,
+                     ctx->tile_w, ctx->tile_h, counts, totals + 3, st);
+    scan_gather_exclusive(counts, nullptr, counts, bin_entries, nullptr, totals, cscan, totals + 1, false, st);
+    CHECK_LAUNCH(ctx);
+    P.sorted_splats = nullptr;
+    return GSR_OK;
+  }
   P.plan_ready = P.capacity > 0;
   uint32_t* plan = P.plan_ready ? as<uint32_t>(B.block_rank) : nullptr;
   if (global_depth) {
@@ -188,11 +211,42 @@ bool per_tile_depth(const gsr_ctx* ctx, const RenderPlan& P) {
   return P.total <= (int64_t(1) << 19);
 }
 
+// The count matrix of the binning by counting stays below 2^26 words (256 MB);
+// past that the radix path is used.
+constexpr int64_t kBinMaxEntries = int64_t(1) << 26;
+
+bool use_bins(const gsr_ctx* ctx, const Buffers& B, const RenderPlan& P, int64_t* entries, int* max_view_tiles) {
+  if (ctx->binning != 1 || P.num == 0 || P.nv == 0 || !per_tile_depth(ctx, P)) return false;
+  int64_t most = 0;
+  for (const ViewDesc& v : P.views) most = std::max<int64_t>(most, (int64_t)v.tiles_x * v.tiles_y);
+  if (!bin_view_fits(most)) return false;
+  const int64_t nb = (P.num + bin_chunk(P.num) - 1) / bin_chunk(P.num);
+  const int64_t m = P.ntiles * nb;
+  if (m > kBinMaxEntries || m >= (int64_t(1) << 31)) return false;
+  if (B.bins.fixed && sizeof(uint32_t) * (size_t)m > B.bins.cap) return false;
+  *entries = m;
+  *max_view_tiles = (int)most;
+  return true;
+}
+
+// Elements of the largest single-pass scan of a render (the splat compaction
+// or the count matrix), for its look-back scratch.
+static int64_t scan_elems(const gsr_ctx* ctx, const Buffers& B, const RenderPlan& P) {
+  int64_t m = 0;
+  int mt = 0;
+  return use_bins(ctx, B, P, &m, &mt) ? std::max(P.total, m) : P.total;
+}
+
 bool use_fused_blend(const gsr_ctx* ctx, const RenderPlan& P) {
   if (ctx->fuse_blend < 0 || ctx->batch_depth != 0 || ctx->bwd_schedule != 0) return false;
   if (ctx->fuse_blend > 0) return true;
   return chunk_len_for(ctx, P) > 0 && P.ntiles <= ctx->fused_resident;
 }
+
+static int launch_sorted_bins(gsr_ctx* ctx, Buffers& B, RenderPlan& P, hipStream_t st, uint32_t*& ik,
+                              uint32_t*& iv, uint32_t*& ika, uint32_t*& iva);
+static int launch_blend_front(gsr_ctx* ctx, Buffers& B, RenderPlan& P, hipStream_t st, const FusedLoss* loss,
+                              bool fused, uint32_t* ik, uint32_t* iv, uint32_t* ika, uint32_t* iva);
 
 int launch_back(gsr_ctx* ctx, Buffers& B, RenderPlan& P, hipStream_t st, const FusedLoss* loss, bool fused) {
   uint32_t* totals = as<uint32_t>(B.total);
@@ -200,6 +254,33 @@ int launch_back(gsr_ctx* ctx, Buffers& B, RenderPlan& P, hipStream_t st, const F
   uint32_t* iv = as<uint32_t>(B.ivals);
   uint32_t* ika = as<uint32_t>(B.ikeys_alt);
   uint32_t* iva = as<uint32_t>(B.ivals_alt);
+  int64_t bin_entries = 0;
+  int bin_tiles = 0;
+  if (use_bins(ctx, B, P, &bin_entries, &bin_tiles)) {
+    StageTimer tm(ctx, GSR_STAGE_EMIT, st);
+    launch_bin_scatter(as<uint32_t>(B.ntiles), as<int4>(B.rect), as<ViewDesc>(B.views), P.nv, P.num, bin_tiles,
+                       ctx->tile_w, ctx->tile_h, as<uint32_t>(B.bins), totals, P.capacity, P.ntiles, ik, iv,
+                       as<uint2>(B.ranges), totals + 2, st);
+  } else {
+    RET_IF(launch_sorted_bins(ctx, B, P, st, ik, iv, ika, iva));
+  }
+  CHECK_LAUNCH(ctx);
+  {
+    StageTimer tm(ctx, GSR_STAGE_RANGES, st);
+    if (use_lpt(ctx, P)) launch_tile_order(as<uint2>(B.ranges), P.ntiles, as<uint32_t>(B.order), st);
+    // the tile_last the previous render of these buffers left (a weight only)
+    if (use_balance(ctx, P))
+      launch_tile_balance(as<uint2>(B.ranges), as<uint32_t>(B.tile_last), P.ntiles, ctx->num_cus,
+                          as<uint32_t>(B.order), st);
+  }
+  return launch_blend_front(ctx, B, P, st, loss, fused, ik, iv, ika, iva);
+}
+
+// The general binning: emission of the instances in the splats' order, a
+// stable radix sort of their tile keys, the tile ranges.
+static int launch_sorted_bins(gsr_ctx* ctx, Buffers& B, RenderPlan& P, hipStream_t st, uint32_t*& ik,
+                              uint32_t*& iv, uint32_t*& ika, uint32_t*& iva) {
+  uint32_t* totals = as<uint32_t>(B.total);
   const int tbits = bits_for(P.ntiles - 1);
   // large sorts take reduce-then-scan passes; small ones the look-back
   // passes, whose global histogram the emission accumulates
@@ -226,16 +307,22 @@ int launch_back(gsr_ctx* ctx, Buffers& B, RenderPlan& P, hipStream_t st, const F
   {
     StageTimer tm(ctx, GSR_STAGE_RANGES, st);
     launch_tile_ranges(ik, totals, P.capacity, as<uint2>(B.ranges), P.ntiles, false, st);
-    if (use_lpt(ctx, P)) launch_tile_order(as<uint2>(B.ranges), P.ntiles, as<uint32_t>(B.order), st);
-    // the tile_last the previous render of these buffers left (a weight only)
-    if (use_balance(ctx, P))
-      launch_tile_balance(as<uint2>(B.ranges), as<uint32_t>(B.tile_last), P.ntiles, ctx->num_cus,
-                          as<uint32_t>(B.order), st);
   }
+  return GSR_OK;
+}
+
+// The per-tile depth sort (where it applies) and the forward blend (or the
+// fused forward + backward launch).
+static int launch_blend_front(gsr_ctx* ctx, Buffers& B, RenderPlan& P, hipStream_t st, const FusedLoss* loss,
+                              bool fused, uint32_t* ik, uint32_t* iv, uint32_t* ika, uint32_t* iva) {
+  uint32_t* totals = as<uint32_t>(B.total);
   CHECK_LAUNCH(ctx);
   if (per_tile_depth(ctx, P)) {
     StageTimer tm(ctx, GSR_STAGE_TILE_DEPTH, st);
-    launch_tile_depth_sort(as<uint2>(B.ranges), P.ntiles, as<uint32_t>(B.zkey), ik, iv, ika, iva, st);
+    int64_t m = 0;
+    int mt = 0;
+    const bool counted = use_bins(ctx, B, P, &m, &mt);   // the lists are not in index order then
+    launch_tile_depth_sort(as<uint2>(B.ranges), P.ntiles, as<uint32_t>(B.zkey), ik, iv, ika, iva, !counted, st);
   }
   CHECK_LAUNCH(ctx);
   P.inst_keys = ik;
@@ -266,6 +353,14 @@ int launch_back(gsr_ctx* ctx, Buffers& B, RenderPlan& P, hipStream_t st, const F
     ba.g2 = as<float>(B.g2);
     ba.tile_done = as<uint32_t>(B.tile_done);
     ba.err = totals + 1;
+    // more tiles than the device holds workgroups at once (the plain grid
+    // needs every forward resident before the backward units that wait on
+    // them): the work-queue form, whose counter is the word after the tiles'
+    // flags
+    if (P.ntiles > ctx->fused_resident && ctx->fused_resident > 0) {
+      ba.queue = as<uint32_t>(B.tile_done) + P.ntiles;
+      ba.queue_grid = (int32_t)ctx->fused_resident;
+    }
     StageTimer tm(ctx, GSR_STAGE_BLEND, st);
     launch_blend_fused(ba, ctx->tile_w, ctx->tile_h, ctx->ppt, st);
   } else {
@@ -319,9 +414,9 @@ void free_buffers(Buffers& B) {
   DevBuf* bufs[] = {&B.views, &B.images, &B.images2, &B.splats, &B.rect, &B.ntiles, &B.zkey, &B.svals,
                     &B.zkey_alt, &B.svals_alt, &B.offsets, &B.ikeys, &B.ivals, &B.ikeys_alt, &B.ivals_alt,
                     &B.hist, &B.hist2, &B.partials, &B.ranges, &B.order, &B.tfinal, &B.last, &B.g2, &B.total,
-                    &B.tile_last, &B.ckpt, &B.block_rank, &B.tile_done};
+                    &B.tile_last, &B.ckpt, &B.block_rank, &B.tile_done, &B.bins};
   for (DevBuf* b : bufs) {
-    if (b->p) (void)hipFree(b->p);
+    if (b->p && !b->fixed) (void)hipFree(b->p);
     b->p = nullptr;
     b->cap = 0;
   }
@@ -348,7 +443,7 @@ int render_impl(gsr_ctx* ctx, const gsr_gaussians* g, int32_t nv, const gsr_came
   P.capacity = 0;
   RET_IF(size_render(ctx, B, P, out, st));
   ClearList L{};
-  front_clears(B, P, L);
+  front_clears(ctx, B, P, L);
   launch_clear(L, st);
   RET_IF(launch_front(ctx, B, P, g->params, st));
   HIP_TRY(ctx, hipMemcpyAsync(ctx->host_total, B.total.p, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
@@ -482,6 +577,11 @@ int gsr_create(gsr_ctx** out, const gsr_options* opt) {
       return GSR_ERR_UNSUPPORTED;
     }
     ctx->bwd_schedule = opt->backward_schedule;
+    if (opt->binning < 0 || opt->binning > 1) {
+      delete ctx;
+      return GSR_ERR_UNSUPPORTED;
+    }
+    ctx->binning = opt->binning;
     for (int k = 0; k < 3; ++k) ctx->bg[k] = opt->bg[k];
     ctx->znear = opt->znear > 0.f ? opt->znear : 0.2f;
   }
@@ -736,7 +836,7 @@ int gsr_get_profile(gsr_ctx* ctx, int32_t stage, double* total_ms, int64_t* laun
   return GSR_OK;
 }
 
-int gsr_last_hip_error(gsr_ctx* ctx) { return ctx ? ctx->hip_err : 0; }
+int gsr_last_hip_error(gsr_ctx* ctx) { return ctx ? ctx->hip_err : ipc_last_hip_error(); }
 
 const char* gsr_status_string(int status) {
   switch (status) {

@@ -767,6 +767,41 @@ blend_fused_kernel(BlendArgs a) {
   }
 }
 
+// The fused launch as a persistent grid over a work queue, for more units
+// than the device holds at once (the plain grid above needs every workgroup
+// resident, or a waiting backward unit could hold the slot its tile's forward
+// needs). As many workgroups as fit take units from a counter in the plain
+// grid's order: every tile's forward with its first chunk, then chunk 1 of
+// every tile, then chunk 2, ... A later chunk is thus taken only after its
+// tile's forward was taken by a running workgroup, which never waits, so
+// every wait ends whatever the tile count.
+template <int TW, int TH, int PPT, int BATCH, bool CK>
+__global__ void __launch_bounds__(TW * TH / PPT) __attribute__((amdgpu_waves_per_eu(4)))
+blend_fused_queue_kernel(BlendArgs a, uint32_t units) {
+  using F = FwdShared<TW * TH / PPT>;
+  using B = BwdShared<TW * TH / PPT / 64, BATCH>;
+  __shared__ __align__(16) unsigned char smem[sizeof(F) > sizeof(B) ? sizeof(F) : sizeof(B)];
+  __shared__ uint32_t s_unit;
+  while (true) {
+    if (threadIdx.x == 0) s_unit = atomicAdd(a.queue, 1u);
+    __syncthreads();
+    const uint32_t u = s_unit;
+    if (u >= units) break;
+    if (u < (uint32_t)a.num_tiles) {
+      const int tile = a.order ? (int)a.order[u] : (int)u;
+      const uint32_t tl = forward_tile<TW, TH, PPT, CK, true>(a, *reinterpret_cast<F*>(smem), tile);
+      __syncthreads();
+      backward_unit<TW, TH, PPT, BATCH, true>(a, *reinterpret_cast<B*>(smem), tile, 0, false, tl);
+    } else {
+      const int unit = (int)(u - (uint32_t)a.num_tiles);
+      const int cu = unit / a.num_tiles, t = unit - cu * a.num_tiles;
+      backward_unit<TW, TH, PPT, BATCH, true>(a, *reinterpret_cast<B*>(smem), a.order ? (int)a.order[t] : t,
+                                              cu + 1, true, 0u);
+    }
+    __syncthreads();   // the LDS and s_unit are free for the next unit
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Splat-parallel backward (a selectable schedule). One wavefront per tile.
 // The tile's list is walked back to front in batches of 64 positions; lane j
@@ -936,7 +971,15 @@ void fused_launch_ppt(const BlendArgs& a, hipStream_t st) {
   constexpr int D = NT >= 256 ? 32 : (NT >= 64 ? 64 : NT);
   // a workgroup per tile (forward and the first chunk), one per later chunk
   const int64_t units = (int64_t)a.num_tiles * (a.chunk_len > 0 ? a.max_chunks - 1 : 0);
-  const dim3 grid((unsigned)(a.num_tiles + units));
+  const int64_t total = a.num_tiles + units;
+  if (a.queue) {
+    const int64_t g = total < (int64_t)a.queue_grid ? total : (int64_t)a.queue_grid;
+    const dim3 grid((unsigned)(g > 1 ? g : 1));
+    if (a.chunk_len > 0) blend_fused_queue_kernel<TW, TH, PPT, D, true><<<grid, NT, 0, st>>>(a, (uint32_t)total);
+    else blend_fused_queue_kernel<TW, TH, PPT, D, false><<<grid, NT, 0, st>>>(a, (uint32_t)total);
+    return;
+  }
+  const dim3 grid((unsigned)total);
   if (a.chunk_len > 0) blend_fused_kernel<TW, TH, PPT, D, true><<<grid, NT, 0, st>>>(a);
   else blend_fused_kernel<TW, TH, PPT, D, false><<<grid, NT, 0, st>>>(a);
 }

@@ -43,6 +43,7 @@ struct Buffers {
   DevBuf tile_last, ckpt;   // per tile: longest walk; per pixel: state at the backward's chunk boundaries
   DevBuf tile_done;         // fused blend: per tile, its forward is done
   DevBuf block_rank;        // emission: first depth rank of every block of output positions
+  DevBuf bins;              // binning by counting: per (tile, workgroup) counts, then run starts
 };
 
 // Sizes and final buffer roles of one forward render.
@@ -119,6 +120,7 @@ struct gsr_ctx {
   int fuse_blend = 0;                   // mapping iteration: 0 automatic, 1 fused, -1 two launches
   int64_t fused_resident = 0;           // workgroups of the fused blend launch the device holds at once
   int depth_sort = 0;                   // 0 automatic, 1 per-tile sort after binning, 2 one global sort before
+  int binning = 0;                      // 0 radix sort of tile keys, 1 counting where it applies
   int bwd_schedule = 0;                 // blend backward: 0 pixel-parallel, 1 splat-parallel
   float bg[3] = {0.f, 0.f, 0.f};
   float znear = 0.2f;
@@ -370,7 +372,7 @@ inline int bits_for(int64_t max_key) {
 // stream capture can record them.
 int plan_render(gsr_ctx* ctx, const gsr_gaussians* g, int32_t nv, const gsr_camera* cams, RenderPlan* plan);
 int size_render(gsr_ctx* ctx, Buffers& B, RenderPlan& plan, const gsr_image* out, hipStream_t st);
-void front_clears(Buffers& B, const RenderPlan& plan, ClearList& L);
+void front_clears(const gsr_ctx* ctx, Buffers& B, const RenderPlan& plan, ClearList& L);
 void back_clears(Buffers& B, const RenderPlan& plan, ClearList& L);
 int launch_front(gsr_ctx* ctx, Buffers& B, RenderPlan& plan, const float* params, hipStream_t st);
 struct FusedLoss {
@@ -388,11 +390,18 @@ bool use_fused_blend(const gsr_ctx* ctx, const RenderPlan& plan);
 // Whether each tile's list is sorted by depth after binning (else all visible
 // splats are sorted once before binning).
 bool per_tile_depth(const gsr_ctx* ctx, const RenderPlan& plan);
+// Binning by counting for this render (per-tile depth order, every view's
+// tiles within the workgroup bins, the count matrix within its bound and,
+// for a fixed buffer, within that buffer): its matrix size in words (tiles x
+// workgroups per view) and the largest view's tile count, else false.
+bool use_bins(const gsr_ctx* ctx, const Buffers& B, const RenderPlan& plan, int64_t* entries, int* max_view_tiles);
 int size_instances(gsr_ctx* ctx, Buffers& B, const RenderPlan& plan);
 void free_buffers(Buffers& B);
 // Points ctx->na_bufs at the current device's static scratch of the
 // allocation-free render (noalloc.hip).
 int noalloc_attach(gsr_ctx* ctx);
+// HIP error of the calling thread's last failed gsr_ipc_* call (ipc.hip).
+int ipc_last_hip_error();
 // Frees the captured mapping iteration and its buffers (iteration.hip).
 void destroy_graph(gsr_ctx* ctx);
 // Waits for every replay still being timed and adds its stage times to the

@@ -187,6 +187,24 @@ void launch_compact_scan(const uint32_t* ntiles, int64_t n, uint32_t* vals, uint
 void launch_compact_visible(const uint32_t* ntiles, const uint32_t* keys, int64_t n, uint32_t* out_keys,
                             uint32_t* out_vals, uint32_t* count_out, uint32_t* scratch, uint32_t* err, bool clear,
                             hipStream_t st);
+// Binning by counting (the per-tile depth order only): splats per workgroup
+// for n Gaussians per view, whether a view of `tiles` tiles fits the
+// workgroup's bins, and the two passes. bin_count: per workgroup and tile of
+// its view, the instance count, into counts[tile * nb + b] (nb = ceil(n /
+// chunk) workgroups per view; num_tiles * nb words); *visible += the listed
+// splats. After an exclusive scan of counts (in place), bin_scatter: the
+// instances of each tile in positions [start, end) (those below capacity),
+// the tile key and splat index of each, ranges[tile] = [start, end) clipped
+// to capacity, and *overflow set when *total_dev exceeds capacity.
+int bin_chunk(int64_t n);
+bool bin_view_fits(int64_t tiles);
+void launch_bin_count(const uint32_t* ntiles, const int4* rect, const ViewDesc* views, int num_views, int64_t n,
+                      int max_view_tiles, int tile_w, int tile_h, uint32_t* counts, uint32_t* visible,
+                      hipStream_t st);
+void launch_bin_scatter(const uint32_t* ntiles, const int4* rect, const ViewDesc* views, int num_views, int64_t n,
+                        int max_view_tiles, int tile_w, int tile_h, const uint32_t* starts,
+                        const uint32_t* total_dev, int64_t capacity, int64_t num_tiles, uint32_t* keys,
+                        uint32_t* vals, uint2* ranges, uint32_t* overflow, hipStream_t st);
 // Instance emission in depth order; writes beyond `capacity` are dropped and
 // set *overflow when the total exceeds it. With hist (and
 // emit_histogram_fits(hist_bits)) the digit histograms of the written tile
@@ -215,13 +233,15 @@ void launch_tile_order(const uint2* ranges, int64_t num_tiles, uint32_t* order, 
 bool tile_balance_supported(int64_t num_tiles);
 void launch_tile_balance(const uint2* ranges, const uint32_t* tile_last, int64_t num_tiles, int ncu, uint32_t* order,
                          hipStream_t st);
-// Sorts each tile's instances (whose splats arrive in index order) by the raw
-// bits of the splat's depth (zkey, per splat, from the projection), stably:
-// the list order becomes (tile, z bits,
-// index). keys/vals: the tile-sorted instances; keys_alt/vals_alt: scratch of
-// the same size (tiles of more than 1536 instances go through it).
+// Sorts each tile's instances by the raw bits of the splat's depth (zkey, per
+// splat, from the projection), stably, so the list order becomes (tile, z
+// bits, index) when the instances arrive in index order (index_order); else
+// equal depths are put in index order afterwards. keys/vals: the
+// tile-grouped instances; keys_alt/vals_alt: scratch of the same size (tiles
+// of more than 1536 instances go through it).
 void launch_tile_depth_sort(const uint2* ranges, int64_t num_tiles, const uint32_t* zkey, uint32_t* keys,
-                            uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, hipStream_t st);
+                            uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, bool index_order,
+                            hipStream_t st);
 
 // Zeroes up to kMaxClear segments of 32-bit words in one launch.
 constexpr int kMaxClear = 10;
@@ -283,6 +303,12 @@ struct BlendArgs {
   // image gradients from loss_grad.
   uint32_t* tile_done;
   uint32_t* err;
+  // Fused launch over a work queue (when its units outnumber the workgroups
+  // the device holds at once): the next-unit counter, zero before the launch;
+  // null for the plain grid. queue_grid: the workgroups it launches (as
+  // many as the device holds at once).
+  uint32_t* queue;
+  int32_t queue_grid;
 };
 constexpr int kCkptFields = 5;
 bool blend_supported(int tile_w, int tile_h);

@@ -21,13 +21,22 @@ static_assert(sizeof(hipIpcEventHandle_t) <= sizeof(gsr_ipc_handle), "event hand
 // not to return on some drivers.
 constexpr size_t kMaxExportBytes = size_t(1) << 30;
 
+// HIP error code of the last failed call of this file on the calling thread
+// (these calls take no context to record it in)
+thread_local int g_last_hip_error = 0;
+
 int hip_status(hipError_t e) {
   if (e == hipSuccess) return GSR_OK;
+  g_last_hip_error = (int)e;
   (void)hipGetLastError();
   return GSR_ERR_HIP;
 }
 
 }  // namespace
+
+namespace gsr {
+int ipc_last_hip_error() { return g_last_hip_error; }
+}  // namespace gsr
 
 extern "C" {
 

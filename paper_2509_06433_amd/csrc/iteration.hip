@@ -137,7 +137,7 @@ int measure_instances(gsr_ctx* ctx, GraphState* G, const float* params, const gs
   P.capacity = std::max<int64_t>(P.capacity, 0);
   RET_IF(size_render(ctx, G->B, P, out, st));
   ClearList L{};
-  front_clears(G->B, P, L);
+  front_clears(ctx, G->B, P, L);
   launch_clear(L, st);
   const uint32_t mask = ctx->profile_mask;
   ctx->profile_mask = 0;
@@ -183,7 +183,7 @@ int record_iteration(gsr_ctx* ctx, GraphState* G, float* params, float* grad, fl
   uint32_t* totals = as<uint32_t>(B.total);
   // one clear for everything the iteration accumulates into
   ClearList L{};
-  front_clears(B, P, L);
+  front_clears(ctx, B, P, L);
   back_clears(B, P, L);
   // (the gradient is overwritten by the projection backward, so it is not
   // cleared)
@@ -191,7 +191,7 @@ int record_iteration(gsr_ctx* ctx, GraphState* G, float* params, float* grad, fl
   // projection backward zeroes the rows it reads)
   if (loss) L.add(loss, 1);
   const bool fused = use_fused_blend(ctx, P);
-  if (fused) L.add(as<uint32_t>(B.tile_done), P.ntiles);
+  if (fused) L.add(as<uint32_t>(B.tile_done), P.ntiles + 1);
   {
     StageTimer tm(ctx, GSR_STAGE_ZERO, st);
     launch_clear(L, st);

@@ -21,6 +21,9 @@ constexpr int64_t kNaMaxInstances = int64_t(1) << 21;   // (tile, Gaussian) inst
 constexpr int64_t kNaMaxPixels = int64_t(1) << 20;      // over all views
 constexpr int64_t kNaMaxTiles = int64_t(1) << 15;       // over all views
 constexpr int kNaMaxViews = 16;
+// count matrix of the binning by counting (tiles x workgroups per view);
+// larger renders take the radix path
+constexpr int64_t kNaMaxBinEntries = int64_t(1) << 20;
 constexpr size_t kNaBytes = size_t(72) << 20;
 
 static __device__ __align__(256) unsigned char scratch[kNaBytes];
@@ -73,7 +76,8 @@ bool carve(unsigned char* base, Buffers& B) {
   // the scratch sizes of the depth sort and the scans grow with the splat
   // count up to this limit (one sort chunk size below 2^19 elements)
   take(B.hist, u4 * (size_t)radix_scratch_elems(kNaMaxSplats, 32));
-  take(B.partials, 2 * u4 * (size_t)scan_partial_elems(kNaMaxSplats));
+  take(B.bins, u4 * (size_t)kNaMaxBinEntries);
+  take(B.partials, 2 * u4 * (size_t)scan_partial_elems(std::max(kNaMaxSplats, kNaMaxBinEntries)));
   return ok;
 }
 
@@ -162,7 +166,7 @@ int render_noalloc_impl(gsr_ctx* ctx, const gsr_gaussians* g, int32_t nv, const 
   const uint32_t mask = ctx->profile_mask;
   ctx->profile_mask = 0;
   ClearList L{};
-  front_clears(B, P, L);
+  front_clears(ctx, B, P, L);
   back_clears(B, P, L);
   launch_clear(L, st);
   int r = GSR_OK;

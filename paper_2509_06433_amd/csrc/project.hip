@@ -442,6 +442,9 @@ __device__ __forceinline__ bool project_splat(const float* __restrict__ P, int64
 // marks the others), so the full projection runs with the wavefront's lanes
 // busy even where most splats are culled, and the parameter reads stay
 // coalesced.
+// MULTI: the several-view form (a separate instantiation, so that each form
+// gets the registers of its own body).
+template <bool MULTI>
 __global__ void __launch_bounds__(256) project_kernel(const float* __restrict__ P, int64_t n, int64_t stride, int deg,
                                                       int num_views, const ViewDesc* __restrict__ views, int tile_w,
                                                       int tile_h, float znear, Splat* __restrict__ splats,
@@ -469,7 +472,7 @@ __global__ void __launch_bounds__(256) project_kernel(const float* __restrict__ 
       const unsigned long long bad = __ballot(mine && degenerate_gaussian(P, stride, i));
       if (bad && (threadIdx.x & 63) == 0) atomicAdd(nonfinite, (uint32_t)__popcll(bad));
     }
-    if (num_views == 1) {
+    if (!MULTI) {
       uint32_t key;
       if (mine) {
         const bool skip = surely_culled(P, stride, i, views[0], znear);
@@ -486,13 +489,12 @@ __global__ void __launch_bounds__(256) project_kernel(const float* __restrict__ 
       }
       continue;
     }
-    // the Gaussian's view-independent part, formed at its first view that
-    // the early cull keeps
-    GaussLocal L;
-    bool have = false, good = false;
-    float o = 0.0f;
+    // views the early cull rules out get their empty records; the
+    // Gaussian's view-independent part is formed once, before its first view
+    // that the cull keeps (out of the view loop, so that the loop body holds
+    // no exponential: 122 rather than 169 VGPRs, four waves per SIMD)
     int view = mine ? 0 : num_views;
-    while (true) {
+    auto skip_culled = [&]() {
       while (view < num_views && surely_culled(P, stride, i, views[view], znear)) {
         const int64_t s = (int64_t)view * n + i;
         rect[s] = make_int4(0, 0, -1, -1);
@@ -500,18 +502,24 @@ __global__ void __launch_bounds__(256) project_kernel(const float* __restrict__ 
         zkey[s] = 0xFFFFFFFFu;
         ++view;
       }
-      if (!__any(view < num_views)) break;
-      if (view >= num_views) continue;
-      const int cur = view++;
-      if (!have) {
-        good = gaussian_local(P, stride, i, L);
-        o = opacity_of(P[10 * stride + i]);
-        have = true;
+    };
+    skip_culled();
+    GaussLocal L;
+    bool good = false;
+    float o = 0.0f;
+    if (view < num_views) {
+      good = gaussian_local(P, stride, i, L);
+      o = opacity_of(P[10 * stride + i]);
+    }
+    while (__any(view < num_views)) {
+      if (view < num_views) {
+        const int cur = view++;
+        uint32_t key;
+        if (project_splat(P, stride, deg, i, (int64_t)cur * n + i, views[cur], tile_w, tile_h, znear, false, L, good,
+                          o, splats, rect, ntiles, zkey, &key))
+          count_key(key);
+        skip_culled();
       }
-      uint32_t key;
-      if (project_splat(P, stride, deg, i, (int64_t)cur * n + i, views[cur], tile_w, tile_h, znear, false, L, good, o,
-                        splats, rect, ntiles, zkey, &key))
-        count_key(key);
     }
   }
   if (zhist) {
@@ -570,7 +578,17 @@ __device__ __forceinline__ void local_f64(const float* __restrict__ P, int64_t s
   g.o = 1.0 / (1.0 + exp(-(double)P[10 * stride + i]));
 }
 
-__device__ __forceinline__ void view_f64(const LocalD& L, double mx, double my, double mz, const ViewDesc& V,
+// Sigma of local_f64 alone (what the per-view chain rule needs; the rest of
+// the local part is formed again once the views are summed, rather than held
+// in registers across the view loop).
+__device__ __forceinline__ void sigma_f64(const float* __restrict__ P, int64_t stride, int64_t i, double* Sig) {
+  LocalD L;
+  local_f64(P, stride, i, L);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Sig[k] = L.Sig[k];
+}
+
+__device__ __forceinline__ void view_f64(const double* Sig, double mx, double my, double mz, const ViewDesc& V,
                                          ViewD& g) {
   const float* W = V.R;
   g.tx = W[0] * mx + W[1] * my + W[2] * mz + V.t[0];
@@ -595,7 +613,7 @@ __device__ __forceinline__ void view_f64(const LocalD& L, double mx, double my, 
   for (int r = 0; r < 2; ++r)
 #pragma unroll
     for (int k = 0; k < 3; ++k)
-      U[r * 3 + k] = g.Tm[r * 3 + 0] * L.Sig[k] + g.Tm[r * 3 + 1] * L.Sig[3 + k] + g.Tm[r * 3 + 2] * L.Sig[6 + k];
+      U[r * 3 + k] = g.Tm[r * 3 + 0] * Sig[k] + g.Tm[r * 3 + 1] * Sig[3 + k] + g.Tm[r * 3 + 2] * Sig[6 + k];
   g.a = U[0] * g.Tm[0] + U[1] * g.Tm[1] + U[2] * g.Tm[2] + (double)kDilation;
   g.b = U[0] * g.Tm[3] + U[1] * g.Tm[4] + U[2] * g.Tm[5];
   g.c = U[3] * g.Tm[3] + U[4] * g.Tm[4] + U[5] * g.Tm[5] + (double)kDilation;
@@ -625,7 +643,16 @@ __device__ __forceinline__ void sh_basis_d(int deg, double x, double y, double z
 }
 
 // d/d(x, y, z) of sum_k c_k Y_k for the polynomials above.
-__device__ __forceinline__ void sh_dir_grad_d(int deg, double x, double y, double z, const double* c, double* g) {
+// One colour channel's SH coefficients, read from the interleaved float array
+// coef[3 k + ch] and widened at each use (no double copy held in registers).
+struct ChannelCoef {
+  const float* coef;
+  int ch;
+  __device__ __forceinline__ double operator[](int k) const { return (double)coef[3 * k + ch]; }
+};
+
+template <class C>
+__device__ __forceinline__ void sh_dir_grad_d(int deg, double x, double y, double z, const C& c, double* g) {
   g[0] = g[1] = g[2] = 0.0;
   if (deg < 1) return;
   const double C1 = 0.4886025119029199, C2a = 1.0925484305920792, C2b = 0.31539156525252005,
@@ -651,9 +678,6 @@ __device__ __forceinline__ void sh_dir_grad_d(int deg, double x, double y, doubl
   g[0] -= K0 * (3.0 * xx - 3.0 * yy) * c[15];  g[1] += 6.0 * K0 * x * y * c[15];
 }
 
-// Chain rule from the screen-space gradients (u, v, conic, opacity, colour,
-// depth) of every view to the parameters, summed over views, in double.
-// One thread per Gaussian, so the parameter gradients need no atomics.
 // Chain rule of one (view, Gaussian) pair from its screen-space gradient G:
 // adds to the mean and SH gradients, and to the sums over views of dL/dSigma
 // (gSig, 3x3) and dL/dopacity (gO), which finish_local turns into the scale,
@@ -663,15 +687,53 @@ __device__ __forceinline__ void sh_dir_grad_d(int deg, double x, double y, doubl
 // gpose[12]: dL/dR (row-major) and dL/dt of x_cam = R x + t. R acts through
 // the camera-space mean, through T = J R and, for view-dependent colour,
 // through the camera centre -R^T t.
-template <int DEG, bool POSE = false>
-__device__ __forceinline__ void chain_view(const float* __restrict__ P, int64_t stride, int64_t i, const ViewDesc& V,
-                                           const LocalD& L, const double* G, const float* coef, double* gmean,
-                                           double* gSig, double& gO, float* gsh, double* gpose = nullptr) {
+// The colour part of one (view, Gaussian) pair's chain rule: from the colour
+// gradients gcol[3] to the SH coefficients (gsh += ...) and, for DEG > 0, to
+// dL/d(mean - camera centre) through the viewing direction (gview, =).
+// Real SH basis function k at the unit direction (x, y, z) and its gradient
+// with respect to (x, y, z) as a polynomial (the same functions as sh_basis_d
+// and sh_dir_grad_d, one at a time; k is a constant after unrolling).
+__device__ __forceinline__ double sh_term_d(int k, double x, double y, double z, double* d) {
+  const double C0 = 0.28209479177387814, C1 = 0.4886025119029199, C2a = 1.0925484305920792,
+               C2b = 0.31539156525252005, C2c = 0.5462742152960396, K0 = 0.5900435899266435,
+               K1 = 2.890611442640554, K2 = 0.4570457994644658, K3 = 0.3731763325901154,
+               K5 = 1.445305721320277;
+  const double xx = x * x, yy = y * y, zz = z * z;
+  switch (k) {
+    case 0: d[0] = 0.0; d[1] = 0.0; d[2] = 0.0; return C0;
+    case 1: d[0] = 0.0; d[1] = -C1; d[2] = 0.0; return -C1 * y;
+    case 2: d[0] = 0.0; d[1] = 0.0; d[2] = C1; return C1 * z;
+    case 3: d[0] = -C1; d[1] = 0.0; d[2] = 0.0; return -C1 * x;
+    case 4: d[0] = C2a * y; d[1] = C2a * x; d[2] = 0.0; return C2a * x * y;
+    case 5: d[0] = 0.0; d[1] = -C2a * z; d[2] = -C2a * y; return -C2a * y * z;
+    case 6: d[0] = -2.0 * C2b * x; d[1] = -2.0 * C2b * y; d[2] = 4.0 * C2b * z; return C2b * (2.0 * zz - xx - yy);
+    case 7: d[0] = -C2a * z; d[1] = 0.0; d[2] = -C2a * x; return -C2a * x * z;
+    case 8: d[0] = 2.0 * C2c * x; d[1] = -2.0 * C2c * y; d[2] = 0.0; return C2c * (xx - yy);
+    case 9: d[0] = -6.0 * K0 * x * y; d[1] = -K0 * (3.0 * xx - 3.0 * yy); d[2] = 0.0;
+      return -K0 * y * (3.0 * xx - yy);
+    case 10: d[0] = K1 * y * z; d[1] = K1 * x * z; d[2] = K1 * x * y; return K1 * x * y * z;
+    case 11: d[0] = 2.0 * K2 * x * y; d[1] = -K2 * (4.0 * zz - xx - 3.0 * yy); d[2] = -8.0 * K2 * y * z;
+      return -K2 * y * (4.0 * zz - xx - yy);
+    case 12: d[0] = -6.0 * K3 * x * z; d[1] = -6.0 * K3 * y * z; d[2] = K3 * (6.0 * zz - 3.0 * xx - 3.0 * yy);
+      return K3 * z * (2.0 * zz - 3.0 * xx - 3.0 * yy);
+    case 13: d[0] = -K2 * (4.0 * zz - 3.0 * xx - yy); d[1] = 2.0 * K2 * x * y; d[2] = -8.0 * K2 * x * z;
+      return -K2 * x * (4.0 * zz - xx - yy);
+    case 14: d[0] = 2.0 * K5 * x * z; d[1] = -2.0 * K5 * y * z; d[2] = K5 * (xx - yy); return K5 * z * (xx - yy);
+    default: d[0] = -K0 * (3.0 * xx - 3.0 * yy); d[1] = 6.0 * K0 * x * y; d[2] = 0.0;
+      return -K0 * x * (xx - 3.0 * yy);
+  }
+}
+
+// The colour part of one (view, Gaussian) pair's chain rule: from the colour
+// gradients gcol[3] to the SH coefficients (gsh += ...) and, for DEG > 0, to
+// dL/d(mean - camera centre) through the viewing direction (gview, =). Two
+// walks over the basis: the raw colours (for the clamp), then the gradients,
+// each basis function formed where it is used (few registers at degree 3).
+template <int DEG>
+__device__ __forceinline__ void colour_chain(const float* __restrict__ P, int64_t stride, int64_t i,
+                                             const ViewDesc& V, const float* gcol, const float* coef, float* gsh,
+                                             double* gview) {
   constexpr int K = (DEG + 1) * (DEG + 1);
-  ViewD g;
-  view_f64(L, (double)P[0 * stride + i], (double)P[1 * stride + i], (double)P[2 * stride + i], V, g);
-  gO += G[G2_O];
-  // colour
   double dir[3] = {0.0, 0.0, 0.0}, dnorm = 1.0;
   if (DEG > 0) {
     dir[0] = (double)P[0 * stride + i] - (double)V.campos[0];
@@ -680,49 +742,73 @@ __device__ __forceinline__ void chain_view(const float* __restrict__ P, int64_t 
     dnorm = sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
     dir[0] /= dnorm; dir[1] /= dnorm; dir[2] /= dnorm;
   }
-  double Y[16];
-  sh_basis_d(DEG, dir[0], dir[1], dir[2], Y);
+  double raw[3] = {0.5, 0.5, 0.5};
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double d[3];
+    const double Yk = sh_term_d(k, dir[0], dir[1], dir[2], d);
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) raw[ch] += (double)coef[3 * k + ch] * Yk;
+  }
+  // the clamp at zero passes no gradient
+  double gc[3];
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) gc[ch] = raw[ch] < 0.0 ? 0.0 : (double)gcol[ch];
   double gdir[3] = {0.0, 0.0, 0.0};
+  // the second walk forms the basis again rather than keeping the first
+  // walk's values (an empty asm hides that the direction is the same)
+  double ux = dir[0], uy = dir[1], uz = dir[2];
+  asm volatile("" : "+v"(ux), "+v"(uy), "+v"(uz));
 #pragma unroll
-  for (int ch = 0; ch < 3; ++ch) {
-    double cc[K];
+  for (int k = 0; k < K; ++k) {
+    double d[3];
+    const double Yk = sh_term_d(k, ux, uy, uz, d);
+    double w = 0.0;
 #pragma unroll
-    for (int k = 0; k < K; ++k) cc[k] = coef[3 * k + ch];
-    double raw = 0.5;
-#pragma unroll
-    for (int k = 0; k < K; ++k) raw += cc[k] * Y[k];
-    if (raw < 0.0) continue;
-    const double gc = G[G2_R + ch];
-#pragma unroll
-    for (int k = 0; k < K; ++k) gsh[3 * k + ch] += (float)(gc * Y[k]);
+    for (int ch = 0; ch < 3; ++ch) {
+      if (!(raw[ch] < 0.0)) gsh[3 * k + ch] += (float)(gc[ch] * Yk);
+      w += gc[ch] * (double)coef[3 * k + ch];
+    }
     if (DEG > 0) {
-      double gd[3];
-      sh_dir_grad_d(DEG, dir[0], dir[1], dir[2], cc, gd);
-      gdir[0] += gc * gd[0];
-      gdir[1] += gc * gd[1];
-      gdir[2] += gc * gd[2];
+      gdir[0] += w * d[0];
+      gdir[1] += w * d[1];
+      gdir[2] += w * d[2];
     }
   }
-  double gview[3] = {0.0, 0.0, 0.0};   // dL/d(mean - camera centre) through the colour
+#pragma unroll
+  for (int j = 0; j < 3; ++j) gview[j] = 0.0;
   if (DEG > 0) {
     const double dot = dir[0] * gdir[0] + dir[1] * gdir[1] + dir[2] * gdir[2];
 #pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      gview[j] = (gdir[j] - dir[j] * dot) / dnorm;
-      gmean[j] += gview[j];
-    }
+    for (int j = 0; j < 3; ++j) gview[j] = (gdir[j] - dir[j] * dot) / dnorm;
+  }
+}
+
+// COLOUR false: the colour part is left out (sh_backward_kernel forms it).
+template <int DEG, bool POSE = false, bool COLOUR = true>
+__device__ __forceinline__ void chain_view(const float* __restrict__ P, int64_t stride, int64_t i, const ViewDesc& V,
+                                           const double* Sig, const float* G, const float* coef, double* gmean,
+                                           double* gSig, double& gO, float* gsh, double* gpose = nullptr) {
+  ViewD g;
+  view_f64(Sig, (double)P[0 * stride + i], (double)P[1 * stride + i], (double)P[2 * stride + i], V, g);
+  gO += (double)G[G2_O];
+  double gview[3] = {0.0, 0.0, 0.0};   // dL/d(mean - camera centre) through the colour
+  if (COLOUR) {
+    colour_chain<DEG>(P, stride, i, V, G + G2_R, coef, gsh, gview);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) gmean[j] += gview[j];
   }
   // conic (A, B, C) = (c, -b, a) / det
   const double a = g.a, b = g.b, c = g.c, det = g.det;
   const double id = 1.0 / det, id2 = id * id;
-  const double gA = G[G2_A], gB = G[G2_B], gC = G[G2_C];
+  const double gA = (double)G[G2_A], gB = (double)G[G2_B], gC = (double)G[G2_C];
   const double ga = (-gA * c * c + gB * b * c - gC * b * b) * id2;
   const double gb = (2.0 * gA * b * c - 2.0 * gB * b * b + 2.0 * gC * a * b) * id2 - gB * id;
   const double gc_ = (-gA * b * b + gB * a * b - gC * a * a) * id2;
   // Sigma' = T Sigma T^T
   const double* T0 = g.Tm;
   const double* T1 = g.Tm + 3;
-  const double* S = L.Sig;
+  const double* S = Sig;
   double ST0[3], ST1[3];
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
@@ -765,11 +851,12 @@ __device__ __forceinline__ void chain_view(const float* __restrict__ P, int64_t 
     gty += gyi * itz;
     gtz += -gyi * ty * itz2;
   }
-  gtx += G[G2_U] * fx * itz;
-  gtz += -G[G2_U] * fx * tx * itz2;
-  gty += G[G2_V] * fy * itz;
-  gtz += -G[G2_V] * fy * ty * itz2;
-  gtz += G[G2_Z];
+  const double gu = (double)G[G2_U], gv = (double)G[G2_V];
+  gtx += gu * fx * itz;
+  gtz += -gu * fx * tx * itz2;
+  gty += gv * fy * itz;
+  gtz += -gv * fy * ty * itz2;
+  gtz += (double)G[G2_Z];
 #pragma unroll
   for (int j = 0; j < 3; ++j) gmean[j] += W[j] * gtx + W[3 + j] * gty + W[6 + j] * gtz;
   if (POSE) {
@@ -828,6 +915,13 @@ __device__ __forceinline__ void finish_local(const LocalD& L, const double* gSig
   gq[3] += (gz - z * dot) / L.qn;
 }
 
+// Chain rule from the screen-space gradients (u, v, conic, opacity, colour,
+// depth) of every view to the parameters, summed over views, in double.
+// One thread per Gaussian, so the parameter gradients need no atomics. For
+// DEG > 0 the colour part (the SH coefficients and the mean's share through
+// the viewing direction) is left to sh_backward_kernel, launched after this
+// one: the two halves each fit in fewer registers than the whole (for SH
+// degree 3, 256 VGPRs and one wave per SIMD together).
 template <int DEG>
 __global__ void __launch_bounds__(256) project_backward_kernel(const float* __restrict__ P, int64_t n, int64_t stride,
                                                                int num_views, const ViewDesc* __restrict__ views,
@@ -835,44 +929,50 @@ __global__ void __launch_bounds__(256) project_backward_kernel(const float* __re
                                                                const uint32_t* __restrict__ ntiles,
                                                                float* __restrict__ grad, bool overwrite,
                                                                bool zero_g2, IterCounters counters) {
-  constexpr int K = (DEG + 1) * (DEG + 1);
+  constexpr bool kColour = DEG == 0;
+  constexpr int K = kColour ? 1 : 0;
   if (counters.stats && blockIdx.x == 0 && threadIdx.x == 0) count_iteration(counters);
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     double gmean[3] = {0, 0, 0}, gls[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, glogit = 0.0;
-    float gsh[3 * K];          // SH gradients: one term per view, float is enough
+    float gsh[3 * K + 1];      // SH gradients (degree 0 only): one term per view, float is enough
 #pragma unroll
     for (int k = 0; k < 3 * K; ++k) gsh[k] = 0.0f;
-    float coef[3 * K];         // SH coefficients, read once (float keeps the register footprint down)
+    float coef[3 * K + 1];     // SH coefficients, read once
 #pragma unroll
     for (int k = 0; k < 3 * K; ++k) coef[k] = P[(11 + k) * stride + i];
     bool touched = false;
-    LocalD L;                  // formed at the first view that passes the Gaussian a gradient
+    double Sig[9];             // formed at the first view that passes the Gaussian a gradient
     double gSig[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, gO = 0.0;
     // views in lockstep (the view descriptor stays wave-uniform, in scalar
     // registers); a lane skips the views that do not see its Gaussian
     for (int cur = 0; cur < num_views; ++cur) {
       if (ntiles[(int64_t)cur * n + i] == 0u) continue;
       float* gv = g2 + ((int64_t)cur * n + i) * G2_N;
-      double G[G2_N];
+      float G[G2_N];
       bool any = false;
 #pragma unroll
       for (int k = 0; k < G2_N; ++k) {
         G[k] = gv[k];
-        any = any || (G[k] != 0.0);
+        any = any || (G[k] != 0.0f);
       }
       if (!any) continue;
       // the mapping iteration leaves the accumulators clean for its next
-      // replay: only rows of splats with tiles ever receive gradients
-      if (zero_g2) {
+      // replay: only rows of splats with tiles ever receive gradients (the
+      // colour half clears them where it runs)
+      if (zero_g2 && kColour) {
 #pragma unroll
         for (int k = 0; k < G2_N; ++k) gv[k] = 0.0f;
       }
-      if (!touched) local_f64(P, stride, i, L);
+      if (!touched) sigma_f64(P, stride, i, Sig);
       touched = true;
       const ViewDesc& V = views[cur];
-      chain_view<DEG>(P, stride, i, V, L, G, coef, gmean, gSig, gO, gsh);
+      chain_view<DEG, false, kColour>(P, stride, i, V, Sig, G, coef, gmean, gSig, gO, gsh);
     }
-    if (touched) finish_local(L, gSig, gO, gls, gq, glogit);
+    if (touched) {
+      LocalD L;
+      local_f64(P, stride, i, L);
+      finish_local(L, gSig, gO, gls, gq, glogit);
+    }
     if (overwrite) {
       // every plane is written (zero for a Gaussian no view composited)
 #pragma unroll
@@ -899,6 +999,64 @@ __global__ void __launch_bounds__(256) project_backward_kernel(const float* __re
   }
 }
 
+// The colour half of the chain rule for DEG > 0 (after
+// project_backward_kernel, which left it out): per Gaussian, over its views,
+// the SH coefficients' gradient and the mean's share through the viewing
+// direction, written (overwrite: every SH plane) or added (mean planes: always
+// added, after the geometry half). Clears the screen-space gradient rows it
+// reads when zero_g2.
+template <int DEG>
+__global__ void __launch_bounds__(256) sh_backward_kernel(const float* __restrict__ P, int64_t n, int64_t stride,
+                                                          int num_views, const ViewDesc* __restrict__ views,
+                                                          float* __restrict__ g2,
+                                                          const uint32_t* __restrict__ ntiles,
+                                                          float* __restrict__ grad, bool overwrite, bool zero_g2) {
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    float gsh[3 * K];
+#pragma unroll
+    for (int k = 0; k < 3 * K; ++k) gsh[k] = 0.0f;
+    float coef[3 * K];
+#pragma unroll
+    for (int k = 0; k < 3 * K; ++k) coef[k] = P[(11 + k) * stride + i];
+    double gmean[3] = {0, 0, 0};
+    bool touched = false;
+    for (int cur = 0; cur < num_views; ++cur) {
+      if (ntiles[(int64_t)cur * n + i] == 0u) continue;
+      float* gv = g2 + ((int64_t)cur * n + i) * G2_N;
+      float G[G2_N];
+      bool any = false;
+#pragma unroll
+      for (int k = 0; k < G2_N; ++k) {
+        G[k] = gv[k];
+        any = any || (G[k] != 0.0f);
+      }
+      if (!any) continue;
+      if (zero_g2) {
+#pragma unroll
+        for (int k = 0; k < G2_N; ++k) gv[k] = 0.0f;
+      }
+      if (G[G2_R] == 0.0f && G[G2_G] == 0.0f && G[G2_BL] == 0.0f) continue;
+      touched = true;
+      double gview[3];
+      colour_chain<DEG>(P, stride, i, views[cur], G + G2_R, coef, gsh, gview);
+#pragma unroll
+      for (int j = 0; j < 3; ++j) gmean[j] += gview[j];
+    }
+    if (overwrite) {
+#pragma unroll
+      for (int k = 0; k < 3 * K; ++k) grad[(11 + k) * stride + i] = gsh[k];
+    } else if (touched) {
+#pragma unroll
+      for (int k = 0; k < 3 * K; ++k) grad[(11 + k) * stride + i] += gsh[k];
+    }
+    if (touched) {
+#pragma unroll
+      for (int j = 0; j < 3; ++j) grad[j * stride + i] += (float)gmean[j];
+    }
+  }
+}
+
 // Camera gradient of every view: per (view, Gaussian) the chain rule of
 // chain_view with the pose terms, summed over each workgroup (in double) and
 // added with one atomic per (workgroup, view, component). gcam[v][12] += dL/dR
@@ -922,29 +1080,29 @@ __global__ void __launch_bounds__(256) pose_backward_kernel(const float* __restr
     float coef[3 * K];
 #pragma unroll
     for (int k = 0; k < 3 * K; ++k) coef[k] = mine ? P[(11 + k) * stride + i] : 0.0f;
-    LocalD L;
-    bool haveL = false;
+    double Sig[9];
+    bool haveS = false;
     for (int cur = 0; cur < num_views; ++cur) {
       double gp[12];
 #pragma unroll
       for (int k = 0; k < 12; ++k) gp[k] = 0.0;
       if (mine && ntiles[(int64_t)cur * n + i] != 0u) {
         const float* gv = g2 + ((int64_t)cur * n + i) * G2_N;
-        double G[G2_N];
+        float G[G2_N];
         bool any = false;
 #pragma unroll
         for (int k = 0; k < G2_N; ++k) {
           G[k] = gv[k];
-          any = any || (G[k] != 0.0);
+          any = any || (G[k] != 0.0f);
         }
         if (any) {
-          if (!haveL) local_f64(P, stride, i, L);
-          haveL = true;
+          if (!haveS) sigma_f64(P, stride, i, Sig);
+          haveS = true;
           double gmean[3] = {0, 0, 0}, gSig[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, gO = 0.0;
           float gsh[3 * K];
 #pragma unroll
           for (int k = 0; k < 3 * K; ++k) gsh[k] = 0.0f;
-          chain_view<DEG, true>(P, stride, i, views[cur], L, G, coef, gmean, gSig, gO, gsh, gp);
+          chain_view<DEG, true>(P, stride, i, views[cur], Sig, G, coef, gmean, gSig, gO, gsh, gp);
         }
       }
 #pragma unroll
@@ -1042,8 +1200,14 @@ void launch_project(const float* params, int64_t n, int64_t stride, int deg, int
                     uint32_t* zkey, uint32_t* zhist, int zrb, int zpasses, uint32_t* nonfinite, hipStream_t st) {
   if (n == 0 || num_views == 0) return;
   if (zpasses * (1 << zrb) > 3 * 2048) zhist = nullptr;
-  project_kernel<<<grid_for(n, 256), 256, 0, st>>>(params, n, stride, deg, num_views, views, tile_w, tile_h, znear,
-                                                   splats, rect, ntiles, zkey, zhist, zrb, zpasses, nonfinite);
+  if (num_views == 1)
+    project_kernel<false><<<grid_for(n, 256), 256, 0, st>>>(params, n, stride, deg, num_views, views, tile_w, tile_h,
+                                                            znear, splats, rect, ntiles, zkey, zhist, zrb, zpasses,
+                                                            nonfinite);
+  else
+    project_kernel<true><<<grid_for(n, 256), 256, 0, st>>>(params, n, stride, deg, num_views, views, tile_w, tile_h,
+                                                           znear, splats, rect, ntiles, zkey, zhist, zrb, zpasses,
+                                                           nonfinite);
 }
 
 void launch_activations(const float* params, int64_t n, int64_t stride, float* scale, float* opacity,
@@ -1067,14 +1231,20 @@ void launch_project_backward(const float* params, int64_t n, int64_t stride, int
     case 1:
       project_backward_kernel<1><<<gsz, 256, 0, st>>>(params, n, stride, num_views, views, g2, ntiles, grad, overwrite,
                                                           zero_g2, ic);
+      sh_backward_kernel<1><<<gsz, 256, 0, st>>>(params, n, stride, num_views, views, g2, ntiles, grad, overwrite,
+                                                     zero_g2);
       break;
     case 2:
       project_backward_kernel<2><<<gsz, 256, 0, st>>>(params, n, stride, num_views, views, g2, ntiles, grad, overwrite,
                                                           zero_g2, ic);
+      sh_backward_kernel<2><<<gsz, 256, 0, st>>>(params, n, stride, num_views, views, g2, ntiles, grad, overwrite,
+                                                     zero_g2);
       break;
     default:
       project_backward_kernel<3><<<gsz, 256, 0, st>>>(params, n, stride, num_views, views, g2, ntiles, grad, overwrite,
                                                           zero_g2, ic);
+      sh_backward_kernel<3><<<gsz, 256, 0, st>>>(params, n, stride, num_views, views, g2, ntiles, grad, overwrite,
+                                                     zero_g2);
       break;
   }
 }

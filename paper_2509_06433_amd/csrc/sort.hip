@@ -743,6 +743,122 @@ __global__ void __launch_bounds__(kSortThreads) onesweep_pass_kernel(
   }
 }
 
+// ---------------------------------------------------------------------------
+// Binning by counting, for the per-tile depth order (each tile's list is
+// sorted by (depth, index) after binning, so the binning itself only has to
+// group the instances by tile). Workgroup (v, b) owns the splats [b C, (b +
+// 1) C) of view v. bin_count_kernel counts its instances per tile of the view
+// in LDS and stores the counts tile-major, counts[tile * nb + b] (tile =
+// global tile id, nb workgroups per view); one exclusive scan over that
+// matrix gives each (tile, workgroup) run its first output position, tiles in
+// global order; bin_scatter_kernel walks the same instances again and puts
+// each into its workgroup's run of its tile (in LDS-atomic order: the depth
+// sort that follows imposes the final order) and writes the tile ranges.
+// This replaces the emission, the radix sort of the tile keys and the range
+// search of the general path: no global atomics, two passes over the splats'
+// records and one over the instances.
+// ---------------------------------------------------------------------------
+constexpr int kBinThreads = 1024;        // one splat per thread per round
+constexpr int kBinMaxTiles = 8192;       // tiles of one view (LDS bins, 32 KB)
+
+struct BinArgs {
+  const uint32_t* ntiles;     // [V * n] tile count per splat (0: not listed)
+  const int4* rect;           // [V * n] pixel rectangle, inclusive
+  const ViewDesc* views;
+  int64_t n;                  // Gaussians (splats per view)
+  int chunk;                  // splats per workgroup, a multiple of kBinThreads
+  int nb;                     // workgroups per view
+  int tw_log2, th_log2;       // tile size (powers of two)
+};
+
+// The tile rectangle of splat sidx (a listed one): its first view-local tile,
+// width and height in tiles.
+__device__ __forceinline__ void bin_rect(const BinArgs& a, int tiles_x, int64_t sidx, int* first, int* w, int* h) {
+  const int4 r = a.rect[sidx];
+  const int tx0 = r.x >> a.tw_log2, tx1 = r.z >> a.tw_log2;
+  const int ty0 = r.y >> a.th_log2, ty1 = r.w >> a.th_log2;
+  *first = ty0 * tiles_x + tx0;
+  *w = tx1 - tx0 + 1;
+  *h = ty1 - ty0 + 1;
+}
+
+__global__ void __launch_bounds__(kBinThreads) bin_count_kernel(BinArgs a, uint32_t* __restrict__ counts,
+                                                                uint32_t* __restrict__ visible_out) {
+  extern __shared__ uint32_t s_bins[];                 // the view's tiles
+  __shared__ uint32_t s_visible;
+  const int v = blockIdx.x / a.nb, b = blockIdx.x % a.nb;
+  const ViewDesc& V = a.views[v];
+  const int tiles_x = V.tiles_x, tiles = V.tiles_x * V.tiles_y;
+  for (int t = threadIdx.x; t < tiles; t += kBinThreads) s_bins[t] = 0u;
+  if (threadIdx.x == 0) s_visible = 0u;
+  __syncthreads();
+  uint32_t visible = 0;
+  const int64_t c0 = (int64_t)b * a.chunk, c1 = min(c0 + (int64_t)a.chunk, a.n);
+  for (int64_t j = c0 + threadIdx.x; j < c1; j += kBinThreads) {
+    const int64_t sidx = (int64_t)v * a.n + j;
+    if (a.ntiles[sidx] == 0u) continue;
+    ++visible;
+    int first, w, h;
+    bin_rect(a, tiles_x, sidx, &first, &w, &h);
+    for (int dy = 0; dy < h; ++dy)
+      for (int dx = 0; dx < w; ++dx) atomicAdd(&s_bins[first + dy * tiles_x + dx], 1u);
+  }
+  const uint64_t any = __ballot(visible != 0u);
+  if (any) {
+    uint32_t x = visible;
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, 64);
+    if ((threadIdx.x & 63) == 0) atomicAdd(&s_visible, x);
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < tiles; t += kBinThreads)
+    counts[(int64_t)(V.tile_offset + t) * a.nb + b] = s_bins[t];
+  if (threadIdx.x == 0 && s_visible) atomicAdd(visible_out, s_visible);
+}
+
+__global__ void __launch_bounds__(kBinThreads) bin_scatter_kernel(BinArgs a, const uint32_t* __restrict__ starts,
+                                                                  const uint32_t* __restrict__ total_dev,
+                                                                  int64_t capacity, int64_t num_tiles,
+                                                                  uint32_t* __restrict__ keys,
+                                                                  uint32_t* __restrict__ vals,
+                                                                  uint2* __restrict__ ranges,
+                                                                  uint32_t* __restrict__ overflow) {
+  extern __shared__ uint32_t s_bins[];                 // next free position of each tile's run
+  const int v = blockIdx.x / a.nb, b = blockIdx.x % a.nb;
+  const ViewDesc& V = a.views[v];
+  const int tiles_x = V.tiles_x, tiles = V.tiles_x * V.tiles_y;
+  const uint32_t toff = (uint32_t)V.tile_offset;
+  const uint32_t total = *total_dev;
+  const uint32_t cap = (uint32_t)min(capacity, (int64_t)0xFFFFFFFF);
+  if (blockIdx.x == 0 && threadIdx.x == 0 && (int64_t)total > capacity) atomicOr(overflow, 1u);
+  for (int t = threadIdx.x; t < tiles; t += kBinThreads) s_bins[t] = starts[(int64_t)(toff + t) * a.nb + b];
+  // the ranges of this view's tiles, spread over its workgroups; clipped to
+  // the instance storage (an overflowing render lists only what fits)
+  for (int t = b * kBinThreads + threadIdx.x; t < tiles; t += a.nb * kBinThreads) {
+    const int64_t g = (int64_t)toff + t;
+    const uint32_t st = starts[g * a.nb];
+    const uint32_t en = g + 1 < num_tiles ? starts[(g + 1) * a.nb] : total;
+    ranges[g] = make_uint2(min(st, cap), min(en, cap));
+  }
+  __syncthreads();
+  const int64_t c0 = (int64_t)b * a.chunk, c1 = min(c0 + (int64_t)a.chunk, a.n);
+  for (int64_t j = c0 + threadIdx.x; j < c1; j += kBinThreads) {
+    const int64_t sidx = (int64_t)v * a.n + j;
+    if (a.ntiles[sidx] == 0u) continue;
+    int first, w, h;
+    bin_rect(a, tiles_x, sidx, &first, &w, &h);
+    for (int dy = 0; dy < h; ++dy)
+      for (int dx = 0; dx < w; ++dx) {
+        const int t = first + dy * tiles_x + dx;
+        const uint32_t pos = atomicAdd(&s_bins[t], 1u);
+        if (pos < cap) {
+          keys[pos] = toff + (uint32_t)t;
+          vals[pos] = (uint32_t)sidx;
+        }
+      }
+  }
+}
+
 // Instance emission, balanced over the output: workgroup b writes the
 // output positions [1024 b, 1024 b + 1024). emit_plan_kernel first records,
 // per block, the depth rank whose instances hold the block's first position;
@@ -976,6 +1092,41 @@ __device__ __forceinline__ void tile_sort_rank(const uint32_t* k, int n, int shi
   }
 }
 
+// A tile's list [0, n) sorted by depth key: each run of equal keys is put in
+// splat-index order (odd-even transposition within the runs until two
+// consecutive rounds change nothing; a list without equal keys costs one
+// comparison per entry). The binning leaves equal depths in whatever order it
+// placed them (index order for the radix path, LDS-atomic order for the
+// counting path); the list order is (tile, depth, index) either way. k and v
+// are LDS or global: every thread of the workgroup calls this together.
+__device__ void order_equal_depths(const uint32_t* k, uint32_t* v, int n) {
+  bool tie = false;
+  for (int e = threadIdx.x; e + 1 < n; e += kTileSortThreads) tie = tie || (k[e] == k[e + 1]);
+  if (!__syncthreads_or(tie)) return;
+  bool prev = true;
+  for (int round = 0;; ++round) {
+    bool swapped = false;
+    const int par = round & 1;
+    for (int q = threadIdx.x; 2 * q + par + 1 < n; q += kTileSortThreads) {
+      const int i = 2 * q + par;
+      if (k[i] == k[i + 1]) {
+        const uint32_t a = v[i], b = v[i + 1];
+        if (a > b) {
+          v[i] = b;
+          v[i + 1] = a;
+          swapped = true;
+        }
+      }
+    }
+    const bool any = __syncthreads_or(swapped);
+    if (!any && !prev) break;
+    prev = any;
+  }
+}
+
+// TIES: the lists did not arrive in splat-index order (the counting
+// binning): equal depths are put in index order after the passes.
+template <bool TIES>
 __global__ void __launch_bounds__(kTileSortThreads) tile_depth_sort_kernel(
     const uint2* __restrict__ ranges, int64_t num_tiles, const uint32_t* __restrict__ zkey,
     uint32_t* __restrict__ keys, uint32_t* __restrict__ vals, uint32_t* __restrict__ keys_alt,
@@ -1058,10 +1209,12 @@ __global__ void __launch_bounds__(kTileSortThreads) tile_depth_sort_kernel(
         }
         __syncthreads();
       }
+      // the fourth pass left the list in s_k[0], s_v[0]
+      if (TIES) order_equal_depths(s_k[0], s_v[0], n);
 #pragma unroll
       for (int r = 0; r < kTileSortRows; ++r) {
         const int e = wave * (64 * kTileSortRows) + r * 64 + lane;
-        if (e < n) vals[rg.x + e] = v[r];
+        if (e < n) vals[rg.x + e] = s_v[0][e];
       }
     } else {
       // longer lists, through global memory: per pass, the digit totals of
@@ -1164,8 +1317,10 @@ __global__ void __launch_bounds__(kTileSortThreads) tile_depth_sort_kernel(
           __syncthreads();
         }
       }
-      // four passes end in (keys, vals); the keys held depth bits: restore
-      // the tile key
+      // four passes end in (keys, vals); the keys held depth bits: order
+      // equal depths, then restore the tile key
+      __syncthreads();
+      if (TIES) order_equal_depths(keys + rg.x, vals + rg.x, n);
       for (int e = tid; e < n; e += kTileSortThreads) keys[rg.x + e] = (uint32_t)tile;
     }
     __syncthreads();
@@ -1400,6 +1555,54 @@ bool emit_histogram_fits(int bits) {
   return bits > 0 && hp * (1 << rb) <= kEmitHist;
 }
 
+int bin_chunk(int64_t n) {
+  // a workgroup per 1024 splats of a view fills the chip at one view; fewer
+  // and longer ones (a smaller count matrix) for large maps
+  const int64_t rounds = n / ((int64_t)kBinThreads * 192);
+  return kBinThreads * (int)(rounds < 1 ? 1 : (rounds > 8 ? 8 : rounds));
+}
+
+bool bin_view_fits(int64_t tiles) { return tiles <= kBinMaxTiles; }
+
+static BinArgs bin_args(const uint32_t* ntiles, const int4* rect, const ViewDesc* views, int64_t n, int tile_w,
+                        int tile_h) {
+  BinArgs a;
+  a.ntiles = ntiles;
+  a.rect = rect;
+  a.views = views;
+  a.n = n;
+  a.chunk = bin_chunk(n);
+  a.nb = (int)((n + a.chunk - 1) / a.chunk);
+  a.tw_log2 = __builtin_ctz((unsigned)tile_w);
+  a.th_log2 = __builtin_ctz((unsigned)tile_h);
+  return a;
+}
+
+void launch_bin_count(const uint32_t* ntiles, const int4* rect, const ViewDesc* views, int num_views, int64_t n,
+                      int max_view_tiles, int tile_w, int tile_h, uint32_t* counts, uint32_t* visible,
+                      hipStream_t st) {
+  if (n == 0 || num_views == 0) return;
+  const BinArgs a = bin_args(ntiles, rect, views, n, tile_w, tile_h);
+  bin_count_kernel<<<(unsigned)(num_views * a.nb), kBinThreads, sizeof(uint32_t) * (size_t)max_view_tiles, st>>>(
+      a, counts, visible);
+}
+
+void launch_bin_scatter(const uint32_t* ntiles, const int4* rect, const ViewDesc* views, int num_views, int64_t n,
+                        int max_view_tiles, int tile_w, int tile_h, const uint32_t* starts,
+                        const uint32_t* total_dev, int64_t capacity, int64_t num_tiles, uint32_t* keys,
+                        uint32_t* vals, uint2* ranges, uint32_t* overflow, hipStream_t st) {
+  if (n == 0 || num_views == 0) {
+    // no splat: every tile is empty
+    if (num_tiles > 0)
+      fill_u32_kernel<<<grid_cap(2 * num_tiles, 256), 256, 0, st>>>(reinterpret_cast<uint32_t*>(ranges), 0u,
+                                                                    2 * num_tiles);
+    return;
+  }
+  const BinArgs a = bin_args(ntiles, rect, views, n, tile_w, tile_h);
+  bin_scatter_kernel<<<(unsigned)(num_views * a.nb), kBinThreads, sizeof(uint32_t) * (size_t)max_view_tiles, st>>>(
+      a, starts, total_dev, capacity, num_tiles, keys, vals, ranges, overflow);
+}
+
 void launch_tile_ranges(const uint32_t* keys, const uint32_t* n_dev, int64_t count, uint2* ranges, int64_t num_tiles,
                         bool clear, hipStream_t st) {
   if (clear)
@@ -1411,11 +1614,16 @@ void launch_tile_ranges(const uint32_t* keys, const uint32_t* n_dev, int64_t cou
 
 
 void launch_tile_depth_sort(const uint2* ranges, int64_t num_tiles, const uint32_t* zkey, uint32_t* keys,
-                            uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, hipStream_t st) {
+                            uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, bool index_order,
+                            hipStream_t st) {
   if (num_tiles == 0) return;
   const unsigned grid = (unsigned)(num_tiles < 65536 ? num_tiles : 65536);
-  tile_depth_sort_kernel<<<grid, kTileSortThreads, 0, st>>>(ranges, num_tiles, zkey, keys, vals, keys_alt,
-                                                             vals_alt);
+  if (index_order)
+    tile_depth_sort_kernel<false><<<grid, kTileSortThreads, 0, st>>>(ranges, num_tiles, zkey, keys, vals, keys_alt,
+                                                                      vals_alt);
+  else
+    tile_depth_sort_kernel<true><<<grid, kTileSortThreads, 0, st>>>(ranges, num_tiles, zkey, keys, vals, keys_alt,
+                                                                     vals_alt);
 }
 
 void launch_tile_order(const uint2* ranges, int64_t num_tiles, uint32_t* order, hipStream_t st) {

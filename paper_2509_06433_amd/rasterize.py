@@ -16,15 +16,15 @@ class Rasterizer:
     """Owns one gsr context (device scratch) and its options."""
 
     def __init__(self, tile_w=16, tile_h=16, bg=(0.0, 0.0, 0.0), znear=0.2, pixels_per_thread=0, batch_depth=0,
-                 tile_order=0, chunk_len=0, max_chunks=0, fuse_blend=0, depth_sort=0, backward_schedule=0):
+                 tile_order=0, chunk_len=0, max_chunks=0, fuse_blend=0, depth_sort=0, backward_schedule=0, binning=0):
         self.tile_w, self.tile_h = tile_w, tile_h
         self.pixels_per_thread, self.batch_depth, self.tile_order = pixels_per_thread, batch_depth, tile_order
         self.chunk_len, self.max_chunks, self.fuse_blend = chunk_len, max_chunks, fuse_blend
-        self.depth_sort, self.backward_schedule = depth_sort, backward_schedule
+        self.depth_sort, self.backward_schedule, self.binning = depth_sort, backward_schedule, binning
         self.bg = tuple(float(x) for x in bg)
         self.znear = znear
         self.handle = _lib.gsr_create(tile_w, tile_h, batch_depth, self.bg, znear, pixels_per_thread, tile_order,
-                                      chunk_len, max_chunks, fuse_blend, depth_sort, backward_schedule)
+                                      chunk_len, max_chunks, fuse_blend, depth_sort, backward_schedule, binning)
 
     def close(self):
         if self.handle is not None:

@@ -93,3 +93,26 @@ def test_product_does_not_import_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "oracle.cpp" not in text, f
+
+
+
+def test_viewer_process_argument_checks(tmp_path):
+    """The viewer process refuses bad arguments and an unreadable or short
+    handle file before it touches the GPU."""
+    import subprocess
+    import sys
+    env = dict(os.environ, PYTHONPATH=ROOT)
+    run = lambda *args: subprocess.run([sys.executable, "-m", "paper_2509_06433_amd.viewer", *args],
+                                       capture_output=True, text=True, timeout=120, env=env, cwd=ROOT)
+    cam = ",".join(["1", "0", "0", "0", "1", "0", "0", "0", "1", "0", "0", "0", "100", "100", "32", "24", "64", "48"])
+    r = run()
+    assert r.returncode == 2
+    r = run(str(tmp_path / "no_such_handle_file"), "--num", "10", "--stride", "10", "--deg", "0", "--cam", cam,
+            "--frames", "1")
+    assert r.returncode == 1 and '"error"' in r.stdout, (r.stdout, r.stderr[-500:])
+    short = tmp_path / "short.bin"
+    short.write_bytes(b"\0" * 10)
+    r = run(str(short), "--num", "10", "--stride", "10", "--deg", "0", "--cam", cam, "--frames", "1")
+    assert r.returncode == 1 and "short handle file" in r.stdout
+    r = run(str(short), "--num", "10", "--stride", "5", "--deg", "0", "--cam", cam, "--frames", "1")
+    assert r.returncode == 2

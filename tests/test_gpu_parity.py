@@ -87,16 +87,8 @@ def test_tile_list_bit_exact(gpu, orc, name, tile):
     assert np.array_equal(g_gpu, g_ref)
 
 
-@pytest.mark.parametrize("depth_sort", [1, 2])
-@pytest.mark.parametrize("big", ["none", "all", "mixed"])
-def test_tile_list_depth_sort_modes(gpu, orc, depth_sort, big):
-    """Both depth orders (per tile after binning; once over all splats before
-    binning) against the oracle's list, bit-exact. all: 5000 Gaussians large
-    enough to cover every tile of a 40x24 view, so every list is longer than
-    the 1536 entries a tile sorts in LDS; ten of them share one depth, so the
-    index breaks their tie. mixed: on a 96x32 view 2000 Gaussians crowd the
-    four left tiles (over 2000 entries each) while 2000 small ones spread over
-    the rest (under 700), so both paths meet in one launch."""
+def depth_case(big):
+    """(scene, params) of the depth-order tests (see below)."""
     if big == "all":
         s = scenes.tiny_random(23, n=5000, width=40, height=24)
         p = s.params.copy()
@@ -118,6 +110,20 @@ def test_tile_list_depth_sort_modes(gpu, orc, depth_sort, big):
     else:
         s = scenes.tiny_random(24, n=300, width=70, height=45)
         p = s.params
+    return s, p
+
+
+@pytest.mark.parametrize("depth_sort", [1, 2])
+@pytest.mark.parametrize("big", ["none", "all", "mixed"])
+def test_tile_list_depth_sort_modes(gpu, orc, depth_sort, big):
+    """Both depth orders (per tile after binning; once over all splats before
+    binning) against the oracle's list, bit-exact. all: 5000 Gaussians large
+    enough to cover every tile of a 40x24 view, so every list is longer than
+    the 1536 entries a tile sorts in LDS; ten of them share one depth, so the
+    index breaks their tie. mixed: on a 96x32 view 2000 Gaussians crowd the
+    four left tiles (over 2000 entries each) while 2000 small ones spread over
+    the rest (under 700), so both paths meet in one launch."""
+    s, p = depth_case(big)
     R = make(gpu, depth_sort=depth_sort)
     outs = R.render(to_dev(p), s.sh_degree, s.cameras)
     torch.cuda.synchronize()
@@ -157,6 +163,43 @@ def test_tile_list_bit_exact_large_sorts(gpu, orc, depth_sort):
     assert s.num > 2**19 and len(t_ref) > 2**19
     assert len(t_gpu) == len(t_ref)
     assert np.array_equal(t_gpu, t_ref) and np.array_equal(g_gpu, g_ref)
+
+
+@pytest.mark.parametrize("case", ["none", "all", "mixed", "multiview", "tile8x8"])
+def test_tile_list_counting_binning(gpu, orc, case):
+    """The binning by counting (option binning = 1: per-workgroup tile counts,
+    one scan, a scatter in LDS-atomic order, equal depths put in index order
+    by the per-tile sort): lists bit-exact against the oracle, including ten
+    Gaussians of one depth ("all") and lists past the per-tile sort's LDS
+    capacity; images bit-identical to the radix binning's."""
+    tw = th = 16
+    if case == "multiview":
+        s = scenes.tiny_random(4, n=80, width=45, height=37)
+        cams = [s.cameras[0], identity_camera(29, 21, 25.0),
+                scenes.look_at_camera([0.3, 0.1, -0.5], [0, 0, 2], 64, 33, 40.0)]
+        p = s.params
+    elif case == "tile8x8":
+        s, p = depth_case("none")
+        cams = s.cameras
+        tw = th = 8
+    else:
+        s, p = depth_case(case)
+        cams = s.cameras
+    say("counting binning", case)
+    R = make(gpu, binning=1, depth_sort=1, tile_w=tw, tile_h=th)
+    outs = R.render(to_dev(p), s.sh_degree, cams)
+    torch.cuda.synchronize()
+    t_gpu, g_gpu = R.instances()
+    t_ref, g_ref = orc.tile_list(p, s.sh_degree, cams, tw, th)
+    assert len(t_gpu) == len(t_ref)
+    assert np.array_equal(t_gpu, t_ref) and np.array_equal(g_gpu, g_ref)
+    assert R.status()["visible"] == int(sum(orc.project(p, s.sh_degree, c)["vis"].sum() for c in cams))
+    O = make(gpu, depth_sort=1, tile_w=tw, tile_h=th)
+    other = O.render(to_dev(p), s.sh_degree, cams)
+    torch.cuda.synchronize()
+    for v in range(len(cams)):
+        for a, b in zip(outs[v], other[v]):
+            assert torch.equal(a, b)
 
 
 def test_tile_list_multiview_bit_exact(gpu, orc):
