@@ -62,9 +62,10 @@ PLAIN_OPS_PER_PAIR_FUSED = PLAIN_OPS_PER_PAIR_FWD + PLAIN_OPS_PER_PAIR_BWD
 # WRITE_SIZE (profiles/mapping_iteration_<workload>.txt), each scaled by what
 # the counter reads for a 256 MiB device copy (FETCH x2.0, WRITE x1.0). An
 # entry is removed whenever its kernel changes.
-MiB = 1024 * 1024
 TRAFFIC = {
-    ("keyframe_640x480_200k", "blend"): (78.57 * MiB, 80.95 * MiB),   # read, write
+    ("keyframe_640x480_200k", "blend"): (82.400e6, 84.883e6),   # read, write
+    ("batch8_640x480_500k", "blend_bwd"): (613.594e6, 815.010e6),
+    ("mixed16_2M_sh3", "blend_bwd"): (775.333e6, 1089.567e6),
 }
 
 

@@ -257,3 +257,54 @@ def test_autotuner_picks_a_timed_candidate(gpu, tmp_path, monkeypatch):
     assert torch.equal(p, p0)
     again = autotune.tune(p, 0, s.cameras, targets, candidates=cands)
     assert again["cached"] and again["tile_w"] == res["tile_w"]
+
+
+@pytest.mark.parametrize("chunk_len", [0, -1])
+def test_queue_fused_launch_matches_eager(gpu, orc, chunk_len):
+    """The fused blend launch over a work queue: 8 views of 320x240 (2400
+    tiles, more than the workgroups the device holds at once), chunked and
+    whole lists. Images bit-exact and gradients to float order against the
+    eager entry points, over three replays; the first replay's images against
+    the FP32 oracle."""
+    s = scenes.tiny_random(31, n=4000, width=320, height=240, sh_degree=1)
+    rng = np.random.default_rng(scenes.SEED_BASE + 531)
+    cams = [s.cameras[0]]
+    for k in range(7):
+        eye = [0.3 * np.cos(k), 0.15 * np.sin(2 * k), -0.5 + 0.05 * k]
+        cams.append(scenes.look_at_camera(eye, [0.0, 0.0, 2.5], 320, 240, 260.0))
+    s.cameras = cams
+    s.target_params = scenes.perturb(rng, s.params, s.sh_degree)
+    deg = s.sh_degree
+    targets = targets_for(gpu, s)
+    R = gpu.Rasterizer(fuse_blend=1, chunk_len=chunk_len)
+    E = gpu.Rasterizer(chunk_len=chunk_len)
+    p = to_dev(s.params)
+    grad = torch.zeros_like(p)
+    loss = torch.zeros(1, device="cuda")
+    outs = R.alloc_images(cams)
+    tiles = sum(((c.width + 15) // 16) * ((c.height + 15) // 16) for c in cams)
+    say("queue fused launch: tiles", tiles, "chunk_len", chunk_len)
+    assert tiles == 2400
+    for k in range(3):
+        R.mapping_iteration(p, deg, cams, outs, targets, grad, 0.5, loss)
+        torch.cuda.synchronize()
+        eo, el, eg = eager_iteration(gpu, E, p, deg, cams, targets)
+        torch.cuda.synchronize()
+        for view in range(len(cams)):
+            for a, b in zip(outs[view], eo[view]):
+                assert torch.equal(a, b), (k, view)
+        # the loss is a float sum over 614k pixels in both launches, added
+        # up in different orders (workgroup atomics in different numbers)
+        assert abs(loss.item() - el.item()) <= 1e-5 * abs(el.item()) + 1e-9, (loss.item(), el.item())
+        check_grad_close(grad, eg, f"queue replay {k}")
+        if k == 0:
+            for view in (0, 5):
+                ref = orc.render(s.params, deg, cams[view], mode="f32")
+                mask = ref["margin"] >= AMBIGUOUS_MARGIN
+                rgb = eo[view][0].cpu().numpy()
+                for ch in range(3):
+                    nbad, worst = image_violations(rgb[ch], ref["rgb"][ch], mask)
+                    assert nbad == 0, (view, ch, worst)
+    st = R.mapping_status()
+    say(st)
+    assert st["iterations"] == 3 and st["skipped"] == 0
