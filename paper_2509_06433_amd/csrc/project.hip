@@ -25,6 +25,7 @@ namespace {
 constexpr float kDilation = 0.3f;
 constexpr float kClampFov = 1.3f;
 constexpr float kQMax = 11.2f;
+constexpr int kLdsViews = 64;           // view descriptors staged in LDS by the several-view projection
 
 __device__ __forceinline__ bool finitef(float x) { return __builtin_isfinite(x); }
 
@@ -462,6 +463,17 @@ __global__ void __launch_bounds__(256) project_kernel(const float* __restrict__ 
     if (zhist)
       for (int p = 0; p < zpasses; ++p) atomicAdd(&s_hist[p * zR + ((key >> (zrb * p)) & (zR - 1))], 1u);
   };
+  // several views: each lane walks its own views, so their descriptors are
+  // read per lane; from LDS rather than through the vector memory path
+  __shared__ ViewDesc s_views[MULTI ? kLdsViews : 1];
+  const bool lds_views = MULTI && num_views <= kLdsViews;
+  if (lds_views) {
+    const int words = (int)(sizeof(ViewDesc) / 4) * num_views;
+    for (int e = threadIdx.x; e < words; e += blockDim.x)
+      reinterpret_cast<uint32_t*>(s_views)[e] = reinterpret_cast<const uint32_t*>(views)[e];
+    __syncthreads();
+  }
+  const ViewDesc* vsrc = lds_views ? s_views : views;
   const int64_t stride_t = (int64_t)gridDim.x * blockDim.x;
   // the loop runs the same number of times on every lane, so the wave-wide
   // votes below see all lanes
@@ -495,7 +507,7 @@ __global__ void __launch_bounds__(256) project_kernel(const float* __restrict__ 
     // no exponential: 122 rather than 169 VGPRs, four waves per SIMD)
     int view = mine ? 0 : num_views;
     auto skip_culled = [&]() {
-      while (view < num_views && surely_culled(P, stride, i, views[view], znear)) {
+      while (view < num_views && surely_culled(P, stride, i, vsrc[view], znear)) {
         const int64_t s = (int64_t)view * n + i;
         rect[s] = make_int4(0, 0, -1, -1);
         ntiles[s] = 0u;
@@ -515,7 +527,7 @@ __global__ void __launch_bounds__(256) project_kernel(const float* __restrict__ 
       if (view < num_views) {
         const int cur = view++;
         uint32_t key;
-        if (project_splat(P, stride, deg, i, (int64_t)cur * n + i, views[cur], tile_w, tile_h, znear, false, L, good,
+        if (project_splat(P, stride, deg, i, (int64_t)cur * n + i, vsrc[cur], tile_w, tile_h, znear, false, L, good,
                           o, splats, rect, ntiles, zkey, &key))
           count_key(key);
         skip_culled();

@@ -69,16 +69,18 @@ def check_grad_close(g, ref, label):
         assert nbad == 0, (label, grp, worst)
 
 
-# (chunk_len, max_chunks, fuse_blend): automatic (chunked and fused at this
-# size), explicit chunks fused, whole lists fused, and two launches
-@pytest.mark.parametrize("chunk", [(0, 0, 0), (16, 5, 0), (-1, 0, 1), (0, 0, -1)])
+# (chunk_len, max_chunks, fuse_blend[, tile_order]): automatic (chunked and
+# fused at this size), explicit chunks fused, whole lists fused, two
+# launches, and the balanced tile order (weights from the previous replay)
+@pytest.mark.parametrize("chunk", [(0, 0, 0), (16, 5, 0), (-1, 0, 1), (0, 0, -1), (0, 0, 0, 3)])
 def test_replays_match_eager(gpu, orc, chunk):
     s = two_view_scene()
     deg, cams = s.sh_degree, s.cameras
     targets = targets_for(gpu, s)
-    say("backward chunks, fused", chunk)
+    say("backward chunks, fused, tile order", chunk)
     opts = dict(chunk_len=chunk[0], max_chunks=chunk[1])
-    R, E = gpu.Rasterizer(fuse_blend=chunk[2], **opts), gpu.Rasterizer(**opts)
+    order = chunk[3] if len(chunk) > 3 else 0
+    R, E = gpu.Rasterizer(fuse_blend=chunk[2], tile_order=order, **opts), gpu.Rasterizer(**opts)
     p = to_dev(s.params)
     m, v = torch.zeros_like(p), torch.zeros_like(p)
     grad = torch.full_like(p, 7.0)

@@ -483,8 +483,9 @@ def test_tile_size_invariance(gpu):
     s = CASES["small"]
     p = to_dev(s.params)
     ref = None
+    # (tile_w, tile_h, pixels per thread, tile order; 3 = balanced over the CUs)
     for tile in [(16, 16, 1, 0), (16, 16, 2, 1), (16, 8, 1, 2), (16, 8, 2, 1), (8, 8, 1, 1), (32, 8, 1, 2),
-                 (32, 8, 2, 1)]:
+                 (32, 8, 2, 1), (16, 16, 1, 3), (8, 8, 1, 3)]:
         outs = make(gpu, tile_w=tile[0], tile_h=tile[1], pixels_per_thread=tile[2],
                     tile_order=tile[3]).render(p, 0, s.cameras)
         cur = [o.cpu().numpy() for o in outs[0]]
