@@ -25,7 +25,9 @@ namespace {
 constexpr float kDilation = 0.3f;
 constexpr float kClampFov = 1.3f;
 constexpr float kQMax = 11.2f;
-constexpr int kLdsViews = 64;           // view descriptors staged in LDS by the several-view projection
+constexpr int kLdsViews = 64;           // views per chunk of the several-view projection (descriptors in LDS)
+constexpr int kProjHist = 4 * 256;      // depth-key digit counters of the projection (four 8-bit digits)
+constexpr bool kStageCoef = true;       // several views: colour coefficients staged in LDS once per Gaussian
 
 __device__ __forceinline__ bool finitef(float x) { return __builtin_isfinite(x); }
 
@@ -345,9 +347,9 @@ __device__ __forceinline__ bool project_geometry(const float* __restrict__ P, in
 // the same decision; the lateral test bounds the extent from above
 //   a <= |row 0 of J|^2 s_max^2 + 0.3 <= (fx / z)^2 (1 + lim_x^2) s_max^2 + 0.3
 // (W is a rotation) and keeps a margin of 1% and a pixel for rounding.
-__device__ __forceinline__ bool surely_culled(const float* __restrict__ P, int64_t stride, int64_t i,
-                                              const ViewDesc& V, float znear) {
-  const float mx = P[0 * stride + i], my = P[1 * stride + i], mz = P[2 * stride + i];
+// mx, my, mz: the mean; lmax: the largest log-scale.
+__device__ __forceinline__ bool surely_culled_at(float mx, float my, float mz, float lmax, const ViewDesc& V,
+                                                 float znear) {
   const float* W = V.R;
   float tc[3];
 #pragma unroll
@@ -357,7 +359,6 @@ __device__ __forceinline__ bool surely_culled(const float* __restrict__ P, int64
     tc[r] = acc + V.t[r];
   }
   if (!(tc[2] >= znear)) return finitef(tc[2]);         // exactly the projection's near-plane cull
-  const float lmax = fmaxf(fmaxf(P[3 * stride + i], P[4 * stride + i]), P[5 * stride + i]);
   if (!finitef(lmax) || lmax > 20.0f) return false;
   const float smax = __expf(lmax) * 1.01f;    // a bound: 1 % covers the fast exp's error
   const float iz = 1.0f / tc[2];
@@ -371,28 +372,48 @@ __device__ __forceinline__ bool surely_culled(const float* __restrict__ P, int64
   return (u + exb < 0.0f) || (u - exb > (float)V.width) || (v + eyb < 0.0f) || (v - eyb > (float)V.height);
 }
 
-// Colour of one Gaussian seen from the view (before and after max(0, .)).
-__device__ __forceinline__ void project_colour(const float* __restrict__ P, int64_t stride, int64_t i, int deg,
-                                               const ViewDesc& V, float* raw, float* col, float* dir,
-                                               float* dnorm) {
+__device__ __forceinline__ float largest_log_scale(const float* __restrict__ P, int64_t stride, int64_t i) {
+  return fmaxf(fmaxf(P[3 * stride + i], P[4 * stride + i]), P[5 * stride + i]);
+}
+
+// The colour coefficients of one Gaussian, plane j = 3 k + channel of the
+// parameter rows 11.. : read from the parameter array ...
+struct GlobalCoef {
+  const float* __restrict__ P;
+  int64_t stride, i;
+  __device__ __forceinline__ float operator()(int j) const { return P[(11 + j) * stride + i]; }
+};
+// ... or, where one thread projects a Gaussian into several views, the
+// constant terms from registers and the rest from the thread's own column of
+// an LDS array that it filled once (3 (K - 1) rows of `pitch` words).
+struct StagedCoef {
+  float dc[3];
+  const float* col;
+  int pitch;
+  __device__ __forceinline__ float operator()(int j) const { return j < 3 ? dc[j] : col[(j - 3) * pitch]; }
+};
+
+// Colour of one Gaussian of mean (mx, my, mz) seen from the view (before and
+// after max(0, .)).
+template <class Coef>
+__device__ __forceinline__ void project_colour(float mx, float my, float mz, const Coef& coef, int deg,
+                                               const ViewDesc& V, float* raw, float* col) {
   float Y[16];
-  float dx = 0.0f, dy = 0.0f, dz = 0.0f, nrm = 1.0f;
+  float dx = 0.0f, dy = 0.0f, dz = 0.0f;
   if (deg > 0) {
-    dx = P[0 * stride + i] - V.campos[0];
-    dy = P[1 * stride + i] - V.campos[1];
-    dz = P[2 * stride + i] - V.campos[2];
-    nrm = sqrtf(dx * dx + dy * dy + dz * dz);
+    dx = mx - V.campos[0];
+    dy = my - V.campos[1];
+    dz = mz - V.campos[2];
+    const float nrm = sqrtf(dx * dx + dy * dy + dz * dz);
     const float inv = 1.0f / nrm;
     dx *= inv; dy *= inv; dz *= inv;
   }
-  dir[0] = dx; dir[1] = dy; dir[2] = dz;
-  *dnorm = nrm;
   sh_basis(deg, dx, dy, dz, Y);
   const int K = (deg + 1) * (deg + 1);
 #pragma unroll
   for (int ch = 0; ch < 3; ++ch) {
-    float acc = SH_C0 * P[(11 + ch) * stride + i];
-    for (int k = 1; k < K; ++k) acc = acc + Y[k] * P[(11 + 3 * k + ch) * stride + i];
+    float acc = SH_C0 * coef(ch);
+    for (int k = 1; k < K; ++k) acc = acc + Y[k] * coef(3 * k + ch);
     raw[ch] = acc + 0.5f;
     col[ch] = fmaxf(raw[ch], 0.0f);
   }
@@ -402,17 +423,18 @@ __device__ __forceinline__ void project_colour(const float* __restrict__ P, int6
 // whether it is visible (and then its depth key).
 // L, good, o: the Gaussian's view-independent part, whether it can be drawn
 // at all, and its opacity.
-__device__ __forceinline__ bool project_splat(const float* __restrict__ P, int64_t stride, int deg, int64_t i,
-                                              int64_t s, const ViewDesc& V, int tile_w, int tile_h, float znear,
-                                              bool skip_geometry, const GaussLocal& L, bool good, float o,
-                                              Splat* __restrict__ splats, int4* __restrict__ rect,
-                                              uint32_t* __restrict__ ntiles, uint32_t* __restrict__ zkey,
-                                              uint32_t* key_out) {
+// coef: its colour coefficients.
+template <class Coef>
+__device__ __forceinline__ bool project_splat(const Coef& coef, int deg, int64_t s, const ViewDesc& V, int tile_w,
+                                              int tile_h, float znear, bool skip_geometry, const GaussLocal& L,
+                                              bool good, float o, Splat* __restrict__ splats,
+                                              int4* __restrict__ rect, uint32_t* __restrict__ ntiles,
+                                              uint32_t* __restrict__ zkey, uint32_t* key_out) {
   ProjState g;
   bool vis = !skip_geometry && good && project_view(L, V, znear, g);
-  float raw[3], col[3], dir[3], dnorm;
+  float raw[3], col[3];
   if (vis) {
-    project_colour(P, stride, i, deg, V, raw, col, dir, &dnorm);
+    project_colour(L.mx, L.my, L.mz, coef, deg, V, raw, col);
     vis = finitef(col[0]) && finitef(col[1]) && finitef(col[2]);
   }
   if (!vis) {
@@ -438,45 +460,53 @@ __device__ __forceinline__ bool project_splat(const float* __restrict__ P, int64
   return true;
 }
 
-// One view: one thread per Gaussian. Several views: one thread per Gaussian
-// walks its own list of views that may see it (the conservative early cull
-// marks the others), so the full projection runs with the wavefront's lanes
-// busy even where most splats are culled, and the parameter reads stay
-// coalesced.
+// One view: one thread per Gaussian. Several views: one thread per Gaussian,
+// in two phases per chunk of up to kLdsViews views. First the conservative
+// cull of every view of the chunk with all lanes on the same view, so that
+// the empty records of the culled views are written coalesced; it leaves each
+// lane a mask of the views it must project. Then each lane walks its own
+// mask, so that the full projection runs with the wavefront's lanes busy even
+// where most of the views are culled.
 // MULTI: the several-view form (a separate instantiation, so that each form
-// gets the registers of its own body).
+// gets the registers of its own body). Its dynamic LDS holds the chunk's view
+// descriptors (read per lane in the second phase) and, when `stage` is set,
+// each thread's colour coefficients past the constant terms, loaded once per
+// Gaussian rather than once per view it is projected into.
 template <bool MULTI>
 __global__ void __launch_bounds__(256) project_kernel(const float* __restrict__ P, int64_t n, int64_t stride, int deg,
                                                       int num_views, const ViewDesc* __restrict__ views, int tile_w,
                                                       int tile_h, float znear, Splat* __restrict__ splats,
                                                       int4* __restrict__ rect, uint32_t* __restrict__ ntiles,
                                                       uint32_t* __restrict__ zkey, uint32_t* __restrict__ zhist,
-                                                      int zrb, int zpasses, uint32_t* __restrict__ nonfinite) {
+                                                      int zrb, int zpasses, uint32_t* __restrict__ nonfinite,
+                                                      bool stage) {
   // digit histograms of the visible splats' depth keys for the radix sort
-  // that follows (zpasses digits of zrb bits; zpasses * 2^zrb <= 3 * 2048)
-  __shared__ uint32_t s_hist[3 * 2048];
+  // that follows (zpasses digits of zrb bits; zpasses * 2^zrb <= kProjHist)
+  __shared__ uint32_t s_hist[kProjHist];
   const int zR = 1 << zrb;
   if (zhist)
     for (int e = threadIdx.x; e < zpasses * zR; e += blockDim.x) s_hist[e] = 0u;
-  __syncthreads();
   auto count_key = [&](uint32_t key) {
     if (zhist)
       for (int p = 0; p < zpasses; ++p) atomicAdd(&s_hist[p * zR + ((key >> (zrb * p)) & (zR - 1))], 1u);
   };
-  // several views: each lane walks its own views, so their descriptors are
-  // read per lane; from LDS rather than through the vector memory path
-  __shared__ ViewDesc s_views[MULTI ? kLdsViews : 1];
-  const bool lds_views = MULTI && num_views <= kLdsViews;
-  if (lds_views) {
-    const int words = (int)(sizeof(ViewDesc) / 4) * num_views;
-    for (int e = threadIdx.x; e < words; e += blockDim.x)
-      reinterpret_cast<uint32_t*>(s_views)[e] = reinterpret_cast<const uint32_t*>(views)[e];
-    __syncthreads();
-  }
-  const ViewDesc* vsrc = lds_views ? s_views : views;
+  extern __shared__ float s_dyn[];
+  ViewDesc* s_views = reinterpret_cast<ViewDesc*>(s_dyn);
+  const int chunk_views = min(num_views, kLdsViews);
+  float* s_sh = s_dyn + chunk_views * (int)(sizeof(ViewDesc) / 4) + threadIdx.x;
+  const int nsh = stage ? 3 * ((deg + 1) * (deg + 1) - 1) : 0;
+  auto load_views = [&](int first, int count) {
+    const int words = (int)(sizeof(ViewDesc) / 4) * count;
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(views + first);
+    for (int e = threadIdx.x; e < words; e += blockDim.x) reinterpret_cast<uint32_t*>(s_dyn)[e] = src[e];
+  };
+  const bool views_resident = num_views <= kLdsViews;
+  if (MULTI && views_resident) load_views(0, num_views);   // else per chunk, in the loop
+  __syncthreads();
   const int64_t stride_t = (int64_t)gridDim.x * blockDim.x;
-  // the loop runs the same number of times on every lane, so the wave-wide
-  // votes below see all lanes
+  // the loop runs the same number of times on every lane (and every wave of
+  // the block), so the wave-wide votes and the block barriers below see all
+  // lanes
   for (int64_t i0 = blockIdx.x * (int64_t)blockDim.x; i0 < n; i0 += stride_t) {
     const int64_t i = i0 + threadIdx.x;
     const bool mine = i < n;
@@ -487,7 +517,8 @@ __global__ void __launch_bounds__(256) project_kernel(const float* __restrict__ 
     if (!MULTI) {
       uint32_t key;
       if (mine) {
-        const bool skip = surely_culled(P, stride, i, views[0], znear);
+        const bool skip = surely_culled_at(P[0 * stride + i], P[1 * stride + i], P[2 * stride + i],
+                                           largest_log_scale(P, stride, i), views[0], znear);
         GaussLocal L;
         bool good = false;
         float o = 0.0f;
@@ -495,43 +526,79 @@ __global__ void __launch_bounds__(256) project_kernel(const float* __restrict__ 
           good = gaussian_local(P, stride, i, L);
           o = opacity_of(P[10 * stride + i]);
         }
-        if (project_splat(P, stride, deg, i, i, views[0], tile_w, tile_h, znear, skip, L, good, o, splats, rect,
-                          ntiles, zkey, &key))
+        if (project_splat(GlobalCoef{P, stride, i}, deg, i, views[0], tile_w, tile_h, znear, skip, L, good, o,
+                          splats, rect, ntiles, zkey, &key))
           count_key(key);
       }
       continue;
     }
-    // views the early cull rules out get their empty records; the
-    // Gaussian's view-independent part is formed once, before its first view
-    // that the cull keeps (out of the view loop, so that the loop body holds
-    // no exponential: 122 rather than 169 VGPRs, four waves per SIMD)
-    int view = mine ? 0 : num_views;
-    auto skip_culled = [&]() {
-      while (view < num_views && surely_culled(P, stride, i, vsrc[view], znear)) {
-        const int64_t s = (int64_t)view * n + i;
-        rect[s] = make_int4(0, 0, -1, -1);
-        ntiles[s] = 0u;
-        zkey[s] = 0xFFFFFFFFu;
-        ++view;
+    float mx = 0.0f, my = 0.0f, mz = 0.0f, lmax = 0.0f;
+    if (mine) {
+      mx = P[0 * stride + i];
+      my = P[1 * stride + i];
+      mz = P[2 * stride + i];
+      lmax = largest_log_scale(P, stride, i);
+    }
+    // phase one over views [vb, vb + nv), whose descriptors are in LDS
+    auto cull_chunk = [&](int vb, int nv) {
+      uint64_t keep = 0;
+      for (int v = 0; v < nv; ++v) {
+        if (!mine) continue;
+        if (surely_culled_at(mx, my, mz, lmax, s_views[v], znear)) {
+          const int64_t s = (int64_t)(vb + v) * n + i;
+          rect[s] = make_int4(0, 0, -1, -1);
+          ntiles[s] = 0u;
+          zkey[s] = 0xFFFFFFFFu;
+        } else {
+          keep |= 1ull << v;
+        }
       }
+      return keep;
     };
-    skip_culled();
-    GaussLocal L;
+    if (!views_resident) {
+      __syncthreads();                       // every lane is done with the previous Gaussian's last chunk
+      load_views(0, chunk_views);
+      __syncthreads();
+    }
+    uint64_t keep = cull_chunk(0, chunk_views);
+    // the Gaussian's view-independent part (and its staged coefficients),
+    // formed once, out of the view walk, so that the walk's body holds no
+    // exponential; skipped where the first chunk culls every view
     bool good = false;
+    GaussLocal L;
     float o = 0.0f;
-    if (view < num_views) {
+    StagedCoef sc;
+    sc.col = s_sh;
+    sc.pitch = blockDim.x;
+    if (mine && (keep || !views_resident)) {
       good = gaussian_local(P, stride, i, L);
       o = opacity_of(P[10 * stride + i]);
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) sc.dc[ch] = P[(11 + ch) * stride + i];
+      for (int j = 0; j < nsh; ++j) s_sh[j * (int)blockDim.x] = P[(14 + j) * stride + i];
     }
-    while (__any(view < num_views)) {
-      if (view < num_views) {
-        const int cur = view++;
-        uint32_t key;
-        if (project_splat(P, stride, deg, i, (int64_t)cur * n + i, vsrc[cur], tile_w, tile_h, znear, false, L, good,
-                          o, splats, rect, ntiles, zkey, &key))
-          count_key(key);
-        skip_culled();
+    for (int vb = 0;;) {
+      // phase two: each lane walks its own kept views
+      while (__any(keep != 0)) {
+        if (keep) {
+          const int v = __builtin_ctzll(keep);
+          keep &= keep - 1;
+          const int64_t s = (int64_t)(vb + v) * n + i;
+          uint32_t key;
+          const bool vis = stage ? project_splat(sc, deg, s, s_views[v], tile_w, tile_h, znear, false, L, good, o,
+                                                 splats, rect, ntiles, zkey, &key)
+                                 : project_splat(GlobalCoef{P, stride, i}, deg, s, s_views[v], tile_w, tile_h,
+                                                 znear, false, L, good, o, splats, rect, ntiles, zkey, &key);
+          if (vis) count_key(key);
+        }
       }
+      vb += kLdsViews;
+      if (vb >= num_views) break;
+      const int nv = min(kLdsViews, num_views - vb);
+      __syncthreads();                       // every lane is done with the previous chunk
+      load_views(vb, nv);
+      __syncthreads();
+      keep = cull_chunk(vb, nv);
     }
   }
   if (zhist) {
@@ -1211,15 +1278,21 @@ void launch_project(const float* params, int64_t n, int64_t stride, int deg, int
                     int tile_w, int tile_h, float znear, Splat* splats, int4* rect, uint32_t* ntiles,
                     uint32_t* zkey, uint32_t* zhist, int zrb, int zpasses, uint32_t* nonfinite, hipStream_t st) {
   if (n == 0 || num_views == 0) return;
-  if (zpasses * (1 << zrb) > 3 * 2048) zhist = nullptr;
-  if (num_views == 1)
+  if (zpasses * (1 << zrb) > kProjHist) zhist = nullptr;
+  if (num_views == 1) {
     project_kernel<false><<<grid_for(n, 256), 256, 0, st>>>(params, n, stride, deg, num_views, views, tile_w, tile_h,
                                                             znear, splats, rect, ntiles, zkey, zhist, zrb, zpasses,
-                                                            nonfinite);
-  else
-    project_kernel<true><<<grid_for(n, 256), 256, 0, st>>>(params, n, stride, deg, num_views, views, tile_w, tile_h,
+                                                            nonfinite, false);
+    return;
+  }
+  // the chunk's view descriptors and (staged) 3 (K - 1) coefficient rows per
+  // thread: at most 64 * 108 B + 45 * 256 * 4 B = 52 KB of dynamic LDS
+  const bool stage = kStageCoef && deg > 0;
+  const size_t lds = (size_t)std::min(num_views, kLdsViews) * sizeof(ViewDesc) +
+                     (stage ? (size_t)3 * ((deg + 1) * (deg + 1) - 1) * 256 * sizeof(float) : 0);
+  project_kernel<true><<<grid_for(n, 256), 256, lds, st>>>(params, n, stride, deg, num_views, views, tile_w, tile_h,
                                                            znear, splats, rect, ntiles, zkey, zhist, zrb, zpasses,
-                                                           nonfinite);
+                                                           nonfinite, stage);
 }
 
 void launch_activations(const float* params, int64_t n, int64_t stride, float* scale, float* opacity,

@@ -202,6 +202,47 @@ def test_tile_list_counting_binning(gpu, orc, case):
             assert torch.equal(a, b)
 
 
+def ring_cameras(count, seed):
+    """`count` small cameras on a ring around the tiny scenes' volume (z in
+    [1, 3]); every seventh looks away from it, so that it culls everything."""
+    rng = np.random.default_rng(seed)
+    cams = []
+    for k in range(count):
+        t = 2.0 * np.pi * k / count
+        eye = [0.5 * np.cos(t), 0.4 * np.sin(t), -0.4 + 0.3 * np.sin(3.0 * t)]
+        target = [0.0, 0.0, -6.0] if k % 7 == 6 else [0.5 * rng.normal(), 0.5 * rng.normal(), 2.0]
+        w, h = [(40, 30), (33, 27), (48, 20)][k % 3]
+        cams.append(scenes.look_at_camera(eye, target, w, h, 1.6 * w))
+    return cams
+
+
+# several views: the lock-step cull, the colour coefficients staged once per
+# Gaussian (degree > 0) and the views taken in chunks of 64 (70 views)
+@pytest.mark.parametrize("deg,count", [(3, 5), (1, 70), (2, 17)])
+def test_projection_multiview_bit_exact(gpu, orc, deg, count):
+    s = scenes.tiny_random(7, n=90, width=40, height=30, sh_degree=deg)
+    cams = ring_cameras(count, deg)
+    say("degree", deg, "views", count)
+    R = make(gpu)
+    R.render(to_dev(s.params), deg, cams)
+    f32 = lambda x: np.asarray(x, np.float32)
+    seen = 0
+    for v, cam in enumerate(cams):
+        sp = R.splats(v, s.num)
+        ref = orc.project(s.params, deg, cam, prec=32)
+        vis = ref["vis"]
+        seen += int(vis.sum())
+        assert np.array_equal(sp[:, 15] >= 0, vis), v
+        for col, key in [(0, "u"), (1, "v"), (2, "z"), (6, "A"), (7, "B"), (8, "C"), (9, "o")]:
+            assert np.array_equal(sp[vis, col], f32(ref[key][vis])), (v, key)
+        for col, key in [(10, "r"), (11, "g"), (12, "b_")]:
+            assert np.allclose(sp[vis, col], ref[key][vis], rtol=2e-6, atol=1e-7), (v, key)
+    assert seen > 2 * count
+    t_gpu, g_gpu = R.instances()
+    t_ref, g_ref = orc.tile_list(s.params, deg, cams, 16, 16)
+    assert np.array_equal(t_gpu, t_ref) and np.array_equal(g_gpu, g_ref)
+
+
 def test_tile_list_multiview_bit_exact(gpu, orc):
     s = scenes.tiny_random(4, n=80, width=45, height=37)
     cams = [s.cameras[0], identity_camera(29, 21, 25.0), scenes.look_at_camera([0.3, 0.1, -0.5], [0, 0, 2], 64, 33, 40.0)]
