@@ -777,7 +777,8 @@ int gsr_copy_splats(gsr_ctx* ctx, int32_t view, float* out, int64_t num) {
   RET_IF(ensure(ctx, ctx->splat_out, sizeof(float) * 16 * (size_t)num));
   const int64_t off = (int64_t)view * num;
   launch_export_splats(ctx->q_params, num, P.stride, as<ViewDesc>(B.views) + view, ctx->znear,
-                       as<Splat>(B.splats) + off, as<int4>(B.rect) + off, as<float>(ctx->splat_out), st);
+                       as<Splat>(B.splats) + off, as<int4>(B.rect) + off, as<uint32_t>(B.ntiles) + off,
+                       as<float>(ctx->splat_out), st);
   CHECK_LAUNCH(ctx);
   HIP_TRY(ctx, hipStreamSynchronize(st));
   HIP_TRY(ctx, hipMemcpy(out, ctx->splat_out.p, sizeof(float) * 16 * (size_t)num, hipMemcpyDeviceToHost));

@@ -41,9 +41,10 @@ constexpr float kAlphaMin = 1.0f / 255.0f;
 constexpr float kTransMin = 1e-4f;
 
 // ---- project.hip ---------------------------------------------------------
-// One thread per (view, Gaussian). Writes splats[s], rect[s] (pixel rectangle,
-// inclusive; x1 < x0 when culled), ntiles[s] and depth key zkey[s] (raw float
-// bits of z, 0xFFFFFFFF when culled); s = view * N + i.
+// One thread per (view, Gaussian). Writes ntiles[s] (0 when culled) and, for
+// the splats it lists (ntiles[s] > 0) only, splats[s], rect[s] (pixel
+// rectangle, inclusive) and the depth key zkey[s] (raw float bits of z);
+// s = view * N + i.
 // Projection of every (view, Gaussian) splat into splats, rect, ntiles and
 // zkey (indexed view * n + Gaussian); with zhist the digit histograms of the
 // visible splats' depth keys are accumulated there; with nonfinite, the number
@@ -120,7 +121,8 @@ void launch_pose_backward(const float* params, int64_t n, int64_t stride, int de
                           hipStream_t st);
 // Inspection copy of the splats of one view: out[n][16] (see gsr_copy_splats).
 void launch_export_splats(const float* params, int64_t n, int64_t stride, const ViewDesc* view, float znear,
-                          const Splat* splats, const int4* rect, float* out, hipStream_t st);
+                          const Splat* splats, const int4* rect, const uint32_t* ntiles, float* out,
+                          hipStream_t st);
 
 // ---- sort.hip --------------------------------------------------------------
 // The digit histograms of a sort are accumulated in kHistCopies copies

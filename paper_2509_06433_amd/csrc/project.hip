@@ -383,6 +383,18 @@ struct GlobalCoef {
   int64_t stride, i;
   __device__ __forceinline__ float operator()(int j) const { return P[(11 + j) * stride + i]; }
 };
+// ... or from registers (an array of them) ...
+struct ArrayCoef {
+  const float* c;
+  __device__ __forceinline__ float operator()(int j) const { return c[j]; }
+};
+// Sums of the SH coefficients' gradient terms over views, in registers.
+struct ArraySink {
+  float* g;
+  __device__ __forceinline__ void operator()(int j, bool passed, float t) const {
+    if (passed) g[j] += t;
+  }
+};
 // ... or, where one thread projects a Gaussian into several views, the
 // constant terms from registers and the rest from the thread's own column of
 // an LDS array that it filled once (3 (K - 1) rows of `pitch` words).
@@ -438,10 +450,9 @@ __device__ __forceinline__ bool project_splat(const Coef& coef, int deg, int64_t
     vis = finitef(col[0]) && finitef(col[1]) && finitef(col[2]);
   }
   if (!vis) {
-    // no splat record: only listed splats are ever read
-    rect[s] = make_int4(0, 0, -1, -1);
+    // a tile count of zero marks the splat as not listed; its other records
+    // are never read
     ntiles[s] = 0u;
-    zkey[s] = 0xFFFFFFFFu;
     return false;
   }
   const int tx0 = g.x0 / tile_w, tx1 = g.x1 / tile_w, ty0 = g.y0 / tile_h, ty1 = g.y1 / tile_h;
@@ -544,14 +555,10 @@ __global__ void __launch_bounds__(256) project_kernel(const float* __restrict__ 
       uint64_t keep = 0;
       for (int v = 0; v < nv; ++v) {
         if (!mine) continue;
-        if (surely_culled_at(mx, my, mz, lmax, s_views[v], znear)) {
-          const int64_t s = (int64_t)(vb + v) * n + i;
-          rect[s] = make_int4(0, 0, -1, -1);
-          ntiles[s] = 0u;
-          zkey[s] = 0xFFFFFFFFu;
-        } else {
+        if (surely_culled_at(mx, my, mz, lmax, s_views[v], znear))
+          ntiles[(int64_t)(vb + v) * n + i] = 0u;
+        else
           keep |= 1ull << v;
-        }
       }
       return keep;
     };
@@ -767,7 +774,8 @@ __device__ __forceinline__ void sh_dir_grad_d(int deg, double x, double y, doubl
 // the camera-space mean, through T = J R and, for view-dependent colour,
 // through the camera centre -R^T t.
 // The colour part of one (view, Gaussian) pair's chain rule: from the colour
-// gradients gcol[3] to the SH coefficients (gsh += ...) and, for DEG > 0, to
+// gradients gcol[3] to the SH coefficients (gsh(j, passed, term): the term of
+// plane j, passed false where the clamp stops it) and, for DEG > 0, to
 // dL/d(mean - camera centre) through the viewing direction (gview, =).
 // Real SH basis function k at the unit direction (x, y, z) and its gradient
 // with respect to (x, y, z) as a polynomial (the same functions as sh_basis_d
@@ -804,13 +812,14 @@ __device__ __forceinline__ double sh_term_d(int k, double x, double y, double z,
 }
 
 // The colour part of one (view, Gaussian) pair's chain rule: from the colour
-// gradients gcol[3] to the SH coefficients (gsh += ...) and, for DEG > 0, to
+// gradients gcol[3] to the SH coefficients (gsh(j, passed, term): the term of
+// plane j, passed false where the clamp stops it) and, for DEG > 0, to
 // dL/d(mean - camera centre) through the viewing direction (gview, =). Two
 // walks over the basis: the raw colours (for the clamp), then the gradients,
 // each basis function formed where it is used (few registers at degree 3).
-template <int DEG>
+template <int DEG, class Coef, class Sink>
 __device__ __forceinline__ void colour_chain(const float* __restrict__ P, int64_t stride, int64_t i,
-                                             const ViewDesc& V, const float* gcol, const float* coef, float* gsh,
+                                             const ViewDesc& V, const float* gcol, const Coef& coef, const Sink& gsh,
                                              double* gview) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   double dir[3] = {0.0, 0.0, 0.0}, dnorm = 1.0;
@@ -822,13 +831,14 @@ __device__ __forceinline__ void colour_chain(const float* __restrict__ P, int64_
     dir[0] /= dnorm; dir[1] /= dnorm; dir[2] /= dnorm;
   }
   double raw[3] = {0.5, 0.5, 0.5};
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
+  auto first_walk = [&](int k) {
     double d[3];
     const double Yk = sh_term_d(k, dir[0], dir[1], dir[2], d);
 #pragma unroll
-    for (int ch = 0; ch < 3; ++ch) raw[ch] += (double)coef[3 * k + ch] * Yk;
-  }
+    for (int ch = 0; ch < 3; ++ch) raw[ch] += (double)coef(3 * k + ch) * Yk;
+  };
+#pragma unroll
+  for (int k = 0; k < K; ++k) first_walk(k);
   // the clamp at zero passes no gradient
   double gc[3];
 #pragma unroll
@@ -838,22 +848,23 @@ __device__ __forceinline__ void colour_chain(const float* __restrict__ P, int64_
   // walk's values (an empty asm hides that the direction is the same)
   double ux = dir[0], uy = dir[1], uz = dir[2];
   asm volatile("" : "+v"(ux), "+v"(uy), "+v"(uz));
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
+  auto second_walk = [&](int k) {
     double d[3];
     const double Yk = sh_term_d(k, ux, uy, uz, d);
     double w = 0.0;
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
-      if (!(raw[ch] < 0.0)) gsh[3 * k + ch] += (float)(gc[ch] * Yk);
-      w += gc[ch] * (double)coef[3 * k + ch];
+      gsh(3 * k + ch, !(raw[ch] < 0.0), (float)(gc[ch] * Yk));
+      w += gc[ch] * (double)coef(3 * k + ch);
     }
     if (DEG > 0) {
       gdir[0] += w * d[0];
       gdir[1] += w * d[1];
       gdir[2] += w * d[2];
     }
-  }
+  };
+#pragma unroll
+  for (int k = 0; k < K; ++k) second_walk(k);
 #pragma unroll
   for (int j = 0; j < 3; ++j) gview[j] = 0.0;
   if (DEG > 0) {
@@ -873,7 +884,7 @@ __device__ __forceinline__ void chain_view(const float* __restrict__ P, int64_t 
   gO += (double)G[G2_O];
   double gview[3] = {0.0, 0.0, 0.0};   // dL/d(mean - camera centre) through the colour
   if (COLOUR) {
-    colour_chain<DEG>(P, stride, i, V, G + G2_R, coef, gsh, gview);
+    colour_chain<DEG>(P, stride, i, V, G + G2_R, ArrayCoef{coef}, ArraySink{gsh}, gview);
 #pragma unroll
     for (int j = 0; j < 3; ++j) gmean[j] += gview[j];
   }
@@ -994,6 +1005,29 @@ __device__ __forceinline__ void finish_local(const LocalD& L, const double* gSig
   gq[3] += (gz - z * dot) / L.qn;
 }
 
+// The backward's per-lane view walks read the view descriptors from LDS
+// (up to kLdsViews of them; else from global memory). Called by every thread
+// of the workgroup, before any early exit.
+__device__ __forceinline__ const ViewDesc* stage_views(const ViewDesc* __restrict__ views, int num_views,
+                                                       ViewDesc* s_views) {
+  if (num_views > kLdsViews) return views;
+  const int words = (int)(sizeof(ViewDesc) / 4) * num_views;
+  for (int e = threadIdx.x; e < words; e += blockDim.x)
+    reinterpret_cast<uint32_t*>(s_views)[e] = reinterpret_cast<const uint32_t*>(views)[e];
+  __syncthreads();
+  return s_views;
+}
+
+// Bit v set for each view vb + v (v < 64) that lists Gaussian i.
+__device__ __forceinline__ uint64_t listed_views(const uint32_t* __restrict__ ntiles, int64_t n, int64_t i, int vb,
+                                                 int num_views) {
+  uint64_t m = 0;
+  const int nv = min(64, num_views - vb);
+  for (int v = 0; v < nv; ++v)
+    if (ntiles[(int64_t)(vb + v) * n + i] != 0u) m |= 1ull << v;
+  return m;
+}
+
 // Chain rule from the screen-space gradients (u, v, conic, opacity, colour,
 // depth) of every view to the parameters, summed over views, in double.
 // One thread per Gaussian, so the parameter gradients need no atomics. For
@@ -1002,7 +1036,7 @@ __device__ __forceinline__ void finish_local(const LocalD& L, const double* gSig
 // one: the two halves each fit in fewer registers than the whole (for SH
 // degree 3, 256 VGPRs and one wave per SIMD together).
 template <int DEG>
-__global__ void __launch_bounds__(256) project_backward_kernel(const float* __restrict__ P, int64_t n, int64_t stride,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) project_backward_kernel(const float* __restrict__ P, int64_t n, int64_t stride,
                                                                int num_views, const ViewDesc* __restrict__ views,
                                                                float* __restrict__ g2,
                                                                const uint32_t* __restrict__ ntiles,
@@ -1011,6 +1045,8 @@ __global__ void __launch_bounds__(256) project_backward_kernel(const float* __re
   constexpr bool kColour = DEG == 0;
   constexpr int K = kColour ? 1 : 0;
   if (counters.stats && blockIdx.x == 0 && threadIdx.x == 0) count_iteration(counters);
+  __shared__ ViewDesc s_views[kLdsViews];
+  const ViewDesc* vsrc = stage_views(views, num_views, s_views);
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     double gmean[3] = {0, 0, 0}, gls[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, glogit = 0.0;
     float gsh[3 * K + 1];      // SH gradients (degree 0 only): one term per view, float is enough
@@ -1022,10 +1058,10 @@ __global__ void __launch_bounds__(256) project_backward_kernel(const float* __re
     bool touched = false;
     double Sig[9];             // formed at the first view that passes the Gaussian a gradient
     double gSig[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, gO = 0.0;
-    // views in lockstep (the view descriptor stays wave-uniform, in scalar
-    // registers); a lane skips the views that do not see its Gaussian
-    for (int cur = 0; cur < num_views; ++cur) {
-      if (ntiles[(int64_t)cur * n + i] == 0u) continue;
+    // each lane walks the views that list its Gaussian, in view order
+    for (int vb = 0; vb < num_views; vb += 64) {
+     for (uint64_t seen = listed_views(ntiles, n, i, vb, num_views); seen; seen &= seen - 1) {
+      const int cur = vb + __builtin_ctzll(seen);
       float* gv = g2 + ((int64_t)cur * n + i) * G2_N;
       float G[G2_N];
       bool any = false;
@@ -1044,8 +1080,8 @@ __global__ void __launch_bounds__(256) project_backward_kernel(const float* __re
       }
       if (!touched) sigma_f64(P, stride, i, Sig);
       touched = true;
-      const ViewDesc& V = views[cur];
-      chain_view<DEG, false, kColour>(P, stride, i, V, Sig, G, coef, gmean, gSig, gO, gsh);
+      chain_view<DEG, false, kColour>(P, stride, i, vsrc[cur], Sig, G, coef, gmean, gSig, gO, gsh);
+     }
     }
     if (touched) {
       LocalD L;
@@ -1078,6 +1114,11 @@ __global__ void __launch_bounds__(256) project_backward_kernel(const float* __re
   }
 }
 
+// Waves per SIMD asked of the compiler for the colour half (it would take
+// just over 256 registers at degree 3, one wave; 184 at degree 2, two).
+template <int DEG>
+constexpr int kShBackwardWaves = DEG == 3 ? 2 : DEG == 2 ? 3 : 4;
+
 // The colour half of the chain rule for DEG > 0 (after
 // project_backward_kernel, which left it out): per Gaussian, over its views,
 // the SH coefficients' gradient and the mean's share through the viewing
@@ -1085,12 +1126,14 @@ __global__ void __launch_bounds__(256) project_backward_kernel(const float* __re
 // added, after the geometry half). Clears the screen-space gradient rows it
 // reads when zero_g2.
 template <int DEG>
-__global__ void __launch_bounds__(256) sh_backward_kernel(const float* __restrict__ P, int64_t n, int64_t stride,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kShBackwardWaves<DEG>))) sh_backward_kernel(const float* __restrict__ P, int64_t n, int64_t stride,
                                                           int num_views, const ViewDesc* __restrict__ views,
                                                           float* __restrict__ g2,
                                                           const uint32_t* __restrict__ ntiles,
                                                           float* __restrict__ grad, bool overwrite, bool zero_g2) {
   constexpr int K = (DEG + 1) * (DEG + 1);
+  __shared__ ViewDesc s_views[kLdsViews];
+  const ViewDesc* vsrc = stage_views(views, num_views, s_views);
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     float gsh[3 * K];
 #pragma unroll
@@ -1100,8 +1143,9 @@ __global__ void __launch_bounds__(256) sh_backward_kernel(const float* __restric
     for (int k = 0; k < 3 * K; ++k) coef[k] = P[(11 + k) * stride + i];
     double gmean[3] = {0, 0, 0};
     bool touched = false;
-    for (int cur = 0; cur < num_views; ++cur) {
-      if (ntiles[(int64_t)cur * n + i] == 0u) continue;
+    for (int vb = 0; vb < num_views; vb += 64) {
+     for (uint64_t seen = listed_views(ntiles, n, i, vb, num_views); seen; seen &= seen - 1) {
+      const int cur = vb + __builtin_ctzll(seen);
       float* gv = g2 + ((int64_t)cur * n + i) * G2_N;
       float G[G2_N];
       bool any = false;
@@ -1116,11 +1160,12 @@ __global__ void __launch_bounds__(256) sh_backward_kernel(const float* __restric
         for (int k = 0; k < G2_N; ++k) gv[k] = 0.0f;
       }
       if (G[G2_R] == 0.0f && G[G2_G] == 0.0f && G[G2_BL] == 0.0f) continue;
-      touched = true;
       double gview[3];
-      colour_chain<DEG>(P, stride, i, views[cur], G + G2_R, coef, gsh, gview);
+      colour_chain<DEG>(P, stride, i, vsrc[cur], G + G2_R, ArrayCoef{coef}, ArraySink{gsh}, gview);
+      touched = true;
 #pragma unroll
       for (int j = 0; j < 3; ++j) gmean[j] += gview[j];
+     }
     }
     if (overwrite) {
 #pragma unroll
@@ -1223,11 +1268,12 @@ __global__ void __launch_bounds__(256) pose_backward_kernel(const float* __restr
 // not kept by the forward, so it is recomputed here by the same projection.
 __global__ void export_splats_kernel(const float* __restrict__ P, int64_t n, int64_t stride,
                                      const ViewDesc* __restrict__ view, float znear, const Splat* __restrict__ splats,
-                                     const int4* __restrict__ rect, float* __restrict__ out) {
+                                     const int4* __restrict__ rect, const uint32_t* __restrict__ ntiles,
+                                     float* __restrict__ out) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const int4 r = rect[i];
     float* o = out + i * 16;
-    const bool vis = r.z >= r.x;
+    const bool vis = ntiles[i] != 0u;
+    const int4 r = vis ? rect[i] : make_int4(0, 0, -1, -1);
     Splat s;
     if (vis) {
       s = splats[i];
@@ -1348,9 +1394,10 @@ void launch_pose_backward(const float* params, int64_t n, int64_t stride, int de
 }
 
 void launch_export_splats(const float* params, int64_t n, int64_t stride, const ViewDesc* view, float znear,
-                          const Splat* splats, const int4* rect, float* out, hipStream_t st) {
+                          const Splat* splats, const int4* rect, const uint32_t* ntiles, float* out,
+                          hipStream_t st) {
   if (n == 0) return;
-  export_splats_kernel<<<grid_for(n, 256), 256, 0, st>>>(params, n, stride, view, znear, splats, rect, out);
+  export_splats_kernel<<<grid_for(n, 256), 256, 0, st>>>(params, n, stride, view, znear, splats, rect, ntiles, out);
 }
 
 }  // namespace gsr
