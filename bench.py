@@ -90,7 +90,9 @@ def parse():
     ap.add_argument("--backward-schedule", type=int, default=0,
                     help="blend backward: 0 = pixel-parallel, 1 = splat-parallel (whole lists, two blend launches)")
     ap.add_argument("--binning", type=int, default=0,
-                    help="instances by tile: 0 = radix sort of tile keys, 1 = counting where it applies")
+                    help="instances by tile: 0 = automatic (blocks of tiles where the per-tile depth order "
+                         "applies, else a radix sort of tile keys), 1 = counting, 2 = radix sort of tile keys, "
+                         "3 = blocks of tiles")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use --tile/--ppt/--batch-depth instead of the autotuner's choice")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -146,6 +148,26 @@ def cpu_baseline(scene, cams, targets_np, repeats=3, single_row_step=8):
                       f"of {scene.name}, {cam.width}x{cam.height}, {scene.num} Gaussians; median of {repeats} on "
                       f"{cores} threads ({t_all:.2f} s); one thread: median of {repeats} over every "
                       f"{single_row_step}th pixel row, extrapolated to the view ({t_one:.1f} s)"}
+
+
+def binning_used(R, num, cams):
+    """The binning the library chooses for this rasterizer and workload (its
+    rule: blocks of tiles, at most 8x8 and 256 over all views, for the
+    per-tile depth order; counting where asked; else the radix sort)."""
+    per_tile = R.depth_sort == 1 or (R.depth_sort == 0 and num * len(cams) <= 2 ** 19)
+    if per_tile and R.binning == 1:
+        return "counting"
+    if per_tile and R.binning in (0, 3):
+        tiles = [((c.width + R.tile_w - 1) // R.tile_w, (c.height + R.tile_h - 1) // R.tile_h) for c in cams]
+        for area in range(7):
+            nb = {w: sum(((tx + (1 << w) - 1) >> w) * ((ty + (1 << (area - w)) - 1) >> (area - w))
+                         for tx, ty in tiles) for w in range(4) if 0 <= area - w <= 3}
+            fits = [w for w, n in nb.items() if n <= 256]
+            if fits:
+                w = min(fits, key=lambda w: (abs(2 * w - area), nb[w]))
+                h = area - w
+                return f"blocks of {1 << w}x{1 << h} tiles, one pass over block ids, per-tile filter and depth sort"
+    return "radix sort of tile keys"
 
 
 def achievable_peaks():
@@ -358,7 +380,7 @@ def main():
                    "max_chunks": R.max_chunks or "default",
                    "blend_launch": "fused" if dominant == "blend" else "separate",
                    "backward_schedule": ["pixel-parallel", "splat-parallel"][R.backward_schedule],
-                   "binning": ["radix sort of tile keys", "counting"][R.binning],
+                   "binning": binning_used(R, scene.num, cams),
                    "autotuned": tuned is not None, "tile_order": ["auto", "longest first", "index", "balanced"][R.tile_order],
                    "adam": use_adam, "mode": args.mode,
                    f"{other}_iters_s": round(1000.0 / other_ms, 3) if other_ms else None,

@@ -109,13 +109,18 @@ typedef struct {
                                Gaussian); the lists are walked whole, so chunk_len and
                                fuse_blend do not apply). Same gradient up to float summation
                                order. */
-  int32_t binning;          /* grouping of the instances by tile: 0 = emission in splat order
-                               and a radix sort of the tile keys (default), 1 = by counting
-                               where each tile's list is sorted by depth afterwards and every
-                               view has at most 8192 tiles (per-workgroup tile counts in LDS,
-                               one scan, a scatter; equal depths then ordered by index), else
-                               as 0. The lists are identical; 1 is slower on the benchmark
-                               workloads (its scatter writes are not coalesced). */
+  int32_t binning;          /* grouping of the instances by tile: 0 = automatic (3 where it applies,
+                               else 2), 1 = by counting where each tile's list is sorted by
+                               depth afterwards and every view has at most 8192 tiles
+                               (per-workgroup tile counts in LDS, one scan, a scatter; equal
+                               depths then ordered by index), else as 2; 2 = emission of one
+                               instance per (splat, tile) in splat order and a radix sort of the
+                               tile keys; 3 = by blocks of tiles where each tile's list is
+                               sorted by depth afterwards and the views' tiles fit in 256
+                               blocks of at most 8 x 8 tiles (one instance per (splat, block),
+                               one 8-bit radix pass over the block ids, then each tile's
+                               workgroup keeps the instances of its block that cover it and
+                               sorts them by depth), else as 2. The lists are identical. */
 } gsr_options;
 
 typedef struct {
@@ -167,7 +172,7 @@ int gsr_render1(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_camera* cam,
  * tight serving loops (a viewer rendering frames of a live map), harnesses
  * that forbid hipMalloc. Same arguments, kernels and images as gsr_render
  * (bit for bit), but every piece of device scratch comes from one static
- * array of 72 MiB in the library (a copy per GPU, held until the process
+ * array of 88 MiB in the library (a copy per GPU, held until the process
  * ends, set up by gsr_create), the instance storage has a fixed capacity, and
  * the call neither allocates (device or host) nor synchronises: it is
  * asynchronous on `stream` like the launches it makes.

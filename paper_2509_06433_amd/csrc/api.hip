@@ -39,7 +39,57 @@ int plan_render(gsr_ctx* ctx, const gsr_gaussians* g, int32_t nv, const gsr_came
   if (P.ntiles >= (int64_t(1) << 31)) return GSR_ERR_INVALID;
   P.capacity = 0;
   P.sorted_splats = P.inst_keys = P.inst_vals = nullptr;
+  plan_blocks(ctx, P);
   return GSR_OK;
+}
+
+// Binning by blocks of tiles applies to the per-tile depth order (option
+// binning 0 or 3). The block is the smallest (at most 8 x 8 tiles; then the
+// squarest, then the one giving fewer blocks) that leaves at most kMaxBlocks
+// blocks over all views, so that a single 8-bit radix pass groups the block
+// instances. Smaller blocks mean shorter block lists for every tile to
+// filter, larger ones fewer block instances.
+void plan_blocks(const gsr_ctx* ctx, RenderPlan& P) {
+  P.use_blocks = false;
+  P.blocks = BlockGeo{};
+  for (ViewDesc& v : P.views) {
+    v.block_offset = 0;
+    v.blocks_x = 0;
+  }
+  if (!(ctx->binning == 0 || ctx->binning == 3) || P.num == 0 || P.nv == 0 || !per_tile_depth(ctx, P)) return;
+  int bw = -1, bh = -1;
+  int64_t best = 0;
+  for (int area = 0; area <= 6 && bw < 0; ++area) {
+    for (int w = 0; w <= 3; ++w) {
+      const int h = area - w;
+      if (h < 0 || h > 3) continue;
+      int64_t nb = 0;
+      for (int v = 0; v < P.nv; ++v)
+        nb += (int64_t)((P.views[v].tiles_x + (1 << w) - 1) >> w) * ((P.views[v].tiles_y + (1 << h) - 1) >> h);
+      if (nb > kMaxBlocks) continue;
+      const int sq = std::abs(w - h), bsq = std::abs(bw - bh);
+      if (bw < 0 || sq < bsq || (sq == bsq && nb < best)) {
+        bw = w;
+        bh = h;
+        best = nb;
+      }
+    }
+  }
+  if (bw < 0) return;
+  int32_t off = 0;
+  for (ViewDesc& v : P.views) {
+    v.block_offset = off;
+    v.blocks_x = (v.tiles_x + (1 << bw) - 1) >> bw;
+    off += v.blocks_x * ((v.tiles_y + (1 << bh) - 1) >> bh);
+  }
+  P.use_blocks = true;
+  P.blocks = BlockGeo{bw, bh, __builtin_ctz((unsigned)ctx->tile_w), __builtin_ctz((unsigned)ctx->tile_h), off};
+}
+
+// Scratch of the tile grouping (B.hist2): the radix sort of the tile keys,
+// or with blocks the pass over the block ids.
+static int64_t tile_sort_scratch_elems(const RenderPlan& P) {
+  return P.use_blocks ? block_sort_scratch_elems(P.capacity) : radix_scratch_elems(P.capacity, bits_for(P.ntiles - 1));
 }
 
 int size_instances(gsr_ctx* ctx, Buffers& B, const RenderPlan& P) {
@@ -49,8 +99,13 @@ int size_instances(gsr_ctx* ctx, Buffers& B, const RenderPlan& P) {
   RET_IF(ensure(ctx, B.ivals, i4));
   RET_IF(ensure(ctx, B.ikeys_alt, i4));
   RET_IF(ensure(ctx, B.ivals_alt, i4));
-  RET_IF(ensure(ctx, B.hist2, sizeof(uint32_t) * (size_t)radix_scratch_elems(P.capacity, bits_for(P.ntiles - 1))));
+  RET_IF(ensure(ctx, B.hist2, sizeof(uint32_t) * (size_t)tile_sort_scratch_elems(P)));
   RET_IF(ensure(ctx, B.block_rank, sizeof(uint32_t) * (size_t)emit_plan_elems(P.capacity)));
+  if (P.use_blocks) {
+    RET_IF(ensure(ctx, B.bkeys, i4));
+    RET_IF(ensure(ctx, B.bvals, i4));
+    RET_IF(ensure(ctx, B.btab, sizeof(uint32_t) * (size_t)kBlockTabWords));
+  }
   return GSR_OK;
 }
 
@@ -103,6 +158,13 @@ void front_clears(const gsr_ctx* ctx, Buffers& B, const RenderPlan& P, ClearList
 }
 
 void back_clears(Buffers& B, const RenderPlan& P, ClearList& L) {
+  if (P.use_blocks) {
+    // the block pass's look-back words and histogram, the per-block tile
+    // counts; every tile's range is written by the per-tile step
+    L.add(B.hist2.p, block_sort_scratch_elems(P.capacity));
+    L.add(B.btab.p, (int64_t)kHistCopies * kMaxBlocks);
+    return;
+  }
   if (P.capacity > 1 && P.ntiles > 1) L.add(B.hist2.p, radix_scratch_elems(P.capacity, bits_for(P.ntiles - 1)));
   L.add(B.ranges.p, 2 * P.ntiles);
 }
@@ -165,6 +227,13 @@ int launch_front(gsr_ctx* ctx, Buffers& B, RenderPlan& P, const float* params, h
       scan_gather_exclusive(as<uint32_t>(B.ntiles), sva, as<uint32_t>(B.offsets), P.total, totals + 3, totals, oscan,
                             totals + 1, false, st, plan, P.capacity);
     }
+  } else if (P.use_blocks) {
+    // the offsets of the block instances; their count goes to totals[5],
+    // the tile lists' instance count to totals[0]
+    StageTimer tm(ctx, GSR_STAGE_SCAN, st);
+    launch_compact_scan_blocks(as<uint32_t>(B.ntiles), as<int4>(B.rect), P.blocks, P.total, sva,
+                               as<uint32_t>(B.offsets), totals + 3, totals + 5, totals, cscan, totals + 1, plan,
+                               P.capacity, st);
   } else {
     StageTimer tm(ctx, GSR_STAGE_SCAN, st);
     launch_compact_scan(as<uint32_t>(B.ntiles), P.total, sva, as<uint32_t>(B.offsets), totals + 3, totals, cscan,
@@ -245,6 +314,17 @@ bool use_fused_blend(const gsr_ctx* ctx, const RenderPlan& P) {
 
 static int launch_sorted_bins(gsr_ctx* ctx, Buffers& B, RenderPlan& P, hipStream_t st, uint32_t*& ik,
                               uint32_t*& iv, uint32_t*& ika, uint32_t*& iva);
+
+// The order in which the blend workgroups take the tiles, from the tile
+// ranges (where it is not the tile order).
+static void launch_tile_orders(gsr_ctx* ctx, Buffers& B, const RenderPlan& P, hipStream_t st) {
+  StageTimer tm(ctx, GSR_STAGE_RANGES, st);
+  if (use_lpt(ctx, P)) launch_tile_order(as<uint2>(B.ranges), P.ntiles, as<uint32_t>(B.order), st);
+  // the tile_last the previous render of these buffers left (a weight only)
+  if (use_balance(ctx, P))
+    launch_tile_balance(as<uint2>(B.ranges), as<uint32_t>(B.tile_last), P.ntiles, ctx->num_cus,
+                        as<uint32_t>(B.order), st);
+}
 static int launch_blend_front(gsr_ctx* ctx, Buffers& B, RenderPlan& P, hipStream_t st, const FusedLoss* loss,
                               bool fused, uint32_t* ik, uint32_t* iv, uint32_t* ika, uint32_t* iva);
 
@@ -256,7 +336,26 @@ int launch_back(gsr_ctx* ctx, Buffers& B, RenderPlan& P, hipStream_t st, const F
   uint32_t* iva = as<uint32_t>(B.ivals_alt);
   int64_t bin_entries = 0;
   int bin_tiles = 0;
-  if (use_bins(ctx, B, P, &bin_entries, &bin_tiles)) {
+  if (P.use_blocks) {
+    // one instance per (splat, block of tiles), grouped by block with one
+    // pass that also writes the block table; the tiles' lists are formed
+    // with their depth order (launch_blend_front)
+    uint32_t* hist2 = as<uint32_t>(B.hist2);
+    uint32_t* whist = as<uint32_t>(B.btab);
+    {
+      StageTimer tm(ctx, GSR_STAGE_EMIT, st);
+      launch_emit_blocks(P.sorted_splats, as<uint32_t>(B.offsets), totals + 5, totals + 3, as<int4>(B.rect),
+                         as<ViewDesc>(B.views), P.num, P.blocks, P.total, ika, iva, P.capacity, totals + 2,
+                         block_sort_hist(hist2, P.capacity), whist, as<uint32_t>(B.block_rank), P.plan_ready, st);
+    }
+    CHECK_LAUNCH(ctx);
+    {
+      StageTimer tm(ctx, GSR_STAGE_TILE_SORT, st);
+      launch_block_sort(ika, iva, totals + 5, P.capacity, P.blocks.nblocks, hist2, whist,
+                        reinterpret_cast<uint4*>(whist + (int64_t)kHistCopies * kMaxBlocks), totals + 1,
+                        as<uint32_t>(B.bkeys), as<uint32_t>(B.bvals), st);
+    }
+  } else if (use_bins(ctx, B, P, &bin_entries, &bin_tiles)) {
     StageTimer tm(ctx, GSR_STAGE_EMIT, st);
     launch_bin_scatter(as<uint32_t>(B.ntiles), as<int4>(B.rect), as<ViewDesc>(B.views), P.nv, P.num, bin_tiles,
                        ctx->tile_w, ctx->tile_h, as<uint32_t>(B.bins), totals, P.capacity, P.ntiles, ik, iv,
@@ -265,14 +364,8 @@ int launch_back(gsr_ctx* ctx, Buffers& B, RenderPlan& P, hipStream_t st, const F
     RET_IF(launch_sorted_bins(ctx, B, P, st, ik, iv, ika, iva));
   }
   CHECK_LAUNCH(ctx);
-  {
-    StageTimer tm(ctx, GSR_STAGE_RANGES, st);
-    if (use_lpt(ctx, P)) launch_tile_order(as<uint2>(B.ranges), P.ntiles, as<uint32_t>(B.order), st);
-    // the tile_last the previous render of these buffers left (a weight only)
-    if (use_balance(ctx, P))
-      launch_tile_balance(as<uint2>(B.ranges), as<uint32_t>(B.tile_last), P.ntiles, ctx->num_cus,
-                          as<uint32_t>(B.order), st);
-  }
+  // with blocks, the ranges exist only after the per-tile step
+  if (!P.use_blocks) launch_tile_orders(ctx, B, P, st);
   return launch_blend_front(ctx, B, P, st, loss, fused, ik, iv, ika, iva);
 }
 
@@ -317,7 +410,18 @@ static int launch_blend_front(gsr_ctx* ctx, Buffers& B, RenderPlan& P, hipStream
                               bool fused, uint32_t* ik, uint32_t* iv, uint32_t* ika, uint32_t* iva) {
   uint32_t* totals = as<uint32_t>(B.total);
   CHECK_LAUNCH(ctx);
-  if (per_tile_depth(ctx, P)) {
+  if (P.use_blocks) {
+    {
+      StageTimer tm(ctx, GSR_STAGE_TILE_DEPTH, st);
+      const uint32_t* whist = as<uint32_t>(B.btab);
+      launch_block_tile_sort(as<ViewDesc>(B.views), P.nv, P.ntiles, P.blocks,
+                             reinterpret_cast<const uint4*>(whist + (int64_t)kHistCopies * kMaxBlocks),
+                             as<uint32_t>(B.bkeys), as<uint32_t>(B.bvals), as<uint32_t>(B.zkey), P.total,
+                             P.capacity, ik, iv, ika, iva, as<uint2>(B.ranges), totals + 2, st);
+    }
+    CHECK_LAUNCH(ctx);
+    launch_tile_orders(ctx, B, P, st);
+  } else if (per_tile_depth(ctx, P)) {
     StageTimer tm(ctx, GSR_STAGE_TILE_DEPTH, st);
     int64_t m = 0;
     int mt = 0;
@@ -414,7 +518,7 @@ void free_buffers(Buffers& B) {
   DevBuf* bufs[] = {&B.views, &B.images, &B.images2, &B.splats, &B.rect, &B.ntiles, &B.zkey, &B.svals,
                     &B.zkey_alt, &B.svals_alt, &B.offsets, &B.ikeys, &B.ivals, &B.ikeys_alt, &B.ivals_alt,
                     &B.hist, &B.hist2, &B.partials, &B.ranges, &B.order, &B.tfinal, &B.last, &B.g2, &B.total,
-                    &B.tile_last, &B.ckpt, &B.block_rank, &B.tile_done, &B.bins};
+                    &B.tile_last, &B.ckpt, &B.block_rank, &B.tile_done, &B.bins, &B.bkeys, &B.bvals, &B.btab};
   for (DevBuf* b : bufs) {
     if (b->p && !b->fixed) (void)hipFree(b->p);
     b->p = nullptr;
@@ -577,7 +681,7 @@ int gsr_create(gsr_ctx** out, const gsr_options* opt) {
       return GSR_ERR_UNSUPPORTED;
     }
     ctx->bwd_schedule = opt->backward_schedule;
-    if (opt->binning < 0 || opt->binning > 1) {
+    if (opt->binning < 0 || opt->binning > 3) {
       delete ctx;
       return GSR_ERR_UNSUPPORTED;
     }
@@ -758,8 +862,26 @@ int gsr_copy_instances(gsr_ctx* ctx, uint32_t* tile, uint32_t* gid, int64_t capa
   const int64_t m = std::min(capacity, I);
   if (m == 0) return GSR_OK;
   if (!tile || !gid) return GSR_ERR_INVALID;
-  HIP_TRY(ctx, hipMemcpy(tile, ctx->q_plan->inst_keys, sizeof(uint32_t) * m, hipMemcpyDeviceToHost));
-  HIP_TRY(ctx, hipMemcpy(gid, ctx->q_plan->inst_vals, sizeof(uint32_t) * m, hipMemcpyDeviceToHost));
+  const RenderPlan& P = *ctx->q_plan;
+  if (P.use_blocks) {
+    // the tiles' lists lie block by block: gather them in tile order
+    std::vector<uint2> rg((size_t)P.ntiles);
+    std::vector<uint32_t> all((size_t)I);
+    HIP_TRY(ctx, hipMemcpy(rg.data(), ctx->q_bufs->ranges.p, sizeof(uint2) * rg.size(), hipMemcpyDeviceToHost));
+    HIP_TRY(ctx, hipMemcpy(all.data(), P.inst_vals, sizeof(uint32_t) * (size_t)I, hipMemcpyDeviceToHost));
+    int64_t o = 0;
+    for (int64_t t = 0; t < P.ntiles && o < m; ++t) {
+      for (uint32_t k = rg[t].x; k < rg[t].y && o < m; ++k, ++o) {
+        if ((int64_t)k >= I) return GSR_ERR_STATE;
+        tile[o] = (uint32_t)t;
+        gid[o] = all[k];
+      }
+    }
+    if (o < m) return GSR_ERR_STATE;
+  } else {
+    HIP_TRY(ctx, hipMemcpy(tile, P.inst_keys, sizeof(uint32_t) * m, hipMemcpyDeviceToHost));
+    HIP_TRY(ctx, hipMemcpy(gid, P.inst_vals, sizeof(uint32_t) * m, hipMemcpyDeviceToHost));
+  }
   const uint32_t N = (uint32_t)ctx->q_plan->num;
   for (int64_t k = 0; k < m; ++k) gid[k] = gid[k] % N;
   return GSR_OK;

@@ -44,6 +44,8 @@ struct Buffers {
   DevBuf tile_done;         // fused blend: per tile, its forward is done
   DevBuf block_rank;        // emission: first depth rank of every block of output positions
   DevBuf bins;              // binning by counting: per (tile, workgroup) counts, then run starts
+  DevBuf bkeys, bvals;      // binning by blocks: the block instances grouped by block
+  DevBuf btab;              // binning by blocks: per-block tile counts (kHistCopies copies), then the block table
 };
 
 // Sizes and final buffer roles of one forward render.
@@ -59,6 +61,8 @@ struct RenderPlan {
   uint32_t* inst_keys = nullptr;       // sorted instance list
   uint32_t* inst_vals = nullptr;
   bool forward_only = false;           // no backward follows: no per-chunk state, no gradient scratch
+  bool use_blocks = false;             // binning by blocks of tiles (blocks; views carry their block offsets)
+  BlockGeo blocks{};
 };
 
 struct GraphState;   // captured mapping iteration
@@ -120,7 +124,7 @@ struct gsr_ctx {
   int fuse_blend = 0;                   // mapping iteration: 0 automatic, 1 fused, -1 two launches
   int64_t fused_resident = 0;           // workgroups of the fused blend launch the device holds at once
   int depth_sort = 0;                   // 0 automatic, 1 per-tile sort after binning, 2 one global sort before
-  int binning = 0;                      // 0 radix sort of tile keys, 1 counting where it applies
+  int binning = 0;                      // 0 automatic, 1 counting, 2 radix sort of tile keys, 3 blocks of tiles
   int bwd_schedule = 0;                 // blend backward: 0 pixel-parallel, 1 splat-parallel
   float bg[3] = {0.f, 0.f, 0.f};
   float znear = 0.2f;
@@ -390,6 +394,13 @@ bool use_fused_blend(const gsr_ctx* ctx, const RenderPlan& plan);
 // Whether each tile's list is sorted by depth after binning (else all visible
 // splats are sorted once before binning).
 bool per_tile_depth(const gsr_ctx* ctx, const RenderPlan& plan);
+// Chooses the binning by blocks of tiles where it applies (plan.use_blocks,
+// plan.blocks) and fills the views' block offsets; called once the plan's
+// views and sizes are set.
+void plan_blocks(const gsr_ctx* ctx, RenderPlan& plan);
+// Words of B.btab: per-block tile counts in kHistCopies copies, then the
+// block table (kMaxBlocks uint4).
+constexpr int64_t kBlockTabWords = (int64_t)kHistCopies * kMaxBlocks + 4 * kMaxBlocks;
 // Binning by counting for this render (per-tile depth order, every view's
 // tiles within the workgroup bins, the count matrix within its bound and,
 // for a fixed buffer, within that buffer): its matrix size in words (tiles x

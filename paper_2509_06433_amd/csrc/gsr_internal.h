@@ -16,6 +16,19 @@ struct ViewDesc {
   int32_t tiles_x, tiles_y;
   int32_t tile_offset;    // first global tile id of this view
   int32_t pix_offset;     // first pixel of this view in per-pixel scratch
+  int32_t block_offset;   // binning by blocks of tiles: first global block id of this view
+  int32_t blocks_x;       // and its blocks per row
+};
+
+// Binning by blocks of tiles: a block is 2^bwl x 2^bhl tiles of one view
+// (at most 8 x 8), numbered view by view, row-major within a view; a tile is
+// 2^twl x 2^thl pixels. At most kMaxBlocks blocks over all views, so that
+// one 8-bit radix pass groups the block instances.
+constexpr int kMaxBlocks = 256;
+struct BlockGeo {
+  int32_t bwl, bhl;
+  int32_t twl, thl;
+  int32_t nblocks;
 };
 
 // Per-view image pointers (forward outputs, backward inputs, loss targets).
@@ -183,6 +196,15 @@ void scan_gather_exclusive(const uint32_t* in, const uint32_t* idx, uint32_t* ou
 void launch_compact_scan(const uint32_t* ntiles, int64_t n, uint32_t* vals, uint32_t* offsets, uint32_t* count_out,
                          uint32_t* total_out, uint32_t* scratch, uint32_t* err, uint32_t* block_rank, int64_t capacity,
                          hipStream_t st);
+// Binning by blocks of tiles (geo): the same compaction, with each visible
+// splat counted by the blocks its tile rectangle overlaps (from rect):
+// offsets[r] = the block instances before the r-th visible splat, their
+// total -> *block_total; the visible splats' tile counts are added to
+// *tile_total (the instance count of the tile lists).
+void launch_compact_scan_blocks(const uint32_t* ntiles, const int4* rect, const BlockGeo& geo, int64_t n,
+                                uint32_t* vals, uint32_t* offsets, uint32_t* count_out, uint32_t* block_total,
+                                uint32_t* tile_total, uint32_t* scratch, uint32_t* err, uint32_t* block_rank,
+                                int64_t capacity, hipStream_t st);
 // Order-preserving compaction of the n splats with a nonzero tile count:
 // out_keys/out_vals[r] = key and index of the r-th one, *count_out = their
 // number. Same scratch size and semantics as scan_gather_exclusive.
@@ -218,6 +240,35 @@ void launch_emit(const uint32_t* sorted_s, const uint32_t* offsets, const uint32
                  const uint32_t* count_dev, const Splat* splats, int64_t count, uint32_t* keys,
                  uint32_t* vals, int64_t capacity, uint32_t* overflow, uint32_t* hist, int hist_bits,
                  uint32_t* block_rank, bool plan_ready, hipStream_t st);
+// Binning by blocks: one instance per (visible splat, block it overlaps), in
+// splat order at the offsets above (at most `capacity`, else *overflow):
+// key = global block id | block-relative tile rectangle << 16 (x0, x1, y0,
+// y1; 4 bits each, one-past-last ends), value = splat index (view * num +
+// Gaussian). hist (kHistCopies x kMaxBlocks, at block_sort_hist) receives the
+// block ids' histogram and whist (the same shape) the tiles they cover.
+void launch_emit_blocks(const uint32_t* visible, const uint32_t* offsets, const uint32_t* total_dev,
+                        const uint32_t* count_dev, const int4* rect, const ViewDesc* views, int64_t num,
+                        const BlockGeo& geo, int64_t count, uint32_t* keys, uint32_t* vals, int64_t capacity,
+                        uint32_t* overflow, uint32_t* hist, uint32_t* whist, uint32_t* block_rank, bool plan_ready,
+                        hipStream_t st);
+// The stable pass over the block ids of min(*n_dev, n) block instances, into
+// keys_out/vals_out, which also writes table[b] = (first, one past last
+// position of block b's run, first position of its tiles' lists, their
+// instance count) for every block. scratch: block_sort_scratch_elems(n)
+// words, zeroed, its histogram (block_sort_hist) filled by the emission.
+int64_t block_sort_scratch_elems(int64_t n);
+uint32_t* block_sort_hist(uint32_t* scratch, int64_t n);
+void launch_block_sort(const uint32_t* keys, const uint32_t* vals, const uint32_t* n_dev, int64_t n, int nblocks,
+                       uint32_t* scratch, const uint32_t* whist, uint4* table, uint32_t* err, uint32_t* keys_out,
+                       uint32_t* vals_out, hipStream_t st);
+// Per tile: its list from its block's run (bkeys, bvals), sorted by depth
+// bits, in vals at [ranges[t].x, ranges[t].y); lists of more than 1536
+// instances are sorted through keys, keys_alt and vals_alt. A tile whose list
+// would pass `capacity` gets an empty range and sets *overflow.
+void launch_block_tile_sort(const ViewDesc* views, int num_views, int64_t num_tiles, const BlockGeo& geo,
+                            const uint4* table, const uint32_t* bkeys, const uint32_t* bvals, const uint32_t* zkey,
+                            int64_t num_splats, int64_t capacity, uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
+                            uint32_t* vals_alt, uint2* ranges, uint32_t* overflow, hipStream_t st);
 // ranges[t] = (start, end) of global tile t in the sorted key array of
 // min(*n_dev, count) instances (count if n_dev is null); clear = false: the
 // caller has zeroed ranges.

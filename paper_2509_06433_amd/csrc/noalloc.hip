@@ -24,7 +24,7 @@ constexpr int kNaMaxViews = 16;
 // count matrix of the binning by counting (tiles x workgroups per view);
 // larger renders take the radix path
 constexpr int64_t kNaMaxBinEntries = int64_t(1) << 20;
-constexpr size_t kNaBytes = size_t(72) << 20;
+constexpr size_t kNaBytes = size_t(88) << 20;
 
 static __device__ __align__(256) unsigned char scratch[kNaBytes];
 
@@ -49,7 +49,7 @@ bool carve(unsigned char* base, Buffers& B) {
     ok = ok && off <= kNaBytes;
   };
   const size_t u4 = sizeof(uint32_t);
-  int64_t hist2 = 0;
+  int64_t hist2 = block_sort_scratch_elems(kNaMaxInstances);
   for (int bits = 0; bits <= 15; ++bits) hist2 = std::max(hist2, radix_scratch_elems(kNaMaxInstances, bits));
   take(B.views, sizeof(ViewDesc) * kNaMaxViews);
   take(B.images, sizeof(ViewImages) * kNaMaxViews);
@@ -65,6 +65,9 @@ bool carve(unsigned char* base, Buffers& B) {
   take(B.ivals, u4 * kNaMaxInstances);
   take(B.ikeys_alt, u4 * kNaMaxInstances);
   take(B.ivals_alt, u4 * kNaMaxInstances);
+  take(B.bkeys, u4 * kNaMaxInstances);
+  take(B.bvals, u4 * kNaMaxInstances);
+  take(B.btab, u4 * (size_t)kBlockTabWords);
   take(B.hist2, u4 * (size_t)hist2);
   take(B.block_rank, u4 * (size_t)emit_plan_elems(kNaMaxInstances));
   take(B.ranges, sizeof(uint2) * kNaMaxTiles);
@@ -149,6 +152,7 @@ int render_noalloc_impl(gsr_ctx* ctx, const gsr_gaussians* g, int32_t nv, const 
   }
   P.ntiles = ntiles;
   P.npix = npix;
+  plan_blocks(ctx, P);
   if (P.total > kNaMaxSplats || P.npix > kNaMaxPixels || P.ntiles > kNaMaxTiles) return GSR_ERR_CAPACITY;
   P.capacity = kNaMaxInstances;
   P.forward_only = true;

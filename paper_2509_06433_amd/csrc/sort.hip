@@ -211,10 +211,23 @@ constexpr unsigned long long kCsAgg = 1ull << 62;
 constexpr unsigned long long kCsInc = 2ull << 62;
 constexpr unsigned long long kCsPayload = (1ull << 62) - 1ull;
 
+// Blocks of tiles a listed splat's tile rectangle overlaps (BlockGeo), from
+// its inclusive pixel rectangle.
+__device__ __forceinline__ uint32_t block_count(const int4& r, const BlockGeo& g) {
+  const uint32_t bx0 = ((uint32_t)r.x >> g.twl) >> g.bwl, bx1 = ((uint32_t)r.z >> g.twl) >> g.bwl;
+  const uint32_t by0 = ((uint32_t)r.y >> g.thl) >> g.bhl, by1 = ((uint32_t)r.w >> g.thl) >> g.bhl;
+  return (bx1 - bx0 + 1u) * (by1 - by0 + 1u);
+}
+
+// BLOCKS: the counts scanned are the splats' block counts (binning by blocks
+// of tiles; rect and geo give them), and the sum of their tile counts is
+// added to *tile_total (one atomic per workgroup).
+template <bool BLOCKS>
 __global__ void __launch_bounds__(kScanThreads) compact_scan_kernel(
     const uint32_t* __restrict__ ntiles, int64_t n, uint32_t* __restrict__ vals, uint32_t* __restrict__ offsets,
     uint32_t* __restrict__ count_out, uint32_t* __restrict__ total_out, unsigned long long* __restrict__ status,
-    uint32_t* __restrict__ err, uint32_t* __restrict__ block_rank, int64_t plan_blocks) {
+    uint32_t* __restrict__ err, uint32_t* __restrict__ block_rank, int64_t plan_blocks,
+    const int4* __restrict__ rect, BlockGeo geo, uint32_t* __restrict__ tile_total) {
   __shared__ uint32_t tile[kScanChunk];
   __shared__ unsigned long long s_excl;
   const uint32_t bid = blockIdx.x;
@@ -222,15 +235,29 @@ __global__ void __launch_bounds__(kScanThreads) compact_scan_kernel(
   // loads at in-bounds addresses for every lane, all issued before the
   // first wait
   uint32_t ld[kScanItems];
+  int4 rct[BLOCKS ? kScanItems : 1];
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     const int64_t j = base + k * kScanThreads + threadIdx.x;
     ld[k] = ntiles[j < n ? j : 0];
+    if (BLOCKS) rct[k] = rect[j < n ? j : 0];
   }
+  uint32_t tsum = 0;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     const int local = k * kScanThreads + threadIdx.x;
-    tile[local] = base + local < n ? ld[k] : 0u;
+    const uint32_t c = base + local < n ? ld[k] : 0u;
+    if (BLOCKS) {
+      // the rectangle of an unlisted splat is stale: only listed ones count
+      tsum += c;
+      tile[local] = c != 0u ? block_count(rct[k], geo) : 0u;
+    } else {
+      tile[local] = c;
+    }
+  }
+  if (BLOCKS) {
+    tsum = wave_incl_scan(tsum);
+    if ((threadIdx.x & 63) == 63 && tsum) atomicAdd(tile_total, tsum);
   }
   __syncthreads();
   uint32_t v[kScanItems];
@@ -433,6 +460,14 @@ __host__ __device__ inline void radix_plan(int bits, int* rb, int* passes) {
   *passes = (bits + 7) / 8;
 }
 
+// Digit bits of the pass over block ids (at least one, so that a single
+// block still gets its pass and its table).
+__host__ __device__ inline int bits_for_blocks(int nblocks) {
+  int b = 1;
+  while (b < 8 && (1 << b) < nblocks) ++b;
+  return b;
+}
+
 __global__ void __launch_bounds__(kSortThreads) global_hist_kernel(const uint32_t* __restrict__ keys,
                                                                    const uint32_t* __restrict__ n_dev, int64_t n_host,
                                                                    int rb, int passes, uint32_t* __restrict__ ghist) {
@@ -500,13 +535,15 @@ __global__ void __launch_bounds__(kSortThreads) digit_count_kernel(const uint32_
 // digit counts plus the global histogram (SCANNED false: `status` holds the
 // published counts), or, SCANNED true, from the exclusive scan of
 // digit_count_kernel's counts (`status` holds that scan, digit-major).
-template <int RB, int ITEMS, bool SCANNED = false>
+// TABLE: the pass over block ids of the binning by blocks, whose first
+// workgroup also writes the block table (see launch_block_sort).
+template <int RB, int ITEMS, bool SCANNED = false, bool TABLE = false>
 __global__ void __launch_bounds__(kSortThreads) onesweep_pass_kernel(
     const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals, const uint32_t* __restrict__ n_dev,
     int64_t n_host, int shift, int dbits, const uint32_t* __restrict__ ghist, int ghist_stride,
     uint32_t* __restrict__ status,
     uint32_t* __restrict__ err, uint32_t* __restrict__ keys_out,
-    uint32_t* __restrict__ vals_out) {
+    uint32_t* __restrict__ vals_out, const uint32_t* __restrict__ whist = nullptr, uint4* __restrict__ table = nullptr) {
   constexpr int R = 1 << RB;
   constexpr int NW = kSortThreads / 64;
   constexpr int CHUNK = kSortThreads * ITEMS;    // keys per workgroup
@@ -521,6 +558,7 @@ __global__ void __launch_bounds__(kSortThreads) onesweep_pass_kernel(
   __shared__ uint32_t gofs[R];         // global start of each digit's run of this block (minus its local start)
   __shared__ uint32_t lstart[R];       // block-local start of each digit's run
   __shared__ uint32_t s_wsum[2][NW];
+  __shared__ uint32_t s_tsum[NW];
   uint32_t (*wcnt)[R] = reinterpret_cast<uint32_t (*)[R]>(s_mem);
   uint32_t* s_keys = s_mem;
   uint32_t* s_vals = s_mem + CHUNK;
@@ -711,6 +749,28 @@ __global__ void __launch_bounds__(kSortThreads) onesweep_pass_kernel(
           SCANNED ? ((uint32_t)d <= dmask ? status[(size_t)d * gridDim.x + bid] : 0u) : gx0 + gpre[t] + excl[t];
       gofs[d] = start - (my0 + mpre[t]);
     }
+    if (TABLE && !SCANNED && DPT == 1 && bid == 0) {
+      // binning by blocks (one pass over the block ids): per block, its run
+      // [start, end) in the sorted output and the first position of its
+      // tiles' lists (the tiles of the blocks before it, summed)
+      const uint32_t h = gs;     // this digit's (block's) instance count
+      uint32_t w = 0;
+#pragma unroll
+      for (int c = 0; c < kHistCopies; ++c) w += whist[(size_t)c * R + tid];
+      uint32_t z = w;
+#pragma unroll
+      for (int dd = 1; dd < 64; dd <<= 1) {
+        const uint32_t zs = __shfl_up(z, dd, 64);
+        if (lane >= dd) z += zs;
+      }
+      if (lane == 63) s_tsum[wave] = z;
+      __syncthreads();
+      uint32_t bz = 0;
+#pragma unroll
+      for (int w2 = 0; w2 < NW; ++w2) bz += (w2 < wave) ? s_tsum[w2] : 0u;
+      const uint32_t st0 = gx0 + gpre[0];
+      table[tid] = make_uint4(st0, st0 + h, bz + z - w, w);
+    }
   }
   __syncthreads();
   // block-local position of every key, then the count storage becomes the
@@ -881,6 +941,14 @@ __global__ void __launch_bounds__(256) emit_plan_kernel(const uint32_t* __restri
   }
 }
 
+// BLOCKS: one instance per (splat, block of tiles) instead of per (splat,
+// tile) (binning by blocks; geo, rect and views give the blocks). Its key is
+// the global block id in bits 0-15 and the part of the splat's tile
+// rectangle inside the block, block-relative, in bits 16-31 (first and
+// one-past-last column, then row, 4 bits each). hist receives the
+// histogram of the block ids (one 8-bit pass) and whist, per block, the
+// tiles its instances cover (both in kHistCopies copies).
+template <bool BLOCKS>
 __global__ void __launch_bounds__(kEmitThreads) emit_kernel(const uint32_t* __restrict__ sorted_s,
                                                            const uint32_t* __restrict__ offsets,
                                                            const uint32_t* __restrict__ total_dev,
@@ -889,11 +957,19 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(const uint32_t* __re
                                                            const Splat* __restrict__ splats, int64_t count_host,
                                                            uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
                                                            int64_t capacity, uint32_t* __restrict__ overflow,
-                                                           uint32_t* __restrict__ hist, int hist_rb, int hist_passes) {
+                                                           uint32_t* __restrict__ hist, int hist_rb, int hist_passes,
+                                                           const int4* __restrict__ rect,
+                                                           const ViewDesc* __restrict__ views, uint32_t num,
+                                                           BlockGeo geo, uint32_t* __restrict__ whist) {
   __shared__ uint32_t s_off[kEmitBlock + 1];
   __shared__ uint32_t s_sid[kEmitBlock];
-  __shared__ int2 s_geo[kEmitBlock];      // first tile id of the rectangle; rectangle width | view row pitch << 16
-  __shared__ uint32_t s_hist[kEmitHist];  // hist_passes * 2^hist_rb <= kEmitHist
+  // first tile id of the rectangle; rectangle width | view row pitch << 16.
+  // BLOCKS: view-local tile rectangle (x0 | x1 << 16, y0 | y1 << 16, both
+  // inclusive), the first block's global id and the splat's blocks per row |
+  // the view's blocks per row << 16
+  __shared__ int4 s_geo4[BLOCKS ? kEmitBlock : 1];
+  __shared__ int2 s_geo2[BLOCKS ? 1 : kEmitBlock];
+  __shared__ uint32_t s_hist[kEmitHist];  // hist_passes * 2^hist_rb <= kEmitHist; BLOCKS: 2 x 256
   const int tid = threadIdx.x;
   const uint32_t total = *total_dev;
   if (blockIdx.x == 0 && tid == 0 && (int64_t)total > capacity) atomicOr(overflow, 1u);
@@ -903,8 +979,9 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(const uint32_t* __re
   const int64_t oend = min(o0 + kEmitBlock, written);
   if (o0 >= oend || count == 0) return;
   const int hR = 1 << hist_rb;
+  const int hwords = BLOCKS ? 2 * kMaxBlocks : hist_passes * hR;
   if (hist)
-    for (int e = tid; e < hist_passes * hR; e += kEmitThreads) s_hist[e] = 0u;
+    for (int e = tid; e < hwords; e += kEmitThreads) s_hist[e] = 0u;
   // ranks [r0, r_end) hold this block's positions
   // (block b + 1's start is read only if that block exists and starts
   // inside the output; it holds the rank of position 1024 (b + 1))
@@ -918,8 +995,20 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(const uint32_t* __re
     s_off[j] = offsets[r];
     const uint32_t sid = sorted_s[r];
     s_sid[j] = sid;
-    // the tile rectangle the projection stored in the record's spare words
-    s_geo[j] = make_int2((int)__float_as_uint(splats[sid].w1.w), (int)__float_as_uint(splats[sid].w2.w));
+    if (BLOCKS) {
+      const int4 rc = rect[sid];
+      const ViewDesc& V = views[sid / num];
+      const uint32_t x0 = (uint32_t)rc.x >> geo.twl, x1 = (uint32_t)rc.z >> geo.twl;
+      const uint32_t y0 = (uint32_t)rc.y >> geo.thl, y1 = (uint32_t)rc.w >> geo.thl;
+      const uint32_t bx0 = x0 >> geo.bwl, by0 = y0 >> geo.bhl;
+      const uint32_t bw = (x1 >> geo.bwl) - bx0 + 1u;
+      s_geo4[j] = make_int4((int)(x0 | (x1 << 16)), (int)(y0 | (y1 << 16)),
+                           (int)((uint32_t)V.block_offset + by0 * (uint32_t)V.blocks_x + bx0),
+                           (int)(bw | ((uint32_t)V.blocks_x << 16)));
+    } else {
+      // the tile rectangle the projection stored in the record's spare words
+      s_geo2[j] = make_int2((int)__float_as_uint(splats[sid].w1.w), (int)__float_as_uint(splats[sid].w2.w));
+    }
   }
   if (tid == 0) s_off[nr] = r0 + nr < count ? offsets[r0 + nr] : total;
   __syncthreads();
@@ -930,21 +1019,49 @@ __global__ void __launch_bounds__(kEmitThreads) emit_kernel(const uint32_t* __re
       if (s_off[mid] <= (uint32_t)o) lo = mid;
       else hi = mid;
     }
-    const int2 geo = s_geo[lo];
-    const uint32_t wdt = (uint32_t)geo.y & 0xFFFFu, pitch = (uint32_t)geo.y >> 16;
     const uint32_t local = (uint32_t)o - s_off[lo];
-    const uint32_t dy = local / wdt, dx = local - dy * wdt;
-    const uint32_t key = (uint32_t)geo.x + dy * pitch + dx;
+    uint32_t key;
+    if (BLOCKS) {
+      const int4 geo4 = s_geo4[lo];
+      const uint32_t wdt = (uint32_t)geo4.w & 0xFFFFu, pitch = (uint32_t)geo4.w >> 16;
+      const uint32_t dy = local / wdt, dx = local - dy * wdt;
+      const uint32_t x0 = (uint32_t)geo4.x & 0xFFFFu, x1 = (uint32_t)geo4.x >> 16;
+      const uint32_t y0 = (uint32_t)geo4.y & 0xFFFFu, y1 = (uint32_t)geo4.y >> 16;
+      const uint32_t bx = (x0 >> geo.bwl) + dx, by = (y0 >> geo.bhl) + dy;
+      const uint32_t cx = bx << geo.bwl, cy = by << geo.bhl;   // the block's first tile
+      const uint32_t rx0 = x0 > cx ? x0 - cx : 0u, rx1 = min(x1 + 1u - cx, 1u << geo.bwl);
+      const uint32_t ry0 = y0 > cy ? y0 - cy : 0u, ry1 = min(y1 + 1u - cy, 1u << geo.bhl);
+      const uint32_t blk = (uint32_t)geo4.z + dy * pitch + dx;
+      key = blk | (rx0 << 16) | (rx1 << 20) | (ry0 << 24) | (ry1 << 28);
+      if (hist) {
+        atomicAdd(&s_hist[blk & (kMaxBlocks - 1)], 1u);
+        atomicAdd(&s_hist[kMaxBlocks + (blk & (kMaxBlocks - 1))], (rx1 - rx0) * (ry1 - ry0));
+      }
+    } else {
+      const int2 geo2 = s_geo2[lo];
+      const uint32_t wdt = (uint32_t)geo2.y & 0xFFFFu, pitch = (uint32_t)geo2.y >> 16;
+      const uint32_t dy = local / wdt, dx = local - dy * wdt;
+      key = (uint32_t)geo2.x + dy * pitch + dx;
+      if (hist)
+        for (int p = 0; p < hist_passes; ++p) atomicAdd(&s_hist[p * hR + ((key >> (hist_rb * p)) & (hR - 1))], 1u);
+    }
     keys[o] = key;
     vals[o] = s_sid[lo];
-    if (hist)
-      for (int p = 0; p < hist_passes; ++p) atomicAdd(&s_hist[p * hR + ((key >> (hist_rb * p)) & (hR - 1))], 1u);
   }
   if (hist) {
     __syncthreads();
-    uint32_t* dst = hist + (size_t)(blockIdx.x % kHistCopies) * (hist_passes * hR);
-    for (int e = tid; e < hist_passes * hR; e += kEmitThreads)
-      if (s_hist[e]) atomicAdd(&dst[e], s_hist[e]);
+    if (BLOCKS) {
+      uint32_t* dst = hist + (size_t)(blockIdx.x % kHistCopies) * kMaxBlocks;
+      uint32_t* wdst = whist + (size_t)(blockIdx.x % kHistCopies) * kMaxBlocks;
+      for (int e = tid; e < kMaxBlocks; e += kEmitThreads) {
+        if (s_hist[e]) atomicAdd(&dst[e], s_hist[e]);
+        if (s_hist[kMaxBlocks + e]) atomicAdd(&wdst[e], s_hist[kMaxBlocks + e]);
+      }
+    } else {
+      uint32_t* dst = hist + (size_t)(blockIdx.x % kHistCopies) * (hist_passes * hR);
+      for (int e = tid; e < hist_passes * hR; e += kEmitThreads)
+        if (s_hist[e]) atomicAdd(&dst[e], s_hist[e]);
+    }
   }
 }
 
@@ -1124,6 +1241,187 @@ __device__ void order_equal_depths(const uint32_t* k, uint32_t* v, int n) {
   }
 }
 
+// LDS of the per-tile depth sort.
+struct TileSortShared {
+  uint32_t k[2][kTileSortCap], v[2][kTileSortCap];
+  uint32_t wcnt[kTileSortWaves][256];
+  uint32_t start[256];     // the digit's first position (whole list) plus earlier chunks' count
+  uint32_t wsum[kTileSortWaves];
+};
+
+// Four 8-bit LSD passes over a list of n <= kTileSortCap entries that the
+// workgroup holds in registers (thread: rows r of its wave, entry
+// wave R 64 + 64 r + lane; entries past n hold key 0xFFFFFFFF). The sorted
+// list ends in S.k[0], S.v[0].
+__device__ __forceinline__ void lds_depth_sort(TileSortShared& S, uint32_t (&k)[kTileSortRows],
+                                               uint32_t (&v)[kTileSortRows], int n) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  uint32_t off[kTileSortRows];
+  for (int pass = 0; pass < 4; ++pass) {
+    const int shift = 8 * pass;
+    for (int w = 0; w < kTileSortWaves; ++w) S.wcnt[w][tid] = 0u;
+    __syncthreads();
+    tile_sort_rank(k, n, shift, off, S.wcnt, wave, lane);
+    __syncthreads();
+    // per digit: exclusive prefix over the waves, and the digit total
+    uint32_t acc = 0;
+    for (int w = 0; w < kTileSortWaves; ++w) {
+      const uint32_t c = S.wcnt[w][tid];
+      S.wcnt[w][tid] = acc;
+      acc += c;
+    }
+    // exclusive scan of the totals over the 256 digits (one per thread)
+    uint32_t x = acc;
+#pragma unroll
+    for (int dd = 1; dd < 64; dd <<= 1) {
+      const uint32_t y = __shfl_up(x, dd, 64);
+      if (lane >= dd) x += y;
+    }
+    if (lane == 63) S.wsum[wave] = x;
+    __syncthreads();
+    uint32_t base = 0;
+    for (int w = 0; w < wave; ++w) base += S.wsum[w];
+    S.start[tid] = base + x - acc;
+    __syncthreads();
+    const int dst = (pass + 1) & 1;
+#pragma unroll
+    for (int r = 0; r < kTileSortRows; ++r) {
+      if (off[r] == 0xFFFFFFFFu) continue;
+      const uint32_t d = (k[r] >> shift) & 255u;
+      const uint32_t pos = S.start[d] + S.wcnt[wave][d] + off[r];
+      if (pos < (uint32_t)n) {     // always, when the counts are right; never outside the list
+        S.k[dst][pos] = k[r];
+        S.v[dst][pos] = v[r];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kTileSortRows; ++r) {
+      const int e = wave * (64 * kTileSortRows) + r * 64 + lane;
+      if (e < n) {
+        k[r] = S.k[dst][e];
+        v[r] = S.v[dst][e];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// A list longer than kTileSortCap, [rg.x, rg.x + n), sorted through global
+// memory: per pass, the digit totals of the whole list, then every chunk in
+// list order scattered after the earlier chunks' entries of each digit;
+// passes alternate between (keys, vals) and (keys_alt, vals_alt) over the
+// range, and the list arrives in vals (its keys are scratch). Ends with the
+// tile key in keys over the range.
+__device__ __forceinline__ void global_depth_sort(TileSortShared& S, uint2 rg, int n, uint32_t tile, bool ties,
+                                  const uint32_t* __restrict__ zkey, uint32_t* __restrict__ keys,
+                                  uint32_t* __restrict__ vals, uint32_t* __restrict__ keys_alt,
+                                  uint32_t* __restrict__ vals_alt) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  uint32_t k[kTileSortRows], v[kTileSortRows], off[kTileSortRows];
+  for (int pass = 0; pass < 4; ++pass) {
+    const int shift = 8 * pass;
+    const uint32_t* ks = (pass & 1) ? keys_alt : keys;
+    const uint32_t* vs = (pass & 1) ? vals_alt : vals;
+    uint32_t* kd = (pass & 1) ? keys : keys_alt;
+    uint32_t* vd = (pass & 1) ? vals : vals_alt;
+    // digit totals of the whole list (the ranking's counts, chunk by chunk)
+    uint32_t total = 0;
+    for (int c0 = 0; c0 < n; c0 += kTileSortCap) {
+      const int cn = min(kTileSortCap, n - c0);
+      // loads at in-bounds positions for every lane (the chunk's first
+      // entry past its end), masked afterwards
+#pragma unroll
+      for (int r = 0; r < kTileSortRows; ++r) {
+        const int e = wave * (64 * kTileSortRows) + r * 64 + lane;
+        const uint32_t at = rg.x + c0 + (e < cn ? e : 0);
+        k[r] = pass == 0 ? vs[at] : ks[at];
+      }
+      if (pass == 0) {
+#pragma unroll
+        for (int r = 0; r < kTileSortRows; ++r) k[r] = zkey[k[r]];
+      }
+#pragma unroll
+      for (int r = 0; r < kTileSortRows; ++r)
+        if (wave * (64 * kTileSortRows) + r * 64 + lane >= cn) k[r] = 0xFFFFFFFFu;
+      for (int w = 0; w < kTileSortWaves; ++w) S.wcnt[w][tid] = 0u;
+      __syncthreads();
+      tile_sort_rank(k, cn, shift, off, S.wcnt, wave, lane);
+      __syncthreads();
+      for (int w = 0; w < kTileSortWaves; ++w) total += S.wcnt[w][tid];
+      __syncthreads();
+    }
+    S.start[tid] = total;
+    __syncthreads();
+    {
+      const uint32_t acc = S.start[tid];
+      uint32_t x = acc;
+#pragma unroll
+      for (int dd = 1; dd < 64; dd <<= 1) {
+        const uint32_t y = __shfl_up(x, dd, 64);
+        if (lane >= dd) x += y;
+      }
+      if (lane == 63) S.wsum[wave] = x;
+      __syncthreads();
+      uint32_t base = 0;
+      for (int w = 0; w < wave; ++w) base += S.wsum[w];
+      __syncthreads();
+      S.start[tid] = base + x - acc;
+    }
+    __syncthreads();
+    for (int c0 = 0; c0 < n; c0 += kTileSortCap) {
+      const int cn = min(kTileSortCap, n - c0);
+#pragma unroll
+      for (int r = 0; r < kTileSortRows; ++r) {
+        const int e = wave * (64 * kTileSortRows) + r * 64 + lane;
+        const uint32_t at = rg.x + c0 + (e < cn ? e : 0);
+        v[r] = vs[at];
+        if (pass != 0) k[r] = ks[at];
+      }
+      if (pass == 0) {
+#pragma unroll
+        for (int r = 0; r < kTileSortRows; ++r) k[r] = zkey[v[r]];
+      }
+#pragma unroll
+      for (int r = 0; r < kTileSortRows; ++r) {
+        if (wave * (64 * kTileSortRows) + r * 64 + lane >= cn) {
+          v[r] = 0u;
+          k[r] = 0xFFFFFFFFu;
+        }
+      }
+      for (int w = 0; w < kTileSortWaves; ++w) S.wcnt[w][tid] = 0u;
+      __syncthreads();
+      tile_sort_rank(k, cn, shift, off, S.wcnt, wave, lane);
+      __syncthreads();
+      uint32_t acc = 0;
+      for (int w = 0; w < kTileSortWaves; ++w) {
+        const uint32_t c = S.wcnt[w][tid];
+        S.wcnt[w][tid] = acc;
+        acc += c;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < kTileSortRows; ++r) {
+        if (off[r] == 0xFFFFFFFFu) continue;
+        const uint32_t d = (k[r] >> shift) & 255u;
+        const uint32_t pos = S.start[d] + S.wcnt[wave][d] + off[r];
+        if (pos < (uint32_t)n) {   // always, when the counts are right; never outside the tile's range
+          kd[rg.x + pos] = k[r];
+          vd[rg.x + pos] = v[r];
+        }
+      }
+      __syncthreads();
+      S.start[tid] += acc;          // this chunk's entries of each digit precede the next chunk's
+      __syncthreads();
+    }
+  }
+  // four passes end in (keys, vals); the keys held depth bits: order
+  // equal depths, then restore the tile key
+  __syncthreads();
+  if (ties) order_equal_depths(keys + rg.x, vals + rg.x, n);
+  for (int e = tid; e < n; e += kTileSortThreads) keys[rg.x + e] = tile;
+}
+
 // TIES: the lists did not arrive in splat-index order (the counting
 // binning): equal depths are put in index order after the passes.
 template <bool TIES>
@@ -1131,21 +1429,18 @@ __global__ void __launch_bounds__(kTileSortThreads) tile_depth_sort_kernel(
     const uint2* __restrict__ ranges, int64_t num_tiles, const uint32_t* __restrict__ zkey,
     uint32_t* __restrict__ keys, uint32_t* __restrict__ vals, uint32_t* __restrict__ keys_alt,
     uint32_t* __restrict__ vals_alt) {
-  __shared__ uint32_t s_k[2][kTileSortCap], s_v[2][kTileSortCap];
-  __shared__ uint32_t wcnt[kTileSortWaves][256];
-  __shared__ uint32_t s_start[256];     // the digit's first position (whole list) plus earlier chunks' count
-  __shared__ uint32_t s_wsum[kTileSortWaves];
+  __shared__ TileSortShared S;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int64_t tile = blockIdx.x; tile < num_tiles; tile += gridDim.x) {
     const uint2 rg = ranges[tile];
     const int n = (int)(rg.y - rg.x);
     if (n < 2) continue;
-    uint32_t k[kTileSortRows], v[kTileSortRows], off[kTileSortRows];
     if (n <= kTileSortCap) {
       // in LDS: load, then four passes between the two buffers. Lanes past
       // the list read its first entry (a listed splat, so its depth key is
       // in bounds too): every row's id and key loads are in flight at once
       // rather than one guarded round trip after another
+      uint32_t k[kTileSortRows], v[kTileSortRows];
 #pragma unroll
       for (int r = 0; r < kTileSortRows; ++r) {
         const int e = wave * (64 * kTileSortRows) + r * 64 + lane;
@@ -1161,169 +1456,224 @@ __global__ void __launch_bounds__(kTileSortThreads) tile_depth_sort_kernel(
           k[r] = 0xFFFFFFFFu;
         }
       }
-      for (int pass = 0; pass < 4; ++pass) {
-        const int shift = 8 * pass;
-        for (int w = 0; w < kTileSortWaves; ++w) wcnt[w][tid] = 0u;
-        __syncthreads();
-        tile_sort_rank(k, n, shift, off, wcnt, wave, lane);
-        __syncthreads();
-        // per digit: exclusive prefix over the waves, and the digit total
-        uint32_t acc = 0;
-        for (int w = 0; w < kTileSortWaves; ++w) {
-          const uint32_t c = wcnt[w][tid];
-          wcnt[w][tid] = acc;
-          acc += c;
+      lds_depth_sort(S, k, v, n);
+      // the fourth pass left the list in S.k[0], S.v[0]
+      if (TIES) order_equal_depths(S.k[0], S.v[0], n);
+#pragma unroll
+      for (int r = 0; r < kTileSortRows; ++r) {
+        const int e = wave * (64 * kTileSortRows) + r * 64 + lane;
+        if (e < n) vals[rg.x + e] = S.v[0][e];
+      }
+    } else {
+      global_depth_sort(S, rg, n, (uint32_t)tile, TIES, zkey, keys, vals, keys_alt, vals_alt);
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Binning by blocks of tiles, the per-tile step. The block instances arrive
+// grouped by block (a stable pass over the block ids of instances emitted in
+// splat-index order), so a block's list is in index order. One workgroup per
+// tile reads its block's list, keeps the instances whose block-relative
+// rectangle covers the tile (a stream compaction by ballots, which keeps the
+// order) and sorts them stably by depth bits as tile_depth_sort_kernel does.
+// The tile's list goes to the first position of its block's tiles (from the
+// block table) plus the tiles of its block before it in row-major order,
+// which every entry of the block's list gives arithmetically from its
+// rectangle: no scan over the tiles is needed. Tiles whose list would pass
+// the capacity get an empty range and raise the overflow flag.
+// ---------------------------------------------------------------------------
+constexpr int kBlockRows = 32;   // rows of 256 list entries whose keep masks stay in LDS
+constexpr int kBlockLoads = 8;   // rows whose loads are in flight together
+
+// Whether a block instance (key) covers the block-relative tile (lx, ly), and
+// how many tiles it covers before that one in the block's row-major order.
+__device__ __forceinline__ void block_entry(uint32_t key, uint32_t lx, uint32_t ly, bool valid, bool& keep,
+                                            uint32_t& before) {
+  const uint32_t rx0 = (key >> 16) & 15u, rx1 = (key >> 20) & 15u, ry0 = (key >> 24) & 15u, ry1 = key >> 28;
+  keep = valid && rx0 <= lx && lx < rx1 && ry0 <= ly && ly < ry1;
+  const uint32_t ye = min(ry1, ly), xe = min(rx1, lx);
+  uint32_t b = (ye > ry0 ? ye - ry0 : 0u) * (rx1 - rx0);
+  if (ry0 <= ly && ly < ry1) b += xe > rx0 ? xe - rx0 : 0u;
+  before = valid ? b : 0u;
+}
+
+// (five workgroups per CU, so that a 640x480 view's 1200 tiles are resident at once)
+__global__ void __launch_bounds__(kTileSortThreads) __attribute__((amdgpu_waves_per_eu(5))) block_tile_sort_kernel(
+    const ViewDesc* __restrict__ views, int num_views, int64_t num_tiles, BlockGeo geo,
+    const uint4* __restrict__ table, const uint32_t* __restrict__ bkeys, const uint32_t* __restrict__ bvals,
+    const uint32_t* __restrict__ zkey, uint32_t num_splats, int64_t capacity, uint32_t* __restrict__ keys,
+    uint32_t* __restrict__ vals, uint32_t* __restrict__ keys_alt, uint32_t* __restrict__ vals_alt,
+    uint2* __restrict__ ranges, uint32_t* __restrict__ overflow) {
+  __shared__ TileSortShared S;
+  __shared__ unsigned long long s_mask[kBlockRows][kTileSortWaves];
+  __shared__ uint32_t s_rowbase[kBlockRows + 1];
+  __shared__ uint32_t s_red[2][kTileSortWaves];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  for (int64_t tile = blockIdx.x; tile < num_tiles; tile += gridDim.x) {
+    __syncthreads();    // the previous tile's LDS is free
+    int view = 0;
+    while (view + 1 < num_views && tile >= views[view + 1].tile_offset) ++view;
+    const ViewDesc& V = views[view];
+    const uint32_t lt = (uint32_t)(tile - V.tile_offset);
+    const uint32_t ty = lt / (uint32_t)V.tiles_x, tx = lt - ty * (uint32_t)V.tiles_x;
+    const uint32_t bx = tx >> geo.bwl, by = ty >> geo.bhl;
+    const uint32_t lx = tx - (bx << geo.bwl), ly = ty - (by << geo.bhl);
+    const uint4 T = table[(uint32_t)V.block_offset + by * (uint32_t)V.blocks_x + bx];
+    const uint32_t start = T.x;
+    const int m = (int)(T.y - T.x);
+    const int nrows = (m + kTileSortThreads - 1) / kTileSortThreads;
+    // pass 1: the tile's count and its offset within the block; the keep
+    // masks of the first kBlockRows rows
+    uint32_t cnt = 0, pre = 0;
+    for (int r0 = 0; r0 < nrows; r0 += kBlockLoads) {
+      uint32_t kk[kBlockLoads];
+#pragma unroll
+      for (int q = 0; q < kBlockLoads; ++q) {
+        const int e = (r0 + q) * kTileSortThreads + tid;
+        kk[q] = bkeys[start + (e < m ? e : 0)];
+      }
+#pragma unroll
+      for (int q = 0; q < kBlockLoads; ++q) {
+        const int r = r0 + q;
+        if (r >= nrows) break;
+        bool keep;
+        uint32_t before;
+        block_entry(kk[q], lx, ly, r * kTileSortThreads + tid < m, keep, before);
+        cnt += keep ? 1u : 0u;
+        pre += before;
+        const uint64_t bal = __ballot(keep);
+        if (r < kBlockRows && lane == 0) s_mask[r][wave] = bal;
+      }
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+      cnt += __shfl_xor(cnt, d, 64);
+      pre += __shfl_xor(pre, d, 64);
+    }
+    if (lane == 0) {
+      s_red[0][wave] = cnt;
+      s_red[1][wave] = pre;
+    }
+    __syncthreads();
+    uint32_t n = 0, P = 0;
+#pragma unroll
+    for (int w = 0; w < kTileSortWaves; ++w) {
+      n += s_red[0][w];
+      P += s_red[1][w];
+    }
+    const uint32_t off = T.z + P;
+    if ((int64_t)off + n > capacity) {
+      if (tid == 0) {
+        atomicOr(overflow, 1u);
+        ranges[tile] = make_uint2(0u, 0u);
+      }
+      continue;
+    }
+    if (tid == 0) ranges[tile] = make_uint2(off, off + n);
+    if (n == 0) continue;
+    const bool in_lds = n <= (uint32_t)kTileSortCap;
+    // pass 2: each kept entry to its position, in LDS (short lists) or at
+    // its place in vals (long ones), segment by segment of kBlockRows rows
+    uint32_t segbase = 0;
+    for (int rb = 0; rb < nrows; rb += kBlockRows) {
+      const int rn = min(kBlockRows, nrows - rb);
+      if (rb > 0) {
+        __syncthreads();   // the previous segment's masks are consumed
+        for (int r0 = 0; r0 < rn; r0 += kBlockLoads) {
+          uint32_t kk[kBlockLoads];
+#pragma unroll
+          for (int q = 0; q < kBlockLoads; ++q) {
+            const int e = (rb + r0 + q) * kTileSortThreads + tid;
+            kk[q] = bkeys[start + (e < m ? e : 0)];
+          }
+#pragma unroll
+          for (int q = 0; q < kBlockLoads; ++q) {
+            if (r0 + q >= rn) break;
+            bool keep;
+            uint32_t before;
+            block_entry(kk[q], lx, ly, (rb + r0 + q) * kTileSortThreads + tid < m, keep, before);
+            const uint64_t bal = __ballot(keep);
+            if (lane == 0) s_mask[r0 + q][wave] = bal;
+          }
         }
-        // exclusive scan of the totals over the 256 digits (one per thread)
-        uint32_t x = acc;
+      }
+      __syncthreads();
+      if (wave == 0) {
+        uint32_t t = 0;
+        if (lane < rn)
+#pragma unroll
+          for (int w = 0; w < kTileSortWaves; ++w) t += (uint32_t)__popcll(s_mask[lane][w]);
+        uint32_t x = t;
 #pragma unroll
         for (int dd = 1; dd < 64; dd <<= 1) {
           const uint32_t y = __shfl_up(x, dd, 64);
           if (lane >= dd) x += y;
         }
-        if (lane == 63) s_wsum[wave] = x;
-        __syncthreads();
-        uint32_t base = 0;
-        for (int w = 0; w < wave; ++w) base += s_wsum[w];
-        s_start[tid] = base + x - acc;
-        __syncthreads();
-        const int dst = (pass + 1) & 1;
-#pragma unroll
-        for (int r = 0; r < kTileSortRows; ++r) {
-          if (off[r] == 0xFFFFFFFFu) continue;
-          const uint32_t d = (k[r] >> shift) & 255u;
-          const uint32_t pos = s_start[d] + wcnt[wave][d] + off[r];
-          if (pos < (uint32_t)n) {     // always, when the counts are right; never outside the list
-            s_k[dst][pos] = k[r];
-            s_v[dst][pos] = v[r];
-          }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < kTileSortRows; ++r) {
-          const int e = wave * (64 * kTileSortRows) + r * 64 + lane;
-          if (e < n) {
-            k[r] = s_k[dst][e];
-            v[r] = s_v[dst][e];
-          }
-        }
-        __syncthreads();
+        if (lane < rn) s_rowbase[lane] = segbase + x - t;
+        if (lane == 63) s_rowbase[kBlockRows] = segbase + x;
       }
-      // the fourth pass left the list in s_k[0], s_v[0]
-      if (TIES) order_equal_depths(s_k[0], s_v[0], n);
+      __syncthreads();
+      for (int r0 = 0; r0 < rn; r0 += kBlockLoads) {
+        uint32_t vv[kBlockLoads];
+#pragma unroll
+        for (int q = 0; q < kBlockLoads; ++q) {
+          const int e = (rb + r0 + q) * kTileSortThreads + tid;
+          vv[q] = bvals[start + (e < m ? e : 0)];
+        }
+#pragma unroll
+        for (int q = 0; q < kBlockLoads; ++q) {
+          const int r = r0 + q;
+          if (r >= rn) break;
+          const uint64_t mk = s_mask[r][wave];
+          if (!((mk >> lane) & 1ull)) continue;
+          uint32_t pos = s_rowbase[r] + (uint32_t)__popcll(mk & lt_mask);
+          for (int w = 0; w < wave; ++w) pos += (uint32_t)__popcll(s_mask[r][w]);
+          if (pos < n) {   // always, when the masks are right
+            if (in_lds) S.v[0][pos] = vv[q];
+            else vals[off + pos] = vv[q];
+          }
+        }
+      }
+      segbase = s_rowbase[kBlockRows];
+    }
+    __syncthreads();
+    if (n < 2) {
+      if (tid == 0) vals[off] = S.v[0][0];
+      continue;
+    }
+    if (in_lds) {
+      uint32_t k[kTileSortRows], v[kTileSortRows];
 #pragma unroll
       for (int r = 0; r < kTileSortRows; ++r) {
         const int e = wave * (64 * kTileSortRows) + r * 64 + lane;
-        if (e < n) vals[rg.x + e] = s_v[0][e];
+        // (every position below n holds a splat index; the clamp keeps the
+        // depth-key gather in bounds regardless)
+        v[r] = min(S.v[0][e < (int)n ? e : 0], num_splats - 1u);
+      }
+#pragma unroll
+      for (int r = 0; r < kTileSortRows; ++r) k[r] = zkey[v[r]];
+#pragma unroll
+      for (int r = 0; r < kTileSortRows; ++r) {
+        const int e = wave * (64 * kTileSortRows) + r * 64 + lane;
+        if (e >= (int)n) {
+          v[r] = 0u;
+          k[r] = 0xFFFFFFFFu;
+        }
+      }
+      __syncthreads();   // every thread holds its entries before the passes reuse the buffers
+      lds_depth_sort(S, k, v, (int)n);
+#pragma unroll
+      for (int r = 0; r < kTileSortRows; ++r) {
+        const int e = wave * (64 * kTileSortRows) + r * 64 + lane;
+        if (e < (int)n) vals[off + e] = S.v[0][e];
       }
     } else {
-      // longer lists, through global memory: per pass, the digit totals of
-      // the whole list, then every chunk in list order scattered after the
-      // earlier chunks' entries of each digit; passes alternate between
-      // (keys, vals) and (keys_alt, vals_alt) over the tile's range
-      for (int pass = 0; pass < 4; ++pass) {
-        const int shift = 8 * pass;
-        const uint32_t* ks = (pass & 1) ? keys_alt : keys;
-        const uint32_t* vs = (pass & 1) ? vals_alt : vals;
-        uint32_t* kd = (pass & 1) ? keys : keys_alt;
-        uint32_t* vd = (pass & 1) ? vals : vals_alt;
-        // digit totals of the whole list (the ranking's counts, chunk by chunk)
-        uint32_t total = 0;
-        for (int c0 = 0; c0 < n; c0 += kTileSortCap) {
-          const int cn = min(kTileSortCap, n - c0);
-          // loads at in-bounds positions for every lane (the chunk's first
-          // entry past its end), masked afterwards
-#pragma unroll
-          for (int r = 0; r < kTileSortRows; ++r) {
-            const int e = wave * (64 * kTileSortRows) + r * 64 + lane;
-            const uint32_t at = rg.x + c0 + (e < cn ? e : 0);
-            k[r] = pass == 0 ? vs[at] : ks[at];
-          }
-          if (pass == 0) {
-#pragma unroll
-            for (int r = 0; r < kTileSortRows; ++r) k[r] = zkey[k[r]];
-          }
-#pragma unroll
-          for (int r = 0; r < kTileSortRows; ++r)
-            if (wave * (64 * kTileSortRows) + r * 64 + lane >= cn) k[r] = 0xFFFFFFFFu;
-          for (int w = 0; w < kTileSortWaves; ++w) wcnt[w][tid] = 0u;
-          __syncthreads();
-          tile_sort_rank(k, cn, shift, off, wcnt, wave, lane);
-          __syncthreads();
-          for (int w = 0; w < kTileSortWaves; ++w) total += wcnt[w][tid];
-          __syncthreads();
-        }
-        s_start[tid] = total;
-        __syncthreads();
-        {
-          const uint32_t acc = s_start[tid];
-          uint32_t x = acc;
-#pragma unroll
-          for (int dd = 1; dd < 64; dd <<= 1) {
-            const uint32_t y = __shfl_up(x, dd, 64);
-            if (lane >= dd) x += y;
-          }
-          if (lane == 63) s_wsum[wave] = x;
-          __syncthreads();
-          uint32_t base = 0;
-          for (int w = 0; w < wave; ++w) base += s_wsum[w];
-          __syncthreads();
-          s_start[tid] = base + x - acc;
-        }
-        __syncthreads();
-        for (int c0 = 0; c0 < n; c0 += kTileSortCap) {
-          const int cn = min(kTileSortCap, n - c0);
-#pragma unroll
-          for (int r = 0; r < kTileSortRows; ++r) {
-            const int e = wave * (64 * kTileSortRows) + r * 64 + lane;
-            const uint32_t at = rg.x + c0 + (e < cn ? e : 0);
-            v[r] = vs[at];
-            if (pass != 0) k[r] = ks[at];
-          }
-          if (pass == 0) {
-#pragma unroll
-            for (int r = 0; r < kTileSortRows; ++r) k[r] = zkey[v[r]];
-          }
-#pragma unroll
-          for (int r = 0; r < kTileSortRows; ++r) {
-            if (wave * (64 * kTileSortRows) + r * 64 + lane >= cn) {
-              v[r] = 0u;
-              k[r] = 0xFFFFFFFFu;
-            }
-          }
-          for (int w = 0; w < kTileSortWaves; ++w) wcnt[w][tid] = 0u;
-          __syncthreads();
-          tile_sort_rank(k, cn, shift, off, wcnt, wave, lane);
-          __syncthreads();
-          uint32_t acc = 0;
-          for (int w = 0; w < kTileSortWaves; ++w) {
-            const uint32_t c = wcnt[w][tid];
-            wcnt[w][tid] = acc;
-            acc += c;
-          }
-          __syncthreads();
-#pragma unroll
-          for (int r = 0; r < kTileSortRows; ++r) {
-            if (off[r] == 0xFFFFFFFFu) continue;
-            const uint32_t d = (k[r] >> shift) & 255u;
-            const uint32_t pos = s_start[d] + wcnt[wave][d] + off[r];
-            if (pos < (uint32_t)n) {   // always, when the counts are right; never outside the tile's range
-              kd[rg.x + pos] = k[r];
-              vd[rg.x + pos] = v[r];
-            }
-          }
-          __syncthreads();
-          s_start[tid] += acc;          // this chunk's entries of each digit precede the next chunk's
-          __syncthreads();
-        }
-      }
-      // four passes end in (keys, vals); the keys held depth bits: order
-      // equal depths, then restore the tile key
-      __syncthreads();
-      if (TIES) order_equal_depths(keys + rg.x, vals + rg.x, n);
-      for (int e = tid; e < n; e += kTileSortThreads) keys[rg.x + e] = (uint32_t)tile;
+      global_depth_sort(S, make_uint2(off, off + n), (int)n, (uint32_t)tile, false, zkey, keys, vals, keys_alt,
+                        vals_alt);
     }
-    __syncthreads();
   }
 }
 
@@ -1441,8 +1791,25 @@ void launch_compact_scan(const uint32_t* ntiles, int64_t n, uint32_t* vals, uint
   }
   const int nb = blocks_for(n, kScanChunk);
   unsigned long long* status = reinterpret_cast<unsigned long long*>(scratch);
-  compact_scan_kernel<<<nb, kScanThreads, 0, st>>>(ntiles, n, vals, offsets, count_out, total_out, status, err,
-                                                   block_rank, (capacity + kEmitBlock - 1) / kEmitBlock);
+  compact_scan_kernel<false><<<nb, kScanThreads, 0, st>>>(ntiles, n, vals, offsets, count_out, total_out, status, err,
+                                                          block_rank, (capacity + kEmitBlock - 1) / kEmitBlock, nullptr,
+                                                          BlockGeo{}, nullptr);
+}
+
+void launch_compact_scan_blocks(const uint32_t* ntiles, const int4* rect, const BlockGeo& geo, int64_t n,
+                                uint32_t* vals, uint32_t* offsets, uint32_t* count_out, uint32_t* block_total,
+                                uint32_t* tile_total, uint32_t* scratch, uint32_t* err, uint32_t* block_rank,
+                                int64_t capacity, hipStream_t st) {
+  if (n == 0) {
+    fill_u32_kernel<<<1, 64, 0, st>>>(count_out, 0u, 1);
+    fill_u32_kernel<<<1, 64, 0, st>>>(block_total, 0u, 1);
+    return;
+  }
+  const int nb = blocks_for(n, kScanChunk);
+  unsigned long long* status = reinterpret_cast<unsigned long long*>(scratch);
+  compact_scan_kernel<true><<<nb, kScanThreads, 0, st>>>(ntiles, n, vals, offsets, count_out, block_total, status, err,
+                                                         block_rank, (capacity + kEmitBlock - 1) / kEmitBlock, rect,
+                                                         geo, tile_total);
 }
 
 void launch_compact_visible(const uint32_t* ntiles, const uint32_t* keys, int64_t n, uint32_t* out_keys,
@@ -1538,15 +1905,38 @@ void launch_emit(const uint32_t* sorted_s, const uint32_t* offsets, const uint32
   const int64_t nblocks = (capacity + kEmitBlock - 1) / kEmitBlock;
   if (nblocks == 0) {
     // no instance slot: only the overflow flag can be raised
-    emit_kernel<<<1, kEmitThreads, 0, st>>>(sorted_s, offsets, total_dev, count_dev, block_rank, splats, count, keys,
-                                            vals, capacity, overflow, nullptr, rb, hp);
+    emit_kernel<false><<<1, kEmitThreads, 0, st>>>(sorted_s, offsets, total_dev, count_dev, block_rank, splats, count,
+                                                   keys, vals, capacity, overflow, nullptr, rb, hp, nullptr, nullptr,
+                                                   1u, BlockGeo{}, nullptr);
     return;
   }
   if (!plan_ready)
     emit_plan_kernel<<<grid_cap(count, 256), 256, 0, st>>>(offsets, total_dev, count_dev, count, nblocks, block_rank);
-  emit_kernel<<<(unsigned)nblocks, kEmitThreads, 0, st>>>(sorted_s, offsets, total_dev, count_dev, block_rank, splats,
-                                                          count, keys, vals, capacity, overflow, fits ? hist : nullptr,
-                                                          rb, hp);
+  emit_kernel<false><<<(unsigned)nblocks, kEmitThreads, 0, st>>>(sorted_s, offsets, total_dev, count_dev, block_rank,
+                                                                 splats, count, keys, vals, capacity, overflow,
+                                                                 fits ? hist : nullptr, rb, hp, nullptr, nullptr, 1u,
+                                                                 BlockGeo{}, nullptr);
+}
+
+void launch_emit_blocks(const uint32_t* visible, const uint32_t* offsets, const uint32_t* total_dev,
+                        const uint32_t* count_dev, const int4* rect, const ViewDesc* views, int64_t num,
+                        const BlockGeo& geo, int64_t count, uint32_t* keys, uint32_t* vals, int64_t capacity,
+                        uint32_t* overflow, uint32_t* hist, uint32_t* whist, uint32_t* block_rank, bool plan_ready,
+                        hipStream_t st) {
+  if (count == 0) return;
+  const int64_t nblocks = (capacity + kEmitBlock - 1) / kEmitBlock;
+  const uint32_t n32 = (uint32_t)(num > 0 ? num : 1);
+  if (nblocks == 0) {
+    emit_kernel<true><<<1, kEmitThreads, 0, st>>>(visible, offsets, total_dev, count_dev, block_rank, nullptr, count,
+                                                  keys, vals, capacity, overflow, nullptr, 8, 1, rect, views, n32, geo,
+                                                  nullptr);
+    return;
+  }
+  if (!plan_ready)
+    emit_plan_kernel<<<grid_cap(count, 256), 256, 0, st>>>(offsets, total_dev, count_dev, count, nblocks, block_rank);
+  emit_kernel<true><<<(unsigned)nblocks, kEmitThreads, 0, st>>>(visible, offsets, total_dev, count_dev, block_rank,
+                                                                nullptr, count, keys, vals, capacity, overflow, hist, 8,
+                                                                1, rect, views, n32, geo, whist);
 }
 
 bool emit_histogram_fits(int bits) {
@@ -1624,6 +2014,41 @@ void launch_tile_depth_sort(const uint2* ranges, int64_t num_tiles, const uint32
   else
     tile_depth_sort_kernel<true><<<grid, kTileSortThreads, 0, st>>>(ranges, num_tiles, zkey, keys, vals, keys_alt,
                                                                      vals_alt);
+}
+
+// Binning by blocks: the one pass over the block ids runs 1024 keys per
+// workgroup (a few hundred thousand keys at the benchmark sizes).
+constexpr int kBlockSortItems = 4;
+constexpr int kBlockSortChunk = kSortThreads * kBlockSortItems;
+
+int64_t block_sort_scratch_elems(int64_t n) {
+  const int64_t nb = blocks_for(n > 0 ? n : 1, kBlockSortChunk);
+  return nb * kMaxBlocks + (int64_t)kHistCopies * kMaxBlocks;
+}
+
+uint32_t* block_sort_hist(uint32_t* scratch, int64_t n) {
+  return scratch + (int64_t)blocks_for(n > 0 ? n : 1, kBlockSortChunk) * kMaxBlocks;
+}
+
+void launch_block_sort(const uint32_t* keys, const uint32_t* vals, const uint32_t* n_dev, int64_t n, int nblocks,
+                       uint32_t* scratch, const uint32_t* whist, uint4* table, uint32_t* err, uint32_t* keys_out,
+                       uint32_t* vals_out, hipStream_t st) {
+  const int nb = blocks_for(n > 0 ? n : 1, kBlockSortChunk);
+  const int dbits = bits_for_blocks(nblocks);
+  onesweep_pass_kernel<8, kBlockSortItems, false, true><<<nb, kSortThreads, 0, st>>>(
+      keys, vals, n_dev, n, 0, dbits, block_sort_hist(scratch, n), kMaxBlocks, scratch, err, keys_out, vals_out, whist,
+      table);
+}
+
+void launch_block_tile_sort(const ViewDesc* views, int num_views, int64_t num_tiles, const BlockGeo& geo,
+                            const uint4* table, const uint32_t* bkeys, const uint32_t* bvals, const uint32_t* zkey,
+                            int64_t num_splats, int64_t capacity, uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
+                            uint32_t* vals_alt, uint2* ranges, uint32_t* overflow, hipStream_t st) {
+  if (num_tiles == 0 || num_splats == 0) return;
+  const unsigned grid = (unsigned)(num_tiles < 65536 ? num_tiles : 65536);
+  block_tile_sort_kernel<<<grid, kTileSortThreads, 0, st>>>(views, num_views, num_tiles, geo, table, bkeys, bvals,
+                                                           zkey, (uint32_t)num_splats, capacity, keys, vals, keys_alt,
+                                                           vals_alt, ranges, overflow);
 }
 
 void launch_tile_order(const uint2* ranges, int64_t num_tiles, uint32_t* order, hipStream_t st) {

@@ -202,6 +202,63 @@ def test_tile_list_counting_binning(gpu, orc, case):
             assert torch.equal(a, b)
 
 
+def block_case(case):
+    """(scene, params, cameras, tile size) of the block-binning tests."""
+    if case == "huge":
+        # 9000 Gaussians over a 64x48 view: twelve 1x1-tile blocks whose lists
+        # (about 9000 entries) take two rounds of keep masks, and every tile
+        # list passes the per-tile sort's LDS capacity
+        s = scenes.tiny_random(41, n=9000, width=64, height=48)
+        p = s.params.copy()
+        p[3:6] = np.log(0.5)
+        return s, p, s.cameras, 16
+    if case == "ragged8x8":
+        # 8x8 tiles on 200x150: 475 tiles, so blocks of 2x1 tiles, the last
+        # block column and tile row ragged
+        s = scenes.tiny_random(42, n=2500, width=200, height=150)
+        return s, s.params, s.cameras, 8
+    if case == "multiview8x8":
+        # three 160x120 views at 8x8 (900 tiles): 2x2-tile blocks, ragged
+        # rows, one view looking away from the scene
+        s = scenes.tiny_random(43, n=1500, width=160, height=120)
+        cams = [s.cameras[0], scenes.look_at_camera([0.2, -0.1, -0.3], [0.1, 0.0, 2.0], 160, 120, 140.0),
+                scenes.look_at_camera([0.0, 0.0, 0.0], [0.0, 0.0, -5.0], 160, 120, 140.0)]
+        return s, s.params, cams, 8
+    s, p = depth_case(case)
+    return s, p, s.cameras, 16
+
+
+@pytest.mark.parametrize("case", ["none", "all", "mixed", "huge", "ragged8x8", "multiview8x8"])
+def test_tile_list_block_binning(gpu, orc, case):
+    """Binning by blocks of tiles (option binning = 3; what the automatic
+    choice takes for the per-tile depth order): one instance per (splat,
+    block), one pass over the block ids, each tile's list filtered from its
+    block's and sorted by depth. Lists bit-exact against the oracle, with
+    block lists long enough for two rounds of keep masks ("huge"), lists past
+    the LDS capacity, ragged blocks and several views; images bit-identical
+    to the radix binning's (option 2)."""
+    s, p, cams, t = block_case(case)
+    say("block binning", case)
+    R = make(gpu, binning=3, depth_sort=1, tile_w=t, tile_h=t)
+    outs = R.render(to_dev(p), s.sh_degree, cams)
+    torch.cuda.synchronize()
+    t_gpu, g_gpu = R.instances()
+    t_ref, g_ref = orc.tile_list(p, s.sh_degree, cams, t, t)
+    counts = np.bincount(t_ref.astype(np.int64))
+    say("instances", len(t_ref), "longest list", int(counts.max()) if len(counts) else 0)
+    if case == "huge":
+        assert counts.max() > 8192 and counts.min() > 1536
+    assert len(t_gpu) == len(t_ref)
+    assert np.array_equal(t_gpu, t_ref) and np.array_equal(g_gpu, g_ref)
+    assert R.status()["instances"] == len(t_ref)
+    O = make(gpu, binning=2, depth_sort=1, tile_w=t, tile_h=t)
+    other = O.render(to_dev(p), s.sh_degree, cams)
+    torch.cuda.synchronize()
+    for v in range(len(cams)):
+        for a, b in zip(outs[v], other[v]):
+            assert torch.equal(a, b)
+
+
 def ring_cameras(count, seed):
     """`count` small cameras on a ring around the tiny scenes' volume (z in
     [1, 3]); every seventh looks away from it, so that it culls everything."""
