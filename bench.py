@@ -164,6 +164,8 @@ def binning_used(R, num, cams):
                          for tx, ty in tiles) for w in range(4) if 0 <= area - w <= 3}
             fits = [w for w, n in nb.items() if n <= 256]
             if fits:
+                if area == 0 and R.binning == 0:
+                    break                           # single-tile blocks: automatic takes the radix path
                 w = min(fits, key=lambda w: (abs(2 * w - area), nb[w]))
                 h = area - w
                 return f"blocks of {1 << w}x{1 << h} tiles, one pass over block ids, per-tile filter and depth sort"

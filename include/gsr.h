@@ -109,8 +109,8 @@ typedef struct {
                                Gaussian); the lists are walked whole, so chunk_len and
                                fuse_blend do not apply). Same gradient up to float summation
                                order. */
-  int32_t binning;          /* grouping of the instances by tile: 0 = automatic (3 where it applies,
-                               else 2), 1 = by counting where each tile's list is sorted by
+  int32_t binning;          /* grouping of the instances by tile: 0 = automatic (3 where it applies
+                               with blocks of at least two tiles, else 2), 1 = by counting where each tile's list is sorted by
                                depth afterwards and every view has at most 8192 tiles
                                (per-workgroup tile counts in LDS, one scan, a scatter; equal
                                depths then ordered by index), else as 2; 2 = emission of one

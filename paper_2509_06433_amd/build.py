@@ -77,3 +77,6 @@ def build(verbose: bool = False) -> str:
     os.replace(tmp, LIB)
     return LIB
 
+
+if __name__ == "__main__":
+    print(build(verbose="-v" in sys.argv[1:]))

@@ -47,8 +47,9 @@ int plan_render(gsr_ctx* ctx, const gsr_gaussians* g, int32_t nv, const gsr_came
 // binning 0 or 3). The block is the smallest (at most 8 x 8 tiles; then the
 // squarest, then the one giving fewer blocks) that leaves at most kMaxBlocks
 // blocks over all views, so that a single 8-bit radix pass groups the block
-// instances. Smaller blocks mean shorter block lists for every tile to
-// filter, larger ones fewer block instances.
+// instances; the automatic choice also wants it to cover at least two
+// tiles. Smaller blocks mean shorter block lists for every tile to filter,
+// larger ones fewer block instances.
 void plan_blocks(const gsr_ctx* ctx, RenderPlan& P) {
   P.use_blocks = false;
   P.blocks = BlockGeo{};
@@ -75,7 +76,9 @@ void plan_blocks(const gsr_ctx* ctx, RenderPlan& P) {
       }
     }
   }
-  if (bw < 0) return;
+  // single-tile blocks: as many block instances as tile instances, and the
+  // per-tile filter on top; the automatic choice takes the radix path then
+  if (bw < 0 || (bw + bh == 0 && ctx->binning == 0)) return;
   int32_t off = 0;
   for (ViewDesc& v : P.views) {
     v.block_offset = off;
@@ -426,7 +429,8 @@ static int launch_blend_front(gsr_ctx* ctx, Buffers& B, RenderPlan& P, hipStream
     int64_t m = 0;
     int mt = 0;
     const bool counted = use_bins(ctx, B, P, &m, &mt);   // the lists are not in index order then
-    launch_tile_depth_sort(as<uint2>(B.ranges), P.ntiles, as<uint32_t>(B.zkey), ik, iv, ika, iva, !counted, st);
+    launch_tile_depth_sort(as<uint2>(B.ranges), P.ntiles, as<uint32_t>(B.zkey), P.total, ik, iv, ika, iva, !counted,
+                           st);
   }
   CHECK_LAUNCH(ctx);
   P.inst_keys = ik;

@@ -266,6 +266,10 @@ __device__ __forceinline__ uint32_t forward_tile(const BlendArgs& a, FwdShared<T
         bool cl;
         ok_a[i] = pair_alpha(qa0, qa1, xs, ys[i], dx, dy, G, al_a[i], cl);
         ok_b[i] = pair_alpha(qb0, qb1, xs, ys[i], dx, dy, G, al_b[i], cl);
+        // both alphas are formed before the first per-lane branch, so that
+        // the two exponentials' latencies overlap (without this the compiler
+        // sinks the second one past the first Gaussian's update)
+        __asm__ volatile("" ::"v"(al_a[i]), "v"(al_b[i]));
       }
       const float4 qa2 = s_q2[k], qb2 = s_q2[k + 1];
 #pragma unroll
@@ -618,9 +622,12 @@ __device__ __forceinline__ void backward_unit(const BlendArgs& a, BwdShared<TW *
       for (int i = 0; i < PPT; ++i) {
         float dxa, dya, Ga, ala, dxb, dyb, Gb, alb;
         bool cla, clb;
-        const bool oka = la && pair_alpha(qa0, qa1, xs, ys[i], dxa, dya, Ga, ala, cla) && (lbase + k < mylast[i]);
-        const bool okb =
-            lb && pair_alpha(qb0, qb1, xs, ys[i], dxb, dyb, Gb, alb, clb) && (lbase + k - 1 < mylast[i]);
+        // both alphas unconditionally (positions past the wave's walk are
+        // masked below), so that the two exponentials' latencies overlap
+        const bool pa = pair_alpha(qa0, qa1, xs, ys[i], dxa, dya, Ga, ala, cla);
+        const bool pb = pair_alpha(qb0, qb1, xs, ys[i], dxb, dyb, Gb, alb, clb);
+        const bool oka = la && pa && (lbase + k < mylast[i]);
+        const bool okb = lb && pb && (lbase + k - 1 < mylast[i]);
         ca = ca || oka;
         cb = cb || okb;
         okA[i] = oka; okB[i] = okb;

@@ -292,8 +292,8 @@ void launch_tile_balance(const uint2* ranges, const uint32_t* tile_last, int64_t
 // equal depths are put in index order afterwards. keys/vals: the
 // tile-grouped instances; keys_alt/vals_alt: scratch of the same size (tiles
 // of more than 1536 instances go through it).
-void launch_tile_depth_sort(const uint2* ranges, int64_t num_tiles, const uint32_t* zkey, uint32_t* keys,
-                            uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, bool index_order,
+void launch_tile_depth_sort(const uint2* ranges, int64_t num_tiles, const uint32_t* zkey, int64_t num_splats,
+                            uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, bool index_order,
                             hipStream_t st);
 
 // Zeroes up to kMaxClear segments of 32-bit words in one launch.

@@ -1314,9 +1314,9 @@ __device__ __forceinline__ void lds_depth_sort(TileSortShared& S, uint32_t (&k)[
 // range, and the list arrives in vals (its keys are scratch). Ends with the
 // tile key in keys over the range.
 __device__ __forceinline__ void global_depth_sort(TileSortShared& S, uint2 rg, int n, uint32_t tile, bool ties,
-                                  const uint32_t* __restrict__ zkey, uint32_t* __restrict__ keys,
-                                  uint32_t* __restrict__ vals, uint32_t* __restrict__ keys_alt,
-                                  uint32_t* __restrict__ vals_alt) {
+                                                  const uint32_t* __restrict__ zkey, uint32_t num_splats,
+                                                  uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                                                  uint32_t* __restrict__ keys_alt, uint32_t* __restrict__ vals_alt) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   uint32_t k[kTileSortRows], v[kTileSortRows], off[kTileSortRows];
   for (int pass = 0; pass < 4; ++pass) {
@@ -1338,8 +1338,10 @@ __device__ __forceinline__ void global_depth_sort(TileSortShared& S, uint2 rg, i
         k[r] = pass == 0 ? vs[at] : ks[at];
       }
       if (pass == 0) {
+        // (the list holds splat indices; the clamp keeps the gather in
+        // bounds regardless)
 #pragma unroll
-        for (int r = 0; r < kTileSortRows; ++r) k[r] = zkey[k[r]];
+        for (int r = 0; r < kTileSortRows; ++r) k[r] = zkey[min(k[r], num_splats - 1u)];
       }
 #pragma unroll
       for (int r = 0; r < kTileSortRows; ++r)
@@ -1380,7 +1382,7 @@ __device__ __forceinline__ void global_depth_sort(TileSortShared& S, uint2 rg, i
       }
       if (pass == 0) {
 #pragma unroll
-        for (int r = 0; r < kTileSortRows; ++r) k[r] = zkey[v[r]];
+        for (int r = 0; r < kTileSortRows; ++r) k[r] = zkey[min(v[r], num_splats - 1u)];
       }
 #pragma unroll
       for (int r = 0; r < kTileSortRows; ++r) {
@@ -1426,7 +1428,7 @@ __device__ __forceinline__ void global_depth_sort(TileSortShared& S, uint2 rg, i
 // binning): equal depths are put in index order after the passes.
 template <bool TIES>
 __global__ void __launch_bounds__(kTileSortThreads) tile_depth_sort_kernel(
-    const uint2* __restrict__ ranges, int64_t num_tiles, const uint32_t* __restrict__ zkey,
+    const uint2* __restrict__ ranges, int64_t num_tiles, const uint32_t* __restrict__ zkey, uint32_t num_splats,
     uint32_t* __restrict__ keys, uint32_t* __restrict__ vals, uint32_t* __restrict__ keys_alt,
     uint32_t* __restrict__ vals_alt) {
   __shared__ TileSortShared S;
@@ -1447,7 +1449,7 @@ __global__ void __launch_bounds__(kTileSortThreads) tile_depth_sort_kernel(
         v[r] = vals[rg.x + (e < n ? e : 0)];
       }
 #pragma unroll
-      for (int r = 0; r < kTileSortRows; ++r) k[r] = zkey[v[r]];
+      for (int r = 0; r < kTileSortRows; ++r) k[r] = zkey[min(v[r], num_splats - 1u)];
 #pragma unroll
       for (int r = 0; r < kTileSortRows; ++r) {
         const int e = wave * (64 * kTileSortRows) + r * 64 + lane;
@@ -1465,7 +1467,7 @@ __global__ void __launch_bounds__(kTileSortThreads) tile_depth_sort_kernel(
         if (e < n) vals[rg.x + e] = S.v[0][e];
       }
     } else {
-      global_depth_sort(S, rg, n, (uint32_t)tile, TIES, zkey, keys, vals, keys_alt, vals_alt);
+      global_depth_sort(S, rg, n, (uint32_t)tile, TIES, zkey, num_splats, keys, vals, keys_alt, vals_alt);
     }
     __syncthreads();
   }
@@ -1671,8 +1673,8 @@ __global__ void __launch_bounds__(kTileSortThreads) __attribute__((amdgpu_waves_
         if (e < (int)n) vals[off + e] = S.v[0][e];
       }
     } else {
-      global_depth_sort(S, make_uint2(off, off + n), (int)n, (uint32_t)tile, false, zkey, keys, vals, keys_alt,
-                        vals_alt);
+      global_depth_sort(S, make_uint2(off, off + n), (int)n, (uint32_t)tile, false, zkey, num_splats, keys, vals,
+                        keys_alt, vals_alt);
     }
   }
 }
@@ -2003,16 +2005,17 @@ void launch_tile_ranges(const uint32_t* keys, const uint32_t* n_dev, int64_t cou
 }
 
 
-void launch_tile_depth_sort(const uint2* ranges, int64_t num_tiles, const uint32_t* zkey, uint32_t* keys,
-                            uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, bool index_order,
+void launch_tile_depth_sort(const uint2* ranges, int64_t num_tiles, const uint32_t* zkey, int64_t num_splats,
+                            uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, bool index_order,
                             hipStream_t st) {
-  if (num_tiles == 0) return;
+  if (num_tiles == 0 || num_splats == 0) return;
   const unsigned grid = (unsigned)(num_tiles < 65536 ? num_tiles : 65536);
+  const uint32_t ns = (uint32_t)num_splats;
   if (index_order)
-    tile_depth_sort_kernel<false><<<grid, kTileSortThreads, 0, st>>>(ranges, num_tiles, zkey, keys, vals, keys_alt,
+    tile_depth_sort_kernel<false><<<grid, kTileSortThreads, 0, st>>>(ranges, num_tiles, zkey, ns, keys, vals, keys_alt,
                                                                       vals_alt);
   else
-    tile_depth_sort_kernel<true><<<grid, kTileSortThreads, 0, st>>>(ranges, num_tiles, zkey, keys, vals, keys_alt,
+    tile_depth_sort_kernel<true><<<grid, kTileSortThreads, 0, st>>>(ranges, num_tiles, zkey, ns, keys, vals, keys_alt,
                                                                      vals_alt);
 }
 
