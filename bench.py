@@ -60,13 +60,16 @@ PLAIN_OPS_PER_PAIR_FUSED = PLAIN_OPS_PER_PAIR_FWD + PLAIN_OPS_PER_PAIR_BWD
 
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (profiles/mapping_iteration_<workload>.txt), each scaled by what
-# the counter reads for a 256 MiB device copy (FETCH x2.0, WRITE x1.0). An
-# entry is removed whenever its kernel changes.
+# the counter reads for a 256 MiB device copy (FETCH x2.0, WRITE x1.0), for
+# the launch configuration profiled there (16x16 tiles, one pixel per
+# thread, the default batch depth). An entry is removed whenever its kernel
+# changes.
 TRAFFIC = {
-    ("keyframe_640x480_200k", "blend"): (82.400e6, 84.883e6),   # read, write
-    ("batch8_640x480_500k", "blend_bwd"): (613.594e6, 815.010e6),
-    ("mixed16_2M_sh3", "blend_bwd"): (775.333e6, 1089.567e6),
+    ("keyframe_640x480_200k", "blend"): (79.606e6, 84.883e6),   # read, write
+    ("batch8_640x480_500k", "blend_bwd"): (622.307e6, 815.010e6),
+    ("mixed16_2M_sh3", "blend_bwd"): (1372.026e6, 1915.826e6),
 }
+PROFILED_CONFIG = (16, 16, 1, 0)   # tile_w, tile_h, pixels per thread, batch depth
 
 
 def parse():
@@ -300,6 +303,8 @@ def main():
             print(f"warning: {mst['skipped']} iterations skipped for instance overflow", file=sys.stderr)
     pairs, visible = R.count_work(len(cams))
     dom_avg_ms = dom_ms / max(args.steps, 1)     # one launch per step in graph mode
+    traffic_known = ((scene.name, dominant) in TRAFFIC and
+                     (R.tile_w, R.tile_h, R.pixels_per_thread or 1, R.batch_depth) == PROFILED_CONFIG)
     ops_per_pair = {"blend_fwd": OPS_PER_PAIR_FWD, "blend_bwd": OPS_PER_PAIR_BWD, "blend": OPS_PER_PAIR_FUSED}[dominant]
     plain_per_pair = {"blend_fwd": PLAIN_OPS_PER_PAIR_FWD, "blend_bwd": PLAIN_OPS_PER_PAIR_BWD,
                       "blend": PLAIN_OPS_PER_PAIR_FUSED}[dominant]
@@ -398,9 +403,8 @@ def main():
                      "frac_published": round(achieved_plain / PEAK_FP32_PUBLISHED_TFLOPS, 4),
                      "published_peak": f"{PEAK_FP32_PUBLISHED_TFLOPS} TFLOP/s FP32 vector (packed FMA as 4 FLOPs); "
                                        f"{plain_per_pair:g} plain FP32 ops per pair",
-                     "traffic": (round(sum(TRAFFIC[(scene.name, dominant)])) if (scene.name, dominant) in TRAFFIC
-                                 else None),
-                     "traffic_read_write": TRAFFIC.get((scene.name, dominant)),
+                     "traffic": (round(sum(TRAFFIC[(scene.name, dominant)])) if traffic_known else None),
+                     "traffic_read_write": TRAFFIC.get((scene.name, dominant)) if traffic_known else None,
                      "avg_ms": round(dom_avg_ms, 4), "launches": dom_n, "pairs": pairs,
                      "ops_per_pair": ops_per_pair},
     }
