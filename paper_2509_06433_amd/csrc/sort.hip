@@ -1186,12 +1186,15 @@ constexpr int kTileSortWaves = kTileSortThreads / 64;
 constexpr int kTileSortRows = 6;
 constexpr int kTileSortCap = kTileSortThreads * kTileSortRows;            // 1536 entries per chunk
 
+// rpw: rows per wave in use (the chunk's entries spread evenly over the
+// waves, at most kTileSortRows; rows past it are neither ranked nor set).
 __device__ __forceinline__ void tile_sort_rank(const uint32_t* k, int n, int shift, uint32_t* off,
-                                               uint32_t (*wcnt)[256], int wave, int lane) {
+                                               uint32_t (*wcnt)[256], int wave, int lane, int rpw) {
   const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
   for (int r = 0; r < kTileSortRows; ++r) {
-    const int e = wave * (64 * kTileSortRows) + r * 64 + lane;
+    if (r >= rpw) break;
+    const int e = wave * (64 * rpw) + r * 64 + lane;
     const bool valid = e < n;
     const uint32_t d = (k[r] >> shift) & 255u;
     uint64_t mask = __ballot(valid);
@@ -1243,7 +1246,12 @@ __device__ void order_equal_depths(const uint32_t* k, uint32_t* v, int n) {
 
 // LDS of the per-tile depth sort.
 struct TileSortShared {
-  uint32_t k[2][kTileSortCap], v[2][kTileSortCap];
+  union {
+    struct {
+      uint32_t k[2][kTileSortCap], v[2][kTileSortCap];
+    };
+    uint32_t part[kTileSortWaves][kTileSortCap];   // per-wave staging of the block filter
+  };
   uint32_t wcnt[kTileSortWaves][256];
   uint32_t start[256];     // the digit's first position (whole list) plus earlier chunks' count
   uint32_t wsum[kTileSortWaves];
@@ -1254,14 +1262,14 @@ struct TileSortShared {
 // wave R 64 + 64 r + lane; entries past n hold key 0xFFFFFFFF). The sorted
 // list ends in S.k[0], S.v[0].
 __device__ __forceinline__ void lds_depth_sort(TileSortShared& S, uint32_t (&k)[kTileSortRows],
-                                               uint32_t (&v)[kTileSortRows], int n) {
+                                               uint32_t (&v)[kTileSortRows], int n, int rpw) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   uint32_t off[kTileSortRows];
   for (int pass = 0; pass < 4; ++pass) {
     const int shift = 8 * pass;
     for (int w = 0; w < kTileSortWaves; ++w) S.wcnt[w][tid] = 0u;
     __syncthreads();
-    tile_sort_rank(k, n, shift, off, S.wcnt, wave, lane);
+    tile_sort_rank(k, n, shift, off, S.wcnt, wave, lane, rpw);
     __syncthreads();
     // per digit: exclusive prefix over the waves, and the digit total
     uint32_t acc = 0;
@@ -1286,6 +1294,7 @@ __device__ __forceinline__ void lds_depth_sort(TileSortShared& S, uint32_t (&k)[
     const int dst = (pass + 1) & 1;
 #pragma unroll
     for (int r = 0; r < kTileSortRows; ++r) {
+      if (r >= rpw) break;
       if (off[r] == 0xFFFFFFFFu) continue;
       const uint32_t d = (k[r] >> shift) & 255u;
       const uint32_t pos = S.start[d] + S.wcnt[wave][d] + off[r];
@@ -1297,7 +1306,8 @@ __device__ __forceinline__ void lds_depth_sort(TileSortShared& S, uint32_t (&k)[
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kTileSortRows; ++r) {
-      const int e = wave * (64 * kTileSortRows) + r * 64 + lane;
+      if (r >= rpw) break;
+      const int e = wave * (64 * rpw) + r * 64 + lane;
       if (e < n) {
         k[r] = S.k[dst][e];
         v[r] = S.v[dst][e];
@@ -1306,6 +1316,9 @@ __device__ __forceinline__ void lds_depth_sort(TileSortShared& S, uint32_t (&k)[
     __syncthreads();
   }
 }
+
+// Rows per wave for a list of n <= kTileSortCap entries in LDS.
+__device__ __forceinline__ int lds_rows(int n) { return (n + kTileSortThreads - 1) / kTileSortThreads; }
 
 // A list longer than kTileSortCap, [rg.x, rg.x + n), sorted through global
 // memory: per pass, the digit totals of the whole list, then every chunk in
@@ -1348,7 +1361,7 @@ __device__ __forceinline__ void global_depth_sort(TileSortShared& S, uint2 rg, i
         if (wave * (64 * kTileSortRows) + r * 64 + lane >= cn) k[r] = 0xFFFFFFFFu;
       for (int w = 0; w < kTileSortWaves; ++w) S.wcnt[w][tid] = 0u;
       __syncthreads();
-      tile_sort_rank(k, cn, shift, off, S.wcnt, wave, lane);
+      tile_sort_rank(k, cn, shift, off, S.wcnt, wave, lane, kTileSortRows);
       __syncthreads();
       for (int w = 0; w < kTileSortWaves; ++w) total += S.wcnt[w][tid];
       __syncthreads();
@@ -1393,7 +1406,7 @@ __device__ __forceinline__ void global_depth_sort(TileSortShared& S, uint2 rg, i
       }
       for (int w = 0; w < kTileSortWaves; ++w) S.wcnt[w][tid] = 0u;
       __syncthreads();
-      tile_sort_rank(k, cn, shift, off, S.wcnt, wave, lane);
+      tile_sort_rank(k, cn, shift, off, S.wcnt, wave, lane, kTileSortRows);
       __syncthreads();
       uint32_t acc = 0;
       for (int w = 0; w < kTileSortWaves; ++w) {
@@ -1443,29 +1456,26 @@ __global__ void __launch_bounds__(kTileSortThreads) tile_depth_sort_kernel(
       // in bounds too): every row's id and key loads are in flight at once
       // rather than one guarded round trip after another
       uint32_t k[kTileSortRows], v[kTileSortRows];
+      const int rpw = lds_rows(n);
 #pragma unroll
       for (int r = 0; r < kTileSortRows; ++r) {
-        const int e = wave * (64 * kTileSortRows) + r * 64 + lane;
-        v[r] = vals[rg.x + (e < n ? e : 0)];
+        const int e = wave * (64 * rpw) + r * 64 + lane;
+        v[r] = vals[rg.x + (r < rpw && e < n ? e : 0)];
       }
 #pragma unroll
       for (int r = 0; r < kTileSortRows; ++r) k[r] = zkey[min(v[r], num_splats - 1u)];
 #pragma unroll
       for (int r = 0; r < kTileSortRows; ++r) {
-        const int e = wave * (64 * kTileSortRows) + r * 64 + lane;
-        if (e >= n) {
+        const int e = wave * (64 * rpw) + r * 64 + lane;
+        if (r >= rpw || e >= n) {
           v[r] = 0u;
           k[r] = 0xFFFFFFFFu;
         }
       }
-      lds_depth_sort(S, k, v, n);
+      lds_depth_sort(S, k, v, n, rpw);
       // the fourth pass left the list in S.k[0], S.v[0]
       if (TIES) order_equal_depths(S.k[0], S.v[0], n);
-#pragma unroll
-      for (int r = 0; r < kTileSortRows; ++r) {
-        const int e = wave * (64 * kTileSortRows) + r * 64 + lane;
-        if (e < n) vals[rg.x + e] = S.v[0][e];
-      }
+      for (int e = tid; e < n; e += kTileSortThreads) vals[rg.x + e] = S.v[0][e];
     } else {
       global_depth_sort(S, rg, n, (uint32_t)tile, TIES, zkey, num_splats, keys, vals, keys_alt, vals_alt);
     }
@@ -1526,35 +1536,38 @@ __global__ void __launch_bounds__(kTileSortThreads) __attribute__((amdgpu_waves_
     const uint4 T = table[(uint32_t)V.block_offset + by * (uint32_t)V.blocks_x + bx];
     const uint32_t start = T.x;
     const int m = (int)(T.y - T.x);
-    const int nrows = (m + kTileSortThreads - 1) / kTileSortThreads;
-    // pass 1: the tile's count and its offset within the block; the keep
-    // masks of the first kBlockRows rows
+    // one pass over the block's run: wave w takes rows [w wr, (w + 1) wr) of
+    // 64 entries, so the waves' kept entries, each wave's in run order at its
+    // running count in its part of LDS, concatenate in run order. Also the
+    // tile's offset within the block (the covered tiles before it).
+    const int wr = ((m + 63) / 64 + kTileSortWaves - 1) / kTileSortWaves;
     uint32_t cnt = 0, pre = 0;
-    for (int r0 = 0; r0 < nrows; r0 += kBlockLoads) {
-      uint32_t kk[kBlockLoads];
+    for (int r0 = 0; r0 < wr; r0 += kBlockLoads) {
+      uint32_t kk[kBlockLoads], vv[kBlockLoads];
 #pragma unroll
       for (int q = 0; q < kBlockLoads; ++q) {
-        const int e = (r0 + q) * kTileSortThreads + tid;
-        kk[q] = bkeys[start + (e < m ? e : 0)];
+        const int e = (wave * wr + r0 + q) * 64 + lane;
+        const uint32_t j = start + (r0 + q < wr && e < m ? (uint32_t)e : 0u);
+        kk[q] = bkeys[j];
+        vv[q] = bvals[j];
       }
 #pragma unroll
       for (int q = 0; q < kBlockLoads; ++q) {
-        const int r = r0 + q;
-        if (r >= nrows) break;
+        if (r0 + q >= wr) break;
         bool keep;
         uint32_t before;
-        block_entry(kk[q], lx, ly, r * kTileSortThreads + tid < m, keep, before);
-        cnt += keep ? 1u : 0u;
+        block_entry(kk[q], lx, ly, (wave * wr + r0 + q) * 64 + lane < m, keep, before);
         pre += before;
         const uint64_t bal = __ballot(keep);
-        if (r < kBlockRows && lane == 0) s_mask[r][wave] = bal;
+        const uint32_t pos = cnt + (uint32_t)__popcll(bal & lt_mask);
+        // (a part holds kTileSortCap entries: a list that fits the LDS sort
+        // never passes it; a longer one is compacted again below)
+        if (keep && pos < (uint32_t)kTileSortCap) S.part[wave][pos] = vv[q];
+        cnt += (uint32_t)__popcll(bal);
       }
     }
 #pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) {
-      cnt += __shfl_xor(cnt, d, 64);
-      pre += __shfl_xor(pre, d, 64);
-    }
+    for (int d = 32; d >= 1; d >>= 1) pre += __shfl_xor(pre, d, 64);
     if (lane == 0) {
       s_red[0][wave] = cnt;
       s_red[1][wave] = pre;
@@ -1576,13 +1589,46 @@ __global__ void __launch_bounds__(kTileSortThreads) __attribute__((amdgpu_waves_
     }
     if (tid == 0) ranges[tile] = make_uint2(off, off + n);
     if (n == 0) continue;
-    const bool in_lds = n <= (uint32_t)kTileSortCap;
-    // pass 2: each kept entry to its position, in LDS (short lists) or at
-    // its place in vals (long ones), segment by segment of kBlockRows rows
-    uint32_t segbase = 0;
-    for (int rb = 0; rb < nrows; rb += kBlockRows) {
-      const int rn = min(kBlockRows, nrows - rb);
-      if (rb > 0) {
+    if (n <= (uint32_t)kTileSortCap) {
+      // list position e lies in the part of the wave w with c_w <= e < c_{w+1}
+      const uint32_t c1 = s_red[0][0], c2 = c1 + s_red[0][1], c3 = c2 + s_red[0][2];
+      uint32_t k[kTileSortRows], v[kTileSortRows];
+      const int rpw = lds_rows((int)n);
+#pragma unroll
+      for (int r = 0; r < kTileSortRows; ++r) {
+        const uint32_t e = (uint32_t)(wave * (64 * rpw) + r * 64 + lane);
+        const uint32_t w = (e >= c1 ? 1u : 0u) + (e >= c2 ? 1u : 0u) + (e >= c3 ? 1u : 0u);
+        const uint32_t cw = w == 0 ? 0u : (w == 1 ? c1 : (w == 2 ? c2 : c3));
+        // (every kept entry is a splat index; the clamp keeps the depth-key
+        // gather of the padding lanes in bounds)
+        v[r] = min(S.part[w][r < rpw && e < n ? e - cw : 0u], num_splats - 1u);
+      }
+#pragma unroll
+      for (int r = 0; r < kTileSortRows; ++r) k[r] = zkey[v[r]];
+#pragma unroll
+      for (int r = 0; r < kTileSortRows; ++r) {
+        const int e = wave * (64 * rpw) + r * 64 + lane;
+        if (r >= rpw || e >= (int)n) {
+          v[r] = 0u;
+          k[r] = 0xFFFFFFFFu;
+        }
+      }
+      if (n == 1) {
+        if (tid == 0) vals[off] = v[0];
+        continue;
+      }
+      __syncthreads();   // every thread holds its entries before the passes reuse the buffers
+      lds_depth_sort(S, k, v, (int)n, rpw);
+      for (int e = tid; e < (int)n; e += kTileSortThreads) vals[off + e] = S.v[0][e];
+    } else {
+      // a list longer than the LDS sort holds: its kept entries again, in
+      // run order (per-row ballots and a prefix over the rows), straight to
+      // their places in vals, segment by segment of kBlockRows rows of 256,
+      // then sorted through global memory
+      const int nrows = (m + kTileSortThreads - 1) / kTileSortThreads;
+      uint32_t segbase = 0;
+      for (int rb = 0; rb < nrows; rb += kBlockRows) {
+        const int rn = min(kBlockRows, nrows - rb);
         __syncthreads();   // the previous segment's masks are consumed
         for (int r0 = 0; r0 < rn; r0 += kBlockLoads) {
           uint32_t kk[kBlockLoads];
@@ -1601,78 +1647,43 @@ __global__ void __launch_bounds__(kTileSortThreads) __attribute__((amdgpu_waves_
             if (lane == 0) s_mask[r0 + q][wave] = bal;
           }
         }
-      }
-      __syncthreads();
-      if (wave == 0) {
-        uint32_t t = 0;
-        if (lane < rn)
+        __syncthreads();
+        if (wave == 0) {
+          uint32_t t = 0;
+          if (lane < rn)
 #pragma unroll
-          for (int w = 0; w < kTileSortWaves; ++w) t += (uint32_t)__popcll(s_mask[lane][w]);
-        uint32_t x = t;
+            for (int w = 0; w < kTileSortWaves; ++w) t += (uint32_t)__popcll(s_mask[lane][w]);
+          uint32_t x = t;
 #pragma unroll
-        for (int dd = 1; dd < 64; dd <<= 1) {
-          const uint32_t y = __shfl_up(x, dd, 64);
-          if (lane >= dd) x += y;
+          for (int dd = 1; dd < 64; dd <<= 1) {
+            const uint32_t y = __shfl_up(x, dd, 64);
+            if (lane >= dd) x += y;
+          }
+          if (lane < rn) s_rowbase[lane] = segbase + x - t;
+          if (lane == 63) s_rowbase[kBlockRows] = segbase + x;
         }
-        if (lane < rn) s_rowbase[lane] = segbase + x - t;
-        if (lane == 63) s_rowbase[kBlockRows] = segbase + x;
-      }
-      __syncthreads();
-      for (int r0 = 0; r0 < rn; r0 += kBlockLoads) {
-        uint32_t vv[kBlockLoads];
+        __syncthreads();
+        for (int r0 = 0; r0 < rn; r0 += kBlockLoads) {
+          uint32_t vv[kBlockLoads];
 #pragma unroll
-        for (int q = 0; q < kBlockLoads; ++q) {
-          const int e = (rb + r0 + q) * kTileSortThreads + tid;
-          vv[q] = bvals[start + (e < m ? e : 0)];
-        }
+          for (int q = 0; q < kBlockLoads; ++q) {
+            const int e = (rb + r0 + q) * kTileSortThreads + tid;
+            vv[q] = bvals[start + (e < m ? e : 0)];
+          }
 #pragma unroll
-        for (int q = 0; q < kBlockLoads; ++q) {
-          const int r = r0 + q;
-          if (r >= rn) break;
-          const uint64_t mk = s_mask[r][wave];
-          if (!((mk >> lane) & 1ull)) continue;
-          uint32_t pos = s_rowbase[r] + (uint32_t)__popcll(mk & lt_mask);
-          for (int w = 0; w < wave; ++w) pos += (uint32_t)__popcll(s_mask[r][w]);
-          if (pos < n) {   // always, when the masks are right
-            if (in_lds) S.v[0][pos] = vv[q];
-            else vals[off + pos] = vv[q];
+          for (int q = 0; q < kBlockLoads; ++q) {
+            const int r = r0 + q;
+            if (r >= rn) break;
+            const uint64_t mk = s_mask[r][wave];
+            if (!((mk >> lane) & 1ull)) continue;
+            uint32_t pos = s_rowbase[r] + (uint32_t)__popcll(mk & lt_mask);
+            for (int w = 0; w < wave; ++w) pos += (uint32_t)__popcll(s_mask[r][w]);
+            if (pos < n) vals[off + pos] = vv[q];   // always, when the masks are right
           }
         }
+        segbase = s_rowbase[kBlockRows];
       }
-      segbase = s_rowbase[kBlockRows];
-    }
-    __syncthreads();
-    if (n < 2) {
-      if (tid == 0) vals[off] = S.v[0][0];
-      continue;
-    }
-    if (in_lds) {
-      uint32_t k[kTileSortRows], v[kTileSortRows];
-#pragma unroll
-      for (int r = 0; r < kTileSortRows; ++r) {
-        const int e = wave * (64 * kTileSortRows) + r * 64 + lane;
-        // (every position below n holds a splat index; the clamp keeps the
-        // depth-key gather in bounds regardless)
-        v[r] = min(S.v[0][e < (int)n ? e : 0], num_splats - 1u);
-      }
-#pragma unroll
-      for (int r = 0; r < kTileSortRows; ++r) k[r] = zkey[v[r]];
-#pragma unroll
-      for (int r = 0; r < kTileSortRows; ++r) {
-        const int e = wave * (64 * kTileSortRows) + r * 64 + lane;
-        if (e >= (int)n) {
-          v[r] = 0u;
-          k[r] = 0xFFFFFFFFu;
-        }
-      }
-      __syncthreads();   // every thread holds its entries before the passes reuse the buffers
-      lds_depth_sort(S, k, v, (int)n);
-#pragma unroll
-      for (int r = 0; r < kTileSortRows; ++r) {
-        const int e = wave * (64 * kTileSortRows) + r * 64 + lane;
-        if (e < (int)n) vals[off + e] = S.v[0][e];
-      }
-    } else {
+      __syncthreads();
       global_depth_sort(S, make_uint2(off, off + n), (int)n, (uint32_t)tile, false, zkey, num_splats, keys, vals,
                         keys_alt, vals_alt);
     }
