@@ -448,7 +448,6 @@ __global__ void __launch_bounds__(kScanThreads) compact_visible_kernel(
 constexpr uint32_t kFlagAgg = 1u << 30;
 constexpr uint32_t kFlagInc = 2u << 30;
 constexpr uint32_t kCountMask = (1u << 30) - 1;
-constexpr int kMaxPasses = 4;
 constexpr int kMaxRadix = 2048;
 
 // Digit width and pass count for a sort on `bits` key bits. 8-bit digits:
@@ -1167,39 +1166,41 @@ __global__ void __launch_bounds__(kOrderThreads) tile_balance_kernel(const uint2
 // (emission in index order, then a stable sort by tile); a stable LSD radix
 // sort of each tile's list on the raw bits of z (positive floats order like
 // their bits; zkey[s], as the projection stores them) then gives the order
-// (tile, z bits, index). One workgroup per
-// tile; four 8-bit passes. Every wave ranks rows of 64 keys in list order
-// with ballots (the rank among equal digits in the row, plus the wave's
-// running count of that digit), so the scatter keeps equal digits in list
-// order. A list of at most kTileSortCap entries is sorted in LDS; a longer one
-// chunk by chunk through the alternate key/value buffers, its tile keys used
-// as scratch and rewritten at the end.
+// (tile, z bits, index). One workgroup per tile. Every wave ranks rows of
+// 64 keys in list order with ballots (the rank among equal digits in the
+// row, plus the wave's running count of that digit), so the scatter keeps
+// equal digits in list order. A list of at most kTileSortCap entries is
+// sorted in LDS, on its keys minus the list's smallest in 9-bit digits (as
+// many passes as the range of its keys needs); a longer one in four 8-bit
+// passes, chunk by chunk through the alternate key/value buffers, its tile
+// keys used as scratch and rewritten at the end.
 // Ranks one chunk of n <= kTileSortCap keys held in registers, wave w owning
-// the chunk's entries [w R 64, (w + 1) R 64) with R = kTileSortRows, row r its
-// entries w R 64 + 64 r + lane: off[r] = the entry's rank among the wave's
-// earlier entries of its digit; wcnt[w][d] = the wave's count of digit d.
+// the chunk's entries [w R 64, (w + 1) R 64) with R = rpw, row r its entries
+// w R 64 + 64 r + lane: off[r] = the entry's rank among the wave's earlier
+// entries of its BITS-bit digit; wcnt[w][d] = the wave's count of digit d.
 constexpr int kTileSortThreads = 256;
 constexpr int kTileSortWaves = kTileSortThreads / 64;
-// rows of 64 per wave per chunk: 6 keeps the kernel at 86 VGPRs and 29.7 KB of
-// LDS, five workgroups per CU (8: 102 VGPRs, 38 KB, four; 640x480/200k:
-// 43 -> 37 us)
+// rows of 64 per wave per chunk: 6 keeps the kernels within five workgroups
+// per CU (8 rows took 102 VGPRs and 38 KB of LDS, four workgroups;
+// 640x480/200k: 43 -> 37 us)
 constexpr int kTileSortRows = 6;
 constexpr int kTileSortCap = kTileSortThreads * kTileSortRows;            // 1536 entries per chunk
 
 // rpw: rows per wave in use (the chunk's entries spread evenly over the
 // waves, at most kTileSortRows; rows past it are neither ranked nor set).
+template <int BITS>
 __device__ __forceinline__ void tile_sort_rank(const uint32_t* k, int n, int shift, uint32_t* off,
-                                               uint32_t (*wcnt)[256], int wave, int lane, int rpw) {
+                                               uint32_t (*wcnt)[1 << BITS], int wave, int lane, int rpw) {
   const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
   for (int r = 0; r < kTileSortRows; ++r) {
     if (r >= rpw) break;
     const int e = wave * (64 * rpw) + r * 64 + lane;
     const bool valid = e < n;
-    const uint32_t d = (k[r] >> shift) & 255u;
+    const uint32_t d = (k[r] >> shift) & ((1u << BITS) - 1u);
     uint64_t mask = __ballot(valid);
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
+    for (int b = 0; b < BITS; ++b) {
       const bool bit = (d >> b) & 1u;
       const uint64_t bal = __ballot(bit);
       mask &= bit ? bal : ~bal;
@@ -1248,38 +1249,80 @@ __device__ void order_equal_depths(const uint32_t* k, uint32_t* v, int n) {
 struct TileSortShared {
   union {
     struct {
-      uint32_t k[2][kTileSortCap], v[2][kTileSortCap];
-    };
+      uint32_t k[kTileSortCap], v[kTileSortCap];   // the list after each pass
+      uint32_t wcnt[kTileSortWaves][512];          // per wave and 9-bit digit
+      uint32_t start[512];                         // the digit's first position
+    } lds;                                         // the sort in LDS
     uint32_t part[kTileSortWaves][kTileSortCap];   // per-wave staging of the block filter
   };
+  // the sort through global memory (8-bit digits)
   uint32_t wcnt[kTileSortWaves][256];
   uint32_t start[256];     // the digit's first position (whole list) plus earlier chunks' count
   uint32_t wsum[kTileSortWaves];
+  uint32_t range[2][kTileSortWaves];   // per wave: smallest and largest key
 };
 
-// Four 8-bit LSD passes over a list of n <= kTileSortCap entries that the
-// workgroup holds in registers (thread: rows r of its wave, entry
-// wave R 64 + 64 r + lane; entries past n hold key 0xFFFFFFFF). The sorted
-// list ends in S.k[0], S.v[0].
+// Stable LSD sort of a list of n <= kTileSortCap entries that the workgroup
+// holds in registers (thread: rows r < rpw of its wave, entry w rpw 64 +
+// 64 r + lane; the other rows and entries past n are padding), on the keys
+// minus the list's smallest key, in 9-bit digits: as many passes as the
+// largest difference needs (a 25-bit range, depths from 1 to 5, takes three
+// where 8-bit digits of the raw keys take four; equal keys none). The
+// sorted list ends in S.lds.k (keys minus the smallest), S.lds.v. The buffers
+// must be free (a barrier since they were last read).
 __device__ __forceinline__ void lds_depth_sort(TileSortShared& S, uint32_t (&k)[kTileSortRows],
                                                uint32_t (&v)[kTileSortRows], int n, int rpw) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  uint32_t off[kTileSortRows];
-  for (int pass = 0; pass < 4; ++pass) {
-    const int shift = 8 * pass;
-    for (int w = 0; w < kTileSortWaves; ++w) S.wcnt[w][tid] = 0u;
-    __syncthreads();
-    tile_sort_rank(k, n, shift, off, S.wcnt, wave, lane, rpw);
-    __syncthreads();
-    // per digit: exclusive prefix over the waves, and the digit total
-    uint32_t acc = 0;
-    for (int w = 0; w < kTileSortWaves; ++w) {
-      const uint32_t c = S.wcnt[w][tid];
-      S.wcnt[w][tid] = acc;
-      acc += c;
+  uint32_t lo = 0xFFFFFFFFu, hi = 0u;
+#pragma unroll
+  for (int r = 0; r < kTileSortRows; ++r) {
+    if (r >= rpw) break;
+    if (wave * (64 * rpw) + r * 64 + lane < n) {
+      lo = min(lo, k[r]);
+      hi = max(hi, k[r]);
     }
-    // exclusive scan of the totals over the 256 digits (one per thread)
-    uint32_t x = acc;
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    lo = min(lo, (uint32_t)__shfl_xor(lo, d, 64));
+    hi = max(hi, (uint32_t)__shfl_xor(hi, d, 64));
+  }
+  if (lane == 0) {
+    S.range[0][wave] = lo;
+    S.range[1][wave] = hi;
+  }
+  for (int w = 0; w < kTileSortWaves; ++w) {
+    S.lds.wcnt[w][tid] = 0u;
+    S.lds.wcnt[w][tid + 256] = 0u;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int w = 0; w < kTileSortWaves; ++w) {
+    lo = min(lo, S.range[0][w]);
+    hi = max(hi, S.range[1][w]);
+  }
+  const uint32_t span = hi - lo;
+  const int passes = span == 0u ? 0 : (32 - __clz(span) + 8) / 9;
+#pragma unroll
+  for (int r = 0; r < kTileSortRows; ++r) k[r] -= lo;   // (padding wraps; it is never ranked)
+  uint32_t off[kTileSortRows];
+  for (int pass = 0; pass < passes; ++pass) {
+    const int shift = 9 * pass;
+    tile_sort_rank<9>(k, n, shift, off, S.lds.wcnt, wave, lane, rpw);
+    __syncthreads();
+    // digits 2 tid and 2 tid + 1: the exclusive prefix over the waves, the
+    // totals, and the exclusive scan of the totals over the 512 digits
+    uint32_t a0 = 0, a1 = 0;
+#pragma unroll
+    for (int w = 0; w < kTileSortWaves; ++w) {
+      uint2* c = reinterpret_cast<uint2*>(&S.lds.wcnt[w][2 * tid]);
+      const uint2 cw = *c;
+      *c = make_uint2(a0, a1);
+      a0 += cw.x;
+      a1 += cw.y;
+    }
+    const uint32_t pair = a0 + a1;
+    uint32_t x = pair;
 #pragma unroll
     for (int dd = 1; dd < 64; dd <<= 1) {
       const uint32_t y = __shfl_up(x, dd, 64);
@@ -1289,28 +1332,49 @@ __device__ __forceinline__ void lds_depth_sort(TileSortShared& S, uint32_t (&k)[
     __syncthreads();
     uint32_t base = 0;
     for (int w = 0; w < wave; ++w) base += S.wsum[w];
-    S.start[tid] = base + x - acc;
+    const uint32_t s0 = base + x - pair;
+    *reinterpret_cast<uint2*>(&S.lds.start[2 * tid]) = make_uint2(s0, s0 + a0);
     __syncthreads();
-    const int dst = (pass + 1) & 1;
 #pragma unroll
     for (int r = 0; r < kTileSortRows; ++r) {
       if (r >= rpw) break;
       if (off[r] == 0xFFFFFFFFu) continue;
-      const uint32_t d = (k[r] >> shift) & 255u;
-      const uint32_t pos = S.start[d] + S.wcnt[wave][d] + off[r];
+      const uint32_t d = (k[r] >> shift) & 511u;
+      const uint32_t pos = S.lds.start[d] + S.lds.wcnt[wave][d] + off[r];
       if (pos < (uint32_t)n) {     // always, when the counts are right; never outside the list
-        S.k[dst][pos] = k[r];
-        S.v[dst][pos] = v[r];
+        S.lds.k[pos] = k[r];
+        S.lds.v[pos] = v[r];
       }
     }
     __syncthreads();
+    if (pass + 1 < passes) {
+      // the next pass's entries, and its counters cleared (every wave has
+      // read this pass's)
+#pragma unroll
+      for (int r = 0; r < kTileSortRows; ++r) {
+        if (r >= rpw) break;
+        const int e = wave * (64 * rpw) + r * 64 + lane;
+        if (e < n) {
+          k[r] = S.lds.k[e];
+          v[r] = S.lds.v[e];
+        }
+      }
+      for (int w = 0; w < kTileSortWaves; ++w) {
+        S.lds.wcnt[w][tid] = 0u;
+        S.lds.wcnt[w][tid + 256] = 0u;
+      }
+      __syncthreads();
+    }
+  }
+  if (passes == 0) {
+    // every key equal: the list stays in its order
 #pragma unroll
     for (int r = 0; r < kTileSortRows; ++r) {
       if (r >= rpw) break;
       const int e = wave * (64 * rpw) + r * 64 + lane;
       if (e < n) {
-        k[r] = S.k[dst][e];
-        v[r] = S.v[dst][e];
+        S.lds.k[e] = k[r];
+        S.lds.v[e] = v[r];
       }
     }
     __syncthreads();
@@ -1361,7 +1425,7 @@ __device__ __forceinline__ void global_depth_sort(TileSortShared& S, uint2 rg, i
         if (wave * (64 * kTileSortRows) + r * 64 + lane >= cn) k[r] = 0xFFFFFFFFu;
       for (int w = 0; w < kTileSortWaves; ++w) S.wcnt[w][tid] = 0u;
       __syncthreads();
-      tile_sort_rank(k, cn, shift, off, S.wcnt, wave, lane, kTileSortRows);
+      tile_sort_rank<8>(k, cn, shift, off, S.wcnt, wave, lane, kTileSortRows);
       __syncthreads();
       for (int w = 0; w < kTileSortWaves; ++w) total += S.wcnt[w][tid];
       __syncthreads();
@@ -1406,7 +1470,7 @@ __device__ __forceinline__ void global_depth_sort(TileSortShared& S, uint2 rg, i
       }
       for (int w = 0; w < kTileSortWaves; ++w) S.wcnt[w][tid] = 0u;
       __syncthreads();
-      tile_sort_rank(k, cn, shift, off, S.wcnt, wave, lane, kTileSortRows);
+      tile_sort_rank<8>(k, cn, shift, off, S.wcnt, wave, lane, kTileSortRows);
       __syncthreads();
       uint32_t acc = 0;
       for (int w = 0; w < kTileSortWaves; ++w) {
@@ -1451,7 +1515,7 @@ __global__ void __launch_bounds__(kTileSortThreads) tile_depth_sort_kernel(
     const int n = (int)(rg.y - rg.x);
     if (n < 2) continue;
     if (n <= kTileSortCap) {
-      // in LDS: load, then four passes between the two buffers. Lanes past
+      // in LDS: load, then the passes the keys' range needs. Lanes past
       // the list read its first entry (a listed splat, so its depth key is
       // in bounds too): every row's id and key loads are in flight at once
       // rather than one guarded round trip after another
@@ -1473,9 +1537,8 @@ __global__ void __launch_bounds__(kTileSortThreads) tile_depth_sort_kernel(
         }
       }
       lds_depth_sort(S, k, v, n, rpw);
-      // the fourth pass left the list in S.k[0], S.v[0]
-      if (TIES) order_equal_depths(S.k[0], S.v[0], n);
-      for (int e = tid; e < n; e += kTileSortThreads) vals[rg.x + e] = S.v[0][e];
+      if (TIES) order_equal_depths(S.lds.k, S.lds.v, n);
+      for (int e = tid; e < n; e += kTileSortThreads) vals[rg.x + e] = S.lds.v[e];
     } else {
       global_depth_sort(S, rg, n, (uint32_t)tile, TIES, zkey, num_splats, keys, vals, keys_alt, vals_alt);
     }
@@ -1619,7 +1682,7 @@ __global__ void __launch_bounds__(kTileSortThreads) __attribute__((amdgpu_waves_
       }
       __syncthreads();   // every thread holds its entries before the passes reuse the buffers
       lds_depth_sort(S, k, v, (int)n, rpw);
-      for (int e = tid; e < (int)n; e += kTileSortThreads) vals[off + e] = S.v[0][e];
+      for (int e = tid; e < (int)n; e += kTileSortThreads) vals[off + e] = S.lds.v[e];
     } else {
       // a list longer than the LDS sort holds: its kept entries again, in
       // run order (per-row ballots and a prefix over the rows), straight to

@@ -259,6 +259,55 @@ def test_tile_list_block_binning(gpu, orc, case):
             assert torch.equal(a, b)
 
 
+def depth_range_case(case):
+    """Scene whose depths span a chosen key range: "flat" puts every
+    Gaussian at one depth (equal keys: the index decides the whole order),
+    "one_digit" within 300 float ulps of 2.0 (one 9-bit digit), "two_digits"
+    within 2e-3 of 2.0 (about 13 bits)."""
+    s = scenes.tiny_random(44, n=3000, width=96, height=64)
+    p = s.params.copy()
+    cam = s.cameras[0]
+    rng = np.random.default_rng(scenes.SEED_BASE + 44)
+    n = p.shape[1]
+    if case == "flat":
+        z = np.full(n, 2.0, np.float32)
+    elif case == "one_digit":
+        z = (np.float32(2.0) + np.float32(np.spacing(np.float32(2.0))) *
+             rng.integers(0, 300, n).astype(np.float32)).astype(np.float32)
+    else:
+        z = (2.0 + rng.uniform(0.0, 2e-3, n)).astype(np.float32)
+    u, v = rng.uniform(0, cam.width, n), rng.uniform(0, cam.height, n)
+    p[0] = ((u - cam.cx) / cam.fx * z).astype(np.float32)
+    p[1] = ((v - cam.cy) / cam.fy * z).astype(np.float32)
+    p[2] = z
+    p[3:6] = np.log(0.02)
+    return s, p
+
+
+@pytest.mark.parametrize("binning", [2, 3])
+@pytest.mark.parametrize("case", ["flat", "one_digit", "two_digits"])
+def test_tile_list_depth_ranges(gpu, orc, case, binning):
+    """The per-tile depth sort takes as many 9-bit passes as the range of a
+    list's keys needs: none for equal depths, one or two for narrow ranges.
+    Lists bit-exact against the oracle's (tile, depth, index) order with both
+    the radix and the block binning."""
+    s, p = depth_range_case(case)
+    say("depth range", case, "binning", binning)
+    R = make(gpu, binning=binning, depth_sort=1)
+    R.render(to_dev(p), s.sh_degree, s.cameras)
+    torch.cuda.synchronize()
+    t_gpu, g_gpu = R.instances()
+    t_ref, g_ref = orc.tile_list(p, s.sh_degree, s.cameras, 16, 16)
+    zk = orc.project(p, s.sh_degree, s.cameras[0], prec=32)["z"]
+    vis = orc.project(p, s.sh_degree, s.cameras[0], prec=32)["vis"]
+    zs = np.unique(np.asarray(zk, np.float32)[vis])
+    say("instances", len(t_ref), "distinct depths", len(zs))
+    if case == "flat":
+        assert len(zs) == 1
+    assert len(t_gpu) == len(t_ref)
+    assert np.array_equal(t_gpu, t_ref) and np.array_equal(g_gpu, g_ref)
+
+
 def ring_cameras(count, seed):
     """`count` small cameras on a ring around the tiny scenes' volume (z in
     [1, 3]); every seventh looks away from it, so that it culls everything."""
