@@ -1052,29 +1052,68 @@ __global__ void __launch_bounds__(256) loss_l1_kernel(const ViewDesc* __restrict
   if (threadIdx.x == 0 && loss) unsafeAtomicAdd(loss, wsum[0] + wsum[1] + wsum[2] + wsum[3]);
 }
 
+__device__ __forceinline__ void adam_one(float gi, float& mi, float& vi, float& pi, float b1, float b2, float eps,
+                                         float bc1, float bc2, float lr) {
+  mi = b1 * mi + (1.0f - b1) * gi;
+  vi = b2 * vi + (1.0f - b2) * gi * gi;
+  pi -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+}
+
+// Adam over the parameter planes: workgroup column y = plane (its learning
+// rate in a scalar register), a grid-stride walk along the plane; with VEC
+// (every plane 16-byte aligned) four scalars per load and store, the last
+// num mod 4 scalars one by one.
+template <bool VEC>
 __global__ void __launch_bounds__(256) adam_kernel(float* __restrict__ p, const float* __restrict__ g,
                                                    float* __restrict__ m, float* __restrict__ v, int64_t num,
-                                                   int64_t stride, int planes, const float* __restrict__ lr,
-                                                   float b1, float b2, float eps, float bc1, float bc2,
+                                                   int64_t stride, const float* __restrict__ lr, float b1, float b2,
+                                                   float eps, float bc1, float bc2,
                                                    const uint32_t* __restrict__ step_dev,
                                                    const uint32_t* __restrict__ skip) {
   if (skip && (skip[0] | skip[1])) return;
   if (step_dev) {
     // in double, as the host does: 1 - b^step cancels badly in float
-    const int step = *step_dev;
-    bc1 = (float)(1.0 - pow((double)b1, (double)step));
-    bc2 = (float)(1.0 - pow((double)b2, (double)step));
+    __shared__ float s_bc[2];
+    if (threadIdx.x == 0) {
+      const int step = *step_dev;
+      s_bc[0] = (float)(1.0 - pow((double)b1, (double)step));
+      s_bc[1] = (float)(1.0 - pow((double)b2, (double)step));
+    }
+    __syncthreads();
+    bc1 = s_bc[0];
+    bc2 = s_bc[1];
   }
-  const int64_t total = num * planes;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    const int plane = (int)(e / num);
-    const int64_t i = plane * stride + (e - (int64_t)plane * num);
-    const float gi = g[i];
-    const float mi = b1 * m[i] + (1.0f - b1) * gi;
-    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  const int64_t off = (int64_t)blockIdx.y * stride;
+  const float lrp = lr[blockIdx.y];
+  p += off;
+  g += off;
+  m += off;
+  v += off;
+  const int64_t step = (int64_t)gridDim.x * blockDim.x;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (VEC) {
+    const int64_t n4 = num >> 2;
+    for (; i < n4; i += step) {
+      const float4 gi = reinterpret_cast<const float4*>(g)[i];
+      float4 mi = reinterpret_cast<const float4*>(m)[i];
+      float4 vi = reinterpret_cast<const float4*>(v)[i];
+      float4 pi = reinterpret_cast<const float4*>(p)[i];
+      adam_one(gi.x, mi.x, vi.x, pi.x, b1, b2, eps, bc1, bc2, lrp);
+      adam_one(gi.y, mi.y, vi.y, pi.y, b1, b2, eps, bc1, bc2, lrp);
+      adam_one(gi.z, mi.z, vi.z, pi.z, b1, b2, eps, bc1, bc2, lrp);
+      adam_one(gi.w, mi.w, vi.w, pi.w, b1, b2, eps, bc1, bc2, lrp);
+      reinterpret_cast<float4*>(m)[i] = mi;
+      reinterpret_cast<float4*>(v)[i] = vi;
+      reinterpret_cast<float4*>(p)[i] = pi;
+    }
+    i = 4 * n4 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  }
+  for (; i < num; i += step) {
+    float mi = m[i], vi = v[i], pi = p[i];
+    adam_one(g[i], mi, vi, pi, b1, b2, eps, bc1, bc2, lrp);
     m[i] = mi;
     v[i] = vi;
-    p[i] -= lr[plane] * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+    p[i] = pi;
   }
 }
 
@@ -1152,10 +1191,14 @@ void launch_loss_l1(const ViewDesc* views, const ViewImages* rendered, const Vie
 void launch_adam(float* p, const float* g, float* m, float* v, int64_t num, int64_t stride, int planes,
                  const float* lr_dev, float b1, float b2, float eps, float bc1, float bc2, const uint32_t* step_dev,
                  const uint32_t* skip, hipStream_t st) {
-  const int64_t total = num * planes;
-  if (total == 0) return;
-  adam_kernel<<<grid_cap(total, 256), 256, 0, st>>>(p, g, m, v, num, stride, planes, lr_dev, b1, b2, eps, bc1, bc2,
-                                                    step_dev, skip);
+  if (num == 0 || planes == 0) return;
+  const bool vec = stride % 4 == 0 && (((uintptr_t)p | (uintptr_t)g | (uintptr_t)m | (uintptr_t)v) & 15u) == 0;
+  const int64_t per = vec ? (num + 3) / 4 : num;
+  const dim3 grid((unsigned)std::min<int64_t>(std::max<int64_t>((per + 255) / 256, 1), 1024), (unsigned)planes);
+  if (vec)
+    adam_kernel<true><<<grid, 256, 0, st>>>(p, g, m, v, num, stride, lr_dev, b1, b2, eps, bc1, bc2, step_dev, skip);
+  else
+    adam_kernel<false><<<grid, 256, 0, st>>>(p, g, m, v, num, stride, lr_dev, b1, b2, eps, bc1, bc2, step_dev, skip);
 }
 
 }  // namespace gsr

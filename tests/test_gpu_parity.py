@@ -602,19 +602,29 @@ def test_loss_matches_oracle(gpu, orc):
     assert (grads[0][2].cpu().numpy() == 0).all()
 
 
-def test_adam_matches_oracle(gpu, orc):
+@pytest.mark.parametrize("n,pad", [(1000, 0), (1003, 0), (1003, 5)])
+def test_adam_matches_oracle(gpu, orc, n, pad):
+    """Adam against the oracle's float64 step; planes of 1000 (four scalars
+    per load), 1003 with pitch 1003 (one by one) and with pitch 1008 (four
+    per load and a tail of three)."""
     rng = np.random.default_rng(2)
-    P, n = 14, 1000
+    P = 14
     x0 = rng.normal(size=(P, n)).astype(np.float32)
     lrs = np.linspace(1e-3, 1e-2, P).astype(np.float32)
     R = make(gpu)
-    x = to_dev(x0)
-    m = torch.zeros_like(x)
-    v = torch.zeros_like(x)
+
+    def padded(a):
+        t = torch.zeros(P, n + pad, device="cuda")
+        t[:, :n] = torch.from_numpy(np.ascontiguousarray(a)).cuda()
+        return t[:, :n]
+
+    x = padded(x0)
+    m = padded(np.zeros((P, n), np.float32))
+    v = padded(np.zeros((P, n), np.float32))
     xr, mr, vr = x0.astype(np.float64), np.zeros((P, n)), np.zeros((P, n))
     for step in range(1, 4):
         g = rng.normal(size=(P, n)).astype(np.float32)
-        R.adam_step(x, to_dev(g), m, v, lrs, step)
+        R.adam_step(x, padded(g), m, v, lrs, step)
         xr, mr, vr = orc.adam_step(xr, g, mr, vr, step, lrs.astype(np.float64))
     # float32 arithmetic: a few ulp of the parameter plus 1e-5 of the total update
     upd = np.abs(xr - x0)
