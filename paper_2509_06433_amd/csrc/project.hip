@@ -1114,17 +1114,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) p
   }
 }
 
-// Waves per SIMD asked of the compiler for the colour half (it would take
-// just over 256 registers at degree 3, one wave; 184 at degree 2, two).
+// Waves per SIMD asked of the compiler for the colour half, whose
+// higher-order SH coefficients sit in LDS (degree 3: 45 KB of them per
+// workgroup, so three workgroups per CU).
 template <int DEG>
-constexpr int kShBackwardWaves = DEG == 3 ? 2 : DEG == 2 ? 3 : 4;
+constexpr int kShBackwardWaves = DEG == 3 ? 2 : 4;
 
 // The colour half of the chain rule for DEG > 0 (after
 // project_backward_kernel, which left it out): per Gaussian, over its views,
 // the SH coefficients' gradient and the mean's share through the viewing
 // direction, written (overwrite: every SH plane) or added (mean planes: always
 // added, after the geometry half). Clears the screen-space gradient rows it
-// reads when zero_g2.
+// reads when zero_g2. The coefficients past degree 0 are read once into the
+// thread's own column of LDS (registers hold the gradient sums).
 template <int DEG>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kShBackwardWaves<DEG>))) sh_backward_kernel(const float* __restrict__ P, int64_t n, int64_t stride,
                                                           int num_views, const ViewDesc* __restrict__ views,
@@ -1132,15 +1134,21 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kShBac
                                                           const uint32_t* __restrict__ ntiles,
                                                           float* __restrict__ grad, bool overwrite, bool zero_g2) {
   constexpr int K = (DEG + 1) * (DEG + 1);
+  static_assert(DEG > 0, "the colour half exists for view-dependent colour only");
   __shared__ ViewDesc s_views[kLdsViews];
+  __shared__ float s_sh[3 * (K - 1) * 256];
   const ViewDesc* vsrc = stage_views(views, num_views, s_views);
+  StagedCoef coef;
+  coef.col = s_sh + threadIdx.x;
+  coef.pitch = 256;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     float gsh[3 * K];
 #pragma unroll
     for (int k = 0; k < 3 * K; ++k) gsh[k] = 0.0f;
-    float coef[3 * K];
 #pragma unroll
-    for (int k = 0; k < 3 * K; ++k) coef[k] = P[(11 + k) * stride + i];
+    for (int ch = 0; ch < 3; ++ch) coef.dc[ch] = P[(11 + ch) * stride + i];
+#pragma unroll
+    for (int j = 0; j < 3 * (K - 1); ++j) s_sh[j * 256 + threadIdx.x] = P[(14 + j) * stride + i];
     double gmean[3] = {0, 0, 0};
     bool touched = false;
     for (int vb = 0; vb < num_views; vb += 64) {
@@ -1161,7 +1169,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kShBac
       }
       if (G[G2_R] == 0.0f && G[G2_G] == 0.0f && G[G2_BL] == 0.0f) continue;
       double gview[3];
-      colour_chain<DEG>(P, stride, i, vsrc[cur], G + G2_R, ArrayCoef{coef}, ArraySink{gsh}, gview);
+      colour_chain<DEG>(P, stride, i, vsrc[cur], G + G2_R, coef, ArraySink{gsh}, gview);
       touched = true;
 #pragma unroll
       for (int j = 0; j < 3; ++j) gmean[j] += gview[j];
