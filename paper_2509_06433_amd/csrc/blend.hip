@@ -395,7 +395,11 @@ enum { M_R = 0, M_G, M_B, M_Z, M_O, M_X, M_Y, M_XX, M_XY, M_YY, M_N };
 // composited (ok false) leaves T and S alone and contributes zero moments;
 // a clamped alpha passes no gradient to opacity or the exponent. FIRST: the
 // moments are assigned (the thread's first pixel) rather than accumulated.
-template <bool FIRST>
+// ROWY: every 16-lane row of the wave is one image row (one pixel per
+// thread, tiles 16 or 32 wide), so dy is the same across the row: the lane
+// keeps only dL/dpower, its dx and dx^2 moments (in M_Y, M_X, M_XX), and
+// the dy factors are applied to the row sums (publish).
+template <bool FIRST, bool ROWY>
 __device__ __forceinline__ void reverse_one(bool ok, float alpha, float G, bool clamped, float dx, float dy,
                                             const float4& q1, const float4& q2, float gc0, float gc1, float gc2,
                                             float gd, float tb, float& T, float& S, float* m) {
@@ -410,6 +414,18 @@ __device__ __forceinline__ void reverse_one(bool ok, float alpha, float G, bool 
   const float gpow = live ? galpha * alpha : 0.0f;     // dL/dpower
   T = ok ? Tk : T;
   S = ok ? Sn : S;
+  if (ROWY) {
+    const float gx = gpow * dx;
+    m[M_R] = w * gc0;
+    m[M_G] = w * gc1;
+    m[M_B] = w * gc2;
+    m[M_Z] = w * gd;
+    m[M_O] = go;
+    m[M_X] = gx;
+    m[M_Y] = gpow;
+    m[M_XX] = gx * dx;
+    return;
+  }
   const float gx = gpow * dx, gy = gpow * dy;
   if (FIRST) {
     m[M_R] = w * gc0;
@@ -440,27 +456,40 @@ __device__ __forceinline__ void reverse_one(bool ok, float alpha, float G, bool 
 // permutes, then row rotations by 4 and 8): every lane ends with its row's
 // total. Step-major over the M_N moments so that the independent chains fill
 // the DPP read-after-write wait states.
+template <int N>
 __device__ __forceinline__ void row_sums(float* m) {
 #pragma unroll
-  for (int c = 0; c < M_N; ++c) m[c] = dpp_add<0xB1, 0xF>(m[c]);   // quad_perm [1,0,3,2]
+  for (int c = 0; c < N; ++c) m[c] = dpp_add<0xB1, 0xF>(m[c]);   // quad_perm [1,0,3,2]
 #pragma unroll
-  for (int c = 0; c < M_N; ++c) m[c] = dpp_add<0x4E, 0xF>(m[c]);   // quad_perm [2,3,0,1]
+  for (int c = 0; c < N; ++c) m[c] = dpp_add<0x4E, 0xF>(m[c]);   // quad_perm [2,3,0,1]
 #pragma unroll
-  for (int c = 0; c < M_N; ++c) m[c] = dpp_add<0x124, 0xF>(m[c]);  // row_ror:4
+  for (int c = 0; c < N; ++c) m[c] = dpp_add<0x124, 0xF>(m[c]);  // row_ror:4
 #pragma unroll
-  for (int c = 0; c < M_N; ++c) m[c] = dpp_add<0x128, 0xF>(m[c]);  // row_ror:8
+  for (int c = 0; c < N; ++c) m[c] = dpp_add<0x128, 0xF>(m[c]);  // row_ror:8
 }
 
 // Row-reduce one Gaussian's moments and store the four row partials of this
-// wave (lanes 15, 31, 47, 63 each hold one row's sum).
-template <int NW, int BATCH>
+// wave (lanes 15, 31, 47, 63 each hold one row's sum). ROWY: eight sums
+// (the last two moments are empty), then M_Y = dy S0, M_XY = dy S1 and
+// M_YY = dy (dy S0) from the row's dy and its sums S0 of dL/dpower and S1
+// of its dx moment.
+template <int NW, int BATCH, bool ROWY>
 __device__ __forceinline__ void publish(float* m, bool any, int lane, int wave, int k,
-                                        float (*s_red)[4][M_N][BATCH]) {
+                                        float (*s_red)[4][M_N][BATCH], float dy) {
   // the wave's slots start each batch at zero: nothing to write when no lane
   // composited the Gaussian
   if (!any) return;
   const int row = lane >> 4;
-  row_sums(m);
+  static_assert(M_XY == M_N - 2 && M_YY == M_N - 1, "the dy moments come last");
+  if (ROWY) {
+    row_sums<M_N - 2>(m);
+    const float s0 = m[M_Y];
+    m[M_Y] = dy * s0;
+    m[M_XY] = dy * m[M_X];
+    m[M_YY] = dy * (dy * s0);
+  } else {
+    row_sums<M_N>(m);
+  }
   if ((lane & 15) == 15) {
 #pragma unroll
     for (int c = 0; c < M_N; ++c) s_red[wave][row][c][k] = m[c];
@@ -490,6 +519,7 @@ __device__ __forceinline__ void backward_unit(const BlendArgs& a, BwdShared<TW *
   constexpr int NT = Shape::NT;
   constexpr int ROWS = Shape::ROWS;
   constexpr int NW = NT / 64;
+  constexpr bool ROWY = PPT == 1 && TW % 16 == 0;
   static_assert(BATCH <= NT, "one staged Gaussian per thread");
   float4* s_q0 = sh.q0;
   float4* s_q1 = sh.q1;
@@ -643,10 +673,10 @@ __device__ __forceinline__ void backward_unit(const BlendArgs& a, BwdShared<TW *
 #pragma unroll
         for (int i = 0; i < PPT; ++i) {
           if (i == 0)
-            reverse_one<true>(okA[i], alA[i], GA[i], clA[i], dxA[i], dyA[i], qa1, qa2, gc0[i], gc1[i], gc2[i], gd[i],
+            reverse_one<true, ROWY>(okA[i], alA[i], GA[i], clA[i], dxA[i], dyA[i], qa1, qa2, gc0[i], gc1[i], gc2[i], gd[i],
                               tb[i], T[i], S[i], ma);
           else
-            reverse_one<false>(okA[i], alA[i], GA[i], clA[i], dxA[i], dyA[i], qa1, qa2, gc0[i], gc1[i], gc2[i],
+            reverse_one<false, ROWY>(okA[i], alA[i], GA[i], clA[i], dxA[i], dyA[i], qa1, qa2, gc0[i], gc1[i], gc2[i],
                                gd[i], tb[i], T[i], S[i], ma);
         }
       }
@@ -654,15 +684,15 @@ __device__ __forceinline__ void backward_unit(const BlendArgs& a, BwdShared<TW *
 #pragma unroll
         for (int i = 0; i < PPT; ++i) {
           if (i == 0)
-            reverse_one<true>(okB[i], alB[i], GB[i], clB[i], dxB[i], dyB[i], qb1, qb2, gc0[i], gc1[i], gc2[i], gd[i],
+            reverse_one<true, ROWY>(okB[i], alB[i], GB[i], clB[i], dxB[i], dyB[i], qb1, qb2, gc0[i], gc1[i], gc2[i], gd[i],
                               tb[i], T[i], S[i], mb);
           else
-            reverse_one<false>(okB[i], alB[i], GB[i], clB[i], dxB[i], dyB[i], qb1, qb2, gc0[i], gc1[i], gc2[i],
+            reverse_one<false, ROWY>(okB[i], alB[i], GB[i], clB[i], dxB[i], dyB[i], qb1, qb2, gc0[i], gc1[i], gc2[i],
                                gd[i], tb[i], T[i], S[i], mb);
         }
       }
-      publish<NW, BATCH>(ma, anya, lane, wave, k, s_red);
-      publish<NW, BATCH>(mb, anyb, lane, wave, k - 1, s_red);
+      publish<NW, BATCH, ROWY>(ma, anya, lane, wave, k, s_red, dyA[0]);
+      publish<NW, BATCH, ROWY>(mb, anyb, lane, wave, k - 1, s_red, dyB[0]);
     }
     if (k == 0 && lbase < wlast) {
       const float4 q0 = s_q0[0], q1 = s_q1[0], q2 = s_q2[0];
@@ -680,14 +710,14 @@ __device__ __forceinline__ void backward_unit(const BlendArgs& a, BwdShared<TW *
 #pragma unroll
         for (int i = 0; i < PPT; ++i) {
           if (i == 0)
-            reverse_one<true>(okc[i], alc[i], Gc[i], clc[i], dxc[i], dyc[i], q1, q2, gc0[i], gc1[i], gc2[i], gd[i],
+            reverse_one<true, ROWY>(okc[i], alc[i], Gc[i], clc[i], dxc[i], dyc[i], q1, q2, gc0[i], gc1[i], gc2[i], gd[i],
                               tb[i], T[i], S[i], m);
           else
-            reverse_one<false>(okc[i], alc[i], Gc[i], clc[i], dxc[i], dyc[i], q1, q2, gc0[i], gc1[i], gc2[i], gd[i],
+            reverse_one<false, ROWY>(okc[i], alc[i], Gc[i], clc[i], dxc[i], dyc[i], q1, q2, gc0[i], gc1[i], gc2[i], gd[i],
                                tb[i], T[i], S[i], m);
         }
       }
-      publish<NW, BATCH>(m, anyc, lane, wave, 0, s_red);
+      publish<NW, BATCH, ROWY>(m, anyc, lane, wave, 0, s_red, dyc[0]);
     }
     __syncthreads();
     // sum the row partials of every wave into slot [0][0], then turn the
@@ -917,7 +947,7 @@ __global__ void __launch_bounds__(64) blend_backward_splat_kernel(BlendArgs a) {
       bool clamped;
       const bool ok = pair_alpha(q0, q1, pa.x, pa.y, dx, dy, G, alpha, clamped) && valid && have &&
                       (uint32_t)pos < __float_as_uint(pa.w);
-      reverse_one<false>(ok, alpha, G, clamped, dx, dy, q1, q2, pg.x, pg.y, pg.z, pg.w, pa.z, T, S, m);
+      reverse_one<false, false>(ok, alpha, G, clamped, dx, dy, q1, q2, pg.x, pg.y, pg.z, pg.w, pa.z, T, S, m);
       if (lane == 63 && valid) sh.state[r] = make_float2(T, S);
       Tin = lane_shift_up(T);
       Sin = lane_shift_up(S);
