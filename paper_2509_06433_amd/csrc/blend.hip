@@ -388,7 +388,7 @@ __device__ __forceinline__ float wave_sum_lane63(float x) {
 // gradients are linear in the moments of dL/dpower over the pixels, so the
 // per-pair work accumulates the moments and the lane that publishes the
 // wave sum turns them into (u, v, A, B, C) gradients.
-enum { M_R = 0, M_G, M_B, M_Z, M_O, M_X, M_Y, M_XX, M_XY, M_YY, M_N };
+enum { M_R = 0, M_G, M_B, M_Z, M_O, M_X, M_XX, M_Y, M_XY, M_YY, M_N };
 
 // Reverse step of one pixel over one Gaussian, without branches: recover
 // T_k, form the pair's moments, update the suffix sum. A pair that was not
@@ -396,9 +396,10 @@ enum { M_R = 0, M_G, M_B, M_Z, M_O, M_X, M_Y, M_XX, M_XY, M_YY, M_N };
 // a clamped alpha passes no gradient to opacity or the exponent. FIRST: the
 // moments are assigned (the thread's first pixel) rather than accumulated.
 // ROWY: every 16-lane row of the wave is one image row (one pixel per
-// thread, tiles 16 or 32 wide), so dy is the same across the row: the lane
-// keeps only dL/dpower, its dx and dx^2 moments (in M_Y, M_X, M_XX), and
-// the dy factors are applied to the row sums (publish).
+// thread, tiles 16 or 32 wide), so dy is the same across the row; and
+// dL/dpower = opacity x dL/dopacity-term (alpha = o G unclamped): the lane
+// keeps the dx and dx^2 moments of dL/dopacity's term (in M_X, M_XX), and
+// publish applies the opacity and the dy factors to the row sums.
 template <bool FIRST, bool ROWY>
 __device__ __forceinline__ void reverse_one(bool ok, float alpha, float G, bool clamped, float dx, float dy,
                                             const float4& q1, const float4& q2, float gc0, float gc1, float gc2,
@@ -415,14 +416,13 @@ __device__ __forceinline__ void reverse_one(bool ok, float alpha, float G, bool 
   T = ok ? Tk : T;
   S = ok ? Sn : S;
   if (ROWY) {
-    const float gx = gpow * dx;
+    const float gx = go * dx;
     m[M_R] = w * gc0;
     m[M_G] = w * gc1;
     m[M_B] = w * gc2;
     m[M_Z] = w * gd;
     m[M_O] = go;
     m[M_X] = gx;
-    m[M_Y] = gpow;
     m[M_XX] = gx * dx;
     return;
   }
@@ -469,23 +469,26 @@ __device__ __forceinline__ void row_sums(float* m) {
 }
 
 // Row-reduce one Gaussian's moments and store the four row partials of this
-// wave (lanes 15, 31, 47, 63 each hold one row's sum). ROWY: eight sums
-// (the last two moments are empty), then M_Y = dy S0, M_XY = dy S1 and
-// M_YY = dy (dy S0) from the row's dy and its sums S0 of dL/dpower and S1
-// of its dx moment.
+// wave (lanes 15, 31, 47, 63 each hold one row's sum). ROWY: seven sums
+// (the last three moments are empty), then with the opacity o and the row's
+// dy, from the sums O of dL/dopacity's term and S1, S2 of its dx and dx^2
+// moments: M_X = o S1, M_XX = o S2, M_Y = dy (o O), M_XY = dy (o S1),
+// M_YY = dy (dy (o O)).
 template <int NW, int BATCH, bool ROWY>
 __device__ __forceinline__ void publish(float* m, bool any, int lane, int wave, int k,
-                                        float (*s_red)[4][M_N][BATCH], float dy) {
+                                        float (*s_red)[4][M_N][BATCH], float dy, float o) {
   // the wave's slots start each batch at zero: nothing to write when no lane
   // composited the Gaussian
   if (!any) return;
   const int row = lane >> 4;
-  static_assert(M_XY == M_N - 2 && M_YY == M_N - 1, "the dy moments come last");
+  static_assert(M_Y == M_N - 3 && M_XY == M_N - 2 && M_YY == M_N - 1, "the dy moments come last");
   if (ROWY) {
-    row_sums<M_N - 2>(m);
-    const float s0 = m[M_Y];
+    row_sums<M_N - 3>(m);
+    const float s0 = o * m[M_O], s1 = o * m[M_X];
+    m[M_X] = s1;
+    m[M_XX] = o * m[M_XX];
     m[M_Y] = dy * s0;
-    m[M_XY] = dy * m[M_X];
+    m[M_XY] = dy * s1;
     m[M_YY] = dy * (dy * s0);
   } else {
     row_sums<M_N>(m);
@@ -691,8 +694,8 @@ __device__ __forceinline__ void backward_unit(const BlendArgs& a, BwdShared<TW *
                                gd[i], tb[i], T[i], S[i], mb);
         }
       }
-      publish<NW, BATCH, ROWY>(ma, anya, lane, wave, k, s_red, dyA[0]);
-      publish<NW, BATCH, ROWY>(mb, anyb, lane, wave, k - 1, s_red, dyB[0]);
+      publish<NW, BATCH, ROWY>(ma, anya, lane, wave, k, s_red, dyA[0], qa1.y);
+      publish<NW, BATCH, ROWY>(mb, anyb, lane, wave, k - 1, s_red, dyB[0], qb1.y);
     }
     if (k == 0 && lbase < wlast) {
       const float4 q0 = s_q0[0], q1 = s_q1[0], q2 = s_q2[0];
@@ -717,7 +720,7 @@ __device__ __forceinline__ void backward_unit(const BlendArgs& a, BwdShared<TW *
                                tb[i], T[i], S[i], m);
         }
       }
-      publish<NW, BATCH, ROWY>(m, anyc, lane, wave, 0, s_red, dyc[0]);
+      publish<NW, BATCH, ROWY>(m, anyc, lane, wave, 0, s_red, dyc[0], q1.y);
     }
     __syncthreads();
     // sum the row partials of every wave into slot [0][0], then turn the
