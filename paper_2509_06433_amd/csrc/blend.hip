@@ -398,8 +398,8 @@ enum { M_R = 0, M_G, M_B, M_Z, M_O, M_X, M_XX, M_Y, M_XY, M_YY, M_N };
 // ROWY: every 16-lane row of the wave is one image row (one pixel per
 // thread, tiles 16 or 32 wide), so dy is the same across the row; and
 // dL/dpower = opacity x dL/dopacity-term (alpha = o G unclamped): the lane
-// keeps the dx and dx^2 moments of dL/dopacity's term (in M_X, M_XX), and
-// publish applies the opacity and the dy factors to the row sums.
+// keeps the dx and dx^2 moments of dL/dopacity's term (in M_X, M_XX); the
+// workgroup's sums apply the rows' dy and the opacity.
 template <bool FIRST, bool ROWY>
 __device__ __forceinline__ void reverse_one(bool ok, float alpha, float G, bool clamped, float dx, float dy,
                                             const float4& q1, const float4& q2, float gc0, float gc1, float gc2,
@@ -468,46 +468,43 @@ __device__ __forceinline__ void row_sums(float* m) {
   for (int c = 0; c < N; ++c) m[c] = dpp_add<0x128, 0xF>(m[c]);  // row_ror:8
 }
 
-// Row-reduce one Gaussian's moments and store the four row partials of this
-// wave (lanes 15, 31, 47, 63 each hold one row's sum). ROWY: seven sums
-// (the last three moments are empty), then with the opacity o and the row's
-// dy, from the sums O of dL/dopacity's term and S1, S2 of its dx and dx^2
-// moments: M_X = o S1, M_XX = o S2, M_Y = dy (o O), M_XY = dy (o S1),
-// M_YY = dy (dy (o O)).
-template <int NW, int BATCH, bool ROWY>
+// The row form of the backward (ROWY in reverse_one): every 16-lane row of
+// a wavefront is one image row. Its rows then store seven moments (the
+// M_Y, M_XY and M_YY of the row follow from them and the row's dy).
+template <int TW, int PPT>
+constexpr bool kRowForm = PPT == 1 && TW % 16 == 0;
+template <int TW, int PPT>
+constexpr int kStoredMoments = kRowForm<TW, PPT> ? M_N - 3 : M_N;
+
+// Row-reduce one Gaussian's MS stored moments and store the four row
+// partials of this wave (lanes 15, 31, 47, 63 each hold one row's sum).
+template <int NW, int BATCH, int MS>
 __device__ __forceinline__ void publish(float* m, bool any, int lane, int wave, int k,
-                                        float (*s_red)[4][M_N][BATCH], float dy, float o) {
+                                        float (*s_red)[4][MS][BATCH]) {
   // the wave's slots start each batch at zero: nothing to write when no lane
   // composited the Gaussian
   if (!any) return;
-  const int row = lane >> 4;
   static_assert(M_Y == M_N - 3 && M_XY == M_N - 2 && M_YY == M_N - 1, "the dy moments come last");
-  if (ROWY) {
-    row_sums<M_N - 3>(m);
-    const float s0 = o * m[M_O], s1 = o * m[M_X];
-    m[M_X] = s1;
-    m[M_XX] = o * m[M_XX];
-    m[M_Y] = dy * s0;
-    m[M_XY] = dy * s1;
-    m[M_YY] = dy * (dy * s0);
-  } else {
-    row_sums<M_N>(m);
-  }
+  const int row = lane >> 4;
+  row_sums<MS>(m);
   if ((lane & 15) == 15) {
 #pragma unroll
-    for (int c = 0; c < M_N; ++c) s_red[wave][row][c][k] = m[c];
+    for (int c = 0; c < MS; ++c) s_red[wave][row][c][k] = m[c];
   }
 }
 
-// LDS of the backward: one batch of records, their ids, and the row
-// partials of the moments, NW * 4 * 10 * BATCH floats.
-template <int NW, int BATCH>
+// LDS of the backward: one batch of records, their ids, the row partials of
+// the MS stored moments, NW * 4 * MS * BATCH floats, and the batch's sums.
+template <int NW, int BATCH, int MS>
 struct BwdShared {
   float4 q0[BATCH], q1[BATCH], q2[BATCH];
   uint32_t id[BATCH];
-  float red[NW][4][M_N][BATCH];   // moments per (wave, 16-lane row)
+  float red[NW][4][MS][BATCH];   // moments per (wave, 16-lane row)
+  float tot[M_N][BATCH];         // per Gaussian of the batch, over the workgroup
   uint32_t fail;
 };
+template <int TW, int TH, int PPT, int BATCH>
+using BwdSharedFor = BwdShared<TW * TH / PPT / 64, BATCH, kStoredMoments<TW, PPT>>;
 
 // Backward of one work unit: a tile's whole list, or with chunking chunk
 // `chunk` of it. BATCH: Gaussians staged per round (the batch depth). X: the
@@ -516,19 +513,21 @@ struct BwdShared {
 // done and reads the tile's longest walk from memory, else the caller is the
 // tile's own forward workgroup and passes it (tile_last).
 template <int TW, int TH, int PPT, int BATCH, bool X>
-__device__ __forceinline__ void backward_unit(const BlendArgs& a, BwdShared<TW * TH / PPT / 64, BATCH>& sh,
+__device__ __forceinline__ void backward_unit(const BlendArgs& a, BwdSharedFor<TW, TH, PPT, BATCH>& sh,
                                               int tile, int chunk, bool wait, uint32_t tile_last) {
   using Shape = TileShape<TW, TH, PPT>;
   constexpr int NT = Shape::NT;
   constexpr int ROWS = Shape::ROWS;
   constexpr int NW = NT / 64;
-  constexpr bool ROWY = PPT == 1 && TW % 16 == 0;
+  constexpr bool ROWY = kRowForm<TW, PPT>;
+  constexpr int MS = kStoredMoments<TW, PPT>;
   static_assert(BATCH <= NT, "one staged Gaussian per thread");
   float4* s_q0 = sh.q0;
   float4* s_q1 = sh.q1;
   float4* s_q2 = sh.q2;
   uint32_t* s_id = sh.id;
-  float (*s_red)[4][M_N][BATCH] = sh.red;
+  float (*s_red)[4][MS][BATCH] = sh.red;
+  float (*s_tot)[BATCH] = sh.tot;
   uint32_t lo = 0, hi = 0xFFFFFFFFu;
   if (a.chunk_len > 0) {
     lo = (uint32_t)chunk * (uint32_t)a.chunk_len;
@@ -635,7 +634,7 @@ __device__ __forceinline__ void backward_unit(const BlendArgs& a, BwdShared<TW *
     }
     {
       float* mine = &s_red[wave][0][0][0];
-      for (int e = lane; e < 4 * M_N * BATCH; e += 64) mine[e] = 0.0f;
+      for (int e = lane; e < 4 * MS * BATCH; e += 64) mine[e] = 0.0f;
     }
     __syncthreads();
     const uint32_t lbase = (uint32_t)(b0 - rg.x);
@@ -694,8 +693,8 @@ __device__ __forceinline__ void backward_unit(const BlendArgs& a, BwdShared<TW *
                                gd[i], tb[i], T[i], S[i], mb);
         }
       }
-      publish<NW, BATCH, ROWY>(ma, anya, lane, wave, k, s_red, dyA[0], qa1.y);
-      publish<NW, BATCH, ROWY>(mb, anyb, lane, wave, k - 1, s_red, dyB[0], qb1.y);
+      publish<NW, BATCH, MS>(ma, anya, lane, wave, k, s_red);
+      publish<NW, BATCH, MS>(mb, anyb, lane, wave, k - 1, s_red);
     }
     if (k == 0 && lbase < wlast) {
       const float4 q0 = s_q0[0], q1 = s_q1[0], q2 = s_q2[0];
@@ -720,27 +719,51 @@ __device__ __forceinline__ void backward_unit(const BlendArgs& a, BwdShared<TW *
                                tb[i], T[i], S[i], m);
         }
       }
-      publish<NW, BATCH, ROWY>(m, anyc, lane, wave, 0, s_red, dyc[0], q1.y);
+      publish<NW, BATCH, MS>(m, anyc, lane, wave, 0, s_red);
     }
     __syncthreads();
-    // sum the row partials of every wave into slot [0][0], then turn the
-    // moments into screen-space gradients and add them with one atomic per
-    // (Gaussian, component)
+    // sum the row partials of every wave, then turn the moments into
+    // screen-space gradients and add them with one atomic per (Gaussian,
+    // component). In the row form M_Y, M_XY and M_YY are the rows' sums of
+    // dL/dopacity's term (O) and of its dx moment weighted by the row's dy
+    // (dy^2 for M_YY; dy formed as every lane of the row formed it), and the
+    // spatial moments take the opacity.
     for (int e = tid; e < cnt * M_N; e += NT) {
       const int c = e / cnt, kk = e - c * cnt;
       float sum = 0.0f;
+      if (c < MS) {
 #pragma unroll
-      for (int w = 0; w < NW; ++w)
+        for (int w = 0; w < NW; ++w)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) sum += s_red[w][r][c][kk];
-      s_red[0][0][c][kk] = sum;
+          for (int r = 0; r < 4; ++r) sum += s_red[w][r][c][kk];
+      } else if (ROWY) {
+        const float v = s_q0[kk].y;
+        const int src = c == M_XY ? M_X : M_O;
+#pragma unroll 1
+        for (int w = 0; w < NW; ++w)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const float dy = v - ((float)(ty * TH + (w * 64 + r * 16) / TW) + 0.5f);
+            const float t = s_red[w][r][src < MS ? src : 0][kk];
+            sum += c == M_YY ? dy * (dy * t) : dy * t;
+          }
+      }
+      s_tot[c][kk] = sum;
     }
     __syncthreads();
     for (int kk = tid; kk < cnt; kk += NT) {
       float mm[M_N];
 #pragma unroll
-      for (int c = 0; c < M_N; ++c) mm[c] = s_red[0][0][c][kk];
+      for (int c = 0; c < M_N; ++c) mm[c] = s_tot[c][kk];
       const float4 q0 = s_q0[kk], q1 = s_q1[kk];
+      if (ROWY) {
+        const float o = q1.y;
+        mm[M_X] *= o;
+        mm[M_XX] *= o;
+        mm[M_Y] *= o;
+        mm[M_XY] *= o;
+        mm[M_YY] *= o;
+      }
       float g[G2_N];
       // d power / d u = -(A dx + B dy) = 2 (-A/2) dx + (-B) dy, likewise for v
       g[G2_U] = 2.0f * q0.z * mm[M_X] + q0.w * mm[M_Y];
@@ -766,7 +789,7 @@ __device__ __forceinline__ void backward_unit(const BlendArgs& a, BwdShared<TW *
 template <int TW, int TH, int PPT, int BATCH>
 __global__ void __launch_bounds__(TW * TH / PPT) __attribute__((amdgpu_waves_per_eu(4)))
 blend_backward_kernel(BlendArgs a) {
-  __shared__ BwdShared<TW * TH / PPT / 64, BATCH> sh;
+  __shared__ BwdSharedFor<TW, TH, PPT, BATCH> sh;
   int unit = (int)blockIdx.x, chunk = 0;
   if (a.chunk_len > 0) {
     const int cu = unit / a.num_tiles;
@@ -786,7 +809,7 @@ template <int TW, int TH, int PPT, int BATCH, bool CK>
 __global__ void __launch_bounds__(TW * TH / PPT) __attribute__((amdgpu_waves_per_eu(4)))
 blend_fused_kernel(BlendArgs a) {
   using F = FwdShared<TW * TH / PPT>;
-  using B = BwdShared<TW * TH / PPT / 64, BATCH>;
+  using B = BwdSharedFor<TW, TH, PPT, BATCH>;
   __shared__ __align__(16) unsigned char smem[sizeof(F) > sizeof(B) ? sizeof(F) : sizeof(B)];
   const int b = (int)blockIdx.x;
   if (b < a.num_tiles) {
@@ -819,7 +842,7 @@ template <int TW, int TH, int PPT, int BATCH, bool CK>
 __global__ void __launch_bounds__(TW * TH / PPT) __attribute__((amdgpu_waves_per_eu(4)))
 blend_fused_queue_kernel(BlendArgs a, uint32_t units) {
   using F = FwdShared<TW * TH / PPT>;
-  using B = BwdShared<TW * TH / PPT / 64, BATCH>;
+  using B = BwdSharedFor<TW, TH, PPT, BATCH>;
   __shared__ __align__(16) unsigned char smem[sizeof(F) > sizeof(B) ? sizeof(F) : sizeof(B)];
   __shared__ uint32_t s_unit;
   while (true) {
