@@ -43,19 +43,31 @@ PEAK_HBM_GBS = 8000.0
 #     scaling by log2 e 1, exp 4, opacity, clamp and skip tests 5), the reverse
 #     step 29 (rcp 4), the wave sums of the ten per-Gaussian moments 10 (63
 #     adds per 64 lanes each);
+#   backward, row form 50 (one pixel per thread, tiles 16 or 32 wide: each
+#     16-lane row is one image row, so the dy factors and the opacity apply
+#     to row sums): the alpha 20, the reverse step 23, seven wave sums 7;
 #   forward 23: the alpha 20 and the transmittance test and update 3 (the
 #     colour and depth accumulation happens once per composited pair).
 #  Plain operations (each FP32 operation once, exp and rcp included), for
-#  the published FLOP figure: backward 53, forward 20.
+#  the published FLOP figure: backward 53 (row form 44), forward 20.
 OPS_PER_PAIR_BWD = 59.0
+OPS_PER_PAIR_BWD_ROW = 50.0
 OPS_PER_PAIR_FWD = 23.0
 PLAIN_OPS_PER_PAIR_BWD = 53.0
+PLAIN_OPS_PER_PAIR_BWD_ROW = 44.0
 PLAIN_OPS_PER_PAIR_FWD = 20.0
 # The fused launch (forward and backward of every tile in one grid) is
 # credited with both per pair walked by the backward; the forward's pairs
 # past each pixel's last composited Gaussian are not counted.
-OPS_PER_PAIR_FUSED = OPS_PER_PAIR_FWD + OPS_PER_PAIR_BWD
-PLAIN_OPS_PER_PAIR_FUSED = PLAIN_OPS_PER_PAIR_FWD + PLAIN_OPS_PER_PAIR_BWD
+
+
+def ops_per_pair_for(kernel, tile_w, ppt):
+    """(issue slots, plain operations) per pair walked of the blend kernel."""
+    row = ppt == 1 and tile_w % 16 == 0
+    bwd = OPS_PER_PAIR_BWD_ROW if row else OPS_PER_PAIR_BWD
+    pbwd = PLAIN_OPS_PER_PAIR_BWD_ROW if row else PLAIN_OPS_PER_PAIR_BWD
+    return {"blend_fwd": (OPS_PER_PAIR_FWD, PLAIN_OPS_PER_PAIR_FWD), "blend_bwd": (bwd, pbwd),
+            "blend": (OPS_PER_PAIR_FWD + bwd, PLAIN_OPS_PER_PAIR_FWD + pbwd)}[kernel]
 
 
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
@@ -65,9 +77,6 @@ PLAIN_OPS_PER_PAIR_FUSED = PLAIN_OPS_PER_PAIR_FWD + PLAIN_OPS_PER_PAIR_BWD
 # thread, the default batch depth). An entry is removed whenever its kernel
 # changes.
 TRAFFIC = {
-    ("keyframe_640x480_200k", "blend"): (79.606e6, 84.883e6),   # read, write
-    ("batch8_640x480_500k", "blend_bwd"): (622.307e6, 815.010e6),
-    ("mixed16_2M_sh3", "blend_bwd"): (1372.026e6, 1915.826e6),
 }
 PROFILED_CONFIG = (16, 16, 1, 0)   # tile_w, tile_h, pixels per thread, batch depth
 
@@ -305,9 +314,7 @@ def main():
     dom_avg_ms = dom_ms / max(args.steps, 1)     # one launch per step in graph mode
     traffic_known = ((scene.name, dominant) in TRAFFIC and
                      (R.tile_w, R.tile_h, R.pixels_per_thread or 1, R.batch_depth) == PROFILED_CONFIG)
-    ops_per_pair = {"blend_fwd": OPS_PER_PAIR_FWD, "blend_bwd": OPS_PER_PAIR_BWD, "blend": OPS_PER_PAIR_FUSED}[dominant]
-    plain_per_pair = {"blend_fwd": PLAIN_OPS_PER_PAIR_FWD, "blend_bwd": PLAIN_OPS_PER_PAIR_BWD,
-                      "blend": PLAIN_OPS_PER_PAIR_FUSED}[dominant]
+    ops_per_pair, plain_per_pair = ops_per_pair_for(dominant, R.tile_w, R.pixels_per_thread or 1)
     achieved = ops_per_pair * pairs / (dom_avg_ms * 1e-3) / 1e12
     achieved_plain = plain_per_pair * pairs / (dom_avg_ms * 1e-3) / 1e12
 
