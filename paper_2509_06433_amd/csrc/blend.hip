@@ -812,22 +812,26 @@ blend_fused_kernel(BlendArgs a) {
   using B = BwdSharedFor<TW, TH, PPT, BATCH>;
   __shared__ __align__(16) unsigned char smem[sizeof(F) > sizeof(B) ? sizeof(F) : sizeof(B)];
   const int b = (int)blockIdx.x;
+  int tile, chunk;
+  uint32_t tl = 0;
   if (b < a.num_tiles) {
     // the tile's forward, then the first chunk of its backward (the whole
     // list when unchunked) without waiting: each thread reads back only its
     // own pixels' state, and the tile's longest walk comes from LDS
-    const int tile = a.order ? (int)a.order[b] : b;
-    const uint32_t tl = forward_tile<TW, TH, PPT, CK, true>(a, *reinterpret_cast<F*>(smem), tile);
+    tile = a.order ? (int)a.order[b] : b;
+    chunk = 0;
+    tl = forward_tile<TW, TH, PPT, CK, true>(a, *reinterpret_cast<F*>(smem), tile);
     __syncthreads();   // every thread has read the forward's LDS before the backward reuses it
-    backward_unit<TW, TH, PPT, BATCH, true>(a, *reinterpret_cast<B*>(smem), tile, 0, false, tl);
   } else {
     // chunks 1, 2, ... of every tile, in chunk order, each waiting for its
     // tile's forward
     const int unit = b - a.num_tiles;
     const int cu = unit / a.num_tiles, t = unit - cu * a.num_tiles;
-    backward_unit<TW, TH, PPT, BATCH, true>(a, *reinterpret_cast<B*>(smem), a.order ? (int)a.order[t] : t, cu + 1,
-                                            true, 0u);
+    tile = a.order ? (int)a.order[t] : t;
+    chunk = cu + 1;
   }
+  // one copy of the backward for both kinds of workgroup
+  backward_unit<TW, TH, PPT, BATCH, true>(a, *reinterpret_cast<B*>(smem), tile, chunk, b >= a.num_tiles, tl);
 }
 
 // The fused launch as a persistent grid over a work queue, for more units
