@@ -77,6 +77,9 @@ def ops_per_pair_for(kernel, tile_w, ppt):
 # thread, the default batch depth). An entry is removed whenever its kernel
 # changes.
 TRAFFIC = {
+    ("keyframe_640x480_200k", "blend"): (77.689e6, 84.883e6),   # read, write
+    ("batch8_640x480_500k", "blend_bwd"): (639.321e6, 815.010e6),
+    ("mixed16_2M_sh3", "blend_bwd"): (1425.186e6, 1915.826e6),
 }
 PROFILED_CONFIG = (16, 16, 1, 0)   # tile_w, tile_h, pixels per thread, batch depth
 
