@@ -1559,8 +1559,8 @@ __global__ void __launch_bounds__(kTileSortThreads) tile_depth_sort_kernel(
 // rectangle: no scan over the tiles is needed. Tiles whose list would pass
 // the capacity get an empty range and raise the overflow flag.
 // ---------------------------------------------------------------------------
-constexpr int kBlockRows = 32;   // rows of 256 list entries whose keep masks stay in LDS
-constexpr int kBlockLoads = 8;   // rows whose loads are in flight together
+constexpr int kBlockRows = 32;   // long lists: rows of 256 entries whose keep masks stay in LDS
+constexpr int kBlockLoads = 8;   // rows whose loads are in flight together (4: same time, 16: slower)
 
 // Whether a block instance (key) covers the block-relative tile (lx, ly), and
 // how many tiles it covers before that one in the block's row-major order.
