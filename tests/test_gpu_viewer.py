@@ -68,7 +68,11 @@ def test_viewer_alongside_mapping(gpu):
     inter-process event after each iteration) with and without the viewer
     rendering 672x376 frames at 30 per second, panning, each frame ordered
     after the mapper's last finished iteration (where the driver offers
-    inter-process events; else the frames read the live buffer unordered)."""
+    inter-process events; else the frames read the live buffer unordered).
+    The loop issues each iteration from Python, so its rate is set by the
+    host as much as by the GPU: the rate with the viewer is compared with
+    the mean of the rates measured without it before and after, which
+    brackets a drift of the host's speed over the test."""
     rasterize, viewer = gpu
     s = scenes.keyframe_640x480()
     p = torch.from_numpy(s.params).cuda()
@@ -106,5 +110,5 @@ def test_viewer_alongside_mapping(gpu):
     say("viewer", rep)
     assert R.mapping_status()["skipped"] == 0
     assert rep["fps"] >= 28.0, rep
-    assert together >= 0.85 * alone, (alone, together)
+    assert together >= 0.85 * 0.5 * (alone + after), (alone, together, after)
     shared.close()
